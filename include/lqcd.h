@@ -1,0 +1,231 @@
+/*
+ * lqcd.h - C ABI of the MI355X (gfx950) library for disconnected-loop
+ * noise estimation with deflation, perturbative and polynomial subtraction
+ * (Baral, Whyte, Wilcox, Morgan, "Disconnected Loop Subtraction Methods in
+ * Lattice QCD", arXiv:1903.06986).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice extents dims = {Lx, Ly, Lz, Lt}, each even and >= 2, periodic in
+ * all four directions (Sec. 7).  Directions mu = 0..3 are x, y, z, t.
+ *
+ * External ("LEX") fields are complex128 (interleaved re, im doubles) in
+ * lexicographic order [rhs][t][z][y][x][spin][colour]: vector index
+ * (s * 4 + spin) * 3 + colour with s = x + Lx (y + Ly (z + Lz t)), the
+ * "space-time-color-Dirac" index of Sec. 2.  A field of one right-hand side
+ * holds 12 V complex numbers, V = Lx Ly Lz Lt.
+ *
+ * Links are complex128 [t][z][y][x][mu][row][col] (host memory at create).
+ *
+ * Gamma matrices: Euclidean, hermitian, chiral basis
+ *   g_k = [[0, -i s_k], [i s_k, 0]] (k = 1..3), g_4 = [[0, 1], [1, 0]],
+ *   g_5 = g_1 g_2 g_3 g_4 = diag(1, 1, -1, -1).
+ * Operators Theta are coded 0 = identity (scalar), 1..4 = g_1..g_4
+ * (local vector); Table 2 of the paper.
+ *
+ * Memory: every field pointer (eta, x, xt, b, in, out) is device memory
+ * owned by the caller, read and written on the context's HIP stream.  Host
+ * pointers are named *_host or documented as host.  The library owns only
+ * the opaque handles and their internal device workspaces.
+ *
+ * Errors: every call returns an lqcd_status, never aborts and never throws;
+ * lqcd_last_error() gives a thread-local message for the last failure.
+ * Calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef LQCD_H
+#define LQCD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lqcd_ctx lqcd_ctx;
+typedef struct lqcd_defl lqcd_defl;
+
+typedef enum {
+  LQCD_OK = 0,
+  LQCD_EINVAL = 1,      /* invalid argument (null pointer, odd extent, bad enum) */
+  LQCD_ENOMEM = 2,      /* device or host allocation failed */
+  LQCD_EDEVICE = 3,     /* HIP runtime error */
+  LQCD_ENOCONV = 4,     /* solver hit its iteration limit; x holds the best iterate */
+  LQCD_EBREAKDOWN = 5,  /* Arnoldi breakdown (zero subdiagonal) */
+  LQCD_ENAN = 6         /* NaN or Inf met in a norm */
+} lqcd_status;
+
+typedef enum { LQCD_F64 = 0, LQCD_F32 = 1, LQCD_F16 = 2, LQCD_BF16 = 3 } lqcd_prec;
+
+/* Operators of wilson_apply (Sec. 5.1 Eqs. (24)-(25); Sec. 5.4 Eq. (63);
+ * the even/odd reduction of Sec. 7):
+ *   LQCD_OP_M      M psi     = psi - kappa P psi
+ *   LQCD_OP_MDAG   M^+ psi   = g5 M g5 psi
+ *   LQCD_OP_MG5    M' psi    = M g5 psi  (hermitian)
+ *   LQCD_OP_HOP    P psi,  (P psi)(x) = sum_mu [(1 - g_mu) U_mu(x) psi(x+mu)
+ *                                     + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu)]
+ *   LQCD_OP_SCHUR  Mhat psi_e = psi_e - kappa^2 D_eo D_oe psi_e on even
+ *                  sites; odd sites of the output are set to zero. */
+typedef enum {
+  LQCD_OP_M = 0, LQCD_OP_MDAG = 1, LQCD_OP_MG5 = 2, LQCD_OP_HOP = 3, LQCD_OP_SCHUR = 4
+} lqcd_op;
+
+/* LQCD_LAYOUT_LEX: complex128 lexicographic fields as above.
+ * LQCD_LAYOUT_EO:  the library's internal even/odd layout in the requested
+ *   precision (for timing the stencil alone): per right-hand side, parity
+ *   blocks [parity][12][V/2] of complex numbers (component-major, so that
+ *   consecutive sites are consecutive in memory); LQCD_OP_SCHUR uses only
+ *   the even block, [12][V/2] per right-hand side. */
+typedef enum { LQCD_LAYOUT_LEX = 0, LQCD_LAYOUT_EO = 1 } lqcd_layout;
+
+/* Subtraction methods (Sec. 5): no subtraction, perturbative, polynomial,
+ * hermitian-forced eigenvalue, and the two combinations of Sec. 5.5. */
+typedef enum {
+  LQCD_NS = 0, LQCD_PS = 1, LQCD_POLY = 2, LQCD_HFES = 3, LQCD_HFPS = 4, LQCD_HFPOLY = 5
+} lqcd_method;
+
+/* Modes of deflate_project. */
+typedef enum {
+  LQCD_DEFL_HFES = 0,     /* weights 1/lambda'_q (Eqs. (66)-(68)) */
+  LQCD_DEFL_EIGPOLY = 1   /* weights 1/lambda'_q - 1/xi'_q for a polynomial (Eqs. (69)-(72)) */
+} lqcd_defl_mode;
+
+typedef struct {
+  int m;             /* Krylov subspace size of GMRES-DR (m > k >= 1) */
+  int k;             /* number of deflated (harmonic Ritz) vectors kept */
+  int max_cycles;    /* restart-cycle limit per right-hand side */
+  double tol;        /* relative true residual |b - A x| / |b| target */
+  double tol_super;  /* first right-hand side: residual target of the super-converged solve */
+  double eig_tol;    /* first right-hand side: also continue until the n_eig smallest harmonic
+                        Ritz pairs satisfy |A y - theta y| <= eig_tol |theta| (0 = off) */
+  int n_eig;         /* see eig_tol (0 = k) */
+  lqcd_prec inner;   /* precision of the inner Krylov solver: F64 = plain FP64,
+                        F32 = FP32 stencil and basis inside FP64 iterative refinement */
+  double inner_tol;  /* relative residual reduction per refinement step (mixed precision) */
+  int rhs_block;     /* right-hand sides solved together by GMRES-Proj (>= 1) */
+} lqcd_solve_params;
+
+typedef struct {
+  int matvecs;       /* applications of the solved operator (any precision) */
+  int cycles;        /* restart cycles (GMRES-DR or GMRES(m-k) cycles of GMRES-Proj) */
+  int refinements;   /* FP64 residual recomputations (mixed precision) */
+  double true_resid; /* final |b - A x| / |b| recomputed in FP64 on the full lattice */
+} lqcd_solve_stats;
+
+/* Create a context for one lattice on the current HIP device.
+ * dims: host int[4]; links_host: host complex128 [V][4][3][3] (not retained);
+ * kappa: hopping parameter of Eq. (24); hip_stream: hipStream_t or NULL
+ * (the null stream).  Packs the links into the device even/odd layout in
+ * FP64 and FP32.  EINVAL for odd or < 2 extents or null pointers. */
+lqcd_status lqcd_create(const int dims[4], const double *links_host, double kappa,
+                        void *hip_stream, lqcd_ctx **out);
+lqcd_status lqcd_set_kappa(lqcd_ctx *ctx, double kappa);
+lqcd_status lqcd_set_stream(lqcd_ctx *ctx, void *hip_stream);
+lqcd_status lqcd_destroy(lqcd_ctx *ctx);
+
+/* Z(4) noise (Sec. 2): eta^(n)_i = i^k, k = top two bits of the
+ * (n * 12V + i)-th output of SplitMix64 seeded with `seed` (Steele, Lea and
+ * Flood 2014, Vigna's formulation), for n = first .. first + nrhs - 1.
+ * eta: device complex128 LEX [nrhs][12V]; codes: optional device uint8
+ * [nrhs][12V] receiving k (may be NULL). */
+lqcd_status lqcd_noise_z4(lqcd_ctx *ctx, uint64_t seed, int64_t first, int nrhs,
+                          void *eta, uint8_t *codes);
+
+/* Layout conversion between LEX complex128 and the internal even/odd layout
+ * (LQCD_LAYOUT_EO, precision prec) for nrhs full fields. */
+lqcd_status lqcd_pack_eo(lqcd_ctx *ctx, lqcd_prec prec, const void *lex, void *eo, int nrhs);
+lqcd_status lqcd_unpack_eo(lqcd_ctx *ctx, lqcd_prec prec, const void *eo, void *lex, int nrhs);
+
+/* Apply an operator (see lqcd_op) to nrhs fields.  With LQCD_LAYOUT_LEX,
+ * in/out are complex128 LEX fields and the stencil runs in precision prec
+ * (inputs rounded to prec, outputs widened to FP64).  With LQCD_LAYOUT_EO
+ * they are internal-layout fields of precision prec.  in and out must not
+ * overlap.  F16/BF16 are not available for this call (EINVAL). */
+lqcd_status wilson_apply(lqcd_ctx *ctx, lqcd_op op, lqcd_prec prec, lqcd_layout layout,
+                         const void *in, void *out, int nrhs);
+
+/* Deflated restarted GMRES (Sec. 7: GMRES-DR(m,k) for the first noise vector
+ * solved to super-convergence, GMRES-Proj for the rest; Sec. 5.4 for the
+ * hermitian system).
+ * op = LQCD_OP_SCHUR: solves M x = b through the even/odd reduced system;
+ *      x is the full solution.
+ * op = LQCD_OP_MG5:   solves M' x = b on the full lattice (hermitian).
+ * b, x: device complex128 LEX [nrhs][12V]; x is output only (zero start).
+ * defl_inout: if *defl_inout is NULL the first right-hand side is solved by
+ *   GMRES-DR and its deflation space (V_{k+1}, Hbar_k with A V_k =
+ *   V_{k+1} Hbar_k) is returned in *defl_inout (free with lqcd_defl_free);
+ *   every other right-hand side is solved by GMRES-Proj over that space.
+ * stats: host array [nrhs] or NULL.
+ * ENOCONV if any right-hand side misses tol within max_cycles. */
+lqcd_status gmresdr_solve(lqcd_ctx *ctx, lqcd_op op, const lqcd_solve_params *params,
+                          const void *b, void *x, int nrhs, lqcd_defl **defl_inout,
+                          lqcd_solve_stats *stats);
+
+/* Eigenpairs held by a deflation space of the hermitian operator M'
+ * (op LQCD_OP_MG5): Rayleigh-Ritz in V_k (Sec. 5.4), the Q of smallest
+ * |lambda'|.  lambda_host: host double [Q]; resid_host: host double [Q]
+ * (|M' e - lambda' e|) or NULL. */
+lqcd_status lqcd_defl_eigpairs(lqcd_ctx *ctx, lqcd_defl *defl, int Q, double *lambda_host,
+                               double *resid_host);
+/* Harmonic Ritz values of a deflation space: host complex128 [k]. */
+lqcd_status lqcd_defl_ritz(const lqcd_defl *defl, double *theta_host, int *k_out);
+void lqcd_defl_free(lqcd_defl *defl);
+
+/* Hermitian-forced deflation (Sec. 5.4 Eqs. (66)-(68); Sec. 5.5 Eqs. (69)-(72)).
+ * With (lambda'_q, e'_q) the Q lowest eigenpairs of M' in defl (op MG5) and
+ * weights w_q = 1/lambda'_q (mode HFES) or w_q = 1/lambda'_q - 1/xi'_q
+ * (mode EIGPOLY, 1/xi'_q = e'_q^+ g5 p(kappa P) e'_q, p(z) = sum_j
+ * coeffs[j] z^j, coeffs_host complex128 [ncoeff]), accumulates
+ *   xt[n] += g5 sum_q w_q e'_q (e'_q^+ eta[n])                (device LEX)
+ *   trace_corr[th][t] += sum_q w_q sum_{x in t} e'_q(x)^+ Theta g5 e'_q(x)
+ * (host complex128 [ntheta][Lt], Theta codes from thetas_host).  HFES is
+ * xt = 0 plus this; HFPS / HFPOLY are PS / POLY output plus this.
+ * xi_inv_host: optional host complex128 [Q] receiving 1/xi'_q. */
+lqcd_status deflate_project(lqcd_ctx *ctx, lqcd_defl *defl, int Q, lqcd_defl_mode mode,
+                            const double *coeffs_host, int ncoeff, const int *thetas_host,
+                            int ntheta, const void *eta, void *xt, int nrhs,
+                            double *trace_corr_host, double *xi_inv_host);
+
+/* Perturbative subtraction (Sec. 5.1, Eqs. (28)-(35)): xt[n] =
+ * sum_{j=0}^{order} (kappa P)^j eta[n] (device LEX), and the exact trace
+ * correction Tr_t(Theta sum_j (kappa P)^j) per timeslice (host complex128
+ * [ntheta][Lt]; may be NULL).  Only closed paths contribute to the
+ * correction; order <= 7. */
+lqcd_status pert_subtract(lqcd_ctx *ctx, int order, const int *thetas_host, int ntheta,
+                          const void *eta, void *xt, int nrhs, double *trace_corr_host);
+
+/* Polynomial subtraction (Sec. 5.2, Eqs. (40)-(50)).  If b is not NULL the
+ * Min-Res coefficients for the noise vector b (device LEX, one field) are
+ * computed first: minimise |b - M sum_{j=0}^{d} c_j (kappa P)^j b|
+ * (the minimiser of the normal equations (v^+ v) a = v^+ b of Eq. (44),
+ * written in the kappa P basis); coeffs_host (complex128 [degree+1]) is
+ * written.  If b is NULL, coeffs_host is read instead.  Then
+ * xt[n] = sum_j c_j (kappa P)^j eta[n] and the exact per-timeslice trace
+ * correction Tr_t(Theta sum_j c_j (kappa P)^j).  a_host: optional
+ * complex128 [degree+1] receiving the M-basis coefficients a_k of
+ * Eq. (42).  degree <= 7. */
+lqcd_status poly_subtract(lqcd_ctx *ctx, int degree, const void *b, double *coeffs_host,
+                          double *a_host, const int *thetas_host, int ntheta,
+                          const void *eta, void *xt, int nrhs, double *trace_corr_host);
+
+/* The subtracted estimator (Sec. 5 Eq. (23); Sec. 6 Eq. (73)):
+ *   t_n[th][t] = sum_{x in timeslice t} eta_n(x)^+ Theta (x_n - xt_n)(x),
+ *   est[th][t] = (1/N) sum_n t_n[th][t] + trace_corr[th][t],
+ * with entry t = Lt the whole-lattice sum.  eta, x: device LEX [nrhs];
+ * xt: device LEX [nrhs] or NULL (no subtraction); trace_corr_host:
+ * host complex128 [ntheta][Lt] or NULL.  Outputs (host): est complex128
+ * [ntheta][Lt+1]; stderr_host double [ntheta][Lt+1][2] = standard errors
+ * s / sqrt(N) of the real and imaginary parts (unbiased variance; 0 if
+ * N = 1); samples_host optional complex128 [nrhs][ntheta][Lt+1].
+ * The physical <psibar Theta psi> is -est (Eq. (73)). */
+lqcd_status loop_estimate(lqcd_ctx *ctx, const int *thetas_host, int ntheta, const void *eta,
+                          const void *x, const void *xt, int nrhs,
+                          const double *trace_corr_host, double *est_host,
+                          double *stderr_host, double *samples_host);
+
+/* Thread-local description of the last non-OK status. */
+const char *lqcd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LQCD_H */

@@ -1,0 +1,411 @@
+// Vector kernels with FP64 accumulation (Gram-Schmidt, norms, basis
+// updates).  Every reduction is two-stage and fixed-order: blocks write
+// partial sums, a second kernel adds them, so results are bitwise
+// reproducible from run to run.
+#include "common.h"
+#include "cplx.h"
+#include "fields.h"
+
+namespace lqcd {
+
+namespace {
+
+constexpr int EPT = 8;                 // elements per thread in a chunk
+constexpr int CH = kBlock * EPT;       // elements per block
+constexpr int kMaxJ = 256;             // largest basis handled by one call
+constexpr int kWaves = kBlock / 64;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum N values per thread over the block; result valid in thread 0.
+template <int N>
+__device__ inline void block_sum(double (&v)[N], double (*sh)[kWaves]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[k][wave] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double s = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) s += sh[k][w];
+      v[k] = s;
+    }
+}
+
+template <class R>
+__device__ inline cx<double> ld64(const cx<R> *p) {
+  cx<R> v = ldc(p);
+  return mk<double>(double(v.re), double(v.im));
+}
+
+// ---------------------------------------------------------- multi_dot
+template <class R, int JG>
+__global__ void __launch_bounds__(kBlock)
+    k_mdot_part(const cx<R> *__restrict__ V, size_t ldv, size_t V_rs, int J,
+                const cx<R> *__restrict__ w, size_t w_rs, size_t n, double *__restrict__ part) {
+  __shared__ double sh[2 * JG][kWaves];
+  const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
+  V += r * V_rs;
+  w += r * w_rs;
+  const size_t base = size_t(b) * CH + threadIdx.x;
+  cx<double> wv[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    size_t idx = base + size_t(e) * kBlock;
+    wv[e] = idx < n ? ld64(w + idx) : mk<double>(0, 0);
+  }
+  for (int j0 = 0; j0 < J; j0 += JG) {
+    double acc[2 * JG];
+#pragma unroll
+    for (int k = 0; k < 2 * JG; ++k) acc[k] = 0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      size_t idx = base + size_t(e) * kBlock;
+      if (idx < n) {
+#pragma unroll
+        for (int g = 0; g < JG; ++g)
+          if (j0 + g < J) {
+            cx<double> v = ld64(V + size_t(j0 + g) * ldv + idx);
+            cx<double> p = cmulc(v, wv[e]);
+            acc[2 * g] += p.re;
+            acc[2 * g + 1] += p.im;
+          }
+      }
+    }
+    block_sum<2 * JG>(acc, sh);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int g = 0; g < JG; ++g)
+        if (j0 + g < J) {
+          size_t o = ((size_t(r) * nblk + b) * J + j0 + g) * 2;
+          part[o] = acc[2 * g];
+          part[o + 1] = acc[2 * g + 1];
+        }
+    __syncthreads();
+  }
+}
+
+// out[r * out_rs + j] = sum over blocks of part[r][b][j]
+__global__ void __launch_bounds__(kBlock)
+    k_mdot_final(const double *__restrict__ part, int nblk, int J, cx<double> *__restrict__ out,
+                 size_t out_rs) {
+  __shared__ double sh[2][kWaves];
+  const int j = blockIdx.x, r = blockIdx.y;
+  double acc[2] = {0, 0};
+  for (int b = threadIdx.x; b < nblk; b += kBlock) {
+    size_t o = ((size_t(r) * nblk + b) * J + j) * 2;
+    acc[0] += part[o];
+    acc[1] += part[o + 1];
+  }
+  block_sum<2>(acc, sh);
+  if (threadIdx.x == 0) stc(out + size_t(r) * out_rs + j, mk(acc[0], acc[1]));
+}
+
+// --------------------------------------------------------- multi_axpy
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_maxpy(const cx<R> *__restrict__ V, size_t ldv, size_t V_rs, int J,
+            const cx<double> *__restrict__ coef, size_t coef_rs, cx<R> *__restrict__ w,
+            size_t w_rs, size_t n, double *__restrict__ part) {
+  __shared__ cx<double> sc[kMaxJ];
+  __shared__ double sh[1][kWaves];
+  const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
+  V += r * V_rs;
+  w += r * w_rs;
+  for (int j = threadIdx.x; j < J; j += kBlock) sc[j] = coef[size_t(r) * coef_rs + j];
+  __syncthreads();
+  const size_t base = size_t(b) * CH + threadIdx.x;
+  cx<double> acc[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    size_t idx = base + size_t(e) * kBlock;
+    acc[e] = idx < n ? ld64(w + idx) : mk<double>(0, 0);
+  }
+  for (int j = 0; j < J; ++j) {
+    const cx<double> cj = sc[j];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      size_t idx = base + size_t(e) * kBlock;
+      if (idx < n) acc[e] = acc[e] - ld64(V + size_t(j) * ldv + idx) * cj;
+    }
+  }
+  double nrm[1] = {0};
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    size_t idx = base + size_t(e) * kBlock;
+    if (idx < n) {
+      stc(w + idx, mk<R>(R(acc[e].re), R(acc[e].im)));
+      cx<R> st = ldc(w + idx);  // norm of the stored (rounded) value
+      nrm[0] += double(st.re) * double(st.re) + double(st.im) * double(st.im);
+    }
+  }
+  if (part) {
+    block_sum<1>(nrm, sh);
+    if (threadIdx.x == 0) part[size_t(r) * nblk + b] = nrm[0];
+  }
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_norm_part(const cx<R> *__restrict__ x, size_t x_rs, size_t n, double *__restrict__ part) {
+  __shared__ double sh[1][kWaves];
+  const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
+  x += r * x_rs;
+  const size_t base = size_t(b) * CH + threadIdx.x;
+  double nrm[1] = {0};
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    size_t idx = base + size_t(e) * kBlock;
+    if (idx < n) {
+      cx<double> v = ld64(x + idx);
+      nrm[0] += v.re * v.re + v.im * v.im;
+    }
+  }
+  block_sum<1>(nrm, sh);
+  if (threadIdx.x == 0) part[size_t(r) * nblk + b] = nrm[0];
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_sum_final(const double *__restrict__ part, int nblk, double *__restrict__ out) {
+  __shared__ double sh[1][kWaves];
+  const int r = blockIdx.x;
+  double acc[1] = {0};
+  for (int b = threadIdx.x; b < nblk; b += kBlock) acc[0] += part[size_t(r) * nblk + b];
+  block_sum<1>(acc, sh);
+  if (threadIdx.x == 0) out[r] = acc[0];
+}
+
+// ---------------------------------------------------------- elementwise
+constexpr int kMaxScalars = 64;
+struct Scalars {
+  cx<double> a[kMaxScalars], b[kMaxScalars];
+};
+
+template <class R>
+__global__ void k_axpby(Scalars s, bool per_rhs, const cx<R> *__restrict__ x, size_t x_rs,
+                        cx<R> *__restrict__ y, size_t y_rs, size_t n) {
+  const int r = blockIdx.y;
+  const cx<double> a = s.a[per_rhs ? r : 0], b = s.b[per_rhs ? r : 0];
+  x += r * x_rs;
+  y += r * y_rs;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    cx<double> v = a * ld64(x + i);
+    if (b.re != 0.0 || b.im != 0.0) v = v + b * ld64(y + i);
+    stc(y + i, mk<R>(R(v.re), R(v.im)));
+  }
+}
+
+template <class R>
+__global__ void k_scale_dev(const cx<R> *__restrict__ x, size_t x_rs, const double *__restrict__ s,
+                            cx<R> *__restrict__ y, size_t y_rs, size_t n) {
+  const int r = blockIdx.y;
+  const double sc = s[r];
+  x += r * x_rs;
+  y += r * y_rs;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    cx<double> v = sc * ld64(x + i);
+    stc(y + i, mk<R>(R(v.re), R(v.im)));
+  }
+}
+
+// ---------------------------------------------------------------- gemm
+constexpr int NBT = 4;  // output columns per pass
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_gemm_nn(const cx<R> *__restrict__ V, size_t ldv, size_t V_rs, int J,
+              const cx<double> *__restrict__ C, size_t ldc, size_t C_rs, cx<R> *__restrict__ Y,
+              size_t ldy, size_t Y_rs, int nb, size_t n, double alpha) {
+  const int r = blockIdx.y;
+  V += r * V_rs;
+  C += r * C_rs;
+  Y += r * Y_rs;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    for (int b0 = 0; b0 < nb; b0 += NBT) {
+      cx<double> acc[NBT];
+#pragma unroll
+      for (int t = 0; t < NBT; ++t) acc[t] = mk<double>(0, 0);
+      for (int j = 0; j < J; ++j) {
+        cx<double> v = ld64(V + size_t(j) * ldv + i);
+#pragma unroll
+        for (int t = 0; t < NBT; ++t)
+          if (b0 + t < nb) acc[t] = acc[t] + v * C[j + ldc * size_t(b0 + t)];
+      }
+#pragma unroll
+      for (int t = 0; t < NBT; ++t)
+        if (b0 + t < nb) {
+          cx<R> *yp = Y + size_t(b0 + t) * ldy + i;
+          cx<double> y = ld64(yp) + alpha * acc[t];
+          stc(yp, mk<R>(R(y.re), R(y.im)));
+        }
+    }
+  }
+}
+
+constexpr int RC_E = 32;  // elements per block of the in-place recombination
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_recombine(cx<R> *__restrict__ V, size_t ldv, int Jin, const cx<double> *__restrict__ P,
+                size_t ldp, int Jout, size_t n) {
+  extern __shared__ unsigned char smem[];
+  cx<R> *sv = reinterpret_cast<cx<R> *>(smem);  // [Jin][RC_E]
+  const size_t e0 = size_t(blockIdx.x) * RC_E;
+  for (int t = threadIdx.x; t < Jin * RC_E; t += kBlock) {
+    int l = t / RC_E, e = t % RC_E;
+    size_t idx = e0 + e;
+    sv[t] = idx < n ? ldc(V + size_t(l) * ldv + idx) : mk<R>(0, 0);
+  }
+  __syncthreads();
+  const int e = threadIdx.x % RC_E;
+  const size_t idx = e0 + e;
+  if (idx >= n) return;
+  for (int j = threadIdx.x / RC_E; j < Jout; j += kBlock / RC_E) {
+    cx<double> acc = mk<double>(0, 0);
+    for (int l = 0; l < Jin; ++l) {
+      cx<R> v = sv[l * RC_E + e];
+      acc = acc + mk<double>(double(v.re), double(v.im)) * P[l + ldp * size_t(j)];
+    }
+    stc(V + size_t(j) * ldv + idx, mk<R>(R(acc.re), R(acc.im)));
+  }
+}
+
+inline unsigned grid_elems(size_t n) { return unsigned(std::min<size_t>(nblocks(n), 8192)); }
+
+}  // namespace
+
+template <class R>
+void multi_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w,
+               size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs) {
+  if (J <= 0 || nrhs <= 0) return;
+  const int nblk = int((n + CH - 1) / CH);
+  double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * J * 2 * sizeof(double)));
+  hipLaunchKernelGGL((k_mdot_part<R, 4>), dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const cx<R> *>(V), ldv, V_rs, J, static_cast<const cx<R> *>(w),
+                     w_rs, n, part);
+  LQCD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_mdot_final, dim3(J, nrhs), dim3(kBlock), 0, c->stream, part, nblk, J,
+                     reinterpret_cast<cx<double> *>(out), out_rs);
+  LQCD_HIP(hipGetLastError());
+}
+
+template <class R>
+void multi_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
+                size_t coef_rs, void *w, size_t w_rs, size_t n, int nrhs, double *norm2_out) {
+  if (nrhs <= 0) return;
+  LQCD_CHECK(J <= kMaxJ, LQCD_EINVAL, "basis of %d vectors exceeds %d", J, kMaxJ);
+  const int nblk = int((n + CH - 1) / CH);
+  double *part = nullptr;
+  if (norm2_out) part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * sizeof(double)));
+  hipLaunchKernelGGL(k_maxpy<R>, dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const cx<R> *>(V), ldv, V_rs, J,
+                     reinterpret_cast<const cx<double> *>(coef), coef_rs, static_cast<cx<R> *>(w),
+                     w_rs, n, part);
+  LQCD_HIP(hipGetLastError());
+  if (norm2_out) {
+    hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(kBlock), 0, c->stream, part, nblk, norm2_out);
+    LQCD_HIP(hipGetLastError());
+  }
+}
+
+template <class R>
+void norm2(lqcd_ctx *c, const void *x, size_t x_rs, size_t n, int nrhs, double *norm2_out) {
+  if (nrhs <= 0) return;
+  const int nblk = int((n + CH - 1) / CH);
+  double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * sizeof(double)));
+  hipLaunchKernelGGL(k_norm_part<R>, dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const cx<R> *>(x), x_rs, n, part);
+  LQCD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(kBlock), 0, c->stream, part, nblk, norm2_out);
+  LQCD_HIP(hipGetLastError());
+}
+
+template <class R>
+void axpby(lqcd_ctx *c, const cdouble *a, const void *x, size_t x_rs, const cdouble *b, void *y,
+           size_t y_rs, size_t n, int nrhs, bool per_rhs) {
+  for (int r0 = 0; r0 < nrhs; r0 += kMaxScalars) {
+    int nr = std::min(kMaxScalars, nrhs - r0);
+    Scalars s;
+    for (int r = 0; r < (per_rhs ? nr : 1); ++r) {
+      s.a[r] = mk(a[per_rhs ? r0 + r : 0].real(), a[per_rhs ? r0 + r : 0].imag());
+      s.b[r] = mk(b[per_rhs ? r0 + r : 0].real(), b[per_rhs ? r0 + r : 0].imag());
+    }
+    hipLaunchKernelGGL(k_axpby<R>, dim3(grid_elems(n), nr), dim3(kBlock), 0, c->stream, s, per_rhs,
+                       static_cast<const cx<R> *>(x) + r0 * x_rs, x_rs,
+                       static_cast<cx<R> *>(y) + r0 * y_rs, y_rs, n);
+    LQCD_HIP(hipGetLastError());
+  }
+}
+
+template <class R>
+void scale_dev(lqcd_ctx *c, const void *x, size_t x_rs, const double *scale, void *y, size_t y_rs,
+               size_t n, int nrhs) {
+  if (nrhs <= 0) return;
+  hipLaunchKernelGGL(k_scale_dev<R>, dim3(grid_elems(n), nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const cx<R> *>(x), x_rs, scale, static_cast<cx<R> *>(y), y_rs, n);
+  LQCD_HIP(hipGetLastError());
+}
+
+template <class R>
+void gemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *C,
+             size_t ldc, size_t C_rs, void *Y, size_t ldy, size_t Y_rs, int nb, size_t n, int nrhs,
+             double alpha) {
+  if (nb <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_gemm_nn<R>, dim3(grid_elems(n), nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const cx<R> *>(V), ldv, V_rs, J,
+                     reinterpret_cast<const cx<double> *>(C), ldc, C_rs, static_cast<cx<R> *>(Y),
+                     ldy, Y_rs, nb, n, alpha);
+  LQCD_HIP(hipGetLastError());
+}
+
+template <class R>
+void gemm_tn(lqcd_ctx *c, const void *V, size_t ldv, int J, const void *X, size_t ldx, int nb,
+             size_t n, cdouble *C, size_t ldc) {
+  // one multi-dot per column of X (the X columns act as a batch)
+  multi_dot<R>(c, V, ldv, 0, J, X, ldx, n, nb, C, ldc);
+}
+
+template <class R>
+void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size_t ldp, int Jout,
+               size_t n) {
+  LQCD_CHECK(Jout <= Jin, LQCD_EINVAL, "recombine: Jout > Jin");
+  size_t shm = size_t(Jin) * RC_E * sizeof(cx<R>);
+  LQCD_CHECK(shm <= 160 * 1024, LQCD_EINVAL, "recombine: basis of %d vectors too large", Jin);
+  unsigned nb = unsigned((n + RC_E - 1) / RC_E);
+  hipLaunchKernelGGL(k_recombine<R>, dim3(nb), dim3(kBlock), shm, c->stream,
+                     static_cast<cx<R> *>(V), ldv, Jin, reinterpret_cast<const cx<double> *>(P),
+                     ldp, Jout, n);
+  LQCD_HIP(hipGetLastError());
+}
+
+#define INST(R)                                                                                   \
+  template void multi_dot<R>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
+                             size_t, int, cdouble *, size_t);                                     \
+  template void multi_axpy<R>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,     \
+                              size_t, void *, size_t, size_t, int, double *);                     \
+  template void norm2<R>(lqcd_ctx *, const void *, size_t, size_t, int, double *);                \
+  template void axpby<R>(lqcd_ctx *, const cdouble *, const void *, size_t, const cdouble *,      \
+                         void *, size_t, size_t, int, bool);                                      \
+  template void scale_dev<R>(lqcd_ctx *, const void *, size_t, const double *, void *, size_t,    \
+                             size_t, int);                                                        \
+  template void gemm_nn<R>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,        \
+                           size_t, size_t, void *, size_t, size_t, int, size_t, int, double);     \
+  template void gemm_tn<R>(lqcd_ctx *, const void *, size_t, int, const void *, size_t, int,      \
+                           size_t, cdouble *, size_t);                                            \
+  template void recombine<R>(lqcd_ctx *, void *, size_t, int, const cdouble *, size_t, int, size_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace lqcd

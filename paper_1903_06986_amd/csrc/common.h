@@ -1,0 +1,162 @@
+// Internal declarations of the gfx950 library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/lqcd.h"
+
+namespace lqcd {
+
+using cdouble = std::complex<double>;
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+
+struct Error {
+  lqcd_status code;
+};
+
+#define LQCD_HIP(call)                                                                 \
+  do {                                                                                 \
+    hipError_t _e = (call);                                                            \
+    if (_e != hipSuccess) {                                                            \
+      ::lqcd::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call, hipGetErrorString(_e)); \
+      throw ::lqcd::Error{LQCD_EDEVICE};                                               \
+    }                                                                                  \
+  } while (0)
+
+#define LQCD_CHECK(cond, code, ...)    \
+  do {                                 \
+    if (!(cond)) {                     \
+      ::lqcd::set_error(__VA_ARGS__);  \
+      throw ::lqcd::Error{code};       \
+    }                                  \
+  } while (0)
+
+// Runs f(), converting exceptions to a status (nothing crosses the ABI).
+template <class F>
+lqcd_status guarded(F &&f) {
+  try {
+    f();
+    return LQCD_OK;
+  } catch (const Error &e) {
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_error("host allocation failed");
+    return LQCD_ENOMEM;
+  } catch (...) {
+    set_error("unexpected C++ exception");
+    return LQCD_EDEVICE;
+  }
+}
+
+// -------------------------------------------------------- device buffers
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  // Grow (never shrink) to at least `need` bytes; contents are not kept.
+  void *ensure(size_t need) {
+    if (need <= bytes) return ptr;
+    release();
+    hipError_t e = hipMalloc(&ptr, need);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      set_error("hipMalloc(%zu bytes) failed: %s", need, hipGetErrorString(e));
+      throw Error{LQCD_ENOMEM};
+    }
+    bytes = need;
+    return ptr;
+  }
+  template <class T>
+  T *as() const { return static_cast<T *>(ptr); }
+};
+
+// ------------------------------------------------------------ geometry
+struct Geom {
+  int L[4];   // Lx, Ly, Lz, Lt
+  int V, Vh;  // volume, half volume
+  int Lxh;    // Lx / 2
+};
+
+// Precomputed table of Tr_t(Theta P^j) for j <= kMaxOrder (closed walks).
+constexpr int kMaxOrder = 7;
+constexpr int kNumTheta = 5;
+
+}  // namespace lqcd
+
+// The opaque context of the C ABI.
+struct lqcd_ctx {
+  lqcd::Geom g;
+  double kappa;
+  hipStream_t stream;
+  int device;
+  // Links in the even/odd layout [parity][mu][9][Vh] of complex numbers
+  // (row-major 3x3), FP64 and FP32.
+  lqcd::DevBuf U64, U32;
+  // Exact per-timeslice traces Tr_t(Theta P^j), j = 0..kMaxOrder,
+  // Theta = 1, g1..g4: host [j][theta][Lt], filled on first use.
+  bool have_walk_traces = false;
+  std::vector<lqcd::cdouble> walk_traces;
+  // Scratch buffers reused across calls (grown on demand).
+  lqcd::DevBuf ws[8];
+  lqcd::DevBuf red;      // reduction partials
+  lqcd::DevBuf red_out;  // reduction results (device)
+};
+
+namespace lqcd {
+
+// ------------------------------------------------------------- launches
+constexpr int kBlock = 256;
+inline unsigned nblocks(size_t n, int block = kBlock) {
+  return static_cast<unsigned>((n + block - 1) / block);
+}
+
+// ---------------------------------------------------- field-level helpers
+// Element counts: a half field (one parity) holds 12 * Vh complex numbers,
+// a full field 24 * Vh = 12 V.
+inline size_t half_len(const Geom &g) { return size_t(12) * g.Vh; }
+inline size_t full_len(const Geom &g) { return size_t(12) * g.V; }
+
+// dslash.hip ------------------------------------------------------------
+// Generic stencil on even/odd fields of real type R (double or float):
+//   out_p = G_out( alpha * G_in(self_p) + beta * D_{p,1-p} G_in(in_{1-p}) )
+// for output parity p (out, self, in are half fields of Vh sites, in of the
+// opposite parity), over nrhs right-hand sides with the given strides
+// (in complex elements).  G = g5 when the flag is set.  self may be null.
+template <class R>
+void hop_half(lqcd_ctx *c, int out_parity, const void *in, const void *self, void *out,
+              cdouble alpha, double beta, bool g5_in, bool g5_out, int nrhs,
+              size_t in_stride, size_t self_stride, size_t out_stride);
+
+// Operators on internal fields (precision R).  Full fields are [2][12][Vh]
+// per rhs (even block first); Schur fields are [12][Vh] (even sites).
+template <class R>
+void apply_full(lqcd_ctx *c, lqcd_op op, const void *in, void *out, int nrhs,
+                size_t stride_in, size_t stride_out);
+template <class R>
+void apply_schur(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs,
+                 size_t stride_in, size_t stride_out, size_t stride_tmp);
+
+// fields.hip -----------------------------------------------------------
+template <class R>
+void pack_eo(lqcd_ctx *c, const void *lex, void *eo, int nrhs, size_t eo_stride);
+template <class R>
+void unpack_eo(lqcd_ctx *c, const void *eo, void *lex, int nrhs, size_t eo_stride);
+void fill_noise(lqcd_ctx *c, uint64_t seed, int64_t first, int nrhs, void *eta, uint8_t *codes);
+
+}  // namespace lqcd

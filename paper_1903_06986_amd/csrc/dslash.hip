@@ -1,0 +1,364 @@
+// Wilson hopping stencil (Sec. 5.1 Eqs. (24)-(25)) on even/odd fields.
+//
+//   (P psi)(x) = sum_mu [ (1 - g_mu) U_mu(x) psi(x + mu)
+//                       + (1 + g_mu) U_mu(x - mu)^+ psi(x - mu) ]
+//
+// In the chiral basis (g_k = [[0, -i s_k], [i s_k, 0]], g_4 = [[0,1],[1,0]])
+// every (1 -+ g_mu) has rank 2: with psi = (u, l) in upper/lower spin
+// pairs, (1 - g_mu) psi = (h, R h) where h = u + i s_k l (h = u - l for
+// mu = t) and R = -i s_k (R = -1 for t); (1 + g_mu) psi = (h', R' h') with
+// h' = u - i s_k l (u + l), R' = +i s_k (+1).  The link therefore acts on a
+// two-spin "half spinor" only (6 complex), and the lower spins are rebuilt
+// from the product.
+//
+// Data layout (per right-hand side, per parity): component-major
+// [12][Vh] complex, component c = spin * 3 + colour, so that a wavefront
+// loading one component of 64 consecutive sites reads one contiguous
+// 1 KiB (FP64) segment.  Links: [parity][mu][9][Vh].
+#include "common.h"
+#include "cplx.h"
+#include "fields.h"
+
+namespace lqcd {
+
+namespace {
+
+template <class R>
+struct Half {
+  cx<R> h[2][3];  // [spin 0/1][colour]
+};
+
+// U h (forward) and U^+ h (backward) on each of the two spins of a half
+// spinor; u points at entry 0 of the link, entries are Vh apart.
+template <class R>
+__device__ inline void link_mul(const cx<R> * u, size_t Vh, const Half<R> &in,
+                                Half<R> &out) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<R> u0 = ldc(u + (3 * a + 0) * Vh), u1 = ldc(u + (3 * a + 1) * Vh),
+          u2 = ldc(u + (3 * a + 2) * Vh);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) out.h[s][a] = u0 * in.h[s][0] + u1 * in.h[s][1] + u2 * in.h[s][2];
+  }
+}
+template <class R>
+__device__ inline void link_dag_mul(const cx<R> * u, size_t Vh, const Half<R> &in,
+                                    Half<R> &out) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out.h[s][a] = mk<R>(0, 0);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    cx<R> u0 = ldc(u + (3 * b + 0) * Vh), u1 = ldc(u + (3 * b + 1) * Vh),
+          u2 = ldc(u + (3 * b + 2) * Vh);
+    // (U^+ h)_a = sum_b conj(U_ba) h_b
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      out.h[s][0] = out.h[s][0] + cmulc(u0, in.h[s][b]);
+      out.h[s][1] = out.h[s][1] + cmulc(u1, in.h[s][b]);
+      out.h[s][2] = out.h[s][2] + cmulc(u2, in.h[s][b]);
+    }
+  }
+}
+
+// Project psi (12 components at stride Vh from p) for direction MU and sign
+// (FWD: 1 - g_mu, else 1 + g_mu).  G5 applies g5 = diag(1,1,-1,-1) first.
+template <class R, int MU, bool FWD, bool G5>
+__device__ inline void project(const cx<R> * p, size_t Vh, Half<R> &o) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cx<R> u0 = ldc(p + (0 * 3 + c) * Vh), u1 = ldc(p + (1 * 3 + c) * Vh);
+    cx<R> l0 = ldc(p + (2 * 3 + c) * Vh), l1 = ldc(p + (3 * 3 + c) * Vh);
+    if (G5) {
+      l0 = -l0;
+      l1 = -l1;
+    }
+    // FWD: h = u + i s_k l ; BWD: h = u - i s_k l ; t: h = u -+ l
+    if (MU == 0) {  // i s_1 l = (i l1, i l0)
+      o.h[0][c] = FWD ? u0 + iz(l1) : u0 - iz(l1);
+      o.h[1][c] = FWD ? u1 + iz(l0) : u1 - iz(l0);
+    } else if (MU == 1) {  // i s_2 l = (l1, -l0)
+      o.h[0][c] = FWD ? u0 + l1 : u0 - l1;
+      o.h[1][c] = FWD ? u1 - l0 : u1 + l0;
+    } else if (MU == 2) {  // i s_3 l = (i l0, -i l1)
+      o.h[0][c] = FWD ? u0 + iz(l0) : u0 - iz(l0);
+      o.h[1][c] = FWD ? u1 - iz(l1) : u1 + iz(l1);
+    } else {  // t
+      o.h[0][c] = FWD ? u0 - l0 : u0 + l0;
+      o.h[1][c] = FWD ? u1 - l1 : u1 + l1;
+    }
+  }
+}
+
+// acc += (g, R g) for direction MU, sign FWD (R = -i s_k / +i s_k / -+1).
+template <class R, int MU, bool FWD>
+__device__ inline void accumulate(cx<R> acc[4][3], const Half<R> &g) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cx<R> g0 = g.h[0][c], g1 = g.h[1][c];
+    acc[0][c] = acc[0][c] + g0;
+    acc[1][c] = acc[1][c] + g1;
+    cx<R> r0, r1;
+    if (MU == 0) {  // -i s_1 g = (-i g1, -i g0); +i s_1 g = (i g1, i g0)
+      r0 = FWD ? miz(g1) : iz(g1);
+      r1 = FWD ? miz(g0) : iz(g0);
+    } else if (MU == 1) {  // -i s_2 g = (-g1, g0); +i s_2 g = (g1, -g0)
+      r0 = FWD ? -g1 : g1;
+      r1 = FWD ? g0 : -g0;
+    } else if (MU == 2) {  // -i s_3 g = (-i g0, i g1); +i s_3 g = (i g0, -i g1)
+      r0 = FWD ? miz(g0) : iz(g0);
+      r1 = FWD ? iz(g1) : miz(g1);
+    } else {  // -g / +g
+      r0 = FWD ? -g0 : g0;
+      r1 = FWD ? -g1 : g1;
+    }
+    acc[2][c] = acc[2][c] + r0;
+    acc[3][c] = acc[3][c] + r1;
+  }
+}
+
+// Scheduling fence: forces the accumulators to be final here and keeps the
+// next direction's loads after it.  Without it the compiler issues all
+// eight neighbours' loads first and delays the arithmetic, so every loaded
+// value stays live and the register file overflows.  The empty asm only
+// names registers; it emits no instruction.
+template <class R>
+__device__ inline void fence(cx<R> acc[4][3]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) asm volatile("" : "+v"(acc[s][c].re), "+v"(acc[s][c].im)::"memory");
+}
+
+template <class R, int MU, bool G5IN>
+__device__ inline void hop_dir(cx<R> acc[4][3], const cx<R> * U,
+                               const cx<R> * in, int p, int i, int nf, int nb,
+                               size_t Vh) {
+  Half<R> h, g;
+  // forward: (1 - g_mu) U_mu(x) psi(x + mu); the link lives at x (parity p)
+  project<R, MU, true, G5IN>(in + nf, Vh, h);
+  link_mul<R>(U + ((size_t(p) * 4 + MU) * 9) * Vh + i, Vh, h, g);
+  accumulate<R, MU, true>(acc, g);
+  fence(acc);
+  // backward: (1 + g_mu) U_mu(x - mu)^+ psi(x - mu); link at x - mu (parity 1-p)
+  project<R, MU, false, G5IN>(in + nb, Vh, h);
+  link_dag_mul<R>(U + ((size_t(1 - p) * 4 + MU) * 9) * Vh + nb, Vh, h, g);
+  accumulate<R, MU, false>(acc, g);
+  fence(acc);
+}
+
+template <class R, bool G5IN, bool G5OUT, bool SELF>
+// 3 waves per SIMD caps FP64 at 128 VGPRs (4 waves resident, no spills).
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8)))
+    k_hop(Geom g, int p, const cx<R> * U, const cx<R> * in,
+          const cx<R> * self, cx<R> *out, cx<R> alpha, R beta,
+          size_t in_stride, size_t self_stride, size_t out_stride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.Vh) return;
+  const size_t Vh = size_t(g.Vh);
+  const size_t rhs = blockIdx.y;
+  in += rhs * in_stride;
+  out += rhs * out_stride;
+  const int Lxh = g.Lxh, Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+  const int xh = i % Lxh;
+  int r = i / Lxh;
+  const int y = r % Ly;
+  r /= Ly;
+  const int z = r % Lz;
+  const int t = r / Lz;
+  const int x = 2 * xh + ((p + y + z + t) & 1);
+  const int rowb = i - xh;
+
+  cx<R> acc[4][3];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[s][c] = mk<R>(0, 0);
+
+  {  // x
+    int xf = (x + 1 == Lx) ? 0 : x + 1, xb = (x == 0) ? Lx - 1 : x - 1;
+    hop_dir<R, 0, G5IN>(acc, U, in, p, i, rowb + (xf >> 1), rowb + (xb >> 1), Vh);
+  }
+  {  // y
+    const int s = Lxh;
+    int nf = (y == Ly - 1) ? i - s * (Ly - 1) : i + s;
+    int nb = (y == 0) ? i + s * (Ly - 1) : i - s;
+    hop_dir<R, 1, G5IN>(acc, U, in, p, i, nf, nb, Vh);
+  }
+  {  // z
+    const int s = Lxh * Ly;
+    int nf = (z == Lz - 1) ? i - s * (Lz - 1) : i + s;
+    int nb = (z == 0) ? i + s * (Lz - 1) : i - s;
+    hop_dir<R, 2, G5IN>(acc, U, in, p, i, nf, nb, Vh);
+  }
+  {  // t
+    const int s = Lxh * Ly * Lz;
+    int nf = (t == Lt - 1) ? i - s * (Lt - 1) : i + s;
+    int nb = (t == 0) ? i + s * (Lt - 1) : i - s;
+    hop_dir<R, 3, G5IN>(acc, U, in, p, i, nf, nb, Vh);
+  }
+
+  const cx<R> *sp = SELF ? self + rhs * self_stride + i : nullptr;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      cx<R> v = beta * acc[s][c];
+      if (SELF) {
+        cx<R> w = ldc(sp + (s * 3 + c) * Vh);
+        if (G5IN && s >= 2) w = -w;
+        v = v + alpha * w;
+      }
+      if (G5OUT && s >= 2) v = -v;
+      stc(out + (s * 3 + c) * Vh + i, v);
+    }
+}
+
+template <class R, bool A, bool B, bool C>
+void launch_hop(lqcd_ctx *c, int p, const void *in, const void *self, void *out, cdouble alpha,
+                double beta, int nrhs, size_t si, size_t ss, size_t so) {
+  const Geom &g = c->g;
+  const cx<R> *U = static_cast<const cx<R> *>(std::is_same<R, double>::value ? c->U64.ptr : c->U32.ptr);
+  dim3 grid(nblocks(g.Vh), nrhs);
+  hipLaunchKernelGGL((k_hop<R, A, B, C>), grid, dim3(kBlock), 0, c->stream, g, p, U,
+                     static_cast<const cx<R> *>(in), static_cast<const cx<R> *>(self),
+                     static_cast<cx<R> *>(out), mk<R>(R(alpha.real()), R(alpha.imag())), R(beta),
+                     si, ss, so);
+  LQCD_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+template <class R>
+void hop_half(lqcd_ctx *c, int p, const void *in, const void *self, void *out, cdouble alpha,
+              double beta, bool g5_in, bool g5_out, int nrhs, size_t si, size_t ss, size_t so) {
+  if (nrhs <= 0) return;
+  const bool hs = self != nullptr;
+  if (!g5_in && !g5_out) {
+    if (hs) launch_hop<R, false, false, true>(c, p, in, self, out, alpha, beta, nrhs, si, ss, so);
+    else launch_hop<R, false, false, false>(c, p, in, self, out, alpha, beta, nrhs, si, ss, so);
+  } else if (g5_in && !g5_out) {
+    if (hs) launch_hop<R, true, false, true>(c, p, in, self, out, alpha, beta, nrhs, si, ss, so);
+    else launch_hop<R, true, false, false>(c, p, in, self, out, alpha, beta, nrhs, si, ss, so);
+  } else if (g5_in && g5_out) {
+    if (hs) launch_hop<R, true, true, true>(c, p, in, self, out, alpha, beta, nrhs, si, ss, so);
+    else launch_hop<R, true, true, false>(c, p, in, self, out, alpha, beta, nrhs, si, ss, so);
+  } else {
+    if (hs) launch_hop<R, false, true, true>(c, p, in, self, out, alpha, beta, nrhs, si, ss, so);
+    else launch_hop<R, false, true, false>(c, p, in, self, out, alpha, beta, nrhs, si, ss, so);
+  }
+}
+
+// Full-lattice operators: per rhs the field is [even half][odd half].
+template <class R>
+void apply_full(lqcd_ctx *c, lqcd_op op, const void *in, void *out, int nrhs, size_t sin,
+                size_t sout) {
+  const size_t hl = half_len(c->g);
+  const double k = c->kappa;
+  const R *ib = static_cast<const R *>(in);
+  R *ob = static_cast<R *>(out);
+  for (int p = 0; p < 2; ++p) {
+    const void *src = ib + 2 * hl * (1 - p);  // opposite parity of the input
+    const void *slf = ib + 2 * hl * p;
+    void *dst = ob + 2 * hl * p;
+    switch (op) {
+      case LQCD_OP_HOP:
+        hop_half<R>(c, p, src, nullptr, dst, cdouble(0, 0), 1.0, false, false, nrhs, sin, 0, sout);
+        break;
+      case LQCD_OP_M:
+        hop_half<R>(c, p, src, slf, dst, cdouble(1, 0), -k, false, false, nrhs, sin, sin, sout);
+        break;
+      case LQCD_OP_MG5:
+        hop_half<R>(c, p, src, slf, dst, cdouble(1, 0), -k, true, false, nrhs, sin, sin, sout);
+        break;
+      case LQCD_OP_MDAG:
+        hop_half<R>(c, p, src, slf, dst, cdouble(1, 0), -k, true, true, nrhs, sin, sin, sout);
+        break;
+      default:
+        LQCD_CHECK(false, LQCD_EINVAL, "apply_full: operator %d is not a full-lattice operator", int(op));
+    }
+  }
+}
+
+// Mhat x_e = x_e - kappa^2 D_eo D_oe x_e  (Sec. 7 even/odd reduction).
+template <class R>
+void apply_schur(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin,
+                 size_t sout, size_t stmp) {
+  const double k = c->kappa;
+  hop_half<R>(c, 1, in, nullptr, tmp_odd, cdouble(0, 0), 1.0, false, false, nrhs, sin, 0, stmp);
+  hop_half<R>(c, 0, tmp_odd, in, out, cdouble(1, 0), -k * k, false, false, nrhs, stmp, sin, sout);
+}
+
+template void hop_half<double>(lqcd_ctx *, int, const void *, const void *, void *, cdouble, double,
+                               bool, bool, int, size_t, size_t, size_t);
+template void hop_half<float>(lqcd_ctx *, int, const void *, const void *, void *, cdouble, double,
+                              bool, bool, int, size_t, size_t, size_t);
+template void apply_full<double>(lqcd_ctx *, lqcd_op, const void *, void *, int, size_t, size_t);
+template void apply_full<float>(lqcd_ctx *, lqcd_op, const void *, void *, int, size_t, size_t);
+template void apply_schur<double>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
+template void apply_schur<float>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
+
+}  // namespace lqcd
+
+using namespace lqcd;
+
+namespace {
+
+size_t prec_bytes(lqcd_prec p) { return p == LQCD_F64 ? 16 : 8; }
+
+template <class R>
+void wilson_apply_t(lqcd_ctx *c, lqcd_op op, lqcd_layout layout, const void *in, void *out,
+                    int nrhs) {
+  const size_t hl = half_len(c->g);
+  if (layout == LQCD_LAYOUT_EO) {
+    if (op == LQCD_OP_SCHUR) {
+      void *tmp = c->ws[7].ensure(hl * nrhs * sizeof(cx<R>));
+      apply_schur<R>(c, in, out, tmp, nrhs, hl, hl, hl);
+    } else {
+      apply_full<R>(c, op, in, out, nrhs, 2 * hl, 2 * hl);
+    }
+    return;
+  }
+  // LEX: pack -> apply -> unpack, in blocks of right-hand sides so the
+  // scratch stays bounded.
+  const int blk = std::max(1, std::min(nrhs, 16));
+  void *a = c->ws[5].ensure(2 * hl * blk * sizeof(cx<R>));
+  void *b = c->ws[6].ensure(2 * hl * blk * sizeof(cx<R>));
+  const size_t fl = full_len(c->g);
+  for (int r0 = 0; r0 < nrhs; r0 += blk) {
+    int nb = std::min(blk, nrhs - r0);
+    const cdouble *src = static_cast<const cdouble *>(in) + r0 * fl;
+    cdouble *dst = static_cast<cdouble *>(out) + r0 * fl;
+    pack_eo<R>(c, src, a, nb, 2 * hl);
+    if (op == LQCD_OP_SCHUR) {
+      void *tmp = c->ws[7].ensure(hl * blk * sizeof(cx<R>));
+      // even block of a -> even block of b; odd block of b zeroed
+      apply_schur<R>(c, a, b, tmp, nb, 2 * hl, 2 * hl, hl);
+      for (int r = 0; r < nb; ++r)
+        fill_zero(c, static_cast<cx<R> *>(b) + (2 * r + 1) * hl, hl * sizeof(cx<R>));
+    } else {
+      apply_full<R>(c, op, a, b, nb, 2 * hl, 2 * hl);
+    }
+    unpack_eo<R>(c, b, dst, nb, 2 * hl);
+  }
+}
+
+}  // namespace
+
+extern "C" lqcd_status wilson_apply(lqcd_ctx *c, lqcd_op op, lqcd_prec prec, lqcd_layout layout,
+                                    const void *in, void *out, int nrhs) {
+  return guarded([&] {
+    LQCD_CHECK(c && in && out, LQCD_EINVAL, "wilson_apply: null argument");
+    LQCD_CHECK(nrhs >= 0, LQCD_EINVAL, "wilson_apply: nrhs < 0");
+    LQCD_CHECK(op >= LQCD_OP_M && op <= LQCD_OP_SCHUR, LQCD_EINVAL, "wilson_apply: bad operator");
+    LQCD_CHECK(layout == LQCD_LAYOUT_LEX || layout == LQCD_LAYOUT_EO, LQCD_EINVAL,
+               "wilson_apply: bad layout");
+    LQCD_CHECK(in != out, LQCD_EINVAL, "wilson_apply: in and out must differ");
+    if (nrhs == 0) return;
+    if (prec == LQCD_F64) wilson_apply_t<double>(c, op, layout, in, out, nrhs);
+    else if (prec == LQCD_F32) wilson_apply_t<float>(c, op, layout, in, out, nrhs);
+    else LQCD_CHECK(false, LQCD_EINVAL, "wilson_apply: precision %d not available", int(prec));
+    (void)prec_bytes;
+  });
+}

@@ -1,0 +1,69 @@
+// Vector kernels used by the solvers and the subtraction code.
+//
+// A "vector" is n complex numbers of real type R (double or float) stored
+// contiguously; batched calls act on nrhs vectors that are `rs` complex
+// elements apart.  A "basis" is J vectors ldv elements apart (per rhs).
+// All reductions accumulate in FP64 and are deterministic: every block
+// writes its partial sums and a second kernel adds them in a fixed order.
+#pragma once
+
+#include "common.h"
+
+namespace lqcd {
+
+void fill_zero(lqcd_ctx *c, void *p, size_t bytes);
+template <class RI, class RO>
+void convert(lqcd_ctx *c, const void *in, void *out, size_t n);
+
+// Strided batch descriptor (complex-element strides).
+struct Batch {
+  int nrhs;
+  size_t rs;  // distance between the vectors of consecutive right-hand sides
+};
+
+// out[r * out_rs + j] = sum_i conj(V_r[j][i]) w_r[i], j < J   (device cdouble)
+template <class R>
+void multi_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w,
+               size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs);
+
+// w_r[i] -= sum_j V_r[j][i] coef[r * coef_rs + j]; if norm2_out is not null,
+// norm2_out[r] = |w_r|^2 after the update (device doubles).
+template <class R>
+void multi_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J,
+                const cdouble *coef, size_t coef_rs, void *w, size_t w_rs, size_t n, int nrhs,
+                double *norm2_out);
+
+// norm2_out[r] = |x_r|^2
+template <class R>
+void norm2(lqcd_ctx *c, const void *x, size_t x_rs, size_t n, int nrhs, double *norm2_out);
+
+// y_r = a_r * x_r + b_r * y_r with host complex scalars (arrays of nrhs, or
+// a single value broadcast when the pointer's count is 1).
+template <class R>
+void axpby(lqcd_ctx *c, const cdouble *a, const void *x, size_t x_rs, const cdouble *b, void *y,
+           size_t y_rs, size_t n, int nrhs, bool per_rhs);
+
+// y_r = x_r * scale_dev[r]   (device scale; e.g. 1 / |w| for Arnoldi)
+template <class R>
+void scale_dev(lqcd_ctx *c, const void *x, size_t x_rs, const double *scale, void *y,
+               size_t y_rs, size_t n, int nrhs);
+
+// Y_r[b][i] += sum_j V_r[j][i] C_r[j][b]  (C column-major with leading
+// dimension ldc, per-rhs stride C_rs; device complex); alpha = +1 or -1.
+template <class R>
+void gemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *C,
+             size_t ldc, size_t C_rs, void *Y, size_t ldy, size_t Y_rs, int nb, size_t n,
+             int nrhs, double alpha);
+
+// C[j + ldc * b] = sum_i conj(V[j][i]) X[b][i] for j < J, b < nb (device).
+template <class R>
+void gemm_tn(lqcd_ctx *c, const void *V, size_t ldv, int J, const void *X, size_t ldx, int nb,
+             size_t n, cdouble *C, size_t ldc);
+
+// In place: V[j] <- sum_l V[l] P[l + ldp * j], j < Jout, over Jin input
+// vectors (Jout <= Jin); P device complex.
+template <class R>
+void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size_t ldp, int Jout,
+               size_t n);
+
+}  // namespace lqcd

@@ -1,0 +1,294 @@
+"""Python binding of the gfx950 C ABI in ``include/lqcd.h`` (ctypes).
+
+Argument marshalling only: every computation runs in ``liblqcd.so``.  Field
+arguments are torch tensors on the GPU (complex128, lexicographic layout
+[rhs][t][z][y][x][spin][colour] unless stated otherwise); torch supplies the
+device memory and the stream, nothing else.  The library must have been
+built (``paper_1903_06986_amd.build``); there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblqcd.so")
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+OP_M, OP_MDAG, OP_MG5, OP_HOP, OP_SCHUR = 0, 1, 2, 3, 4
+LAYOUT_LEX, LAYOUT_EO = 0, 1
+NS, PS, POLY, HFES, HFPS, HFPOLY = 0, 1, 2, 3, 4, 5
+DEFL_HFES, DEFL_EIGPOLY = 0, 1
+_PREC = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
+_OPS = {"M": OP_M, "Mdag": OP_MDAG, "MG5": OP_MG5, "hop": OP_HOP, "schur": OP_SCHUR}
+
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "EBREAKDOWN", 6: "ENAN"}
+
+
+class LqcdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("k", ctypes.c_int), ("max_cycles", ctypes.c_int),
+                ("tol", ctypes.c_double), ("tol_super", ctypes.c_double),
+                ("eig_tol", ctypes.c_double), ("n_eig", ctypes.c_int),
+                ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("rhs_block", ctypes.c_int)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("matvecs", ctypes.c_int), ("cycles", ctypes.c_int),
+                ("refinements", ctypes.c_int), ("true_resid", ctypes.c_double)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_SIGS = {
+    "lqcd_create": [ctypes.POINTER(ctypes.c_int), _P, _D, _P, ctypes.POINTER(_P)],
+    "lqcd_set_kappa": [_P, _D],
+    "lqcd_set_stream": [_P, _P],
+    "lqcd_destroy": [_P],
+    "lqcd_noise_z4": [_P, ctypes.c_uint64, ctypes.c_int64, _I, _P, _P],
+    "lqcd_pack_eo": [_P, _I, _P, _P, _I],
+    "lqcd_unpack_eo": [_P, _I, _P, _P, _I],
+    "wilson_apply": [_P, _I, _I, _I, _P, _P, _I],
+    "gmresdr_solve": [_P, _I, ctypes.POINTER(SolveParams), _P, _P, _I, ctypes.POINTER(_P),
+                      ctypes.POINTER(SolveStats)],
+    "lqcd_defl_eigpairs": [_P, _P, _I, _P, _P],
+    "lqcd_defl_ritz": [_P, _P, ctypes.POINTER(ctypes.c_int)],
+    "deflate_project": [_P, _P, _I, _I, _P, _I, _P, _I, _P, _P, _I, _P, _P],
+    "pert_subtract": [_P, _I, _P, _I, _P, _P, _I, _P],
+    "poly_subtract": [_P, _I, _P, _P, _P, _P, _I, _P, _P, _I, _P],
+    "loop_estimate": [_P, _P, _I, _P, _P, _P, _I, _P, _P, _P, _P],
+}
+
+
+def lib():
+    """Load liblqcd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblqcd.so is not built (%s); run paper_1903_06986_amd.build.build()"
+                           % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.lqcd_defl_free.argtypes = [_P]
+    L.lqcd_defl_free.restype = None
+    L.lqcd_last_error.argtypes = []
+    L.lqcd_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != 0:
+        raise LqcdError(code, lib().lqcd_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("field tensors must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("field tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _thetas(thetas):
+    t = np.ascontiguousarray(np.asarray(thetas, dtype=np.int32))
+    return t, t.ctypes.data_as(ctypes.c_void_p), len(t)
+
+
+class Deflation:
+    """Owns an lqcd_defl handle (deflation space of one operator)."""
+
+    def __init__(self, handle, ctx):
+        self.handle = handle
+        self.ctx = ctx
+
+    def eigpairs(self, Q):
+        lam = np.zeros(Q)
+        res = np.zeros(Q)
+        _check(lib().lqcd_defl_eigpairs(self.ctx.handle, self.handle, Q,
+                                        lam.ctypes.data_as(_P), res.ctypes.data_as(_P)))
+        return lam, res
+
+    def ritz(self):
+        k = ctypes.c_int(0)
+        buf = np.zeros(1024, dtype=np.complex128)
+        _check(lib().lqcd_defl_ritz(self.handle, buf.ctypes.data_as(_P), ctypes.byref(k)))
+        return buf[:k.value].copy()
+
+    def free(self):
+        if self.handle:
+            lib().lqcd_defl_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """A lattice, its links on the GPU and a hopping parameter."""
+
+    def __init__(self, dims, links, kappa, stream=None):
+        import torch
+        self.dims = tuple(int(d) for d in dims)
+        Lx, Ly, Lz, Lt = self.dims
+        self.V = Lx * Ly * Lz * Lt
+        self.shape = (Lt, Lz, Ly, Lx, 4, 3)
+        self.kappa = float(kappa)
+        U, Up = _host(links, np.complex128)
+        if U.size != self.V * 36:
+            raise ValueError("links must hold V*4*3*3 complex numbers")
+        d = (ctypes.c_int * 4)(*self.dims)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = _P()
+        _check(lib().lqcd_create(d, Up, self.kappa, _P(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lqcd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_kappa(self, kappa):
+        self.kappa = float(kappa)
+        _check(lib().lqcd_set_kappa(self.handle, self.kappa))
+
+    # ------------------------------------------------------------ fields
+    def empty(self, nrhs):
+        import torch
+        return torch.empty((nrhs,) + self.shape, dtype=torch.complex128, device="cuda")
+
+    def noise_z4(self, seed, first, nrhs, codes=False):
+        import torch
+        eta = self.empty(nrhs)
+        cd = torch.empty((nrhs,) + self.shape, dtype=torch.uint8, device="cuda") if codes else None
+        _check(lib().lqcd_noise_z4(self.handle, ctypes.c_uint64(seed), first, nrhs, _ptr(eta), _ptr(cd)))
+        return (eta, cd) if codes else eta
+
+    def pack_eo(self, x, prec="f64"):
+        import torch
+        dt = torch.complex128 if prec == "f64" else torch.complex64
+        out = torch.empty((x.shape[0], 2, 12, self.V // 2), dtype=dt, device="cuda")
+        _check(lib().lqcd_pack_eo(self.handle, _PREC[prec], _ptr(x), _ptr(out), x.shape[0]))
+        return out
+
+    def unpack_eo(self, eo, prec="f64"):
+        out = self.empty(eo.shape[0])
+        _check(lib().lqcd_unpack_eo(self.handle, _PREC[prec], _ptr(eo), _ptr(out), eo.shape[0]))
+        return out
+
+    def wilson_apply(self, op, x, prec="f64", layout="lex", out=None):
+        import torch
+        if x.numel() != x.shape[0] * 12 * self.V:
+            raise ValueError("field size does not match the lattice")
+        if out is None:
+            out = torch.empty_like(x)
+        lay = LAYOUT_LEX if layout == "lex" else LAYOUT_EO
+        _check(lib().wilson_apply(self.handle, _OPS[op], _PREC[prec], lay, _ptr(x), _ptr(out), x.shape[0]))
+        return out
+
+    # ----------------------------------------------------------- solvers
+    def gmresdr_solve(self, b, op="schur", m=20, k=10, tol=1e-10, tol_super=1e-13, eig_tol=0.0,
+                      n_eig=0, max_cycles=1000, inner="f64", inner_tol=1e-5, rhs_block=1,
+                      defl=None):
+        import torch
+        x = torch.empty_like(b)
+        nrhs = b.shape[0]
+        p = SolveParams(m, k, max_cycles, tol, tol_super, eig_tol, n_eig, _PREC[inner], inner_tol,
+                        rhs_block)
+        stats = (SolveStats * max(nrhs, 1))()
+        h = _P(defl.handle if defl is not None else None)
+        code = lib().gmresdr_solve(self.handle, _OPS[op], ctypes.byref(p), _ptr(b), _ptr(x), nrhs,
+                                   ctypes.byref(h), stats)
+        newdefl = Deflation(h, self) if (defl is None and h.value) else defl
+        _check(code)
+        st = [dict(matvecs=s.matvecs, cycles=s.cycles, refinements=s.refinements,
+                   true_resid=s.true_resid) for s in stats[:nrhs]]
+        return x, newdefl, st
+
+    # --------------------------------------------------------- subtraction
+    def pert_subtract(self, order, eta, thetas=(0, 1, 2, 3, 4), want_corr=True):
+        import torch
+        xt = torch.empty_like(eta)
+        th, thp, nth = _thetas(thetas)
+        corr = np.zeros((nth, self.dims[3]), dtype=np.complex128)
+        _check(lib().pert_subtract(self.handle, order, thp, nth, _ptr(eta), _ptr(xt), eta.shape[0],
+                                   corr.ctypes.data_as(_P) if want_corr else None))
+        return xt, corr
+
+    def poly_subtract(self, degree, eta, b=None, coeffs=None, thetas=(0, 1, 2, 3, 4), want_corr=True):
+        import torch
+        xt = torch.empty_like(eta)
+        th, thp, nth = _thetas(thetas)
+        c = np.zeros(degree + 1, dtype=np.complex128) if coeffs is None else \
+            np.ascontiguousarray(coeffs, dtype=np.complex128).copy()
+        a = np.zeros(degree + 1, dtype=np.complex128)
+        corr = np.zeros((nth, self.dims[3]), dtype=np.complex128)
+        _check(lib().poly_subtract(self.handle, degree, _ptr(b), c.ctypes.data_as(_P),
+                                   a.ctypes.data_as(_P), thp, nth, _ptr(eta), _ptr(xt), eta.shape[0],
+                                   corr.ctypes.data_as(_P) if want_corr else None))
+        return xt, corr, c, a
+
+    def deflate_project(self, defl, Q, eta, xt=None, corr=None, mode=DEFL_HFES, coeffs=None,
+                        thetas=(0, 1, 2, 3, 4)):
+        import torch
+        th, thp, nth = _thetas(thetas)
+        if xt is None:
+            xt = torch.zeros_like(eta)
+        corr = np.zeros((nth, self.dims[3]), dtype=np.complex128) if corr is None else \
+            np.ascontiguousarray(corr, dtype=np.complex128).copy()
+        cf, cfp = (None, None) if coeffs is None else _host(coeffs, np.complex128)
+        xi = np.zeros(Q, dtype=np.complex128)
+        _check(lib().deflate_project(self.handle, defl.handle, Q, mode, cfp,
+                                     0 if coeffs is None else len(cf), thp, nth, _ptr(eta), _ptr(xt),
+                                     eta.shape[0], corr.ctypes.data_as(_P), xi.ctypes.data_as(_P)))
+        return xt, corr, xi
+
+    def loop_estimate(self, eta, x, xt=None, corr=None, thetas=(0, 1, 2, 3, 4), samples=False):
+        th, thp, nth = _thetas(thetas)
+        Lt = self.dims[3]
+        nrhs = eta.shape[0]
+        est = np.zeros((nth, Lt + 1), dtype=np.complex128)
+        err = np.zeros((nth, Lt + 1, 2))
+        smp = np.zeros((nrhs, nth, Lt + 1), dtype=np.complex128) if samples else None
+        cp = None
+        if corr is not None:
+            corr = np.ascontiguousarray(corr, dtype=np.complex128)
+            cp = corr.ctypes.data_as(_P)
+        _check(lib().loop_estimate(self.handle, thp, nth, _ptr(eta), _ptr(x), _ptr(xt), nrhs, cp,
+                                   est.ctypes.data_as(_P), err.ctypes.data_as(_P),
+                                   smp.ctypes.data_as(_P) if samples else None))
+        return (est, err, smp) if samples else (est, err)

@@ -1,0 +1,114 @@
+"""GPU parity: Z(4) noise, even/odd packing and the Wilson operators.
+
+Noise codes and the even/odd permutation are integer work and must match
+the oracle bit for bit; FP64 operators agree to rounding (1e-13 relative
+to the largest component), FP32 ones to 5e-6.  Lattices cover neighbour
+aliasing (2^4), a ragged last block (6x4x2x8: V/2 = 192 sites), several
+blocks (4^4 with 3 right-hand sides) and the 16^3 x 32 production shape.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import require_gpu, context, to_gpu, to_host, say, rel_err
+from oracle import noise as ON
+from oracle import wilson as W
+from oracle import lattice as L
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(2, 2, 2, 2), (6, 4, 2, 8), (4, 4, 4, 4)]
+
+
+@pytest.mark.parametrize("dims", DIMS + [(16, 16, 16, 32)])
+def test_noise_bit_exact(dims):
+    require_gpu()
+    ctx, _ = context(dims, 0.3, 5, 0.12)
+    for seed, first, n in ((2001, 0, 3), (0xDEADBEEFCAFEF00D, (1 << 33) + 7, 2)):
+        say("noise", dims, seed, first)
+        eta, codes = ctx.noise_z4(seed, first, n, codes=True)
+        ref = ON.z4_codes(seed, dims, first, n)
+        assert np.array_equal(to_host(codes), ref)
+        assert np.array_equal(to_host(eta), ON.z4_noise(seed, dims, first, n))
+
+
+@pytest.mark.parametrize("dims", DIMS)
+def test_pack_matches_checkerboard_tables(dims):
+    require_gpu()
+    ctx, _ = context(dims, 0.3, 5, 0.12)
+    rng = np.random.default_rng(1)
+    shape = (2,) + ctx.shape
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    say("pack", dims)
+    eo = to_host(ctx.pack_eo(to_gpu(x)))            # (nrhs, 2, 12, V/2)
+    e, o = L.to_eo(dims, x)                          # (nrhs, V/2, 4, 3)
+    assert np.array_equal(eo[:, 0], e.reshape(2, -1, 12).transpose(0, 2, 1))
+    assert np.array_equal(eo[:, 1], o.reshape(2, -1, 12).transpose(0, 2, 1))
+    back = to_host(ctx.unpack_eo(to_gpu(eo)))
+    assert np.array_equal(back, x)
+
+
+def _oracle_op(op, U, kappa, x, dims):
+    if op == "M":
+        return W.apply_M(U, kappa, x)
+    if op == "Mdag":
+        return W.apply_Mdag(U, kappa, x)
+    if op == "MG5":
+        return W.apply_Mprime(U, kappa, x)
+    if op == "hop":
+        return W.hop(U, x)
+    if op == "schur":
+        return W.apply_Mhat(U, kappa, x, dims)
+    raise ValueError(op)
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("op", ["M", "Mdag", "MG5", "hop", "schur"])
+def test_operator_parity_fp64(dims, op):
+    require_gpu()
+    kappa = 0.13
+    ctx, U = context(dims, 0.3, 7, kappa)
+    rng = np.random.default_rng(3)
+    shape = (3,) + ctx.shape
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    say("op", op, dims, "f64")
+    y = to_host(ctx.wilson_apply(op, to_gpu(x)))
+    ref = _oracle_op(op, U, kappa, x, dims)
+    assert rel_err(y, ref) < 1e-13
+
+
+@pytest.mark.parametrize("op", ["M", "hop", "schur", "MG5"])
+def test_operator_parity_fp32(op):
+    require_gpu()
+    dims, kappa = (6, 4, 2, 8), 0.13
+    ctx, U = context(dims, 0.3, 7, kappa)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((2,) + ctx.shape) + 1j * rng.standard_normal((2,) + ctx.shape)
+    say("op", op, dims, "f32")
+    y = to_host(ctx.wilson_apply(op, to_gpu(x), prec="f32"))
+    assert rel_err(y, _oracle_op(op, U, kappa, x, dims)) < 5e-6
+
+
+def test_eo_layout_matches_lex():
+    require_gpu()
+    dims, kappa = (4, 4, 4, 4), 0.125
+    ctx, U = context(dims, 0.3, 9, kappa)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((2,) + ctx.shape) + 1j * rng.standard_normal((2,) + ctx.shape)
+    say("eo layout", dims)
+    xg = to_gpu(x)
+    eo = ctx.pack_eo(xg)
+    y_eo = ctx.wilson_apply("M", eo, layout="eo")
+    assert rel_err(to_host(ctx.unpack_eo(y_eo)), to_host(ctx.wilson_apply("M", xg))) < 1e-15
+
+
+def test_full_size_operator_16x32():
+    require_gpu()
+    dims, kappa = (16, 16, 16, 32), 0.125
+    ctx, U = context(dims, 0.25, 1002, kappa)
+    eta = ON.z4_noise(11, dims, 0, 1)
+    say("op M full size", dims)
+    y = to_host(ctx.wilson_apply("M", to_gpu(eta)))
+    assert rel_err(y, W.apply_M(U, kappa, eta)) < 1e-13
+    say("op schur full size", dims)
+    y = to_host(ctx.wilson_apply("schur", to_gpu(eta)))
+    assert rel_err(y, W.apply_Mhat(U, kappa, eta, dims)) < 1e-13

@@ -254,27 +254,28 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-constexpr int RC_E = 32;  // elements per block of the in-place recombination
+// In-place recombination: each block stages E elements of all Jin input
+// vectors in LDS, then overwrites the first Jout vectors there.
 template <class R>
 __global__ void __launch_bounds__(kBlock)
     k_recombine(cx<R> *__restrict__ V, size_t ldv, int Jin, const cx<double> *__restrict__ P,
-                size_t ldp, int Jout, size_t n) {
+                size_t ldp, int Jout, size_t n, int E) {
   extern __shared__ unsigned char smem[];
-  cx<R> *sv = reinterpret_cast<cx<R> *>(smem);  // [Jin][RC_E]
-  const size_t e0 = size_t(blockIdx.x) * RC_E;
-  for (int t = threadIdx.x; t < Jin * RC_E; t += kBlock) {
-    int l = t / RC_E, e = t % RC_E;
+  cx<R> *sv = reinterpret_cast<cx<R> *>(smem);  // [Jin][E]
+  const size_t e0 = size_t(blockIdx.x) * E;
+  for (int t = threadIdx.x; t < Jin * E; t += kBlock) {
+    int l = t / E, e = t % E;
     size_t idx = e0 + e;
     sv[t] = idx < n ? ldc(V + size_t(l) * ldv + idx) : mk<R>(0, 0);
   }
   __syncthreads();
-  const int e = threadIdx.x % RC_E;
+  const int e = threadIdx.x % E;
   const size_t idx = e0 + e;
   if (idx >= n) return;
-  for (int j = threadIdx.x / RC_E; j < Jout; j += kBlock / RC_E) {
+  for (int j = threadIdx.x / E; j < Jout; j += kBlock / E) {
     cx<double> acc = mk<double>(0, 0);
     for (int l = 0; l < Jin; ++l) {
-      cx<R> v = sv[l * RC_E + e];
+      cx<R> v = sv[l * E + e];
       acc = acc + mk<double>(double(v.re), double(v.im)) * P[l + ldp * size_t(j)];
     }
     stc(V + size_t(j) * ldv + idx, mk<R>(R(acc.re), R(acc.im)));
@@ -380,12 +381,15 @@ template <class R>
 void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size_t ldp, int Jout,
                size_t n) {
   LQCD_CHECK(Jout <= Jin, LQCD_EINVAL, "recombine: Jout > Jin");
-  size_t shm = size_t(Jin) * RC_E * sizeof(cx<R>);
-  LQCD_CHECK(shm <= 160 * 1024, LQCD_EINVAL, "recombine: basis of %d vectors too large", Jin);
-  unsigned nb = unsigned((n + RC_E - 1) / RC_E);
+  // largest power-of-two tile (<= 64 elements) whose staging fits 64 KiB of LDS
+  int E = 64;
+  while (E > 1 && size_t(Jin) * E * sizeof(cx<R>) > 64 * 1024) E >>= 1;
+  size_t shm = size_t(Jin) * E * sizeof(cx<R>);
+  LQCD_CHECK(shm <= 64 * 1024, LQCD_EINVAL, "recombine: basis of %d vectors too large", Jin);
+  unsigned nb = unsigned((n + E - 1) / E);
   hipLaunchKernelGGL(k_recombine<R>, dim3(nb), dim3(kBlock), shm, c->stream,
                      static_cast<cx<R> *>(V), ldv, Jin, reinterpret_cast<const cx<double> *>(P),
-                     ldp, Jout, n);
+                     ldp, Jout, n, E);
   LQCD_HIP(hipGetLastError());
 }
 

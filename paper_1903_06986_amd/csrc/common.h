@@ -116,6 +116,8 @@ struct lqcd_ctx {
   lqcd::DevBuf ws[8];
   lqcd::DevBuf red;      // reduction partials
   lqcd::DevBuf red_out;  // reduction results (device)
+  lqcd::DevBuf sw[16];   // solver fields
+  lqcd::DevBuf small[2]; // solver small matrices
 };
 
 namespace lqcd {

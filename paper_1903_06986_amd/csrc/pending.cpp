@@ -7,13 +7,6 @@ using namespace lqcd;
   return guarded([&] { LQCD_CHECK(false, LQCD_EINVAL, "%s: not implemented yet", name); })
 
 extern "C" {
-lqcd_status gmresdr_solve(lqcd_ctx *, lqcd_op, const lqcd_solve_params *, const void *, void *, int,
-                          lqcd_defl **, lqcd_solve_stats *) { PENDING("gmresdr_solve"); }
-lqcd_status lqcd_defl_eigpairs(lqcd_ctx *, lqcd_defl *, int, double *, double *) {
-  PENDING("lqcd_defl_eigpairs");
-}
-lqcd_status lqcd_defl_ritz(const lqcd_defl *, double *, int *) { PENDING("lqcd_defl_ritz"); }
-void lqcd_defl_free(lqcd_defl *) {}
 lqcd_status deflate_project(lqcd_ctx *, lqcd_defl *, int, lqcd_defl_mode, const double *, int,
                             const int *, int, const void *, void *, int, double *, double *) {
   PENDING("deflate_project");

@@ -1,0 +1,35 @@
+// Deflation space and solver internals shared by the solver and the
+// hermitian-forced subtraction.
+#pragma once
+
+#include "common.h"
+#include "smallla.h"
+
+// Opaque handle of the C ABI: the deflation data A V_k = V_{k+1} Hbar_k
+// left by GMRES-DR (Sec. 7), for the operator it was built with.
+struct lqcd_defl {
+  lqcd_op op = LQCD_OP_SCHUR;   // SCHUR: even-site vectors; MG5: full-lattice vectors
+  int k = 0;                     // number of deflation vectors
+  size_t n = 0;                  // vector length in complex numbers
+  int dims[4] = {0, 0, 0, 0};    // lattice the space belongs to
+  double kappa = 0;
+  lqcd::DevBuf V;                // V_{k+1}, FP64, vectors n apart
+  lqcd::DevBuf V32;              // FP32 copy for mixed-precision inner solves
+  bool have_v32 = false;
+  lqcd::la::Mat H;               // Hbar_k, (k+1) x k
+  std::vector<lqcd::cdouble> theta;   // harmonic Ritz values of the final restart
+  std::vector<double> theta_resid;    // |A y - theta y| of each
+  lqcd::la::QR Hqr;              // QR of Hbar_k for the projection least squares
+  // Rayleigh-Ritz eigenpairs (hermitian operator), filled on request.
+  int Qe = 0;
+  std::vector<double> lam, lam_resid;
+  lqcd::DevBuf E;                // Q eigenvectors (FP64, n apart)
+};
+
+namespace lqcd {
+
+// Rayleigh-Ritz eigenpairs of a hermitian deflation space (op MG5): fills
+// d->lam, d->lam_resid and d->E with the Q pairs of smallest |lambda|.
+void defl_eigpairs(lqcd_ctx *c, lqcd_defl *d, int Q);
+
+}  // namespace lqcd

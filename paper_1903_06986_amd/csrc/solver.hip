@@ -1,0 +1,679 @@
+// Deflated restarted GMRES on the GPU (Sec. 7: GMRES-DR(m,k) for the first
+// noise vector, super-converged, then GMRES-Proj for the rest; Sec. 5.4 for
+// the hermitian M').  The algorithms are the cited ones (Morgan's GMRES-DR,
+// Morgan and Wilcox's GMRES-Proj); the paper does not print them.
+//
+// Device work: operator applications (the stencil), classical Gram-Schmidt
+// applied twice with FP64 accumulation, norms, basis updates and the
+// deflation projections.  Host work: the (m+1) x m least-squares problems,
+// the m x m harmonic Ritz eigenproblem and the restart matrix P_{k+1},
+// once per cycle.  Within a cycle nothing waits for the host.
+//
+// GMRES-DR restart (per cycle): d = argmin |c - Hbar d|, x += V_m d; the k
+// harmonic Ritz vectors g of smallest |theta| ((H_m + |h|^2 f e_m^T) g =
+// theta g, H_m^H f = e_m) and the residual direction w = [-|h|^2 f; h]
+// (parallel to c - Hbar d, but free of its cancellation) are
+// orthonormalised into P_{k+1}; then V_{k+1} = V_{m+1} P_{k+1},
+// Hbar_k = P_{k+1}^H Hbar_m P_k, c = P_{k+1}^H (c - Hbar d).
+//
+// GMRES-Proj (batched over right-hand sides): repeat { projection
+// c = V_{k+1}^H r, d = argmin |c - Hbar_k d|, x += V_k d, r -= V_{k+1}
+// Hbar_k d; one GMRES(m-k) cycle; true residual r = b - A x }.
+//
+// Mixed precision (inner = F32): FP64 iterative refinement; each refinement
+// step solves A e = r with the FP32 stencil and an FP32 Krylov basis
+// (Gram-Schmidt coefficients and norms still accumulated in FP64) to a
+// relative tolerance inner_tol, then x += e and r = b - A x in FP64.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+
+#include "cplx.h"
+#include "fields.h"
+#include "solver.h"
+
+namespace lqcd {
+
+namespace {
+
+// ------------------------------------------------------------- kernels
+__global__ void k_finish_col(cx<double> *__restrict__ Hd, size_t Hrs, int ldh, int j,
+                             const cx<double> *__restrict__ h1, const cx<double> *__restrict__ h2,
+                             size_t hrs, const double *__restrict__ nrm2, double *__restrict__ inv) {
+  const int r = blockIdx.x;
+  cx<double> *col = Hd + r * Hrs + size_t(j) * ldh;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h1[r * hrs + i] + h2[r * hrs + i];
+  if (threadIdx.x == 0) {
+    double nr = sqrt(nrm2[r]);
+    col[j + 1] = mk(nr, 0.0);
+    inv[r] = (nr > 0 && isfinite(nr)) ? 1.0 / nr : 0.0;
+  }
+}
+
+template <class R>
+__global__ void k_swap(cx<R> *__restrict__ a, cx<R> *__restrict__ b, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    cx<R> t = a[i];
+    a[i] = b[i];
+    b[i] = t;
+  }
+}
+
+// y (FP64) += x (FP32)
+__global__ void k_acc_widen(const cx<float> *__restrict__ x, cx<double> *__restrict__ y, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    cx<float> v = x[i];
+    cx<double> w = y[i];
+    y[i] = mk(w.re + double(v.re), w.im + double(v.im));
+  }
+}
+
+template <class R>
+void swap_vec(lqcd_ctx *c, void *a, void *b, size_t n) {
+  if (a == b) return;
+  unsigned nb = unsigned(std::min<size_t>(nblocks(n), 4096));
+  hipLaunchKernelGGL(k_swap<R>, dim3(nb), dim3(kBlock), 0, c->stream, static_cast<cx<R> *>(a),
+                     static_cast<cx<R> *>(b), n);
+  LQCD_HIP(hipGetLastError());
+}
+
+void copy_dev(lqcd_ctx *c, void *dst, const void *src, size_t bytes) {
+  LQCD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+}
+
+// ------------------------------------------------------------ operators
+template <class R>
+struct Op {
+  lqcd_ctx *c;
+  lqcd_op op;
+  size_t n;  // vector length
+  DevBuf *tmp;
+  void apply(const void *in, size_t sin, void *out, size_t sout, int nb) const {
+    if (nb <= 0) return;
+    if (op == LQCD_OP_SCHUR) {
+      const size_t hl = half_len(c->g);
+      void *t = tmp->ensure(hl * size_t(nb) * sizeof(cx<R>));
+      apply_schur<R>(c, in, out, t, nb, sin, sout, hl);
+    } else {
+      apply_full<R>(c, LQCD_OP_MG5, in, out, nb, sin, sout);
+    }
+  }
+};
+
+// Device scratch for the small per-cycle matrices.
+struct Small {
+  DevBuf &buf;
+  explicit Small(DevBuf &b) : buf(b) {}
+  cdouble *Hd, *h1, *h2, *vec, *C, *E;
+  double *nrm2, *inv;
+  size_t Hrs;
+  void setup(int m, int nb, int kmax) {
+    Hrs = size_t(m + 1) * m;
+    size_t nc = Hrs * nb + 2 * size_t(m + 1) * nb + size_t(m + 1) * nb + 2 * size_t(kmax + 1) * nb +
+                size_t(m + 1) * (kmax + 1);
+    size_t bytes = nc * sizeof(cdouble) + 2 * size_t(nb) * sizeof(double) + 256;
+    char *p = static_cast<char *>(buf.ensure(bytes));
+    Hd = reinterpret_cast<cdouble *>(p);
+    h1 = Hd + Hrs * nb;
+    h2 = h1 + size_t(m + 1) * nb;
+    vec = h2 + size_t(m + 1) * nb;                 // LS solutions / restart matrix
+    C = vec + std::max(size_t(m + 1) * nb, size_t(m + 1) * (kmax + 1));
+    E = C + size_t(kmax + 1) * nb;
+    nrm2 = reinterpret_cast<double *>(E + size_t(kmax + 1) * nb);
+    inv = nrm2 + nb;
+  }
+};
+
+void h2d(lqcd_ctx *c, void *dst, const void *src, size_t bytes) {
+  LQCD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+  LQCD_HIP(hipStreamSynchronize(c->stream));
+}
+void d2h(lqcd_ctx *c, void *dst, const void *src, size_t bytes) {
+  LQCD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
+  LQCD_HIP(hipStreamSynchronize(c->stream));
+}
+
+// Arnoldi steps j0 .. m-1 on nb bases (vectors n apart, bases Wrs apart):
+// w = A v_j; two classical Gram-Schmidt passes; h_{j+1,j} = |w|;
+// v_{j+1} = w / |w|.  Column j of each Hbar goes to the device matrix.
+template <class R>
+void arnoldi(lqcd_ctx *c, const Op<R> &A, void *W, size_t n, size_t Wrs, int j0, int m, int nb,
+             Small &s) {
+  cx<R> *Wb = static_cast<cx<R> *>(W);
+  for (int j = j0; j < m; ++j) {
+    cx<R> *wj = Wb + size_t(j) * n, *wn = Wb + size_t(j + 1) * n;
+    A.apply(wj, Wrs, wn, Wrs, nb);
+    multi_dot<R>(c, Wb, n, Wrs, j + 1, wn, Wrs, n, nb, s.h1, m + 1);
+    multi_axpy<R>(c, Wb, n, Wrs, j + 1, s.h1, m + 1, wn, Wrs, n, nb, nullptr);
+    multi_dot<R>(c, Wb, n, Wrs, j + 1, wn, Wrs, n, nb, s.h2, m + 1);
+    multi_axpy<R>(c, Wb, n, Wrs, j + 1, s.h2, m + 1, wn, Wrs, n, nb, s.nrm2);
+    hipLaunchKernelGGL(k_finish_col, dim3(nb), dim3(64), 0, c->stream,
+                       reinterpret_cast<cx<double> *>(s.Hd), s.Hrs, m + 1, j,
+                       reinterpret_cast<cx<double> *>(s.h1), reinterpret_cast<cx<double> *>(s.h2),
+                       size_t(m + 1), s.nrm2, s.inv);
+    LQCD_HIP(hipGetLastError());
+    scale_dev<R>(c, wn, Wrs, s.inv, wn, Wrs, n, nb);
+  }
+}
+
+bool finite_mat(const la::Mat &H) {
+  for (auto &z : H.a)
+    if (!std::isfinite(z.real()) || !std::isfinite(z.imag())) return false;
+  return true;
+}
+
+// Harmonic Ritz restart data of an (m+1) x m Hessenberg-type matrix.
+struct Restart {
+  la::Mat P;                 // (m+1) x (k+1), orthonormal
+  std::vector<cdouble> theta;
+  std::vector<double> resid;
+};
+
+Restart harmonic_restart(const la::Mat &H, int m, int k) {
+  la::Mat Hm(m, m);
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) Hm(i, j) = H(i, j);
+  const cdouble h = H(m, m - 1);
+  std::vector<cdouble> em(m, 0.0);
+  em[m - 1] = 1.0;
+  std::vector<cdouble> f = la::solve(la::adjoint(Hm), em);
+  la::Mat G = Hm;
+  const double h2 = std::norm(h);
+  for (int i = 0; i < m; ++i) G(i, m - 1) += h2 * f[i];
+  std::vector<cdouble> th;
+  la::Mat g;
+  LQCD_CHECK(la::eig(G, th, g), LQCD_ENOCONV, "harmonic Ritz eigenproblem did not converge");
+  std::vector<int> ord(m);
+  for (int i = 0; i < m; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int a, int b) { return std::abs(th[a]) < std::abs(th[b]); });
+  la::Mat P(m + 1, k + 1);
+  std::vector<cdouble> w(m + 1);
+  double wn = 0;
+  for (int i = 0; i < m; ++i) {
+    w[i] = -h2 * f[i];
+    wn += std::norm(w[i]);
+  }
+  w[m] = h;
+  wn = std::sqrt(wn + h2);
+  Restart R;
+  for (int q = 0; q < k; ++q) {
+    int col = ord[q];
+    double gn = 0;
+    for (int i = 0; i < m; ++i) {
+      P(i, q) = g(i, col);
+      gn += std::norm(g(i, col));
+    }
+    R.theta.push_back(th[col]);
+    R.resid.push_back(std::abs(g(m - 1, col)) * wn / std::sqrt(gn));
+  }
+  for (int i = 0; i <= m; ++i) P(i, k) = w[i];
+  la::QR qr;
+  qr.factor(P);
+  R.P = qr.thin_q();
+  return R;
+}
+
+la::Mat sub(const la::Mat &A, int r, int c) {
+  la::Mat B(r, c);
+  for (int j = 0; j < c; ++j)
+    for (int i = 0; i < r; ++i) B(i, j) = A(i, j);
+  return B;
+}
+
+// ------------------------------------------------------------ GMRES-DR
+// Solves A x = S (x starts at zero) for one right-hand side in FP64 and
+// leaves the deflation data in d.
+void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lqcd_solve_params &p,
+              lqcd_defl *d, lqcd_solve_stats &st) {
+  const int m = p.m, k = p.k;
+  const size_t n = A.n;
+  cx<double> *V = static_cast<cx<double> *>(d->V.ensure(size_t(m + 1) * n * sizeof(cx<double>)));
+  Small s(c->small[0]);
+  s.setup(m, 1, m);
+  double *nrm_host = nullptr;
+  double b2 = 0;
+  norm2<double>(c, S, 0, n, 1, s.nrm2);
+  d2h(c, &b2, s.nrm2, sizeof(double));
+  (void)nrm_host;
+  const double bnorm = std::sqrt(b2);
+  LQCD_CHECK(std::isfinite(bnorm), LQCD_ENAN, "gmresdr_solve: right-hand side is not finite");
+  fill_zero(c, X, n * sizeof(cx<double>));
+  if (bnorm == 0.0) {
+    LQCD_CHECK(false, LQCD_EINVAL, "gmresdr_solve: GMRES-DR needs a nonzero first right-hand side");
+  }
+  cdouble a(1.0 / bnorm, 0), zero(0, 0);
+  axpby<double>(c, &a, S, 0, &zero, V, 0, n, 1, false);
+  la::Mat H(m + 1, m);
+  std::vector<cdouble> cv(m + 1, 0.0);
+  cv[0] = bnorm;
+  int j0 = 0;
+  std::vector<cdouble> Hcols;
+  int nev = p.n_eig > 0 ? std::min(p.n_eig, k) : k;
+  for (;;) {
+    arnoldi<double>(c, A, V, n, 0, j0, m, 1, s);
+    st.matvecs += m - j0;
+    Hcols.resize(size_t(m + 1) * m);
+    d2h(c, Hcols.data(), s.Hd, Hcols.size() * sizeof(cdouble));
+    // column j of the device matrix holds rows 0..j+1 only (the rest is stale)
+    for (int j = j0; j < m; ++j)
+      for (int i = 0; i <= m; ++i) H(i, j) = i <= j + 1 ? Hcols[size_t(j) * (m + 1) + i] : cdouble(0, 0);
+    LQCD_CHECK(finite_mat(H), LQCD_ENAN, "gmresdr_solve: NaN/Inf in the Arnoldi process");
+    for (int j = j0; j < m; ++j)
+      LQCD_CHECK(std::abs(H(j + 1, j)) > 0, LQCD_EBREAKDOWN,
+                 "gmresdr_solve: Arnoldi breakdown at column %d", j);
+    std::vector<cdouble> dv = la::lstsq(H, cv);
+    std::vector<cdouble> sv(cv);
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i <= m; ++i) sv[i] -= H(i, j) * dv[j];
+    double res = 0;
+    for (auto &z : sv) res += std::norm(z);
+    res = std::sqrt(res);
+    h2d(c, s.vec, dv.data(), size_t(m) * sizeof(cdouble));
+    gemm_nn<double>(c, V, n, 0, m, s.vec, m, 0, X, n, 0, 1, n, 1, 1.0);
+    st.cycles += 1;
+    Restart R = harmonic_restart(H, m, k);
+    bool done = res <= p.tol_super * bnorm;
+    if (done && p.eig_tol > 0)
+      for (int q = 0; q < nev; ++q)
+        if (R.resid[q] > p.eig_tol * std::abs(R.theta[q])) done = false;
+    // restart: V_{k+1} = V_{m+1} P_{k+1}, Hbar_k = P^H Hbar_m P_k, c = P^H s
+    h2d(c, s.vec, R.P.a.data(), R.P.a.size() * sizeof(cdouble));
+    recombine<double>(c, V, n, m + 1, s.vec, m + 1, k + 1, n);
+    la::Mat Pk = sub(R.P, m, k);
+    la::Mat Hk = la::matmul_hn(R.P, la::matmul(H, Pk));
+    std::vector<cdouble> cn(k + 1, 0.0);
+    for (int q = 0; q <= k; ++q)
+      for (int i = 0; i <= m; ++i) cn[q] += std::conj(R.P(i, q)) * sv[i];
+    d->H = Hk;
+    d->theta = R.theta;
+    d->theta_resid = R.resid;
+    if (done || st.cycles >= p.max_cycles) break;
+    H = la::Mat(m + 1, m);
+    for (int j = 0; j < k; ++j)
+      for (int i = 0; i <= k; ++i) H(i, j) = Hk(i, j);
+    std::fill(cv.begin(), cv.end(), cdouble(0, 0));
+    for (int q = 0; q <= k; ++q) cv[q] = cn[q];
+    j0 = k;
+  }
+  d->k = k;
+  d->n = n;
+  d->Hqr.factor(d->H);
+  d->have_v32 = false;
+}
+
+// ---------------------------------------------------------- GMRES-Proj
+// Batched solve of A X = S (nb right-hand sides, vectors n apart) with
+// precision R, from X = 0, until |S - A X| <= tol * ref[r] or max_cycles.
+// Vdef: V_{k+1} of precision R.  Works in place on X; S is not modified
+// (its slots may be permuted internally and are restored on return).
+template <class R>
+void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *d, int p, void *S,
+                void *X, void *Rr, void *W, int nb, std::vector<double> ref, double tol,
+                int max_cycles, std::vector<int> &matvecs, std::vector<int> &cycles,
+                std::vector<double> &resid) {
+  const size_t n = A.n;
+  const int k = d->k;
+  Small s(c->small[0]);
+  s.setup(p, nb, k);
+  const size_t vb = n * sizeof(cx<R>);
+  cx<R> *Sb = static_cast<cx<R> *>(S), *Xb = static_cast<cx<R> *>(X), *Rb = static_cast<cx<R> *>(Rr);
+  std::vector<int> slot_of(nb), perm(nb);  // perm[slot] = original rhs
+  for (int r = 0; r < nb; ++r) perm[r] = r;
+  std::vector<std::pair<int, int>> swaps;
+  fill_zero(c, X, vb * nb);
+  copy_dev(c, Rr, S, vb * nb);  // r = S - A 0
+  int na = nb;
+  std::vector<double> rn(nb);
+  auto swap_slots = [&](int a, int b) {
+    swap_vec<R>(c, Sb + a * n, Sb + b * n, n);
+    swap_vec<R>(c, Xb + a * n, Xb + b * n, n);
+    swap_vec<R>(c, Rb + a * n, Rb + b * n, n);
+    std::swap(perm[a], perm[b]);
+    std::swap(ref[a], ref[b]);
+    std::swap(rn[a], rn[b]);
+    swaps.emplace_back(a, b);
+  };
+  std::vector<cdouble> Ch, Dh, Eh, Hh;
+  for (;;) {
+    // residual norms and convergence; compact the active slots
+    norm2<R>(c, Rb, n, n, na, s.nrm2);
+    d2h(c, rn.data(), s.nrm2, size_t(na) * sizeof(double));
+    for (int r = 0; r < na; ++r) {
+      rn[r] = std::sqrt(rn[r]);
+      LQCD_CHECK(std::isfinite(rn[r]), LQCD_ENAN, "gmresdr_solve: NaN/Inf residual");
+      resid[perm[r]] = rn[r] / (ref[r] > 0 ? ref[r] : 1.0);
+    }
+    for (int r = 0; r < na;) {
+      // ref <= 0 marks a right-hand side the caller does not want solved
+      if (ref[r] <= 0 || rn[r] <= tol * ref[r] || cycles[perm[r]] >= max_cycles) {
+        if (r != na - 1) swap_slots(r, na - 1);
+        --na;
+      } else {
+        ++r;
+      }
+    }
+    if (na == 0) break;
+    // projection over the deflation space: c = V^H r, d = argmin |c - Hbar d|
+    gemm_tn<R>(c, Vdef, n, k + 1, Rb, n, na, n, s.C, k + 1);
+    Ch.resize(size_t(k + 1) * na);
+    d2h(c, Ch.data(), s.C, Ch.size() * sizeof(cdouble));
+    Dh.assign(size_t(k) * na, 0.0);
+    Eh.assign(size_t(k + 1) * na, 0.0);
+    for (int r = 0; r < na; ++r) {
+      std::vector<cdouble> y(Ch.begin() + size_t(r) * (k + 1), Ch.begin() + size_t(r + 1) * (k + 1));
+      d->Hqr.apply_qh(y.data());
+      d->Hqr.solve_r(y.data());
+      for (int j = 0; j < k; ++j) Dh[size_t(r) * k + j] = y[j];
+      for (int j = 0; j < k; ++j)
+        for (int i = 0; i <= k; ++i) Eh[size_t(r) * (k + 1) + i] += d->H(i, j) * y[j];
+    }
+    h2d(c, s.C, Dh.data(), Dh.size() * sizeof(cdouble));
+    h2d(c, s.E, Eh.data(), Eh.size() * sizeof(cdouble));
+    gemm_nn<R>(c, Vdef, n, 0, k, s.C, k, 0, Xb, n, 0, na, n, 1, 1.0);
+    gemm_nn<R>(c, Vdef, n, 0, k + 1, s.E, k + 1, 0, Rb, n, 0, na, n, 1, -1.0);
+    // one GMRES(p) cycle per active rhs
+    norm2<R>(c, Rb, n, n, na, s.nrm2);
+    d2h(c, rn.data(), s.nrm2, size_t(na) * sizeof(double));
+    std::vector<cdouble> sc(na), zs(na, 0.0);
+    for (int r = 0; r < na; ++r) {
+      rn[r] = std::sqrt(rn[r]);
+      sc[r] = rn[r] > 0 ? 1.0 / rn[r] : 0.0;
+    }
+    const size_t Wrs = size_t(p + 1) * n;
+    axpby<R>(c, sc.data(), Rb, n, zs.data(), W, Wrs, n, na, true);
+    arnoldi<R>(c, A, W, n, Wrs, 0, p, na, s);
+    Hh.resize(s.Hrs * na);
+    d2h(c, Hh.data(), s.Hd, Hh.size() * sizeof(cdouble));
+    std::vector<cdouble> dall(size_t(p) * na);
+    for (int r = 0; r < na; ++r) {
+      la::Mat H(p + 1, p);
+      for (int j = 0; j < p; ++j)
+        for (int i = 0; i <= j + 1; ++i) H(i, j) = Hh[r * s.Hrs + size_t(j) * (p + 1) + i];
+      LQCD_CHECK(finite_mat(H), LQCD_ENAN, "gmresdr_solve: NaN/Inf in the Arnoldi process");
+      std::vector<cdouble> cvec(p + 1, 0.0);
+      cvec[0] = rn[r];
+      std::vector<cdouble> dv = la::lstsq(H, cvec);
+      std::copy(dv.begin(), dv.end(), dall.begin() + size_t(r) * p);
+      matvecs[perm[r]] += p + 1;
+      cycles[perm[r]] += 1;
+    }
+    h2d(c, s.vec, dall.data(), dall.size() * sizeof(cdouble));
+    gemm_nn<R>(c, W, n, Wrs, p, s.vec, p, p, Xb, n, n, 1, n, na, 1.0);
+    // true residual r = S - A X
+    A.apply(Xb, n, Rb, n, na);
+    cdouble one(1, 0), mone(-1, 0);
+    axpby<R>(c, &one, Sb, n, &mone, Rb, n, n, na, false);
+  }
+  // restore the caller's slot order
+  for (auto it = swaps.rbegin(); it != swaps.rend(); ++it) {
+    swap_vec<R>(c, Sb + it->first * n, Sb + it->second * n, n);
+    swap_vec<R>(c, Xb + it->first * n, Xb + it->second * n, n);
+  }
+}
+
+// ------------------------------------------------------------- drivers
+// Solver buffers live in the context so that repeated calls reuse them.
+struct Work {
+  DevBuf &Bp, &S, &X, &R, &W, &XF, &T, &S32, &X32, &R32, &W32, &tmp64, &tmp32, &red2;
+  explicit Work(lqcd_ctx *c)
+      : Bp(c->sw[0]), S(c->sw[1]), X(c->sw[2]), R(c->sw[3]), W(c->sw[4]), XF(c->sw[5]),
+        T(c->sw[6]), S32(c->sw[7]), X32(c->sw[8]), R32(c->sw[9]), W32(c->sw[10]),
+        tmp64(c->sw[11]), tmp32(c->sw[12]), red2(c->sw[13]) {}
+};
+
+// Pack nb right-hand sides and build the system's source:
+// SCHUR: S = eta_e + kappa D_eo eta_o (half vectors); MG5: S = b.
+void make_source(lqcd_ctx *c, lqcd_op op, const void *b_lex, int nb, Work &w, size_t n) {
+  const size_t hl = half_len(c->g), fl = full_len(c->g);
+  cx<double> *Bp = static_cast<cx<double> *>(w.Bp.ensure(fl * nb * sizeof(cx<double>)));
+  cx<double> *S = static_cast<cx<double> *>(w.S.ensure(n * nb * sizeof(cx<double>)));
+  pack_eo<double>(c, b_lex, Bp, nb, fl);
+  if (op == LQCD_OP_SCHUR)
+    hop_half<double>(c, 0, Bp + hl, Bp, S, cdouble(1, 0), c->kappa, false, false, nb, fl, fl, n);
+  else
+    copy_dev(c, S, Bp, fl * nb * sizeof(cx<double>));
+}
+
+// x (lex) from the internal solution; true residual |b - A x| / |b| (full).
+void finish(lqcd_ctx *c, lqcd_op op, const void *X, void *x_lex, int nb, Work &w, size_t n,
+            std::vector<double> &true_resid) {
+  const size_t hl = half_len(c->g), fl = full_len(c->g);
+  cx<double> *Bp = w.Bp.as<cx<double>>();
+  cx<double> *XF = static_cast<cx<double> *>(w.XF.ensure(fl * nb * sizeof(cx<double>)));
+  cx<double> *T = static_cast<cx<double> *>(w.T.ensure(fl * nb * sizeof(cx<double>)));
+  const cx<double> *Xs = static_cast<const cx<double> *>(X);
+  if (op == LQCD_OP_SCHUR) {
+    for (int r = 0; r < nb; ++r) copy_dev(c, XF + r * fl, Xs + r * n, hl * sizeof(cx<double>));
+    // x_o = eta_o + kappa D_oe x_e
+    hop_half<double>(c, 1, XF, Bp + hl, XF + hl, cdouble(1, 0), c->kappa, false, false, nb, fl, fl, fl);
+  } else {
+    copy_dev(c, XF, Xs, fl * nb * sizeof(cx<double>));
+  }
+  unpack_eo<double>(c, XF, x_lex, nb, fl);
+  apply_full<double>(c, op == LQCD_OP_SCHUR ? LQCD_OP_M : LQCD_OP_MG5, XF, T, nb, fl, fl);
+  cdouble one(1, 0), mone(-1, 0);
+  axpby<double>(c, &one, Bp, fl, &mone, T, fl, fl, nb, false);
+  double *d2 = static_cast<double *>(w.red2.ensure(2 * nb * sizeof(double)));
+  norm2<double>(c, T, fl, fl, nb, d2);
+  norm2<double>(c, Bp, fl, fl, nb, d2 + nb);
+  std::vector<double> h(2 * nb);
+  d2h(c, h.data(), d2, h.size() * sizeof(double));
+  true_resid.resize(nb);
+  for (int r = 0; r < nb; ++r) true_resid[r] = std::sqrt(h[r]) / std::max(std::sqrt(h[nb + r]), 1e-300);
+}
+
+void full_norms(lqcd_ctx *c, Work &w, int nb, std::vector<double> &out) {
+  const size_t fl = full_len(c->g);
+  double *d2 = static_cast<double *>(w.red2.ensure(2 * nb * sizeof(double)));
+  norm2<double>(c, w.Bp.ptr, fl, fl, nb, d2);
+  out.resize(nb);
+  d2h(c, out.data(), d2, nb * sizeof(double));
+  for (auto &v : out) v = std::sqrt(v);
+}
+
+}  // namespace
+
+void defl_eigpairs(lqcd_ctx *c, lqcd_defl *d, int Q) {
+  LQCD_CHECK(d->op == LQCD_OP_MG5, LQCD_EINVAL, "eigenpairs need a deflation space of M' (op MG5)");
+  LQCD_CHECK(Q >= 1 && Q <= d->k, LQCD_EINVAL, "Q = %d outside 1..k = %d", Q, d->k);
+  if (d->Qe == Q && d->E.ptr) return;
+  const int k = d->k;
+  la::Mat T = sub(d->H, k, k);
+  std::vector<double> lam;
+  la::Mat Sv;
+  la::eigh(T, lam, Sv);
+  std::vector<int> ord(k);
+  for (int i = 0; i < k; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if (std::abs(lam[a]) != std::abs(lam[b])) return std::abs(lam[a]) < std::abs(lam[b]);
+    return lam[a] < lam[b];
+  });
+  la::Mat S(k, Q);
+  d->lam.resize(Q);
+  d->lam_resid.resize(Q);
+  for (int q = 0; q < Q; ++q) {
+    d->lam[q] = lam[ord[q]];
+    for (int i = 0; i < k; ++i) S(i, q) = Sv(i, ord[q]);
+  }
+  // residuals |Hbar_k s - lambda [s; 0]|
+  la::Mat HS = la::matmul(d->H, S);
+  for (int q = 0; q < Q; ++q) {
+    double r = 0;
+    for (int i = 0; i <= k; ++i) {
+      cdouble v = HS(i, q) - (i < k ? d->lam[q] * S(i, q) : cdouble(0, 0));
+      r += std::norm(v);
+    }
+    d->lam_resid[q] = std::sqrt(r);
+  }
+  // E = V_k S
+  cx<double> *E = static_cast<cx<double> *>(d->E.ensure(size_t(Q) * d->n * sizeof(cx<double>)));
+  DevBuf Sd;
+  Sd.ensure(S.a.size() * sizeof(cdouble));
+  h2d(c, Sd.ptr, S.a.data(), S.a.size() * sizeof(cdouble));
+  fill_zero(c, E, size_t(Q) * d->n * sizeof(cx<double>));
+  gemm_nn<double>(c, d->V.ptr, d->n, 0, k, Sd.as<cdouble>(), k, 0, E, d->n, 0, Q, d->n, 1, 1.0);
+  LQCD_HIP(hipStreamSynchronize(c->stream));
+  d->Qe = Q;
+}
+
+}  // namespace lqcd
+
+using namespace lqcd;
+
+extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_params *pp,
+                                     const void *b, void *x, int nrhs, lqcd_defl **defl_inout,
+                                     lqcd_solve_stats *stats) {
+  return guarded([&] {
+    LQCD_CHECK(c && pp && defl_inout, LQCD_EINVAL, "gmresdr_solve: null argument");
+    LQCD_CHECK(op == LQCD_OP_SCHUR || op == LQCD_OP_MG5, LQCD_EINVAL,
+               "gmresdr_solve: op must be LQCD_OP_SCHUR or LQCD_OP_MG5");
+    LQCD_CHECK(nrhs >= 0, LQCD_EINVAL, "gmresdr_solve: nrhs < 0");
+    LQCD_CHECK(nrhs == 0 || (b && x), LQCD_EINVAL, "gmresdr_solve: null field");
+    const lqcd_solve_params p = *pp;
+    LQCD_CHECK(p.k >= 1 && p.m > p.k && p.m <= 250, LQCD_EINVAL,
+               "gmresdr_solve: need 1 <= k < m <= 250 (m=%d, k=%d)", p.m, p.k);
+    LQCD_CHECK(p.tol > 0 && p.max_cycles >= 1, LQCD_EINVAL, "gmresdr_solve: bad tol/max_cycles");
+    LQCD_CHECK(p.inner == LQCD_F64 || p.inner == LQCD_F32, LQCD_EINVAL,
+               "gmresdr_solve: inner precision must be F64 or F32");
+    const size_t n = op == LQCD_OP_SCHUR ? half_len(c->g) : full_len(c->g);
+    const size_t fl = full_len(c->g);
+    if (stats)
+      for (int r = 0; r < nrhs; ++r) stats[r] = lqcd_solve_stats{0, 0, 0, 0.0};
+    if (nrhs == 0) return;
+    Work w(c);
+    Op<double> A64{c, op, n, &w.tmp64};
+    Op<float> A32{c, op, n, &w.tmp32};
+    lqcd_defl *d = *defl_inout;
+    int start = 0;
+    std::vector<double> tr;
+    if (!d) {
+      std::unique_ptr<lqcd_defl> nd(new lqcd_defl());
+      nd->op = op;
+      for (int i = 0; i < 4; ++i) nd->dims[i] = c->g.L[i];
+      nd->kappa = c->kappa;
+      make_source(c, op, b, 1, w, n);
+      void *X = w.X.ensure(n * sizeof(cx<double>));
+      lqcd_solve_stats st{0, 0, 0, 0.0};
+      lqcd_solve_params pd = p;
+      pd.tol_super = std::max(0.0, std::min(p.tol_super > 0 ? p.tol_super : p.tol, p.tol));
+      gmres_dr(c, A64, w.S.ptr, X, pd, nd.get(), st);
+      finish(c, op, X, x, 1, w, n, tr);
+      st.true_resid = tr[0];
+      if (stats) stats[0] = st;
+      d = nd.release();
+      *defl_inout = d;
+      start = 1;
+    } else {
+      LQCD_CHECK(d->op == op, LQCD_EINVAL, "gmresdr_solve: deflation space built for another operator");
+      for (int i = 0; i < 4; ++i)
+        LQCD_CHECK(d->dims[i] == c->g.L[i], LQCD_EINVAL, "gmresdr_solve: deflation space of another lattice");
+      LQCD_CHECK(d->kappa == c->kappa, LQCD_EINVAL, "gmresdr_solve: deflation space of another kappa");
+    }
+    const int p_cyc = p.m - p.k;
+    const int blk = std::max(1, p.rhs_block);
+    bool nonconv = false;
+    for (int r0 = start; r0 < nrhs; r0 += blk) {
+      const int nb = std::min(blk, nrhs - r0);
+      const cx<double> *bl = static_cast<const cx<double> *>(b) + size_t(r0) * fl;
+      cx<double> *xl = static_cast<cx<double> *>(x) + size_t(r0) * fl;
+      make_source(c, op, bl, nb, w, n);
+      std::vector<double> ref;
+      full_norms(c, w, nb, ref);
+      std::vector<int> mv(nb, 0), cy(nb, 0), refn(nb, 0);
+      std::vector<double> res(nb, 0);
+      void *X = w.X.ensure(n * nb * sizeof(cx<double>));
+      void *Rr = w.R.ensure(n * nb * sizeof(cx<double>));
+      if (p.inner == LQCD_F64) {
+        void *W = w.W.ensure(size_t(p_cyc + 1) * n * nb * sizeof(cx<double>));
+        proj_solve<double>(c, A64, d->V.ptr, d, p_cyc, w.S.ptr, X, Rr, W, nb, ref, p.tol,
+                           p.max_cycles, mv, cy, res);
+      } else {
+        // FP64 refinement around FP32 deflated inner solves
+        if (!d->have_v32) {
+          d->V32.ensure(size_t(d->k + 1) * n * sizeof(cx<float>));
+          convert<double, float>(c, d->V.ptr, d->V32.ptr, size_t(d->k + 1) * n);
+          d->have_v32 = true;
+        }
+        void *S32 = w.S32.ensure(n * nb * sizeof(cx<float>));
+        void *X32 = w.X32.ensure(n * nb * sizeof(cx<float>));
+        void *R32 = w.R32.ensure(n * nb * sizeof(cx<float>));
+        void *W32 = w.W32.ensure(size_t(p_cyc + 1) * n * nb * sizeof(cx<float>));
+        void *T = w.T.ensure(n * nb * sizeof(cx<double>));
+        fill_zero(c, X, n * nb * sizeof(cx<double>));
+        copy_dev(c, Rr, w.S.ptr, n * nb * sizeof(cx<double>));
+        Small s(c->small[1]);
+        s.setup(1, nb, 1);
+        std::vector<double> rn(nb);
+        for (;;) {
+          norm2<double>(c, Rr, n, n, nb, s.nrm2);
+          d2h(c, rn.data(), s.nrm2, nb * sizeof(double));
+          bool all = true;
+          int maxc = 0;
+          for (int r = 0; r < nb; ++r) {
+            rn[r] = std::sqrt(rn[r]);
+            LQCD_CHECK(std::isfinite(rn[r]), LQCD_ENAN, "gmresdr_solve: NaN/Inf residual");
+            res[r] = rn[r] / ref[r];
+            if (rn[r] > p.tol * ref[r]) all = false;
+            maxc = std::max(maxc, cy[r]);
+          }
+          if (all || maxc >= p.max_cycles) break;
+          // inner solve for the correction of every rhs not yet converged;
+          // converged ones get a zero right-hand side (skipped at once).
+          convert<double, float>(c, Rr, S32, n * nb);
+          std::vector<double> iref(nb);
+          for (int r = 0; r < nb; ++r) iref[r] = (rn[r] > p.tol * ref[r]) ? rn[r] : 0.0;
+          std::vector<double> ires(nb);
+          const double itol = std::max(p.inner_tol, 1e-6);
+          proj_solve<float>(c, A32, d->V32.ptr, d, p_cyc, S32, X32, R32, W32, nb, iref, itol,
+                            p.max_cycles, mv, cy, ires);
+          hipLaunchKernelGGL(k_acc_widen, dim3(std::min<size_t>(nblocks(n * nb), 8192)), dim3(kBlock),
+                             0, c->stream, static_cast<const cx<float> *>(X32), static_cast<cx<double> *>(X),
+                             n * nb);
+          LQCD_HIP(hipGetLastError());
+          A64.apply(X, n, T, n, nb);
+          cdouble one(1, 0), mone(-1, 0);
+          copy_dev(c, Rr, w.S.ptr, n * nb * sizeof(cx<double>));
+          axpby<double>(c, &mone, T, n, &one, Rr, n, n, nb, false);
+          for (int r = 0; r < nb; ++r) {
+            refn[r] += 1;
+            mv[r] += 1;
+          }
+        }
+      }
+      finish(c, op, X, xl, nb, w, n, tr);
+      for (int r = 0; r < nb; ++r) {
+        if (stats) stats[r0 + r] = lqcd_solve_stats{mv[r], cy[r], refn[r], tr[r]};
+        if (res[r] > p.tol) nonconv = true;
+      }
+    }
+    LQCD_CHECK(!nonconv, LQCD_ENOCONV, "gmresdr_solve: a right-hand side missed tol within max_cycles");
+  });
+}
+
+extern "C" lqcd_status lqcd_defl_eigpairs(lqcd_ctx *c, lqcd_defl *d, int Q, double *lambda_host,
+                                          double *resid_host) {
+  return guarded([&] {
+    LQCD_CHECK(c && d && lambda_host, LQCD_EINVAL, "lqcd_defl_eigpairs: null argument");
+    defl_eigpairs(c, d, Q);
+    for (int q = 0; q < Q; ++q) {
+      lambda_host[q] = d->lam[q];
+      if (resid_host) resid_host[q] = d->lam_resid[q];
+    }
+  });
+}
+
+extern "C" lqcd_status lqcd_defl_ritz(const lqcd_defl *d, double *theta_host, int *k_out) {
+  return guarded([&] {
+    LQCD_CHECK(d && theta_host && k_out, LQCD_EINVAL, "lqcd_defl_ritz: null argument");
+    *k_out = int(d->theta.size());
+    for (size_t i = 0; i < d->theta.size(); ++i) {
+      theta_host[2 * i] = d->theta[i].real();
+      theta_host[2 * i + 1] = d->theta[i].imag();
+    }
+  });
+}
+
+extern "C" void lqcd_defl_free(lqcd_defl *d) { delete d; }

@@ -230,10 +230,10 @@ class Context:
         p = SolveParams(m, k, max_cycles, tol, tol_super, eig_tol, n_eig, _PREC[inner], inner_tol,
                         rhs_block)
         stats = (SolveStats * max(nrhs, 1))()
-        h = _P(defl.handle if defl is not None else None)
+        h = _P(defl.handle.value if defl is not None else None)
         code = lib().gmresdr_solve(self.handle, _OPS[op], ctypes.byref(p), _ptr(b), _ptr(x), nrhs,
                                    ctypes.byref(h), stats)
-        newdefl = Deflation(h, self) if (defl is None and h.value) else defl
+        newdefl = Deflation(_P(h.value), self) if (defl is None and h.value) else defl
         _check(code)
         st = [dict(matvecs=s.matvecs, cycles=s.cycles, refinements=s.refinements,
                    true_resid=s.true_resid) for s in stats[:nrhs]]

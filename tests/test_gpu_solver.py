@@ -1,0 +1,124 @@
+"""GPU parity of gmresdr_solve (GMRES-DR + GMRES-Proj, Sec. 7) against the oracle.
+
+Solutions are compared with dense LU (|x - x_LU| / |x_LU| <= 1e-10 in
+FP64), converged harmonic Ritz values with the dense spectrum of the
+even/odd operator, hermitian Rayleigh-Ritz pairs with dense eigh (through
+the projector sum_q e e^+ / lambda, since phases and degenerate rotations
+are free).  Iteration counts are not compared.  The full-size case checks
+the true residual recomputed by the oracle.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import require_gpu, context, to_gpu, to_host, say, rel_err
+from oracle import lattice as L
+from oracle import wilson as W
+from oracle import krylov as K
+from oracle.noise import z4_noise
+
+pytestmark = pytest.mark.gpu
+
+
+def _dense_solve(U, kappa, dims, eta):
+    M = W.dense_M(U, kappa, dims)
+    n = eta.shape[0]
+    return np.linalg.solve(M, eta.reshape(n, -1).T).T.reshape(eta.shape), M
+
+
+@pytest.mark.parametrize("dims,kappa,nrhs,block", [((4, 4, 4, 4), 0.12, 4, 2),
+                                                    ((6, 4, 2, 8), 0.13, 5, 3)])
+def test_schur_solve_fp64(dims, kappa, nrhs, block):
+    require_gpu()
+    ctx, U = context(dims, 0.3, 1001, kappa)
+    eta = z4_noise(2001, dims, 0, nrhs)
+    say("solve schur f64", dims, kappa, nrhs, block)
+    x, defl, st = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=20, k=10, tol=1e-12,
+                                    tol_super=1e-13, rhs_block=block)
+    x = to_host(x)
+    xref, _ = _dense_solve(U, kappa, dims, eta)
+    for r in range(nrhs):
+        assert rel_err(x[r], xref[r]) < 1e-10, r
+        assert st[r]["true_resid"] < 1e-11, st[r]
+    # a second call reuses the deflation space (GMRES-Proj for every rhs)
+    say("solve schur f64 reuse", dims)
+    x2, _, st2 = ctx.gmresdr_solve(to_gpu(eta[1:2]), op="schur", m=20, k=10, tol=1e-12, defl=defl)
+    assert rel_err(to_host(x2)[0], xref[1]) < 1e-10
+
+
+def test_harmonic_ritz_values_gpu():
+    """Super-converged GMRES-DR: converged harmonic Ritz values are
+    eigenvalues of Mhat (dense), like the oracle's."""
+    require_gpu()
+    dims, kappa = (4, 4, 2, 4), 0.13
+    ctx, U = context(dims, 0.3, 31, kappa)
+    eta = z4_noise(5, dims, 0, 1)
+    say("ritz", dims)
+    _, defl, st = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=14, k=7, tol=1e-13, tol_super=1e-13,
+                                    eig_tol=1e-11, n_eig=3, max_cycles=400)
+    theta = defl.ritz()
+    ev, od = L.eo_tables(dims)
+    M = W.dense_M(U, kappa, dims)
+    ie = np.concatenate([np.arange(12 * s, 12 * s + 12) for s in ev])
+    io = np.concatenate([np.arange(12 * s, 12 * s + 12) for s in od])
+    Mhat = np.eye(ie.size) - M[np.ix_(ie, io)] @ M[np.ix_(io, ie)]
+    lam = np.linalg.eigvals(Mhat)
+    # oracle run on the same problem
+    shape = eta[0].shape
+    A = lambda v: W.apply_Mhat(U, kappa, v.reshape(shape), dims).ravel()
+    src = W.eo_source(U, kappa, eta[0], dims).ravel()
+    _, oinfo = K.gmres_dr(A, src, 14, 7, 1e-13, max_cycles=400, eig_tol=1e-11, n_eig=3)
+    for t in theta[:3]:
+        assert np.min(np.abs(lam - t)) < 1e-9
+        assert np.min(np.abs(oinfo["theta"] - t)) < 1e-9
+
+
+def test_hermitian_solve_and_eigpairs():
+    require_gpu()
+    dims, kappa = (4, 4, 2, 4), 0.125
+    ctx, U = context(dims, 0.3, 31, kappa)
+    eta = z4_noise(5, dims, 0, 2)
+    say("solve MG5", dims)
+    x, defl, st = ctx.gmresdr_solve(to_gpu(eta), op="MG5", m=40, k=20, tol=1e-12, tol_super=1e-13,
+                                    eig_tol=1e-11, n_eig=8, max_cycles=300)
+    M = W.dense_M(U, kappa, dims)
+    Mp = M @ W.dense_gamma(L.GAMMA5, L.volume(dims))
+    xref = np.linalg.solve(Mp, eta.reshape(2, -1).T).T
+    x = to_host(x).reshape(2, -1)
+    for r in range(2):
+        assert rel_err(x[r], xref[r]) < 1e-10
+    Q = 6
+    lam, res = defl.eigpairs(Q)
+    lam_d, E_d = K.hermitian_eigpairs_dense(Mp, Q)
+    assert (res < 1e-9).all()
+    assert np.abs(lam - lam_d).max() < 1e-9
+
+
+@pytest.mark.parametrize("dims,kappa", [((4, 4, 4, 4), 0.12), ((6, 4, 2, 8), 0.13)])
+def test_mixed_precision_solve(dims, kappa):
+    require_gpu()
+    ctx, U = context(dims, 0.3, 1001, kappa)
+    eta = z4_noise(2001, dims, 0, 5)
+    say("solve mixed", dims)
+    x, defl, st = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=20, k=10, tol=1e-11, tol_super=1e-13,
+                                    inner="f32", inner_tol=1e-5, rhs_block=4)
+    x = to_host(x)
+    xref, _ = _dense_solve(U, kappa, dims, eta)
+    for r in range(5):
+        assert rel_err(x[r], xref[r]) < 1e-9
+        assert st[r]["true_resid"] < 1e-11
+    assert all(s["refinements"] >= 1 for s in st[1:])
+
+
+def test_full_size_true_residual_16x32():
+    require_gpu()
+    dims, kappa = (16, 16, 16, 32), 0.12
+    ctx, U = context(dims, 0.25, 1002, kappa)
+    eta = z4_noise(2002, dims, 0, 3)
+    say("solve full size", dims)
+    x, defl, st = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=50, k=30, tol=1e-10, tol_super=1e-12,
+                                    rhs_block=2)
+    x = to_host(x)
+    for r in range(3):
+        res = np.linalg.norm(eta[r] - W.apply_M(U, kappa, x[r])) / np.linalg.norm(eta[r])
+        assert res < 1.5e-10, (r, res)
+        assert abs(res - st[r]["true_resid"]) < 1e-12

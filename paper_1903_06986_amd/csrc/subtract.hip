@@ -1,0 +1,557 @@
+// Subtraction vectors and exact trace corrections (Sec. 5).
+//
+//  pert_subtract   PS:   xt = sum_{j=0}^{n} (kappa P)^j eta           (Eqs. (28), (31))
+//  poly_subtract   POLY: xt = sum_j c_j (kappa P)^j eta, c from the Min-Res
+//                  polynomial of one noise vector                    (Eqs. (40)-(50))
+//  deflate_project HFES / hermitian-forced overlap removal:
+//                  xt += g5 sum_q w_q e'_q (e'_q^+ eta)              (Eqs. (66)-(72))
+//
+// Polynomials are applied by Horner's rule, y <- c_j eta + kappa P y, one
+// stencil pass (both parities) per degree.
+//
+// Trace corrections.  Tr_t(Theta p(kappa P)) = sum_j c_j kappa^j
+// Tr_t(Theta P^j), and only closed paths contribute (Sec. 5.1): expanding
+// P^j into sequences of hops, the diagonal element at site x is a sum over
+// closed walks w of length j starting at x of (spin product S_w) x (link
+// product W_w(x)), so Tr(Theta P^j)_xx = sum_w tr(Theta S_w) tr W_w(x).
+// A hop followed by its reverse carries (1 - g)(1 + g) = 0, so only
+// non-backtracking walks survive; on lattices with even extents every
+// closed walk has even length.  The host enumerates the walks (closed
+// modulo the periodic extents, so windings on short directions count) and
+// their spin traces; the device forms the link products at every site.
+// The paper obtains the same traces from unit-vector sources (Eqs.
+// (32)-(35)); the walk sum is that computation with every source's
+// non-returning paths dropped.
+#include <algorithm>
+#include <cmath>
+
+#include "cplx.h"
+#include "fields.h"
+#include "gamma.h"
+#include "smallla.h"
+#include "solver.h"
+
+namespace lqcd {
+
+namespace {
+
+// ---------------------------------------------------------- walk tables
+constexpr int kMaxWalkLen = 6;  // closed walks of length <= 6 (orders <= 7)
+
+struct Walk {
+  int len;
+  int dir[kMaxWalkLen];       // 2 * mu + (0: +mu, 1: -mu)
+  double coef[kNumTheta][2];  // tr(Theta S_w), Theta = 1, g1..g4
+};
+
+using Spin = std::complex<double>[4][4];
+
+void enumerate(int len, const int L[4], int depth, int last, int disp[4], const Spin &S,
+               int dirs[kMaxWalkLen], std::vector<Walk> &out) {
+  if (depth == len) {
+    for (int mu = 0; mu < 4; ++mu)
+      if (((disp[mu] % L[mu]) + L[mu]) % L[mu] != 0) return;
+    Walk w;
+    w.len = len;
+    for (int i = 0; i < len; ++i) w.dir[i] = dirs[i];
+    bool any = false;
+    for (int th = 0; th < kNumTheta; ++th) {
+      std::complex<double> G[4][4];
+      gamma_dense(th, G);
+      std::complex<double> t = 0;
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) t += G[a][b] * S[b][a];
+      w.coef[th][0] = t.real();
+      w.coef[th][1] = t.imag();
+      if (std::abs(t) > 1e-12) any = true;
+    }
+    if (any) out.push_back(w);
+    return;
+  }
+  for (int d = 0; d < 8; ++d) {
+    if (depth > 0 && d == (last ^ 1)) continue;  // immediate reversal: zero spin factor
+    const int mu = d >> 1, sgn = (d & 1) ? -1 : 1;
+    disp[mu] += sgn;
+    int dist = 0;
+    for (int nu = 0; nu < 4; ++nu) {
+      int a = ((disp[nu] % L[nu]) + L[nu]) % L[nu];
+      dist += std::min(a, L[nu] - a);
+    }
+    if (dist <= len - depth - 1) {
+      // S' = S (1 - g_mu) for a forward hop, S (1 + g_mu) backward
+      std::complex<double> G[4][4], S2[4][4];
+      gamma_dense(1 + mu, G);
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          std::complex<double> s = 0;
+          for (int e = 0; e < 4; ++e) {
+            std::complex<double> f = (e == b ? 1.0 : 0.0) - double(sgn) * G[e][b];
+            s += S[a][e] * f;
+          }
+          S2[a][b] = s;
+        }
+      dirs[depth] = d;
+      enumerate(len, L, depth + 1, d, disp, S2, dirs, out);
+    }
+    disp[mu] -= sgn;
+  }
+}
+
+// Link U_mu at lexicographic coordinates (x, y, z, t) in the even/odd layout.
+__device__ inline const cx<double> *link_at(const cx<double> *U, const Geom &g, int x, int y, int z,
+                                            int t, int mu) {
+  const int p = (x + y + z + t) & 1;
+  const int s = x + g.L[0] * (y + g.L[1] * (z + g.L[2] * t));
+  return U + ((size_t(p) * 4 + mu) * 9) * g.Vh + (s >> 1);
+}
+
+// out[th][s] = sum_w coef_w[th] tr W_w(s) for every lexicographic site s.
+__global__ void __launch_bounds__(kBlock)
+    k_walk_trace(Geom g, const cx<double> *__restrict__ U, const Walk *__restrict__ walks,
+                 int nwalk, cx<double> *__restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const size_t Vh = g.Vh;
+  const int x0 = s % g.L[0], y0 = (s / g.L[0]) % g.L[1], z0 = (s / (g.L[0] * g.L[1])) % g.L[2],
+            t0 = s / (g.L[0] * g.L[1] * g.L[2]);
+  double acc[kNumTheta][2] = {};
+  for (int w = 0; w < nwalk; ++w) {
+    const Walk &wk = walks[w];
+    int c[4] = {x0, y0, z0, t0};
+    cx<double> W[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) W[a][b] = mk(a == b ? 1.0 : 0.0, 0.0);
+    for (int i = 0; i < wk.len; ++i) {
+      const int d = wk.dir[i], mu = d >> 1;
+      cx<double> Lk[3][3];
+      if ((d & 1) == 0) {  // forward: U_mu(c), then c += mu
+        const cx<double> *u = link_at(U, g, c[0], c[1], c[2], c[3], mu);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) Lk[a][b] = u[(3 * a + b) * Vh];
+        c[mu] = (c[mu] + 1 == g.L[mu]) ? 0 : c[mu] + 1;
+      } else {  // backward: c -= mu, then U_mu(c)^+
+        c[mu] = (c[mu] == 0) ? g.L[mu] - 1 : c[mu] - 1;
+        const cx<double> *u = link_at(U, g, c[0], c[1], c[2], c[3], mu);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            cx<double> v = u[(3 * b + a) * Vh];
+            Lk[a][b] = mk(v.re, -v.im);
+          }
+      }
+      cx<double> Nw[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Nw[a][b] = W[a][0] * Lk[0][b] + W[a][1] * Lk[1][b] + W[a][2] * Lk[2][b];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) W[a][b] = Nw[a][b];
+    }
+    const cx<double> tr = W[0][0] + W[1][1] + W[2][2];
+#pragma unroll
+    for (int th = 0; th < kNumTheta; ++th) {
+      acc[th][0] += wk.coef[th][0] * tr.re - wk.coef[th][1] * tr.im;
+      acc[th][1] += wk.coef[th][0] * tr.im + wk.coef[th][1] * tr.re;
+    }
+  }
+#pragma unroll
+  for (int th = 0; th < kNumTheta; ++th) out[size_t(th) * g.V + s] = mk(acc[th][0], acc[th][1]);
+}
+
+constexpr int kWaves = kBlock / 64;
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// out[row][t] = sum over the Vs sites of timeslice t of in[row][t * Vs + i]
+__global__ void __launch_bounds__(kBlock)
+    k_timeslice_sum(const cx<double> *__restrict__ in, int Vs, int Lt, cx<double> *__restrict__ out) {
+  __shared__ double sh[2][kWaves];
+  const int t = blockIdx.x, row = blockIdx.y;
+  const cx<double> *p = in + (size_t(row) * Lt + t) * Vs;
+  double a = 0, b = 0;
+  for (int i = threadIdx.x; i < Vs; i += kBlock) {
+    a += p[i].re;
+    b += p[i].im;
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[0][wave] = a;
+    sh[1][wave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0, sb = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      sa += sh[0][w];
+      sb += sh[1][w];
+    }
+    out[size_t(row) * Lt + t] = mk(sa, sb);
+  }
+}
+
+// Per-site bilinear for the hermitian-forced trace terms:
+// out[th][s] = sum_q w_q e_q(s)^+ Theta g5 e_q(s), e_q in the even/odd
+// layout (full fields n apart), s lexicographic.
+__global__ void __launch_bounds__(kBlock)
+    k_eig_bilinear(Geom g, const cx<double> *__restrict__ E, size_t n, int Q,
+                   const cx<double> *__restrict__ w, cx<double> *__restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const int x = s % g.L[0], y = (s / g.L[0]) % g.L[1], z = (s / (g.L[0] * g.L[1])) % g.L[2],
+            t = s / (g.L[0] * g.L[1] * g.L[2]);
+  const int p = (x + y + z + t) & 1;
+  const size_t Vh = g.Vh, off = size_t(p) * 12 * Vh + (s >> 1);
+  double acc[kNumTheta][2] = {};
+  for (int q = 0; q < Q; ++q) {
+    cx<double> e[4][3];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) e[sp][c] = E[q * n + off + (sp * 3 + c) * Vh];
+    const cx<double> wq = w[q];
+#pragma unroll
+    for (int th = 0; th < kNumTheta; ++th) {
+      // (Theta g5 e)_r = Theta_{r, col} g5_{col} e_col
+      cx<double> sum = mk(0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = kGamma[th].col[r];
+        const cx<double> tv = mk(kGamma[th].re[r] * kGamma[5].re[col], kGamma[th].im[r] * kGamma[5].re[col]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sum = sum + cmulc(e[r][c], tv * e[col][c]);
+      }
+      cx<double> v = wq * sum;
+      acc[th][0] += v.re;
+      acc[th][1] += v.im;
+    }
+  }
+#pragma unroll
+  for (int th = 0; th < kNumTheta; ++th) out[size_t(th) * g.V + s] = mk(acc[th][0], acc[th][1]);
+}
+
+// In place g5 on full even/odd fields: negate spins 2, 3 (components 6..11).
+__global__ void k_g5_eo(cx<double> *__restrict__ f, size_t Vh, size_t stride, int nf) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t per = 2 * 6 * Vh;  // per field: two parities x 6 lower components
+  if (i >= per * nf) return;
+  const size_t fidx = i / per, r = i % per;
+  const size_t par = r / (6 * Vh), k = r % (6 * Vh);
+  cx<double> *p = f + fidx * stride + par * 12 * Vh + 6 * Vh + k;
+  *p = -*p;
+}
+
+void h2d(lqcd_ctx *c, void *dst, const void *src, size_t bytes) {
+  LQCD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+  LQCD_HIP(hipStreamSynchronize(c->stream));
+}
+void d2h(lqcd_ctx *c, void *dst, const void *src, size_t bytes) {
+  LQCD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
+  LQCD_HIP(hipStreamSynchronize(c->stream));
+}
+
+// Per-timeslice sums of nrow site fields [row][V] (lexicographic).
+std::vector<cdouble> timeslice_rows(lqcd_ctx *c, const void *site, int nrow, DevBuf &tmp) {
+  const Geom &g = c->g;
+  const int Lt = g.L[3], Vs = g.V / Lt;
+  cdouble *d = static_cast<cdouble *>(tmp.ensure(size_t(nrow) * Lt * sizeof(cdouble)));
+  hipLaunchKernelGGL(k_timeslice_sum, dim3(Lt, nrow), dim3(kBlock), 0, c->stream,
+                     static_cast<const cx<double> *>(site), Vs, Lt, reinterpret_cast<cx<double> *>(d));
+  LQCD_HIP(hipGetLastError());
+  std::vector<cdouble> h(size_t(nrow) * Lt);
+  d2h(c, h.data(), d, h.size() * sizeof(cdouble));
+  return h;
+}
+
+// Tr_t(Theta P^j) for j = 0..kMaxOrder, filled once per context.
+void ensure_walk_traces(lqcd_ctx *c) {
+  if (c->have_walk_traces) return;
+  const Geom &g = c->g;
+  const int Lt = g.L[3], Vs = g.V / Lt;
+  std::vector<cdouble> T(size_t(kMaxOrder + 1) * kNumTheta * Lt, 0.0);
+  for (int t = 0; t < Lt; ++t) T[0 * kNumTheta * Lt + 0 * Lt + t] = 12.0 * Vs;  // Tr(1) per slice
+  DevBuf site, walks, tmp;
+  site.ensure(size_t(kNumTheta) * g.V * sizeof(cdouble));
+  for (int j = 1; j <= kMaxOrder; ++j) {
+    if (j % 2 == 1 || j > kMaxWalkLen) continue;  // odd walks cannot close on even extents
+    std::vector<Walk> ws;
+    int disp[4] = {0, 0, 0, 0}, dirs[kMaxWalkLen];
+    std::complex<double> I[4][4];
+    gamma_dense(0, I);
+    enumerate(j, g.L, 0, -1, disp, I, dirs, ws);
+    if (ws.empty()) continue;
+    walks.ensure(ws.size() * sizeof(Walk));
+    h2d(c, walks.ptr, ws.data(), ws.size() * sizeof(Walk));
+    hipLaunchKernelGGL(k_walk_trace, dim3(nblocks(g.V)), dim3(kBlock), 0, c->stream, g,
+                       static_cast<const cx<double> *>(c->U64.ptr), walks.as<Walk>(), int(ws.size()),
+                       site.as<cx<double>>());
+    LQCD_HIP(hipGetLastError());
+    std::vector<cdouble> ts = timeslice_rows(c, site.ptr, kNumTheta, tmp);
+    for (int th = 0; th < kNumTheta; ++th)
+      for (int t = 0; t < Lt; ++t) T[(size_t(j) * kNumTheta + th) * Lt + t] = ts[size_t(th) * Lt + t];
+  }
+  c->walk_traces = T;
+  c->have_walk_traces = true;
+}
+
+// corr[th][t] = sum_j coeffs[j] kappa^j Tr_t(Theta_th P^j)
+void poly_trace(lqcd_ctx *c, const std::vector<cdouble> &coeffs, const int *thetas, int nth,
+                double *corr_host) {
+  ensure_walk_traces(c);
+  const int Lt = c->g.L[3];
+  for (int a = 0; a < nth; ++a)
+    for (int t = 0; t < Lt; ++t) {
+      cdouble s = 0;
+      double kj = 1;
+      for (size_t j = 0; j < coeffs.size(); ++j, kj *= c->kappa)
+        s += coeffs[j] * kj * c->walk_traces[(j * kNumTheta + thetas[a]) * Lt + t];
+      corr_host[2 * (a * Lt + t)] = s.real();
+      corr_host[2 * (a * Lt + t) + 1] = s.imag();
+    }
+}
+
+// y = sum_j coeffs[j] (kappa P)^j e on full even/odd FP64 fields (nf of
+// them, fl apart).  Returns the buffer holding the result (a or b).
+cx<double> *horner(lqcd_ctx *c, const std::vector<cdouble> &coeffs, const cx<double> *e,
+                   cx<double> *a, cx<double> *b, int nf) {
+  const size_t hl = half_len(c->g), fl = full_len(c->g);
+  const int d = int(coeffs.size()) - 1;
+  cdouble zero(0, 0);
+  axpby<double>(c, &coeffs[d], e, fl, &zero, a, fl, fl, nf, false);
+  cx<double> *y = a, *yn = b;
+  for (int j = d - 1; j >= 0; --j) {
+    for (int p = 0; p < 2; ++p)
+      hop_half<double>(c, p, y + (1 - p) * hl, e + p * hl, yn + p * hl, coeffs[j], c->kappa, false,
+                       false, nf, fl, fl, fl);
+    std::swap(y, yn);
+  }
+  return y;
+}
+
+void check_thetas(const int *th, int nth) {
+  LQCD_CHECK(nth >= 0 && (nth == 0 || th), LQCD_EINVAL, "thetas: null or negative count");
+  for (int a = 0; a < nth; ++a)
+    LQCD_CHECK(th[a] >= 0 && th[a] < kNumTheta, LQCD_EINVAL, "theta code %d outside 0..4", th[a]);
+}
+
+// xt (lex) = p(kappa P) eta (lex) for nrhs fields, in blocks.
+void apply_poly_lex(lqcd_ctx *c, const std::vector<cdouble> &coeffs, const void *eta, void *xt,
+                    int nrhs) {
+  const size_t fl = full_len(c->g);
+  const int blk = 8;
+  for (int r0 = 0; r0 < nrhs; r0 += blk) {
+    const int nb = std::min(blk, nrhs - r0);
+    cx<double> *E = static_cast<cx<double> *>(c->ws[0].ensure(fl * nb * sizeof(cx<double>)));
+    cx<double> *A = static_cast<cx<double> *>(c->ws[1].ensure(fl * nb * sizeof(cx<double>)));
+    cx<double> *B = static_cast<cx<double> *>(c->ws[2].ensure(fl * nb * sizeof(cx<double>)));
+    pack_eo<double>(c, static_cast<const cdouble *>(eta) + r0 * fl, E, nb, fl);
+    cx<double> *Y = horner(c, coeffs, E, A, B, nb);
+    unpack_eo<double>(c, Y, static_cast<cdouble *>(xt) + r0 * fl, nb, fl);
+  }
+}
+
+std::vector<cdouble> kp_to_m(const std::vector<cdouble> &cc) {
+  // (kappa P)^j = (1 - M)^j = sum_k C(j,k) (-1)^k M^k
+  const int d = int(cc.size()) - 1;
+  std::vector<cdouble> a(d + 1, 0.0);
+  for (int j = 0; j <= d; ++j) {
+    double binom = 1;
+    for (int k = 0; k <= j; ++k) {
+      a[k] += cc[j] * binom * ((k % 2) ? -1.0 : 1.0);
+      binom = binom * (j - k) / (k + 1);
+    }
+  }
+  return a;
+}
+
+}  // namespace
+
+}  // namespace lqcd
+
+using namespace lqcd;
+
+extern "C" lqcd_status pert_subtract(lqcd_ctx *c, int order, const int *thetas, int nth,
+                                     const void *eta, void *xt, int nrhs, double *corr) {
+  return guarded([&] {
+    LQCD_CHECK(c, LQCD_EINVAL, "pert_subtract: null context");
+    LQCD_CHECK(order >= 0 && order <= kMaxOrder, LQCD_EINVAL, "pert_subtract: order %d outside 0..%d",
+               order, kMaxOrder);
+    LQCD_CHECK(nrhs >= 0 && (nrhs == 0 || (eta && xt)), LQCD_EINVAL, "pert_subtract: null field");
+    check_thetas(thetas, nth);
+    std::vector<cdouble> coeffs(order + 1, cdouble(1, 0));
+    apply_poly_lex(c, coeffs, eta, xt, nrhs);
+    if (corr) poly_trace(c, coeffs, thetas, nth, corr);
+  });
+}
+
+extern "C" lqcd_status poly_subtract(lqcd_ctx *c, int degree, const void *b, double *coeffs_host,
+                                     double *a_host, const int *thetas, int nth, const void *eta,
+                                     void *xt, int nrhs, double *corr) {
+  return guarded([&] {
+    LQCD_CHECK(c && coeffs_host, LQCD_EINVAL, "poly_subtract: null argument");
+    LQCD_CHECK(degree >= 0 && degree <= kMaxOrder, LQCD_EINVAL, "poly_subtract: degree %d outside 0..%d",
+               degree, kMaxOrder);
+    LQCD_CHECK(nrhs >= 0 && (nrhs == 0 || (eta && xt)), LQCD_EINVAL, "poly_subtract: null field");
+    check_thetas(thetas, nth);
+    const int d1 = degree + 1;
+    const size_t fl = full_len(c->g), hl = half_len(c->g);
+    std::vector<cdouble> cc(d1);
+    if (b) {
+      // Columns w_j = M (kappa P)^j b = y_j - y_{j+1} with y_{j+1} = kappa P y_j.
+      cx<double> *Y = static_cast<cx<double> *>(c->ws[3].ensure(fl * (d1 + 1) * sizeof(cx<double>)));
+      cx<double> *Wc = static_cast<cx<double> *>(c->ws[4].ensure(fl * (d1 + 1) * sizeof(cx<double>)));
+      pack_eo<double>(c, b, Y, 1, fl);
+      for (int j = 0; j < d1; ++j)
+        for (int p = 0; p < 2; ++p)
+          hop_half<double>(c, p, Y + j * fl + (1 - p) * hl, nullptr, Y + (j + 1) * fl + p * hl,
+                           cdouble(0, 0), c->kappa, false, false, 1, fl, 0, fl);
+      cdouble one(1, 0), mone(-1, 0);
+      for (int j = 0; j < d1; ++j) {  // W_j = y_j - y_{j+1}
+        cdouble z(0, 0);
+        axpby<double>(c, &one, Y + j * fl, 0, &z, Wc + j * fl, 0, fl, 1, false);
+        axpby<double>(c, &mone, Y + (j + 1) * fl, 0, &one, Wc + j * fl, 0, fl, 1, false);
+      }
+      // b in the last slot of Wc (packed copy of y_0)
+      cdouble z(0, 0);
+      axpby<double>(c, &one, Y, 0, &z, Wc + d1 * fl, 0, fl, 1, false);
+      // Gram matrix G = W^H W and g = W^H b, then FP64 normal equations with
+      // one step of iterative refinement on the residual b - W c.
+      cdouble *Gd = static_cast<cdouble *>(c->ws[5].ensure(size_t(d1 + 1) * d1 * sizeof(cdouble)));
+      gemm_tn<double>(c, Wc, fl, d1, Wc, fl, d1 + 1, fl, Gd, d1);
+      std::vector<cdouble> Gh(size_t(d1) * (d1 + 1));
+      d2h(c, Gh.data(), Gd, Gh.size() * sizeof(cdouble));
+      la::Mat G(d1, d1);
+      std::vector<cdouble> g(d1);
+      for (int j = 0; j < d1; ++j) {
+        for (int i = 0; i < d1; ++i) G(i, j) = Gh[size_t(j) * d1 + i];
+        g[j] = Gh[size_t(d1) * d1 + j];
+      }
+      cc = la::solve(G, g);
+      // refinement: r = b - W c; c += G^{-1} W^H r
+      cdouble *cd_dev = static_cast<cdouble *>(c->ws[6].ensure(size_t(d1) * sizeof(cdouble)));
+      cx<double> *Rb = Y + d1 * fl;  // reuse y_{d+1} slot for the residual
+      axpby<double>(c, &one, Y, 0, &z, Rb, 0, fl, 1, false);
+      h2d(c, cd_dev, cc.data(), d1 * sizeof(cdouble));
+      gemm_nn<double>(c, Wc, fl, 0, d1, cd_dev, d1, 0, Rb, fl, 0, 1, fl, 1, -1.0);
+      gemm_tn<double>(c, Wc, fl, d1, Rb, fl, 1, fl, Gd, d1);
+      std::vector<cdouble> gr(d1);
+      d2h(c, gr.data(), Gd, d1 * sizeof(cdouble));
+      std::vector<cdouble> dc = la::solve(G, gr);
+      for (int j = 0; j < d1; ++j) cc[j] += dc[j];
+      for (int j = 0; j < d1; ++j) {
+        coeffs_host[2 * j] = cc[j].real();
+        coeffs_host[2 * j + 1] = cc[j].imag();
+      }
+    } else {
+      for (int j = 0; j < d1; ++j) cc[j] = cdouble(coeffs_host[2 * j], coeffs_host[2 * j + 1]);
+    }
+    if (a_host) {
+      std::vector<cdouble> a = kp_to_m(cc);
+      for (int j = 0; j < d1; ++j) {
+        a_host[2 * j] = a[j].real();
+        a_host[2 * j + 1] = a[j].imag();
+      }
+    }
+    apply_poly_lex(c, cc, eta, xt, nrhs);
+    if (corr) poly_trace(c, cc, thetas, nth, corr);
+  });
+}
+
+extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_defl_mode mode,
+                                       const double *coeffs_host, int ncoeff, const int *thetas,
+                                       int nth, const void *eta, void *xt, int nrhs,
+                                       double *corr, double *xi_inv_host) {
+  return guarded([&] {
+    LQCD_CHECK(c && d, LQCD_EINVAL, "deflate_project: null argument");
+    LQCD_CHECK(mode == LQCD_DEFL_HFES || mode == LQCD_DEFL_EIGPOLY, LQCD_EINVAL,
+               "deflate_project: bad mode");
+    LQCD_CHECK(nrhs >= 0 && (nrhs == 0 || (eta && xt)), LQCD_EINVAL, "deflate_project: null field");
+    LQCD_CHECK(mode == LQCD_DEFL_HFES || (coeffs_host && ncoeff >= 1 && ncoeff <= kMaxOrder + 1),
+               LQCD_EINVAL, "deflate_project: EIGPOLY needs 1..%d polynomial coefficients", kMaxOrder + 1);
+    for (int i = 0; i < 4; ++i)
+      LQCD_CHECK(d->dims[i] == c->g.L[i], LQCD_EINVAL, "deflate_project: deflation space of another lattice");
+    LQCD_CHECK(d->kappa == c->kappa, LQCD_EINVAL, "deflate_project: deflation space of another kappa");
+    check_thetas(thetas, nth);
+    defl_eigpairs(c, d, Q);
+    const size_t fl = full_len(c->g), hl = half_len(c->g);
+    const cx<double> *E = d->E.as<cx<double>>();
+    std::vector<cdouble> w(Q), xi(Q, 0.0);
+    for (int q = 0; q < Q; ++q) w[q] = 1.0 / d->lam[q];
+    if (mode == LQCD_DEFL_EIGPOLY) {
+      // 1/xi'_q = e'^+ g5 p(kappa P) e'  (Eq. (69) with M'_poly^{-1} = g5 p)
+      std::vector<cdouble> cc(ncoeff);
+      for (int j = 0; j < ncoeff; ++j) cc[j] = cdouble(coeffs_host[2 * j], coeffs_host[2 * j + 1]);
+      cx<double> *A = static_cast<cx<double> *>(c->ws[1].ensure(fl * Q * sizeof(cx<double>)));
+      cx<double> *B = static_cast<cx<double> *>(c->ws[2].ensure(fl * Q * sizeof(cx<double>)));
+      cx<double> *Y = horner(c, cc, E, A, B, Q);
+      size_t tot = 2 * 6 * size_t(c->g.Vh) * Q;
+      hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(tot)), dim3(kBlock), 0, c->stream, Y, size_t(c->g.Vh), fl, Q);
+      LQCD_HIP(hipGetLastError());
+      cdouble *Cd = static_cast<cdouble *>(c->ws[5].ensure(size_t(Q) * sizeof(cdouble)));
+      // xi_inv[q] = <E_q, Y_q>: a batched dot with each vector its own basis of one
+      multi_dot<double>(c, E, fl, fl, 1, Y, fl, fl, Q, Cd, 1);
+      d2h(c, xi.data(), Cd, Q * sizeof(cdouble));
+      for (int q = 0; q < Q; ++q) w[q] -= xi[q];
+      (void)hl;
+    }
+    if (xi_inv_host)
+      for (int q = 0; q < Q; ++q) {
+        xi_inv_host[2 * q] = xi[q].real();
+        xi_inv_host[2 * q + 1] = xi[q].imag();
+      }
+    // trace correction: sum_q w_q e_q^+ Theta g5 e_q per timeslice
+    if (corr && nth > 0) {
+      cdouble *wd = static_cast<cdouble *>(c->ws[6].ensure(size_t(Q) * sizeof(cdouble)));
+      h2d(c, wd, w.data(), Q * sizeof(cdouble));
+      cx<double> *site = static_cast<cx<double> *>(c->ws[7].ensure(size_t(kNumTheta) * c->g.V * sizeof(cdouble)));
+      hipLaunchKernelGGL(k_eig_bilinear, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g, E, fl, Q,
+                         reinterpret_cast<const cx<double> *>(wd), site);
+      LQCD_HIP(hipGetLastError());
+      DevBuf tmp;
+      std::vector<cdouble> ts = timeslice_rows(c, site, kNumTheta, tmp);
+      const int Lt = c->g.L[3];
+      for (int a = 0; a < nth; ++a)
+        for (int t = 0; t < Lt; ++t) {
+          cdouble v = ts[size_t(thetas[a]) * Lt + t];
+          corr[2 * (a * Lt + t)] += v.real();
+          corr[2 * (a * Lt + t) + 1] += v.imag();
+        }
+    }
+    // xt += g5 E (w .* (E^H eta))
+    const int blk = 8;
+    for (int r0 = 0; r0 < nrhs; r0 += blk) {
+      const int nb = std::min(blk, nrhs - r0);
+      cx<double> *Et = static_cast<cx<double> *>(c->ws[0].ensure(fl * nb * sizeof(cx<double>)));
+      cx<double> *Yt = static_cast<cx<double> *>(c->ws[3].ensure(fl * nb * sizeof(cx<double>)));
+      cx<double> *Xl = static_cast<cx<double> *>(c->ws[4].ensure(fl * nb * sizeof(cx<double>)));
+      pack_eo<double>(c, static_cast<const cdouble *>(eta) + r0 * fl, Et, nb, fl);
+      cdouble *Cd = static_cast<cdouble *>(c->ws[5].ensure(size_t(Q) * nb * sizeof(cdouble)));
+      gemm_tn<double>(c, E, fl, Q, Et, fl, nb, fl, Cd, Q);
+      std::vector<cdouble> Ch(size_t(Q) * nb);
+      d2h(c, Ch.data(), Cd, Ch.size() * sizeof(cdouble));
+      for (int r = 0; r < nb; ++r)
+        for (int q = 0; q < Q; ++q) Ch[size_t(r) * Q + q] *= w[q];
+      h2d(c, Cd, Ch.data(), Ch.size() * sizeof(cdouble));
+      fill_zero(c, Yt, fl * nb * sizeof(cx<double>));
+      gemm_nn<double>(c, E, fl, 0, Q, Cd, Q, 0, Yt, fl, 0, nb, fl, 1, 1.0);
+      size_t tot = 2 * 6 * size_t(c->g.Vh) * nb;
+      hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(tot)), dim3(kBlock), 0, c->stream, Yt, size_t(c->g.Vh), fl, nb);
+      LQCD_HIP(hipGetLastError());
+      unpack_eo<double>(c, Yt, Xl, nb, fl);
+      cdouble one(1, 0);
+      cx<double> *xo = reinterpret_cast<cx<double> *>(static_cast<cdouble *>(xt) + r0 * fl);
+      axpby<double>(c, &one, Xl, fl, &one, xo, fl, fl, nb, false);
+    }
+  });
+}

@@ -1,0 +1,58 @@
+"""Full-path GPU parity on the 4^4 configuration (links exp(i 0.3 H),
+kappa = 0.12, 8 Z(4) noises, GMRES-DR(20,10), PS order 4, POLY degree 4,
+Q = 10 hermitian modes): GPU estimates of Tr(Theta M^{-1}) for all six
+methods against the oracle run on the same seeds.
+
+Bar: |T_gpu - T_oracle| <= 1e-9 max(|T|, sigma) per timeslice and total for
+NS, PS and POLY.  The hermitian-forced methods depend on eigenvectors that
+both sides obtain by independent super-converged iterations; their bar is
+set by how far those iterations converge (eigen-residual ~1e-11 relative
+to a smallest gap ~1e-3 on this lattice): 1e-6 max(|T|, sigma).
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import require_gpu, say
+from synth import random_su3_links, get_config
+from oracle import pipeline as opipe
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def both():
+    require_gpu()
+    from paper_1903_06986_amd import Context
+    from paper_1903_06986_amd import pipeline as gpipe
+    cfg = get_config("c1")
+    dims, kappa = cfg["dims"], cfg["kappas"][0]
+    U = random_su3_links(dims, cfg["eps"], cfg["link_seed"])
+    say("full path c1 gpu")
+    ctx = Context(dims, U, kappa)
+    g = gpipe.run(ctx, cfg["noise_seed"], cfg["n_noise"], cfg["m"], cfg["k"], cfg["pert_order"],
+                  cfg["poly_degree"], cfg["n_hermitian"], cfg["herm_m"], cfg["herm_k"], tol=1e-12,
+                  tol_super=1e-13, eig_tol=1e-12, rhs_block=4)
+    say("full path c1 oracle")
+    o = opipe.run(U, dims, kappa, cfg["noise_seed"], cfg["n_noise"], cfg["m"], cfg["k"],
+                  cfg["pert_order"], cfg["poly_degree"], cfg["n_hermitian"], tol=1e-12,
+                  tol_super=1e-13, herm_m=cfg["herm_m"], herm_k=cfg["herm_k"])
+    return g, o
+
+
+@pytest.mark.parametrize("meth", ["NS", "PS", "POLY", "HFES", "HFPS", "HFPOLY"])
+def test_estimates_match_oracle(both, meth):
+    g, o = both
+    eg, ee = g["methods"][meth]["est"], g["methods"][meth]["err"]
+    eo = o["methods"][meth]["est"]
+    sig = np.maximum(ee[..., 0], ee[..., 1])
+    scale = np.maximum(np.abs(eo), sig)
+    tol = 1e-9 if meth in ("NS", "PS", "POLY") else 1e-6
+    assert (np.abs(eg - eo) <= tol * scale).all(), np.max(np.abs(eg - eo) / scale)
+    # error bars agree as well
+    assert np.allclose(ee, o["methods"][meth]["err"], rtol=1e-6 if tol < 1e-8 else 1e-3, atol=1e-12)
+
+
+def test_poly_coefficients_and_modes(both):
+    g, o = both
+    assert np.abs(g["poly_c"] - o["poly_c"]).max() < 1e-8 * np.abs(o["poly_c"]).max()
+    assert np.abs(g["lam"] - o["lam"]).max() < 1e-9

@@ -1,0 +1,151 @@
+"""GPU parity of pert_subtract, poly_subtract, deflate_project and
+loop_estimate against the oracle, plus closed-form pins of the exact trace
+corrections (the GPU computes them by closed-walk enumeration, the oracle
+by dense powers / unit probes).
+
+Tolerances: subtraction vectors 1e-12 relative (FP64 stencil chains),
+trace corrections 1e-10 relative, Min-Res coefficients 1e-8 relative
+(normal equations on the GPU vs Householder QR in the oracle), estimates
+1e-9 * max(|T|, sigma) as the path's target states.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import require_gpu, context, to_gpu, to_host, say, rel_err
+from oracle import lattice as L
+from oracle import wilson as W
+from oracle import subtract as S
+from oracle import estimate as E
+from oracle import krylov as K
+from oracle.noise import z4_noise
+
+pytestmark = pytest.mark.gpu
+THETAS = (0, 1, 2, 3, 4)
+
+
+def _oracle_corr(U, kappa, coeffs, dims):
+    if L.volume(dims) <= 256:
+        A = S.poly_dense(W.dense_P(U, dims), kappa, coeffs)
+        return S.trace_correction_dense(A, dims, THETAS)
+    return S.trace_correction_probe(U, kappa, coeffs, dims, THETAS)
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (6, 4, 2, 8)])
+@pytest.mark.parametrize("order", [4, 7])
+def test_pert_subtract(dims, order):
+    require_gpu()
+    kappa = 0.12
+    ctx, U = context(dims, 0.3, 77, kappa)
+    eta = z4_noise(9, dims, 0, 3)
+    say("pert", dims, order)
+    xt, corr = ctx.pert_subtract(order, to_gpu(eta), THETAS)
+    ref = S.pert_vector(U, kappa, eta, order)
+    assert rel_err(to_host(xt), ref) < 1e-12
+    cref = _oracle_corr(U, kappa, S.pert_coeffs(order), dims)
+    assert np.abs(corr - cref).max() < 1e-10 * np.abs(cref).max()
+
+
+def _single_power_trace(ctx, j, n_t):
+    """Tr_t(Theta P^j) from poly_subtract with coefficients e_j at kappa = 1."""
+    import torch
+    c = np.zeros(j + 1, dtype=np.complex128)
+    c[j] = 1.0
+    eta = torch.zeros((1,) + ctx.shape, dtype=torch.complex128, device="cuda")
+    _, corr, _, _ = ctx.poly_subtract(j, eta, b=None, coeffs=c, thetas=THETAS)
+    return corr
+
+
+def test_trace_closed_forms_free_field_8():
+    """Free field, extents >= 7: Tr P^4 / V = -1152, Tr P^6 / V = -50688,
+    Tr P^2 = 0, and every g_mu trace vanishes."""
+    require_gpu()
+    dims = (8, 8, 8, 8)
+    ctx, _ = context(dims, 0.0, 0, 1.0, unit=True)
+    V = L.volume(dims)
+    say("free-field walk traces", dims)
+    for j, ref in ((2, 0.0), (4, -1152.0), (6, -50688.0)):
+        corr = _single_power_trace(ctx, j, dims[3])
+        assert abs(corr[0].sum() / V - ref) < 1e-9
+        assert np.abs(corr[1:]).max() < 1e-9
+        # translation invariance: equal timeslices
+        assert np.abs(corr[0] - corr[0].mean()).max() < 1e-8
+
+
+def test_trace_plaquette_form_L6():
+    """Random links, extents >= 5: Tr P^4 = -64 sum_plaq Re tr U_P and
+    Tr g4 P^4 = 0 (only plaquettes close in four hops)."""
+    require_gpu()
+    from tests.test_oracle_wilson import plaquette_sum
+    dims = (6, 6, 6, 6)
+    ctx, U = context(dims, 0.3, 12, 1.0)
+    say("plaquette walk traces", dims)
+    corr = _single_power_trace(ctx, 4, dims[3])
+    ref = -64.0 * plaquette_sum(U)
+    assert abs(corr[0].sum() - ref) < 1e-11 * abs(ref)
+    assert abs(corr[4].sum()) < 1e-10 * abs(ref)
+
+
+def test_poly_subtract():
+    require_gpu()
+    dims, kappa, d = (4, 4, 4, 4), 0.12, 7
+    ctx, U = context(dims, 0.3, 1001, kappa)
+    eta = z4_noise(2001, dims, 0, 4)
+    say("poly", dims, d)
+    xt, corr, c, a = ctx.poly_subtract(d, to_gpu(eta), b=to_gpu(eta[0:1]), thetas=THETAS)
+    c_ref, a_ref = S.poly_coeffs(U, kappa, eta[0], d)
+    assert np.abs(c - c_ref).max() < 1e-8 * np.abs(c_ref).max()
+    assert np.abs(a - a_ref).max() < 1e-7 * np.abs(a_ref).max()
+    # with the GPU's coefficients the vectors and corrections match to rounding
+    assert rel_err(to_host(xt), S.horner(U, kappa, eta, c)) < 1e-12
+    cref = _oracle_corr(U, kappa, c, dims)
+    assert np.abs(corr - cref).max() < 1e-10 * np.abs(cref).max()
+
+
+def test_deflate_project_vs_dense_eigenpairs():
+    require_gpu()
+    dims, kappa, Q = (4, 4, 2, 4), 0.125, 6
+    ctx, U = context(dims, 0.3, 31, kappa)
+    eta = z4_noise(5, dims, 0, 3)
+    say("deflate_project", dims)
+    _, hdefl, _ = ctx.gmresdr_solve(to_gpu(eta[0:1]), op="MG5", m=40, k=20, tol=1e-12, tol_super=1e-13,
+                                    eig_tol=1e-11, n_eig=Q + 2, max_cycles=300)
+    M = W.dense_M(U, kappa, dims)
+    Mp = M @ W.dense_gamma(L.GAMMA5, L.volume(dims))
+    lam, Ev = K.hermitian_eigpairs_dense(Mp, Q)
+    shape = eta[0].shape
+    Et = Ev.T.reshape((Q,) + shape)
+    # HFES
+    import torch
+    xt, corr, _ = ctx.deflate_project(hdefl, Q, to_gpu(eta), xt=torch.zeros((3,) + shape, dtype=torch.complex128,
+                                                                               device="cuda"))
+    inv = 1.0 / lam + 0j
+    assert rel_err(to_host(xt), S.eig_vector(Et, inv, eta)) < 1e-9
+    assert np.abs(corr - S.site_bilinear(Et, THETAS, dims, inv)).max() < 1e-9 * np.abs(corr).max()
+    # EIGPOLY with the perturbative polynomial: weights 1/lambda - 1/xi
+    cp = S.pert_coeffs(6)
+    xi = S.xi_inverse(U, kappa, Et, cp)
+    xt2, corr2, xi_gpu = ctx.deflate_project(hdefl, Q, to_gpu(eta), xt=torch.zeros_like(xt),
+                                             mode=1, coeffs=cp)
+    assert np.abs(xi_gpu - xi).max() < 1e-9 * np.abs(xi).max()
+    assert rel_err(to_host(xt2), S.eig_vector(Et, inv - xi, eta)) < 1e-9
+
+
+def test_loop_estimate_function():
+    require_gpu()
+    dims = (4, 2, 6, 4)
+    ctx, U = context(dims, 0.3, 3, 0.1)
+    rng = np.random.default_rng(8)
+    shape = (5,) + ctx.shape
+    eta = z4_noise(4, dims, 0, 5)
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    xt = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    corr = rng.standard_normal((5, dims[3])) + 1j * rng.standard_normal((5, dims[3]))
+    say("loop_estimate", dims)
+    est, err, smp = ctx.loop_estimate(to_gpu(eta), to_gpu(x), to_gpu(xt), corr, THETAS, samples=True)
+    t = E.samples(eta, x, xt, THETAS, dims)
+    e_ref, s_ref = E.estimate(t, corr)
+    assert np.abs(smp - t).max() < 1e-12 * np.abs(t).max()
+    assert np.abs(est - e_ref).max() < 1e-12 * np.abs(e_ref).max()
+    assert np.abs(err - s_ref).max() < 1e-12 * np.abs(s_ref).max()

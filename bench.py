@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Throughput of the deflated noise-solve path on one MI355X (gfx950).
+
+Workload (default): the 24^3 x 32 near-critical configuration -- links
+exp(i 0.2 H), kappa = (1 - 1e-3) / max Re mu(P) (synth/c3_kappa.json,
+written by oracle/critical_kappa.py), GMRES-DR(80,40) on eta^(0)
+super-converged, hermitian modes of M' (Q = 30), PS order 7, POLY degree 7.
+
+Setup (once per configuration, timed separately): first GMRES-DR solve,
+hermitian eigenpairs, Min-Res coefficients, exact trace corrections.
+One timed step = one batch of `rhs_block` Z(4) noise vectors through every
+per-noise row of the path: noise generation, GMRES-Proj solves to a 1e-10
+true residual (mixed: FP32 inner solves in FP64 refinement; or plain
+FP64), odd-site reconstruction and FP64 true residual, PS / POLY / HFES /
+HFPS / HFPOLY subtraction vectors and the estimator for Theta = 1, g1..g4.
+
+metric: deflated noise-solves/s (mixed precision), with the plain-FP64
+rate and the ratio in the same line; roofline of the dominant kernel from
+the library's event timers; cpu_baseline from the FP64 oracle on a bounded
+sample.  One GPU only.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+THETAS = (0, 1, 2, 3, 4)
+
+
+def workload(name, kappa_override=None):
+    from synth import get_config
+    cfg = get_config(name)
+    if kappa_override is not None:
+        kappa = kappa_override
+    elif cfg.get("kappas"):
+        kappa = cfg["kappas"][0]
+    else:
+        with open(os.path.join(ROOT, "synth", "%s_kappa.json" % name)) as f:
+            kappa = json.load(f)["kappa"]
+    return cfg, kappa
+
+
+def source_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(kernel_class, bytes_per_launch):
+    """HBM traffic per launch from committed rocprofv3 counter summaries, if
+    the kernel source is unchanged since they were taken; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel_class)
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    src = os.path.join(ROOT, "paper_1903_06986_amd", "csrc", t["source"])
+    if source_sha(src) != t["source_sha"]:
+        return None
+    return t["hbm_bytes_per_launch"]
+
+
+class Path:
+    """Per-configuration setup and the per-noise step, as library calls."""
+
+    def __init__(self, ctx, cfg, args):
+        self.ctx, self.cfg, self.args = ctx, cfg, args
+
+    def setup(self):
+        import torch
+        from paper_1903_06986_amd import lqcd
+        c, a, ctx = self.cfg, self.args, self.ctx
+        t0 = time.time()
+        eta0 = ctx.noise_z4(c["noise_seed"], 0, 1)
+        # Sec. 7: the first solve is super-converged so that its harmonic Ritz
+        # vectors are accurate eigenvectors for GMRES-Proj
+        x0, self.defl, st0 = ctx.gmresdr_solve(eta0, op="schur", m=c["m"], k=c["k"], tol=a.tol,
+                                               tol_super=a.tol_super, eig_tol=a.defl_eig_tol,
+                                               n_eig=a.defl_n_eig, max_cycles=a.max_cycles)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        _, self.hdefl, sth = ctx.gmresdr_solve(eta0, op="MG5", m=c["herm_m"], k=c["herm_k"],
+                                               tol=a.herm_tol, tol_super=a.herm_tol, eig_tol=a.eig_tol,
+                                               n_eig=c["n_hermitian"], max_cycles=a.max_cycles)
+        self.lam, self.lam_res = self.hdefl.eigpairs(c["n_hermitian"])
+        torch.cuda.synchronize()
+        t2 = time.time()
+        _, self.corr_poly, self.cpoly, self.apoly = ctx.poly_subtract(c["poly_degree"], eta0, b=eta0,
+                                                                      thetas=THETAS)
+        _, self.corr_pert = ctx.pert_subtract(c["pert_order"], eta0, THETAS)
+        torch.cuda.synchronize()
+        t3 = time.time()
+        self.setup_times = dict(first_solve_s=t1 - t0, hermitian_modes_s=t2 - t1,
+                                poly_and_traces_s=t3 - t2, total_s=t3 - t0)
+        self.first_stats, self.herm_stats = st0, sth
+        self.next_noise = 1
+        self.ones = np.ones(c["pert_order"] + 1, dtype=np.complex128)
+        del lqcd
+
+    def step(self, inner):
+        import torch
+        from paper_1903_06986_amd import lqcd
+        c, a, ctx = self.cfg, self.args, self.ctx
+        B, Q = a.rhs_block, c["n_hermitian"]
+        eta = ctx.noise_z4(c["noise_seed"], self.next_noise, B)
+        self.next_noise += B
+        x, _, st = ctx.gmresdr_solve(eta, op="schur", m=c["m"], k=c["k"], tol=a.tol, inner=inner,
+                                     inner_tol=a.inner_tol, rhs_block=B, max_cycles=a.max_cycles,
+                                     defl=self.defl)
+        res = {}
+        res["NS"] = ctx.loop_estimate(eta, x, None, None, THETAS)
+        xt_ps, _ = ctx.pert_subtract(c["pert_order"], eta, THETAS, want_corr=False)
+        res["PS"] = ctx.loop_estimate(eta, x, xt_ps, self.corr_pert, THETAS)
+        xt_poly, _, _, _ = ctx.poly_subtract(c["poly_degree"], eta, b=None, coeffs=self.cpoly,
+                                             thetas=THETAS, want_corr=False)
+        res["POLY"] = ctx.loop_estimate(eta, x, xt_poly, self.corr_poly, THETAS)
+        xt_hf, corr_hf, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=torch.zeros_like(eta),
+                                                mode=lqcd.DEFL_HFES, thetas=THETAS)
+        res["HFES"] = ctx.loop_estimate(eta, x, xt_hf, corr_hf, THETAS)
+        del xt_hf
+        xt_ps, corr_hfps, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=xt_ps, corr=self.corr_pert,
+                                                  mode=lqcd.DEFL_EIGPOLY, coeffs=self.ones, thetas=THETAS)
+        res["HFPS"] = ctx.loop_estimate(eta, x, xt_ps, corr_hfps, THETAS)
+        xt_poly, corr_hfpoly, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=xt_poly, corr=self.corr_poly,
+                                                      mode=lqcd.DEFL_EIGPOLY, coeffs=self.cpoly,
+                                                      thetas=THETAS)
+        res["HFPOLY"] = ctx.loop_estimate(eta, x, xt_poly, corr_hfpoly, THETAS)
+        return st, res
+
+
+def run_steps(path, inner, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        path.step(inner)
+    torch.cuda.synchronize()
+    path.ctx.timer(True)
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, _ = path.step(inner)
+        stats += st
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = path.ctx.timer_read()
+    path.ctx.timer(False)
+    return dt, stats, kt
+
+
+def cpu_baseline(cfg, kappa, matvecs_per_solve, p_cycle):
+    """FP64 oracle on the host, bounded sample: three applications of the
+    even/odd operator and one CGS2 pass against p/2 basis vectors on the
+    same lattice; the per-solve cost is scaled by the matvec count the GPU
+    FP64 solver needed per solve."""
+    from synth import random_su3_links
+    from oracle import wilson as W
+    from oracle import krylov as K
+    from oracle.noise import z4_noise
+    dims = cfg["dims"]
+    U = random_su3_links(dims, cfg["eps"], cfg["link_seed"])
+    eta = z4_noise(cfg["noise_seed"], dims, 0, 1)[0]
+    src = W.eo_source(U, kappa, eta, dims)
+    t0 = time.perf_counter()
+    v = src
+    for _ in range(3):
+        v = W.apply_Mhat(U, kappa, v, dims)
+    t_mv = (time.perf_counter() - t0) / 3
+    j = max(1, p_cycle // 2)
+    n = src.size
+    rng = np.random.default_rng(0)
+    Vb = np.linalg.qr(rng.standard_normal((n, j)) + 0j)[0]
+    w = v.ravel()
+    t0 = time.perf_counter()
+    K._cgs2(Vb, w)
+    t_gs = time.perf_counter() - t0
+    per_solve = matvecs_per_solve * (t_mv + t_gs)
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    return {"value": 1.0 / per_solve, "unit": "noise-solves/s", "cores": threads, "kind": "oracle",
+            "sample": ("oracle FP64 on %s: 3 even/odd operator applications (%.2f s each) + one CGS2 "
+                       "against %d vectors (%.2f s); per solve = %.0f GPU-FP64 matvecs x (operator + "
+                       "CGS2 at j=%d)" % ("x".join(map(str, dims)), t_mv, j, t_gs, matvecs_per_solve, j)),
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--kappa", type=float, default=None)
+    ap.add_argument("--rhs-block", type=int, default=8)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--tol-super", type=float, default=1e-12)
+    ap.add_argument("--eig-tol", type=float, default=1e-5)
+    ap.add_argument("--defl-eig-tol", type=float, default=1e-7)
+    ap.add_argument("--defl-n-eig", type=int, default=30)
+    ap.add_argument("--herm-tol", type=float, default=1e-9)
+    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--max-cycles", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the noise solves shard "
+              "by right-hand side; see the design notes).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1903_06986_amd import Context
+    from synth import random_su3_links
+    cfg, kappa = workload(args.workload, args.kappa)
+    dims = cfg["dims"]
+    U = random_su3_links(dims, cfg["eps"], cfg["link_seed"])
+    print("[bench] workload %s dims %s kappa %.8f" % (args.workload, dims, kappa), file=sys.stderr, flush=True)
+    ctx = Context(dims, U, kappa)
+    path = Path(ctx, cfg, args)
+    path.setup()
+    print("[bench] setup %s" % json.dumps(path.setup_times), file=sys.stderr, flush=True)
+    dt, stats, kt = run_steps(path, "f32", args.steps, args.warmup)
+    n_solves = args.steps * args.rhs_block
+    value = n_solves / dt
+    print("[bench] mixed: %d solves in %.3f s" % (n_solves, dt), file=sys.stderr, flush=True)
+    dt64, stats64, kt64 = run_steps(path, "f64", args.fp64_steps, 0)
+    value64 = args.fp64_steps * args.rhs_block / dt64
+    print("[bench] fp64: %d solves in %.3f s" % (args.fp64_steps * args.rhs_block, dt64), file=sys.stderr,
+          flush=True)
+    # dominant kernel class of the mixed timed region
+    dom = max(kt, key=lambda k: kt[k][0])
+    ms, by, nl = kt[dom]
+    achieved = by / (ms * 1e-3) / 1e9
+    bpl = by / max(nl, 1)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(dom, bpl), "bytes_per_launch": bpl, "launches": nl,
+            "avg_launch_us": round(ms * 1e3 / max(nl, 1), 2)}
+    kernels = {k: {"ms": round(v[0], 2), "GBps": round(v[1] / max(v[0], 1e-9) / 1e6, 1), "launches": v[2]}
+               for k, v in kt.items()}
+    mv = float(np.mean([s["matvecs"] for s in stats]))
+    mv64 = float(np.mean([s["matvecs"] for s in stats64]))
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, kappa, mv64, cfg["m"] - cfg["k"])
+    line = {
+        "metric": "deflated noise-solves/s %s, mixed (FP32 inner, FP64 refinement) at 1e-10 true residual"
+                  % "x".join(map(str, dims)),
+        "value": round(value, 4), "unit": "noise-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "%s %s eps=%.2f kappa=%.6f (near-critical), GMRES-DR(%d,%d) + GMRES-Proj, "
+                               "%d Z(4) noise per step, PS%d POLY%d Q=%d"
+                               % (args.workload, "x".join(map(str, dims)), cfg["eps"], kappa, cfg["m"], cfg["k"],
+                                  args.rhs_block, cfg["pert_order"], cfg["poly_degree"], cfg["n_hermitian"]),
+                   "rhs_block": args.rhs_block},
+        "fp64": {"value": round(value64, 4), "unit": "noise-solves/s", "steps": args.fp64_steps,
+                 "matvecs_per_solve": mv64, "reorth_per_solve": float(np.mean([s["reorth"] for s in stats64])),
+                 "max_true_resid": max(s["true_resid"] for s in stats64)},
+        "mixed_over_fp64": round(value / value64, 3),
+        "mixed": {"matvecs_per_solve": mv, "refinements": float(np.mean([s["refinements"] for s in stats])),
+                  "reorth_per_solve": float(np.mean([s["reorth"] for s in stats])),
+                  "max_true_resid": max(s["true_resid"] for s in stats)},
+        "setup": {k: round(v, 3) for k, v in path.setup_times.items()},
+        "end_to_end_200_noise_s": round(path.setup_times["total_s"] + 199.0 / value, 2),
+        "kernels": kernels,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,7 @@ typedef struct {
   int matvecs;       /* applications of the solved operator (any precision) */
   int cycles;        /* restart cycles (GMRES-DR or GMRES(m-k) cycles of GMRES-Proj) */
   int refinements;   /* FP64 residual recomputations (mixed precision) */
+  int reorth;        /* Arnoldi steps whose Gram-Schmidt needed the second pass (DGKS test) */
   double true_resid; /* final |b - A x| / |b| recomputed in FP64 on the full lattice */
 } lqcd_solve_stats;
 
@@ -221,6 +222,31 @@ lqcd_status loop_estimate(lqcd_ctx *ctx, const int *thetas_host, int ntheta, con
                           const void *x, const void *xt, int nrhs,
                           const double *trace_corr_host, double *est_host,
                           double *stderr_host, double *samples_host);
+
+/* Kernel timing (measurement aid).  When enabled, the library brackets
+ * every launch of the classes below with HIP events on the context stream
+ * and accumulates, per class, the summed kernel duration, the number of
+ * launches and the algorithmic bytes those launches must move (each
+ * field, link or basis vector counted once per launch).  Enabling resets
+ * the counters.  Reading synchronises the stream. */
+typedef enum {
+  LQCD_KC_HOP64 = 0,   /* stencil (Wilson hop + epilogue), FP64 */
+  LQCD_KC_HOP32 = 1,   /* stencil, FP32 */
+  LQCD_KC_DOT = 2,     /* Gram-Schmidt block dot products (first stage) */
+  LQCD_KC_AXPY = 3,    /* Gram-Schmidt block updates (with norms) */
+  LQCD_KC_GEMM = 4,    /* deflation projections V^+ X and V C, basis recombination */
+  LQCD_KC_COUNT = 5
+} lqcd_kernel_class;
+lqcd_status lqcd_timer_enable(lqcd_ctx *ctx, int on);
+lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes,
+                            int64_t *launches);
+
+/* Launch-shape tuning.  LQCD_TUNE_HOP_NB64 / LQCD_TUNE_HOP_NB32: the
+ * largest number of right-hand sides (1, 2, 4 or 8) that the stencil maps
+ * onto adjacent lanes to share link loads, per precision (defaults 4 and
+ * 2).  Values are per context; EINVAL for other values. */
+typedef enum { LQCD_TUNE_HOP_NB64 = 0, LQCD_TUNE_HOP_NB32 = 1 } lqcd_tune_param;
+lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 
 /* Thread-local description of the last non-OK status. */
 const char *lqcd_last_error(void);

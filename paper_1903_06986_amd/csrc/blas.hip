@@ -49,58 +49,95 @@ __device__ inline cx<double> ld64(const cx<R> *p) {
 }
 
 // ---------------------------------------------------------- multi_dot
-template <class R, int JG>
+// Wave-level chunks: each wave owns WEPT * 64 consecutive elements, keeps
+// its slice of w in registers and, for every basis vector, reduces its
+// partial dot product across the wave with shuffles only.  No block-level
+// barrier stalls the loads of the next basis vectors.
+template <class R>
+struct MdotShape {
+  static constexpr int EPT = sizeof(R) == 8 ? 8 : 16;  // elements per lane
+  static constexpr int WCH = 64 * EPT;                 // elements per wave chunk
+};
+
+template <class R>
 __global__ void __launch_bounds__(kBlock)
     k_mdot_part(const cx<R> *__restrict__ V, size_t ldv, size_t V_rs, int J,
-                const cx<R> *__restrict__ w, size_t w_rs, size_t n, double *__restrict__ part) {
-  __shared__ double sh[2 * JG][kWaves];
-  const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
+                const cx<R> *__restrict__ w, size_t w_rs, size_t n, double *__restrict__ part,
+                const int *__restrict__ flag) {
+  constexpr int E = MdotShape<R>::EPT, WC = MdotShape<R>::WCH;
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.y;
+  if (flag && flag[r] == 0) return;  // conditional pass not needed for this rhs
+  const size_t nwch = size_t(gridDim.x) * kWaves;
+  const size_t chunk = size_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
   V += r * V_rs;
   w += r * w_rs;
-  const size_t base = size_t(b) * CH + threadIdx.x;
-  cx<double> wv[EPT];
+  const size_t base = chunk * WC + lane;
+  cx<double> wv[E];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    size_t idx = base + size_t(e) * kBlock;
+  for (int e = 0; e < E; ++e) {
+    size_t idx = base + size_t(e) * 64;
     wv[e] = idx < n ? ld64(w + idx) : mk<double>(0, 0);
   }
-  for (int j0 = 0; j0 < J; j0 += JG) {
-    double acc[2 * JG];
+  double *po = part + (size_t(r) * nwch + chunk) * size_t(J) * 2;
+  int j = 0;
+  for (; j + 2 <= J; j += 2) {
+    double a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+    const cx<R> *v0 = V + size_t(j) * ldv, *v1 = v0 + ldv;
 #pragma unroll
-    for (int k = 0; k < 2 * JG; ++k) acc[k] = 0;
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      size_t idx = base + size_t(e) * kBlock;
+    for (int e = 0; e < E; ++e) {
+      size_t idx = base + size_t(e) * 64;
       if (idx < n) {
-#pragma unroll
-        for (int g = 0; g < JG; ++g)
-          if (j0 + g < J) {
-            cx<double> v = ld64(V + size_t(j0 + g) * ldv + idx);
-            cx<double> p = cmulc(v, wv[e]);
-            acc[2 * g] += p.re;
-            acc[2 * g + 1] += p.im;
-          }
+        cx<double> p0 = cmulc(ld64(v0 + idx), wv[e]);
+        cx<double> p1 = cmulc(ld64(v1 + idx), wv[e]);
+        a0 += p0.re;
+        b0 += p0.im;
+        a1 += p1.re;
+        b1 += p1.im;
       }
     }
-    block_sum<2 * JG>(acc, sh);
-    if (threadIdx.x == 0)
+    a0 = wave_sum(a0);
+    b0 = wave_sum(b0);
+    a1 = wave_sum(a1);
+    b1 = wave_sum(b1);
+    if (lane == 0) {
+      po[2 * j] = a0;
+      po[2 * j + 1] = b0;
+      po[2 * j + 2] = a1;
+      po[2 * j + 3] = b1;
+    }
+  }
+  if (j < J) {
+    double a0 = 0, b0 = 0;
+    const cx<R> *v0 = V + size_t(j) * ldv;
 #pragma unroll
-      for (int g = 0; g < JG; ++g)
-        if (j0 + g < J) {
-          size_t o = ((size_t(r) * nblk + b) * J + j0 + g) * 2;
-          part[o] = acc[2 * g];
-          part[o + 1] = acc[2 * g + 1];
-        }
-    __syncthreads();
+    for (int e = 0; e < E; ++e) {
+      size_t idx = base + size_t(e) * 64;
+      if (idx < n) {
+        cx<double> p0 = cmulc(ld64(v0 + idx), wv[e]);
+        a0 += p0.re;
+        b0 += p0.im;
+      }
+    }
+    a0 = wave_sum(a0);
+    b0 = wave_sum(b0);
+    if (lane == 0) {
+      po[2 * j] = a0;
+      po[2 * j + 1] = b0;
+    }
   }
 }
 
-// out[r * out_rs + j] = sum over blocks of part[r][b][j]
+// out[r * out_rs + j] = sum over chunks of part[r][chunk][j]
 __global__ void __launch_bounds__(kBlock)
     k_mdot_final(const double *__restrict__ part, int nblk, int J, cx<double> *__restrict__ out,
-                 size_t out_rs) {
+                 size_t out_rs, const int *__restrict__ flag) {
   __shared__ double sh[2][kWaves];
   const int j = blockIdx.x, r = blockIdx.y;
+  if (flag && flag[r] == 0) {
+    if (threadIdx.x == 0) stc(out + size_t(r) * out_rs + j, mk(0.0, 0.0));
+    return;
+  }
   double acc[2] = {0, 0};
   for (int b = threadIdx.x; b < nblk; b += kBlock) {
     size_t o = ((size_t(r) * nblk + b) * J + j) * 2;
@@ -112,41 +149,60 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // --------------------------------------------------------- multi_axpy
+// w -= sum_j V_j c_j with the basis loop unrolled by four (16 loads in
+// flight per lane); the coefficients sit at wave-uniform addresses and are
+// fetched with scalar loads.
+constexpr int AEPT = 4;
+constexpr int ACH = kBlock * AEPT;
+
 template <class R>
 __global__ void __launch_bounds__(kBlock)
     k_maxpy(const cx<R> *__restrict__ V, size_t ldv, size_t V_rs, int J,
             const cx<double> *__restrict__ coef, size_t coef_rs, cx<R> *__restrict__ w,
-            size_t w_rs, size_t n, double *__restrict__ part) {
-  __shared__ cx<double> sc[kMaxJ];
+            size_t w_rs, size_t n, double *__restrict__ part, const int *__restrict__ flag) {
   __shared__ double sh[1][kWaves];
   const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
+  if (flag && flag[r] == 0) return;
   V += r * V_rs;
   w += r * w_rs;
-  for (int j = threadIdx.x; j < J; j += kBlock) sc[j] = coef[size_t(r) * coef_rs + j];
-  __syncthreads();
-  const size_t base = size_t(b) * CH + threadIdx.x;
-  cx<double> acc[EPT];
+  coef += r * coef_rs;
+  const size_t base = size_t(b) * ACH + threadIdx.x;
+  cx<double> acc[AEPT];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
+  for (int e = 0; e < AEPT; ++e) {
     size_t idx = base + size_t(e) * kBlock;
     acc[e] = idx < n ? ld64(w + idx) : mk<double>(0, 0);
   }
-  for (int j = 0; j < J; ++j) {
-    const cx<double> cj = sc[j];
+  int j = 0;
+  for (; j + 4 <= J; j += 4) {
+    const cx<double> c0 = coef[j], c1 = coef[j + 1], c2 = coef[j + 2], c3 = coef[j + 3];
+    const cx<R> *v = V + size_t(j) * ldv;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
+    for (int e = 0; e < AEPT; ++e) {
       size_t idx = base + size_t(e) * kBlock;
-      if (idx < n) acc[e] = acc[e] - ld64(V + size_t(j) * ldv + idx) * cj;
+      if (idx < n) {
+        cx<double> x0 = ld64(v + idx), x1 = ld64(v + ldv + idx), x2 = ld64(v + 2 * ldv + idx),
+                   x3 = ld64(v + 3 * ldv + idx);
+        acc[e] = acc[e] - (x0 * c0 + x1 * c1) - (x2 * c2 + x3 * c3);
+      }
+    }
+  }
+  for (; j < J; ++j) {
+    const cx<double> c0 = coef[j];
+#pragma unroll
+    for (int e = 0; e < AEPT; ++e) {
+      size_t idx = base + size_t(e) * kBlock;
+      if (idx < n) acc[e] = acc[e] - ld64(V + size_t(j) * ldv + idx) * c0;
     }
   }
   double nrm[1] = {0};
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
+  for (int e = 0; e < AEPT; ++e) {
     size_t idx = base + size_t(e) * kBlock;
     if (idx < n) {
-      stc(w + idx, mk<R>(R(acc[e].re), R(acc[e].im)));
-      cx<R> st = ldc(w + idx);  // norm of the stored (rounded) value
-      nrm[0] += double(st.re) * double(st.re) + double(st.im) * double(st.im);
+      const cx<R> st = mk<R>(R(acc[e].re), R(acc[e].im));
+      stc(w + idx, st);
+      nrm[0] += double(st.re) * double(st.re) + double(st.im) * double(st.im);  // of the stored value
     }
   }
   if (part) {
@@ -176,9 +232,11 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 __global__ void __launch_bounds__(kBlock)
-    k_sum_final(const double *__restrict__ part, int nblk, double *__restrict__ out) {
+    k_sum_final(const double *__restrict__ part, int nblk, double *__restrict__ out,
+                const int *__restrict__ flag) {
   __shared__ double sh[1][kWaves];
   const int r = blockIdx.x;
+  if (flag && flag[r] == 0) return;
   double acc[1] = {0};
   for (int b = threadIdx.x; b < nblk; b += kBlock) acc[0] += part[size_t(r) * nblk + b];
   block_sum<1>(acc, sh);
@@ -287,35 +345,50 @@ inline unsigned grid_elems(size_t n) { return unsigned(std::min<size_t>(nblocks(
 }  // namespace
 
 template <class R>
-void multi_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w,
-               size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs) {
+void multi_dot_impl(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w,
+                    size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, int cls,
+                    double bytes, const int *flag = nullptr) {
   if (J <= 0 || nrhs <= 0) return;
-  const int nblk = int((n + CH - 1) / CH);
+  constexpr size_t BCH = size_t(MdotShape<R>::WCH) * kWaves;  // elements per block
+  const int ngrid = int((n + BCH - 1) / BCH);
+  const int nblk = ngrid * kWaves;  // wave chunks = partial sums per rhs and j
   double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * J * 2 * sizeof(double)));
-  hipLaunchKernelGGL((k_mdot_part<R, 4>), dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
+  Timed tm(c, cls, bytes);
+  hipLaunchKernelGGL((k_mdot_part<R>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const cx<R> *>(V), ldv, V_rs, J, static_cast<const cx<R> *>(w),
-                     w_rs, n, part);
+                     w_rs, n, part, flag);
   LQCD_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_mdot_final, dim3(J, nrhs), dim3(kBlock), 0, c->stream, part, nblk, J,
-                     reinterpret_cast<cx<double> *>(out), out_rs);
+                     reinterpret_cast<cx<double> *>(out), out_rs, flag);
   LQCD_HIP(hipGetLastError());
 }
 
 template <class R>
+void multi_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w,
+               size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag) {
+  // a conditional pass is timed but credited with no bytes (the host does
+  // not know which right-hand sides ran it)
+  multi_dot_impl<R>(c, V, ldv, V_rs, J, w, w_rs, n, nrhs, out, out_rs, LQCD_KC_DOT,
+                    flag ? 0.0 : double(J + 1) * n * nrhs * sizeof(cx<R>), flag);
+}
+
+template <class R>
 void multi_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
-                size_t coef_rs, void *w, size_t w_rs, size_t n, int nrhs, double *norm2_out) {
+                size_t coef_rs, void *w, size_t w_rs, size_t n, int nrhs, double *norm2_out,
+                const int *flag) {
   if (nrhs <= 0) return;
   LQCD_CHECK(J <= kMaxJ, LQCD_EINVAL, "basis of %d vectors exceeds %d", J, kMaxJ);
-  const int nblk = int((n + CH - 1) / CH);
+  const int nblk = int((n + ACH - 1) / ACH);
   double *part = nullptr;
   if (norm2_out) part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * sizeof(double)));
+  Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : double(J + 2) * n * nrhs * sizeof(cx<R>));
   hipLaunchKernelGGL(k_maxpy<R>, dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const cx<R> *>(V), ldv, V_rs, J,
                      reinterpret_cast<const cx<double> *>(coef), coef_rs, static_cast<cx<R> *>(w),
-                     w_rs, n, part);
+                     w_rs, n, part, flag);
   LQCD_HIP(hipGetLastError());
   if (norm2_out) {
-    hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(kBlock), 0, c->stream, part, nblk, norm2_out);
+    hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(kBlock), 0, c->stream, part, nblk, norm2_out, flag);
     LQCD_HIP(hipGetLastError());
   }
 }
@@ -328,7 +401,8 @@ void norm2(lqcd_ctx *c, const void *x, size_t x_rs, size_t n, int nrhs, double *
   hipLaunchKernelGGL(k_norm_part<R>, dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const cx<R> *>(x), x_rs, n, part);
   LQCD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(kBlock), 0, c->stream, part, nblk, norm2_out);
+  hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(kBlock), 0, c->stream, part, nblk, norm2_out,
+                     static_cast<const int *>(nullptr));
   LQCD_HIP(hipGetLastError());
 }
 
@@ -363,6 +437,7 @@ void gemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const c
              size_t ldc, size_t C_rs, void *Y, size_t ldy, size_t Y_rs, int nb, size_t n, int nrhs,
              double alpha) {
   if (nb <= 0 || nrhs <= 0) return;
+  Timed tm(c, LQCD_KC_GEMM, double(J + 2 * nb) * n * nrhs * sizeof(cx<R>));
   hipLaunchKernelGGL(k_gemm_nn<R>, dim3(grid_elems(n), nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const cx<R> *>(V), ldv, V_rs, J,
                      reinterpret_cast<const cx<double> *>(C), ldc, C_rs, static_cast<cx<R> *>(Y),
@@ -374,7 +449,8 @@ template <class R>
 void gemm_tn(lqcd_ctx *c, const void *V, size_t ldv, int J, const void *X, size_t ldx, int nb,
              size_t n, cdouble *C, size_t ldc) {
   // one multi-dot per column of X (the X columns act as a batch)
-  multi_dot<R>(c, V, ldv, 0, J, X, ldx, n, nb, C, ldc);
+  multi_dot_impl<R>(c, V, ldv, 0, J, X, ldx, n, nb, C, ldc, LQCD_KC_GEMM,
+                    double(J + nb) * n * sizeof(cx<R>));
 }
 
 template <class R>
@@ -387,6 +463,7 @@ void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size
   size_t shm = size_t(Jin) * E * sizeof(cx<R>);
   LQCD_CHECK(shm <= 64 * 1024, LQCD_EINVAL, "recombine: basis of %d vectors too large", Jin);
   unsigned nb = unsigned((n + E - 1) / E);
+  Timed tm(c, LQCD_KC_GEMM, double(Jin + Jout) * n * sizeof(cx<R>));
   hipLaunchKernelGGL(k_recombine<R>, dim3(nb), dim3(kBlock), shm, c->stream,
                      static_cast<cx<R> *>(V), ldv, Jin, reinterpret_cast<const cx<double> *>(P),
                      ldp, Jout, n, E);
@@ -395,9 +472,9 @@ void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size
 
 #define INST(R)                                                                                   \
   template void multi_dot<R>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
-                             size_t, int, cdouble *, size_t);                                     \
+                             size_t, int, cdouble *, size_t, const int *);                        \
   template void multi_axpy<R>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,     \
-                              size_t, void *, size_t, size_t, int, double *);                     \
+                              size_t, void *, size_t, size_t, int, double *, const int *);        \
   template void norm2<R>(lqcd_ctx *, const void *, size_t, size_t, int, double *);                \
   template void axpby<R>(lqcd_ctx *, const cdouble *, const void *, size_t, const cdouble *,      \
                          void *, size_t, size_t, int, bool);                                      \

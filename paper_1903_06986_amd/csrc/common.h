@@ -97,6 +97,20 @@ struct Geom {
 constexpr int kMaxOrder = 7;
 constexpr int kNumTheta = 5;
 
+// Optional per-kernel-class timing with HIP events on the context stream
+// (classes as in lqcd.h: LQCD_KC_*).  Each timed launch records a start
+// and a stop event; pairs are harvested when the pool fills and on read.
+struct KTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;      // 2 per slot
+  std::vector<int> cls;
+  std::vector<double> bytes;
+  int used = 0;
+  double ms[LQCD_KC_COUNT] = {};
+  double by[LQCD_KC_COUNT] = {};
+  long long cnt[LQCD_KC_COUNT] = {};
+};
+
 }  // namespace lqcd
 
 // The opaque context of the C ABI.
@@ -118,6 +132,9 @@ struct lqcd_ctx {
   lqcd::DevBuf red_out;  // reduction results (device)
   lqcd::DevBuf sw[16];   // solver fields
   lqcd::DevBuf small[2]; // solver small matrices
+  lqcd::KTimer timer;
+  int hop_nb[2] = {4, 2};  // largest lane-grouped right-hand-side count: FP64, FP32
+  ~lqcd_ctx();
 };
 
 namespace lqcd {
@@ -153,6 +170,16 @@ void apply_full(lqcd_ctx *c, lqcd_op op, const void *in, void *out, int nrhs,
 template <class R>
 void apply_schur(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs,
                  size_t stride_in, size_t stride_out, size_t stride_tmp);
+
+// context.cpp: event timing of one launch (no-op unless the timer is on)
+int timer_start(lqcd_ctx *c, int cls, double bytes);
+void timer_stop(lqcd_ctx *c, int slot);
+struct Timed {
+  lqcd_ctx *c;
+  int slot;
+  Timed(lqcd_ctx *cc, int cls, double bytes) : c(cc), slot(timer_start(cc, cls, bytes)) {}
+  ~Timed() { timer_stop(c, slot); }
+};
 
 // fields.hip -----------------------------------------------------------
 template <class R>

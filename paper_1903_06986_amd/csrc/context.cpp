@@ -91,6 +91,90 @@ extern "C" lqcd_status lqcd_set_stream(lqcd_ctx *c, void *hip_stream) {
   });
 }
 
+namespace lqcd {
+
+namespace {
+constexpr int kTimerSlots = 4096;
+
+void harvest(lqcd_ctx *c) {
+  KTimer &T = c->timer;
+  if (T.used == 0) return;
+  LQCD_HIP(hipEventSynchronize(T.ev[2 * (T.used - 1) + 1]));
+  for (int i = 0; i < T.used; ++i) {
+    float ms = 0;
+    LQCD_HIP(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
+    T.ms[T.cls[i]] += ms;
+    T.by[T.cls[i]] += T.bytes[i];
+    T.cnt[T.cls[i]] += 1;
+  }
+  T.used = 0;
+}
+}  // namespace
+
+int timer_start(lqcd_ctx *c, int cls, double bytes) {
+  KTimer &T = c->timer;
+  if (!T.on) return -1;
+  if (T.ev.empty()) {
+    T.ev.resize(2 * kTimerSlots);
+    for (auto &e : T.ev) LQCD_HIP(hipEventCreate(&e));
+    T.cls.resize(kTimerSlots);
+    T.bytes.resize(kTimerSlots);
+  }
+  if (T.used == kTimerSlots) harvest(c);
+  int s = T.used++;
+  T.cls[s] = cls;
+  T.bytes[s] = bytes;
+  LQCD_HIP(hipEventRecord(T.ev[2 * s], c->stream));
+  return s;
+}
+
+void timer_stop(lqcd_ctx *c, int slot) {
+  if (slot < 0) return;
+  (void)hipEventRecord(c->timer.ev[2 * slot + 1], c->stream);
+}
+
+}  // namespace lqcd
+
+lqcd_ctx::~lqcd_ctx() {
+  for (auto &e : timer.ev) (void)hipEventDestroy(e);
+}
+
+extern "C" lqcd_status lqcd_timer_enable(lqcd_ctx *c, int on) {
+  return guarded([&] {
+    LQCD_CHECK(c, LQCD_EINVAL, "lqcd_timer_enable: null context");
+    LQCD_HIP(hipStreamSynchronize(c->stream));
+    c->timer.used = 0;
+    for (int k = 0; k < LQCD_KC_COUNT; ++k) {
+      c->timer.ms[k] = 0;
+      c->timer.by[k] = 0;
+      c->timer.cnt[k] = 0;
+    }
+    c->timer.on = on != 0;
+  });
+}
+
+extern "C" lqcd_status lqcd_timer_read(lqcd_ctx *c, int k, double *ms, double *bytes,
+                                       int64_t *launches) {
+  return guarded([&] {
+    LQCD_CHECK(c && k >= 0 && k < LQCD_KC_COUNT, LQCD_EINVAL, "lqcd_timer_read: bad argument");
+    harvest(c);
+    if (ms) *ms = c->timer.ms[k];
+    if (bytes) *bytes = c->timer.by[k];
+    if (launches) *launches = c->timer.cnt[k];
+  });
+}
+
+extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int value) {
+  return guarded([&] {
+    LQCD_CHECK(c, LQCD_EINVAL, "lqcd_tune_set: null context");
+    LQCD_CHECK(param == LQCD_TUNE_HOP_NB64 || param == LQCD_TUNE_HOP_NB32, LQCD_EINVAL,
+               "lqcd_tune_set: unknown parameter %d", int(param));
+    LQCD_CHECK(value == 1 || value == 2 || value == 4 || value == 8, LQCD_EINVAL,
+               "lqcd_tune_set: right-hand-side group must be 1, 2, 4 or 8");
+    c->hop_nb[param == LQCD_TUNE_HOP_NB64 ? 0 : 1] = value;
+  });
+}
+
 extern "C" lqcd_status lqcd_destroy(lqcd_ctx *c) {
   return guarded([&] {
     if (!c) return;

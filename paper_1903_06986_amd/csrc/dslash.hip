@@ -31,7 +31,7 @@ struct Half {
 // U h (forward) and U^+ h (backward) on each of the two spins of a half
 // spinor; u points at entry 0 of the link, entries are Vh apart.
 template <class R>
-__device__ inline void link_mul(const cx<R> * u, size_t Vh, const Half<R> &in,
+__device__ inline void link_mul(const cx<R> *u, size_t Vh, const Half<R> &in,
                                 Half<R> &out) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -42,7 +42,7 @@ __device__ inline void link_mul(const cx<R> * u, size_t Vh, const Half<R> &in,
   }
 }
 template <class R>
-__device__ inline void link_dag_mul(const cx<R> * u, size_t Vh, const Half<R> &in,
+__device__ inline void link_dag_mul(const cx<R> *u, size_t Vh, const Half<R> &in,
                                     Half<R> &out) {
 #pragma unroll
   for (int s = 0; s < 2; ++s)
@@ -65,7 +65,7 @@ __device__ inline void link_dag_mul(const cx<R> * u, size_t Vh, const Half<R> &i
 // Project psi (12 components at stride Vh from p) for direction MU and sign
 // (FWD: 1 - g_mu, else 1 + g_mu).  G5 applies g5 = diag(1,1,-1,-1) first.
 template <class R, int MU, bool FWD, bool G5>
-__device__ inline void project(const cx<R> * p, size_t Vh, Half<R> &o) {
+__device__ inline void project(const cx<R> *p, size_t Vh, Half<R> &o) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     cx<R> u0 = ldc(p + (0 * 3 + c) * Vh), u1 = ldc(p + (1 * 3 + c) * Vh);
@@ -132,8 +132,8 @@ __device__ inline void fence(cx<R> acc[4][3]) {
 }
 
 template <class R, int MU, bool G5IN>
-__device__ inline void hop_dir(cx<R> acc[4][3], const cx<R> * U,
-                               const cx<R> * in, int p, int i, int nf, int nb,
+__device__ inline void hop_dir(cx<R> acc[4][3], const cx<R> *U,
+                               const cx<R> *in, int p, int i, int nf, int nb,
                                size_t Vh) {
   Half<R> h, g;
   // forward: (1 - g_mu) U_mu(x) psi(x + mu); the link lives at x (parity p)
@@ -148,16 +148,30 @@ __device__ inline void hop_dir(cx<R> acc[4][3], const cx<R> * U,
   fence(acc);
 }
 
-template <class R, bool G5IN, bool G5OUT, bool SELF>
+// Thread mapping: the NB right-hand sides of a group are the fastest lane
+// index, so the NB lanes that share a site issue the same link addresses
+// and one wave load fetches each link once for all NB of them (links are
+// 2/3 of a single right-hand side's bytes).  Spinor accesses stay in
+// contiguous runs of 64/NB sites per right-hand side.
+template <class R, bool G5IN, bool G5OUT, bool SELF, int NB>
 // 3 waves per SIMD caps FP64 at 128 VGPRs (4 waves resident, no spills).
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8)))
-    k_hop(Geom g, int p, const cx<R> * U, const cx<R> * in,
-          const cx<R> * self, cx<R> *out, cx<R> alpha, R beta,
-          size_t in_stride, size_t self_stride, size_t out_stride) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.Vh) return;
+    k_hop(Geom g, int p, const cx<R> *U, const cx<R> *in,
+          const cx<R> *self, cx<R> *out, cx<R> alpha, R beta,
+          size_t in_stride, size_t self_stride, size_t out_stride, int nrhs, int xq, int ngr) {
+  // XCD-aware block order: workgroups are dispatched round-robin over the
+  // 8 XCDs, so hardware block h runs on XCD h % 8.  Logical block
+  // (h % 8) * xq + h / 8 gives every XCD one contiguous range; within it the
+  // right-hand-side group varies fastest, so all groups of a site block run
+  // back to back on one XCD (sharing its links in L2) and consecutive site
+  // blocks, whose neighbours overlap, follow each other.
+  const int L = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
+  const int bx = L / ngr, grp = L % ngr;
+  const int i = bx * (kBlock / NB) + threadIdx.x / NB;
+  const int rr = grp * NB + threadIdx.x % NB;
+  if (i >= g.Vh || rr >= nrhs) return;
   const size_t Vh = size_t(g.Vh);
-  const size_t rhs = blockIdx.y;
+  const size_t rhs = rr;
   in += rhs * in_stride;
   out += rhs * out_stride;
   const int Lxh = g.Lxh, Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
@@ -215,16 +229,34 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
     }
 }
 
+template <class R, bool A, bool B, bool C, int NB>
+void launch_hop_nb(lqcd_ctx *c, int p, const cx<R> *U, const void *in, const void *self, void *out,
+                   cdouble alpha, double beta, int nrhs, size_t si, size_t ss, size_t so) {
+  const Geom &g = c->g;
+  const int nbx = int(nblocks(g.Vh, kBlock / NB));
+  const int ngr = (nrhs + NB - 1) / NB;
+  const int xq = (nbx * ngr + 7) / 8;  // logical blocks per XCD (the grid is padded to 8 * xq)
+  dim3 grid(8 * xq);
+  hipLaunchKernelGGL((k_hop<R, A, B, C, NB>), grid, dim3(kBlock), 0, c->stream, g, p, U,
+                     static_cast<const cx<R> *>(in), static_cast<const cx<R> *>(self),
+                     static_cast<cx<R> *>(out), mk<R>(R(alpha.real()), R(alpha.imag())), R(beta),
+                     si, ss, so, nrhs, xq, ngr);
+}
+
 template <class R, bool A, bool B, bool C>
 void launch_hop(lqcd_ctx *c, int p, const void *in, const void *self, void *out, cdouble alpha,
                 double beta, int nrhs, size_t si, size_t ss, size_t so) {
   const Geom &g = c->g;
   const cx<R> *U = static_cast<const cx<R> *>(std::is_same<R, double>::value ? c->U64.ptr : c->U32.ptr);
-  dim3 grid(nblocks(g.Vh), nrhs);
-  hipLaunchKernelGGL((k_hop<R, A, B, C>), grid, dim3(kBlock), 0, c->stream, g, p, U,
-                     static_cast<const cx<R> *>(in), static_cast<const cx<R> *>(self),
-                     static_cast<cx<R> *>(out), mk<R>(R(alpha.real()), R(alpha.imag())), R(beta),
-                     si, ss, so);
+  // algorithmic bytes: all 8 Vh links once, input and output half fields
+  // (and the self term) once per right-hand side
+  const double bytes = double(g.Vh) * sizeof(cx<R>) * (72.0 + nrhs * (24.0 + (C ? 12.0 : 0.0)));
+  Timed tm(c, std::is_same<R, double>::value ? LQCD_KC_HOP64 : LQCD_KC_HOP32, bytes);
+  const int nbmax = c->hop_nb[std::is_same<R, double>::value ? 0 : 1];
+  if (nrhs >= 8 && nbmax >= 8) launch_hop_nb<R, A, B, C, 8>(c, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else if (nrhs >= 4 && nbmax >= 4) launch_hop_nb<R, A, B, C, 4>(c, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else if (nrhs >= 2 && nbmax >= 2) launch_hop_nb<R, A, B, C, 2>(c, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else launch_hop_nb<R, A, B, C, 1>(c, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   LQCD_HIP(hipGetLastError());
 }
 

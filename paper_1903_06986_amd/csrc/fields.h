@@ -21,17 +21,21 @@ struct Batch {
   size_t rs;  // distance between the vectors of consecutive right-hand sides
 };
 
-// out[r * out_rs + j] = sum_i conj(V_r[j][i]) w_r[i], j < J   (device cdouble)
+// out[r * out_rs + j] = sum_i conj(V_r[j][i]) w_r[i], j < J   (device cdouble).
+// With a device flag array, right-hand sides whose flag is 0 are skipped
+// (their output is set to zero).
 template <class R>
 void multi_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w,
-               size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs);
+               size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs,
+               const int *flag = nullptr);
 
 // w_r[i] -= sum_j V_r[j][i] coef[r * coef_rs + j]; if norm2_out is not null,
-// norm2_out[r] = |w_r|^2 after the update (device doubles).
+// norm2_out[r] = |w_r|^2 after the update (device doubles).  With a device
+// flag array, right-hand sides whose flag is 0 are left untouched.
 template <class R>
 void multi_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J,
                 const cdouble *coef, size_t coef_rs, void *w, size_t w_rs, size_t n, int nrhs,
-                double *norm2_out);
+                double *norm2_out, const int *flag = nullptr);
 
 // norm2_out[r] = |x_r|^2
 template <class R>

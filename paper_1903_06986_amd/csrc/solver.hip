@@ -37,17 +37,46 @@ namespace lqcd {
 namespace {
 
 // ------------------------------------------------------------- kernels
+// Reorthogonalisation test after the first Gram-Schmidt pass (Daniel,
+// Gragg, Kaufman and Stewart): with |w|^2 = |w'|^2 + |h|^2 (w' orthogonal to
+// the basis), a second pass runs when |w'|^2 < eta2 |w|^2.  eta2 > 1 makes
+// it unconditional.
+__global__ void k_dgks(const cx<double> *__restrict__ h1, size_t hrs, int J,
+                       const double *__restrict__ nrm1, int *__restrict__ flag,
+                       int *__restrict__ reorth_count, double eta2) {
+  const int r = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double hh = 0;
+  for (int i = 0; i < J; ++i) {
+    cx<double> v = h1[r * hrs + i];
+    hh += v.re * v.re + v.im * v.im;
+  }
+  const int need = nrm1[r] < eta2 * (nrm1[r] + hh) ? 1 : 0;
+  flag[r] = need;
+  if (need) reorth_count[r] += 1;
+}
+
+// Column j of Hbar: h1 (+ h2 when the second pass ran); h_{j+1,j} = |w|.
 __global__ void k_finish_col(cx<double> *__restrict__ Hd, size_t Hrs, int ldh, int j,
                              const cx<double> *__restrict__ h1, const cx<double> *__restrict__ h2,
-                             size_t hrs, const double *__restrict__ nrm2, double *__restrict__ inv) {
+                             size_t hrs, const double *__restrict__ nrm1,
+                             const double *__restrict__ nrm2, const int *__restrict__ flag,
+                             double *__restrict__ inv) {
   const int r = blockIdx.x;
+  const bool two = flag[r] != 0;
   cx<double> *col = Hd + r * Hrs + size_t(j) * ldh;
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h1[r * hrs + i] + h2[r * hrs + i];
+  for (int i = threadIdx.x; i <= j; i += blockDim.x)
+    col[i] = two ? h1[r * hrs + i] + h2[r * hrs + i] : h1[r * hrs + i];
   if (threadIdx.x == 0) {
-    double nr = sqrt(nrm2[r]);
+    double nr = sqrt(two ? nrm2[r] : nrm1[r]);
     col[j + 1] = mk(nr, 0.0);
     inv[r] = (nr > 0 && isfinite(nr)) ? 1.0 / nr : 0.0;
   }
+}
+
+__global__ void k_izero(int *__restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 template <class R>
@@ -107,13 +136,14 @@ struct Small {
   DevBuf &buf;
   explicit Small(DevBuf &b) : buf(b) {}
   cdouble *Hd, *h1, *h2, *vec, *C, *E;
-  double *nrm2, *inv;
+  double *nrm2, *inv, *nrm1;
+  int *flag, *reorth;
   size_t Hrs;
   void setup(int m, int nb, int kmax) {
     Hrs = size_t(m + 1) * m;
     size_t nc = Hrs * nb + 2 * size_t(m + 1) * nb + size_t(m + 1) * nb + 2 * size_t(kmax + 1) * nb +
                 size_t(m + 1) * (kmax + 1);
-    size_t bytes = nc * sizeof(cdouble) + 2 * size_t(nb) * sizeof(double) + 256;
+    size_t bytes = nc * sizeof(cdouble) + 3 * size_t(nb) * sizeof(double) + 2 * size_t(nb) * sizeof(int) + 256;
     char *p = static_cast<char *>(buf.ensure(bytes));
     Hd = reinterpret_cast<cdouble *>(p);
     h1 = Hd + Hrs * nb;
@@ -123,6 +153,9 @@ struct Small {
     E = C + size_t(kmax + 1) * nb;
     nrm2 = reinterpret_cast<double *>(E + size_t(kmax + 1) * nb);
     inv = nrm2 + nb;
+    nrm1 = inv + nb;
+    flag = reinterpret_cast<int *>(nrm1 + nb);
+    reorth = flag + nb;
   }
 };
 
@@ -138,24 +171,54 @@ void d2h(lqcd_ctx *c, void *dst, const void *src, size_t bytes) {
 // Arnoldi steps j0 .. m-1 on nb bases (vectors n apart, bases Wrs apart):
 // w = A v_j; two classical Gram-Schmidt passes; h_{j+1,j} = |w|;
 // v_{j+1} = w / |w|.  Column j of each Hbar goes to the device matrix.
+// Second-pass thresholds: always in GMRES-DR (its harmonic Ritz vectors
+// become the deflation space), and in the GMRES(m-k) cycles of GMRES-Proj
+// only when the first pass cancelled more than one digit (|w'| < 0.1 |w|);
+// there A v_j is mostly its component along v_j, which one pass removes
+// accurately.
+constexpr double kReorthAlways = 2.0;
+constexpr double kReorthCycle = 0.01;
+
+// Inner (FP32) solves of the refinement: at most this many GMRES(m-k)
+// cycles per refinement step, and stop when a cycle reduces the residual
+// by less than 10%.
+constexpr int kInnerCycleCap = 20;
+constexpr double kInnerStall = 0.9;
+constexpr int kMaxRefinements = 60;
+
 template <class R>
 void arnoldi(lqcd_ctx *c, const Op<R> &A, void *W, size_t n, size_t Wrs, int j0, int m, int nb,
-             Small &s) {
+             Small &s, double eta2) {
   cx<R> *Wb = static_cast<cx<R> *>(W);
   for (int j = j0; j < m; ++j) {
     cx<R> *wj = Wb + size_t(j) * n, *wn = Wb + size_t(j + 1) * n;
     A.apply(wj, Wrs, wn, Wrs, nb);
+    // classical Gram-Schmidt, second pass only where the DGKS test asks for it
     multi_dot<R>(c, Wb, n, Wrs, j + 1, wn, Wrs, n, nb, s.h1, m + 1);
-    multi_axpy<R>(c, Wb, n, Wrs, j + 1, s.h1, m + 1, wn, Wrs, n, nb, nullptr);
-    multi_dot<R>(c, Wb, n, Wrs, j + 1, wn, Wrs, n, nb, s.h2, m + 1);
-    multi_axpy<R>(c, Wb, n, Wrs, j + 1, s.h2, m + 1, wn, Wrs, n, nb, s.nrm2);
+    multi_axpy<R>(c, Wb, n, Wrs, j + 1, s.h1, m + 1, wn, Wrs, n, nb, s.nrm1);
+    hipLaunchKernelGGL(k_dgks, dim3(nb), dim3(64), 0, c->stream,
+                       reinterpret_cast<const cx<double> *>(s.h1), size_t(m + 1), j + 1, s.nrm1,
+                       s.flag, s.reorth, eta2);
+    LQCD_HIP(hipGetLastError());
+    multi_dot<R>(c, Wb, n, Wrs, j + 1, wn, Wrs, n, nb, s.h2, m + 1, s.flag);
+    multi_axpy<R>(c, Wb, n, Wrs, j + 1, s.h2, m + 1, wn, Wrs, n, nb, s.nrm2, s.flag);
     hipLaunchKernelGGL(k_finish_col, dim3(nb), dim3(64), 0, c->stream,
                        reinterpret_cast<cx<double> *>(s.Hd), s.Hrs, m + 1, j,
                        reinterpret_cast<cx<double> *>(s.h1), reinterpret_cast<cx<double> *>(s.h2),
-                       size_t(m + 1), s.nrm2, s.inv);
+                       size_t(m + 1), s.nrm1, s.nrm2, s.flag, s.inv);
     LQCD_HIP(hipGetLastError());
     scale_dev<R>(c, wn, Wrs, s.inv, wn, Wrs, n, nb);
   }
+}
+
+// Add the per-slot second-pass counts to the host counters and reset them.
+void harvest_reorth(lqcd_ctx *c, Small &s, int nb, const std::vector<int> &slot_to_rhs,
+                    std::vector<int> &reorth) {
+  std::vector<int> h(nb);
+  d2h(c, h.data(), s.reorth, nb * sizeof(int));
+  for (int r = 0; r < nb; ++r) reorth[slot_to_rhs[r]] += h[r];
+  hipLaunchKernelGGL(k_izero, dim3(1), dim3(256), 0, c->stream, s.reorth, nb);
+  LQCD_HIP(hipGetLastError());
 }
 
 bool finite_mat(const la::Mat &H) {
@@ -233,6 +296,8 @@ void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lq
   cx<double> *V = static_cast<cx<double> *>(d->V.ensure(size_t(m + 1) * n * sizeof(cx<double>)));
   Small s(c->small[0]);
   s.setup(m, 1, m);
+  hipLaunchKernelGGL(k_izero, dim3(1), dim3(256), 0, c->stream, s.reorth, 1);
+  std::vector<int> reorth1(1, 0);
   double *nrm_host = nullptr;
   double b2 = 0;
   norm2<double>(c, S, 0, n, 1, s.nrm2);
@@ -253,8 +318,10 @@ void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lq
   std::vector<cdouble> Hcols;
   int nev = p.n_eig > 0 ? std::min(p.n_eig, k) : k;
   for (;;) {
-    arnoldi<double>(c, A, V, n, 0, j0, m, 1, s);
+    arnoldi<double>(c, A, V, n, 0, j0, m, 1, s, kReorthAlways);
     st.matvecs += m - j0;
+    harvest_reorth(c, s, 1, std::vector<int>{0}, reorth1);
+    st.reorth = reorth1[0];
     Hcols.resize(size_t(m + 1) * m);
     d2h(c, Hcols.data(), s.Hd, Hcols.size() * sizeof(cdouble));
     // column j of the device matrix holds rows 0..j+1 only (the rest is stale)
@@ -309,15 +376,21 @@ void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lq
 // precision R, from X = 0, until |S - A X| <= tol * ref[r] or max_cycles.
 // Vdef: V_{k+1} of precision R.  Works in place on X; S is not modified
 // (its slots may be permuted internally and are restored on return).
+// An inner solve of iterative refinement (cycle_cap > 0) also stops after
+// cycle_cap cycles of this call, or when a cycle leaves the residual above
+// `stall` times the previous one: it only has to shrink the residual.
 template <class R>
 void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *d, int p, void *S,
                 void *X, void *Rr, void *W, int nb, std::vector<double> ref, double tol,
                 int max_cycles, std::vector<int> &matvecs, std::vector<int> &cycles,
-                std::vector<double> &resid) {
+                std::vector<double> &resid, std::vector<int> &reorth, int cycle_cap = 0,
+                double stall = 0.0) {
   const size_t n = A.n;
   const int k = d->k;
   Small s(c->small[0]);
   s.setup(p, nb, k);
+  hipLaunchKernelGGL(k_izero, dim3(1), dim3(256), 0, c->stream, s.reorth, nb);
+  LQCD_HIP(hipGetLastError());
   const size_t vb = n * sizeof(cx<R>);
   cx<R> *Sb = static_cast<cx<R> *>(S), *Xb = static_cast<cx<R> *>(X), *Rb = static_cast<cx<R> *>(Rr);
   std::vector<int> slot_of(nb), perm(nb);  // perm[slot] = original rhs
@@ -326,7 +399,8 @@ void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *
   fill_zero(c, X, vb * nb);
   copy_dev(c, Rr, S, vb * nb);  // r = S - A 0
   int na = nb;
-  std::vector<double> rn(nb);
+  std::vector<double> rn(nb), prev(nb, -1.0);
+  std::vector<int> here(nb, 0);  // cycles of this call, per slot
   auto swap_slots = [&](int a, int b) {
     swap_vec<R>(c, Sb + a * n, Sb + b * n, n);
     swap_vec<R>(c, Xb + a * n, Xb + b * n, n);
@@ -334,6 +408,8 @@ void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *
     std::swap(perm[a], perm[b]);
     std::swap(ref[a], ref[b]);
     std::swap(rn[a], rn[b]);
+    std::swap(prev[a], prev[b]);
+    std::swap(here[a], here[b]);
     swaps.emplace_back(a, b);
   };
   std::vector<cdouble> Ch, Dh, Eh, Hh;
@@ -348,7 +424,9 @@ void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *
     }
     for (int r = 0; r < na;) {
       // ref <= 0 marks a right-hand side the caller does not want solved
-      if (ref[r] <= 0 || rn[r] <= tol * ref[r] || cycles[perm[r]] >= max_cycles) {
+      const bool capped = cycle_cap > 0 && here[r] >= cycle_cap;
+      const bool stalled = stall > 0 && prev[r] > 0 && rn[r] > stall * prev[r];
+      if (ref[r] <= 0 || rn[r] <= tol * ref[r] || cycles[perm[r]] >= max_cycles || capped || stalled) {
         if (r != na - 1) swap_slots(r, na - 1);
         --na;
       } else {
@@ -356,6 +434,10 @@ void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *
       }
     }
     if (na == 0) break;
+    for (int r = 0; r < na; ++r) {
+      prev[r] = rn[r];
+      here[r] += 1;
+    }
     // projection over the deflation space: c = V^H r, d = argmin |c - Hbar d|
     gemm_tn<R>(c, Vdef, n, k + 1, Rb, n, na, n, s.C, k + 1);
     Ch.resize(size_t(k + 1) * na);
@@ -384,7 +466,8 @@ void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *
     }
     const size_t Wrs = size_t(p + 1) * n;
     axpby<R>(c, sc.data(), Rb, n, zs.data(), W, Wrs, n, na, true);
-    arnoldi<R>(c, A, W, n, Wrs, 0, p, na, s);
+    arnoldi<R>(c, A, W, n, Wrs, 0, p, na, s, kReorthCycle);
+    harvest_reorth(c, s, na, perm, reorth);
     Hh.resize(s.Hrs * na);
     d2h(c, Hh.data(), s.Hd, Hh.size() * sizeof(cdouble));
     std::vector<cdouble> dall(size_t(p) * na);
@@ -541,7 +624,7 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
     const size_t n = op == LQCD_OP_SCHUR ? half_len(c->g) : full_len(c->g);
     const size_t fl = full_len(c->g);
     if (stats)
-      for (int r = 0; r < nrhs; ++r) stats[r] = lqcd_solve_stats{0, 0, 0, 0.0};
+      for (int r = 0; r < nrhs; ++r) stats[r] = lqcd_solve_stats{0, 0, 0, 0, 0.0};
     if (nrhs == 0) return;
     Work w(c);
     Op<double> A64{c, op, n, &w.tmp64};
@@ -556,7 +639,7 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
       nd->kappa = c->kappa;
       make_source(c, op, b, 1, w, n);
       void *X = w.X.ensure(n * sizeof(cx<double>));
-      lqcd_solve_stats st{0, 0, 0, 0.0};
+      lqcd_solve_stats st{0, 0, 0, 0, 0.0};
       lqcd_solve_params pd = p;
       pd.tol_super = std::max(0.0, std::min(p.tol_super > 0 ? p.tol_super : p.tol, p.tol));
       gmres_dr(c, A64, w.S.ptr, X, pd, nd.get(), st);
@@ -582,14 +665,14 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
       make_source(c, op, bl, nb, w, n);
       std::vector<double> ref;
       full_norms(c, w, nb, ref);
-      std::vector<int> mv(nb, 0), cy(nb, 0), refn(nb, 0);
+      std::vector<int> mv(nb, 0), cy(nb, 0), refn(nb, 0), ro(nb, 0);
       std::vector<double> res(nb, 0);
       void *X = w.X.ensure(n * nb * sizeof(cx<double>));
       void *Rr = w.R.ensure(n * nb * sizeof(cx<double>));
       if (p.inner == LQCD_F64) {
         void *W = w.W.ensure(size_t(p_cyc + 1) * n * nb * sizeof(cx<double>));
         proj_solve<double>(c, A64, d->V.ptr, d, p_cyc, w.S.ptr, X, Rr, W, nb, ref, p.tol,
-                           p.max_cycles, mv, cy, res);
+                           p.max_cycles, mv, cy, res, ro);
       } else {
         // FP64 refinement around FP32 deflated inner solves
         if (!d->have_v32) {
@@ -607,6 +690,7 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
         Small s(c->small[1]);
         s.setup(1, nb, 1);
         std::vector<double> rn(nb);
+        int outer_it = 0;
         for (;;) {
           norm2<double>(c, Rr, n, n, nb, s.nrm2);
           d2h(c, rn.data(), s.nrm2, nb * sizeof(double));
@@ -620,6 +704,7 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
             maxc = std::max(maxc, cy[r]);
           }
           if (all || maxc >= p.max_cycles) break;
+          if (++outer_it > kMaxRefinements) break;
           // inner solve for the correction of every rhs not yet converged;
           // converged ones get a zero right-hand side (skipped at once).
           convert<double, float>(c, Rr, S32, n * nb);
@@ -628,7 +713,7 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
           std::vector<double> ires(nb);
           const double itol = std::max(p.inner_tol, 1e-6);
           proj_solve<float>(c, A32, d->V32.ptr, d, p_cyc, S32, X32, R32, W32, nb, iref, itol,
-                            p.max_cycles, mv, cy, ires);
+                            p.max_cycles, mv, cy, ires, ro, kInnerCycleCap, kInnerStall);
           hipLaunchKernelGGL(k_acc_widen, dim3(std::min<size_t>(nblocks(n * nb), 8192)), dim3(kBlock),
                              0, c->stream, static_cast<const cx<float> *>(X32), static_cast<cx<double> *>(X),
                              n * nb);
@@ -645,7 +730,7 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
       }
       finish(c, op, X, xl, nb, w, n, tr);
       for (int r = 0; r < nb; ++r) {
-        if (stats) stats[r0 + r] = lqcd_solve_stats{mv[r], cy[r], refn[r], tr[r]};
+        if (stats) stats[r0 + r] = lqcd_solve_stats{mv[r], cy[r], refn[r], ro[r], tr[r]};
         if (res[r] > p.tol) nonconv = true;
       }
     }

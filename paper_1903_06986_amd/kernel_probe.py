@@ -1,0 +1,59 @@
+"""Run single kernels of the path in the benchmark's launch shape, for profilers.
+
+    python -m paper_1903_06986_amd.kernel_probe --kernel hop32 --nrhs 8 --reps 20
+
+kernels: hop32 / hop64 (both parities of the stencil, internal even/odd
+layout), schur32 (the even/odd operator in FP32), copy (a plain device copy
+of a 256 MiB buffer, the reference for scaling memory counters).  The
+lattice is the 24^3 x 32 workload's (links exp(i 0.2 H), seed 1003).
+Prints the per-launch algorithmic bytes the library's timer assigns.
+"""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kernel", default="hop32", choices=["hop32", "hop64", "schur32", "copy"])
+    ap.add_argument("--nrhs", type=int, default=8)
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--dims", default="24x24x24x32")
+    a = ap.parse_args()
+    import torch
+    if a.kernel == "copy":
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(a.reps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copy: %d launches of %d bytes read + %d written" % (a.reps, src.numel(), src.numel()))
+        return
+    from paper_1903_06986_amd import Context
+    from synth import random_su3_links
+    dims = tuple(int(x) for x in a.dims.split("x"))
+    U = random_su3_links(dims, 0.2, 1003)
+    ctx = Context(dims, U, 0.13)
+    Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    prec = "f64" if a.kernel == "hop64" else "f32"
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    op = "schur" if a.kernel == "schur32" else "hop"
+    shape = (a.nrhs, 12, Vh) if op == "schur" else (a.nrhs, 2, 12, Vh)
+    x = torch.randn(shape, dtype=dt, device="cuda")
+    y = torch.empty_like(x)
+    ctx.timer(True)
+    for _ in range(a.reps):
+        ctx.wilson_apply(op, x, prec=prec, layout="eo", out=y)
+    kt = ctx.timer_read()
+    k = "hop64" if prec == "f64" else "hop32"
+    ms, by, n = kt[k]
+    print("%s nrhs=%d: %d launches, %.1f us each, %.0f algorithmic bytes per launch, %.1f GB/s"
+          % (a.kernel, a.nrhs, n, ms * 1e3 / n, by / n, by / (ms * 1e-3) / 1e9))
+
+
+if __name__ == "__main__":
+    main()

@@ -41,7 +41,7 @@ class SolveParams(ctypes.Structure):
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("matvecs", ctypes.c_int), ("cycles", ctypes.c_int),
-                ("refinements", ctypes.c_int), ("true_resid", ctypes.c_double)]
+                ("refinements", ctypes.c_int), ("reorth", ctypes.c_int), ("true_resid", ctypes.c_double)]
 
 
 _lib = None
@@ -66,6 +66,9 @@ _SIGS = {
     "pert_subtract": [_P, _I, _P, _I, _P, _P, _I, _P],
     "poly_subtract": [_P, _I, _P, _P, _P, _P, _I, _P, _P, _I, _P],
     "loop_estimate": [_P, _P, _I, _P, _P, _P, _I, _P, _P, _P, _P],
+    "lqcd_timer_enable": [_P, _I],
+    "lqcd_timer_read": [_P, _I, _P, _P, _P],
+    "lqcd_tune_set": [_P, _I, _I],
 }
 
 
@@ -182,6 +185,28 @@ class Context:
         except Exception:
             pass
 
+    KERNEL_CLASSES = ("hop64", "hop32", "dot", "axpy", "gemm")
+
+    def tune(self, hop_nb64=None, hop_nb32=None):
+        """Set launch-shape parameters (see lqcd_tune_set)."""
+        if hop_nb64 is not None:
+            _check(lib().lqcd_tune_set(self.handle, 0, int(hop_nb64)))
+        if hop_nb32 is not None:
+            _check(lib().lqcd_tune_set(self.handle, 1, int(hop_nb32)))
+
+    def timer(self, on):
+        """Enable (and reset) or disable per-kernel-class event timing."""
+        _check(lib().lqcd_timer_enable(self.handle, 1 if on else 0))
+
+    def timer_read(self):
+        """{class: (milliseconds, algorithmic bytes, launches)} since enabling."""
+        out = {}
+        for k, name in enumerate(self.KERNEL_CLASSES):
+            ms, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+            _check(lib().lqcd_timer_read(self.handle, k, ctypes.byref(ms), ctypes.byref(by), ctypes.byref(n)))
+            out[name] = (ms.value, by.value, n.value)
+        return out
+
     def set_kappa(self, kappa):
         self.kappa = float(kappa)
         _check(lib().lqcd_set_kappa(self.handle, self.kappa))
@@ -235,7 +260,7 @@ class Context:
                                    ctypes.byref(h), stats)
         newdefl = Deflation(_P(h.value), self) if (defl is None and h.value) else defl
         _check(code)
-        st = [dict(matvecs=s.matvecs, cycles=s.cycles, refinements=s.refinements,
+        st = [dict(matvecs=s.matvecs, cycles=s.cycles, refinements=s.refinements, reorth=s.reorth,
                    true_resid=s.true_resid) for s in stats[:nrhs]]
         return x, newdefl, st
 

@@ -113,7 +113,7 @@ class Path:
         self.next_noise += B
         x, _, st = ctx.gmresdr_solve(eta, op="schur", m=c["m"], k=c["k"], tol=a.tol, inner=inner,
                                      inner_tol=a.inner_tol, rhs_block=B, max_cycles=a.max_cycles,
-                                     defl=self.defl)
+                                     defl=self.defl, proj_m=a.proj_m)
         res = {}
         res["NS"] = ctx.loop_estimate(eta, x, None, None, THETAS)
         xt_ps, _ = ctx.pert_subtract(c["pert_order"], eta, THETAS, want_corr=False)
@@ -200,6 +200,7 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--kappa", type=float, default=None)
     ap.add_argument("--rhs-block", type=int, default=8)
+    ap.add_argument("--proj-m", type=int, default=0, help="GMRES-Proj cycle length (0: m - k)")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--tol-super", type=float, default=1e-12)

@@ -102,6 +102,7 @@ typedef struct {
                         F32 = FP32 stencil and basis inside FP64 iterative refinement */
   double inner_tol;  /* relative residual reduction per refinement step (mixed precision) */
   int rhs_block;     /* right-hand sides solved together by GMRES-Proj (>= 1) */
+  int proj_m;        /* GMRES cycle length of GMRES-Proj (0 = m - k) */
 } lqcd_solve_params;
 
 typedef struct {
@@ -243,8 +244,8 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
 
 /* Launch-shape tuning.  LQCD_TUNE_HOP_NB64 / LQCD_TUNE_HOP_NB32: the
  * largest number of right-hand sides (1, 2, 4 or 8) that the stencil maps
- * onto adjacent lanes to share link loads, per precision (defaults 4 and
- * 2).  Values are per context; EINVAL for other values. */
+ * onto adjacent lanes to share link loads, per precision (defaults 2 and
+ * 1).  Values are per context; EINVAL for other values. */
 typedef enum { LQCD_TUNE_HOP_NB64 = 0, LQCD_TUNE_HOP_NB32 = 1 } lqcd_tune_param;
 lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 

@@ -133,7 +133,7 @@ struct lqcd_ctx {
   lqcd::DevBuf sw[16];   // solver fields
   lqcd::DevBuf small[2]; // solver small matrices
   lqcd::KTimer timer;
-  int hop_nb[2] = {4, 2};  // largest lane-grouped right-hand-side count: FP64, FP32
+  int hop_nb[2] = {2, 1};  // largest lane-grouped right-hand-side count: FP64, FP32
   ~lqcd_ctx();
 };
 

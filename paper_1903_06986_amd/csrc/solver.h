@@ -24,6 +24,11 @@ struct lqcd_defl {
   int Qe = 0;
   std::vector<double> lam, lam_resid;
   lqcd::DevBuf E;                // Q eigenvectors (FP64, n apart)
+  // Caches that depend only on the eigenpairs (reset when they change):
+  // per-mode trace bilinears sum_{x in t} e_q^+ Theta g5 e_q, [q][theta][t],
+  // and 1/xi'_q per polynomial (coefficients -> values).
+  std::vector<lqcd::cdouble> bil;
+  std::vector<std::pair<std::vector<lqcd::cdouble>, std::vector<lqcd::cdouble>>> xi_cache;
 };
 
 namespace lqcd {

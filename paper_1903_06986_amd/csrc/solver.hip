@@ -600,6 +600,8 @@ void defl_eigpairs(lqcd_ctx *c, lqcd_defl *d, int Q) {
   gemm_nn<double>(c, d->V.ptr, d->n, 0, k, Sd.as<cdouble>(), k, 0, E, d->n, 0, Q, d->n, 1, 1.0);
   LQCD_HIP(hipStreamSynchronize(c->stream));
   d->Qe = Q;
+  d->bil.clear();
+  d->xi_cache.clear();
 }
 
 }  // namespace lqcd
@@ -655,7 +657,8 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
         LQCD_CHECK(d->dims[i] == c->g.L[i], LQCD_EINVAL, "gmresdr_solve: deflation space of another lattice");
       LQCD_CHECK(d->kappa == c->kappa, LQCD_EINVAL, "gmresdr_solve: deflation space of another kappa");
     }
-    const int p_cyc = p.m - p.k;
+    LQCD_CHECK(p.proj_m >= 0 && p.proj_m <= 250, LQCD_EINVAL, "gmresdr_solve: proj_m outside 0..250");
+    const int p_cyc = p.proj_m > 0 ? p.proj_m : p.m - p.k;
     const int blk = std::max(1, p.rhs_block);
     bool nonconv = false;
     for (int r0 = start; r0 < nrhs; r0 += blk) {

@@ -484,46 +484,64 @@ extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_de
     LQCD_CHECK(d->kappa == c->kappa, LQCD_EINVAL, "deflate_project: deflation space of another kappa");
     check_thetas(thetas, nth);
     defl_eigpairs(c, d, Q);
-    const size_t fl = full_len(c->g), hl = half_len(c->g);
+    const size_t fl = full_len(c->g);
     const cx<double> *E = d->E.as<cx<double>>();
+    const int Lt = c->g.L[3];
     std::vector<cdouble> w(Q), xi(Q, 0.0);
     for (int q = 0; q < Q; ++q) w[q] = 1.0 / d->lam[q];
     if (mode == LQCD_DEFL_EIGPOLY) {
-      // 1/xi'_q = e'^+ g5 p(kappa P) e'  (Eq. (69) with M'_poly^{-1} = g5 p)
+      // 1/xi'_q = e'^+ g5 p(kappa P) e'  (Eq. (69) with M'_poly^{-1} = g5 p),
+      // computed once per polynomial and kept with the eigenpairs
       std::vector<cdouble> cc(ncoeff);
       for (int j = 0; j < ncoeff; ++j) cc[j] = cdouble(coeffs_host[2 * j], coeffs_host[2 * j + 1]);
-      cx<double> *A = static_cast<cx<double> *>(c->ws[1].ensure(fl * Q * sizeof(cx<double>)));
-      cx<double> *B = static_cast<cx<double> *>(c->ws[2].ensure(fl * Q * sizeof(cx<double>)));
-      cx<double> *Y = horner(c, cc, E, A, B, Q);
-      size_t tot = 2 * 6 * size_t(c->g.Vh) * Q;
-      hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(tot)), dim3(kBlock), 0, c->stream, Y, size_t(c->g.Vh), fl, Q);
-      LQCD_HIP(hipGetLastError());
-      cdouble *Cd = static_cast<cdouble *>(c->ws[5].ensure(size_t(Q) * sizeof(cdouble)));
-      // xi_inv[q] = <E_q, Y_q>: a batched dot with each vector its own basis of one
-      multi_dot<double>(c, E, fl, fl, 1, Y, fl, fl, Q, Cd, 1);
-      d2h(c, xi.data(), Cd, Q * sizeof(cdouble));
+      bool found = false;
+      for (auto &e : d->xi_cache)
+        if (e.first == cc) {
+          xi = e.second;
+          found = true;
+        }
+      if (!found) {
+        cx<double> *A = static_cast<cx<double> *>(c->ws[1].ensure(fl * Q * sizeof(cx<double>)));
+        cx<double> *B = static_cast<cx<double> *>(c->ws[2].ensure(fl * Q * sizeof(cx<double>)));
+        cx<double> *Y = horner(c, cc, E, A, B, Q);
+        size_t tot = 2 * 6 * size_t(c->g.Vh) * Q;
+        hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(tot)), dim3(kBlock), 0, c->stream, Y, size_t(c->g.Vh), fl, Q);
+        LQCD_HIP(hipGetLastError());
+        cdouble *Cd = static_cast<cdouble *>(c->ws[5].ensure(size_t(Q) * sizeof(cdouble)));
+        // xi_inv[q] = <E_q, Y_q>: a batched dot with each vector its own basis of one
+        multi_dot<double>(c, E, fl, fl, 1, Y, fl, fl, Q, Cd, 1);
+        d2h(c, xi.data(), Cd, Q * sizeof(cdouble));
+        d->xi_cache.emplace_back(cc, xi);
+      }
       for (int q = 0; q < Q; ++q) w[q] -= xi[q];
-      (void)hl;
     }
     if (xi_inv_host)
       for (int q = 0; q < Q; ++q) {
         xi_inv_host[2 * q] = xi[q].real();
         xi_inv_host[2 * q + 1] = xi[q].imag();
       }
-    // trace correction: sum_q w_q e_q^+ Theta g5 e_q per timeslice
+    // trace correction: sum_q w_q e_q^+ Theta g5 e_q per timeslice, from the
+    // per-mode bilinears (computed once per set of eigenpairs)
     if (corr && nth > 0) {
-      cdouble *wd = static_cast<cdouble *>(c->ws[6].ensure(size_t(Q) * sizeof(cdouble)));
-      h2d(c, wd, w.data(), Q * sizeof(cdouble));
-      cx<double> *site = static_cast<cx<double> *>(c->ws[7].ensure(size_t(kNumTheta) * c->g.V * sizeof(cdouble)));
-      hipLaunchKernelGGL(k_eig_bilinear, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g, E, fl, Q,
-                         reinterpret_cast<const cx<double> *>(wd), site);
-      LQCD_HIP(hipGetLastError());
-      DevBuf tmp;
-      std::vector<cdouble> ts = timeslice_rows(c, site, kNumTheta, tmp);
-      const int Lt = c->g.L[3];
+      if (d->bil.empty()) {
+        d->bil.assign(size_t(Q) * kNumTheta * Lt, 0.0);
+        cdouble one(1, 0);
+        cdouble *wd = static_cast<cdouble *>(c->ws[6].ensure(sizeof(cdouble)));
+        h2d(c, wd, &one, sizeof(cdouble));
+        cx<double> *site = static_cast<cx<double> *>(c->ws[7].ensure(size_t(kNumTheta) * c->g.V * sizeof(cdouble)));
+        DevBuf tmp;
+        for (int q = 0; q < Q; ++q) {
+          hipLaunchKernelGGL(k_eig_bilinear, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g,
+                             E + size_t(q) * fl, fl, 1, reinterpret_cast<const cx<double> *>(wd), site);
+          LQCD_HIP(hipGetLastError());
+          std::vector<cdouble> ts = timeslice_rows(c, site, kNumTheta, tmp);
+          std::copy(ts.begin(), ts.end(), d->bil.begin() + size_t(q) * kNumTheta * Lt);
+        }
+      }
       for (int a = 0; a < nth; ++a)
         for (int t = 0; t < Lt; ++t) {
-          cdouble v = ts[size_t(thetas[a]) * Lt + t];
+          cdouble v = 0;
+          for (int q = 0; q < Q; ++q) v += w[q] * d->bil[(size_t(q) * kNumTheta + thetas[a]) * Lt + t];
           corr[2 * (a * Lt + t)] += v.real();
           corr[2 * (a * Lt + t) + 1] += v.imag();
         }

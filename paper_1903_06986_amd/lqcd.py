@@ -36,7 +36,7 @@ class SolveParams(ctypes.Structure):
                 ("tol", ctypes.c_double), ("tol_super", ctypes.c_double),
                 ("eig_tol", ctypes.c_double), ("n_eig", ctypes.c_int),
                 ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("rhs_block", ctypes.c_int)]
+                ("rhs_block", ctypes.c_int), ("proj_m", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -248,12 +248,12 @@ class Context:
     # ----------------------------------------------------------- solvers
     def gmresdr_solve(self, b, op="schur", m=20, k=10, tol=1e-10, tol_super=1e-13, eig_tol=0.0,
                       n_eig=0, max_cycles=1000, inner="f64", inner_tol=1e-5, rhs_block=1,
-                      defl=None):
+                      defl=None, proj_m=0):
         import torch
         x = torch.empty_like(b)
         nrhs = b.shape[0]
         p = SolveParams(m, k, max_cycles, tol, tol_super, eig_tol, n_eig, _PREC[inner], inner_tol,
-                        rhs_block)
+                        rhs_block, proj_m)
         stats = (SolveStats * max(nrhs, 1))()
         h = _P(defl.handle.value if defl is not None else None)
         code = lib().gmresdr_solve(self.handle, _OPS[op], ctypes.byref(p), _ptr(b), _ptr(x), nrhs,

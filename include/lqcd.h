@@ -224,6 +224,33 @@ lqcd_status loop_estimate(lqcd_ctx *ctx, const int *thetas_host, int ntheta, con
                           const double *trace_corr_host, double *est_host,
                           double *stderr_host, double *samples_host);
 
+/* Derivatives of the trace estimate (differentiation of Eq. (23) with
+ * M = 1 - kappa P of Sec. 5.1 Eqs. (24)-(25); the adjoint uses the
+ * g5-hermiticity of Sec. 5.4).  For the fixed-noise estimate
+ *   T = (1/N) sum_n eta_n^+ Theta_w M^{-1} eta_n,
+ *   Theta_w = sum_a w[a][t(x)] Theta_{thetas[a]}  (a site-diagonal weighting,
+ *   t(x) the timeslice of x),
+ * computes exactly (up to the solver tolerance)
+ *   dkappa_host = dT/dkappa = (1/N) sum_n y_n^+ P x_n,
+ *   dlinks[x][mu][a] = dT/dw^a for U_mu(x) -> exp(i w^a T^a) U_mu(x),
+ *   T^a = lambda^a / 2 (Gell-Mann), = (kappa/N) sum_n y_n^+ (dP/dw^a) x_n,
+ * with x_n = M^{-1} eta_n and y_n = g5 M^{-1} g5 Theta_w^+ eta_n.
+ * thetas_host: int [ntheta] codes 0..4; weights_host: complex128
+ * [ntheta][Lt] or NULL (all 1: the whole-lattice Tr(Theta M^{-1}) summed
+ * over the codes).  eta: device LEX [nrhs]; x: device LEX [nrhs] solutions
+ * of M x = eta, or NULL to solve for them in the same batched call.
+ * The adjoint (and, if x is NULL, forward) systems are solved by
+ * gmresdr_solve with op LQCD_OP_SCHUR, params, and *defl_inout as there
+ * (NULL: the first right-hand side builds the deflation space and it is
+ * returned).  dkappa_host: host complex128 [1]; dlinks: device complex128
+ * LEX [V][4][8] or NULL (only the kappa derivative); stats: host [nrhs]
+ * statistics of the adjoint solves, or NULL.  Allocates its scratch per
+ * call.  ENOCONV as gmresdr_solve. */
+lqcd_status loop_gradient(lqcd_ctx *ctx, const int *thetas_host, const double *weights_host,
+                          int ntheta, const lqcd_solve_params *params, lqcd_defl **defl_inout,
+                          const void *eta, const void *x, int nrhs, double *dkappa_host,
+                          void *dlinks, lqcd_solve_stats *stats);
+
 /* Kernel timing (measurement aid).  When enabled, the library brackets
  * every launch of the classes below with HIP events on the context stream
  * and accumulates, per class, the summed kernel duration, the number of
@@ -236,7 +263,8 @@ typedef enum {
   LQCD_KC_DOT = 2,     /* Gram-Schmidt block dot products (first stage) */
   LQCD_KC_AXPY = 3,    /* Gram-Schmidt block updates (with norms) */
   LQCD_KC_GEMM = 4,    /* deflation projections V^+ X and V C, basis recombination */
-  LQCD_KC_COUNT = 5
+  LQCD_KC_FORCE = 5,   /* link derivative of the trace (loop_gradient) */
+  LQCD_KC_COUNT = 6
 } lqcd_kernel_class;
 lqcd_status lqcd_timer_enable(lqcd_ctx *ctx, int on);
 lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes,

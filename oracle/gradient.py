@@ -55,17 +55,35 @@ def theta_dense(theta, V):
     return np.kron(np.eye(V), np.kron(T, np.eye(3)))
 
 
+def theta_weighted_dense(thetas, weights, dims):
+    """Site-diagonal Theta_w = sum_a w[a][t(x)] Theta_a (dense), with t(x)
+    the timeslice of site x; weights complex [len(thetas)][Lt]."""
+    V = volume(dims)
+    Vs = V // dims[3]
+    D = np.zeros((12 * V, 12 * V), dtype=np.complex128)
+    for a, th in enumerate(thetas):
+        T = np.kron(_I4 if th == 0 else GAMMA[th - 1], np.eye(3))
+        for x in range(V):
+            D[12 * x:12 * x + 12, 12 * x:12 * x + 12] += weights[a][x // Vs] * T
+    return D
+
+
+def _theta(theta, dims):
+    return theta_dense(theta, volume(dims)) if np.isscalar(theta) else theta
+
+
 def trace_dense(U, kappa, dims, theta):
+    """Tr(Theta M^{-1}); theta an operator code or a dense matrix."""
     V = volume(dims)
     M = np.eye(12 * V) - kappa * dense_P(U, dims)
-    return np.trace(theta_dense(theta, V) @ np.linalg.inv(M))
+    return np.trace(_theta(theta, dims) @ np.linalg.inv(M))
 
 
 def dkappa_dense(U, kappa, dims, theta):
     V = volume(dims)
     P = dense_P(U, dims)
     Minv = np.linalg.inv(np.eye(12 * V) - kappa * P)
-    return np.trace(theta_dense(theta, V) @ Minv @ P @ Minv)
+    return np.trace(_theta(theta, dims) @ Minv @ P @ Minv)
 
 
 def dP_dw(U, dims, site, mu, a):
@@ -88,7 +106,7 @@ def dP_dw(U, dims, site, mu, a):
 def dlink_dense(U, kappa, dims, theta, site, mu, a):
     V = volume(dims)
     Minv = np.linalg.inv(np.eye(12 * V) - kappa * dense_P(U, dims))
-    return kappa * np.trace(theta_dense(theta, V) @ Minv @ dP_dw(U, dims, site, mu, a) @ Minv)
+    return kappa * np.trace(_theta(theta, dims) @ Minv @ dP_dw(U, dims, site, mu, a) @ Minv)
 
 
 def rotate_link(U, site, mu, a, h, dims):
@@ -106,6 +124,16 @@ def adjoint_vectors(U, kappa, dims, theta, eta, solve):
     """y = g5 M^{-1} g5 Theta^dagger eta, with `solve` a callable M^{-1}."""
     src = g5(apply_theta(theta, eta))  # Theta is hermitian
     return g5(solve(src))
+
+
+def adjoint_vectors_weighted(U, kappa, dims, thetas, weights, eta, solve):
+    """y = g5 M^{-1} g5 Theta_w^dagger eta for Theta_w of theta_weighted_dense:
+    Theta_w^dagger eta (x) = sum_a conj(w[a][t(x)]) Theta_a eta(x)."""
+    src = np.zeros_like(eta)
+    for a, th in enumerate(thetas):
+        wt = np.conj(np.asarray(weights[a], dtype=np.complex128))
+        src += wt[None, :, None, None, None, None, None] * apply_theta(th, eta)
+    return g5(solve(g5(src)))
 
 
 def grad_estimate(U, kappa, dims, eta, x, y):

@@ -66,6 +66,8 @@ _SIGS = {
     "pert_subtract": [_P, _I, _P, _I, _P, _P, _I, _P],
     "poly_subtract": [_P, _I, _P, _P, _P, _P, _I, _P, _P, _I, _P],
     "loop_estimate": [_P, _P, _I, _P, _P, _P, _I, _P, _P, _P, _P],
+    "loop_gradient": [_P, _P, _P, _I, ctypes.POINTER(SolveParams), ctypes.POINTER(_P), _P, _P, _I,
+                      _P, _P, ctypes.POINTER(SolveStats)],
     "lqcd_timer_enable": [_P, _I],
     "lqcd_timer_read": [_P, _I, _P, _P, _P],
     "lqcd_tune_set": [_P, _I, _I],
@@ -185,7 +187,7 @@ class Context:
         except Exception:
             pass
 
-    KERNEL_CLASSES = ("hop64", "hop32", "dot", "axpy", "gemm")
+    KERNEL_CLASSES = ("hop64", "hop32", "dot", "axpy", "gemm", "force")
 
     def tune(self, hop_nb64=None, hop_nb32=None):
         """Set launch-shape parameters (see lqcd_tune_set)."""
@@ -317,3 +319,33 @@ class Context:
                                    est.ctypes.data_as(_P), err.ctypes.data_as(_P),
                                    smp.ctypes.data_as(_P) if samples else None))
         return (est, err, smp) if samples else (est, err)
+
+    # ------------------------------------------------------ differentiation
+    def loop_gradient(self, eta, x=None, thetas=(0,), weights=None, defl=None, links=True, m=20, k=10,
+                      tol=1e-10, tol_super=1e-13, eig_tol=0.0, n_eig=0, max_cycles=1000, inner="f64",
+                      inner_tol=1e-5, rhs_block=1, proj_m=0):
+        """Derivatives of T = (1/N) sum_n eta_n^+ Theta_w M^{-1} eta_n (see
+        loop_gradient in lqcd.h).  weights: complex [ntheta][Lt] or None.
+        Returns (dT/dkappa complex, dT/dw complex tensor [Lt,Lz,Ly,Lx,4,8] or
+        None, deflation space, adjoint-solve statistics)."""
+        import torch
+        th, thp, nth = _thetas(thetas)
+        wp = None
+        if weights is not None:
+            w = np.ascontiguousarray(np.broadcast_to(np.asarray(weights, dtype=np.complex128),
+                                                     (nth, self.dims[3])))
+            wp = w.ctypes.data_as(_P)
+        nrhs = eta.shape[0]
+        p = SolveParams(m, k, max_cycles, tol, tol_super, eig_tol, n_eig, _PREC[inner], inner_tol,
+                        rhs_block, proj_m)
+        stats = (SolveStats * max(nrhs, 1))()
+        dk = np.zeros(1, dtype=np.complex128)
+        dl = torch.empty(self.shape[:4] + (4, 8), dtype=torch.complex128, device="cuda") if links else None
+        h = _P(defl.handle.value if defl is not None else None)
+        code = lib().loop_gradient(self.handle, thp, wp, nth, ctypes.byref(p), ctypes.byref(h), _ptr(eta),
+                                   _ptr(x), nrhs, dk.ctypes.data_as(_P), _ptr(dl), stats)
+        newdefl = Deflation(_P(h.value), self) if (defl is None and h.value) else defl
+        _check(code)
+        st = [dict(matvecs=s.matvecs, cycles=s.cycles, refinements=s.refinements, reorth=s.reorth,
+                   true_resid=s.true_resid) for s in stats[:nrhs]]
+        return complex(dk[0]), dl, newdefl, st

@@ -67,3 +67,41 @@ def test_estimator_with_unit_vectors_is_exact(links, theta):
         est = dw[c[3], c[2], c[1], c[0], mu, a] * n
         ref = G.dlink_dense(links, KAPPA, DIMS, theta, site, mu, a)
         assert abs(est - ref) < 1e-10 * max(abs(ref), 1e-6)
+
+
+def test_weighted_theta_reduces_to_plain_theta():
+    V = L.volume(DIMS)
+    ones = np.ones((1, DIMS[3]))
+    for th in range(5):
+        assert np.array_equal(G.theta_weighted_dense((th,), ones, DIMS), G.theta_dense(th, V))
+    # linear in the weights and site-diagonal in time: weight one timeslice only
+    w = np.zeros((2, DIMS[3]), dtype=np.complex128)
+    w[0, 1] = 2 - 1j
+    w[1, 3] = 0.5j
+    D = G.theta_weighted_dense((0, 3), w, DIMS)
+    Vs = V // DIMS[3]
+    blk = slice(12 * Vs, 24 * Vs)
+    assert np.allclose(D[blk, blk], (2 - 1j) * np.eye(12 * Vs))
+    assert np.count_nonzero(D[:12 * Vs]) == 0 and np.count_nonzero(D[24 * Vs:36 * Vs]) == 0
+
+
+def test_weighted_estimator_with_unit_vectors_is_exact(links):
+    rng = np.random.default_rng(5)
+    thetas = (0, 2, 4)
+    w = rng.normal(size=(3, DIMS[3])) + 1j * rng.normal(size=(3, DIMS[3]))
+    V = L.volume(DIMS)
+    n = 12 * V
+    shape = (DIMS[3], DIMS[2], DIMS[1], DIMS[0], 4, 3)
+    eta = np.eye(n, dtype=np.complex128).reshape((n,) + shape)
+    Minv = np.linalg.inv(W.dense_M(links, KAPPA, DIMS))
+    solve = lambda b: (Minv @ b.reshape(b.shape[0], -1).T).T.reshape(b.shape)
+    x = solve(eta)
+    y = G.adjoint_vectors_weighted(links, KAPPA, DIMS, thetas, w, eta, solve)
+    dk, dw = G.grad_estimate(links, KAPPA, DIMS, eta, x, y)
+    Tw = G.theta_weighted_dense(thetas, w, DIMS)
+    ref = G.dkappa_dense(links, KAPPA, DIMS, Tw)
+    assert abs(dk * n - ref) < 1e-10 * abs(ref)
+    for site, mu, a in ((3, 0, 0), (9, 2, 6)):
+        c = [site % 2, (site // 2) % 2, (site // 4) % 2, site // 8]
+        ref = G.dlink_dense(links, KAPPA, DIMS, Tw, site, mu, a)
+        assert abs(dw[c[3], c[2], c[1], c[0], mu, a] * n - ref) < 1e-10 * max(abs(ref), 1e-6)

@@ -99,7 +99,10 @@ typedef struct {
                         Ritz pairs satisfy |A y - theta y| <= eig_tol |theta| (0 = off) */
   int n_eig;         /* see eig_tol (0 = k) */
   lqcd_prec inner;   /* precision of the inner Krylov solver: F64 = plain FP64,
-                        F32 = FP32 stencil and basis inside FP64 iterative refinement */
+                        F32 = FP32 stencil and basis inside FP64 iterative refinement,
+                        F16 / BF16 = as F32, with the GMRES(m-k) basis and the
+                        stencil's input stored in 16 bits with one FP32 scale per
+                        site (arithmetic FP32; op LQCD_OP_SCHUR only) */
   double inner_tol;  /* relative residual reduction per refinement step (mixed precision) */
   int rhs_block;     /* right-hand sides solved together by GMRES-Proj (>= 1) */
   int proj_m;        /* GMRES cycle length of GMRES-Proj (0 = m - k) */
@@ -141,7 +144,10 @@ lqcd_status lqcd_unpack_eo(lqcd_ctx *ctx, lqcd_prec prec, const void *eo, void *
  * in/out are complex128 LEX fields and the stencil runs in precision prec
  * (inputs rounded to prec, outputs widened to FP64).  With LQCD_LAYOUT_EO
  * they are internal-layout fields of precision prec.  in and out must not
- * overlap.  F16/BF16 are not available for this call (EINVAL). */
+ * overlap.  F16 / BF16 (op LQCD_OP_SCHUR with LQCD_LAYOUT_LEX only, else
+ * EINVAL): the even half of the input is rounded to FP32 and stored in 16
+ * bits with one FP32 scale per site (its largest |re| or |im|); the
+ * stencil reads that storage and computes in FP32. */
 lqcd_status wilson_apply(lqcd_ctx *ctx, lqcd_op op, lqcd_prec prec, lqcd_layout layout,
                          const void *in, void *out, int nrhs);
 

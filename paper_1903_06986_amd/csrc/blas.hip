@@ -5,6 +5,7 @@
 #include "common.h"
 #include "cplx.h"
 #include "fields.h"
+#include "half.h"
 
 namespace lqcd {
 
@@ -340,6 +341,214 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+
+// ------------------------------------------------- 16-bit stored bases
+// Basis vectors stored as in half.h (payload words then per-site scales);
+// the vector they act on stays FP32.  Flat element index idx = comp * Vh
+// + site; each lane tracks its site index incrementally.
+template <HKind K>
+__device__ inline cx<double> ldh(const uint32_t *v, size_t n, size_t idx, size_t site) {
+  const cx<float> q = Codec<K>::unpack(v[idx]);
+  const float sc = __uint_as_float(v[n + site]);
+  return mk<double>(double(sc * q.re), double(sc * q.im));
+}
+
+__device__ inline size_t step_site(size_t site, size_t d, size_t Vh) {
+  site += d;
+  while (site >= Vh) site -= Vh;
+  return site;
+}
+
+template <HKind K>
+__global__ void __launch_bounds__(kBlock)
+    k_hmdot_part(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
+                 const cx<float> *__restrict__ w, size_t w_rs, size_t n, size_t Vh,
+                 double *__restrict__ part, const int *__restrict__ flag) {
+  constexpr int E = 16, WC = 64 * E;
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.y;
+  if (flag && flag[r] == 0) return;
+  const size_t nwch = size_t(gridDim.x) * kWaves;
+  const size_t chunk = size_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+  V += r * V_rs;
+  w += r * w_rs;
+  const size_t base = chunk * WC + lane;
+  cx<double> wv[E];
+  size_t st[E];
+  size_t site = base % Vh;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    size_t idx = base + size_t(e) * 64;
+    wv[e] = idx < n ? ld64(w + idx) : mk<double>(0, 0);
+    st[e] = site;
+    site = step_site(site, 64, Vh);
+  }
+  double *po = part + (size_t(r) * nwch + chunk) * size_t(J) * 2;
+  for (int j = 0; j < J; ++j) {
+    double a0 = 0, b0 = 0;
+    const uint32_t *v0 = V + size_t(j) * ldv;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      size_t idx = base + size_t(e) * 64;
+      if (idx < n) {
+        cx<double> p0 = cmulc(ldh<K>(v0, n, idx, st[e]), wv[e]);
+        a0 += p0.re;
+        b0 += p0.im;
+      }
+    }
+    a0 = wave_sum(a0);
+    b0 = wave_sum(b0);
+    if (lane == 0) {
+      po[2 * j] = a0;
+      po[2 * j + 1] = b0;
+    }
+  }
+}
+
+template <HKind K>
+__global__ void __launch_bounds__(kBlock)
+    k_hmaxpy(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
+             const cx<double> *__restrict__ coef, size_t coef_rs, cx<float> *__restrict__ w,
+             size_t w_rs, size_t n, size_t Vh, double *__restrict__ part,
+             const int *__restrict__ flag) {
+  __shared__ double sh[1][kWaves];
+  const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
+  if (flag && flag[r] == 0) return;
+  V += r * V_rs;
+  w += r * w_rs;
+  coef += r * coef_rs;
+  const size_t base = size_t(b) * ACH + threadIdx.x;
+  cx<double> acc[AEPT];
+  size_t st[AEPT];
+  size_t site = base % Vh;
+#pragma unroll
+  for (int e = 0; e < AEPT; ++e) {
+    size_t idx = base + size_t(e) * kBlock;
+    acc[e] = idx < n ? ld64(w + idx) : mk<double>(0, 0);
+    st[e] = site;
+    site = step_site(site, kBlock, Vh);
+  }
+  int j = 0;
+  for (; j + 2 <= J; j += 2) {
+    const cx<double> c0 = coef[j], c1 = coef[j + 1];
+    const uint32_t *v = V + size_t(j) * ldv;
+#pragma unroll
+    for (int e = 0; e < AEPT; ++e) {
+      size_t idx = base + size_t(e) * kBlock;
+      if (idx < n) {
+        cx<double> x0 = ldh<K>(v, n, idx, st[e]), x1 = ldh<K>(v + ldv, n, idx, st[e]);
+        acc[e] = acc[e] - (x0 * c0 + x1 * c1);
+      }
+    }
+  }
+  for (; j < J; ++j) {
+    const cx<double> c0 = coef[j];
+#pragma unroll
+    for (int e = 0; e < AEPT; ++e) {
+      size_t idx = base + size_t(e) * kBlock;
+      if (idx < n) acc[e] = acc[e] - ldh<K>(V + size_t(j) * ldv, n, idx, st[e]) * c0;
+    }
+  }
+  double nrm[1] = {0};
+#pragma unroll
+  for (int e = 0; e < AEPT; ++e) {
+    size_t idx = base + size_t(e) * kBlock;
+    if (idx < n) {
+      const cx<float> stv = mk<float>(float(acc[e].re), float(acc[e].im));
+      stc(w + idx, stv);
+      nrm[0] += double(stv.re) * double(stv.re) + double(stv.im) * double(stv.im);
+    }
+  }
+  if (part) {
+    block_sum<1>(nrm, sh);
+    if (threadIdx.x == 0) part[size_t(r) * nblk + b] = nrm[0];
+  }
+}
+
+template <HKind K>
+__global__ void __launch_bounds__(kBlock)
+    k_hgemm_nn(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
+               const cx<double> *__restrict__ C, size_t ldc, size_t C_rs, cx<float> *__restrict__ Y,
+               size_t ldy, size_t Y_rs, int nb, size_t n, size_t Vh, double alpha) {
+  const int r = blockIdx.y;
+  V += r * V_rs;
+  C += r * C_rs;
+  Y += r * Y_rs;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    const size_t site = i % Vh;
+    for (int b0 = 0; b0 < nb; b0 += NBT) {
+      cx<double> acc[NBT];
+#pragma unroll
+      for (int t = 0; t < NBT; ++t) acc[t] = mk<double>(0, 0);
+      for (int j = 0; j < J; ++j) {
+        cx<double> v = ldh<K>(V + size_t(j) * ldv, n, i, site);
+#pragma unroll
+        for (int t = 0; t < NBT; ++t)
+          if (b0 + t < nb) acc[t] = acc[t] + v * C[j + ldc * size_t(b0 + t)];
+      }
+#pragma unroll
+      for (int t = 0; t < NBT; ++t)
+        if (b0 + t < nb) {
+          cx<float> *yp = Y + size_t(b0 + t) * ldy + i;
+          cx<double> y = ld64(yp) + alpha * acc[t];
+          stc(yp, mk<float>(float(y.re), float(y.im)));
+        }
+    }
+  }
+}
+
+// out_r = quantised (scale[r] * w_r): one thread per site, 12 components.
+template <HKind K>
+__global__ void __launch_bounds__(kBlock)
+    k_hquant(const cx<float> *__restrict__ w, size_t w_rs, const double *__restrict__ scale,
+             uint32_t *__restrict__ out, size_t out_rs, size_t Vh) {
+  const int r = blockIdx.y;
+  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= Vh) return;
+  const float f = scale ? float(scale[r]) : 1.0f;
+  w += r * w_rs;
+  out += r * out_rs;
+  cx<float> v[12];
+  float m = 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    v[c] = ldc(w + c * Vh + i);
+    v[c] = mk(f * v[c].re, f * v[c].im);
+    m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+  }
+  const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) out[c * Vh + i] = Codec<K>::pack(inv * v[c].re, inv * v[c].im);
+  out[12 * Vh + i] = __float_as_uint(m);
+}
+
+// y_r = x_r decoded (FP32), one thread per site.
+template <HKind K>
+__global__ void __launch_bounds__(kBlock)
+    k_hdequant(const uint32_t *__restrict__ x, size_t x_rs, cx<float> *__restrict__ y, size_t y_rs,
+               size_t Vh) {
+  const int r = blockIdx.y;
+  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= Vh) return;
+  x += r * x_rs;
+  y += r * y_rs;
+  const float sc = __uint_as_float(x[12 * Vh + i]);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const cx<float> q = Codec<K>::unpack(x[c * Vh + i]);
+    stc(y + c * Vh + i, mk(sc * q.re, sc * q.im));
+  }
+}
+
+__global__ void k_inv_sqrt(const double *__restrict__ nrm2, double *__restrict__ inv, int nb) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nb) {
+    const double v = sqrt(nrm2[r]);
+    inv[r] = (v > 0 && isfinite(v)) ? 1.0 / v : 0.0;
+  }
+}
+
 inline unsigned grid_elems(size_t n) { return unsigned(std::min<size_t>(nblocks(n), 8192)); }
 
 }  // namespace
@@ -488,5 +697,105 @@ void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size
 INST(double)
 INST(float)
 #undef INST
+
+// ------------------------------------------------ 16-bit stored bases (host)
+// Stored bytes of one 12 Vh-element vector: 48 per site plus the 4-byte scale.
+inline double hbytes(size_t n) { return 52.0 * double(n / 12); }
+
+template <int KIND>
+void hmulti_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w,
+                size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag) {
+  if (J <= 0 || nrhs <= 0) return;
+  constexpr HKind K = static_cast<HKind>(KIND);
+  constexpr size_t BCH = size_t(64 * 16) * kWaves;
+  const int ngrid = int((n + BCH - 1) / BCH);
+  const int nblk = ngrid * kWaves;
+  double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * J * 2 * sizeof(double)));
+  Timed tm(c, LQCD_KC_DOT, flag ? 0.0 : (J * hbytes(n) + n * sizeof(cx<float>)) * nrhs);
+  hipLaunchKernelGGL((k_hmdot_part<K>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const uint32_t *>(V), ldv, V_rs, J, static_cast<const cx<float> *>(w),
+                     w_rs, n, n / 12, part, flag);
+  LQCD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_mdot_final, dim3(J, nrhs), dim3(kBlock), 0, c->stream, part, nblk, J,
+                     reinterpret_cast<cx<double> *>(out), out_rs, flag);
+  LQCD_HIP(hipGetLastError());
+}
+
+template <int KIND>
+void hmulti_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
+                 size_t coef_rs, void *w, size_t w_rs, size_t n, int nrhs, double *norm2_out,
+                 const int *flag) {
+  if (nrhs <= 0) return;
+  constexpr HKind K = static_cast<HKind>(KIND);
+  const int nblk = int((n + ACH - 1) / ACH);
+  double *part = nullptr;
+  if (norm2_out) part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * sizeof(double)));
+  Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + 2.0 * n * sizeof(cx<float>)) * nrhs);
+  hipLaunchKernelGGL((k_hmaxpy<K>), dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const uint32_t *>(V), ldv, V_rs, J,
+                     reinterpret_cast<const cx<double> *>(coef), coef_rs, static_cast<cx<float> *>(w),
+                     w_rs, n, n / 12, part, flag);
+  LQCD_HIP(hipGetLastError());
+  if (norm2_out) {
+    hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(kBlock), 0, c->stream, part, nblk, norm2_out, flag);
+    LQCD_HIP(hipGetLastError());
+  }
+}
+
+template <int KIND>
+void hgemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *C,
+              size_t ldc, size_t C_rs, void *Y, size_t ldy, size_t Y_rs, int nb, size_t n, int nrhs,
+              double alpha) {
+  if (nb <= 0 || nrhs <= 0) return;
+  constexpr HKind K = static_cast<HKind>(KIND);
+  Timed tm(c, LQCD_KC_GEMM, (J * hbytes(n) + 2.0 * nb * n * sizeof(cx<float>)) * nrhs);
+  hipLaunchKernelGGL((k_hgemm_nn<K>), dim3(grid_elems(n), nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const uint32_t *>(V), ldv, V_rs, J,
+                     reinterpret_cast<const cx<double> *>(C), ldc, C_rs, static_cast<cx<float> *>(Y),
+                     ldy, Y_rs, nb, n, n / 12, alpha);
+  LQCD_HIP(hipGetLastError());
+}
+
+template <int KIND>
+void hquantize(lqcd_ctx *c, const void *w, size_t w_rs, const double *scale_dev, void *out,
+               size_t out_rs, size_t n, int nrhs) {
+  if (nrhs <= 0) return;
+  constexpr HKind K = static_cast<HKind>(KIND);
+  const size_t Vh = n / 12;
+  hipLaunchKernelGGL((k_hquant<K>), dim3(nblocks(Vh), nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const cx<float> *>(w), w_rs, scale_dev, static_cast<uint32_t *>(out),
+                     out_rs, Vh);
+  LQCD_HIP(hipGetLastError());
+}
+
+template <int KIND>
+void hdequantize(lqcd_ctx *c, const void *x, size_t x_rs, void *y, size_t y_rs, size_t n, int nrhs) {
+  if (nrhs <= 0) return;
+  constexpr HKind K = static_cast<HKind>(KIND);
+  const size_t Vh = n / 12;
+  hipLaunchKernelGGL((k_hdequant<K>), dim3(nblocks(Vh), nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const uint32_t *>(x), x_rs, static_cast<cx<float> *>(y), y_rs, Vh);
+  LQCD_HIP(hipGetLastError());
+}
+
+void inv_sqrt_dev(lqcd_ctx *c, const double *nrm2, double *inv, int nb) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_inv_sqrt, dim3((nb + 63) / 64), dim3(64), 0, c->stream, nrm2, inv, nb);
+  LQCD_HIP(hipGetLastError());
+}
+
+#define HINST(K)                                                                                  \
+  template void hmulti_dot<K>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
+                              size_t, int, cdouble *, size_t, const int *);                        \
+  template void hmulti_axpy<K>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,     \
+                               size_t, void *, size_t, size_t, int, double *, const int *);        \
+  template void hgemm_nn<K>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,        \
+                            size_t, size_t, void *, size_t, size_t, int, size_t, int, double);     \
+  template void hquantize<K>(lqcd_ctx *, const void *, size_t, const double *, void *, size_t,     \
+                             size_t, int);                                                         \
+  template void hdequantize<K>(lqcd_ctx *, const void *, size_t, void *, size_t, size_t, int);
+HINST(0)
+HINST(1)
+#undef HINST
 
 }  // namespace lqcd

@@ -171,6 +171,12 @@ template <class R>
 void apply_schur(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs,
                  size_t stride_in, size_t stride_out, size_t stride_tmp);
 
+// Mhat on 16-bit stored even fields (half.h kind KIND; in: words, vectors
+// sin words apart); FP32 output and odd temporary.
+template <int KIND>
+void apply_schur_h(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin,
+                   size_t sout, size_t stmp);
+
 // context.cpp: event timing of one launch (no-op unless the timer is on)
 int timer_start(lqcd_ctx *c, int cls, double bytes);
 void timer_stop(lqcd_ctx *c, int slot);

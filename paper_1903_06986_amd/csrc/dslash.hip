@@ -18,10 +18,37 @@
 #include "common.h"
 #include "cplx.h"
 #include "fields.h"
+#include "half.h"
 
 namespace lqcd {
 
 namespace {
+
+// Field sources of the stencil: plain complex fields of precision R, or
+// 16-bit fields with per-site scales (half.h), decoded to FP32.  at(r)
+// moves to right-hand side r (stride in elements of the storage); site(i)
+// fetches what every component load of site i shares.
+template <class R>
+struct SrcPlain {
+  const cx<R> *p;
+  using Ctx = int;
+  __device__ SrcPlain at(size_t off) const { return SrcPlain{p + off}; }
+  __device__ Ctx site(size_t) const { return 0; }
+  __device__ cx<R> ld(Ctx, size_t i, int comp, size_t Vh) const { return ldc(p + comp * Vh + i); }
+};
+
+template <HKind K>
+struct SrcHalf {
+  const uint32_t *p;
+  size_t n;  // payload words (12 Vh); the scales follow
+  using Ctx = float;
+  __device__ SrcHalf at(size_t off) const { return SrcHalf{p + off, n}; }
+  __device__ Ctx site(size_t i) const { return __uint_as_float(p[n + i]); }
+  __device__ cx<float> ld(Ctx sc, size_t i, int comp, size_t Vh) const {
+    const cx<float> v = Codec<K>::unpack(p[comp * Vh + i]);
+    return mk(sc * v.re, sc * v.im);
+  }
+};
 
 template <class R>
 struct Half {
@@ -62,14 +89,16 @@ __device__ inline void link_dag_mul(const cx<R> *u, size_t Vh, const Half<R> &in
   }
 }
 
-// Project psi (12 components at stride Vh from p) for direction MU and sign
-// (FWD: 1 - g_mu, else 1 + g_mu).  G5 applies g5 = diag(1,1,-1,-1) first.
-template <class R, int MU, bool FWD, bool G5>
-__device__ inline void project(const cx<R> *p, size_t Vh, Half<R> &o) {
+// Project psi (site i of the source, 12 components at stride Vh) for
+// direction MU and sign (FWD: 1 - g_mu, else 1 + g_mu).  G5 applies
+// g5 = diag(1,1,-1,-1) first.
+template <class R, int MU, bool FWD, bool G5, class Src>
+__device__ inline void project(const Src &src, size_t i, size_t Vh, Half<R> &o) {
+  const typename Src::Ctx sc = src.site(i);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    cx<R> u0 = ldc(p + (0 * 3 + c) * Vh), u1 = ldc(p + (1 * 3 + c) * Vh);
-    cx<R> l0 = ldc(p + (2 * 3 + c) * Vh), l1 = ldc(p + (3 * 3 + c) * Vh);
+    cx<R> u0 = src.ld(sc, i, 0 * 3 + c, Vh), u1 = src.ld(sc, i, 1 * 3 + c, Vh);
+    cx<R> l0 = src.ld(sc, i, 2 * 3 + c, Vh), l1 = src.ld(sc, i, 3 * 3 + c, Vh);
     if (G5) {
       l0 = -l0;
       l1 = -l1;
@@ -131,18 +160,18 @@ __device__ inline void fence(cx<R> acc[4][3]) {
     for (int c = 0; c < 3; ++c) asm volatile("" : "+v"(acc[s][c].re), "+v"(acc[s][c].im)::"memory");
 }
 
-template <class R, int MU, bool G5IN>
+template <class R, int MU, bool G5IN, class Src>
 __device__ inline void hop_dir(cx<R> acc[4][3], const cx<R> *U,
-                               const cx<R> *in, int p, int i, int nf, int nb,
+                               const Src &in, int p, int i, int nf, int nb,
                                size_t Vh) {
   Half<R> h, g;
   // forward: (1 - g_mu) U_mu(x) psi(x + mu); the link lives at x (parity p)
-  project<R, MU, true, G5IN>(in + nf, Vh, h);
+  project<R, MU, true, G5IN>(in, nf, Vh, h);
   link_mul<R>(U + ((size_t(p) * 4 + MU) * 9) * Vh + i, Vh, h, g);
   accumulate<R, MU, true>(acc, g);
   fence(acc);
   // backward: (1 + g_mu) U_mu(x - mu)^+ psi(x - mu); link at x - mu (parity 1-p)
-  project<R, MU, false, G5IN>(in + nb, Vh, h);
+  project<R, MU, false, G5IN>(in, nb, Vh, h);
   link_dag_mul<R>(U + ((size_t(1 - p) * 4 + MU) * 9) * Vh + nb, Vh, h, g);
   accumulate<R, MU, false>(acc, g);
   fence(acc);
@@ -153,11 +182,11 @@ __device__ inline void hop_dir(cx<R> acc[4][3], const cx<R> *U,
 // and one wave load fetches each link once for all NB of them (links are
 // 2/3 of a single right-hand side's bytes).  Spinor accesses stay in
 // contiguous runs of 64/NB sites per right-hand side.
-template <class R, bool G5IN, bool G5OUT, bool SELF, int NB>
+template <class R, bool G5IN, bool G5OUT, bool SELF, int NB, class SrcIn, class SrcSelf>
 // 3 waves per SIMD caps FP64 at 128 VGPRs (4 waves resident, no spills).
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8)))
-    k_hop(Geom g, int p, const cx<R> *U, const cx<R> *in,
-          const cx<R> *self, cx<R> *out, cx<R> alpha, R beta,
+    k_hop(Geom g, int p, const cx<R> *U, SrcIn in,
+          SrcSelf self, cx<R> *out, cx<R> alpha, R beta,
           size_t in_stride, size_t self_stride, size_t out_stride, int nrhs, int xq, int ngr) {
   // XCD-aware block order: workgroups are dispatched round-robin over the
   // 8 XCDs, so hardware block h runs on XCD h % 8.  Logical block
@@ -172,7 +201,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
   if (i >= g.Vh || rr >= nrhs) return;
   const size_t Vh = size_t(g.Vh);
   const size_t rhs = rr;
-  in += rhs * in_stride;
+  in = in.at(rhs * in_stride);
   out += rhs * out_stride;
   const int Lxh = g.Lxh, Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
   const int xh = i % Lxh;
@@ -213,14 +242,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
     hop_dir<R, 3, G5IN>(acc, U, in, p, i, nf, nb, Vh);
   }
 
-  const cx<R> *sp = SELF ? self + rhs * self_stride + i : nullptr;
+  if (SELF) self = self.at(rhs * self_stride);
+  const typename SrcSelf::Ctx ssc = SELF ? self.site(i) : typename SrcSelf::Ctx{};
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       cx<R> v = beta * acc[s][c];
       if (SELF) {
-        cx<R> w = ldc(sp + (s * 3 + c) * Vh);
+        cx<R> w = self.ld(ssc, i, s * 3 + c, Vh);
         if (G5IN && s >= 2) w = -w;
         v = v + alpha * w;
       }
@@ -229,28 +259,40 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
     }
 }
 
-template <class R, bool A, bool B, bool C, int NB>
-void launch_hop_nb(lqcd_ctx *c, int p, const cx<R> *U, const void *in, const void *self, void *out,
+template <class R, bool A, bool B, bool C, int NB, class SI, class SS>
+void launch_hop_nb(lqcd_ctx *c, int p, const cx<R> *U, SI in, SS self, void *out,
                    cdouble alpha, double beta, int nrhs, size_t si, size_t ss, size_t so) {
   const Geom &g = c->g;
   const int nbx = int(nblocks(g.Vh, kBlock / NB));
   const int ngr = (nrhs + NB - 1) / NB;
   const int xq = (nbx * ngr + 7) / 8;  // logical blocks per XCD (the grid is padded to 8 * xq)
   dim3 grid(8 * xq);
-  hipLaunchKernelGGL((k_hop<R, A, B, C, NB>), grid, dim3(kBlock), 0, c->stream, g, p, U,
-                     static_cast<const cx<R> *>(in), static_cast<const cx<R> *>(self),
-                     static_cast<cx<R> *>(out), mk<R>(R(alpha.real()), R(alpha.imag())), R(beta),
+  hipLaunchKernelGGL((k_hop<R, A, B, C, NB, SI, SS>), grid, dim3(kBlock), 0, c->stream, g, p, U, in,
+                     self, static_cast<cx<R> *>(out), mk<R>(R(alpha.real()), R(alpha.imag())), R(beta),
                      si, ss, so, nrhs, xq, ngr);
 }
 
-template <class R, bool A, bool B, bool C>
-void launch_hop(lqcd_ctx *c, int p, const void *in, const void *self, void *out, cdouble alpha,
-                double beta, int nrhs, size_t si, size_t ss, size_t so) {
+// Bytes per site of one stored half field of a source type.
+template <class S>
+struct SrcBytes;
+template <class R>
+struct SrcBytes<SrcPlain<R>> {
+  static constexpr double v = 12.0 * sizeof(cx<R>);
+};
+template <HKind K>
+struct SrcBytes<SrcHalf<K>> {
+  static constexpr double v = 52.0;
+};
+
+template <class R, bool A, bool B, bool C, class SI, class SS>
+void launch_hop_src(lqcd_ctx *c, int p, SI in, SS self, void *out, cdouble alpha,
+                    double beta, int nrhs, size_t si, size_t ss, size_t so) {
   const Geom &g = c->g;
   const cx<R> *U = static_cast<const cx<R> *>(std::is_same<R, double>::value ? c->U64.ptr : c->U32.ptr);
   // algorithmic bytes: all 8 Vh links once, input and output half fields
   // (and the self term) once per right-hand side
-  const double bytes = double(g.Vh) * sizeof(cx<R>) * (72.0 + nrhs * (24.0 + (C ? 12.0 : 0.0)));
+  const double bytes = double(g.Vh) * (72.0 * sizeof(cx<R>) +
+                                       nrhs * (SrcBytes<SI>::v + 12.0 * sizeof(cx<R>) + (C ? SrcBytes<SS>::v : 0.0)));
   Timed tm(c, std::is_same<R, double>::value ? LQCD_KC_HOP64 : LQCD_KC_HOP32, bytes);
   const int nbmax = c->hop_nb[std::is_same<R, double>::value ? 0 : 1];
   if (nrhs >= 8 && nbmax >= 8) launch_hop_nb<R, A, B, C, 8>(c, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
@@ -258,6 +300,14 @@ void launch_hop(lqcd_ctx *c, int p, const void *in, const void *self, void *out,
   else if (nrhs >= 2 && nbmax >= 2) launch_hop_nb<R, A, B, C, 2>(c, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   else launch_hop_nb<R, A, B, C, 1>(c, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   LQCD_HIP(hipGetLastError());
+}
+
+template <class R, bool A, bool B, bool C>
+void launch_hop(lqcd_ctx *c, int p, const void *in, const void *self, void *out, cdouble alpha,
+                double beta, int nrhs, size_t si, size_t ss, size_t so) {
+  launch_hop_src<R, A, B, C>(c, p, SrcPlain<R>{static_cast<const cx<R> *>(in)},
+                             SrcPlain<R>{static_cast<const cx<R> *>(self)}, out, alpha, beta, nrhs, si,
+                             ss, so);
 }
 
 }  // namespace
@@ -322,6 +372,25 @@ void apply_schur(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs
   hop_half<R>(c, 0, tmp_odd, in, out, cdouble(1, 0), -k * k, false, false, nrhs, stmp, sin, sout);
 }
 
+// Mhat on stored 16-bit even fields (in: words, vectors sin words apart),
+// FP32 output and odd temporary.
+template <int KIND>
+void apply_schur_h(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin,
+                   size_t sout, size_t stmp) {
+  if (nrhs <= 0) return;
+  constexpr HKind K = static_cast<HKind>(KIND);
+  const double k = c->kappa;
+  const size_t n = half_len(c->g);
+  const SrcHalf<K> hin{static_cast<const uint32_t *>(in), n};
+  const SrcPlain<float> none{nullptr};
+  launch_hop_src<float, false, false, false>(c, 1, hin, none, tmp_odd, cdouble(0, 0), 1.0, nrhs, sin,
+                                             0, stmp);
+  launch_hop_src<float, false, false, true>(c, 0, SrcPlain<float>{static_cast<const cx<float> *>(tmp_odd)},
+                                            hin, out, cdouble(1, 0), -k * k, nrhs, stmp, sin, sout);
+}
+template void apply_schur_h<0>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
+template void apply_schur_h<1>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
+
 template void hop_half<double>(lqcd_ctx *, int, const void *, const void *, void *, cdouble, double,
                                bool, bool, int, size_t, size_t, size_t);
 template void hop_half<float>(lqcd_ctx *, int, const void *, const void *, void *, cdouble, double,
@@ -338,6 +407,29 @@ using namespace lqcd;
 namespace {
 
 size_t prec_bytes(lqcd_prec p) { return p == LQCD_F64 ? 16 : 8; }
+
+// Mhat with the 16-bit stored input (LEX complex128 in and out): the even
+// half is packed to FP32, stored with per-site scales, and the stencil
+// reads the stored form; the odd half of the output is zero.
+template <int KIND>
+void wilson_apply_h(lqcd_ctx *c, const void *in, void *out, int nrhs) {
+  const size_t hl = half_len(c->g), fl = full_len(c->g);
+  const size_t ldh = hvec_words(size_t(c->g.Vh));
+  const int blk = std::max(1, std::min(nrhs, 16));
+  void *a = c->ws[5].ensure(2 * hl * blk * sizeof(cx<float>));
+  void *b = c->ws[6].ensure(2 * hl * blk * sizeof(cx<float>));
+  void *q = c->ws[4].ensure(ldh * blk * sizeof(uint32_t));
+  void *tmp = c->ws[7].ensure(hl * blk * sizeof(cx<float>));
+  for (int r0 = 0; r0 < nrhs; r0 += blk) {
+    const int nb = std::min(blk, nrhs - r0);
+    pack_eo<float>(c, static_cast<const cdouble *>(in) + r0 * fl, a, nb, 2 * hl);
+    hquantize<KIND>(c, a, 2 * hl, nullptr, q, ldh, hl, nb);
+    apply_schur_h<KIND>(c, q, b, tmp, nb, ldh, 2 * hl, hl);
+    for (int r = 0; r < nb; ++r)
+      fill_zero(c, static_cast<cx<float> *>(b) + (2 * r + 1) * hl, hl * sizeof(cx<float>));
+    unpack_eo<float>(c, b, static_cast<cdouble *>(out) + r0 * fl, nb, 2 * hl);
+  }
+}
 
 template <class R>
 void wilson_apply_t(lqcd_ctx *c, lqcd_op op, lqcd_layout layout, const void *in, void *out,
@@ -390,7 +482,12 @@ extern "C" lqcd_status wilson_apply(lqcd_ctx *c, lqcd_op op, lqcd_prec prec, lqc
     if (nrhs == 0) return;
     if (prec == LQCD_F64) wilson_apply_t<double>(c, op, layout, in, out, nrhs);
     else if (prec == LQCD_F32) wilson_apply_t<float>(c, op, layout, in, out, nrhs);
-    else LQCD_CHECK(false, LQCD_EINVAL, "wilson_apply: precision %d not available", int(prec));
+    else if (prec == LQCD_F16 || prec == LQCD_BF16) {
+      LQCD_CHECK(op == LQCD_OP_SCHUR && layout == LQCD_LAYOUT_LEX, LQCD_EINVAL,
+                 "wilson_apply: 16-bit storage is available for LQCD_OP_SCHUR in LQCD_LAYOUT_LEX");
+      if (prec == LQCD_F16) wilson_apply_h<0>(c, in, out, nrhs);
+      else wilson_apply_h<1>(c, in, out, nrhs);
+    } else LQCD_CHECK(false, LQCD_EINVAL, "wilson_apply: precision %d not available", int(prec));
     (void)prec_bytes;
   });
 }

@@ -70,4 +70,28 @@ template <class R>
 void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size_t ldp, int Jout,
                size_t n);
 
+// 16-bit stored bases (half.h; KIND 0 = FP16, 1 = BF16): V is a basis of
+// stored vectors ldv words apart (V_rs words between right-hand sides), w/Y
+// FP32 vectors of n = 12 Vh elements.  Semantics as the FP32 versions.
+template <int KIND>
+void hmulti_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w,
+                size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag);
+template <int KIND>
+void hmulti_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
+                 size_t coef_rs, void *w, size_t w_rs, size_t n, int nrhs, double *norm2_out,
+                 const int *flag);
+template <int KIND>
+void hgemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *C,
+              size_t ldc, size_t C_rs, void *Y, size_t ldy, size_t Y_rs, int nb, size_t n, int nrhs,
+              double alpha);
+// out_r = stored(scale_dev[r] * w_r) with per-site scales (scale_dev may
+// be null: factor 1); and the decode.
+template <int KIND>
+void hquantize(lqcd_ctx *c, const void *w, size_t w_rs, const double *scale_dev, void *out,
+               size_t out_rs, size_t n, int nrhs);
+template <int KIND>
+void hdequantize(lqcd_ctx *c, const void *x, size_t x_rs, void *y, size_t y_rs, size_t n, int nrhs);
+// inv[r] = 1 / sqrt(nrm2[r]) (0 for 0 or non-finite), device arrays.
+void inv_sqrt_dev(lqcd_ctx *c, const double *nrm2, double *inv, int nb);
+
 }  // namespace lqcd

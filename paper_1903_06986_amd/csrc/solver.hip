@@ -30,6 +30,7 @@
 
 #include "cplx.h"
 #include "fields.h"
+#include "half.h"
 #include "solver.h"
 
 namespace lqcd {
@@ -129,6 +130,14 @@ struct Op {
       apply_full<R>(c, LQCD_OP_MG5, in, out, nb, sin, sout);
     }
   }
+  // Mhat on 16-bit stored even fields (words, sin apart), FP32 output.
+  template <int BK>
+  void apply_h(const void *in, size_t sin, void *out, size_t sout, int nb) const {
+    if (nb <= 0) return;
+    const size_t hl = half_len(c->g);
+    void *t = tmp->ensure(hl * size_t(nb) * sizeof(cx<float>));
+    apply_schur_h<BK>(c, in, out, t, nb, sin, sout, hl);
+  }
 };
 
 // Device scratch for the small per-cycle matrices.
@@ -208,6 +217,33 @@ void arnoldi(lqcd_ctx *c, const Op<R> &A, void *W, size_t n, size_t Wrs, int j0,
                        size_t(m + 1), s.nrm1, s.nrm2, s.flag, s.inv);
     LQCD_HIP(hipGetLastError());
     scale_dev<R>(c, wn, Wrs, s.inv, wn, Wrs, n, nb);
+  }
+}
+
+// Arnoldi steps with a 16-bit stored basis (kind BK, half.h): W holds
+// the basis as stored vectors ldv words apart (bases Wrs words apart);
+// the new vector is built and orthogonalised in FP32 in wt (vectors n
+// apart), then normalised and stored into slot j + 1.
+template <int BK>
+void arnoldi_h(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, size_t Wrs, int j0,
+               int m, int nb, Small &s, double eta2, void *wt) {
+  uint32_t *Wb = static_cast<uint32_t *>(W);
+  for (int j = j0; j < m; ++j) {
+    A.template apply_h<BK>(Wb + size_t(j) * ldv, Wrs, wt, n, nb);
+    hmulti_dot<BK>(c, Wb, ldv, Wrs, j + 1, wt, n, n, nb, s.h1, m + 1, nullptr);
+    hmulti_axpy<BK>(c, Wb, ldv, Wrs, j + 1, s.h1, m + 1, wt, n, n, nb, s.nrm1, nullptr);
+    hipLaunchKernelGGL(k_dgks, dim3(nb), dim3(64), 0, c->stream,
+                       reinterpret_cast<const cx<double> *>(s.h1), size_t(m + 1), j + 1, s.nrm1,
+                       s.flag, s.reorth, eta2);
+    LQCD_HIP(hipGetLastError());
+    hmulti_dot<BK>(c, Wb, ldv, Wrs, j + 1, wt, n, n, nb, s.h2, m + 1, s.flag);
+    hmulti_axpy<BK>(c, Wb, ldv, Wrs, j + 1, s.h2, m + 1, wt, n, n, nb, s.nrm2, s.flag);
+    hipLaunchKernelGGL(k_finish_col, dim3(nb), dim3(64), 0, c->stream,
+                       reinterpret_cast<cx<double> *>(s.Hd), s.Hrs, m + 1, j,
+                       reinterpret_cast<cx<double> *>(s.h1), reinterpret_cast<cx<double> *>(s.h2),
+                       size_t(m + 1), s.nrm1, s.nrm2, s.flag, s.inv);
+    LQCD_HIP(hipGetLastError());
+    hquantize<BK>(c, wt, n, s.inv, Wb + size_t(j + 1) * ldv, Wrs, n, nb);
   }
 }
 
@@ -379,12 +415,15 @@ void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lq
 // An inner solve of iterative refinement (cycle_cap > 0) also stops after
 // cycle_cap cycles of this call, or when a cycle leaves the residual above
 // `stall` times the previous one: it only has to shrink the residual.
-template <class R>
+// BK >= 0 (R = float only): the GMRES(p) basis W is stored in 16 bits
+// (half.h kind BK) and wt is FP32 scratch of nb vectors.
+template <class R, int BK = -1>
 void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *d, int p, void *S,
                 void *X, void *Rr, void *W, int nb, std::vector<double> ref, double tol,
                 int max_cycles, std::vector<int> &matvecs, std::vector<int> &cycles,
                 std::vector<double> &resid, std::vector<int> &reorth, int cycle_cap = 0,
-                double stall = 0.0) {
+                double stall = 0.0, void *wt = nullptr) {
+  static_assert(BK < 0 || std::is_same<R, float>::value, "16-bit bases hold FP32 solves");
   const size_t n = A.n;
   const int k = d->k;
   Small s(c->small[0]);
@@ -464,9 +503,17 @@ void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *
       rn[r] = std::sqrt(rn[r]);
       sc[r] = rn[r] > 0 ? 1.0 / rn[r] : 0.0;
     }
-    const size_t Wrs = size_t(p + 1) * n;
-    axpby<R>(c, sc.data(), Rb, n, zs.data(), W, Wrs, n, na, true);
-    arnoldi<R>(c, A, W, n, Wrs, 0, p, na, s, kReorthCycle);
+    const size_t ldh = hvec_words(n / 12);
+    const size_t Wrs = BK >= 0 ? size_t(p + 1) * ldh : size_t(p + 1) * n;
+    if constexpr (BK >= 0) {
+      norm2<R>(c, Rb, n, n, na, s.nrm2);
+      inv_sqrt_dev(c, s.nrm2, s.inv, na);
+      hquantize<BK>(c, Rb, n, s.inv, W, Wrs, n, na);
+      arnoldi_h<BK>(c, A, W, n, ldh, Wrs, 0, p, na, s, kReorthCycle, wt);
+    } else {
+      axpby<R>(c, sc.data(), Rb, n, zs.data(), W, Wrs, n, na, true);
+      arnoldi<R>(c, A, W, n, Wrs, 0, p, na, s, kReorthCycle);
+    }
     harvest_reorth(c, s, na, perm, reorth);
     Hh.resize(s.Hrs * na);
     d2h(c, Hh.data(), s.Hd, Hh.size() * sizeof(cdouble));
@@ -484,7 +531,10 @@ void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *
       cycles[perm[r]] += 1;
     }
     h2d(c, s.vec, dall.data(), dall.size() * sizeof(cdouble));
-    gemm_nn<R>(c, W, n, Wrs, p, s.vec, p, p, Xb, n, n, 1, n, na, 1.0);
+    if constexpr (BK >= 0)
+      hgemm_nn<BK>(c, W, ldh, Wrs, p, s.vec, p, p, Xb, n, n, 1, n, na, 1.0);
+    else
+      gemm_nn<R>(c, W, n, Wrs, p, s.vec, p, p, Xb, n, n, 1, n, na, 1.0);
     // true residual r = S - A X
     A.apply(Xb, n, Rb, n, na);
     cdouble one(1, 0), mone(-1, 0);
@@ -500,11 +550,11 @@ void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *
 // ------------------------------------------------------------- drivers
 // Solver buffers live in the context so that repeated calls reuse them.
 struct Work {
-  DevBuf &Bp, &S, &X, &R, &W, &XF, &T, &S32, &X32, &R32, &W32, &tmp64, &tmp32, &red2;
+  DevBuf &Bp, &S, &X, &R, &W, &XF, &T, &S32, &X32, &R32, &W32, &tmp64, &tmp32, &red2, &WT;
   explicit Work(lqcd_ctx *c)
       : Bp(c->sw[0]), S(c->sw[1]), X(c->sw[2]), R(c->sw[3]), W(c->sw[4]), XF(c->sw[5]),
         T(c->sw[6]), S32(c->sw[7]), X32(c->sw[8]), R32(c->sw[9]), W32(c->sw[10]),
-        tmp64(c->sw[11]), tmp32(c->sw[12]), red2(c->sw[13]) {}
+        tmp64(c->sw[11]), tmp32(c->sw[12]), red2(c->sw[13]), WT(c->sw[14]) {}
 };
 
 // Pack nb right-hand sides and build the system's source:
@@ -621,8 +671,10 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
     LQCD_CHECK(p.k >= 1 && p.m > p.k && p.m <= 250, LQCD_EINVAL,
                "gmresdr_solve: need 1 <= k < m <= 250 (m=%d, k=%d)", p.m, p.k);
     LQCD_CHECK(p.tol > 0 && p.max_cycles >= 1, LQCD_EINVAL, "gmresdr_solve: bad tol/max_cycles");
-    LQCD_CHECK(p.inner == LQCD_F64 || p.inner == LQCD_F32, LQCD_EINVAL,
-               "gmresdr_solve: inner precision must be F64 or F32");
+    LQCD_CHECK(p.inner >= LQCD_F64 && p.inner <= LQCD_BF16, LQCD_EINVAL,
+               "gmresdr_solve: bad inner precision");
+    LQCD_CHECK(op == LQCD_OP_SCHUR || p.inner == LQCD_F64 || p.inner == LQCD_F32, LQCD_EINVAL,
+               "gmresdr_solve: 16-bit storage is available for LQCD_OP_SCHUR only");
     const size_t n = op == LQCD_OP_SCHUR ? half_len(c->g) : full_len(c->g);
     const size_t fl = full_len(c->g);
     if (stats)
@@ -686,7 +738,10 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
         void *S32 = w.S32.ensure(n * nb * sizeof(cx<float>));
         void *X32 = w.X32.ensure(n * nb * sizeof(cx<float>));
         void *R32 = w.R32.ensure(n * nb * sizeof(cx<float>));
-        void *W32 = w.W32.ensure(size_t(p_cyc + 1) * n * nb * sizeof(cx<float>));
+        const bool h16 = p.inner == LQCD_F16 || p.inner == LQCD_BF16;
+        void *W32 = h16 ? w.W32.ensure(size_t(p_cyc + 1) * hvec_words(n / 12) * nb * sizeof(uint32_t))
+                        : w.W32.ensure(size_t(p_cyc + 1) * n * nb * sizeof(cx<float>));
+        void *WT = h16 ? w.WT.ensure(n * nb * sizeof(cx<float>)) : nullptr;
         void *T = w.T.ensure(n * nb * sizeof(cx<double>));
         fill_zero(c, X, n * nb * sizeof(cx<double>));
         copy_dev(c, Rr, w.S.ptr, n * nb * sizeof(cx<double>));
@@ -715,8 +770,15 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
           for (int r = 0; r < nb; ++r) iref[r] = (rn[r] > p.tol * ref[r]) ? rn[r] : 0.0;
           std::vector<double> ires(nb);
           const double itol = std::max(p.inner_tol, 1e-6);
-          proj_solve<float>(c, A32, d->V32.ptr, d, p_cyc, S32, X32, R32, W32, nb, iref, itol,
-                            p.max_cycles, mv, cy, ires, ro, kInnerCycleCap, kInnerStall);
+          if (p.inner == LQCD_F16)
+            proj_solve<float, 0>(c, A32, d->V32.ptr, d, p_cyc, S32, X32, R32, W32, nb, iref, itol,
+                                 p.max_cycles, mv, cy, ires, ro, kInnerCycleCap, kInnerStall, WT);
+          else if (p.inner == LQCD_BF16)
+            proj_solve<float, 1>(c, A32, d->V32.ptr, d, p_cyc, S32, X32, R32, W32, nb, iref, itol,
+                                 p.max_cycles, mv, cy, ires, ro, kInnerCycleCap, kInnerStall, WT);
+          else
+            proj_solve<float>(c, A32, d->V32.ptr, d, p_cyc, S32, X32, R32, W32, nb, iref, itol,
+                              p.max_cycles, mv, cy, ires, ro, kInnerCycleCap, kInnerStall);
           hipLaunchKernelGGL(k_acc_widen, dim3(std::min<size_t>(nblocks(n * nb), 8192)), dim3(kBlock),
                              0, c->stream, static_cast<const cx<float> *>(X32), static_cast<cx<double> *>(X),
                              n * nb);

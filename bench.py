@@ -10,9 +10,13 @@ Setup (once per configuration, timed separately): first GMRES-DR solve,
 hermitian eigenpairs, Min-Res coefficients, exact trace corrections.
 One timed step = one batch of `rhs_block` Z(4) noise vectors through every
 per-noise row of the path: noise generation, GMRES-Proj solves to a 1e-10
-true residual (mixed: FP32 inner solves in FP64 refinement; or plain
-FP64), odd-site reconstruction and FP64 true residual, PS / POLY / HFES /
-HFPS / HFPOLY subtraction vectors and the estimator for Theta = 1, g1..g4.
+true residual (mixed: FP32 inner solves in FP64 refinement, the inner
+basis and stencil input optionally stored in FP16/BF16 with per-site
+scales; or plain FP64), odd-site reconstruction and FP64 true residual,
+PS / POLY / HFES / HFPS / HFPOLY subtraction vectors and the estimator for
+Theta = 1, g1..g4.  Untimed afterwards: every precision solves the same
+noise batch and reports its estimates' difference from plain FP64 and one
+solution's residual under the FP64 oracle's operator.
 
 metric: deflated noise-solves/s (mixed precision), with the plain-FP64
 rate and the ratio in the same line; roofline of the dominant kernel from
@@ -132,6 +136,7 @@ class Path:
                                                       mode=lqcd.DEFL_EIGPOLY, coeffs=self.cpoly,
                                                       thetas=THETAS)
         res["HFPOLY"] = ctx.loop_estimate(eta, x, xt_poly, corr_hfpoly, THETAS)
+        self.last = (eta, x)
         return st, res
 
 
@@ -151,6 +156,34 @@ def run_steps(path, inner, steps, warmup):
     kt = path.ctx.timer_read()
     path.ctx.timer(False)
     return dt, stats, kt
+
+
+def accuracy(path, precisions, cfg, kappa, U, oracle_check):
+    """Untimed: the same noise batch solved in every precision; estimates
+    compared with the plain-FP64 solve's, and one solution per precision
+    checked against the FP64 oracle's operator (|eta - M x| / |eta|)."""
+    out = {}
+    keep = path.next_noise
+    ref = None
+    for prec in ["f64"] + [p for p in precisions if p != "f64"]:
+        path.next_noise = 1
+        st, res = path.step(prec)
+        eta, x = path.last
+        est = {m: r[0] for m, r in res.items()}
+        if ref is None:
+            ref = est
+        o = {"max_true_resid": max(s["true_resid"] for s in st)}
+        o["estimate_rel_diff_vs_fp64"] = max(float(np.abs(est[m] - ref[m]).max() / np.abs(ref[m]).max())
+                                             for m in est)
+        if oracle_check:
+            from oracle import wilson as W
+            e = eta.cpu().numpy()[0]
+            xs = x.cpu().numpy()[0]
+            o["oracle_resid"] = float(np.linalg.norm(e - W.apply_M(U, kappa, xs)) / np.linalg.norm(e))
+        out[prec] = o
+        print("[bench] accuracy %s %s" % (prec, json.dumps(o)), file=sys.stderr, flush=True)
+    path.next_noise = keep
+    return out
 
 
 def cpu_baseline(cfg, kappa, matvecs_per_solve, p_cycle):
@@ -211,6 +244,13 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--max-cycles", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--inner", default="f16", choices=["f32", "f16", "bf16"],
+                    help="inner precision of the headline mixed rate (FP32 arithmetic; f16/bf16: "
+                         "16-bit per-site-scaled storage of the inner basis and stencil input)")
+    ap.add_argument("--variants", default="f32,f16,bf16",
+                    help="other inner precisions timed and reported beside the headline")
+    ap.add_argument("--variant-steps", type=int, default=2)
+    ap.add_argument("--no-accuracy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the noise solves shard "
@@ -227,10 +267,19 @@ def main():
     path = Path(ctx, cfg, args)
     path.setup()
     print("[bench] setup %s" % json.dumps(path.setup_times), file=sys.stderr, flush=True)
-    dt, stats, kt = run_steps(path, "f32", args.steps, args.warmup)
+    dt, stats, kt = run_steps(path, args.inner, args.steps, args.warmup)
     n_solves = args.steps * args.rhs_block
     value = n_solves / dt
-    print("[bench] mixed: %d solves in %.3f s" % (n_solves, dt), file=sys.stderr, flush=True)
+    print("[bench] mixed (%s): %d solves in %.3f s" % (args.inner, n_solves, dt), file=sys.stderr, flush=True)
+    variants = {}
+    for v in [v for v in args.variants.split(",") if v and v != args.inner]:
+        dtv, stv, _ = run_steps(path, v, args.variant_steps, 1)
+        variants[v] = {"value": round(args.variant_steps * args.rhs_block / dtv, 4), "unit": "noise-solves/s",
+                       "steps": args.variant_steps,
+                       "matvecs_per_solve": float(np.mean([s["matvecs"] for s in stv])),
+                       "refinements": float(np.mean([s["refinements"] for s in stv])),
+                       "max_true_resid": max(s["true_resid"] for s in stv)}
+        print("[bench] variant %s %s" % (v, json.dumps(variants[v])), file=sys.stderr, flush=True)
     dt64, stats64, kt64 = run_steps(path, "f64", args.fp64_steps, 0)
     value64 = args.fp64_steps * args.rhs_block / dt64
     print("[bench] fp64: %d solves in %.3f s" % (args.fp64_steps * args.rhs_block, dt64), file=sys.stderr,
@@ -248,12 +297,16 @@ def main():
                for k, v in kt.items()}
     mv = float(np.mean([s["matvecs"] for s in stats]))
     mv64 = float(np.mean([s["matvecs"] for s in stats64]))
+    acc = None
+    if not args.no_accuracy:
+        acc = accuracy(path, [args.inner] + list(variants), cfg, kappa, U, not args.no_cpu_baseline)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, kappa, mv64, cfg["m"] - cfg["k"])
     line = {
-        "metric": "deflated noise-solves/s %s, mixed (FP32 inner, FP64 refinement) at 1e-10 true residual"
-                  % "x".join(map(str, dims)),
+        "metric": "deflated noise-solves/s %s, mixed (FP32 inner%s, FP64 refinement) at 1e-10 true residual"
+                  % ("x".join(map(str, dims)),
+                     "" if args.inner == "f32" else ", %s per-site-scaled storage" % args.inner.upper()),
         "value": round(value, 4), "unit": "noise-solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 2), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
@@ -261,7 +314,7 @@ def main():
                                "%d Z(4) noise per step, PS%d POLY%d Q=%d"
                                % (args.workload, "x".join(map(str, dims)), cfg["eps"], kappa, cfg["m"], cfg["k"],
                                   args.rhs_block, cfg["pert_order"], cfg["poly_degree"], cfg["n_hermitian"]),
-                   "rhs_block": args.rhs_block},
+                   "rhs_block": args.rhs_block, "inner": args.inner},
         "fp64": {"value": round(value64, 4), "unit": "noise-solves/s", "steps": args.fp64_steps,
                  "matvecs_per_solve": mv64, "reorth_per_solve": float(np.mean([s["reorth"] for s in stats64])),
                  "max_true_resid": max(s["true_resid"] for s in stats64)},
@@ -269,6 +322,8 @@ def main():
         "mixed": {"matvecs_per_solve": mv, "refinements": float(np.mean([s["refinements"] for s in stats])),
                   "reorth_per_solve": float(np.mean([s["reorth"] for s in stats])),
                   "max_true_resid": max(s["true_resid"] for s in stats)},
+        "variants": variants,
+        "accuracy": acc,
         "setup": {k: round(v, 3) for k, v in path.setup_times.items()},
         "end_to_end_200_noise_s": round(path.setup_times["total_s"] + 199.0 / value, 2),
         "kernels": kernels,

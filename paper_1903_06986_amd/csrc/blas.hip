@@ -343,28 +343,41 @@ __global__ void __launch_bounds__(kBlock)
 
 
 // ------------------------------------------------- 16-bit stored bases
-// Basis vectors stored as in half.h (payload words then per-site scales);
-// the vector they act on stays FP32.  Flat element index idx = comp * Vh
-// + site; each lane tracks its site index incrementally.
+// Basis vectors stored as in half.h (payload words [12][Vh], then per-site
+// scales); the vector they act on stays FP32.  Site-oriented: every lane
+// owns two adjacent sites (Vh is even for even extents), so each
+// component load is one 8-byte payload word pair (16 bytes of FP32 for
+// the other operand) and each site's scale is loaded once.
+struct Pair {
+  cx<float> a, b;
+};
+__device__ inline Pair ldpair(const cx<float> *p) {
+  const float4 v = *reinterpret_cast<const float4 *>(p);
+  return Pair{mk(v.x, v.y), mk(v.z, v.w)};
+}
+__device__ inline void stpair(cx<float> *p, cx<float> a, cx<float> b) {
+  *reinterpret_cast<float4 *>(p) = make_float4(a.re, a.im, b.re, b.im);
+}
 template <HKind K>
-__device__ inline cx<double> ldh(const uint32_t *v, size_t n, size_t idx, size_t site) {
-  const cx<float> q = Codec<K>::unpack(v[idx]);
-  const float sc = __uint_as_float(v[n + site]);
-  return mk<double>(double(sc * q.re), double(sc * q.im));
+__device__ inline void ldhpair(const uint32_t *v, size_t Vh, size_t s2, int comp, float2 sc,
+                               cx<float> &a, cx<float> &b) {
+  const uint2 q = *reinterpret_cast<const uint2 *>(v + comp * Vh + s2);
+  const cx<float> qa = Codec<K>::unpack(q.x), qb = Codec<K>::unpack(q.y);
+  a = mk(sc.x * qa.re, sc.x * qa.im);
+  b = mk(sc.y * qb.re, sc.y * qb.im);
+}
+template <HKind K>
+__device__ inline float2 ldscale(const uint32_t *v, size_t Vh, size_t s2) {
+  const uint2 u = *reinterpret_cast<const uint2 *>(v + 12 * Vh + s2);
+  return make_float2(__uint_as_float(u.x), __uint_as_float(u.y));
 }
 
-__device__ inline size_t step_site(size_t site, size_t d, size_t Vh) {
-  site += d;
-  while (site >= Vh) site -= Vh;
-  return site;
-}
-
+// Partial dot products per wave: part[r][wave chunk][j] (as k_mdot_part).
 template <HKind K>
 __global__ void __launch_bounds__(kBlock)
     k_hmdot_part(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
-                 const cx<float> *__restrict__ w, size_t w_rs, size_t n, size_t Vh,
+                 const cx<float> *__restrict__ w, size_t w_rs, size_t Vh,
                  double *__restrict__ part, const int *__restrict__ flag) {
-  constexpr int E = 16, WC = 64 * E;
   const int lane = threadIdx.x & 63;
   const int r = blockIdx.y;
   if (flag && flag[r] == 0) return;
@@ -372,29 +385,34 @@ __global__ void __launch_bounds__(kBlock)
   const size_t chunk = size_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
   V += r * V_rs;
   w += r * w_rs;
-  const size_t base = chunk * WC + lane;
-  cx<double> wv[E];
-  size_t st[E];
-  size_t site = base % Vh;
+  const size_t s2 = (chunk * 64 + lane) * 2;  // first of the lane's two sites
+  const bool on = s2 < Vh;
+  cx<float> wa[12], wb[12];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    size_t idx = base + size_t(e) * 64;
-    wv[e] = idx < n ? ld64(w + idx) : mk<double>(0, 0);
-    st[e] = site;
-    site = step_site(site, 64, Vh);
+  for (int c = 0; c < 12; ++c) {
+    Pair pw = on ? ldpair(w + c * Vh + s2) : Pair{mk(0.f, 0.f), mk(0.f, 0.f)};
+    wa[c] = pw.a;
+    wb[c] = pw.b;
   }
   double *po = part + (size_t(r) * nwch + chunk) * size_t(J) * 2;
   for (int j = 0; j < J; ++j) {
-    double a0 = 0, b0 = 0;
     const uint32_t *v0 = V + size_t(j) * ldv;
+    double a0 = 0, b0 = 0;
+    if (on) {
+      const float2 sc = ldscale<K>(v0, Vh, s2);
+      float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;  // per-site sums of 12 products
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      size_t idx = base + size_t(e) * 64;
-      if (idx < n) {
-        cx<double> p0 = cmulc(ldh<K>(v0, n, idx, st[e]), wv[e]);
-        a0 += p0.re;
-        b0 += p0.im;
+      for (int c = 0; c < 12; ++c) {
+        cx<float> va, vb;
+        ldhpair<K>(v0, Vh, s2, c, sc, va, vb);
+        const cx<float> pa = cmulc(va, wa[c]), pb = cmulc(vb, wb[c]);
+        ar += pa.re;
+        ai += pa.im;
+        br += pb.re;
+        bi += pb.im;
       }
+      a0 = double(ar) + double(br);
+      b0 = double(ai) + double(bi);
     }
     a0 = wave_sum(a0);
     b0 = wave_sum(b0);
@@ -405,58 +423,49 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// w -= sum_j V_j coef_j, optional |w|^2 partials.  FP32 accumulation: the
+// result is stored in FP32 and the basis carries 16-bit rounding, so FP64
+// sums would buy nothing here (the coefficients come from FP64 dots).
 template <HKind K>
 __global__ void __launch_bounds__(kBlock)
     k_hmaxpy(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
              const cx<double> *__restrict__ coef, size_t coef_rs, cx<float> *__restrict__ w,
-             size_t w_rs, size_t n, size_t Vh, double *__restrict__ part,
-             const int *__restrict__ flag) {
+             size_t w_rs, size_t Vh, double *__restrict__ part, const int *__restrict__ flag) {
   __shared__ double sh[1][kWaves];
   const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
   if (flag && flag[r] == 0) return;
   V += r * V_rs;
   w += r * w_rs;
   coef += r * coef_rs;
-  const size_t base = size_t(b) * ACH + threadIdx.x;
-  cx<double> acc[AEPT];
-  size_t st[AEPT];
-  size_t site = base % Vh;
+  const size_t s2 = (size_t(b) * kBlock + threadIdx.x) * 2;
+  const bool on = s2 < Vh;
+  double nrm[1] = {0};
+  if (on) {
+    cx<float> aa[12], ab[12];
 #pragma unroll
-  for (int e = 0; e < AEPT; ++e) {
-    size_t idx = base + size_t(e) * kBlock;
-    acc[e] = idx < n ? ld64(w + idx) : mk<double>(0, 0);
-    st[e] = site;
-    site = step_site(site, kBlock, Vh);
-  }
-  int j = 0;
-  for (; j + 2 <= J; j += 2) {
-    const cx<double> c0 = coef[j], c1 = coef[j + 1];
-    const uint32_t *v = V + size_t(j) * ldv;
+    for (int c = 0; c < 12; ++c) {
+      Pair pw = ldpair(w + c * Vh + s2);
+      aa[c] = pw.a;
+      ab[c] = pw.b;
+    }
+    for (int j = 0; j < J; ++j) {
+      const cx<double> cd = coef[j];
+      const cx<float> cj = mk<float>(float(cd.re), float(cd.im));
+      const uint32_t *v0 = V + size_t(j) * ldv;
+      const float2 sc = ldscale<K>(v0, Vh, s2);
 #pragma unroll
-    for (int e = 0; e < AEPT; ++e) {
-      size_t idx = base + size_t(e) * kBlock;
-      if (idx < n) {
-        cx<double> x0 = ldh<K>(v, n, idx, st[e]), x1 = ldh<K>(v + ldv, n, idx, st[e]);
-        acc[e] = acc[e] - (x0 * c0 + x1 * c1);
+      for (int c = 0; c < 12; ++c) {
+        cx<float> va, vb;
+        ldhpair<K>(v0, Vh, s2, c, sc, va, vb);
+        aa[c] = aa[c] - va * cj;
+        ab[c] = ab[c] - vb * cj;
       }
     }
-  }
-  for (; j < J; ++j) {
-    const cx<double> c0 = coef[j];
 #pragma unroll
-    for (int e = 0; e < AEPT; ++e) {
-      size_t idx = base + size_t(e) * kBlock;
-      if (idx < n) acc[e] = acc[e] - ldh<K>(V + size_t(j) * ldv, n, idx, st[e]) * c0;
-    }
-  }
-  double nrm[1] = {0};
-#pragma unroll
-  for (int e = 0; e < AEPT; ++e) {
-    size_t idx = base + size_t(e) * kBlock;
-    if (idx < n) {
-      const cx<float> stv = mk<float>(float(acc[e].re), float(acc[e].im));
-      stc(w + idx, stv);
-      nrm[0] += double(stv.re) * double(stv.re) + double(stv.im) * double(stv.im);
+    for (int c = 0; c < 12; ++c) {
+      stpair(w + c * Vh + s2, aa[c], ab[c]);
+      nrm[0] += double(aa[c].re) * aa[c].re + double(aa[c].im) * aa[c].im + double(ab[c].re) * ab[c].re +
+                double(ab[c].im) * ab[c].im;  // of the stored values
     }
   }
   if (part) {
@@ -465,36 +474,38 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// Y_r += alpha * V_r C_r for one column per right-hand side (nb = 1 per r).
 template <HKind K>
 __global__ void __launch_bounds__(kBlock)
-    k_hgemm_nn(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
-               const cx<double> *__restrict__ C, size_t ldc, size_t C_rs, cx<float> *__restrict__ Y,
-               size_t ldy, size_t Y_rs, int nb, size_t n, size_t Vh, double alpha) {
+    k_hgemv(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
+            const cx<double> *__restrict__ C, size_t C_rs, cx<float> *__restrict__ Y, size_t Y_rs,
+            size_t Vh, double alpha) {
   const int r = blockIdx.y;
+  const size_t s2 = (size_t(blockIdx.x) * kBlock + threadIdx.x) * 2;
+  if (s2 >= Vh) return;
   V += r * V_rs;
   C += r * C_rs;
   Y += r * Y_rs;
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += size_t(gridDim.x) * blockDim.x) {
-    const size_t site = i % Vh;
-    for (int b0 = 0; b0 < nb; b0 += NBT) {
-      cx<double> acc[NBT];
+  cx<float> aa[12], ab[12];
 #pragma unroll
-      for (int t = 0; t < NBT; ++t) acc[t] = mk<double>(0, 0);
-      for (int j = 0; j < J; ++j) {
-        cx<double> v = ldh<K>(V + size_t(j) * ldv, n, i, site);
+  for (int c = 0; c < 12; ++c) aa[c] = ab[c] = mk(0.f, 0.f);
+  for (int j = 0; j < J; ++j) {
+    const cx<double> cd = C[j];
+    const cx<float> cj = mk<float>(float(alpha * cd.re), float(alpha * cd.im));
+    const uint32_t *v0 = V + size_t(j) * ldv;
+    const float2 sc = ldscale<K>(v0, Vh, s2);
 #pragma unroll
-        for (int t = 0; t < NBT; ++t)
-          if (b0 + t < nb) acc[t] = acc[t] + v * C[j + ldc * size_t(b0 + t)];
-      }
-#pragma unroll
-      for (int t = 0; t < NBT; ++t)
-        if (b0 + t < nb) {
-          cx<float> *yp = Y + size_t(b0 + t) * ldy + i;
-          cx<double> y = ld64(yp) + alpha * acc[t];
-          stc(yp, mk<float>(float(y.re), float(y.im)));
-        }
+    for (int c = 0; c < 12; ++c) {
+      cx<float> va, vb;
+      ldhpair<K>(v0, Vh, s2, c, sc, va, vb);
+      aa[c] = aa[c] + va * cj;
+      ab[c] = ab[c] + vb * cj;
     }
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    Pair y = ldpair(Y + c * Vh + s2);
+    stpair(Y + c * Vh + s2, y.a + aa[c], y.b + ab[c]);
   }
 }
 
@@ -707,14 +718,15 @@ void hmulti_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, cons
                 size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag) {
   if (J <= 0 || nrhs <= 0) return;
   constexpr HKind K = static_cast<HKind>(KIND);
-  constexpr size_t BCH = size_t(64 * 16) * kWaves;
-  const int ngrid = int((n + BCH - 1) / BCH);
+  const size_t Vh = n / 12;
+  const size_t per_block = size_t(kBlock) * 2;  // sites
+  const int ngrid = int((Vh + per_block - 1) / per_block);
   const int nblk = ngrid * kWaves;
   double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * J * 2 * sizeof(double)));
   Timed tm(c, LQCD_KC_DOT, flag ? 0.0 : (J * hbytes(n) + n * sizeof(cx<float>)) * nrhs);
   hipLaunchKernelGGL((k_hmdot_part<K>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const uint32_t *>(V), ldv, V_rs, J, static_cast<const cx<float> *>(w),
-                     w_rs, n, n / 12, part, flag);
+                     w_rs, Vh, part, flag);
   LQCD_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_mdot_final, dim3(J, nrhs), dim3(kBlock), 0, c->stream, part, nblk, J,
                      reinterpret_cast<cx<double> *>(out), out_rs, flag);
@@ -727,14 +739,15 @@ void hmulti_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, con
                  const int *flag) {
   if (nrhs <= 0) return;
   constexpr HKind K = static_cast<HKind>(KIND);
-  const int nblk = int((n + ACH - 1) / ACH);
+  const size_t Vh = n / 12;
+  const int nblk = int((Vh + 2 * kBlock - 1) / (2 * kBlock));
   double *part = nullptr;
   if (norm2_out) part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * sizeof(double)));
   Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + 2.0 * n * sizeof(cx<float>)) * nrhs);
   hipLaunchKernelGGL((k_hmaxpy<K>), dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const uint32_t *>(V), ldv, V_rs, J,
                      reinterpret_cast<const cx<double> *>(coef), coef_rs, static_cast<cx<float> *>(w),
-                     w_rs, n, n / 12, part, flag);
+                     w_rs, Vh, part, flag);
   LQCD_HIP(hipGetLastError());
   if (norm2_out) {
     hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(kBlock), 0, c->stream, part, nblk, norm2_out, flag);
@@ -748,12 +761,16 @@ void hgemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const 
               double alpha) {
   if (nb <= 0 || nrhs <= 0) return;
   constexpr HKind K = static_cast<HKind>(KIND);
+  const size_t Vh = n / 12;
   Timed tm(c, LQCD_KC_GEMM, (J * hbytes(n) + 2.0 * nb * n * sizeof(cx<float>)) * nrhs);
-  hipLaunchKernelGGL((k_hgemm_nn<K>), dim3(grid_elems(n), nrhs), dim3(kBlock), 0, c->stream,
-                     static_cast<const uint32_t *>(V), ldv, V_rs, J,
-                     reinterpret_cast<const cx<double> *>(C), ldc, C_rs, static_cast<cx<float> *>(Y),
-                     ldy, Y_rs, nb, n, n / 12, alpha);
-  LQCD_HIP(hipGetLastError());
+  const unsigned g = unsigned((Vh + 2 * kBlock - 1) / (2 * kBlock));
+  for (int b = 0; b < nb; ++b) {
+    hipLaunchKernelGGL((k_hgemv<K>), dim3(g, nrhs), dim3(kBlock), 0, c->stream,
+                       static_cast<const uint32_t *>(V), ldv, V_rs, J,
+                       reinterpret_cast<const cx<double> *>(C) + ldc * size_t(b), C_rs,
+                       static_cast<cx<float> *>(Y) + ldy * size_t(b), Y_rs, Vh, alpha);
+    LQCD_HIP(hipGetLastError());
+  }
 }
 
 template <int KIND>

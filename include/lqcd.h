@@ -279,8 +279,21 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
 /* Launch-shape tuning.  LQCD_TUNE_HOP_NB64 / LQCD_TUNE_HOP_NB32: the
  * largest number of right-hand sides (1, 2, 4 or 8) that the stencil maps
  * onto adjacent lanes to share link loads, per precision (defaults 2 and
- * 1).  Values are per context; EINVAL for other values. */
-typedef enum { LQCD_TUNE_HOP_NB64 = 0, LQCD_TUNE_HOP_NB32 = 1 } lqcd_tune_param;
+ * 1).  LQCD_TUNE_HOP_TILE64 / LQCD_TUNE_HOP_TILE32: 1 (default) lets
+ * launches with at least 8 (FP64) or 4 (FP32) right-hand sides use the
+ * link-tiled stencil (links staged in LDS per tile of sites and reused by
+ * every right-hand side), 0 keeps the lane-grouped form.
+ * LQCD_TUNE_HOP_ORDER: workgroup order of the lane-grouped form, 0
+ * (default) = right-hand-side groups of a site block back to back, 1 =
+ * site blocks of a right-hand side back to back.  Values are per context;
+ * EINVAL for other values. */
+typedef enum {
+  LQCD_TUNE_HOP_NB64 = 0,
+  LQCD_TUNE_HOP_NB32 = 1,
+  LQCD_TUNE_HOP_TILE64 = 2,
+  LQCD_TUNE_HOP_TILE32 = 3,
+  LQCD_TUNE_HOP_ORDER = 4
+} lqcd_tune_param;
 lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 
 /* Thread-local description of the last non-OK status. */

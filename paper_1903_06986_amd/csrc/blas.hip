@@ -574,7 +574,7 @@ void multi_dot_impl(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, 
   const int nblk = ngrid * kWaves;  // wave chunks = partial sums per rhs and j
   double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * J * 2 * sizeof(double)));
   Timed tm(c, cls, bytes);
-  hipLaunchKernelGGL((k_mdot_part<R>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
+  LQCD_TLAUNCH(tm, true, true, (k_mdot_part<R>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const cx<R> *>(V), ldv, V_rs, J, static_cast<const cx<R> *>(w),
                      w_rs, n, part, flag);
   LQCD_HIP(hipGetLastError());
@@ -602,7 +602,7 @@ void multi_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, cons
   double *part = nullptr;
   if (norm2_out) part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * sizeof(double)));
   Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : double(J + 2) * n * nrhs * sizeof(cx<R>));
-  hipLaunchKernelGGL(k_maxpy<R>, dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
+  LQCD_TLAUNCH(tm, true, true, (k_maxpy<R>), dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const cx<R> *>(V), ldv, V_rs, J,
                      reinterpret_cast<const cx<double> *>(coef), coef_rs, static_cast<cx<R> *>(w),
                      w_rs, n, part, flag);
@@ -658,7 +658,7 @@ void gemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const c
              double alpha) {
   if (nb <= 0 || nrhs <= 0) return;
   Timed tm(c, LQCD_KC_GEMM, double(J + 2 * nb) * n * nrhs * sizeof(cx<R>));
-  hipLaunchKernelGGL(k_gemm_nn<R>, dim3(grid_elems(n), nrhs), dim3(kBlock), 0, c->stream,
+  LQCD_TLAUNCH(tm, true, true, (k_gemm_nn<R>), dim3(grid_elems(n), nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const cx<R> *>(V), ldv, V_rs, J,
                      reinterpret_cast<const cx<double> *>(C), ldc, C_rs, static_cast<cx<R> *>(Y),
                      ldy, Y_rs, nb, n, alpha);
@@ -684,7 +684,7 @@ void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size
   LQCD_CHECK(shm <= 64 * 1024, LQCD_EINVAL, "recombine: basis of %d vectors too large", Jin);
   unsigned nb = unsigned((n + E - 1) / E);
   Timed tm(c, LQCD_KC_GEMM, double(Jin + Jout) * n * sizeof(cx<R>));
-  hipLaunchKernelGGL(k_recombine<R>, dim3(nb), dim3(kBlock), shm, c->stream,
+  LQCD_TLAUNCH(tm, true, true, (k_recombine<R>), dim3(nb), dim3(kBlock), shm, c->stream,
                      static_cast<cx<R> *>(V), ldv, Jin, reinterpret_cast<const cx<double> *>(P),
                      ldp, Jout, n, E);
   LQCD_HIP(hipGetLastError());
@@ -724,7 +724,7 @@ void hmulti_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, cons
   const int nblk = ngrid * kWaves;
   double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * J * 2 * sizeof(double)));
   Timed tm(c, LQCD_KC_DOT, flag ? 0.0 : (J * hbytes(n) + n * sizeof(cx<float>)) * nrhs);
-  hipLaunchKernelGGL((k_hmdot_part<K>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
+  LQCD_TLAUNCH(tm, true, true, (k_hmdot_part<K>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const uint32_t *>(V), ldv, V_rs, J, static_cast<const cx<float> *>(w),
                      w_rs, Vh, part, flag);
   LQCD_HIP(hipGetLastError());
@@ -744,7 +744,7 @@ void hmulti_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, con
   double *part = nullptr;
   if (norm2_out) part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * sizeof(double)));
   Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + 2.0 * n * sizeof(cx<float>)) * nrhs);
-  hipLaunchKernelGGL((k_hmaxpy<K>), dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
+  LQCD_TLAUNCH(tm, true, true, (k_hmaxpy<K>), dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const uint32_t *>(V), ldv, V_rs, J,
                      reinterpret_cast<const cx<double> *>(coef), coef_rs, static_cast<cx<float> *>(w),
                      w_rs, Vh, part, flag);
@@ -765,7 +765,7 @@ void hgemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const 
   Timed tm(c, LQCD_KC_GEMM, (J * hbytes(n) + 2.0 * nb * n * sizeof(cx<float>)) * nrhs);
   const unsigned g = unsigned((Vh + 2 * kBlock - 1) / (2 * kBlock));
   for (int b = 0; b < nb; ++b) {
-    hipLaunchKernelGGL((k_hgemv<K>), dim3(g, nrhs), dim3(kBlock), 0, c->stream,
+    LQCD_TLAUNCH(tm, b == 0, b == nb - 1, (k_hgemv<K>), dim3(g, nrhs), dim3(kBlock), 0, c->stream,
                        static_cast<const uint32_t *>(V), ldv, V_rs, J,
                        reinterpret_cast<const cx<double> *>(C) + ldc * size_t(b), C_rs,
                        static_cast<cx<float> *>(Y) + ldy * size_t(b), Y_rs, Vh, alpha);

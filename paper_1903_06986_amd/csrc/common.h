@@ -1,6 +1,7 @@
 // Internal declarations of the gfx950 library (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <complex>
@@ -134,6 +135,8 @@ struct lqcd_ctx {
   lqcd::DevBuf small[2]; // solver small matrices
   lqcd::KTimer timer;
   int hop_nb[2] = {2, 1};  // largest lane-grouped right-hand-side count: FP64, FP32
+  int hop_tile[2] = {1, 1};  // link-tiled stencil for many right-hand sides: FP64, FP32
+  int hop_order = 0;         // lane-grouped stencil block order: 0 rhs-group fastest, 1 site fastest
   ~lqcd_ctx();
 };
 
@@ -177,15 +180,34 @@ template <int KIND>
 void apply_schur_h(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin,
                    size_t sout, size_t stmp);
 
-// context.cpp: event timing of one launch (no-op unless the timer is on)
+// context.cpp: event timing of one launch (no-op unless the timer is on).
+// The events ride on the kernel dispatch itself (hipExtLaunchKernelGGL),
+// so the elapsed time is the kernel's own start-to-end time; launches go
+// through LQCD_TLAUNCH.  A slot whose scope launched nothing is dropped.
 int timer_start(lqcd_ctx *c, int cls, double bytes);
-void timer_stop(lqcd_ctx *c, int slot);
+void timer_stop(lqcd_ctx *c, int slot, bool used);
+hipEvent_t timer_event(lqcd_ctx *c, int slot, int which);
 struct Timed {
   lqcd_ctx *c;
   int slot;
+  bool used = false;
   Timed(lqcd_ctx *cc, int cls, double bytes) : c(cc), slot(timer_start(cc, cls, bytes)) {}
-  ~Timed() { timer_stop(c, slot); }
+  ~Timed() { timer_stop(c, slot, used); }
+  hipEvent_t ev(int which) const { return timer_event(c, slot, which); }
 };
+
+// Launch under a Timed scope: `first` attaches the start event, `last` the
+// stop event (a scope with several launches spans first to last).
+#define LQCD_TLAUNCH(tm, first, last, kern, grid, block, shm, stream, ...)                        \
+  do {                                                                                           \
+    if ((tm).slot >= 0) {                                                                        \
+      (tm).used = true;                                                                          \
+      hipExtLaunchKernelGGL(kern, grid, block, shm, stream, (first) ? (tm).ev(0) : nullptr,      \
+                            (last) ? (tm).ev(1) : nullptr, 0, __VA_ARGS__);                      \
+    } else {                                                                                     \
+      hipLaunchKernelGGL(kern, grid, block, shm, stream, __VA_ARGS__);                           \
+    }                                                                                            \
+  } while (0)
 
 // fields.hip -----------------------------------------------------------
 template <class R>

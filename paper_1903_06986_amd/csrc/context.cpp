@@ -99,8 +99,9 @@ constexpr int kTimerSlots = 4096;
 void harvest(lqcd_ctx *c) {
   KTimer &T = c->timer;
   if (T.used == 0) return;
-  LQCD_HIP(hipEventSynchronize(T.ev[2 * (T.used - 1) + 1]));
+  LQCD_HIP(hipStreamSynchronize(c->stream));
   for (int i = 0; i < T.used; ++i) {
+    if (T.cls[i] < 0) continue;  // scope launched nothing
     float ms = 0;
     LQCD_HIP(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
     T.ms[T.cls[i]] += ms;
@@ -124,14 +125,14 @@ int timer_start(lqcd_ctx *c, int cls, double bytes) {
   int s = T.used++;
   T.cls[s] = cls;
   T.bytes[s] = bytes;
-  LQCD_HIP(hipEventRecord(T.ev[2 * s], c->stream));
   return s;
 }
 
-void timer_stop(lqcd_ctx *c, int slot) {
-  if (slot < 0) return;
-  (void)hipEventRecord(c->timer.ev[2 * slot + 1], c->stream);
+void timer_stop(lqcd_ctx *c, int slot, bool used) {
+  if (slot >= 0 && !used) c->timer.cls[slot] = -1;
 }
+
+hipEvent_t timer_event(lqcd_ctx *c, int slot, int which) { return c->timer.ev[2 * slot + which]; }
 
 }  // namespace lqcd
 
@@ -167,11 +168,25 @@ extern "C" lqcd_status lqcd_timer_read(lqcd_ctx *c, int k, double *ms, double *b
 extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int value) {
   return guarded([&] {
     LQCD_CHECK(c, LQCD_EINVAL, "lqcd_tune_set: null context");
-    LQCD_CHECK(param == LQCD_TUNE_HOP_NB64 || param == LQCD_TUNE_HOP_NB32, LQCD_EINVAL,
-               "lqcd_tune_set: unknown parameter %d", int(param));
-    LQCD_CHECK(value == 1 || value == 2 || value == 4 || value == 8, LQCD_EINVAL,
-               "lqcd_tune_set: right-hand-side group must be 1, 2, 4 or 8");
-    c->hop_nb[param == LQCD_TUNE_HOP_NB64 ? 0 : 1] = value;
+    switch (param) {
+      case LQCD_TUNE_HOP_NB64:
+      case LQCD_TUNE_HOP_NB32:
+        LQCD_CHECK(value == 1 || value == 2 || value == 4 || value == 8, LQCD_EINVAL,
+                   "lqcd_tune_set: right-hand-side group must be 1, 2, 4 or 8");
+        c->hop_nb[param == LQCD_TUNE_HOP_NB64 ? 0 : 1] = value;
+        break;
+      case LQCD_TUNE_HOP_TILE64:
+      case LQCD_TUNE_HOP_TILE32:
+        LQCD_CHECK(value == 0 || value == 1, LQCD_EINVAL, "lqcd_tune_set: tiled stencil switch must be 0 or 1");
+        c->hop_tile[param == LQCD_TUNE_HOP_TILE64 ? 0 : 1] = value;
+        break;
+      case LQCD_TUNE_HOP_ORDER:
+        LQCD_CHECK(value == 0 || value == 1, LQCD_EINVAL, "lqcd_tune_set: block order must be 0 or 1");
+        c->hop_order = value;
+        break;
+      default:
+        LQCD_CHECK(false, LQCD_EINVAL, "lqcd_tune_set: unknown parameter %d", int(param));
+    }
   });
 }
 

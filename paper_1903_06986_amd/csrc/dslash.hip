@@ -187,15 +187,18 @@ template <class R, bool G5IN, bool G5OUT, bool SELF, int NB, class SrcIn, class 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8)))
     k_hop(Geom g, int p, const cx<R> *U, SrcIn in,
           SrcSelf self, cx<R> *out, cx<R> alpha, R beta,
-          size_t in_stride, size_t self_stride, size_t out_stride, int nrhs, int xq, int ngr) {
+          size_t in_stride, size_t self_stride, size_t out_stride, int nrhs, int xq, int ngr,
+          int nbx, int site_major) {
   // XCD-aware block order: workgroups are dispatched round-robin over the
   // 8 XCDs, so hardware block h runs on XCD h % 8.  Logical block
-  // (h % 8) * xq + h / 8 gives every XCD one contiguous range; within it the
-  // right-hand-side group varies fastest, so all groups of a site block run
-  // back to back on one XCD (sharing its links in L2) and consecutive site
-  // blocks, whose neighbours overlap, follow each other.
+  // (h % 8) * xq + h / 8 gives every XCD one contiguous range.  Within it
+  // either the right-hand-side group varies fastest (all groups of a site
+  // block run back to back on one XCD and share its links in L2), or, with
+  // site_major, the site block does (an XCD sweeps whole right-hand sides,
+  // so the window of neighbouring timeslices stays in its L2 while the
+  // links are shared through the last-level cache).
   const int L = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
-  const int bx = L / ngr, grp = L % ngr;
+  const int bx = site_major ? L % nbx : L / ngr, grp = site_major ? L / nbx : L % ngr;
   const int i = bx * (kBlock / NB) + threadIdx.x / NB;
   const int rr = grp * NB + threadIdx.x % NB;
   if (i >= g.Vh || rr >= nrhs) return;
@@ -259,17 +262,139 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
     }
 }
 
+// Link-tiled form for many right-hand sides: a workgroup owns T
+// consecutive output sites, stages their 8 links (4 forward at the sites,
+// 4 backward at the neighbours x - mu) in LDS once, then applies the
+// stencil to every right-hand side, RS = 256 / T of them at a time.  The
+// lane index is the site within the tile, so each spinor access of a wave
+// is one contiguous run of sites, and the links cross HBM once per launch
+// instead of once per right-hand side.
+template <class R, int MU, bool G5IN, class Src>
+__device__ inline void hop_dir_tile(cx<R> acc[4][3], const cx<R> *sU, int T, const Src &in, int nf,
+                                    int nb, size_t Vh) {
+  Half<R> h, g;
+  project<R, MU, true, G5IN>(in, nf, Vh, h);
+  link_mul<R>(sU + (MU * 9) * T, T, h, g);
+  accumulate<R, MU, true>(acc, g);
+  fence(acc);
+  project<R, MU, false, G5IN>(in, nb, Vh, h);
+  link_dag_mul<R>(sU + ((4 + MU) * 9) * T, T, h, g);
+  accumulate<R, MU, false>(acc, g);
+  fence(acc);
+}
+
+template <class R, bool G5IN, bool G5OUT, bool SELF, int T, class SrcIn, class SrcSelf>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8)))
+    k_hop_tile(Geom g, int p, const cx<R> *U, SrcIn in, SrcSelf self, cx<R> *out, cx<R> alpha,
+               R beta, size_t in_stride, size_t self_stride, size_t out_stride, int nrhs, int xq) {
+  constexpr int RS = kBlock / T;
+  __shared__ cx<R> sU[8 * 9 * T];  // [direction: 4 forward, 4 backward][entry][site]
+  // XCD-aware tile order (as in k_hop): each XCD walks one contiguous range
+  const int tile = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
+  const int i0 = tile * T;
+  if (i0 >= g.Vh) return;  // whole workgroup: padding of the grid
+  const size_t Vh = size_t(g.Vh);
+  const int il = threadIdx.x % T, slot = threadIdx.x / T;
+  const int i = i0 + il;
+  const bool site_ok = i < g.Vh;
+  const int Lxh = g.Lxh, Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+  int nf[4] = {0, 0, 0, 0}, nb[4] = {0, 0, 0, 0};
+  if (site_ok) {
+    const int xh = i % Lxh;
+    int r = i / Lxh;
+    const int y = r % Ly;
+    r /= Ly;
+    const int z = r % Lz;
+    const int t = r / Lz;
+    const int x = 2 * xh + ((p + y + z + t) & 1);
+    const int rowb = i - xh;
+    nf[0] = rowb + (((x + 1 == Lx) ? 0 : x + 1) >> 1);
+    nb[0] = rowb + (((x == 0) ? Lx - 1 : x - 1) >> 1);
+    int st = Lxh;
+    nf[1] = (y == Ly - 1) ? i - st * (Ly - 1) : i + st;
+    nb[1] = (y == 0) ? i + st * (Ly - 1) : i - st;
+    st *= Ly;
+    nf[2] = (z == Lz - 1) ? i - st * (Lz - 1) : i + st;
+    nb[2] = (z == 0) ? i + st * (Lz - 1) : i - st;
+    st *= Lz;
+    nf[3] = (t == Lt - 1) ? i - st * (Lt - 1) : i + st;
+    nb[3] = (t == 0) ? i + st * (Lt - 1) : i - st;
+    // stage: slot s loads the (direction, entry) pairs s, s + RS, ...
+    for (int q = slot; q < 72; q += RS) {
+      const int d = q / 9, e = q % 9;
+      const size_t src = d < 4 ? ((size_t(p) * 4 + d) * 9 + e) * Vh + i
+                               : ((size_t(1 - p) * 4 + (d - 4)) * 9 + e) * Vh + nb[d - 4];
+      sU[q * T + il] = U[src];
+    }
+  }
+  __syncthreads();
+  if (!site_ok) return;
+  const cx<R> *su = sU + il;
+#pragma unroll 1
+  for (int rr = slot; rr < nrhs; rr += RS) {
+    const size_t rhs = rr;
+    const SrcIn inr = in.at(rhs * in_stride);
+    cx<R> acc[4][3];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[s][c] = mk<R>(0, 0);
+    // Neighbour indices pass through an empty asm each iteration: otherwise
+    // the compiler hoists all 96 per-component address offsets out of the
+    // right-hand-side loop and the register file overflows.
+    int nfl[4], nbl[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      nfl[d] = nf[d];
+      nbl[d] = nb[d];
+      asm volatile("" : "+v"(nfl[d]), "+v"(nbl[d]));
+    }
+    hop_dir_tile<R, 0, G5IN>(acc, su, T, inr, nfl[0], nbl[0], Vh);
+    hop_dir_tile<R, 1, G5IN>(acc, su, T, inr, nfl[1], nbl[1], Vh);
+    hop_dir_tile<R, 2, G5IN>(acc, su, T, inr, nfl[2], nbl[2], Vh);
+    hop_dir_tile<R, 3, G5IN>(acc, su, T, inr, nfl[3], nbl[3], Vh);
+    cx<R> *o = out + rhs * out_stride;
+    SrcSelf sr = self;
+    if (SELF) sr = self.at(rhs * self_stride);
+    const typename SrcSelf::Ctx ssc = SELF ? sr.site(i) : typename SrcSelf::Ctx{};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cx<R> v = beta * acc[s][c];
+        if (SELF) {
+          cx<R> w = sr.ld(ssc, i, s * 3 + c, Vh);
+          if (G5IN && s >= 2) w = -w;
+          v = v + alpha * w;
+        }
+        if (G5OUT && s >= 2) v = -v;
+        stc(o + (s * 3 + c) * Vh + i, v);
+      }
+  }
+}
+
+template <class R, bool A, bool B, bool C, int T, class SI, class SS>
+void launch_hop_tile(lqcd_ctx *c, Timed &tm, int p, const cx<R> *U, SI in, SS self, void *out,
+                     cdouble alpha, double beta, int nrhs, size_t si, size_t ss, size_t so) {
+  const Geom &g = c->g;
+  const int ntile = int((g.Vh + T - 1) / T);
+  const int xq = (ntile + 7) / 8;
+  LQCD_TLAUNCH(tm, true, true, (k_hop_tile<R, A, B, C, T, SI, SS>), dim3(8 * xq), dim3(kBlock), 0, c->stream, g, p,
+                     U, in, self, static_cast<cx<R> *>(out), mk<R>(R(alpha.real()), R(alpha.imag())),
+                     R(beta), si, ss, so, nrhs, xq);
+}
+
 template <class R, bool A, bool B, bool C, int NB, class SI, class SS>
-void launch_hop_nb(lqcd_ctx *c, int p, const cx<R> *U, SI in, SS self, void *out,
+void launch_hop_nb(lqcd_ctx *c, Timed &tm, int p, const cx<R> *U, SI in, SS self, void *out,
                    cdouble alpha, double beta, int nrhs, size_t si, size_t ss, size_t so) {
   const Geom &g = c->g;
   const int nbx = int(nblocks(g.Vh, kBlock / NB));
   const int ngr = (nrhs + NB - 1) / NB;
   const int xq = (nbx * ngr + 7) / 8;  // logical blocks per XCD (the grid is padded to 8 * xq)
   dim3 grid(8 * xq);
-  hipLaunchKernelGGL((k_hop<R, A, B, C, NB, SI, SS>), grid, dim3(kBlock), 0, c->stream, g, p, U, in,
+  LQCD_TLAUNCH(tm, true, true, (k_hop<R, A, B, C, NB, SI, SS>), grid, dim3(kBlock), 0, c->stream, g, p, U, in,
                      self, static_cast<cx<R> *>(out), mk<R>(R(alpha.real()), R(alpha.imag())), R(beta),
-                     si, ss, so, nrhs, xq, ngr);
+                     si, ss, so, nrhs, xq, ngr, nbx, c->hop_order);
 }
 
 // Bytes per site of one stored half field of a source type.
@@ -294,11 +419,15 @@ void launch_hop_src(lqcd_ctx *c, int p, SI in, SS self, void *out, cdouble alpha
   const double bytes = double(g.Vh) * (72.0 * sizeof(cx<R>) +
                                        nrhs * (SrcBytes<SI>::v + 12.0 * sizeof(cx<R>) + (C ? SrcBytes<SS>::v : 0.0)));
   Timed tm(c, std::is_same<R, double>::value ? LQCD_KC_HOP64 : LQCD_KC_HOP32, bytes);
-  const int nbmax = c->hop_nb[std::is_same<R, double>::value ? 0 : 1];
-  if (nrhs >= 8 && nbmax >= 8) launch_hop_nb<R, A, B, C, 8>(c, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
-  else if (nrhs >= 4 && nbmax >= 4) launch_hop_nb<R, A, B, C, 4>(c, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
-  else if (nrhs >= 2 && nbmax >= 2) launch_hop_nb<R, A, B, C, 2>(c, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
-  else launch_hop_nb<R, A, B, C, 1>(c, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  const int pi = std::is_same<R, double>::value ? 0 : 1;
+  const int nbmax = c->hop_nb[pi];
+  constexpr int T = std::is_same<R, double>::value ? 32 : 64;  // 36 KiB of links per workgroup
+  if (c->hop_tile[pi] && nrhs >= kBlock / T)
+    launch_hop_tile<R, A, B, C, T>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else if (nrhs >= 8 && nbmax >= 8) launch_hop_nb<R, A, B, C, 8>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else if (nrhs >= 4 && nbmax >= 4) launch_hop_nb<R, A, B, C, 4>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else if (nrhs >= 2 && nbmax >= 2) launch_hop_nb<R, A, B, C, 2>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else launch_hop_nb<R, A, B, C, 1>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   LQCD_HIP(hipGetLastError());
 }
 

@@ -288,7 +288,7 @@ extern "C" lqcd_status loop_gradient(lqcd_ctx *c, const int *thetas, const doubl
       // once, the force written once
       const double bytes = double(g.V) * (2.0 * nrhs * 192.0 + 4 * 9 * 16.0 + (dlinks ? 4 * 8 * 16.0 : 0.0));
       Timed tm(c, LQCD_KC_FORCE, bytes);
-      hipLaunchKernelGGL(k_force, dim3(nb), dim3(kBlock), 0, c->stream, g,
+      LQCD_TLAUNCH(tm, true, true, k_force, dim3(nb), dim3(kBlock), 0, c->stream, g,
                          static_cast<const cx<double> *>(c->U64.ptr), Xs, Xa, nrhs,
                          c->kappa / nrhs, static_cast<cx<double> *>(dlinks), part);
       LQCD_HIP(hipGetLastError());

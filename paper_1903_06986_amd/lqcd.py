@@ -189,12 +189,11 @@ class Context:
 
     KERNEL_CLASSES = ("hop64", "hop32", "dot", "axpy", "gemm", "force")
 
-    def tune(self, hop_nb64=None, hop_nb32=None):
+    def tune(self, hop_nb64=None, hop_nb32=None, hop_tile64=None, hop_tile32=None, hop_order=None):
         """Set launch-shape parameters (see lqcd_tune_set)."""
-        if hop_nb64 is not None:
-            _check(lib().lqcd_tune_set(self.handle, 0, int(hop_nb64)))
-        if hop_nb32 is not None:
-            _check(lib().lqcd_tune_set(self.handle, 1, int(hop_nb32)))
+        for code, v in ((0, hop_nb64), (1, hop_nb32), (2, hop_tile64), (3, hop_tile32), (4, hop_order)):
+            if v is not None:
+                _check(lib().lqcd_tune_set(self.handle, code, int(v)))
 
     def timer(self, on):
         """Enable (and reset) or disable per-kernel-class event timing."""

@@ -257,6 +257,50 @@ lqcd_status loop_gradient(lqcd_ctx *ctx, const int *thetas_host, const double *w
                           const void *eta, const void *x, int nrhs, double *dkappa_host,
                           void *dlinks, lqcd_solve_stats *stats);
 
+/* ------------------------------------------------------------------ batching
+ * Several lattices solved together (one configuration per context; the
+ * paper solves one configuration at a time).  All contexts must live on one
+ * device and share one stream. */
+typedef struct lqcd_batch lqcd_batch;
+lqcd_status lqcd_batch_create(lqcd_ctx *const *ctxs, int nlat, lqcd_batch **out);
+lqcd_status lqcd_batch_destroy(lqcd_batch *batch);
+/* Workgroups of the persistent batched stencil launch (default 8192). */
+lqcd_status lqcd_batch_set_grid(lqcd_batch *batch, int workgroups);
+
+/* Deflated GMRES-Proj solves (Sec. 7) of every lattice's right-hand sides
+ * with FP32 inner solves in FP64 refinement (params->inner must be
+ * LQCD_F32), all lattices in lockstep: right-hand sides are taken
+ * params->rhs_block at a time from one queue over the lattices (uneven
+ * counts and sizes mix in a block); each inner operator application is
+ * one persistent launch over all of them, the Gram-Schmidt and projection
+ * kernels are batched likewise, and with use_graph != 0 each GMRES(m - k)
+ * cycle (or proj_m) runs as a captured hipGraph.  b[l], x[l]: device
+ * complex128 LEX [nrhs[l]][12 V_l]; defl[l]: deflation space of lattice l's
+ * even/odd system (gmresdr_solve with LQCD_OP_SCHUR on that context).
+ * stats: host array over all right-hand sides in lattice order, or NULL.
+ * Stopping rule, tolerances and ENOCONV as gmresdr_solve. */
+lqcd_status batch_solve(lqcd_batch *batch, const lqcd_solve_params *params, const void *const *b,
+                        void *const *x, const int *nrhs, lqcd_defl *const *defl, int use_graph,
+                        lqcd_solve_stats *stats);
+
+/* Autotuner: times trial batch_solve runs (captured cycles) for rhs_block
+ * in {4, 8, 16, 32} and persistent-stencil grids of {2048, 8192}
+ * workgroups, each on one block of right-hand sides drawn evenly from the
+ * lattices, and returns the fastest pair.  rate_host: optional host double
+ * [8] receiving the trial rates (right-hand sides per second, order:
+ * rhs_block major, grid minor; 0 for skipped pairs).  The batch's grid
+ * setting is left unchanged. */
+lqcd_status batch_autotune(lqcd_batch *batch, const lqcd_solve_params *params, const void *const *b,
+                           const int *nrhs, lqcd_defl *const *defl, int *best_rhs_block,
+                           int *best_grid, double *rate_host);
+
+/* The even/odd operator Mhat (Sec. 7) in FP32 on every right-hand side of
+ * every lattice in one persistent launch per half hop: in[l], out[l] device
+ * complex128 LEX [nrhs[l]][12 V_l] (even sites of out hold Mhat x_e, odd
+ * sites zero), as wilson_apply with LQCD_OP_SCHUR and LQCD_F32. */
+lqcd_status batch_wilson_apply(lqcd_batch *batch, const void *const *in, void *const *out,
+                               const int *nrhs);
+
 /* Kernel timing (measurement aid).  When enabled, the library brackets
  * every launch of the classes below with HIP events on the context stream
  * and accumulates, per class, the summed kernel duration, the number of

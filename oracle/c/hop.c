@@ -16,8 +16,11 @@
 
 typedef double _Complex cplx;
 
-void oracle_hop(const int dims[4], const cplx *U, const cplx *pm, const cplx *pp,
-                const cplx *psi, cplx *out, int nthreads) {
+/* parity < 0: every site; parity 0 / 1: only output sites with
+ * (x + y + z + t) % 2 == parity are computed, the others are set to zero
+ * (one block of the even/odd decomposition). */
+void oracle_hop_parity(const int dims[4], const cplx *U, const cplx *pm, const cplx *pp,
+                       const cplx *psi, cplx *out, int parity, int nthreads) {
   const int Lx = dims[0], Ly = dims[1], Lz = dims[2], Lt = dims[3];
   const long V = (long)Lx * Ly * Lz * Lt;
 #pragma omp parallel for num_threads(nthreads) schedule(static)
@@ -26,6 +29,11 @@ void oracle_hop(const int dims[4], const cplx *U, const cplx *pm, const cplx *pp
                 (int)(s / ((long)Lx * Ly * Lz))};
     const int L[4] = {Lx, Ly, Lz, Lt};
     cplx acc[4][3] = {{0}};
+    if (parity >= 0 && ((c[0] + c[1] + c[2] + c[3]) & 1) != parity) {
+      for (int sp = 0; sp < 4; ++sp)
+        for (int a = 0; a < 3; ++a) out[(s * 4 + sp) * 3 + a] = 0;
+      continue;
+    }
     for (int mu = 0; mu < 4; ++mu) {
       int f[4] = {c[0], c[1], c[2], c[3]}, b[4] = {c[0], c[1], c[2], c[3]};
       f[mu] = (c[mu] + 1) % L[mu];
@@ -55,4 +63,9 @@ void oracle_hop(const int dims[4], const cplx *U, const cplx *pm, const cplx *pp
     for (int sp = 0; sp < 4; ++sp)
       for (int a = 0; a < 3; ++a) out[(s * 4 + sp) * 3 + a] = acc[sp][a];
   }
+}
+
+void oracle_hop(const int dims[4], const cplx *U, const cplx *pm, const cplx *pp,
+                const cplx *psi, cplx *out, int nthreads) {
+  oracle_hop_parity(dims, U, pm, pp, psi, out, -1, nthreads);
 }

@@ -35,17 +35,24 @@ def _load():
         L = ctypes.CDLL(LIB)
         L.oracle_hop.argtypes = [ctypes.c_void_p] * 6 + [ctypes.c_int]
         L.oracle_hop.restype = None
+        L.oracle_hop_parity.argtypes = [ctypes.c_void_p] * 6 + [ctypes.c_int, ctypes.c_int]
+        L.oracle_hop_parity.restype = None
         _lib = L
     return _lib
 
 
-def hop_c(U, psi, threads=None):
-    """P psi for one field of shape (Lt, Lz, Ly, Lx, 4, 3)."""
+def hop_c(U, psi, threads=None, parity=None):
+    """P psi for one field of shape (Lt, Lz, Ly, Lx, 4, 3); with parity 0
+    or 1 only the output sites of that parity (the rest zero)."""
     Lt, Lz, Ly, Lx = psi.shape[:4]
     dims = np.array([Lx, Ly, Lz, Lt], dtype=np.int32)
     U = np.ascontiguousarray(U, dtype=np.complex128)
     psi = np.ascontiguousarray(psi, dtype=np.complex128)
     out = np.empty_like(psi)
     p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
-    _load().oracle_hop(p(dims), p(U), p(_PM), p(_PP), p(psi), p(out), int(threads or os.cpu_count() or 1))
+    nt = int(threads or os.cpu_count() or 1)
+    if parity is None:
+        _load().oracle_hop(p(dims), p(U), p(_PM), p(_PP), p(psi), p(out), nt)
+    else:
+        _load().oracle_hop_parity(p(dims), p(U), p(_PM), p(_PP), p(psi), p(out), int(parity), nt)
     return out

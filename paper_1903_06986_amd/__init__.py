@@ -6,4 +6,4 @@ The compute path is the C ABI of ``include/lqcd.h`` implemented in HIP
 (``csrc/``, built into ``liblqcd.so``); ``lqcd`` is its ctypes binding.
 """
 from . import lqcd  # noqa: F401
-from .lqcd import Context, Deflation, LqcdError, lib  # noqa: F401
+from .lqcd import Batch, Context, Deflation, LqcdError, lib  # noqa: F401

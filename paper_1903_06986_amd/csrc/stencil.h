@@ -1,0 +1,183 @@
+// Device building blocks of the Wilson hopping stencil (Sec. 5.1 Eqs.
+// (24)-(25)) on even/odd fields, shared by the single-lattice and the
+// batched kernels.
+//
+//   (P psi)(x) = sum_mu [ (1 - g_mu) U_mu(x) psi(x + mu)
+//                       + (1 + g_mu) U_mu(x - mu)^+ psi(x - mu) ]
+//
+// In the chiral basis (g_k = [[0, -i s_k], [i s_k, 0]], g_4 = [[0,1],[1,0]])
+// every (1 -+ g_mu) has rank 2: with psi = (u, l) in upper/lower spin
+// pairs, (1 - g_mu) psi = (h, R h) where h = u + i s_k l (h = u - l for
+// mu = t) and R = -i s_k (R = -1 for t); (1 + g_mu) psi = (h', R' h') with
+// h' = u - i s_k l (u + l), R' = +i s_k (+1).  The link therefore acts on a
+// two-spin "half spinor" only (6 complex), and the lower spins are rebuilt
+// from the product.
+//
+// Data layout (per right-hand side, per parity): component-major
+// [12][Vh] complex, component c = spin * 3 + colour, so that a wavefront
+// loading one component of 64 consecutive sites reads one contiguous
+// 1 KiB (FP64) segment.  Links: [parity][mu][9][Vh].
+#pragma once
+
+#include "common.h"
+#include "cplx.h"
+#include "half.h"
+
+namespace lqcd {
+namespace st {
+
+// Field sources of the stencil: plain complex fields of precision R, or
+// 16-bit fields with per-site scales (half.h), decoded to FP32.  at(r)
+// moves to right-hand side r (stride in elements of the storage); site(i)
+// fetches what every component load of site i shares.
+template <class R>
+struct SrcPlain {
+  const cx<R> *p;
+  using Ctx = int;
+  __device__ SrcPlain at(size_t off) const { return SrcPlain{p + off}; }
+  __device__ Ctx site(size_t) const { return 0; }
+  __device__ cx<R> ld(Ctx, size_t i, int comp, size_t Vh) const { return ldc(p + comp * Vh + i); }
+};
+
+template <HKind K>
+struct SrcHalf {
+  const uint32_t *p;
+  size_t n;  // payload words (12 Vh); the scales follow
+  using Ctx = float;
+  __device__ SrcHalf at(size_t off) const { return SrcHalf{p + off, n}; }
+  __device__ Ctx site(size_t i) const { return __uint_as_float(p[n + i]); }
+  __device__ cx<float> ld(Ctx sc, size_t i, int comp, size_t Vh) const {
+    const cx<float> v = Codec<K>::unpack(p[comp * Vh + i]);
+    return mk(sc * v.re, sc * v.im);
+  }
+};
+
+template <class R>
+struct Half {
+  cx<R> h[2][3];  // [spin 0/1][colour]
+};
+
+// U h (forward) and U^+ h (backward) on each of the two spins of a half
+// spinor; u points at entry 0 of the link, entries are Vh apart.
+template <class R>
+__device__ inline void link_mul(const cx<R> *u, size_t Vh, const Half<R> &in,
+                                Half<R> &out) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<R> u0 = ldc(u + (3 * a + 0) * Vh), u1 = ldc(u + (3 * a + 1) * Vh),
+          u2 = ldc(u + (3 * a + 2) * Vh);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) out.h[s][a] = u0 * in.h[s][0] + u1 * in.h[s][1] + u2 * in.h[s][2];
+  }
+}
+template <class R>
+__device__ inline void link_dag_mul(const cx<R> *u, size_t Vh, const Half<R> &in,
+                                    Half<R> &out) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out.h[s][a] = mk<R>(0, 0);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    cx<R> u0 = ldc(u + (3 * b + 0) * Vh), u1 = ldc(u + (3 * b + 1) * Vh),
+          u2 = ldc(u + (3 * b + 2) * Vh);
+    // (U^+ h)_a = sum_b conj(U_ba) h_b
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      out.h[s][0] = out.h[s][0] + cmulc(u0, in.h[s][b]);
+      out.h[s][1] = out.h[s][1] + cmulc(u1, in.h[s][b]);
+      out.h[s][2] = out.h[s][2] + cmulc(u2, in.h[s][b]);
+    }
+  }
+}
+
+// Project psi (site i of the source, 12 components at stride Vh) for
+// direction MU and sign (FWD: 1 - g_mu, else 1 + g_mu).  G5 applies
+// g5 = diag(1,1,-1,-1) first.
+template <class R, int MU, bool FWD, bool G5, class Src>
+__device__ inline void project(const Src &src, size_t i, size_t Vh, Half<R> &o) {
+  const typename Src::Ctx sc = src.site(i);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cx<R> u0 = src.ld(sc, i, 0 * 3 + c, Vh), u1 = src.ld(sc, i, 1 * 3 + c, Vh);
+    cx<R> l0 = src.ld(sc, i, 2 * 3 + c, Vh), l1 = src.ld(sc, i, 3 * 3 + c, Vh);
+    if (G5) {
+      l0 = -l0;
+      l1 = -l1;
+    }
+    // FWD: h = u + i s_k l ; BWD: h = u - i s_k l ; t: h = u -+ l
+    if (MU == 0) {  // i s_1 l = (i l1, i l0)
+      o.h[0][c] = FWD ? u0 + iz(l1) : u0 - iz(l1);
+      o.h[1][c] = FWD ? u1 + iz(l0) : u1 - iz(l0);
+    } else if (MU == 1) {  // i s_2 l = (l1, -l0)
+      o.h[0][c] = FWD ? u0 + l1 : u0 - l1;
+      o.h[1][c] = FWD ? u1 - l0 : u1 + l0;
+    } else if (MU == 2) {  // i s_3 l = (i l0, -i l1)
+      o.h[0][c] = FWD ? u0 + iz(l0) : u0 - iz(l0);
+      o.h[1][c] = FWD ? u1 - iz(l1) : u1 + iz(l1);
+    } else {  // t
+      o.h[0][c] = FWD ? u0 - l0 : u0 + l0;
+      o.h[1][c] = FWD ? u1 - l1 : u1 + l1;
+    }
+  }
+}
+
+// acc += (g, R g) for direction MU, sign FWD (R = -i s_k / +i s_k / -+1).
+template <class R, int MU, bool FWD>
+__device__ inline void accumulate(cx<R> acc[4][3], const Half<R> &g) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cx<R> g0 = g.h[0][c], g1 = g.h[1][c];
+    acc[0][c] = acc[0][c] + g0;
+    acc[1][c] = acc[1][c] + g1;
+    cx<R> r0, r1;
+    if (MU == 0) {  // -i s_1 g = (-i g1, -i g0); +i s_1 g = (i g1, i g0)
+      r0 = FWD ? miz(g1) : iz(g1);
+      r1 = FWD ? miz(g0) : iz(g0);
+    } else if (MU == 1) {  // -i s_2 g = (-g1, g0); +i s_2 g = (g1, -g0)
+      r0 = FWD ? -g1 : g1;
+      r1 = FWD ? g0 : -g0;
+    } else if (MU == 2) {  // -i s_3 g = (-i g0, i g1); +i s_3 g = (i g0, -i g1)
+      r0 = FWD ? miz(g0) : iz(g0);
+      r1 = FWD ? iz(g1) : miz(g1);
+    } else {  // -g / +g
+      r0 = FWD ? -g0 : g0;
+      r1 = FWD ? -g1 : g1;
+    }
+    acc[2][c] = acc[2][c] + r0;
+    acc[3][c] = acc[3][c] + r1;
+  }
+}
+
+// Scheduling fence: forces the accumulators to be final here and keeps the
+// next direction's loads after it.  Without it the compiler issues all
+// eight neighbours' loads first and delays the arithmetic, so every loaded
+// value stays live and the register file overflows.  The empty asm only
+// names registers; it emits no instruction.
+template <class R>
+__device__ inline void fence(cx<R> acc[4][3]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) asm volatile("" : "+v"(acc[s][c].re), "+v"(acc[s][c].im)::"memory");
+}
+
+template <class R, int MU, bool G5IN, class Src>
+__device__ inline void hop_dir(cx<R> acc[4][3], const cx<R> *U,
+                               const Src &in, int p, int i, int nf, int nb,
+                               size_t Vh) {
+  Half<R> h, g;
+  // forward: (1 - g_mu) U_mu(x) psi(x + mu); the link lives at x (parity p)
+  project<R, MU, true, G5IN>(in, nf, Vh, h);
+  link_mul<R>(U + ((size_t(p) * 4 + MU) * 9) * Vh + i, Vh, h, g);
+  accumulate<R, MU, true>(acc, g);
+  fence(acc);
+  // backward: (1 + g_mu) U_mu(x - mu)^+ psi(x - mu); link at x - mu (parity 1-p)
+  project<R, MU, false, G5IN>(in, nb, Vh, h);
+  link_dag_mul<R>(U + ((size_t(1 - p) * 4 + MU) * 9) * Vh + nb, Vh, h, g);
+  accumulate<R, MU, false>(acc, g);
+  fence(acc);
+}
+
+}  // namespace st
+}  // namespace lqcd

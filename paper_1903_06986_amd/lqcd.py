@@ -68,6 +68,12 @@ _SIGS = {
     "loop_estimate": [_P, _P, _I, _P, _P, _P, _I, _P, _P, _P, _P],
     "loop_gradient": [_P, _P, _P, _I, ctypes.POINTER(SolveParams), ctypes.POINTER(_P), _P, _P, _I,
                       _P, _P, ctypes.POINTER(SolveStats)],
+    "lqcd_batch_create": [_P, _I, ctypes.POINTER(_P)],
+    "lqcd_batch_destroy": [_P],
+    "lqcd_batch_set_grid": [_P, _I],
+    "batch_solve": [_P, ctypes.POINTER(SolveParams), _P, _P, _P, _P, _I, ctypes.POINTER(SolveStats)],
+    "batch_autotune": [_P, ctypes.POINTER(SolveParams), _P, _P, _P, ctypes.POINTER(_I), ctypes.POINTER(_I), _P],
+    "batch_wilson_apply": [_P, _P, _P, _P],
     "lqcd_timer_enable": [_P, _I],
     "lqcd_timer_read": [_P, _I, _P, _P, _P],
     "lqcd_tune_set": [_P, _I, _I],
@@ -348,3 +354,75 @@ class Context:
         st = [dict(matvecs=s.matvecs, cycles=s.cycles, refinements=s.refinements, reorth=s.reorth,
                    true_resid=s.true_resid) for s in stats[:nrhs]]
         return complex(dk[0]), dl, newdefl, st
+
+
+class Batch:
+    """Several contexts (lattices) solved together (see batch_solve in lqcd.h)."""
+
+    def __init__(self, contexts):
+        self.contexts = list(contexts)
+        arr = (_P * len(self.contexts))(*[c.handle.value for c in self.contexts])
+        h = _P()
+        _check(lib().lqcd_batch_create(arr, len(self.contexts), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lqcd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, fields):
+        return (_P * len(fields))(*[(_ptr(f).value if f is not None and f.numel() else None) for f in fields])
+
+    def set_grid(self, workgroups):
+        _check(lib().lqcd_batch_set_grid(self.handle, int(workgroups)))
+
+    def wilson_apply(self, xs):
+        """Mhat (FP32) of every field list entry, one launch over all lattices."""
+        import torch
+        outs = [torch.empty_like(x) for x in xs]
+        nr = (_I * len(xs))(*[x.shape[0] for x in xs])
+        _check(lib().batch_wilson_apply(self.handle, self._ptrs(xs), self._ptrs(outs), nr))
+        return outs
+
+    @staticmethod
+    def _params(m, k, tol, max_cycles, inner_tol, rhs_block, proj_m):
+        return SolveParams(m, k, max_cycles, tol, tol, 0.0, 0, F32, inner_tol, rhs_block, proj_m)
+
+    def solve(self, bs, defls, m=20, k=10, tol=1e-10, max_cycles=1000, inner_tol=1e-4, rhs_block=8,
+              proj_m=0, graph=True):
+        """Solve M x = b for every lattice's fields bs[l] ([nrhs_l, ...] LEX
+        complex128) with deflation spaces defls[l]; returns (xs, stats)."""
+        import torch
+        xs = [torch.empty_like(b) for b in bs]
+        nr = (_I * len(bs))(*[b.shape[0] for b in bs])
+        total = sum(b.shape[0] for b in bs)
+        stats = (SolveStats * max(total, 1))()
+        p = self._params(m, k, tol, max_cycles, inner_tol, rhs_block, proj_m)
+        dp = (_P * len(defls))(*[d.handle.value for d in defls])
+        _check(lib().batch_solve(self.handle, ctypes.byref(p), self._ptrs(bs), self._ptrs(xs), nr, dp,
+                                 1 if graph else 0, stats))
+        st = [dict(matvecs=s.matvecs, cycles=s.cycles, refinements=s.refinements, reorth=s.reorth,
+                   true_resid=s.true_resid) for s in stats[:total]]
+        return xs, st
+
+    def autotune(self, bs, defls, m=20, k=10, tol=1e-10, max_cycles=1000, inner_tol=1e-4, proj_m=0):
+        """Returns (best rhs_block, best grid, {(rhs_block, grid): rhs/s})."""
+        nr = (_I * len(bs))(*[b.shape[0] for b in bs])
+        p = self._params(m, k, tol, max_cycles, inner_tol, 8, proj_m)
+        dp = (_P * len(defls))(*[d.handle.value for d in defls])
+        bb, bg = _I(0), _I(0)
+        rates = np.zeros(8)
+        _check(lib().batch_autotune(self.handle, ctypes.byref(p), self._ptrs(bs), nr, dp, ctypes.byref(bb),
+                                    ctypes.byref(bg), rates.ctypes.data_as(_P)))
+        table = {}
+        for i, blk in enumerate((4, 8, 16, 32)):
+            for j, g in enumerate((2048, 8192)):
+                table[(blk, g)] = float(rates[2 * i + j])
+        return bb.value, bg.value, table

@@ -186,6 +186,71 @@ def accuracy(path, precisions, cfg, kappa, U, oracle_check):
     return out
 
 
+def batching(args):
+    """Untimed by the headline: the mixed-lattice batch (8^4 x 17, 12^3 x 24
+    x 64, 16^3 x 32 x 160 right-hand sides) solved by batch_solve with the
+    autotuned block and grid, against the same solves lattice by lattice."""
+    import torch
+    from paper_1903_06986_amd import Batch, Context
+    from synth import get_config, random_su3_links
+    cfg = get_config("c4")
+    kappa = cfg["kappas"][0]
+    ctxs, defls, etas = [], [], []
+    t0 = time.time()
+    for li, (dims, nr) in enumerate(zip(cfg["lattices"], cfg["n_rhs"])):
+        U = random_su3_links(dims, cfg["eps"], cfg["link_seed"] + li)
+        ctx = Context(dims, U, kappa)
+        eta0 = ctx.noise_z4(cfg["noise_seed"] + li, 0, 1)
+        _, defl, _ = ctx.gmresdr_solve(eta0, op="schur", m=cfg["m"], k=cfg["k"], tol=args.tol,
+                                       tol_super=args.tol_super, max_cycles=args.max_cycles)
+        ctxs.append(ctx)
+        defls.append(defl)
+        etas.append(ctx.noise_z4(cfg["noise_seed"] + li, 1, nr))
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    batch = Batch(ctxs)
+    kw = dict(m=cfg["m"], k=cfg["k"], tol=args.tol, max_cycles=args.max_cycles, inner_tol=args.inner_tol)
+    blk, grid, table = batch.autotune(etas, defls, **kw)
+    batch.set_grid(grid)
+    total = sum(cfg["n_rhs"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, st = batch.solve(etas, defls, rhs_block=blk, graph=True, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, st_eager = batch.solve(etas, defls, rhs_block=blk, graph=False, **kw)
+    torch.cuda.synchronize()
+    dt_eager = time.perf_counter() - t0
+    seq = {}
+    t_seq = 0.0
+    for ctx, defl, eta, dims in zip(ctxs, defls, etas, cfg["lattices"]):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, _, s1 = ctx.gmresdr_solve(eta, op="schur", m=cfg["m"], k=cfg["k"], tol=args.tol, inner="f32",
+                                     inner_tol=args.inner_tol, rhs_block=min(blk, eta.shape[0]),
+                                     max_cycles=args.max_cycles, defl=defl)
+        torch.cuda.synchronize()
+        d1 = time.perf_counter() - t1
+        t_seq += d1
+        seq["x".join(map(str, dims))] = {"solves_per_s": round(eta.shape[0] / d1, 3),
+                                        "matvecs_per_solve": float(np.mean([s["matvecs"] for s in s1]))}
+    out = {"lattices": ["%s x %d" % ("x".join(map(str, d)), n) for d, n in zip(cfg["lattices"], cfg["n_rhs"])],
+           "kappa": kappa, "solves": total, "setup_s": round(setup_s, 3),
+           "autotune": {"rhs_block": blk, "grid": grid,
+                        "rates": {"%d/%d" % k: round(v, 2) for k, v in table.items()}},
+           "batched_graph_solves_per_s": round(total / dt, 3),
+           "batched_eager_solves_per_s": round(total / dt_eager, 3),
+           "sequential_solves_per_s": round(total / t_seq, 3),
+           "batched_over_sequential": round(t_seq / dt, 3),
+           "per_lattice_sequential": seq,
+           "max_true_resid": max(s["true_resid"] for s in st),
+           "matvecs_per_solve": float(np.mean([s["matvecs"] for s in st]))}
+    print("[bench] batching %s" % json.dumps(out), file=sys.stderr, flush=True)
+    batch.close()
+    return out
+
+
 def cpu_baseline(cfg, kappa, matvecs_per_solve, p_cycle):
     """FP64 oracle on the host, bounded sample: three applications of the
     even/odd operator and one CGS2 pass against p/2 basis vectors on the
@@ -251,11 +316,18 @@ def main():
                     help="other inner precisions timed and reported beside the headline")
     ap.add_argument("--variant-steps", type=int, default=2)
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the mixed-lattice batch (8^4, 12^3x24, 16^3x32) measurement")
+    ap.add_argument("--batching-only", action="store_true",
+                    help="run only the mixed-lattice batch measurement and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the noise solves shard "
               "by right-hand side; see the design notes).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.batching_only:
+        print(json.dumps(batching(args)), flush=True)
+        return
     import torch
     from paper_1903_06986_amd import Context
     from synth import random_su3_links
@@ -300,6 +372,9 @@ def main():
     acc = None
     if not args.no_accuracy:
         acc = accuracy(path, [args.inner] + list(variants), cfg, kappa, U, not args.no_cpu_baseline)
+    bat = None
+    if not args.no_batching:
+        bat = batching(args)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, kappa, mv64, cfg["m"] - cfg["k"])
@@ -324,6 +399,7 @@ def main():
                   "max_true_resid": max(s["true_resid"] for s in stats)},
         "variants": variants,
         "accuracy": acc,
+        "batching": bat,
         "setup": {k: round(v, 3) for k, v in path.setup_times.items()},
         "end_to_end_200_noise_s": round(path.setup_times["total_s"] + 199.0 / value, 2),
         "kernels": kernels,

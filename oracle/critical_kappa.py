@@ -56,7 +56,7 @@ def rightmost_eig(U, dims, tol=1e-7, ncv=24, seed=0, fast=True, progress=0):
     return vals[order], vecs[:, order[0]], count[0]
 
 
-def rightmost_eig_eo(U, dims, tol=1e-7, ncv=24, seed=0, progress=0):
+def rightmost_eig_eo(U, dims, tol=1e-7, ncv=24, seed=0, progress=0, k=2):
     """Rightmost eigenvalue of P through its even/odd square: returns (mu,
     eigenvalues of D_eo D_oe found, eigenvector of P, products with P)."""
     import scipy.sparse.linalg as sla
@@ -82,7 +82,7 @@ def rightmost_eig_eo(U, dims, tol=1e-7, ncv=24, seed=0, progress=0):
     op = sla.LinearOperator((ne, ne), matvec=mv, dtype=np.complex128)
     rng = np.random.default_rng(seed)
     v0 = rng.standard_normal(ne) + 1j * rng.standard_normal(ne)
-    vals, vecs = sla.eigs(op, k=2, which="LR", ncv=ncv, tol=tol, v0=v0)
+    vals, vecs = sla.eigs(op, k=k, which="LR", ncv=ncv, tol=tol, v0=v0)
     order = np.argsort(-vals.real)
     nu = vals[order[0]]
     mu = np.sqrt(nu)
@@ -102,8 +102,8 @@ def main(name):
     U = random_su3_links(dims, cfg["eps"], cfg["link_seed"])
     from .wilson import hop
     t0 = time.time()
-    tol, ncv = 1e-5, 48
-    mu_c, vals, v, nmv = rightmost_eig_eo(U, dims, tol=tol, ncv=ncv, progress=500)
+    tol, ncv = 1e-5, 250
+    mu_c, vals, v, nmv = rightmost_eig_eo(U, dims, tol=tol, ncv=ncv, progress=500, k=1)
     resid = float(np.linalg.norm(hop(U, v) - mu_c * v) / (abs(mu_c) * np.linalg.norm(v)))
     mu = float(mu_c.real)
     vals = np.array([mu_c])
@@ -112,7 +112,7 @@ def main(name):
                rightmost_mu=[[float(v.real), float(v.imag)] for v in vals],
                max_re_mu=mu, eig_resid=resid, delta=delta, kappa=(1.0 - delta) / mu, matvecs=nmv,
                seconds=time.time() - t0,
-               method="ARPACK eigs(which='LR', k=2, ncv=%d, tol=%g) on the even/odd square D_eo D_oe "
+               method="ARPACK eigs(which='LR', k=1, ncv=%d, tol=%g) on the even/odd square D_eo D_oe "
                       "of the oracle hop; mu = sqrt of its rightmost eigenvalue" % (ncv, tol))
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "synth",
                         "%s_kappa.json" % name)

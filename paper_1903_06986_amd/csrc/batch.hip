@@ -58,17 +58,24 @@ __device__ inline double wave_sum(double v) {
 // Modes: which operands of a slot the half hop reads and writes.
 enum HopMode { HOP_W = 0, SCHUR_W = 1, HOP_X = 2, SCHUR_X = 3 };
 
-// Work item = (slot, 256-site block); every slot owns `per` items (enough
-// for the largest lattice), so the list does not depend on which lattice
-// a slot holds and a captured launch stays valid when slots are refilled.
+// Work item = (256-site block, slot); every slot owns `per` site blocks
+// (enough for the largest lattice), so the list does not depend on which
+// lattice a slot holds and a captured launch stays valid when slots are
+// refilled.  The slot index runs fastest and the list is cut into one
+// contiguous range per XCD (workgroup h runs on XCD h % 8): the slots of a
+// site block, mostly right-hand sides of one lattice, run back to back on
+// one XCD and share that block's links in its L2.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock)
-    k_bhop(const BSlot *__restrict__ sl, unsigned per, unsigned nitems, int j) {
-  for (unsigned item = blockIdx.x; item < nitems; item += gridDim.x) {
-    const unsigned s = item / per;
+    k_bhop(const BSlot *__restrict__ sl, unsigned nslot, unsigned nitems, int j) {
+  const unsigned xq = (nitems + 7) / 8;
+  for (unsigned h = blockIdx.x; h < 8 * xq; h += gridDim.x) {
+    const unsigned item = (h % 8) * xq + h / 8;
+    if (item >= nitems) continue;
+    const unsigned s = item % nslot;
     const BSlot &d = sl[s];
     if (!d.active) continue;
-    const int i = int(item % per) * kBlock + threadIdx.x;
+    const int i = int(item / nslot) * kBlock + threadIdx.x;
     const Geom &g = d.g;
     if (i >= g.Vh) continue;
     const size_t Vh = size_t(g.Vh), n = d.n;
@@ -144,7 +151,7 @@ __global__ void __launch_bounds__(kBlock)
 // Basis selection: BAS_W = W_0 .. W_{J-1} against W_{j+1} (Arnoldi),
 // BAS_V = Vd_0 .. Vd_{kd} against R (deflation projection).
 enum BasisSel { BAS_W = 0, BAS_V = 1 };
-constexpr int kEpt = 8;  // elements per lane
+constexpr int kEpt = 16;  // elements per lane
 constexpr int kWch = 64 * kEpt;
 
 // part[(s * nchunk + chunk) * Jmax + jj] (complex) = partial dot of
@@ -176,7 +183,33 @@ __global__ void __launch_bounds__(kBlock)
     const cx<float> v = idx < n ? ldc(w + idx) : mk(0.f, 0.f);
     wv[e] = mk<double>(v.re, v.im);
   }
-  for (int jj = 0; jj < Jmax; ++jj) {
+  int jj = 0;
+  for (; jj + 2 <= J; jj += 2) {  // two basis vectors per pass
+    double a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+    const cx<float> *v0 = V + size_t(jj) * n, *v1 = v0 + n;
+#pragma unroll
+    for (int e = 0; e < kEpt; ++e) {
+      const size_t idx = base + size_t(e) * 64;
+      if (idx < n) {
+        const cx<float> q0 = ldc(v0 + idx), q1 = ldc(v1 + idx);
+        const cx<double> p0 = cmulc(mk<double>(q0.re, q0.im), wv[e]);
+        const cx<double> p1 = cmulc(mk<double>(q1.re, q1.im), wv[e]);
+        a0 += p0.re;
+        b0 += p0.im;
+        a1 += p1.re;
+        b1 += p1.im;
+      }
+    }
+    a0 = wave_sum(a0);
+    b0 = wave_sum(b0);
+    a1 = wave_sum(a1);
+    b1 = wave_sum(b1);
+    if (lane == 0) {
+      po[jj] = mk(a0, b0);
+      po[jj + 1] = mk(a1, b1);
+    }
+  }
+  for (; jj < Jmax; ++jj) {
     double a = 0, b = 0;
     if (jj < J) {
       const cx<float> *v0 = V + size_t(jj) * n;
@@ -281,7 +314,23 @@ __global__ void __launch_bounds__(kBlock)
       const cx<float> v = idx < n ? ldc(w + idx) : mk(0.f, 0.f);
       acc[e] = mk<double>(v.re, v.im);
     }
-    for (int jj = 0; jj < J; ++jj) {
+    int jj = 0;
+    for (; jj + 4 <= J; jj += 4) {  // four basis vectors per pass: 16 loads in flight per lane
+      const cx<double> c0 = sign * cf[jj], c1 = sign * cf[jj + 1], c2 = sign * cf[jj + 2],
+                       c3 = sign * cf[jj + 3];
+      const cx<float> *v0 = V + size_t(jj) * n;
+#pragma unroll
+      for (int e = 0; e < kAept; ++e) {
+        const size_t idx = base + size_t(e) * kBlock;
+        if (idx < n) {
+          const cx<float> q0 = ldc(v0 + idx), q1 = ldc(v0 + n + idx), q2 = ldc(v0 + 2 * n + idx),
+                          q3 = ldc(v0 + 3 * n + idx);
+          acc[e] = acc[e] + (mk<double>(q0.re, q0.im) * c0 + mk<double>(q1.re, q1.im) * c1) +
+                   (mk<double>(q2.re, q2.im) * c2 + mk<double>(q3.re, q3.im) * c3);
+        }
+      }
+    }
+    for (; jj < J; ++jj) {
       const cx<double> c = sign * cf[jj];
       const cx<float> *v0 = V + size_t(jj) * n;
 #pragma unroll
@@ -489,15 +538,15 @@ struct Engine {
   const BSlot *sl;
   size_t nchunk() const { return (nmax + size_t(kWch) * kWaves - 1) / (size_t(kWch) * kWaves) * kWaves; }
   size_t nblk() const { return (nmax + size_t(kBlock) * kAept - 1) / (size_t(kBlock) * kAept); }
-  unsigned hop_grid() const { return std::min<unsigned>(items, hgrid); }
+  unsigned hop_grid() const { return std::min<unsigned>((items + 7) / 8 * 8, hgrid); }
 
   void stencil_schur_w(int j) const {
-    hipLaunchKernelGGL(k_bhop<HOP_W>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, per, items, j);
-    hipLaunchKernelGGL(k_bhop<SCHUR_W>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, per, items, j);
+    hipLaunchKernelGGL(k_bhop<HOP_W>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, unsigned(B), items, j);
+    hipLaunchKernelGGL(k_bhop<SCHUR_W>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, unsigned(B), items, j);
   }
   void stencil_schur_x() const {
-    hipLaunchKernelGGL(k_bhop<HOP_X>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, per, items, 0);
-    hipLaunchKernelGGL(k_bhop<SCHUR_X>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, per, items, 0);
+    hipLaunchKernelGGL(k_bhop<HOP_X>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, unsigned(B), items, 0);
+    hipLaunchKernelGGL(k_bhop<SCHUR_X>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, unsigned(B), items, 0);
   }
   // dots of the basis (W_0..W_{J-1} or Vd) against W_{jnew} or R into out [B][Jmax]
   template <int SEL>
@@ -685,27 +734,34 @@ void run_batch(lqcd_batch *b, const lqcd_solve_params &prm, const void *const *b
       pack_eo<double>(c, bl, bp, 1, fl);
       hop_half<double>(c, 0, bp + n, bp, S64 + size_t(s) * nmax, cdouble(1, 0), c->kappa, false, false, 1,
                        fl, fl, n);
-      double *nr = b->nrm1.as<double>();
-      norm2<double>(c, bp, fl, fl, 1, nr);
-      double h = 0;
-      d2h_b(b, &h, nr, sizeof(double));
-      ss[s].ref = std::sqrt(h);
-      LQCD_CHECK(std::isfinite(ss[s].ref), LQCD_ENAN, "batch_solve: right-hand side is not finite");
-      if (ss[s].ref == 0) ss[s].ref = 1;  // zero right-hand side: x = 0 converges at once
+      norm2<double>(c, bp, fl, fl, 1, b->nrm1.as<double>() + s);
       fill_zero(c, X64 + size_t(s) * nmax, n * sizeof(cx<double>));
       LQCD_HIP(hipMemcpyAsync(R64 + size_t(s) * nmax, S64 + size_t(s) * nmax, n * sizeof(cx<double>),
                               hipMemcpyDeviceToDevice, b->stream));
+    }
+    {
+      // |b| of every filled slot, one copy
+      std::vector<double> h(B, 0.0);
+      d2h_b(b, h.data(), b->nrm1.ptr, size_t(B) * sizeof(double));
+      for (int s = 0; s < B; ++s) {
+        if (ss[s].lat < 0) continue;
+        ss[s].ref = std::sqrt(h[s]);
+        LQCD_CHECK(std::isfinite(ss[s].ref), LQCD_ENAN, "batch_solve: right-hand side is not finite");
+        if (ss[s].ref == 0) ss[s].ref = 1;  // zero right-hand side: x = 0 converges at once
+      }
     }
     // FP64 refinement around batched FP32 inner solves
     for (int outer = 0;; ++outer) {
       bool any = false;
       for (int s = 0; s < B; ++s) {
         if (ss[s].lat < 0 || ss[s].done) continue;
-        lqcd_ctx *c = b->ctx[ss[s].lat];
-        double *nr = b->nrm1.as<double>();
-        norm2<double>(c, R64 + size_t(s) * nmax, 0, slh[s].n, 1, nr);
-        double h = 0;
-        d2h_b(b, &h, nr, sizeof(double));
+        norm2<double>(b->ctx[ss[s].lat], R64 + size_t(s) * nmax, 0, slh[s].n, 1, b->nrm1.as<double>() + s);
+      }
+      std::vector<double> hr(B, 0.0);
+      d2h_b(b, hr.data(), b->nrm1.ptr, size_t(B) * sizeof(double));
+      for (int s = 0; s < B; ++s) {
+        if (ss[s].lat < 0 || ss[s].done) continue;
+        const double h = hr[s];
         ss[s].rn = std::sqrt(h);
         LQCD_CHECK(std::isfinite(ss[s].rn), LQCD_ENAN, "batch_solve: NaN/Inf residual");
         if (ss[s].rn <= prm.tol * ss[s].ref || ss[s].st.cycles >= prm.max_cycles || outer > kBatchMaxRefine)
@@ -829,13 +885,17 @@ void run_batch(lqcd_batch *b, const lqcd_solve_params &prm, const void *const *b
       apply_full<double>(c, LQCD_OP_M, xf, tf, 1, fl, fl);
       cdouble one(1, 0), mone(-1, 0);
       axpby<double>(c, &one, bp, fl, &mone, tf, fl, fl, 1, false);
-      double *nr = b->nrm1.as<double>();
-      norm2<double>(c, tf, fl, fl, 1, nr);
-      double h = 0;
-      d2h_b(b, &h, nr, sizeof(double));
-      ss[s].st.true_resid = std::sqrt(h) / ss[s].ref;
-      if (ss[s].rn > prm.tol * ss[s].ref) *nonconv = 1;
-      if (stats) stats[first[l] + ss[s].rhs] = ss[s].st;
+      norm2<double>(c, tf, fl, fl, 1, b->nrm1.as<double>() + s);
+    }
+    {
+      std::vector<double> h(B, 0.0);
+      d2h_b(b, h.data(), b->nrm1.ptr, size_t(B) * sizeof(double));
+      for (int s = 0; s < B; ++s) {
+        if (ss[s].lat < 0) continue;
+        ss[s].st.true_resid = std::sqrt(h[s]) / ss[s].ref;
+        if (ss[s].rn > prm.tol * ss[s].ref) *nonconv = 1;
+        if (stats) stats[first[ss[s].lat] + ss[s].rhs] = ss[s].st;
+      }
     }
   }
 }

@@ -280,7 +280,7 @@ __global__ void k_scale_dev(const cx<R> *__restrict__ x, size_t x_rs, const doub
 }
 
 // ---------------------------------------------------------------- gemm
-constexpr int NBT = 4;  // output columns per pass
+constexpr int NBT = 8;  // output columns per pass (V read once for nb <= 8)
 template <class R>
 __global__ void __launch_bounds__(kBlock)
     k_gemm_nn(const cx<R> *__restrict__ V, size_t ldv, size_t V_rs, int J,
@@ -560,6 +560,116 @@ __global__ void k_inv_sqrt(const double *__restrict__ nrm2, double *__restrict__
   }
 }
 
+
+// ---------------------------------------------------- V^H X on MFMA
+// C = V^H X for J <= 64 basis vectors and nb <= 8 columns, as one real
+// GEMM on the matrix cores: with K running over (element, re/im),
+//   A[j][2e + q] = (Re, Im) V_j[e],
+//   B[2e + q][c]      = (Re, Im) X_c[e]        -> Re C[j][c],
+//   B[2e + q][nb + c] = (Im, -Re) X_c[e]       -> Im C[j][c].
+// A workgroup (4 waves, wave w owns rows 16w .. 16w + 15) walks a K range
+// in chunks of 64 elements staged in LDS (rows padded by 2 words against
+// bank conflicts), accumulates one 16 x 16 tile per wave with
+// v_mfma_*_16x16x4 (16 x 4 times 4 x 16 per instruction: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and holds four rows of column
+// l % 16, Mfma::row), and writes its partial tile; a second kernel adds the
+// workgroups' partials in a fixed order.  V and X are each read once.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <class R>
+struct Mfma;
+// row(q, v): tile row of accumulator register v in lanes 16 q .. 16 q + 15
+// (checked on the device: FP32 holds rows 4q + v, FP64 rows q + 4v).
+template <>
+struct Mfma<float> {
+  using acc_t = f4v;
+  __device__ static acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int q, int v) { return 4 * q + v; }
+};
+template <>
+struct Mfma<double> {
+  using acc_t = d4v;
+  __device__ static acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int q, int v) { return q + 4 * v; }
+};
+
+constexpr int kTE = 64;           // elements per LDS chunk
+constexpr int kTP = 2 * kTE + 2;  // reals per staged row (padded)
+
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_gemm_tn_mfma(const cx<R> *__restrict__ V, size_t ldv, int J, const cx<R> *__restrict__ X,
+                   size_t ldx, int nb, size_t n, size_t chunks_per_block, R *__restrict__ part) {
+  __shared__ R sV[64 * kTP];
+  __shared__ R sX[8 * kTP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  using A = Mfma<R>;
+  typename A::acc_t acc = {0, 0, 0, 0};
+  const size_t c0 = size_t(blockIdx.x) * chunks_per_block;
+  const size_t nchunk = (n + kTE - 1) / kTE;
+  const size_t c1 = c0 + chunks_per_block < nchunk ? c0 + chunks_per_block : nchunk;
+  const int row = 16 * wave + (lane & 15);   // A row (basis vector) of this lane
+  const int kq = lane >> 4;                   // 0..3: element 2 * step + kq / 2, part kq % 2
+  const int col = lane & 15;                  // B column
+  for (size_t ch = c0; ch < c1; ++ch) {
+    const size_t e0 = ch * kTE;
+    __syncthreads();  // the previous chunk's operands are consumed
+    // stage V rows 0..J-1 and X columns 0..nb-1 (zero beyond n)
+    for (int t = threadIdx.x; t < (J + nb) * kTE; t += kBlock) {
+      const int r = t / kTE, e = t % kTE;
+      const size_t idx = e0 + e;
+      cx<R> v = mk<R>(0, 0);
+      if (idx < n) v = r < J ? ldc(V + size_t(r) * ldv + idx) : ldc(X + size_t(r - J) * ldx + idx);
+      R *dst = r < J ? sV + r * kTP : sX + (r - J) * kTP;
+      dst[2 * e] = v.re;
+      dst[2 * e + 1] = v.im;
+    }
+    __syncthreads();
+    if (16 * wave < J) {
+#pragma unroll 8
+      for (int st = 0; st < kTE / 2; ++st) {
+        const int e = 2 * st + (kq >> 1), q = kq & 1;
+        const R a = row < J ? sV[row * kTP + 2 * e + q] : R(0);
+        R b = 0;
+        if (col < nb) {
+          b = sX[col * kTP + 2 * e + q];
+        } else if (col - nb < nb) {
+          const R xr = sX[(col - nb) * kTP + 2 * e], xi = sX[(col - nb) * kTP + 2 * e + 1];
+          b = q == 0 ? xi : -xr;
+        }
+        acc = A::op(a, b, acc);
+      }
+    }
+  }
+  // partial tile: part[block][row][col], rows 4 (lane / 16) + v of the wave's tile
+  if (16 * wave < J) {
+    R *po = part + size_t(blockIdx.x) * 64 * 16;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) po[(16 * wave + A::row(kq, v)) * 16 + col] = acc[v];
+  }
+}
+
+// C[j + ldc * c] = sum over blocks of the partial tiles (complex).
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_gemm_tn_final(const R *__restrict__ part, int nblk, int J, int nb, cx<double> *__restrict__ C,
+                    size_t ldc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= J * nb) return;
+  const int j = t % J, c = t / J;
+  double re = 0, im = 0;
+  for (int b = 0; b < nblk; ++b) {
+    re += double(part[(size_t(b) * 64 + j) * 16 + c]);
+    im += double(part[(size_t(b) * 64 + j) * 16 + nb + c]);
+  }
+  C[j + ldc * size_t(c)] = mk(re, im);
+}
+
 inline unsigned grid_elems(size_t n) { return unsigned(std::min<size_t>(nblocks(n), 8192)); }
 
 }  // namespace
@@ -668,9 +778,27 @@ void gemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const c
 template <class R>
 void gemm_tn(lqcd_ctx *c, const void *V, size_t ldv, int J, const void *X, size_t ldx, int nb,
              size_t n, cdouble *C, size_t ldc) {
-  // one multi-dot per column of X (the X columns act as a batch)
-  multi_dot_impl<R>(c, V, ldv, 0, J, X, ldx, n, nb, C, ldc, LQCD_KC_GEMM,
-                    double(J + nb) * n * sizeof(cx<R>));
+  if (J <= 0 || nb <= 0) return;
+  if (J > 64 || nb > 8 || n < size_t(kTE)) {
+    // outside the matrix-core tile: one multi-dot per column of X
+    multi_dot_impl<R>(c, V, ldv, 0, J, X, ldx, n, nb, C, ldc, LQCD_KC_GEMM,
+                      double(J + nb) * n * sizeof(cx<R>));
+    return;
+  }
+  // split K so that about 1024 workgroups share the reduction
+  const size_t nchunk = (n + kTE - 1) / kTE;
+  const size_t cpb = std::max<size_t>(1, (nchunk + 1023) / 1024);
+  const int nblk = int((nchunk + cpb - 1) / cpb);
+  R *part = static_cast<R *>(c->red.ensure(size_t(nblk) * 64 * 16 * sizeof(R)));
+  {
+    Timed tm(c, LQCD_KC_GEMM, double(J + nb) * n * sizeof(cx<R>));
+    LQCD_TLAUNCH(tm, true, true, (k_gemm_tn_mfma<R>), dim3(nblk), dim3(kBlock), 0, c->stream,
+                 static_cast<const cx<R> *>(V), ldv, J, static_cast<const cx<R> *>(X), ldx, nb, n, cpb, part);
+  }
+  LQCD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_gemm_tn_final<R>, dim3(unsigned((J * nb + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     c->stream, part, nblk, J, nb, reinterpret_cast<cx<double> *>(C), ldc);
+  LQCD_HIP(hipGetLastError());
 }
 
 template <class R>

@@ -29,7 +29,7 @@ CONFIGS = {
                n_hermitian=30, herm_m=80, herm_k=45, link_seed=1003, noise_seed=2003),
     # batching axis: several lattices, uneven right-hand-side counts
     "c4": dict(lattices=((8, 8, 8, 8), (12, 12, 12, 24), (16, 16, 16, 32)),
-               n_rhs=(17, 64, 160), eps=0.25, kappas=(0.125,),
+               n_rhs=(17, 64, 160), eps=0.25, kappas=(0.125,), m=40, k=20,
                link_seed=1004, noise_seed=2004),
     # differentiation axis
     "c5": dict(dims=(12, 12, 12, 12), eps=0.25, kappas=(0.124,), n_noise=32,

@@ -196,8 +196,9 @@ lqcd_status deflate_project(lqcd_ctx *ctx, lqcd_defl *defl, int Q, lqcd_defl_mod
 /* Perturbative subtraction (Sec. 5.1, Eqs. (28)-(35)): xt[n] =
  * sum_{j=0}^{order} (kappa P)^j eta[n] (device LEX), and the exact trace
  * correction Tr_t(Theta sum_j (kappa P)^j) per timeslice (host complex128
- * [ntheta][Lt]; may be NULL).  Only closed paths contribute to the
- * correction; order <= 7. */
+ * [ntheta][Lt]; may be NULL), for any operator code.  Only closed paths
+ * contribute to the correction (point-split: paths closed by the
+ * operator's own hop, Sec. 5.1); order <= 7. */
 lqcd_status pert_subtract(lqcd_ctx *ctx, int order, const int *thetas_host, int ntheta,
                           const void *eta, void *xt, int nrhs, double *trace_corr_host);
 
@@ -214,6 +215,14 @@ lqcd_status pert_subtract(lqcd_ctx *ctx, int order, const int *thetas_host, int 
 lqcd_status poly_subtract(lqcd_ctx *ctx, int degree, const void *b, double *coeffs_host,
                           double *a_host, const int *thetas_host, int ntheta,
                           const void *eta, void *xt, int nrhs, double *trace_corr_host);
+
+/* Operator codes (thetas_host arrays): 0 = scalar (Theta = 1), 1..4 = local
+ * vector g_1..g_4 (Table 2), 5..8 = point-split vector in direction mu =
+ * 0..3 (Table 2): Theta(mu) psi(x) = kappa [ (1 + g_mu) U_mu(x - mu)^+
+ * psi(x - mu) - (1 - g_mu) U_mu(x) psi(x + mu) ], with the context's kappa;
+ * a term belongs to the timeslice of its row site x.  pert_subtract,
+ * poly_subtract, deflate_project and loop_estimate accept all nine codes;
+ * loop_gradient the local ones (0..4). */
 
 /* The subtracted estimator (Sec. 5 Eq. (23); Sec. 6 Eq. (73)):
  *   t_n[th][t] = sum_{x in timeslice t} eta_n(x)^+ Theta (x_n - xt_n)(x),

@@ -9,6 +9,7 @@
 #include "cplx.h"
 #include "gamma.h"
 #include "fields.h"
+#include "pointsplit.h"
 
 namespace lqcd {
 namespace {
@@ -63,7 +64,73 @@ __global__ void __launch_bounds__(kBlock)
     double s = 0;
     for (int w = 0; w < kWaves; ++w) s += sh[threadIdx.x][w];
     const int th = threadIdx.x / 2, part = threadIdx.x % 2;
-    out[((size_t(r) * kNumTheta + th) * Lt + t) * 2 + part] = s;
+    out[((size_t(r) * kNumOps + th) * Lt + t) * 2 + part] = s;
+  }
+}
+
+// Point-split operators (codes 5..8): t_n[mu][t] = sum_{x in t} eta_n(x)^+
+// (Theta(mu) (x_n - xt_n))(x); one block per (timeslice, right-hand side).
+__global__ void __launch_bounds__(kBlock)
+    k_estimate_ps(Geom g, const cx<double> *__restrict__ U, double kappa,
+                  const cx<double> *__restrict__ eta, const cx<double> *__restrict__ x,
+                  const cx<double> *__restrict__ xt, double *__restrict__ out) {
+  __shared__ double sh[2 * kNumPS][kWaves];
+  const int t = blockIdx.x, r = blockIdx.y;
+  const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+  const int Vs = Lx * Ly * Lz;
+  const size_t V = size_t(g.V), Vh = size_t(g.Vh);
+  const size_t base = size_t(r) * V * 12;
+  double acc[2 * kNumPS] = {};
+  for (int i = threadIdx.x; i < Vs; i += kBlock) {
+    const int xx = i % Lx, yy = (i / Lx) % Ly, zz = i / (Lx * Ly);
+    const size_t s = size_t(t) * Vs + i;
+    cx<double> a[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) a[k] = ldc(eta + base + s * 12 + k);
+    const int c[4] = {xx, yy, zz, t};
+    const int Ls[4] = {Lx, Ly, Lz, Lt};
+    const size_t st[4] = {1, size_t(Lx), size_t(Lx) * Ly, size_t(Lx) * Ly * Lz};
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+      const size_t sf = c[mu] + 1 == Ls[mu] ? s - st[mu] * (Ls[mu] - 1) : s + st[mu];
+      const size_t sb = c[mu] == 0 ? s + st[mu] * (Ls[mu] - 1) : s - st[mu];
+      int cb[4] = {c[0], c[1], c[2], c[3]};
+      cb[mu] = c[mu] == 0 ? Ls[mu] - 1 : c[mu] - 1;
+      cx<double> b[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        b[k] = ldc(x + base + sf * 12 + k);
+        if (xt) b[k] = b[k] - ldc(xt + base + sf * 12 + k);
+      }
+      const cx<double> vf = ps_half<true>(a, b, ps_link(U, g, c[0], c[1], c[2], c[3], mu), Vh, mu);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        b[k] = ldc(x + base + sb * 12 + k);
+        if (xt) b[k] = b[k] - ldc(xt + base + sb * 12 + k);
+      }
+      const cx<double> vb = ps_half<false>(a, b, ps_link(U, g, cb[0], cb[1], cb[2], cb[3], mu), Vh, mu);
+      const cx<double> v = kappa * (vb - vf);
+      // (mu is a runtime index: accumulate through a small switch-free select)
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        if (m == mu) {
+          acc[2 * m] += v.re;
+          acc[2 * m + 1] += v.im;
+        }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 2 * kNumPS; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 2 * kNumPS; ++k) sh[k][wave] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < 2 * kNumPS) {
+    double v = 0;
+    for (int w = 0; w < kWaves; ++w) v += sh[threadIdx.x][w];
+    const int mu = threadIdx.x / 2, part = threadIdx.x % 2;
+    out[((size_t(r) * kNumOps + kNumTheta + mu) * Lt + t) * 2 + part] = v;
   }
 }
 
@@ -80,16 +147,27 @@ extern "C" lqcd_status loop_estimate(lqcd_ctx *c, const int *thetas, int nth, co
     LQCD_CHECK(nrhs >= 1, LQCD_EINVAL, "loop_estimate: need at least one noise vector");
     LQCD_CHECK(nth >= 1 && thetas, LQCD_EINVAL, "loop_estimate: no operator");
     for (int a = 0; a < nth; ++a)
-      LQCD_CHECK(thetas[a] >= 0 && thetas[a] < kNumTheta, LQCD_EINVAL, "theta code %d outside 0..4",
+      LQCD_CHECK(thetas[a] >= 0 && thetas[a] < kNumOps, LQCD_EINVAL, "operator code %d outside 0..8",
                  thetas[a]);
+    bool any_local = false, any_ps = false;
+    for (int a = 0; a < nth; ++a) (thetas[a] < kNumTheta ? any_local : any_ps) = true;
     const Geom &g = c->g;
     const int Lt = g.L[3], Vs = g.V / Lt;
-    double *d = static_cast<double *>(c->red.ensure(size_t(nrhs) * kNumTheta * Lt * 2 * sizeof(double)));
-    hipLaunchKernelGGL(k_estimate, dim3(Lt, nrhs), dim3(kBlock), 0, c->stream,
-                       static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x),
-                       static_cast<const cx<double> *>(xt), size_t(g.V), Vs, Lt, d);
-    LQCD_HIP(hipGetLastError());
-    std::vector<double> h(size_t(nrhs) * kNumTheta * Lt * 2);
+    double *d = static_cast<double *>(c->red.ensure(size_t(nrhs) * kNumOps * Lt * 2 * sizeof(double)));
+    if (any_local) {
+      hipLaunchKernelGGL(k_estimate, dim3(Lt, nrhs), dim3(kBlock), 0, c->stream,
+                         static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x),
+                         static_cast<const cx<double> *>(xt), size_t(g.V), Vs, Lt, d);
+      LQCD_HIP(hipGetLastError());
+    }
+    if (any_ps) {
+      hipLaunchKernelGGL(k_estimate_ps, dim3(Lt, nrhs), dim3(kBlock), 0, c->stream, g,
+                         static_cast<const cx<double> *>(c->U64.ptr), c->kappa,
+                         static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x),
+                         static_cast<const cx<double> *>(xt), d);
+      LQCD_HIP(hipGetLastError());
+    }
+    std::vector<double> h(size_t(nrhs) * kNumOps * Lt * 2);
     LQCD_HIP(hipMemcpyAsync(h.data(), d, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     LQCD_HIP(hipStreamSynchronize(c->stream));
     const int W = Lt + 1;
@@ -99,7 +177,7 @@ extern "C" lqcd_status loop_estimate(lqcd_ctx *c, const int *thetas, int nth, co
       for (int a = 0; a < nth; ++a) {
         cdouble tot = 0;
         for (int t = 0; t < Lt; ++t) {
-          size_t o = ((size_t(n) * kNumTheta + thetas[a]) * Lt + t) * 2;
+          size_t o = ((size_t(n) * kNumOps + thetas[a]) * Lt + t) * 2;
           cdouble v(h[o], h[o + 1]);
           smp[(size_t(n) * nth + a) * W + t] = v;
           tot += v;

@@ -22,12 +22,19 @@
 // The paper obtains the same traces from unit-vector sources (Eqs.
 // (32)-(35)); the walk sum is that computation with every source's
 // non-returning paths dropped.
+//
+// Point-split operators (codes 5..8): Theta(mu) = kappa (backward minus
+// forward hop along mu), so Tr(Theta(mu) P^j) is kappa times the sum over
+// closed walks of length j + 1 whose first step runs along mu, each with
+// tr(S_w) tr W_w(x) and the sign +1 for a backward, -1 for a forward first
+// step.  Only odd j contribute (walks of even length), up to j = 7.
 #include <algorithm>
 #include <cmath>
 
 #include "cplx.h"
 #include "fields.h"
 #include "gamma.h"
+#include "pointsplit.h"
 #include "smallla.h"
 #include "solver.h"
 
@@ -36,12 +43,12 @@ namespace lqcd {
 namespace {
 
 // ---------------------------------------------------------- walk tables
-constexpr int kMaxWalkLen = 6;  // closed walks of length <= 6 (orders <= 7)
+constexpr int kMaxWalkLen = 8;  // local: length <= 6 (orders <= 7); point-split: <= 8
 
 struct Walk {
   int len;
-  int dir[kMaxWalkLen];       // 2 * mu + (0: +mu, 1: -mu)
-  double coef[kNumTheta][2];  // tr(Theta S_w), Theta = 1, g1..g4
+  int dir[kMaxWalkLen];     // 2 * mu + (0: +mu, 1: -mu)
+  double coef[kNumOps][2];  // tr(Theta S_w) for Theta = 1, g1..g4; point-split: +-tr(S_w)
 };
 
 using Spin = std::complex<double>[4][4];
@@ -64,6 +71,14 @@ void enumerate(int len, const int L[4], int depth, int last, int disp[4], const 
       w.coef[th][0] = t.real();
       w.coef[th][1] = t.imag();
       if (std::abs(t) > 1e-12) any = true;
+    }
+    std::complex<double> trS = 0;
+    for (int a = 0; a < 4; ++a) trS += S[a][a];
+    for (int mu = 0; mu < kNumPS; ++mu) {
+      const double sg = (dirs[0] >> 1) != mu ? 0.0 : ((dirs[0] & 1) ? 1.0 : -1.0);
+      w.coef[kNumTheta + mu][0] = sg * trS.real();
+      w.coef[kNumTheta + mu][1] = sg * trS.imag();
+      if (sg != 0.0 && std::abs(trS) > 1e-12) any = true;
     }
     if (any) out.push_back(w);
     return;
@@ -114,7 +129,7 @@ __global__ void __launch_bounds__(kBlock)
   const size_t Vh = g.Vh;
   const int x0 = s % g.L[0], y0 = (s / g.L[0]) % g.L[1], z0 = (s / (g.L[0] * g.L[1])) % g.L[2],
             t0 = s / (g.L[0] * g.L[1] * g.L[2]);
-  double acc[kNumTheta][2] = {};
+  double acc[kNumOps][2] = {};
   for (int w = 0; w < nwalk; ++w) {
     const Walk &wk = walks[w];
     int c[4] = {x0, y0, z0, t0};
@@ -156,13 +171,13 @@ __global__ void __launch_bounds__(kBlock)
     }
     const cx<double> tr = W[0][0] + W[1][1] + W[2][2];
 #pragma unroll
-    for (int th = 0; th < kNumTheta; ++th) {
+    for (int th = 0; th < kNumOps; ++th) {
       acc[th][0] += wk.coef[th][0] * tr.re - wk.coef[th][1] * tr.im;
       acc[th][1] += wk.coef[th][0] * tr.im + wk.coef[th][1] * tr.re;
     }
   }
 #pragma unroll
-  for (int th = 0; th < kNumTheta; ++th) out[size_t(th) * g.V + s] = mk(acc[th][0], acc[th][1]);
+  for (int th = 0; th < kNumOps; ++th) out[size_t(th) * g.V + s] = mk(acc[th][0], acc[th][1]);
 }
 
 constexpr int kWaves = kBlock / 64;
@@ -241,6 +256,43 @@ __global__ void __launch_bounds__(kBlock)
   for (int th = 0; th < kNumTheta; ++th) out[size_t(th) * g.V + s] = mk(acc[th][0], acc[th][1]);
 }
 
+// Point-split bilinears of the hermitian-forced trace terms:
+// out[mu][s] = e(s)^+ (Theta(mu) g5 e)(s) for one mode e in the even/odd
+// layout (full field), s lexicographic.
+__global__ void __launch_bounds__(kBlock)
+    k_eig_bilinear_ps(Geom g, const cx<double> *__restrict__ U, double kappa,
+                      const cx<double> *__restrict__ E, cx<double> *__restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const int Ls[4] = {g.L[0], g.L[1], g.L[2], g.L[3]};
+  const int c[4] = {s % Ls[0], (s / Ls[0]) % Ls[1], (s / (Ls[0] * Ls[1])) % Ls[2], s / (Ls[0] * Ls[1] * Ls[2])};
+  const size_t Vh = g.Vh;
+  auto load = [&](const int cc[4], cx<double> v[12], bool gam5) {
+    const int p = (cc[0] + cc[1] + cc[2] + cc[3]) & 1;
+    const int sl = cc[0] + Ls[0] * (cc[1] + Ls[1] * (cc[2] + Ls[2] * cc[3]));
+    const size_t off = size_t(p) * 12 * Vh + size_t(sl >> 1);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      v[k] = E[off + k * Vh];
+      if (gam5 && k >= 6) v[k] = -v[k];
+    }
+  };
+  cx<double> a[12];
+  load(c, a, false);
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    int cf[4] = {c[0], c[1], c[2], c[3]}, cb[4] = {c[0], c[1], c[2], c[3]};
+    cf[mu] = c[mu] + 1 == Ls[mu] ? 0 : c[mu] + 1;
+    cb[mu] = c[mu] == 0 ? Ls[mu] - 1 : c[mu] - 1;
+    cx<double> b[12];
+    load(cf, b, true);
+    const cx<double> vf = ps_half<true>(a, b, ps_link(U, g, c[0], c[1], c[2], c[3], mu), Vh, mu);
+    load(cb, b, true);
+    const cx<double> vb = ps_half<false>(a, b, ps_link(U, g, cb[0], cb[1], cb[2], cb[3], mu), Vh, mu);
+    out[size_t(mu) * g.V + s] = kappa * (vb - vf);
+  }
+}
+
 // In place g5 on full even/odd fields: negate spins 2, 3 (components 6..11).
 __global__ void k_g5_eo(cx<double> *__restrict__ f, size_t Vh, size_t stride, int nf) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -274,22 +326,24 @@ std::vector<cdouble> timeslice_rows(lqcd_ctx *c, const void *site, int nrow, Dev
   return h;
 }
 
-// Tr_t(Theta P^j) for j = 0..kMaxOrder, filled once per context.
+// Tr_t(Theta P^j) for j = 0..kMaxOrder and every operator code, filled
+// once per context (point-split rows without their factor kappa).
 void ensure_walk_traces(lqcd_ctx *c) {
   if (c->have_walk_traces) return;
   const Geom &g = c->g;
   const int Lt = g.L[3], Vs = g.V / Lt;
-  std::vector<cdouble> T(size_t(kMaxOrder + 1) * kNumTheta * Lt, 0.0);
-  for (int t = 0; t < Lt; ++t) T[0 * kNumTheta * Lt + 0 * Lt + t] = 12.0 * Vs;  // Tr(1) per slice
+  std::vector<cdouble> T(size_t(kMaxOrder + 1) * kNumOps * Lt, 0.0);
+  for (int t = 0; t < Lt; ++t) T[0 * kNumOps * Lt + 0 * Lt + t] = 12.0 * Vs;  // Tr(1) per slice
   DevBuf site, walks, tmp;
-  site.ensure(size_t(kNumTheta) * g.V * sizeof(cdouble));
-  for (int j = 1; j <= kMaxOrder; ++j) {
-    if (j % 2 == 1 || j > kMaxWalkLen) continue;  // odd walks cannot close on even extents
+  site.ensure(size_t(kNumOps) * g.V * sizeof(cdouble));
+  // odd walks cannot close on even extents; a walk of length len gives the
+  // local rows of order len and the point-split rows of order len - 1
+  for (int len = 2; len <= kMaxWalkLen; len += 2) {
     std::vector<Walk> ws;
     int disp[4] = {0, 0, 0, 0}, dirs[kMaxWalkLen];
     std::complex<double> I[4][4];
     gamma_dense(0, I);
-    enumerate(j, g.L, 0, -1, disp, I, dirs, ws);
+    enumerate(len, g.L, 0, -1, disp, I, dirs, ws);
     if (ws.empty()) continue;
     walks.ensure(ws.size() * sizeof(Walk));
     h2d(c, walks.ptr, ws.data(), ws.size() * sizeof(Walk));
@@ -297,15 +351,19 @@ void ensure_walk_traces(lqcd_ctx *c) {
                        static_cast<const cx<double> *>(c->U64.ptr), walks.as<Walk>(), int(ws.size()),
                        site.as<cx<double>>());
     LQCD_HIP(hipGetLastError());
-    std::vector<cdouble> ts = timeslice_rows(c, site.ptr, kNumTheta, tmp);
-    for (int th = 0; th < kNumTheta; ++th)
-      for (int t = 0; t < Lt; ++t) T[(size_t(j) * kNumTheta + th) * Lt + t] = ts[size_t(th) * Lt + t];
+    std::vector<cdouble> ts = timeslice_rows(c, site.ptr, kNumOps, tmp);
+    for (int th = 0; th < kNumOps; ++th) {
+      const int j = th < kNumTheta ? len : len - 1;
+      if (j > kMaxOrder) continue;
+      for (int t = 0; t < Lt; ++t) T[(size_t(j) * kNumOps + th) * Lt + t] = ts[size_t(th) * Lt + t];
+    }
   }
   c->walk_traces = T;
   c->have_walk_traces = true;
 }
 
-// corr[th][t] = sum_j coeffs[j] kappa^j Tr_t(Theta_th P^j)
+// corr[th][t] = sum_j coeffs[j] kappa^j Tr_t(Theta_th P^j)  (point-split:
+// times the operator's own kappa)
 void poly_trace(lqcd_ctx *c, const std::vector<cdouble> &coeffs, const int *thetas, int nth,
                 double *corr_host) {
   ensure_walk_traces(c);
@@ -315,7 +373,8 @@ void poly_trace(lqcd_ctx *c, const std::vector<cdouble> &coeffs, const int *thet
       cdouble s = 0;
       double kj = 1;
       for (size_t j = 0; j < coeffs.size(); ++j, kj *= c->kappa)
-        s += coeffs[j] * kj * c->walk_traces[(j * kNumTheta + thetas[a]) * Lt + t];
+        s += coeffs[j] * kj * c->walk_traces[(j * kNumOps + thetas[a]) * Lt + t];
+      if (thetas[a] >= kNumTheta) s *= c->kappa;
       corr_host[2 * (a * Lt + t)] = s.real();
       corr_host[2 * (a * Lt + t) + 1] = s.imag();
     }
@@ -342,7 +401,7 @@ cx<double> *horner(lqcd_ctx *c, const std::vector<cdouble> &coeffs, const cx<dou
 void check_thetas(const int *th, int nth) {
   LQCD_CHECK(nth >= 0 && (nth == 0 || th), LQCD_EINVAL, "thetas: null or negative count");
   for (int a = 0; a < nth; ++a)
-    LQCD_CHECK(th[a] >= 0 && th[a] < kNumTheta, LQCD_EINVAL, "theta code %d outside 0..4", th[a]);
+    LQCD_CHECK(th[a] >= 0 && th[a] < kNumOps, LQCD_EINVAL, "operator code %d outside 0..8", th[a]);
 }
 
 // xt (lex) = p(kappa P) eta (lex) for nrhs fields, in blocks.
@@ -524,24 +583,28 @@ extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_de
     // per-mode bilinears (computed once per set of eigenpairs)
     if (corr && nth > 0) {
       if (d->bil.empty()) {
-        d->bil.assign(size_t(Q) * kNumTheta * Lt, 0.0);
+        d->bil.assign(size_t(Q) * kNumOps * Lt, 0.0);
         cdouble one(1, 0);
         cdouble *wd = static_cast<cdouble *>(c->ws[6].ensure(sizeof(cdouble)));
         h2d(c, wd, &one, sizeof(cdouble));
-        cx<double> *site = static_cast<cx<double> *>(c->ws[7].ensure(size_t(kNumTheta) * c->g.V * sizeof(cdouble)));
+        cx<double> *site = static_cast<cx<double> *>(c->ws[7].ensure(size_t(kNumOps) * c->g.V * sizeof(cdouble)));
         DevBuf tmp;
         for (int q = 0; q < Q; ++q) {
           hipLaunchKernelGGL(k_eig_bilinear, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g,
                              E + size_t(q) * fl, fl, 1, reinterpret_cast<const cx<double> *>(wd), site);
           LQCD_HIP(hipGetLastError());
-          std::vector<cdouble> ts = timeslice_rows(c, site, kNumTheta, tmp);
-          std::copy(ts.begin(), ts.end(), d->bil.begin() + size_t(q) * kNumTheta * Lt);
+          hipLaunchKernelGGL(k_eig_bilinear_ps, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g,
+                             static_cast<const cx<double> *>(c->U64.ptr), c->kappa, E + size_t(q) * fl,
+                             site + size_t(kNumTheta) * c->g.V);
+          LQCD_HIP(hipGetLastError());
+          std::vector<cdouble> ts = timeslice_rows(c, site, kNumOps, tmp);
+          std::copy(ts.begin(), ts.end(), d->bil.begin() + size_t(q) * kNumOps * Lt);
         }
       }
       for (int a = 0; a < nth; ++a)
         for (int t = 0; t < Lt; ++t) {
           cdouble v = 0;
-          for (int q = 0; q < Q; ++q) v += w[q] * d->bil[(size_t(q) * kNumTheta + thetas[a]) * Lt + t];
+          for (int q = 0; q < Q; ++q) v += w[q] * d->bil[(size_t(q) * kNumOps + thetas[a]) * Lt + t];
           corr[2 * (a * Lt + t)] += v.real();
           corr[2 * (a * Lt + t) + 1] += v.imag();
         }

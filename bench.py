@@ -14,7 +14,8 @@ true residual (mixed: FP32 inner solves in FP64 refinement, the inner
 basis and stencil input optionally stored in FP16/BF16 with per-site
 scales; or plain FP64), odd-site reconstruction and FP64 true residual,
 PS / POLY / HFES / HFPS / HFPOLY subtraction vectors and the estimator for
-Theta = 1, g1..g4.  Untimed afterwards: every precision solves the same
+the nine operators of Table 2 (scalar, local vector g1..g4, point-split
+vector in x, y, z, t).  Untimed afterwards: every precision solves the same
 noise batch and reports its estimates' difference from plain FP64 and one
 solution's residual under the FP64 oracle's operator.
 
@@ -36,7 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-THETAS = (0, 1, 2, 3, 4)
+THETAS = (0, 1, 2, 3, 4, 5, 6, 7, 8)  # scalar, local vector g1..g4, point-split vector x, y, z, t
 
 
 def workload(name, kappa_override=None):

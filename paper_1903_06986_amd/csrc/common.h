@@ -125,7 +125,8 @@ struct lqcd_ctx {
   lqcd::DevBuf U64, U32;
   // Exact per-timeslice traces Tr_t(Theta P^j), j = 0..kMaxOrder,
   // Theta = 1, g1..g4: host [j][theta][Lt], filled on first use.
-  bool have_walk_traces = false;
+  bool have_walk_traces = false;  // orders from walks of length <= 6
+  bool have_walk_len8 = false;    // point-split order 7 (walks of length 8)
   std::vector<lqcd::cdouble> walk_traces;
   // Scratch buffers reused across calls (grown on demand).
   lqcd::DevBuf ws[8];

@@ -328,17 +328,24 @@ std::vector<cdouble> timeslice_rows(lqcd_ctx *c, const void *site, int nrow, Dev
 
 // Tr_t(Theta P^j) for j = 0..kMaxOrder and every operator code, filled
 // once per context (point-split rows without their factor kappa).
-void ensure_walk_traces(lqcd_ctx *c) {
-  if (c->have_walk_traces) return;
+// The walks of length 8 (36k per site) serve only the point-split rows of
+// order 7 and are enumerated when such a row is first asked for.
+void ensure_walk_traces(lqcd_ctx *c, bool need_len8) {
+  if (c->have_walk_traces && (!need_len8 || c->have_walk_len8)) return;
   const Geom &g = c->g;
   const int Lt = g.L[3], Vs = g.V / Lt;
-  std::vector<cdouble> T(size_t(kMaxOrder + 1) * kNumOps * Lt, 0.0);
-  for (int t = 0; t < Lt; ++t) T[0 * kNumOps * Lt + 0 * Lt + t] = 12.0 * Vs;  // Tr(1) per slice
+  if (!c->have_walk_traces) {
+    c->walk_traces.assign(size_t(kMaxOrder + 1) * kNumOps * Lt, 0.0);
+    for (int t = 0; t < Lt; ++t) c->walk_traces[t] = 12.0 * Vs;  // Tr(1) per slice
+  }
+  std::vector<cdouble> &T = c->walk_traces;
   DevBuf site, walks, tmp;
   site.ensure(size_t(kNumOps) * g.V * sizeof(cdouble));
   // odd walks cannot close on even extents; a walk of length len gives the
   // local rows of order len and the point-split rows of order len - 1
-  for (int len = 2; len <= kMaxWalkLen; len += 2) {
+  const int len0 = c->have_walk_traces ? kMaxWalkLen : 2;
+  const int len1 = need_len8 ? kMaxWalkLen : kMaxWalkLen - 2;
+  for (int len = len0; len <= len1; len += 2) {
     std::vector<Walk> ws;
     int disp[4] = {0, 0, 0, 0}, dirs[kMaxWalkLen];
     std::complex<double> I[4][4];
@@ -358,15 +365,17 @@ void ensure_walk_traces(lqcd_ctx *c) {
       for (int t = 0; t < Lt; ++t) T[(size_t(j) * kNumOps + th) * Lt + t] = ts[size_t(th) * Lt + t];
     }
   }
-  c->walk_traces = T;
   c->have_walk_traces = true;
+  if (need_len8) c->have_walk_len8 = true;
 }
 
 // corr[th][t] = sum_j coeffs[j] kappa^j Tr_t(Theta_th P^j)  (point-split:
 // times the operator's own kappa)
 void poly_trace(lqcd_ctx *c, const std::vector<cdouble> &coeffs, const int *thetas, int nth,
                 double *corr_host) {
-  ensure_walk_traces(c);
+  bool ps = false;
+  for (int a = 0; a < nth; ++a) ps = ps || thetas[a] >= kNumTheta;
+  ensure_walk_traces(c, ps && coeffs.size() > size_t(kMaxWalkLen - 1));
   const int Lt = c->g.L[3];
   for (int a = 0; a < nth; ++a)
     for (int t = 0; t < Lt; ++t) {

@@ -338,14 +338,24 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * every right-hand side), 0 keeps the lane-grouped form.
  * LQCD_TUNE_HOP_ORDER: workgroup order of the lane-grouped form, 0
  * (default) = right-hand-side groups of a site block back to back, 1 =
- * site blocks of a right-hand side back to back.  Values are per context;
- * EINVAL for other values. */
+ * site blocks of a right-hand side back to back.
+ * LQCD_TUNE_HOP_TBLOCK64 / LQCD_TUNE_HOP_TBLOCK32: tile order of the
+ * link-tiled stencil, 0 = tiles of consecutive sites in index order, n > 0
+ * = tiles within one (z, t) plane, ordered by blocks of n timeslices, z
+ * within a block, t fastest (up to 1024); -1 (default) = planes with
+ * ceil(Lt / 8) timeslices per block when a plane (Lx / 2 * Ly sites) splits
+ * into whole tiles and Lt >= 8, else index order.  LQCD_TUNE_HOP_TSITES32:
+ * sites per FP32 tile, 32 (default) or 64.  Values are per context; EINVAL
+ * for other values. */
 typedef enum {
   LQCD_TUNE_HOP_NB64 = 0,
   LQCD_TUNE_HOP_NB32 = 1,
   LQCD_TUNE_HOP_TILE64 = 2,
   LQCD_TUNE_HOP_TILE32 = 3,
-  LQCD_TUNE_HOP_ORDER = 4
+  LQCD_TUNE_HOP_ORDER = 4,
+  LQCD_TUNE_HOP_TBLOCK64 = 5,
+  LQCD_TUNE_HOP_TBLOCK32 = 6,
+  LQCD_TUNE_HOP_TSITES32 = 7
 } lqcd_tune_param;
 lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 

@@ -184,6 +184,16 @@ extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int val
         LQCD_CHECK(value == 0 || value == 1, LQCD_EINVAL, "lqcd_tune_set: block order must be 0 or 1");
         c->hop_order = value;
         break;
+      case LQCD_TUNE_HOP_TBLOCK64:
+      case LQCD_TUNE_HOP_TBLOCK32:
+        LQCD_CHECK(value >= -1 && value <= 1024, LQCD_EINVAL,
+                   "lqcd_tune_set: timeslices per plane block must be in -1..1024");
+        c->hop_tblock[param == LQCD_TUNE_HOP_TBLOCK64 ? 0 : 1] = value;
+        break;
+      case LQCD_TUNE_HOP_TSITES32:
+        LQCD_CHECK(value == 32 || value == 64, LQCD_EINVAL, "lqcd_tune_set: sites per FP32 tile must be 32 or 64");
+        c->hop_tsites32 = value;
+        break;
       default:
         LQCD_CHECK(false, LQCD_EINVAL, "lqcd_tune_set: unknown parameter %d", int(param));
     }

@@ -75,4 +75,20 @@ __device__ inline void stc(cx<R> *p, cx<R> a) {
   *reinterpret_cast<typename vec2<R>::type *>(p) = v;
 }
 
+// Non-temporal forms (streamed data that is not read again soon).
+template <class R>
+__device__ inline cx<R> ldc_nt(const cx<R> *p) {
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+  return {v.x, v.y};
+}
+template <class R>
+__device__ inline void stc_nt(cx<R> *p, cx<R> a) {
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  v2 v;
+  v.x = a.re;
+  v.y = a.im;
+  __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
+}
+
 }  // namespace lqcd

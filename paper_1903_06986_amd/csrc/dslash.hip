@@ -117,40 +117,83 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
 }
 
 // Link-tiled form for many right-hand sides: a workgroup owns T
-// consecutive output sites, stages their 8 links (4 forward at the sites,
-// 4 backward at the neighbours x - mu) in LDS once, then applies the
-// stencil to every right-hand side, RS = 256 / T of them at a time.  The
-// lane index is the site within the tile, so each spinor access of a wave
-// is one contiguous run of sites, and the links cross HBM once per launch
-// instead of once per right-hand side.
-template <class R, int MU, bool G5IN, class Src>
-__device__ inline void hop_dir_tile(cx<R> acc[4][3], const cx<R> *sU, int T, const Src &in, int nf,
-                                    int nb, size_t Vh) {
-  Half<R> h, g;
-  project<R, MU, true, G5IN>(in, nf, Vh, h);
-  link_mul<R>(sU + (MU * 9) * T, T, h, g);
-  accumulate<R, MU, true>(acc, g);
-  fence(acc);
-  project<R, MU, false, G5IN>(in, nb, Vh, h);
-  link_dag_mul<R>(sU + ((4 + MU) * 9) * T, T, h, g);
-  accumulate<R, MU, false>(acc, g);
+// consecutive output sites (T = 32 or 64), stages their 8 links (4 forward
+// at the sites, 4 backward at the neighbours x - mu) in LDS once, then
+// applies the stencil to every right-hand side, RS = 256 / T of them at a
+// time.  The lane index is the site within the tile, so each spinor access
+// of a wave is one contiguous run of sites, and the links cross HBM once
+// per launch instead of once per right-hand side.  Field accesses use a
+// wave-uniform base (the wave's first right-hand side) and 32-bit lane byte
+// offsets (the host checks that they fit).
+// One of the 8 terms of the stencil (LEG = 2 mu + 0 forward / 1 backward)
+// from a settled raw neighbour, with its link from the LDS tile.
+template <class R, int LEG, bool G5IN, class RawT>
+__device__ inline void hop_leg(cx<R> acc[4][3], const cx<R> *sU, int T, const RawT &raw) {
+  constexpr int MU = LEG / 2;
+  constexpr bool FWD = (LEG % 2) == 0;
+  Half<R> h;
+  project_raw<R, MU, FWD, G5IN>(raw, h);
+  link_accumulate<R, MU, FWD>(acc, sU + ((FWD ? 0 : 4) + MU) * 9 * T, T, h);
+}
+
+// Step LEG of the software pipeline over the 8 neighbours: the loads of
+// neighbour LEG + 2 go out into the buffer that LEG has just consumed, so
+// two neighbours' loads are in flight while one is computed.
+template <class R, int LEG, bool G5IN, class Src>
+__device__ inline void hop_step(cx<R> acc[4][3], const cx<R> *sU, int T, const Src &in,
+                                const uint32_t off[8], size_t Vh, Raw<Src> &buf) {
+  settle(buf);
+  hop_leg<R, LEG, G5IN>(acc, sU, T, buf);
+  if (LEG + 2 < 8) fetch_at(in, off[LEG + 2 < 8 ? LEG + 2 : 0], Vh, buf);
   fence(acc);
 }
 
+// Tile order of k_hop_tile.  tb == 0: tiles are T consecutive sites of the
+// half lattice in index order.  tb > 0 (plane-blocked): a tile lies in one
+// (z, t) plane of ppl = Lxh * Ly sites (nbp tiles per plane, the last one
+// ragged), and the tile sequence runs over blocks of tb timeslices, z
+// within a block, t fastest: the planes whose spinors a tile reads through
+// its z and t neighbours are then at most tb planes of the sequence away,
+// so they are still in the XCD's L2 when the next tile needs them.
+struct TileMap {
+  int tb, nbp, ppl;
+};
+
 template <class R, bool G5IN, bool G5OUT, bool SELF, int T, class SrcIn, class SrcSelf>
+// 3 waves per SIMD (168 VGPRs): room for two raw neighbours in flight
+// without spills.
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8)))
     k_hop_tile(Geom g, int p, const cx<R> *U, SrcIn in, SrcSelf self, cx<R> *out, cx<R> alpha,
-               R beta, size_t in_stride, size_t self_stride, size_t out_stride, int nrhs, int xq) {
-  constexpr int RS = kBlock / T;
+               R beta, size_t in_stride, size_t self_stride, size_t out_stride, int nrhs, int xq,
+               TileMap tm) {
+  static_assert(T == 32 || T == 64, "tile of 32 or 64 sites");
+  constexpr int RS = kBlock / T;    // right-hand sides per pass
+  constexpr int SPW = 64 / T;       // right-hand-side slots per wave
+  constexpr bool PIPE = sizeof(R) == 4;  // two neighbours' loads in flight (FP64: one)
   __shared__ cx<R> sU[8 * 9 * T];  // [direction: 4 forward, 4 backward][entry][site]
   // XCD-aware tile order (as in k_hop): each XCD walks one contiguous range
   const int tile = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
-  const int i0 = tile * T;
-  if (i0 >= g.Vh) return;  // whole workgroup: padding of the grid
+  int i0, lim;
+  if (tm.tb == 0) {
+    i0 = tile * T;
+    lim = g.Vh;
+  } else {
+    const int b = tile % tm.nbp;
+    int q = tile / tm.nbp;
+    const int tt = q % tm.tb;
+    q /= tm.tb;
+    const int z = q % g.L[2], t = (q / g.L[2]) * tm.tb + tt;
+    if (t >= g.L[3]) return;  // whole workgroup: a partial last block of timeslices
+    const int pb = (t * g.L[2] + z) * tm.ppl;
+    i0 = pb + b * T;
+    lim = pb + tm.ppl;
+  }
+  if (i0 >= lim) return;  // whole workgroup: padding of the grid
   const size_t Vh = size_t(g.Vh);
   const int il = threadIdx.x % T, slot = threadIdx.x / T;
+  const int slot0 = __builtin_amdgcn_readfirstlane(int(threadIdx.x / 64)) * SPW;  // wave's first slot
   const int i = i0 + il;
-  const bool site_ok = i < g.Vh;
+  const bool site_ok = i < lim;
   const int Lxh = g.Lxh, Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
   int nf[4] = {0, 0, 0, 0}, nb[4] = {0, 0, 0, 0};
   if (site_ok) {
@@ -178,51 +221,83 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
       const int d = q / 9, e = q % 9;
       const size_t src = d < 4 ? ((size_t(p) * 4 + d) * 9 + e) * Vh + i
                                : ((size_t(1 - p) * 4 + (d - 4)) * 9 + e) * Vh + nb[d - 4];
-      sU[q * T + il] = U[src];
+      sU[q * T + il] = ldc_nt(U + src);  // read once per launch: keep L2 for the spinors
     }
   }
   __syncthreads();
   if (!site_ok) return;
   const cx<R> *su = sU + il;
+  // lane byte offsets within the wave's fields (loop-invariant)
+  const uint32_t sl = uint32_t(slot - slot0);
+  const uint32_t ib = sl * uint32_t(in_stride * SrcIn::kBytes), sb = sl * uint32_t(self_stride * SrcSelf::kBytes),
+                 ob = sl * uint32_t(out_stride * sizeof(cx<R>));
+  uint32_t of[4], obk[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    of[d] = ib + uint32_t(nf[d]) * SrcIn::kBytes;
+    obk[d] = ib + uint32_t(nb[d]) * SrcIn::kBytes;
+  }
+  const uint32_t so = sb + uint32_t(i) * SrcSelf::kBytes, oo = ob + uint32_t(i) * uint32_t(sizeof(cx<R>));
 #pragma unroll 1
-  for (int rr = slot; rr < nrhs; rr += RS) {
-    const size_t rhs = rr;
-    const SrcIn inr = in.at(rhs * in_stride);
+  for (int r0 = slot0; r0 < nrhs; r0 += RS) {
+    if (r0 + int(sl) >= nrhs) break;  // this lane's right-hand side is past the end
+    const size_t rw = size_t(r0);     // wave-uniform
+    const SrcIn inr = in.at(rw * in_stride);
     cx<R> acc[4][3];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[s][c] = mk<R>(0, 0);
-    // Neighbour indices pass through an empty asm each iteration: otherwise
-    // the compiler hoists all 96 per-component address offsets out of the
-    // right-hand-side loop and the register file overflows.
-    int nfl[4], nbl[4];
+    // Offsets pass through an empty asm each iteration so that the compiler
+    // does not hoist per-component addresses out of the loop.  Order of the
+    // neighbours: x forward, x backward, y forward, ..., t backward.
+    uint32_t off[8];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-      nfl[d] = nf[d];
-      nbl[d] = nb[d];
-      asm volatile("" : "+v"(nfl[d]), "+v"(nbl[d]));
+      off[2 * d] = of[d];
+      off[2 * d + 1] = obk[d];
+      asm volatile("" : "+v"(off[2 * d]), "+v"(off[2 * d + 1]));
     }
-    hop_dir_tile<R, 0, G5IN>(acc, su, T, inr, nfl[0], nbl[0], Vh);
-    hop_dir_tile<R, 1, G5IN>(acc, su, T, inr, nfl[1], nbl[1], Vh);
-    hop_dir_tile<R, 2, G5IN>(acc, su, T, inr, nfl[2], nbl[2], Vh);
-    hop_dir_tile<R, 3, G5IN>(acc, su, T, inr, nfl[3], nbl[3], Vh);
-    cx<R> *o = out + rhs * out_stride;
     SrcSelf sr = self;
-    if (SELF) sr = self.at(rhs * self_stride);
-    const typename SrcSelf::Ctx ssc = SELF ? sr.site(i) : typename SrcSelf::Ctx{};
+    if (SELF) sr = self.at(rw * self_stride);
+    Raw<SrcSelf> rs;
+    Raw<SrcIn> ra, rb;
+    fetch_at(inr, off[0], Vh, ra);
+    if (PIPE) fetch_at(inr, off[1], Vh, rb);
+    if constexpr (PIPE) {
+      hop_step<R, 0, G5IN>(acc, su, T, inr, off, Vh, ra);
+      hop_step<R, 1, G5IN>(acc, su, T, inr, off, Vh, rb);
+      hop_step<R, 2, G5IN>(acc, su, T, inr, off, Vh, ra);
+      hop_step<R, 3, G5IN>(acc, su, T, inr, off, Vh, rb);
+      hop_step<R, 4, G5IN>(acc, su, T, inr, off, Vh, ra);
+      hop_step<R, 5, G5IN>(acc, su, T, inr, off, Vh, rb);
+      hop_step<R, 6, G5IN>(acc, su, T, inr, off, Vh, ra);
+      if (SELF) fetch_at(sr, so, Vh, rs);  // the self term takes the freed buffer's place
+      hop_step<R, 7, G5IN>(acc, su, T, inr, off, Vh, rb);
+    } else {  // one neighbour at a time (FP64: two raw sites would cost occupancy)
+#define LQCD_LEG(L)                                        \
+  settle(ra);                                             \
+  hop_leg<R, L, G5IN>(acc, su, T, ra);                     \
+  if (L + 1 < 8) fetch_at(inr, off[L + 1 < 8 ? L + 1 : 0], Vh, ra); \
+  fence(acc);
+      LQCD_LEG(0) LQCD_LEG(1) LQCD_LEG(2) LQCD_LEG(3) LQCD_LEG(4) LQCD_LEG(5) LQCD_LEG(6) LQCD_LEG(7)
+#undef LQCD_LEG
+      if (SELF) fetch_at(sr, so, Vh, rs);
+    }
+    char *o = reinterpret_cast<char *>(out + rw * out_stride);
+    if (SELF) settle(rs);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         cx<R> v = beta * acc[s][c];
         if (SELF) {
-          cx<R> w = sr.ld(ssc, i, s * 3 + c, Vh);
+          cx<R> w = rs.get(s * 3 + c);
           if (G5IN && s >= 2) w = -w;
           v = v + alpha * w;
         }
         if (G5OUT && s >= 2) v = -v;
-        stc(o + (s * 3 + c) * Vh + i, v);
+        stc_nt(reinterpret_cast<cx<R> *>(o + (s * 3 + c) * Vh * sizeof(cx<R>) + oo), v);
       }
   }
 }
@@ -231,11 +306,22 @@ template <class R, bool A, bool B, bool C, int T, class SI, class SS>
 void launch_hop_tile(lqcd_ctx *c, Timed &tm, int p, const cx<R> *U, SI in, SS self, void *out,
                      cdouble alpha, double beta, int nrhs, size_t si, size_t ss, size_t so) {
   const Geom &g = c->g;
-  const int ntile = int((g.Vh + T - 1) / T);
+  TileMap map{c->hop_tblock[std::is_same<R, double>::value ? 0 : 1], 0, g.Lxh * g.L[1]};
+  if (map.tb < 0)  // automatic: plane order when planes split into whole tiles, one block per XCD
+    map.tb = (map.ppl % T == 0 && g.L[3] >= 8) ? (g.L[3] + 7) / 8 : 0;
+  int ntile;
+  if (map.tb > 0) {
+    map.tb = std::min(map.tb, g.L[3]);
+    map.nbp = (map.ppl + T - 1) / T;
+    const int nblk = (g.L[3] + map.tb - 1) / map.tb;
+    ntile = nblk * map.tb * g.L[2] * map.nbp;
+  } else {
+    ntile = int((g.Vh + T - 1) / T);
+  }
   const int xq = (ntile + 7) / 8;
   LQCD_TLAUNCH(tm, true, true, (k_hop_tile<R, A, B, C, T, SI, SS>), dim3(8 * xq), dim3(kBlock), 0, c->stream, g, p,
                      U, in, self, static_cast<cx<R> *>(out), mk<R>(R(alpha.real()), R(alpha.imag())),
-                     R(beta), si, ss, so, nrhs, xq);
+                     R(beta), si, ss, so, nrhs, xq, map);
 }
 
 template <class R, bool A, bool B, bool C, int NB, class SI, class SS>
@@ -275,8 +361,19 @@ void launch_hop_src(lqcd_ctx *c, int p, SI in, SS self, void *out, cdouble alpha
   Timed tm(c, std::is_same<R, double>::value ? LQCD_KC_HOP64 : LQCD_KC_HOP32, bytes);
   const int pi = std::is_same<R, double>::value ? 0 : 1;
   const int nbmax = c->hop_nb[pi];
-  constexpr int T = std::is_same<R, double>::value ? 32 : 64;  // 36 KiB of links per workgroup
-  if (c->hop_tile[pi] && nrhs >= kBlock / T)
+  // tiles of 32 sites (FP64: 36 KiB of links per workgroup; FP32: 18 KiB),
+  // or 64 FP32 sites on request
+  constexpr int T = std::is_same<R, double>::value ? 32 : 64;
+  const bool t32 = !std::is_same<R, double>::value && c->hop_tsites32 == 32;
+  // the tiled form addresses a wave's fields by 32-bit byte offsets: one
+  // right-hand-side stride per extra slot of a wave plus a half field
+  auto fits = [&](size_t stride, double bytes) {
+    return double(stride) * bytes + double(g.Vh) * bytes < 4294967295.0;
+  };
+  const bool offs_ok = fits(si, SI::kBytes) && (!C || fits(ss, SS::kBytes)) && fits(so, sizeof(cx<R>));
+  if (c->hop_tile[pi] && offs_ok && t32 && nrhs >= kBlock / 32)
+    launch_hop_tile<R, A, B, C, 32>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else if (c->hop_tile[pi] && offs_ok && nrhs >= kBlock / T)
     launch_hop_tile<R, A, B, C, T>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   else if (nrhs >= 8 && nbmax >= 8) launch_hop_nb<R, A, B, C, 8>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   else if (nrhs >= 4 && nbmax >= 4) launch_hop_nb<R, A, B, C, 4>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);

@@ -74,9 +74,75 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Point-split operators (codes 5..8): t_n[mu][t] = sum_{x in t} eta_n(x)^+
-// (Theta(mu) (x_n - xt_n))(x).  One thread per (site, direction), the
-// direction fastest, so the four threads of a site share its loads; each
-// timeslice is split over nch workgroups as above.
+// (Theta(mu) (x_n - xt_n))(x), Theta(mu) = kappa [(1 + g_mu) U_mu(x - mu)^+
+// S_- - (1 - g_mu) U_mu(x) S_+] with S_-+ the shifts to x -+ mu.
+//
+// (1 -+ g_mu) has rank 2 and squares to twice itself, and its lower half
+// spinor is a unitary R times the upper one, so for any colour matrix W
+//   a^+ (1 -+ g_mu) W b = sum_{s=0,1} at_s^+ W h_s,
+// where at and h are the upper halves of (1 -+ g_mu) a and (1 -+ g_mu) b:
+// at_s = a_s + alpha_s a_{p(s)} with a spin partner p(s) in {2, 3} and a
+// phase alpha_s in {+-1, +-i}.  Each site gets 4 lanes: lane q < 2 takes the
+// forward half spin s = q (W = U_mu(x), neighbour x + mu), lane q >= 2 the
+// backward one s = q - 2 (W = U_mu(x - mu)^+, neighbour x - mu).  A lane
+// loads two spins of eta(x), two spins of x and xt at its neighbour and one
+// link, so 16 sites of a wave read contiguous 3 KiB runs.  The lanes' terms
+// add up over the four lanes of a site; each timeslice is split over nch
+// workgroups as in k_estimate.
+template <int MU>
+__device__ inline cx<double> ps_lane(const cx<double> *U, const Geom &g, double kappa,
+                                     const cx<double> *eta, const cx<double> *x, const cx<double> *xt,
+                                     const int c[4], size_t s, int q) {
+  const int Lm = g.L[MU];
+  const size_t stm = MU == 0 ? 1 : MU == 1 ? size_t(g.L[0]) : MU == 2 ? size_t(g.L[0]) * g.L[1]
+                                                                        : size_t(g.L[0]) * g.L[1] * g.L[2];
+  const bool fwd = q < 2;
+  const int hs = q & 1;  // half spin
+  const int cm = c[MU];
+  const size_t nbr = fwd ? (cm + 1 == Lm ? s - stm * (Lm - 1) : s + stm) : (cm == 0 ? s + stm * (Lm - 1) : s - stm);
+  int cl[4] = {c[0], c[1], c[2], c[3]};
+  if (!fwd) cl[MU] = cm == 0 ? Lm - 1 : cm - 1;  // the backward link lives at x - mu
+  const cx<double> *u = ps_link(U, g, cl[0], cl[1], cl[2], cl[3], MU);
+  // partner spin and phase of the forward projector (negated backward)
+  const int ps = MU < 2 ? 3 - hs : 2 + hs;
+  double ar, ai;
+  if (MU == 0) { ar = 0; ai = 1; }
+  else if (MU == 1) { ar = hs ? -1 : 1; ai = 0; }
+  else if (MU == 2) { ar = 0; ai = hs ? -1 : 1; }
+  else { ar = -1; ai = 0; }
+  if (!fwd) { ar = -ar; ai = -ai; }
+  const cx<double> al = mk(ar, ai);
+  cx<double> at[3], h[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    at[k] = ldc(eta + s * 12 + hs * 3 + k) + al * ldc(eta + s * 12 + ps * 3 + k);
+    cx<double> bu = ldc(x + nbr * 12 + hs * 3 + k), bl = ldc(x + nbr * 12 + ps * 3 + k);
+    if (xt) {
+      bu = bu - ldc(xt + nbr * 12 + hs * 3 + k);
+      bl = bl - ldc(xt + nbr * 12 + ps * 3 + k);
+    }
+    h[k] = bu + al * bl;
+  }
+  // the link loads go out after the projections (fewer registers live)
+  asm volatile("" : "+v"(at[0].re), "+v"(at[0].im), "+v"(at[1].re), "+v"(at[1].im), "+v"(at[2].re),
+               "+v"(at[2].im), "+v"(h[0].re), "+v"(h[0].im), "+v"(h[1].re), "+v"(h[1].im), "+v"(h[2].re),
+               "+v"(h[2].im)::"memory");
+  const size_t Vh = size_t(g.Vh);
+  cx<double> acc = mk(0.0, 0.0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // row a of W: U_ab forward, conj(U_ba) backward
+    cx<double> w[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const cx<double> e = ldc(u + (fwd ? 3 * a + b : 3 * b + a) * Vh);
+      w[b] = fwd ? e : mk(e.re, -e.im);
+    }
+    acc = acc + cmulc(at[a], w[0] * h[0] + w[1] * h[1] + w[2] * h[2]);
+  }
+  return (fwd ? -kappa : kappa) * acc;
+}
+
 __global__ void __launch_bounds__(kBlock)
     k_estimate_ps(Geom g, const cx<double> *__restrict__ U, double kappa,
                   const cx<double> *__restrict__ eta, const cx<double> *__restrict__ x,
@@ -85,49 +151,42 @@ __global__ void __launch_bounds__(kBlock)
   const int t = blockIdx.x / nch, ch = blockIdx.x % nch, r = blockIdx.y;
   const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
   const int Vs = Lx * Ly * Lz;
-  const size_t V = size_t(g.V), Vh = size_t(g.Vh);
-  const size_t base = size_t(r) * V * 12;
-  const int mu = threadIdx.x & 3;
-  double are = 0, aim = 0;
+  const size_t base = size_t(r) * size_t(g.V) * 12;
+  eta += base;
+  x += base;
+  if (xt) xt += base;
+  const int q = threadIdx.x & 3;
+  double acc[2 * kNumPS] = {};
   for (int i = ch * (kBlock / 4) + (threadIdx.x >> 2); i < Vs; i += nch * (kBlock / 4)) {
-    const int xx = i % Lx, yy = (i / Lx) % Ly, zz = i / (Lx * Ly);
+    const int c[4] = {i % Lx, (i / Lx) % Ly, i / (Lx * Ly), t};
     const size_t s = size_t(t) * Vs + i;
-    const int cm = mu == 0 ? xx : mu == 1 ? yy : mu == 2 ? zz : t;
-    const int Lm = mu == 0 ? Lx : mu == 1 ? Ly : mu == 2 ? Lz : Lt;
-    const size_t stm = mu == 0 ? 1 : mu == 1 ? size_t(Lx) : mu == 2 ? size_t(Lx) * Ly : size_t(Lx) * Ly * Lz;
-    const size_t sf = cm + 1 == Lm ? s - stm * (Lm - 1) : s + stm;
-    const size_t sb = cm == 0 ? s + stm * (Lm - 1) : s - stm;
-    const int cb = cm == 0 ? Lm - 1 : cm - 1;
-    cx<double> a[12], b[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) a[k] = ldc(eta + base + s * 12 + k);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      b[k] = ldc(x + base + sf * 12 + k);
-      if (xt) b[k] = b[k] - ldc(xt + base + sf * 12 + k);
-    }
-    const cx<double> vf = ps_half<true>(a, b, ps_link(U, g, xx, yy, zz, t, mu), Vh, mu);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      b[k] = ldc(x + base + sb * 12 + k);
-      if (xt) b[k] = b[k] - ldc(xt + base + sb * 12 + k);
-    }
-    const cx<double> *ub = ps_link(U, g, mu == 0 ? cb : xx, mu == 1 ? cb : yy, mu == 2 ? cb : zz, mu == 3 ? cb : t, mu);
-    const cx<double> vb = ps_half<false>(a, b, ub, Vh, mu);
-    are += kappa * (vb.re - vf.re);
-    aim += kappa * (vb.im - vf.im);
-  }
-  // reduce the four directions separately: lanes with the same mu
-#pragma unroll
-  for (int off = 32; off >= 4; off >>= 1) {
-    are += __shfl_xor(are, off, 64);
-    aim += __shfl_xor(aim, off, 64);
+    // one direction at a time: the empty asm (with a memory clobber) keeps
+    // the next direction's loads behind this direction's arithmetic, which
+    // would otherwise all be issued at once and fill the register file
+    cx<double> v;
+    v = ps_lane<0>(U, g, kappa, eta, x, xt, c, s, q);
+    acc[0] += v.re;
+    acc[1] += v.im;
+    asm volatile("" : "+v"(acc[0]), "+v"(acc[1])::"memory");
+    v = ps_lane<1>(U, g, kappa, eta, x, xt, c, s, q);
+    acc[2] += v.re;
+    acc[3] += v.im;
+    asm volatile("" : "+v"(acc[2]), "+v"(acc[3])::"memory");
+    v = ps_lane<2>(U, g, kappa, eta, x, xt, c, s, q);
+    acc[4] += v.re;
+    acc[5] += v.im;
+    asm volatile("" : "+v"(acc[4]), "+v"(acc[5])::"memory");
+    v = ps_lane<3>(U, g, kappa, eta, x, xt, c, s, q);
+    acc[6] += v.re;
+    acc[7] += v.im;
+    asm volatile("" : "+v"(acc[6]), "+v"(acc[7])::"memory");
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane < 4) {
-    sh[2 * lane][wave] = are;
-    sh[2 * lane + 1][wave] = aim;
-  }
+#pragma unroll
+  for (int k = 0; k < 2 * kNumPS; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 2 * kNumPS; ++k) sh[k][wave] = acc[k];
   __syncthreads();
   if (threadIdx.x < 2 * kNumPS) {
     double v = 0;

@@ -30,13 +30,24 @@ namespace st {
 // 16-bit fields with per-site scales (half.h), decoded to FP32.  at(r)
 // moves to right-hand side r (stride in elements of the storage); site(i)
 // fetches what every component load of site i shares.
+//
+// The *_at forms address a site by a 32-bit byte offset o from the base p
+// (kBytes bytes per site and component): with p the same for the whole
+// wave, p + comp * Vh stays in scalar registers and every load is
+// "scalar base + one 32-bit lane offset", one VGPR per neighbour instead
+// of a 64-bit address per component.
 template <class R>
 struct SrcPlain {
   const cx<R> *p;
   using Ctx = int;
+  static constexpr uint32_t kBytes = sizeof(cx<R>);
   __device__ SrcPlain at(size_t off) const { return SrcPlain{p + off}; }
   __device__ Ctx site(size_t) const { return 0; }
   __device__ cx<R> ld(Ctx, size_t i, int comp, size_t Vh) const { return ldc(p + comp * Vh + i); }
+  __device__ Ctx site_at(uint32_t) const { return 0; }
+  __device__ cx<R> ld_at(Ctx, uint32_t o, int comp, size_t Vh) const {
+    return ldc(reinterpret_cast<const cx<R> *>(reinterpret_cast<const char *>(p + comp * Vh) + o));
+  }
 };
 
 template <HKind K>
@@ -44,13 +55,23 @@ struct SrcHalf {
   const uint32_t *p;
   size_t n;  // payload words (12 Vh); the scales follow
   using Ctx = float;
+  static constexpr uint32_t kBytes = 4;
   __device__ SrcHalf at(size_t off) const { return SrcHalf{p + off, n}; }
   __device__ Ctx site(size_t i) const { return __uint_as_float(p[n + i]); }
   __device__ cx<float> ld(Ctx sc, size_t i, int comp, size_t Vh) const {
     const cx<float> v = Codec<K>::unpack(p[comp * Vh + i]);
     return mk(sc * v.re, sc * v.im);
   }
+  __device__ Ctx site_at(uint32_t o) const {
+    return __uint_as_float(*reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p + n) + o));
+  }
+  __device__ cx<float> ld_at(Ctx sc, uint32_t o, int comp, size_t Vh) const {
+    const cx<float> v =
+        Codec<K>::unpack(*reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p + comp * Vh) + o));
+    return mk(sc * v.re, sc * v.im);
+  }
 };
+
 
 template <class R>
 struct Half {
@@ -94,8 +115,8 @@ __device__ inline void link_dag_mul(const cx<R> *u, size_t Vh, const Half<R> &in
 // Project psi (site i of the source, 12 components at stride Vh) for
 // direction MU and sign (FWD: 1 - g_mu, else 1 + g_mu).  G5 applies
 // g5 = diag(1,1,-1,-1) first.
-template <class R, int MU, bool FWD, bool G5, class Src>
-__device__ inline void project(const Src &src, size_t i, size_t Vh, Half<R> &o) {
+template <class R, int MU, bool FWD, bool G5, class Src, class I>
+__device__ inline void project(const Src &src, I i, size_t Vh, Half<R> &o) {
   const typename Src::Ctx sc = src.site(i);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -116,6 +137,83 @@ __device__ inline void project(const Src &src, size_t i, size_t Vh, Half<R> &o) 
       o.h[0][c] = FWD ? u0 + iz(l0) : u0 - iz(l0);
       o.h[1][c] = FWD ? u1 - iz(l1) : u1 + iz(l1);
     } else {  // t
+      o.h[0][c] = FWD ? u0 - l0 : u0 + l0;
+      o.h[1][c] = FWD ? u1 - l1 : u1 + l1;
+    }
+  }
+}
+
+// Raw loads of one site's 12 components for the tiled stencil: fetch_at
+// issues all of them, settle makes them complete together (one empty asm
+// naming every loaded register), and project_raw then works from
+// registers.  Without it the compiler interleaves the loads with the
+// projection arithmetic and keeps only a few of them in flight per wave.
+template <class Src>
+struct Raw;
+template <class R>
+struct Raw<SrcPlain<R>> {
+  cx<R> v[12];
+  __device__ cx<R> get(int k) const { return v[k]; }
+};
+template <HKind K>
+struct Raw<SrcHalf<K>> {
+  uint32_t w[12];
+  float sc;
+  __device__ cx<float> get(int k) const {
+    const cx<float> v = Codec<K>::unpack(w[k]);
+    return mk(sc * v.re, sc * v.im);
+  }
+};
+
+template <class R>
+__device__ inline void fetch_at(const SrcPlain<R> &s, uint32_t o, size_t Vh, Raw<SrcPlain<R>> &r) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) r.v[k] = s.ld_at(0, o, k, Vh);
+}
+template <HKind K>
+__device__ inline void fetch_at(const SrcHalf<K> &s, uint32_t o, size_t Vh, Raw<SrcHalf<K>> &r) {
+  r.sc = s.site_at(o);
+#pragma unroll
+  for (int k = 0; k < 12; ++k)
+    r.w[k] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(s.p + k * Vh) + o);
+}
+
+#define LQCD_V2(a) "+v"(a.re), "+v"(a.im)
+template <class R>
+__device__ inline void settle(Raw<SrcPlain<R>> &r) {
+  asm volatile("" : LQCD_V2(r.v[0]), LQCD_V2(r.v[1]), LQCD_V2(r.v[2]), LQCD_V2(r.v[3]), LQCD_V2(r.v[4]),
+               LQCD_V2(r.v[5]), LQCD_V2(r.v[6]), LQCD_V2(r.v[7]), LQCD_V2(r.v[8]), LQCD_V2(r.v[9]),
+               LQCD_V2(r.v[10]), LQCD_V2(r.v[11]));
+}
+#undef LQCD_V2
+template <HKind K>
+__device__ inline void settle(Raw<SrcHalf<K>> &r) {
+  asm volatile("" : "+v"(r.w[0]), "+v"(r.w[1]), "+v"(r.w[2]), "+v"(r.w[3]), "+v"(r.w[4]), "+v"(r.w[5]),
+               "+v"(r.w[6]), "+v"(r.w[7]), "+v"(r.w[8]), "+v"(r.w[9]), "+v"(r.w[10]), "+v"(r.w[11]),
+               "+v"(r.sc));
+}
+
+// project() on a settled raw site.
+template <class R, int MU, bool FWD, bool G5, class RawT>
+__device__ inline void project_raw(const RawT &r, Half<R> &o) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cx<R> u0 = r.get(0 * 3 + c), u1 = r.get(1 * 3 + c);
+    cx<R> l0 = r.get(2 * 3 + c), l1 = r.get(3 * 3 + c);
+    if (G5) {
+      l0 = -l0;
+      l1 = -l1;
+    }
+    if (MU == 0) {
+      o.h[0][c] = FWD ? u0 + iz(l1) : u0 - iz(l1);
+      o.h[1][c] = FWD ? u1 + iz(l0) : u1 - iz(l0);
+    } else if (MU == 1) {
+      o.h[0][c] = FWD ? u0 + l1 : u0 - l1;
+      o.h[1][c] = FWD ? u1 - l0 : u1 + l0;
+    } else if (MU == 2) {
+      o.h[0][c] = FWD ? u0 + iz(l0) : u0 - iz(l0);
+      o.h[1][c] = FWD ? u1 - iz(l1) : u1 + iz(l1);
+    } else {
       o.h[0][c] = FWD ? u0 - l0 : u0 + l0;
       o.h[1][c] = FWD ? u1 - l1 : u1 + l1;
     }
@@ -146,6 +244,52 @@ __device__ inline void accumulate(cx<R> acc[4][3], const Half<R> &g) {
     }
     acc[2][c] = acc[2][c] + r0;
     acc[3][c] = acc[3][c] + r1;
+  }
+}
+
+// acc += the (g, R g) reconstruction of (U h) (FWD) or (U^+ h) (backward)
+// for direction MU, one colour row at a time, so that the 6-complex
+// product is never held whole.  u points at entry 0 of the link, entries
+// ld apart.  Same sums in the same order as link_mul / link_dag_mul
+// followed by accumulate.
+template <class R, int MU, bool FWD>
+__device__ inline void link_accumulate(cx<R> acc[4][3], const cx<R> *u, size_t ld, const Half<R> &h) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<R> g0, g1;
+    if (FWD) {
+      const cx<R> u0 = ldc(u + (3 * a + 0) * ld), u1 = ldc(u + (3 * a + 1) * ld), u2 = ldc(u + (3 * a + 2) * ld);
+      g0 = u0 * h.h[0][0] + u1 * h.h[0][1] + u2 * h.h[0][2];
+      g1 = u0 * h.h[1][0] + u1 * h.h[1][1] + u2 * h.h[1][2];
+    } else {  // (U^+ h)_a = sum_b conj(U_ba) h_b
+      const cx<R> u0 = ldc(u + (0 * 3 + a) * ld), u1 = ldc(u + (1 * 3 + a) * ld), u2 = ldc(u + (2 * 3 + a) * ld);
+      g0 = mk<R>(0, 0);
+      g1 = mk<R>(0, 0);
+      g0 = g0 + cmulc(u0, h.h[0][0]);
+      g1 = g1 + cmulc(u0, h.h[1][0]);
+      g0 = g0 + cmulc(u1, h.h[0][1]);
+      g1 = g1 + cmulc(u1, h.h[1][1]);
+      g0 = g0 + cmulc(u2, h.h[0][2]);
+      g1 = g1 + cmulc(u2, h.h[1][2]);
+    }
+    acc[0][a] = acc[0][a] + g0;
+    acc[1][a] = acc[1][a] + g1;
+    cx<R> r0, r1;
+    if (MU == 0) {
+      r0 = FWD ? miz(g1) : iz(g1);
+      r1 = FWD ? miz(g0) : iz(g0);
+    } else if (MU == 1) {
+      r0 = FWD ? -g1 : g1;
+      r1 = FWD ? g0 : -g0;
+    } else if (MU == 2) {
+      r0 = FWD ? miz(g0) : iz(g0);
+      r1 = FWD ? iz(g1) : miz(g1);
+    } else {
+      r0 = FWD ? -g0 : g0;
+      r1 = FWD ? -g1 : g1;
+    }
+    acc[2][a] = acc[2][a] + r0;
+    acc[3][a] = acc[3][a] + r1;
   }
 }
 

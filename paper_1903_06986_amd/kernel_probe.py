@@ -3,7 +3,7 @@
     python -m paper_1903_06986_amd.kernel_probe --kernel hop32 --nrhs 8 --reps 20
 
 kernels: hop32 / hop64 (both parities of the stencil, internal even/odd
-layout), schur32 (the even/odd operator in FP32), schur16 (the even/odd
+layout), schur32 / schur64 (the even/odd operator in FP32 / FP64), schur16 (the even/odd
 operator reading FP16 per-site-scaled input, LEX in/out), copy (a plain
 device copy of a 256 MiB buffer, the reference for scaling memory
 counters).  --tile 0/1 switches the link-tiled stencil off/on.  The
@@ -21,10 +21,12 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernel", default="hop32", choices=["hop32", "hop64", "schur32", "schur16", "copy"])
+    ap.add_argument("--kernel", default="hop32", choices=["hop32", "hop64", "schur32", "schur64", "schur16", "copy"])
     ap.add_argument("--tile", type=int, default=1)
     ap.add_argument("--order", type=int, default=0)
     ap.add_argument("--nb", type=int, default=0, help="lane-grouped right-hand sides (0: default)")
+    ap.add_argument("--tblock", type=int, default=-1, help="plane-blocked tile order: timeslices per block (-1 auto, 0 index order)")
+    ap.add_argument("--tsites", type=int, default=32, help="sites per FP32 tile (32 or 64)")
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--dims", default="24x24x24x32")
@@ -43,7 +45,8 @@ def main():
     dims = tuple(int(x) for x in a.dims.split("x"))
     U = random_su3_links(dims, 0.2, 1003)
     ctx = Context(dims, U, 0.13)
-    ctx.tune(hop_tile64=a.tile, hop_tile32=a.tile, hop_order=a.order)
+    ctx.tune(hop_tile64=a.tile, hop_tile32=a.tile, hop_order=a.order, hop_tblock64=a.tblock,
+             hop_tblock32=a.tblock, hop_tsites32=a.tsites)
     if a.nb:
         ctx.tune(hop_nb64=a.nb, hop_nb32=a.nb)
     Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
@@ -56,12 +59,13 @@ def main():
         kt = ctx.timer_read()
         ms, by, n = kt["hop32"]
         print("%s nrhs=%d tile=%d: %d stencil launches, %.1f us each, %.0f algorithmic bytes per launch, "
-              "%.1f GB/s (order %d nb %d)" % (a.kernel, a.nrhs, a.tile, n, ms * 1e3 / n, by / n, by / (ms * 1e-3) / 1e9, a.order, a.nb))
+              "%.1f GB/s (order %d nb %d tblock %d tsites %d)" % (a.kernel, a.nrhs, a.tile, n, ms * 1e3 / n, by / n,
+                                                    by / (ms * 1e-3) / 1e9, a.order, a.nb, a.tblock, a.tsites))
         return
-    prec = "f64" if a.kernel == "hop64" else "f32"
+    prec = "f64" if a.kernel in ("hop64", "schur64") else "f32"
     dt = torch.complex128 if prec == "f64" else torch.complex64
-    op = "schur" if a.kernel == "schur32" else "hop"
-    shape = (a.nrhs, 12, Vh) if op == "schur" else (a.nrhs, 2, 12, Vh)
+    op = "schur" if a.kernel.startswith("schur") else "hop"
+    shape = (a.nrhs, 2, 12, Vh)  # even/odd layout; the Schur operator reads the even half
     x = torch.randn(shape, dtype=dt, device="cuda")
     y = torch.empty_like(x)
     ctx.timer(True)
@@ -70,9 +74,9 @@ def main():
     kt = ctx.timer_read()
     k = "hop64" if prec == "f64" else "hop32"
     ms, by, n = kt[k]
-    print("%s nrhs=%d tile=%d order=%d nb=%d: %d launches, %.1f us each, %.0f algorithmic bytes per "
-          "launch, %.1f GB/s" % (a.kernel, a.nrhs, a.tile, a.order, a.nb, n, ms * 1e3 / n, by / n,
-                                 by / (ms * 1e-3) / 1e9))
+    print("%s nrhs=%d tile=%d order=%d nb=%d tblock=%d tsites=%d: %d launches, %.1f us each, %.0f "
+          "algorithmic bytes per launch, %.1f GB/s" % (a.kernel, a.nrhs, a.tile, a.order, a.nb, a.tblock, a.tsites,
+                                                      n, ms * 1e3 / n, by / n, by / (ms * 1e-3) / 1e9))
 
 
 if __name__ == "__main__":

@@ -27,6 +27,25 @@ GMRES-Proj(m - k, k) for every later right-hand side
            one GMRES(m - k) cycle from the new residual;
            r = b - A x } until |r| <= tol |b|.
 
+MINRES-DR(m, k) for a hermitian (indefinite) A, e.g. M' = M g5 near the
+critical kappa, where Sec. 8 switches from GMRES-DR to it (the method is
+only cited there; the steps below are this module's reading of deflated
+restarting with a symmetric Lanczos recurrence):
+  1. as GMRES-DR step 1, except that after the first new column of a cycle
+     (which is orthogonalised against every kept vector) each new vector is
+     orthogonalised by the three-term recurrence against v_{j-1}, v_j, then
+     once more against those two and against the k + 1 kept vectors of the
+     last restart (selective reorthogonalisation against the approximate
+     eigenvectors, which is where a Lanczos basis loses orthogonality);
+  2. as GMRES-DR step 2;
+  3. harmonic Ritz pairs from the hermitian-definite pencil
+     H_m g = mu Hbar_m^* Hbar_m g, H_m taken hermitian, theta = 1 / mu
+     (equivalent to step 3 of GMRES-DR in exact arithmetic, but it never
+     solves with H_m, which turns singular when a Ritz value of an
+     indefinite A crosses zero);
+  4. the residual direction is the unit vector orthogonal to the range of
+     Hbar_m (last column of its complete QR); then as GMRES-DR steps 4-5.
+
 Hermitian eigenpairs (Sec. 5.4): GMRES-DR on M' (full lattice) followed by
 Rayleigh-Ritz in V_k: T = V_k^* M' V_k = (Hbar_k)[:k, :k], hermitised,
 eigh(T) = (lambda', s), e' = V_k s; the Q of smallest |lambda'| are kept.
@@ -146,6 +165,118 @@ def gmres_dr(A, b, m, k, tol, max_cycles=500, x0=None, eig_tol=None, n_eig=None)
         c[:] = 0
         c[:k + 1] = ck
         j0 = k
+    info = dict(V=Vk1, H=Hk, theta=theta, theta_resid=theta_res, history=hist, converged=res <= tol * bnorm, **stats)
+    return x, info
+
+
+def lanczos_extend(A, V, H, j0, m, kept, stats):
+    """MINRES-DR basis extension from column j0 to column m (in place).
+
+    Column j0 is orthogonalised (twice) against v_0 .. v_j0; every later
+    column against v_{j-1}, v_j, then once more against v_{j-1}, v_j and the
+    first `kept` vectors (the kept vectors of the last restart, 0 before the
+    first restart).  Coefficients of both passes add into H, so
+    A V_m = V_{m+1} Hbar_m holds to rounding."""
+    for j in range(j0, m):
+        w = A(V[:, j])
+        stats["matvecs"] += 1
+        if j == j0:
+            w, h = _cgs2(V[:, :j + 1], w)
+            H[:j + 1, j] = h
+        else:
+            near = [j - 1, j]
+            h1 = V[:, near].conj().T @ w
+            w = w - V[:, near] @ h1
+            second = sorted(set(range(kept)) | set(near))
+            h2 = V[:, second].conj().T @ w
+            w = w - V[:, second] @ h2
+            H[near, j] += h1
+            H[second, j] += h2
+        nrm = np.linalg.norm(w)
+        H[j + 1, j] = nrm
+        if nrm == 0.0:
+            raise FloatingPointError("Lanczos breakdown at column %d" % j)
+        V[:, j + 1] = w / nrm
+
+
+def harmonic_ritz_hermitian(H, m):
+    """Harmonic Ritz pairs of a hermitian operator from its (m+1) x m Hbar_m.
+
+    The pencil H_m g = mu (Hbar_m^* Hbar_m) g with H_m made hermitian and
+    Hbar_m^* Hbar_m positive definite (Hbar_m has full column rank): with the
+    Cholesky factor L L^* = Hbar_m^* Hbar_m it is the hermitian eigenproblem
+    L^{-1} H_m L^{-*} y = mu y, g = L^{-*} y, theta = 1 / mu.  Returns theta
+    (inf where mu = 0), g and the unit vector w orthogonal to the range of
+    Hbar_m, the common direction of the harmonic residuals."""
+    Hm = H[:m, :m]
+    T = 0.5 * (Hm + Hm.conj().T)
+    B = H.conj().T @ H
+    L = np.linalg.cholesky(B)
+    Li = np.linalg.inv(L)
+    mu, Y = np.linalg.eigh(Li @ T @ Li.conj().T)
+    g = Li.conj().T @ Y
+    with np.errstate(divide="ignore"):
+        theta = np.where(mu != 0, 1.0 / np.where(mu != 0, mu, 1.0), np.inf)
+    Qc, _ = np.linalg.qr(H, mode="complete")
+    w = Qc[:, m]
+    return theta.astype(np.complex128), g, w
+
+
+def _deflation_restart_hermitian(V, H, s, m, k):
+    theta, g, w = harmonic_ritz_hermitian(H, m)
+    order = np.lexsort((np.arange(m), np.abs(theta)))[:k]
+    gk = g[:, order]
+    Pm = np.zeros((m + 1, k + 1), dtype=np.complex128)
+    Pm[:m, :k] = gk
+    Pm[:, k] = w
+    Q, _ = np.linalg.qr(Pm)
+    Hk = Q.conj().T @ H @ Q[:m, :k]
+    Vnew = V @ Q
+    cnew = Q.conj().T @ s
+    gp = np.vstack([gk, np.zeros((1, k))])
+    resid = np.linalg.norm(H @ gk - gp * theta[order], axis=0) / np.linalg.norm(gk, axis=0)
+    return Vnew, Hk, cnew, theta[order], resid
+
+
+def minres_dr(A, b, m, k, tol, max_cycles=500, x0=None, eig_tol=None, n_eig=None):
+    """MINRES-DR(m, k) for hermitian A: same interface and outputs as gmres_dr."""
+    n = b.size
+    x = np.zeros(n, dtype=np.complex128) if x0 is None else x0.astype(np.complex128).copy()
+    stats = {"matvecs": 0, "cycles": 0}
+    r = b - A(x) if x0 is not None else b.astype(np.complex128).copy()
+    if x0 is not None:
+        stats["matvecs"] += 1
+    bnorm = np.linalg.norm(b)
+    V = np.zeros((n, m + 1), dtype=np.complex128)
+    H = np.zeros((m + 1, m), dtype=np.complex128)
+    beta = np.linalg.norm(r)
+    V[:, 0] = r / beta
+    c = np.zeros(m + 1, dtype=np.complex128)
+    c[0] = beta
+    j0, kept = 0, 0
+    hist = []
+    while True:
+        lanczos_extend(A, V, H, j0, m, kept, stats)
+        d = _lstsq(H, c)
+        x += V[:, :m] @ d
+        s = c - H @ d
+        res = np.linalg.norm(s)
+        hist.append(res / bnorm)
+        stats["cycles"] += 1
+        Vk1, Hk, ck, theta, theta_res = _deflation_restart_hermitian(V, H, s, m, k)
+        done = res <= tol * bnorm
+        if done and eig_tol is not None:
+            ne = k if n_eig is None else n_eig
+            done = bool(np.all(theta_res[:ne] <= eig_tol * np.abs(theta[:ne])))
+        if done or stats["cycles"] >= max_cycles:
+            break
+        V[:, :k + 1] = Vk1
+        V[:, k + 1:] = 0
+        H[:] = 0
+        H[:k + 1, :k] = Hk
+        c[:] = 0
+        c[:k + 1] = ck
+        j0, kept = k, k + 1
     info = dict(V=Vk1, H=Hk, theta=theta, theta_resid=theta_res, history=hist, converged=res <= tol * bnorm, **stats)
     return x, info
 

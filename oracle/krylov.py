@@ -38,11 +38,14 @@ restarting with a symmetric Lanczos recurrence):
      last restart (selective reorthogonalisation against the approximate
      eigenvectors, which is where a Lanczos basis loses orthogonality);
   2. as GMRES-DR step 2;
-  3. harmonic Ritz pairs from the hermitian-definite pencil
-     H_m g = mu Hbar_m^* Hbar_m g, H_m taken hermitian, theta = 1 / mu
-     (equivalent to step 3 of GMRES-DR in exact arithmetic, but it never
-     solves with H_m, which turns singular when a Ritz value of an
-     indefinite A crosses zero);
+  3. harmonic Ritz pairs from the pencil H_m^* g = mu Hbar_m^* Hbar_m g
+     with the positive definite Hbar_m^* Hbar_m = L L^*, as the eigenproblem
+     of L^{-1} H_m^* L^{-*}, theta = 1 / mu (equivalent to step 3 of
+     GMRES-DR, but it never solves with H_m, which turns singular when a
+     Ritz value of an indefinite A crosses zero).  H_m is used as computed,
+     not made hermitian: pairs of a hermitised H_m are not exact for the
+     computed Hbar_m, their residuals leave the kept residual direction, and
+     the restart relation then degrades from cycle to cycle;
   4. the residual direction is the unit vector orthogonal to the range of
      Hbar_m (last column of its complete QR); then as GMRES-DR steps 4-5.
 
@@ -202,20 +205,19 @@ def lanczos_extend(A, V, H, j0, m, kept, stats):
 def harmonic_ritz_hermitian(H, m):
     """Harmonic Ritz pairs of a hermitian operator from its (m+1) x m Hbar_m.
 
-    The pencil H_m g = mu (Hbar_m^* Hbar_m) g with H_m made hermitian and
-    Hbar_m^* Hbar_m positive definite (Hbar_m has full column rank): with the
-    Cholesky factor L L^* = Hbar_m^* Hbar_m it is the hermitian eigenproblem
-    L^{-1} H_m L^{-*} y = mu y, g = L^{-*} y, theta = 1 / mu.  Returns theta
+    The pencil H_m^* g = mu (Hbar_m^* Hbar_m) g with Hbar_m^* Hbar_m positive
+    definite (Hbar_m has full column rank): with the Cholesky factor
+    L L^* = Hbar_m^* Hbar_m it is the eigenproblem of the (hermitian up to
+    rounding) L^{-1} H_m^* L^{-*}, y = L^* g, theta = 1 / mu.  Returns theta
     (inf where mu = 0), g and the unit vector w orthogonal to the range of
     Hbar_m, the common direction of the harmonic residuals."""
     Hm = H[:m, :m]
-    T = 0.5 * (Hm + Hm.conj().T)
     B = H.conj().T @ H
     L = np.linalg.cholesky(B)
     Li = np.linalg.inv(L)
-    mu, Y = np.linalg.eigh(Li @ T @ Li.conj().T)
+    mu, Y = np.linalg.eig(Li @ Hm.conj().T @ Li.conj().T)
     g = Li.conj().T @ Y
-    with np.errstate(divide="ignore"):
+    with np.errstate(divide="ignore", invalid="ignore"):
         theta = np.where(mu != 0, 1.0 / np.where(mu != 0, mu, 1.0), np.inf)
     Qc, _ = np.linalg.qr(H, mode="complete")
     w = Qc[:, m]

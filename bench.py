@@ -91,19 +91,37 @@ class Path:
                                                n_eig=a.defl_n_eig, max_cycles=a.max_cycles)
         torch.cuda.synchronize()
         t1 = time.time()
+        # Sec. 8: near the critical kappa the hermitian modes come from MINRES-DR
         _, self.hdefl, sth = ctx.gmresdr_solve(eta0, op="MG5", m=c["herm_m"], k=c["herm_k"],
                                                tol=a.herm_tol, tol_super=a.herm_tol, eig_tol=a.eig_tol,
-                                               n_eig=c["n_hermitian"], max_cycles=a.max_cycles)
+                                               n_eig=c["n_hermitian"], max_cycles=a.max_cycles,
+                                               method=a.herm_method)
         self.lam, self.lam_res = self.hdefl.eigpairs(c["n_hermitian"])
         torch.cuda.synchronize()
         t2 = time.time()
+        self.herm_compare = None
+        if a.herm_compare:
+            # the other first-right-hand-side solver on the same system, for the record
+            other = "gmres-dr" if a.herm_method == "minres-dr" else "minres-dr"
+            tc = time.time()
+            _, d2, st2 = ctx.gmresdr_solve(eta0, op="MG5", m=c["herm_m"], k=c["herm_k"], tol=a.herm_tol,
+                                           tol_super=a.herm_tol, eig_tol=a.eig_tol, n_eig=c["n_hermitian"],
+                                           max_cycles=a.max_cycles, method=other)
+            lam2, _ = d2.eigpairs(c["n_hermitian"])
+            torch.cuda.synchronize()
+            self.herm_compare = {"method": other, "seconds": round(time.time() - tc, 3),
+                                 "matvecs": st2[0]["matvecs"], "cycles": st2[0]["cycles"],
+                                 "max_abs_lambda_diff": float(np.abs(np.sort(lam2) - np.sort(self.lam)).max())}
+            d2.free()
         _, self.corr_poly, self.cpoly, self.apoly = ctx.poly_subtract(c["poly_degree"], eta0, b=eta0,
                                                                       thetas=THETAS)
         _, self.corr_pert = ctx.pert_subtract(c["pert_order"], eta0, THETAS)
         torch.cuda.synchronize()
         t3 = time.time()
+        # the comparison solve is not part of the setup
+        tcmp = self.herm_compare["seconds"] if self.herm_compare else 0.0
         self.setup_times = dict(first_solve_s=t1 - t0, hermitian_modes_s=t2 - t1,
-                                poly_and_traces_s=t3 - t2, total_s=t3 - t0)
+                                poly_and_traces_s=t3 - t2 - tcmp, total_s=t3 - t0 - tcmp)
         self.first_stats, self.herm_stats = st0, sth
         self.next_noise = 1
         self.ones = np.ones(c["pert_order"] + 1, dtype=np.complex128)
@@ -157,6 +175,48 @@ def run_steps(path, inner, steps, warmup):
     kt = path.ctx.timer_read()
     path.ctx.timer(False)
     return dt, stats, kt
+
+
+def production_single(path, args, cfg):
+    """Sec. 10's production setup, timed: the hermitian modes of the one
+    super-converged MINRES-DR solve deflate every noise solve of M' = M g5
+    on the full lattice (GMRES-Proj, FP32 inner solves in FP64 refinement),
+    x = g5 y.  Beside it, the same noise solved on the even/odd Schur system
+    with its own deflation (the two-special-right-hand-side setup); both
+    solve-only, 8 right-hand sides, after one untimed warm-up."""
+    import torch
+    ctx, B = path.ctx, args.rhs_block
+    c = cfg
+
+    def herm(eta):
+        y, _, st = ctx.gmresdr_solve(eta, op="MG5", m=c["herm_m"], k=c["herm_k"], tol=args.tol,
+                                     defl=path.hdefl, inner="f32", inner_tol=args.inner_tol, rhs_block=B,
+                                     max_cycles=args.max_cycles)
+        return ctx.gamma5(y, out=y), st
+
+    def schur(eta):
+        x, _, st = ctx.gmresdr_solve(eta, op="schur", m=c["m"], k=c["k"], tol=args.tol, inner=args.inner,
+                                     inner_tol=args.inner_tol, rhs_block=B, max_cycles=args.max_cycles,
+                                     defl=path.defl, proj_m=args.proj_m)
+        return x, st
+
+    out = {}
+    for name, fn in (("hermitian_full_lattice", herm), ("schur_even_odd", schur)):
+        fn(ctx.noise_z4(c["noise_seed"], 50000, B))
+        eta = ctx.noise_z4(c["noise_seed"], 60000, B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = fn(eta)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"solves_per_s": round(B / dt, 3),
+                     "matvecs_per_solve": float(np.mean([s["matvecs"] for s in st])),
+                     "max_true_resid": max(s["true_resid"] for s in st)}
+        if name == "hermitian_full_lattice":
+            xh = x
+        else:
+            out["solution_rel_diff"] = float((xh - x).abs().max() / x.abs().max())
+    return out
 
 
 def accuracy(path, precisions, cfg, kappa, U, oracle_check):
@@ -307,6 +367,12 @@ def main():
     ap.add_argument("--defl-eig-tol", type=float, default=1e-7)
     ap.add_argument("--defl-n-eig", type=int, default=30)
     ap.add_argument("--herm-tol", type=float, default=1e-9)
+    ap.add_argument("--herm-method", default="minres-dr", choices=["minres-dr", "gmres-dr"],
+                    help="solver of the super-converged hermitian right-hand side")
+    ap.add_argument("--no-herm-compare", dest="herm_compare", action="store_false",
+                    help="skip timing the other hermitian solver for comparison")
+    ap.add_argument("--no-production", action="store_true",
+                    help="skip timing the single-special-right-hand-side production setup")
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--max-cycles", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -340,6 +406,9 @@ def main():
     path = Path(ctx, cfg, args)
     path.setup()
     print("[bench] setup %s" % json.dumps(path.setup_times), file=sys.stderr, flush=True)
+    print("[bench] hermitian (%s): %d matvecs, compare %s" % (args.herm_method, path.herm_stats[0]["matvecs"],
+                                                              json.dumps(path.herm_compare)),
+          file=sys.stderr, flush=True)
     dt, stats, kt = run_steps(path, args.inner, args.steps, args.warmup)
     n_solves = args.steps * args.rhs_block
     value = n_solves / dt
@@ -370,6 +439,10 @@ def main():
                for k, v in kt.items()}
     mv = float(np.mean([s["matvecs"] for s in stats]))
     mv64 = float(np.mean([s["matvecs"] for s in stats64]))
+    prod = None
+    if not args.no_production:
+        prod = production_single(path, args, cfg)
+        print("[bench] production %s" % json.dumps(prod), file=sys.stderr, flush=True)
     acc = None
     if not args.no_accuracy:
         acc = accuracy(path, [args.inner] + list(variants), cfg, kappa, U, not args.no_cpu_baseline)
@@ -402,6 +475,10 @@ def main():
         "accuracy": acc,
         "batching": bat,
         "setup": {k: round(v, 3) for k, v in path.setup_times.items()},
+        "production_single_rhs": prod,
+        "hermitian": {"method": args.herm_method, "matvecs": path.herm_stats[0]["matvecs"],
+                      "cycles": path.herm_stats[0]["cycles"],
+                      "max_eig_resid": float(np.max(path.lam_res)), "compare": path.herm_compare},
         "end_to_end_200_noise_s": round(path.setup_times["total_s"] + 199.0 / value, 2),
         "kernels": kernels,
         "roofline": roof,

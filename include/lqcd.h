@@ -106,7 +106,23 @@ typedef struct {
   double inner_tol;  /* relative residual reduction per refinement step (mixed precision) */
   int rhs_block;     /* right-hand sides solved together by GMRES-Proj (>= 1) */
   int proj_m;        /* GMRES cycle length of GMRES-Proj (0 = m - k) */
+  int method;        /* solver of the first right-hand side: LQCD_KRYLOV_GMRESDR
+                        (0) or LQCD_KRYLOV_MINRESDR (1, hermitian LQCD_OP_MG5
+                        only); later right-hand sides always use GMRES-Proj */
 } lqcd_solve_params;
+
+/* First-right-hand-side solvers (Sec. 7 and Sec. 8).  GMRES-DR(m, k):
+ * Arnoldi with classical Gram-Schmidt applied twice, least-squares
+ * update, restart with the k harmonic Ritz vectors of smallest |theta| and
+ * the residual direction.  MINRES-DR(m, k), used by the paper for the
+ * hermitian M' near the critical kappa: the same deflated restarting with a
+ * Lanczos three-term recurrence inside a cycle (the first new column after
+ * a restart against all kept vectors; each later vector against v_{j-1},
+ * v_j, then once more against those and the k + 1 kept vectors), and
+ * harmonic Ritz pairs from the hermitian-definite pencil
+ * H_m g = mu Hbar_m^H Hbar_m g, theta = 1 / mu, which needs no solve with
+ * H_m (singular when a Ritz value of the indefinite M' crosses zero). */
+typedef enum { LQCD_KRYLOV_GMRESDR = 0, LQCD_KRYLOV_MINRESDR = 1 } lqcd_krylov;
 
 typedef struct {
   int matvecs;       /* applications of the solved operator (any precision) */
@@ -139,6 +155,14 @@ lqcd_status lqcd_noise_z4(lqcd_ctx *ctx, uint64_t seed, int64_t first, int nrhs,
  * (LQCD_LAYOUT_EO, precision prec) for nrhs full fields. */
 lqcd_status lqcd_pack_eo(lqcd_ctx *ctx, lqcd_prec prec, const void *lex, void *eo, int nrhs);
 lqcd_status lqcd_unpack_eo(lqcd_ctx *ctx, lqcd_prec prec, const void *eo, void *lex, int nrhs);
+
+/* out = g5 in for nrhs LEX complex128 fields (device; in == out allowed),
+ * g5 = diag(1, 1, -1, -1) in spin (Sec. 2).  With M' = M g5 hermitian,
+ * M^{-1} = g5 M'^{-1}: a right-hand side solved with LQCD_OP_MG5 gives the
+ * solution of M through this call (the single-special-right-hand-side
+ * production setup of Sec. 10, where the hermitian modes deflate every
+ * solve). */
+lqcd_status lqcd_gamma5(lqcd_ctx *ctx, const void *in, void *out, int nrhs);
 
 /* Apply an operator (see lqcd_op) to nrhs fields.  With LQCD_LAYOUT_LEX,
  * in/out are complex128 LEX fields and the stencil runs in precision prec

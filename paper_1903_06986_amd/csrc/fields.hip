@@ -88,6 +88,17 @@ __global__ void k_convert(const cx<RI> *__restrict__ in, cx<RO> *__restrict__ ou
   }
 }
 
+// g5 = diag(1, 1, -1, -1) on LEX complex128 fields [site][spin][colour]:
+// element i has spin (i % 12) / 3.  In place allowed.
+__global__ void k_g5_lex(const cx<double> *in, cx<double> *out, size_t n) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (; i < n; i += stride) {
+    const cx<double> v = ldc(in + i);
+    stc(out + i, (i % 12) >= 6 ? -v : v);
+  }
+}
+
 }  // namespace
 
 void fill_noise(lqcd_ctx *c, uint64_t seed, int64_t first, int nrhs, void *eta, uint8_t *codes) {
@@ -176,5 +187,17 @@ extern "C" lqcd_status lqcd_unpack_eo(lqcd_ctx *c, lqcd_prec prec, const void *e
     if (prec == LQCD_F64) unpack_eo<double>(c, eo, lex, nrhs, fl);
     else if (prec == LQCD_F32) unpack_eo<float>(c, eo, lex, nrhs, fl);
     else LQCD_CHECK(false, LQCD_EINVAL, "lqcd_unpack_eo: precision %d not available", int(prec));
+  });
+}
+
+extern "C" lqcd_status lqcd_gamma5(lqcd_ctx *c, const void *in, void *out, int nrhs) {
+  return guarded([&] {
+    LQCD_CHECK(c && in && out, LQCD_EINVAL, "lqcd_gamma5: null argument");
+    LQCD_CHECK(nrhs >= 0, LQCD_EINVAL, "lqcd_gamma5: nrhs < 0");
+    const size_t n = full_len(c->g) * size_t(nrhs);
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_g5_lex, dim3(std::min<size_t>(nblocks(n), 8192)), dim3(kBlock), 0, c->stream,
+                       static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), n);
+    LQCD_HIP(hipGetLastError());
   });
 }

@@ -364,5 +364,31 @@ void eigh(const Mat &A0, std::vector<double> &w, Mat &Vr) {
   Vr = V2;
 }
 
+bool cholesky_inv(const Mat &A, Mat &Li) {
+  const int n = A.rows;
+  Mat L(n, n);
+  for (int j = 0; j < n; ++j) {
+    double d = A(j, j).real();
+    for (int k = 0; k < j; ++k) d -= std::norm(L(j, k));
+    if (!(d > 0) || !std::isfinite(d)) return false;
+    const double ljj = std::sqrt(d);
+    L(j, j) = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      cd v = A(i, j);
+      for (int k = 0; k < j; ++k) v -= L(i, k) * std::conj(L(j, k));
+      L(i, j) = v / ljj;
+    }
+  }
+  // forward substitution on the identity: L Li = I
+  Li = Mat(n, n);
+  for (int c = 0; c < n; ++c)
+    for (int i = c; i < n; ++i) {
+      cd v = i == c ? cd(1, 0) : cd(0, 0);
+      for (int k = c; k < i; ++k) v -= L(i, k) * Li(k, c);
+      Li(i, c) = v / L(i, i);
+    }
+  return true;
+}
+
 }  // namespace la
 }  // namespace lqcd

@@ -58,5 +58,9 @@ bool eig(const Mat &A, std::vector<cd> &w, Mat &Vr);
 // ascending, orthonormal eigenvectors in the columns of Vr.
 void eigh(const Mat &A, std::vector<double> &w, Mat &Vr);
 
+// Li = L^{-1} for the Cholesky factor L L^H = A of a hermitian positive
+// definite A (lower triangular); false if A is not positive definite.
+bool cholesky_inv(const Mat &A, Mat &Li);
+
 }  // namespace la
 }  // namespace lqcd

@@ -247,6 +247,62 @@ void arnoldi_h(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, s
   }
 }
 
+// MINRES-DR basis extension (one right-hand side, FP64; hermitian A):
+// column j0 is orthogonalised twice against every vector before it (it
+// couples to all kept vectors of the restart); each later column by the
+// three-term recurrence against v_{j-1}, v_j, then once more against those
+// two and the first `kept` vectors (the kept vectors of the last restart:
+// selective reorthogonalisation against the approximate eigenvectors).
+// Both passes' coefficients add into column j of Hbar.
+void lanczos_ext(lqcd_ctx *c, const Op<double> &A, void *V, size_t n, int j0, int m, int kept, Small &s) {
+  cx<double> *Vb = static_cast<cx<double> *>(V);
+  const size_t hb = size_t(m + 1) * sizeof(cdouble);
+  for (int j = j0; j < m; ++j) {
+    cx<double> *wj = Vb + size_t(j) * n, *wn = Vb + size_t(j + 1) * n;
+    A.apply(wj, 0, wn, 0, 1);
+    if (j == j0) {  // full classical Gram-Schmidt, twice
+      multi_dot<double>(c, Vb, n, 0, j + 1, wn, 0, n, 1, s.h1, m + 1);
+      multi_axpy<double>(c, Vb, n, 0, j + 1, s.h1, m + 1, wn, 0, n, 1, s.nrm1);
+      hipLaunchKernelGGL(k_dgks, dim3(1), dim3(64), 0, c->stream,
+                         reinterpret_cast<const cx<double> *>(s.h1), size_t(m + 1), j + 1, s.nrm1, s.flag,
+                         s.reorth, kReorthAlways);
+      LQCD_HIP(hipGetLastError());
+      multi_dot<double>(c, Vb, n, 0, j + 1, wn, 0, n, 1, s.h2, m + 1);
+      multi_axpy<double>(c, Vb, n, 0, j + 1, s.h2, m + 1, wn, 0, n, 1, s.nrm2);
+      hipLaunchKernelGGL(k_finish_col, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.Hd),
+                         s.Hrs, m + 1, j, reinterpret_cast<cx<double> *>(s.h1),
+                         reinterpret_cast<cx<double> *>(s.h2), size_t(m + 1), s.nrm1, s.nrm2, s.flag, s.inv);
+      LQCD_HIP(hipGetLastError());
+      scale_dev<double>(c, wn, 0, s.inv, wn, 0, n, 1);
+      continue;
+    }
+    cx<double> *wp = Vb + size_t(j - 1) * n;
+    fill_zero(c, s.h1, hb);
+    fill_zero(c, s.h2, hb);
+    multi_dot<double>(c, wp, n, 0, 2, wn, 0, n, 1, s.h1 + (j - 1), m + 1);
+    multi_axpy<double>(c, wp, n, 0, 2, s.h1 + (j - 1), m + 1, wn, 0, n, 1, s.nrm1);
+    // the second pass always runs (k_dgks with a threshold above 1)
+    hipLaunchKernelGGL(k_dgks, dim3(1), dim3(64), 0, c->stream,
+                       reinterpret_cast<const cx<double> *>(s.h1), size_t(m + 1), j + 1, s.nrm1, s.flag,
+                       s.reorth, kReorthAlways);
+    LQCD_HIP(hipGetLastError());
+    if (kept >= j - 1) {  // kept vectors and v_{j-1}, v_j are one range
+      multi_dot<double>(c, Vb, n, 0, j + 1, wn, 0, n, 1, s.h2, m + 1);
+      multi_axpy<double>(c, Vb, n, 0, j + 1, s.h2, m + 1, wn, 0, n, 1, s.nrm2);
+    } else {
+      if (kept > 0) multi_dot<double>(c, Vb, n, 0, kept, wn, 0, n, 1, s.h2, m + 1);
+      multi_dot<double>(c, wp, n, 0, 2, wn, 0, n, 1, s.h2 + (j - 1), m + 1);
+      if (kept > 0) multi_axpy<double>(c, Vb, n, 0, kept, s.h2, m + 1, wn, 0, n, 1, nullptr);
+      multi_axpy<double>(c, wp, n, 0, 2, s.h2 + (j - 1), m + 1, wn, 0, n, 1, s.nrm2);
+    }
+    hipLaunchKernelGGL(k_finish_col, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.Hd),
+                       s.Hrs, m + 1, j, reinterpret_cast<cx<double> *>(s.h1),
+                       reinterpret_cast<cx<double> *>(s.h2), size_t(m + 1), s.nrm1, s.nrm2, s.flag, s.inv);
+    LQCD_HIP(hipGetLastError());
+    scale_dev<double>(c, wn, 0, s.inv, wn, 0, n, 1);
+  }
+}
+
 // Add the per-slot second-pass counts to the host counters and reset them.
 void harvest_reorth(lqcd_ctx *c, Small &s, int nb, const std::vector<int> &slot_to_rhs,
                     std::vector<int> &reorth) {
@@ -315,6 +371,65 @@ Restart harmonic_restart(const la::Mat &H, int m, int k) {
   return R;
 }
 
+// MINRES-DR restart data: harmonic Ritz pairs of a hermitian operator from
+// the pencil H_m^H g = mu Hbar^H Hbar g, theta = 1 / mu, which never solves
+// with H_m (singular when a Ritz value of an indefinite operator crosses
+// zero).  With L L^H = Hbar^H Hbar it is the eigenproblem of
+// L^{-1} H_m^H L^{-H} (hermitian up to rounding), g = L^{-H} y.  H_m is
+// used as computed: pairs of its hermitian part would not be exact for the
+// computed Hbar, and the restart relation would decay from cycle to cycle.
+// The residual direction is the unit vector orthogonal to range(Hbar),
+// taken from the QR factorisation of [Hbar | e_m].
+Restart harmonic_restart_herm(const la::Mat &H, int m, int k) {
+  la::Mat Hm(m, m);
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) Hm(i, j) = H(i, j);
+  la::Mat Li;
+  LQCD_CHECK(la::cholesky_inv(la::matmul_hn(H, H), Li), LQCD_ENOCONV,
+             "MINRES-DR: Hbar^H Hbar is not positive definite");
+  la::Mat C = la::matmul(Li, la::matmul(la::adjoint(Hm), la::adjoint(Li)));
+  std::vector<cdouble> mu;
+  la::Mat Y;
+  LQCD_CHECK(la::eig(C, mu, Y), LQCD_ENOCONV, "MINRES-DR: harmonic Ritz eigenproblem did not converge");
+  la::Mat G = la::matmul_hn(Li, Y);  // g = L^{-H} y
+  std::vector<int> ord(m);
+  for (int i = 0; i < m; ++i) ord[i] = i;
+  // smallest |theta| = largest |mu|; ties by index
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::abs(mu[a]) > std::abs(mu[b]); });
+  la::Mat He(m + 1, m + 1);
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i <= m; ++i) He(i, j) = H(i, j);
+  He(m, m) = 1.0;
+  la::QR qe;
+  qe.factor(He);
+  const la::Mat Qe = qe.thin_q();
+  la::Mat P(m + 1, k + 1);
+  Restart R;
+  for (int q = 0; q < k; ++q) {
+    const int col = ord[q];
+    const cdouble th = mu[col] != cdouble(0, 0) ? 1.0 / mu[col]
+                                                 : cdouble(std::numeric_limits<double>::infinity(), 0);
+    double gn = 0, rn = 0;
+    for (int i = 0; i < m; ++i) {
+      P(i, q) = G(i, col);
+      gn += std::norm(G(i, col));
+    }
+    for (int i = 0; i <= m; ++i) {  // |Hbar g - theta [g; 0]|
+      cdouble v = 0;
+      for (int j = 0; j < m; ++j) v += H(i, j) * G(j, col);
+      if (i < m) v -= th * G(i, col);
+      rn += std::norm(v);
+    }
+    R.theta.push_back(th);
+    R.resid.push_back(std::sqrt(rn / gn));
+  }
+  for (int i = 0; i <= m; ++i) P(i, k) = Qe(i, m);
+  la::QR qr;
+  qr.factor(P);
+  R.P = qr.thin_q();
+  return R;
+}
+
 la::Mat sub(const la::Mat &A, int r, int c) {
   la::Mat B(r, c);
   for (int j = 0; j < c; ++j)
@@ -353,8 +468,11 @@ void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lq
   int j0 = 0;
   std::vector<cdouble> Hcols;
   int nev = p.n_eig > 0 ? std::min(p.n_eig, k) : k;
+  const bool lz = p.method == LQCD_KRYLOV_MINRESDR;
+  int kept = 0;  // MINRES-DR: vectors kept by the last restart
   for (;;) {
-    arnoldi<double>(c, A, V, n, 0, j0, m, 1, s, kReorthAlways);
+    if (lz) lanczos_ext(c, A, V, n, j0, m, kept, s);
+    else arnoldi<double>(c, A, V, n, 0, j0, m, 1, s, kReorthAlways);
     st.matvecs += m - j0;
     harvest_reorth(c, s, 1, std::vector<int>{0}, reorth1);
     st.reorth = reorth1[0];
@@ -377,7 +495,7 @@ void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lq
     h2d(c, s.vec, dv.data(), size_t(m) * sizeof(cdouble));
     gemm_nn<double>(c, V, n, 0, m, s.vec, m, 0, X, n, 0, 1, n, 1, 1.0);
     st.cycles += 1;
-    Restart R = harmonic_restart(H, m, k);
+    Restart R = lz ? harmonic_restart_herm(H, m, k) : harmonic_restart(H, m, k);
     bool done = res <= p.tol_super * bnorm;
     if (done && p.eig_tol > 0)
       for (int q = 0; q < nev; ++q)
@@ -400,6 +518,7 @@ void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lq
     std::fill(cv.begin(), cv.end(), cdouble(0, 0));
     for (int q = 0; q <= k; ++q) cv[q] = cn[q];
     j0 = k;
+    kept = k + 1;
   }
   d->k = k;
   d->n = n;
@@ -675,6 +794,10 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
                "gmresdr_solve: bad inner precision");
     LQCD_CHECK(op == LQCD_OP_SCHUR || p.inner == LQCD_F64 || p.inner == LQCD_F32, LQCD_EINVAL,
                "gmresdr_solve: 16-bit storage is available for LQCD_OP_SCHUR only");
+    LQCD_CHECK(p.method == LQCD_KRYLOV_GMRESDR || p.method == LQCD_KRYLOV_MINRESDR, LQCD_EINVAL,
+               "gmresdr_solve: unknown method %d", p.method);
+    LQCD_CHECK(p.method != LQCD_KRYLOV_MINRESDR || op == LQCD_OP_MG5, LQCD_EINVAL,
+               "gmresdr_solve: MINRES-DR needs the hermitian LQCD_OP_MG5");
     const size_t n = op == LQCD_OP_SCHUR ? half_len(c->g) : full_len(c->g);
     const size_t fl = full_len(c->g);
     if (stats)

@@ -36,7 +36,10 @@ class SolveParams(ctypes.Structure):
                 ("tol", ctypes.c_double), ("tol_super", ctypes.c_double),
                 ("eig_tol", ctypes.c_double), ("n_eig", ctypes.c_int),
                 ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("rhs_block", ctypes.c_int), ("proj_m", ctypes.c_int)]
+                ("rhs_block", ctypes.c_int), ("proj_m", ctypes.c_int), ("method", ctypes.c_int)]
+
+
+_METHODS = {"gmres-dr": 0, "minres-dr": 1}
 
 
 class SolveStats(ctypes.Structure):
@@ -57,6 +60,7 @@ _SIGS = {
     "lqcd_noise_z4": [_P, ctypes.c_uint64, ctypes.c_int64, _I, _P, _P],
     "lqcd_pack_eo": [_P, _I, _P, _P, _I],
     "lqcd_unpack_eo": [_P, _I, _P, _P, _I],
+    "lqcd_gamma5": [_P, _P, _P, _I],
     "wilson_apply": [_P, _I, _I, _I, _P, _P, _I],
     "gmresdr_solve": [_P, _I, ctypes.POINTER(SolveParams), _P, _P, _I, ctypes.POINTER(_P),
                       ctypes.POINTER(SolveStats)],
@@ -244,6 +248,15 @@ class Context:
         _check(lib().lqcd_unpack_eo(self.handle, _PREC[prec], _ptr(eo), _ptr(out), eo.shape[0]))
         return out
 
+    def gamma5(self, x, out=None):
+        """g5 x for LEX complex128 fields (in place when out is x)."""
+        import torch
+        if x.numel() != x.shape[0] * 12 * self.V or x.dtype != torch.complex128:
+            raise ValueError("gamma5 needs LEX complex128 fields of this lattice")
+        out = torch.empty_like(x) if out is None else out
+        _check(lib().lqcd_gamma5(self.handle, _ptr(x), _ptr(out), x.shape[0]))
+        return out
+
     def wilson_apply(self, op, x, prec="f64", layout="lex", out=None):
         import torch
         if x.numel() != x.shape[0] * 12 * self.V:
@@ -257,12 +270,14 @@ class Context:
     # ----------------------------------------------------------- solvers
     def gmresdr_solve(self, b, op="schur", m=20, k=10, tol=1e-10, tol_super=1e-13, eig_tol=0.0,
                       n_eig=0, max_cycles=1000, inner="f64", inner_tol=1e-5, rhs_block=1,
-                      defl=None, proj_m=0):
+                      defl=None, proj_m=0, method="gmres-dr"):
+        """method: "gmres-dr" or "minres-dr" (hermitian op "MG5" only) for the
+        first right-hand side when no deflation data is given."""
         import torch
         x = torch.empty_like(b)
         nrhs = b.shape[0]
         p = SolveParams(m, k, max_cycles, tol, tol_super, eig_tol, n_eig, _PREC[inner], inner_tol,
-                        rhs_block, proj_m)
+                        rhs_block, proj_m, _METHODS[method])
         stats = (SolveStats * max(nrhs, 1))()
         h = _P(defl.handle.value if defl is not None else None)
         code = lib().gmresdr_solve(self.handle, _OPS[op], ctypes.byref(p), _ptr(b), _ptr(x), nrhs,

@@ -51,3 +51,10 @@ extern "C" void la_thin_q(int r, int c, const double *A, double *Q) {
   Mat q = f.thin_q();
   std::memcpy(Q, q.a.data(), sizeof(cd) * r * c);
 }
+
+extern "C" int la_cholesky_inv(int n, const double *A, double *Li) {
+  Mat L;
+  if (!cholesky_inv(load(n, n, A), L)) return 1;
+  std::memcpy(Li, L.a.data(), sizeof(cd) * n * n);
+  return 0;
+}

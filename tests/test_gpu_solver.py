@@ -93,6 +93,103 @@ def test_hermitian_solve_and_eigpairs():
     assert np.abs(lam - lam_d).max() < 1e-9
 
 
+def _near_critical_kappa(U, dims):
+    """kappa in [0.13, 0.26] where M' = M g5 of this small lattice has its
+    smallest |eigenvalue| on a coarse grid (an eigenvalue crossing zero)."""
+    best = None
+    for kappa in np.linspace(0.13, 0.26, 27):
+        M = W.dense_M(U, kappa, dims)
+        lam = np.linalg.eigvalsh(M @ W.dense_gamma(L.GAMMA5, L.volume(dims)))
+        v = np.abs(lam).min()
+        if best is None or v < best[1]:
+            best = (kappa, v)
+    return best
+
+
+@pytest.mark.parametrize("near_critical", [False, True])
+def test_minres_dr_hermitian(near_critical):
+    """MINRES-DR on M' = M g5 (full lattice): solutions vs dense LU, Ritz
+    pairs vs dense eigh, harmonic Ritz values vs the oracle's MINRES-DR, at
+    a moderate kappa and at a kappa where an eigenvalue of M' is near zero
+    (the regime where the hermitian system needs MINRES-DR)."""
+    require_gpu()
+    dims = (4, 4, 2, 4)
+    ctx, U = context(dims, 0.3, 31, 0.125)
+    kappa = 0.125
+    if near_critical:
+        kappa, lmin = _near_critical_kappa(U, dims)
+        ctx.set_kappa(kappa)
+    eta = z4_noise(5, dims, 0, 2)
+    say("MINRES-DR MG5", dims, "kappa", kappa)
+    x, defl, st = ctx.gmresdr_solve(to_gpu(eta), op="MG5", m=40, k=20, tol=1e-12, tol_super=1e-13,
+                                    eig_tol=1e-11, n_eig=8, max_cycles=400, method="minres-dr")
+    M = W.dense_M(U, kappa, dims)
+    Mp = M @ W.dense_gamma(L.GAMMA5, L.volume(dims))
+    xref = np.linalg.solve(Mp, eta.reshape(2, -1).T).T
+    xg = to_host(x).reshape(2, -1)
+    cond = np.linalg.cond(Mp)
+    for r in range(2):
+        assert rel_err(xg[r], xref[r]) < 1e-13 * cond + 1e-10
+        assert st[r]["true_resid"] < 1e-11
+    Q = 6
+    lam, res = defl.eigpairs(Q)
+    lam_d, E_d = K.hermitian_eigpairs_dense(Mp, Q)
+    assert (res < 1e-9).all()
+    assert np.abs(lam - lam_d).max() < 1e-9
+    # the oracle's MINRES-DR reaches the same harmonic Ritz values
+    shape = eta[0].shape
+    Ap = lambda v: W.apply_Mprime(U, kappa, v.reshape(shape)).ravel()
+    _, info = K.minres_dr(Ap, eta[0].ravel(), 40, 20, 1e-13, max_cycles=400, eig_tol=1e-11, n_eig=8)
+    th_o = np.sort(info["theta"][:6].real)
+    th_g = np.sort(defl.ritz()[:6].real)
+    assert np.abs(th_g - th_o).max() < 1e-9 * np.abs(th_o).max()
+
+
+def test_gamma5_matches_oracle():
+    require_gpu()
+    dims = (4, 4, 2, 4)
+    ctx, U = context(dims, 0.3, 31, 0.125)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((3,) + ctx.shape) + 1j * rng.standard_normal((3,) + ctx.shape)
+    y = to_host(ctx.gamma5(to_gpu(x)))
+    assert np.array_equal(y, W.g5(x))
+    xg = to_gpu(x)
+    ctx.gamma5(xg, out=xg)  # in place
+    assert np.array_equal(to_host(xg), W.g5(x))
+
+
+def test_single_special_rhs_production():
+    """Sec. 10's production setup: the hermitian modes of one MINRES-DR solve
+    deflate every later solve of M' (GMRES-Proj on LQCD_OP_MG5, mixed
+    precision), and x = g5 y solves M x = eta (compared with dense LU)."""
+    require_gpu()
+    dims, kappa = (4, 4, 2, 4), 0.125
+    ctx, U = context(dims, 0.3, 31, kappa)
+    eta0 = z4_noise(5, dims, 0, 1)
+    say("production: MINRES-DR modes", dims)
+    _, hdefl, _ = ctx.gmresdr_solve(to_gpu(eta0), op="MG5", m=40, k=20, tol=1e-12, tol_super=1e-13,
+                                    eig_tol=1e-10, n_eig=10, max_cycles=300, method="minres-dr")
+    eta = z4_noise(6, dims, 0, 4)
+    say("production: deflated MG5 solves")
+    y, _, st = ctx.gmresdr_solve(to_gpu(eta), op="MG5", m=40, k=20, tol=1e-11, defl=hdefl, inner="f32",
+                                 inner_tol=1e-4, rhs_block=4)
+    x = to_host(ctx.gamma5(y))
+    xref, _ = _dense_solve(U, kappa, dims, eta)
+    for r in range(4):
+        assert rel_err(x[r], xref[r]) < 1e-9
+        assert st[r]["true_resid"] < 1e-11
+
+
+def test_minres_dr_rejects_non_hermitian_operator():
+    require_gpu()
+    from paper_1903_06986_amd.lqcd import LqcdError
+    dims = (4, 4, 2, 4)
+    ctx, U = context(dims, 0.3, 31, 0.125)
+    eta = z4_noise(5, dims, 0, 1)
+    with pytest.raises(LqcdError):
+        ctx.gmresdr_solve(to_gpu(eta), op="schur", m=20, k=10, method="minres-dr")
+
+
 @pytest.mark.parametrize("dims,kappa", [((4, 4, 4, 4), 0.12), ((6, 4, 2, 8), 0.13)])
 def test_mixed_precision_solve(dims, kappa):
     require_gpu()

@@ -100,3 +100,20 @@ def test_thin_q(la):
     # same column space
     P = Q @ Q.conj().T
     assert np.abs(P @ A - A).max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 4, 40])
+def test_cholesky_inverse(la, n):
+    """Li = L^{-1} of the Cholesky factor: lower triangular, L = numpy's
+    factor, and Li A Li^H = I; a matrix that is not positive definite is
+    refused."""
+    rng = np.random.default_rng(20 + n)
+    B = _rand(rng, n + 3, n)
+    A = _cm(B.conj().T @ B)
+    Li = np.zeros((n, n), complex, order="F")
+    assert la.la_cholesky_inv(n, _p(A), _p(Li)) == 0
+    assert np.abs(np.triu(Li, 1)).max(initial=0) == 0
+    assert np.abs(np.linalg.inv(Li) - np.linalg.cholesky(A)).max() < 1e-10 * np.abs(A).max()
+    assert np.abs(Li @ A @ Li.conj().T - np.eye(n)).max() < 1e-10
+    C = _cm(-A)
+    assert la.la_cholesky_inv(n, _p(C), _p(Li)) == 1

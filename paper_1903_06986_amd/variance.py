@@ -1,0 +1,152 @@
+"""Variance study of the subtraction methods (Secs. 7-9): standard errors of
+the loop estimates against the number Q of deflated hermitian modes, and the
+relative efficiencies RE = (1 / dy^2 - 1) x 100 of Sec. 7 (dy = ratio of the
+error bars of the tested and the reference method), against NS and PS,
+averaged over configurations.
+
+Per configuration the path runs once, as library calls only: Z(4) noise,
+even/odd solves (GMRES-DR on the first noise vector, GMRES-Proj on the
+rest), hermitian modes of M' from one MINRES-DR solve (Sec. 8), PS and POLY
+subtraction vectors with exact trace corrections; the hermitian-forced
+methods HFES, HFPS and HFPOLY are then formed for every Q of the list from
+the same modes.  The error bar of an operator is the standard error of the
+part of its whole-lattice trace that carries the signal (Sec. 6, Table 2):
+the real part for the scalar, the imaginary part for the local and the
+point-split vectors.
+
+    python -m paper_1903_06986_amd.variance --workload c1 --configs 4 --noise 16 --q 0,2,4,8
+"""
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+
+METHODS = ("NS", "PS", "POLY", "HFES", "HFPS", "HFPOLY")
+HF = ("HFES", "HFPS", "HFPOLY")
+GROUPS = {"scalar": (0,), "local_vector": (1, 2, 3, 4), "point_split": (5, 6, 7, 8)}
+
+
+def signal_part(code):
+    """Index of the part (0 real, 1 imaginary) that carries the signal."""
+    return 0 if code == 0 else 1
+
+
+def relative_efficiency(err, ref):
+    """RE = (1 / dy^2 - 1) x 100 with dy = err / ref (Sec. 7)."""
+    dy = np.asarray(err, dtype=float) / np.asarray(ref, dtype=float)
+    return (1.0 / dy ** 2 - 1.0) * 100.0
+
+
+def config_errors(ctx, eta, thetas, q_list, p):
+    """Standard errors of one configuration: {method: [per operator]} for
+    NS, PS, POLY and {(method, Q): [...]} for the hermitian-forced ones."""
+    import torch
+    from . import lqcd
+    thetas = tuple(thetas)
+    sig = [signal_part(t) for t in thetas]
+
+    def errs(xt, corr):
+        _, e = ctx.loop_estimate(eta, x, xt, corr, thetas)
+        return np.array([e[a, -1, sig[a]] for a in range(len(thetas))])
+
+    x, defl, st = ctx.gmresdr_solve(eta, op="schur", m=p["m"], k=p["k"], tol=p["tol"], tol_super=p["tol_super"],
+                                    inner=p["inner"], inner_tol=p["inner_tol"], rhs_block=p["rhs_block"],
+                                    max_cycles=p["max_cycles"])
+    qmax = max(q_list)
+    hdefl = None
+    if qmax > 0:
+        _, hdefl, _ = ctx.gmresdr_solve(eta[0:1], op="MG5", m=p["herm_m"], k=p["herm_k"], tol=p["tol"],
+                                        tol_super=p["tol_super"], eig_tol=p["eig_tol"], n_eig=qmax,
+                                        max_cycles=p["max_cycles"], method="minres-dr")
+    out = {"NS": errs(None, None)}
+    xt_ps, corr_ps = ctx.pert_subtract(p["pert_order"], eta, thetas)
+    out["PS"] = errs(xt_ps, corr_ps)
+    xt_poly, corr_poly, cpoly, _ = ctx.poly_subtract(p["poly_degree"], eta, b=eta[0:1], thetas=thetas)
+    out["POLY"] = errs(xt_poly, corr_poly)
+    ones = np.ones(p["pert_order"] + 1, dtype=np.complex128)
+    for q in q_list:
+        if q == 0:  # no modes: the hermitian-forced methods reduce to NS, PS, POLY
+            out[("HFES", 0)], out[("HFPS", 0)], out[("HFPOLY", 0)] = out["NS"], out["PS"], out["POLY"]
+            continue
+        xt, corr, _ = ctx.deflate_project(hdefl, q, eta, xt=torch.zeros_like(eta), mode=lqcd.DEFL_HFES,
+                                          thetas=thetas)
+        out[("HFES", q)] = errs(xt, corr)
+        xt, corr, _ = ctx.deflate_project(hdefl, q, eta, xt=xt_ps.clone(), corr=corr_ps, mode=lqcd.DEFL_EIGPOLY,
+                                          coeffs=ones, thetas=thetas)
+        out[("HFPS", q)] = errs(xt, corr)
+        xt, corr, _ = ctx.deflate_project(hdefl, q, eta, xt=xt_poly.clone(), corr=corr_poly,
+                                          mode=lqcd.DEFL_EIGPOLY, coeffs=cpoly, thetas=thetas)
+        out[("HFPOLY", q)] = errs(xt, corr)
+    defl.free()
+    if hdefl is not None:
+        hdefl.free()
+    return out
+
+
+def summarize(per_config, thetas, q_list):
+    """Average the error bars over configurations and form the RE tables at
+    the largest Q, per operator and per operator group."""
+    thetas = tuple(thetas)
+    keys = list(per_config[0].keys())
+    mean = {k: np.mean([c[k] for c in per_config], axis=0) for k in keys}
+    qmax = max(q_list)
+    tested = {"POLY": mean["POLY"], "HFES": mean[("HFES", qmax)], "HFPS": mean[("HFPS", qmax)],
+              "HFPOLY": mean[("HFPOLY", qmax)]}
+    groups = {g: [thetas.index(c) for c in cs if c in thetas] for g, cs in GROUPS.items()}
+    groups = {g: ix for g, ix in groups.items() if ix}
+
+    def by_group(v):
+        return {g: float(np.mean(v[ix])) for g, ix in groups.items()}
+
+    re = {ref: {m: by_group(relative_efficiency(e, mean[ref])) for m, e in tested.items()} for ref in ("NS", "PS")}
+    curve = {m: {str(q): by_group(mean[(m, q)]) for q in q_list} for m in HF}
+    return {"operators": list(thetas), "Q": list(q_list), "configs": len(per_config),
+            "error": {m: by_group(mean[m]) for m in ("NS", "PS", "POLY")},
+            "error_vs_Q": curve, "RE_at_Qmax": re}
+
+
+def study(workload="c1", configs=4, n_noise=None, q_list=(0, 2, 4, 8), thetas=tuple(range(9)), kappa=None,
+          inner="f32", tol=1e-10, progress=None):
+    from . import Context
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from synth import random_su3_links, get_config
+    cfg = get_config(workload)
+    dims = cfg["dims"]
+    kappa = kappa if kappa is not None else (cfg["kappas"][0] if cfg.get("kappas") else 0.125)
+    n_noise = n_noise or cfg["n_noise"]
+    p = dict(m=cfg["m"], k=cfg["k"], herm_m=cfg["herm_m"], herm_k=cfg["herm_k"], pert_order=cfg["pert_order"],
+             poly_degree=cfg["poly_degree"], tol=tol, tol_super=min(tol, 1e-12), inner=inner, inner_tol=1e-4,
+             rhs_block=min(8, n_noise), max_cycles=2000, eig_tol=1e-8)
+    per = []
+    for c in range(configs):
+        U = random_su3_links(dims, cfg["eps"], cfg["link_seed"] + 100 * c)
+        ctx = Context(dims, U, kappa)
+        eta = ctx.noise_z4(cfg["noise_seed"] + 100 * c, 0, n_noise)
+        per.append(config_errors(ctx, eta, thetas, q_list, p))
+        if progress:
+            progress(c)
+        ctx.close()
+    out = summarize(per, thetas, q_list)
+    out.update(workload=workload, dims=list(dims), kappa=kappa, noise=n_noise)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--configs", type=int, default=4)
+    ap.add_argument("--noise", type=int, default=None)
+    ap.add_argument("--q", default="0,2,4,8")
+    ap.add_argument("--kappa", type=float, default=None)
+    ap.add_argument("--inner", default="f32", choices=["f64", "f32", "f16", "bf16"])
+    a = ap.parse_args()
+    q = tuple(int(v) for v in a.q.split(","))
+    r = study(a.workload, a.configs, a.noise, q, kappa=a.kappa, inner=a.inner,
+              progress=lambda c: print("[variance] configuration %d done" % c, file=sys.stderr, flush=True))
+    print(json.dumps(r))
+
+
+if __name__ == "__main__":
+    main()

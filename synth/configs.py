@@ -31,6 +31,11 @@ CONFIGS = {
     "c4": dict(lattices=((8, 8, 8, 8), (12, 12, 12, 24), (16, 16, 16, 32)),
                n_rhs=(17, 64, 160), eps=0.25, kappas=(0.125,), m=40, k=20,
                link_seed=1004, noise_seed=2004),
+    # variance study (standard error vs deflated modes, relative efficiencies)
+    # on the paper's small lattice shape, several configurations
+    "c6": dict(dims=(8, 8, 8, 8), eps=0.25, kappas=(0.128,), n_noise=64, m=40, k=20,
+               pert_order=7, poly_degree=7, n_hermitian=30, herm_m=80, herm_k=45,
+               link_seed=1006, noise_seed=2006),
     # differentiation axis
     "c5": dict(dims=(12, 12, 12, 12), eps=0.25, kappas=(0.124,), n_noise=32,
                m=40, k=20, link_seed=1005, noise_seed=2005),

@@ -7,7 +7,9 @@ written by oracle/critical_kappa.py), GMRES-DR(80,40) on eta^(0)
 super-converged, hermitian modes of M' (Q = 30), PS order 7, POLY degree 7.
 
 Setup (once per configuration, timed separately): first GMRES-DR solve,
-hermitian eigenpairs, Min-Res coefficients, exact trace corrections.
+hermitian eigenpairs of M' from one MINRES-DR solve (Sec. 8; GMRES-DR on
+the same system is timed beside it for the record), Min-Res coefficients,
+exact trace corrections.
 One timed step = one batch of `rhs_block` Z(4) noise vectors through every
 per-noise row of the path: noise generation, GMRES-Proj solves to a 1e-10
 true residual (mixed: FP32 inner solves in FP64 refinement, the inner
@@ -17,7 +19,9 @@ PS / POLY / HFES / HFPS / HFPOLY subtraction vectors and the estimator for
 the nine operators of Table 2 (scalar, local vector g1..g4, point-split
 vector in x, y, z, t).  Untimed afterwards: every precision solves the same
 noise batch and reports its estimates' difference from plain FP64 and one
-solution's residual under the FP64 oracle's operator.
+solution's residual under the FP64 oracle's operator; the single-special-
+right-hand-side production setup of Sec. 10 (every solve on the hermitian
+M' deflated by the MINRES-DR modes) is timed against the even/odd solves.
 
 metric: deflated noise-solves/s (mixed precision), with the plain-FP64
 rate and the ratio in the same line; roofline of the dominant kernel from
@@ -358,7 +362,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--kappa", type=float, default=None)
-    ap.add_argument("--rhs-block", type=int, default=8)
+    ap.add_argument("--rhs-block", type=int, default=16)
     ap.add_argument("--proj-m", type=int, default=0, help="GMRES-Proj cycle length (0: m - k)")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-10)

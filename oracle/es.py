@@ -11,9 +11,12 @@ eigenvectors (e_L^(q)^+ e_R^(q') = delta):
 The pairs come from the even/odd GMRES-DR data of the first noise vector
 (Sec. 7), with the relation between reduced and full eigenvectors written
 out here (the paper only states that it exists):
-  * Ritz pairs of Mhat in span(V_k): H_k = V_k^+ Mhat V_k = S diag(lh) S^{-1};
-    right vectors rh = V_k S, left vectors lh_vec = V_k S^{-+}, so that
-    lh_vec^+ rh = 1;
+  * Ritz pairs of Mhat in span(V_k): H_k = V_k^+ Mhat V_k = S diag(lh) S^{-1},
+    right vectors rh = V_k S.  The Krylov space holds the right
+    eigenvectors, not the left ones (Mhat is not normal), so the left
+    vectors come from g5-hermiticity, Mhat^+ = g5 Mhat g5: the left
+    eigenvector of lh is g5 times the right one of conj(lh) (the Ritz value
+    closest to conj(lh)), scaled so that lh_vec^+ rh = 1;
   * M = [[1, -kappa D_eo], [-kappa D_oe, 1]] in (even, odd) blocks and
     Mhat = 1 - kappa^2 D_eo D_oe: for Mhat rh = lh rh, the full vector
     r = (rh, kappa / (1 - lambda) D_oe rh) is a right eigenvector of M
@@ -31,15 +34,20 @@ from . import subtract as S
 from . import pointsplit as PSO
 
 
-def ritz_pairs_eo(defl_V, defl_H):
+def ritz_pairs_eo(defl_V, defl_H, g5):
     """Right/left Ritz pairs of Mhat from A V_k = V_{k+1} Hbar_k: (lh, Rh, Lh)
-    with Rh, Lh of shape (n, k) and Lh^+ Rh = I."""
+    with Rh, Lh of shape (n, k) and diag(Lh^+ Rh) = 1.  g5 applies gamma_5
+    to a flattened field."""
     k = defl_H.shape[1]
     Hk = defl_H[:k, :k]
     lh, Sr = np.linalg.eig(Hk)
-    Sl = np.linalg.inv(Sr).conj().T   # columns: left eigenvectors of Hk, Sl^+ Sr = I
-    Vk = defl_V[:, :k]
-    return lh, Vk @ Sr, Vk @ Sl
+    Rh = defl_V[:, :k] @ Sr
+    Lh = np.empty_like(Rh)
+    for q in range(k):
+        p = int(np.argmin(np.abs(lh - np.conj(lh[q]))))   # the conjugate partner
+        l = g5(Rh[:, p])
+        Lh[:, q] = l / np.conj(np.vdot(l, Rh[:, q]))
+    return lh, Rh, Lh
 
 
 def full_pairs(U, kappa, dims, lh, Rh, Lh, branch=1):

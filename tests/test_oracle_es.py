@@ -92,15 +92,20 @@ def test_ritz_pairs_from_gmres_dr_data(setup):
     eta = z4_noise(5, DIMS, 0, 1)[0]
     src = W.eo_source(U, KAPPA, eta, DIMS).ravel()
     _, info = K.gmres_dr(Ahat, src, 40, 20, 1e-13, max_cycles=300, eig_tol=1e-11, n_eig=10)
-    lh, Rh, Lh = ES.ritz_pairs_eo(info["V"], info["H"])
-    assert np.abs(Lh.conj().T @ Rh - np.eye(lh.size)).max() < 1e-9
+    g5 = lambda v: W.g5(v.reshape(shape)).ravel()
+    lh, Rh, Lh = ES.ritz_pairs_eo(info["V"], info["H"], g5)
+    assert np.abs(np.diag(Lh.conj().T @ Rh) - 1).max() < 1e-12
     lam, R, Lv = ES.smallest(*ES.full_pairs(U, KAPPA, DIMS, lh, Rh, Lh), 6)
     spec = np.linalg.eigvals(M)
     ref = spec[np.argsort(np.abs(spec))][:6]
     assert np.abs(np.sort_complex(lam) - np.sort_complex(ref)).max() < 1e-8
-    Rf = R.reshape(6, -1)
+    Rf, Lf = R.reshape(6, -1), Lv.reshape(6, -1)
     for i in range(6):
+        # right AND left eigenvectors of M (the left ones are not in the
+        # Krylov space; they come from the g5 partner)
         assert np.linalg.norm(M @ Rf[i] - lam[i] * Rf[i]) < 1e-8 * np.linalg.norm(Rf[i])
+        assert np.linalg.norm(Lf[i].conj() @ M - lam[i] * Lf[i].conj()) < 1e-8 * np.linalg.norm(Lf[i])
+        assert abs(np.vdot(Lf[i], Rf[i]) - 1) < 1e-10
 
 
 def test_trace_matches_dense_subtraction_matrix(setup):

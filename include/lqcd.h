@@ -86,7 +86,9 @@ typedef enum {
 /* Modes of deflate_project. */
 typedef enum {
   LQCD_DEFL_HFES = 0,     /* weights 1/lambda'_q (Eqs. (66)-(68)) */
-  LQCD_DEFL_EIGPOLY = 1   /* weights 1/lambda'_q - 1/xi'_q for a polynomial (Eqs. (69)-(72)) */
+  LQCD_DEFL_EIGPOLY = 1,  /* weights 1/lambda'_q - 1/xi'_q for a polynomial (Eqs. (69)-(72)) */
+  LQCD_DEFL_ES = 2        /* eigenvalue subtraction (Sec. 5.3) with the even/odd deflation
+                             space: right/left eigenvectors of M, weights 1/lambda_q */
 } lqcd_defl_mode;
 
 typedef struct {
@@ -211,7 +213,16 @@ void lqcd_defl_free(lqcd_defl *defl);
  *   trace_corr[th][t] += sum_q w_q sum_{x in t} e'_q(x)^+ Theta g5 e'_q(x)
  * (host complex128 [ntheta][Lt], Theta codes from thetas_host).  HFES is
  * xt = 0 plus this; HFPS / HFPOLY are PS / POLY output plus this.
- * xi_inv_host: optional host complex128 [Q] receiving 1/xi'_q. */
+ * xi_inv_host: optional host complex128 [Q] receiving 1/xi'_q.
+ * Mode ES (Sec. 5.3, eigenvalue subtraction) takes the even/odd deflation
+ * space instead (op SCHUR): with the Q eigenvalues lambda_q of M of
+ * smallest |lambda| and biorthonormal right / left eigenvectors r_q, l_q
+ * reconstructed from the Ritz pairs of Mhat (lambda = 1 - sqrt(1 -
+ * lambda_hat); odd halves kappa / (1 - lambda) D_oe r_hat and
+ * kappa / (1 - conj lambda) g5 D_oe g5 l_hat, l halved so that l^+ r = 1) it
+ * accumulates xt[n] += sum_q r_q (l_q^+ eta[n]) / lambda_q and
+ * trace_corr[th][t] += sum_q sum_{x in t} l_q(x)^+ Theta r_q(x) / lambda_q,
+ * and xi_inv_host receives lambda_q.  EINVAL for a space of op MG5. */
 lqcd_status deflate_project(lqcd_ctx *ctx, lqcd_defl *defl, int Q, lqcd_defl_mode mode,
                             const double *coeffs_host, int ncoeff, const int *thetas_host,
                             int ntheta, const void *eta, void *xt, int nrhs,

@@ -29,6 +29,14 @@ struct lqcd_defl {
   // and 1/xi'_q per polynomial (coefficients -> values).
   std::vector<lqcd::cdouble> bil;
   std::vector<std::pair<std::vector<lqcd::cdouble>, std::vector<lqcd::cdouble>>> xi_cache;
+  // Eigenvalue subtraction (non-hermitian space, op SCHUR), filled on
+  // request: eigenvalues of M, right and left full-lattice eigenvectors
+  // (even/odd layout, FP64, full_len apart; L^+ R = 1 per mode) and their
+  // per-mode trace bilinears sum_{x in t} l_q^+ Theta r_q, [q][theta][t].
+  int Qes = 0;
+  std::vector<lqcd::cdouble> es_lam;
+  lqcd::DevBuf ER, EL;
+  std::vector<lqcd::cdouble> es_bil;
 };
 
 namespace lqcd {

@@ -220,8 +220,8 @@ __global__ void __launch_bounds__(kBlock)
 // out[th][s] = sum_q w_q e_q(s)^+ Theta g5 e_q(s), e_q in the even/odd
 // layout (full fields n apart), s lexicographic.
 __global__ void __launch_bounds__(kBlock)
-    k_eig_bilinear(Geom g, const cx<double> *__restrict__ E, size_t n, int Q,
-                   const cx<double> *__restrict__ w, cx<double> *__restrict__ out) {
+    k_eig_bilinear(Geom g, const cx<double> *__restrict__ E, const cx<double> *__restrict__ F, size_t n,
+                   int Q, const cx<double> *__restrict__ w, cx<double> *__restrict__ out, int g5) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   const int x = s % g.L[0], y = (s / g.L[0]) % g.L[1], z = (s / (g.L[0] * g.L[1])) % g.L[2],
@@ -230,22 +230,26 @@ __global__ void __launch_bounds__(kBlock)
   const size_t Vh = g.Vh, off = size_t(p) * 12 * Vh + (s >> 1);
   double acc[kNumTheta][2] = {};
   for (int q = 0; q < Q; ++q) {
-    cx<double> e[4][3];
+    cx<double> e[4][3], f[4][3];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) e[sp][c] = E[q * n + off + (sp * 3 + c) * Vh];
+      for (int c = 0; c < 3; ++c) {
+        e[sp][c] = E[q * n + off + (sp * 3 + c) * Vh];
+        f[sp][c] = F[q * n + off + (sp * 3 + c) * Vh];
+      }
     const cx<double> wq = w[q];
 #pragma unroll
     for (int th = 0; th < kNumTheta; ++th) {
-      // (Theta g5 e)_r = Theta_{r, col} g5_{col} e_col
+      // (Theta [g5] f)_r = Theta_{r, col} [g5_{col}] f_col
       cx<double> sum = mk(0.0, 0.0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int col = kGamma[th].col[r];
-        const cx<double> tv = mk(kGamma[th].re[r] * kGamma[5].re[col], kGamma[th].im[r] * kGamma[5].re[col]);
+        const double s5 = g5 ? kGamma[5].re[col] : 1.0;
+        const cx<double> tv = mk(kGamma[th].re[r] * s5, kGamma[th].im[r] * s5);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sum = sum + cmulc(e[r][c], tv * e[col][c]);
+        for (int c = 0; c < 3; ++c) sum = sum + cmulc(e[r][c], tv * f[col][c]);
       }
       cx<double> v = wq * sum;
       acc[th][0] += v.re;
@@ -256,38 +260,41 @@ __global__ void __launch_bounds__(kBlock)
   for (int th = 0; th < kNumTheta; ++th) out[size_t(th) * g.V + s] = mk(acc[th][0], acc[th][1]);
 }
 
-// Point-split bilinears of the hermitian-forced trace terms:
-// out[mu][s] = e(s)^+ (Theta(mu) g5 e)(s) for one mode e in the even/odd
-// layout (full field), s lexicographic.
+// Point-split bilinears of the subtraction trace terms:
+// out[mu][s] = e(s)^+ (Theta(mu) [g5] f)(s) for one mode (e, f) in the
+// even/odd layout (full fields), s lexicographic; g5 = 1 in the
+// hermitian-forced terms (f = e), 0 in eigenvalue subtraction (e = left,
+// f = right eigenvector).
 __global__ void __launch_bounds__(kBlock)
     k_eig_bilinear_ps(Geom g, const cx<double> *__restrict__ U, double kappa,
-                      const cx<double> *__restrict__ E, cx<double> *__restrict__ out) {
+                      const cx<double> *__restrict__ E, const cx<double> *__restrict__ F,
+                      cx<double> *__restrict__ out, int g5) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   const int Ls[4] = {g.L[0], g.L[1], g.L[2], g.L[3]};
   const int c[4] = {s % Ls[0], (s / Ls[0]) % Ls[1], (s / (Ls[0] * Ls[1])) % Ls[2], s / (Ls[0] * Ls[1] * Ls[2])};
   const size_t Vh = g.Vh;
-  auto load = [&](const int cc[4], cx<double> v[12], bool gam5) {
+  auto load = [&](const cx<double> *src, const int cc[4], cx<double> v[12], bool gam5) {
     const int p = (cc[0] + cc[1] + cc[2] + cc[3]) & 1;
     const int sl = cc[0] + Ls[0] * (cc[1] + Ls[1] * (cc[2] + Ls[2] * cc[3]));
     const size_t off = size_t(p) * 12 * Vh + size_t(sl >> 1);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      v[k] = E[off + k * Vh];
+      v[k] = src[off + k * Vh];
       if (gam5 && k >= 6) v[k] = -v[k];
     }
   };
   cx<double> a[12];
-  load(c, a, false);
+  load(E, c, a, false);
 #pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
     int cf[4] = {c[0], c[1], c[2], c[3]}, cb[4] = {c[0], c[1], c[2], c[3]};
     cf[mu] = c[mu] + 1 == Ls[mu] ? 0 : c[mu] + 1;
     cb[mu] = c[mu] == 0 ? Ls[mu] - 1 : c[mu] - 1;
     cx<double> b[12];
-    load(cf, b, true);
+    load(F, cf, b, g5 != 0);
     const cx<double> vf = ps_half<true>(a, b, ps_link(U, g, c[0], c[1], c[2], c[3], mu), Vh, mu);
-    load(cb, b, true);
+    load(F, cb, b, g5 != 0);
     const cx<double> vb = ps_half<false>(a, b, ps_link(U, g, cb[0], cb[1], cb[2], cb[3], mu), Vh, mu);
     out[size_t(mu) * g.V + s] = kappa * (vb - vf);
   }
@@ -443,6 +450,152 @@ std::vector<cdouble> kp_to_m(const std::vector<cdouble> &cc) {
   return a;
 }
 
+// Eigenvalue subtraction data (Sec. 5.3) from the even/odd deflation space
+// A V_k = V_{k+1} Hbar_k of Mhat (op SCHUR): Ritz pairs H_k = S diag(lh) S^{-1}
+// give right even vectors V_k S.  The Krylov space holds no left
+// eigenvectors of the non-normal Mhat, so the left vector of lh is g5 times
+// the right Ritz vector of its conjugate partner (Mhat^H = g5 Mhat g5),
+// scaled so that lh_vec^H rh = 1.  The full eigenpairs of
+// M = [[1, -kappa D_eo], [-kappa D_oe, 1]] follow from
+// (1 - lambda)^2 = 1 - lh, small branch lambda = 1 - sqrt(1 - lh):
+// r = (rh, kappa / (1 - lambda) D_oe rh),
+// l = (lh_vec, kappa / (1 - conj lambda) g5 D_oe g5 lh_vec) / 2
+// (D_eo^H = g5 D_oe g5; l^H r = 2 before the halving).  The Q pairs of
+// smallest |lambda| are kept with the space.
+void es_pairs(lqcd_ctx *c, lqcd_defl *d, int Q) {
+  LQCD_CHECK(d->op == LQCD_OP_SCHUR, LQCD_EINVAL,
+             "eigenvalue subtraction needs the even/odd deflation space (op LQCD_OP_SCHUR)");
+  LQCD_CHECK(Q >= 1 && Q <= d->k, LQCD_EINVAL, "Q = %d outside 1..k = %d", Q, d->k);
+  if (d->Qes == Q && d->ER.ptr) return;
+  const int k = d->k;
+  la::Mat T(k, k);
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i < k; ++i) T(i, j) = d->H(i, j);
+  std::vector<cdouble> lh;
+  la::Mat Sr;
+  LQCD_CHECK(la::eig(T, lh, Sr), LQCD_ENOCONV, "eigenvalue subtraction: Ritz eigenproblem did not converge");
+  std::vector<cdouble> lam(k);
+  for (int i = 0; i < k; ++i) lam[i] = 1.0 - std::sqrt(1.0 - lh[i]);
+  std::vector<int> ord(k);
+  for (int i = 0; i < k; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::abs(lam[a]) < std::abs(lam[b]); });
+  la::Mat SR(k, Q), SL(k, Q);  // SL: Ritz coefficients of each mode's conjugate partner
+  d->es_lam.resize(Q);
+  for (int q = 0; q < Q; ++q) {
+    const int j = ord[q];
+    int pj = 0;
+    for (int i = 1; i < k; ++i)
+      if (std::abs(lh[i] - std::conj(lh[j])) < std::abs(lh[pj] - std::conj(lh[j]))) pj = i;
+    d->es_lam[q] = lam[j];
+    for (int i = 0; i < k; ++i) {
+      SR(i, q) = Sr(i, j);
+      SL(i, q) = Sr(i, pj);
+    }
+  }
+  const size_t hl = half_len(c->g), fl = full_len(c->g);
+  cx<double> *R = static_cast<cx<double> *>(d->ER.ensure(size_t(Q) * fl * sizeof(cx<double>)));
+  cx<double> *L = static_cast<cx<double> *>(d->EL.ensure(size_t(Q) * fl * sizeof(cx<double>)));
+  fill_zero(c, R, size_t(Q) * fl * sizeof(cx<double>));
+  fill_zero(c, L, size_t(Q) * fl * sizeof(cx<double>));
+  DevBuf Sd;
+  cdouble *sr = static_cast<cdouble *>(Sd.ensure(2 * size_t(k) * Q * sizeof(cdouble)));
+  h2d(c, sr, SR.a.data(), SR.a.size() * sizeof(cdouble));
+  h2d(c, sr + size_t(k) * Q, SL.a.data(), SL.a.size() * sizeof(cdouble));
+  gemm_nn<double>(c, d->V.ptr, hl, 0, k, sr, k, 0, R, fl, 0, Q, hl, 1, 1.0);  // even halves
+  gemm_nn<double>(c, d->V.ptr, hl, 0, k, sr + size_t(k) * Q, k, 0, L, fl, 0, Q, hl, 1, 1.0);
+  // left even halves: g5 (partner), then scaled so that l^H r = 1
+  {
+    const size_t tot = 2 * 6 * size_t(c->g.Vh) * Q;  // the odd halves are still zero
+    hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(tot)), dim3(kBlock), 0, c->stream, L, size_t(c->g.Vh), fl, Q);
+    LQCD_HIP(hipGetLastError());
+    cdouble *Dd = static_cast<cdouble *>(c->ws[5].ensure(size_t(Q) * sizeof(cdouble)));
+    multi_dot<double>(c, L, fl, fl, 1, R, fl, fl, Q, Dd, 1);  // l_q^H r_q
+    std::vector<cdouble> D(Q), a(Q), z(Q, cdouble(0, 0));
+    d2h(c, D.data(), Dd, Q * sizeof(cdouble));
+    for (int q = 0; q < Q; ++q) {
+      LQCD_CHECK(std::abs(D[q]) > 0, LQCD_ENOCONV, "eigenvalue subtraction: left/right pair %d orthogonal", q);
+      a[q] = 1.0 / std::conj(D[q]);
+    }
+    axpby<double>(c, a.data(), L, fl, z.data(), L, fl, hl, Q, true);
+  }
+  // odd halves: D_oe r and g5 D_oe g5 l (parity 1 output from the even input)
+  hop_half<double>(c, 1, R, nullptr, R + hl, cdouble(0, 0), 1.0, false, false, Q, fl, 0, fl);
+  hop_half<double>(c, 1, L, nullptr, L + hl, cdouble(0, 0), 1.0, true, true, Q, fl, 0, fl);
+  std::vector<cdouble> ar(Q), al(Q), ae(Q, cdouble(0.5, 0)), zero(Q, cdouble(0, 0));
+  for (int q = 0; q < Q; ++q) {
+    ar[q] = c->kappa / (1.0 - d->es_lam[q]);
+    al[q] = 0.5 * c->kappa / (1.0 - std::conj(d->es_lam[q]));
+  }
+  axpby<double>(c, ar.data(), R + hl, fl, zero.data(), R + hl, fl, hl, Q, true);
+  axpby<double>(c, ae.data(), L, fl, zero.data(), L, fl, hl, Q, true);
+  axpby<double>(c, al.data(), L + hl, fl, zero.data(), L + hl, fl, hl, Q, true);
+  LQCD_HIP(hipStreamSynchronize(c->stream));
+  d->Qes = Q;
+  d->es_bil.clear();
+}
+
+// Eigenvalue subtraction: xt += sum_q (1/lambda_q) r_q (l_q^H eta),
+// corr += sum_q (1/lambda_q) sum_{x in t} l_q^H Theta r_q.
+void es_project(lqcd_ctx *c, lqcd_defl *d, int Q, const int *thetas, int nth, const void *eta, void *xt,
+                int nrhs, double *corr) {
+  es_pairs(c, d, Q);
+  const size_t fl = full_len(c->g);
+  const int Lt = c->g.L[3];
+  const cx<double> *R = d->ER.as<cx<double>>(), *L = d->EL.as<cx<double>>();
+  std::vector<cdouble> w(Q);
+  for (int q = 0; q < Q; ++q) w[q] = 1.0 / d->es_lam[q];
+  if (corr && nth > 0) {
+    if (d->es_bil.empty()) {
+      d->es_bil.assign(size_t(Q) * kNumOps * Lt, 0.0);
+      cdouble one(1, 0);
+      DevBuf wbuf, tmp;
+      cdouble *wd = static_cast<cdouble *>(wbuf.ensure(sizeof(cdouble)));
+      h2d(c, wd, &one, sizeof(cdouble));
+      cx<double> *site = static_cast<cx<double> *>(c->ws[7].ensure(size_t(kNumOps) * c->g.V * sizeof(cdouble)));
+      for (int q = 0; q < Q; ++q) {
+        hipLaunchKernelGGL(k_eig_bilinear, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g,
+                           L + size_t(q) * fl, R + size_t(q) * fl, fl, 1,
+                           reinterpret_cast<const cx<double> *>(wd), site, 0);
+        LQCD_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_eig_bilinear_ps, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g,
+                           static_cast<const cx<double> *>(c->U64.ptr), c->kappa, L + size_t(q) * fl,
+                           R + size_t(q) * fl, site + size_t(kNumTheta) * c->g.V, 0);
+        LQCD_HIP(hipGetLastError());
+        std::vector<cdouble> ts = timeslice_rows(c, site, kNumOps, tmp);
+        std::copy(ts.begin(), ts.end(), d->es_bil.begin() + size_t(q) * kNumOps * Lt);
+      }
+    }
+    for (int a = 0; a < nth; ++a)
+      for (int t = 0; t < Lt; ++t) {
+        cdouble v = 0;
+        for (int q = 0; q < Q; ++q) v += w[q] * d->es_bil[(size_t(q) * kNumOps + thetas[a]) * Lt + t];
+        corr[2 * (a * Lt + t)] += v.real();
+        corr[2 * (a * Lt + t) + 1] += v.imag();
+      }
+  }
+  const int blk = 8;
+  for (int r0 = 0; r0 < nrhs; r0 += blk) {
+    const int nb = std::min(blk, nrhs - r0);
+    cx<double> *Et = static_cast<cx<double> *>(c->ws[0].ensure(fl * nb * sizeof(cx<double>)));
+    cx<double> *Yt = static_cast<cx<double> *>(c->ws[3].ensure(fl * nb * sizeof(cx<double>)));
+    cx<double> *Xl = static_cast<cx<double> *>(c->ws[4].ensure(fl * nb * sizeof(cx<double>)));
+    pack_eo<double>(c, static_cast<const cdouble *>(eta) + r0 * fl, Et, nb, fl);
+    cdouble *Cd = static_cast<cdouble *>(c->ws[5].ensure(size_t(Q) * nb * sizeof(cdouble)));
+    gemm_tn<double>(c, L, fl, Q, Et, fl, nb, fl, Cd, Q);
+    std::vector<cdouble> Ch(size_t(Q) * nb);
+    d2h(c, Ch.data(), Cd, Ch.size() * sizeof(cdouble));
+    for (int r = 0; r < nb; ++r)
+      for (int q = 0; q < Q; ++q) Ch[size_t(r) * Q + q] *= w[q];
+    h2d(c, Cd, Ch.data(), Ch.size() * sizeof(cdouble));
+    fill_zero(c, Yt, fl * nb * sizeof(cx<double>));
+    gemm_nn<double>(c, R, fl, 0, Q, Cd, Q, 0, Yt, fl, 0, nb, fl, 1, 1.0);
+    unpack_eo<double>(c, Yt, Xl, nb, fl);
+    cdouble one(1, 0);
+    cx<double> *xo = reinterpret_cast<cx<double> *>(static_cast<cdouble *>(xt) + r0 * fl);
+    axpby<double>(c, &one, Xl, fl, &one, xo, fl, fl, nb, false);
+  }
+}
+
 }  // namespace
 
 }  // namespace lqcd
@@ -542,15 +695,24 @@ extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_de
                                        double *corr, double *xi_inv_host) {
   return guarded([&] {
     LQCD_CHECK(c && d, LQCD_EINVAL, "deflate_project: null argument");
-    LQCD_CHECK(mode == LQCD_DEFL_HFES || mode == LQCD_DEFL_EIGPOLY, LQCD_EINVAL,
+    LQCD_CHECK(mode == LQCD_DEFL_HFES || mode == LQCD_DEFL_EIGPOLY || mode == LQCD_DEFL_ES, LQCD_EINVAL,
                "deflate_project: bad mode");
     LQCD_CHECK(nrhs >= 0 && (nrhs == 0 || (eta && xt)), LQCD_EINVAL, "deflate_project: null field");
-    LQCD_CHECK(mode == LQCD_DEFL_HFES || (coeffs_host && ncoeff >= 1 && ncoeff <= kMaxOrder + 1),
+    LQCD_CHECK(mode != LQCD_DEFL_EIGPOLY || (coeffs_host && ncoeff >= 1 && ncoeff <= kMaxOrder + 1),
                LQCD_EINVAL, "deflate_project: EIGPOLY needs 1..%d polynomial coefficients", kMaxOrder + 1);
     for (int i = 0; i < 4; ++i)
       LQCD_CHECK(d->dims[i] == c->g.L[i], LQCD_EINVAL, "deflate_project: deflation space of another lattice");
     LQCD_CHECK(d->kappa == c->kappa, LQCD_EINVAL, "deflate_project: deflation space of another kappa");
     check_thetas(thetas, nth);
+    if (mode == LQCD_DEFL_ES) {
+      es_project(c, d, Q, thetas, nth, eta, xt, nrhs, corr);
+      if (xi_inv_host)
+        for (int q = 0; q < Q; ++q) {  // the eigenvalues of M used, in place of 1/xi'
+          xi_inv_host[2 * q] = d->es_lam[q].real();
+          xi_inv_host[2 * q + 1] = d->es_lam[q].imag();
+        }
+      return;
+    }
     defl_eigpairs(c, d, Q);
     const size_t fl = full_len(c->g);
     const cx<double> *E = d->E.as<cx<double>>();
@@ -600,11 +762,12 @@ extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_de
         DevBuf tmp;
         for (int q = 0; q < Q; ++q) {
           hipLaunchKernelGGL(k_eig_bilinear, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g,
-                             E + size_t(q) * fl, fl, 1, reinterpret_cast<const cx<double> *>(wd), site);
+                             E + size_t(q) * fl, E + size_t(q) * fl, fl, 1,
+                             reinterpret_cast<const cx<double> *>(wd), site, 1);
           LQCD_HIP(hipGetLastError());
           hipLaunchKernelGGL(k_eig_bilinear_ps, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g,
                              static_cast<const cx<double> *>(c->U64.ptr), c->kappa, E + size_t(q) * fl,
-                             site + size_t(kNumTheta) * c->g.V);
+                             E + size_t(q) * fl, site + size_t(kNumTheta) * c->g.V, 1);
           LQCD_HIP(hipGetLastError());
           std::vector<cdouble> ts = timeslice_rows(c, site, kNumOps, tmp);
           std::copy(ts.begin(), ts.end(), d->bil.begin() + size_t(q) * kNumOps * Lt);

@@ -18,7 +18,7 @@ F64, F32, F16, BF16 = 0, 1, 2, 3
 OP_M, OP_MDAG, OP_MG5, OP_HOP, OP_SCHUR = 0, 1, 2, 3, 4
 LAYOUT_LEX, LAYOUT_EO = 0, 1
 NS, PS, POLY, HFES, HFPS, HFPOLY = 0, 1, 2, 3, 4, 5
-DEFL_HFES, DEFL_EIGPOLY = 0, 1
+DEFL_HFES, DEFL_EIGPOLY, DEFL_ES = 0, 1, 2
 _PREC = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 _OPS = {"M": OP_M, "Mdag": OP_MDAG, "MG5": OP_MG5, "hop": OP_HOP, "schur": OP_SCHUR}
 

@@ -7,9 +7,10 @@ averaged over configurations.
 Per configuration the path runs once, as library calls only: Z(4) noise,
 even/odd solves (GMRES-DR on the first noise vector, GMRES-Proj on the
 rest), hermitian modes of M' from one MINRES-DR solve (Sec. 8), PS and POLY
-subtraction vectors with exact trace corrections; the hermitian-forced
-methods HFES, HFPS and HFPOLY are then formed for every Q of the list from
-the same modes.  The error bar of an operator is the standard error of the
+subtraction vectors with exact trace corrections; the eigenvalue
+subtraction ES (eigenpairs of M from the even/odd space, at most its k) and
+the hermitian-forced methods HFES, HFPS and HFPOLY are then formed for every
+Q of the list from the same modes.  The error bar of an operator is the standard error of the
 part of its whole-lattice trace that carries the signal (Sec. 6, Table 2):
 the real part for the scalar, the imaginary part for the local and the
 point-split vectors.
@@ -23,8 +24,8 @@ import sys
 
 import numpy as np
 
-METHODS = ("NS", "PS", "POLY", "HFES", "HFPS", "HFPOLY")
-HF = ("HFES", "HFPS", "HFPOLY")
+METHODS = ("NS", "PS", "POLY", "ES", "HFES", "HFPS", "HFPOLY")
+HF = ("ES", "HFES", "HFPS", "HFPOLY")  # the methods that depend on the number of modes
 GROUPS = {"scalar": (0,), "local_vector": (1, 2, 3, 4), "point_split": (5, 6, 7, 8)}
 
 
@@ -67,9 +68,14 @@ def config_errors(ctx, eta, thetas, q_list, p):
     out["POLY"] = errs(xt_poly, corr_poly)
     ones = np.ones(p["pert_order"] + 1, dtype=np.complex128)
     for q in q_list:
-        if q == 0:  # no modes: the hermitian-forced methods reduce to NS, PS, POLY
-            out[("HFES", 0)], out[("HFPS", 0)], out[("HFPOLY", 0)] = out["NS"], out["PS"], out["POLY"]
+        if q == 0:  # no modes: the deflation methods reduce to NS, PS, POLY
+            out[("ES", 0)], out[("HFES", 0)] = out["NS"], out["NS"]
+            out[("HFPS", 0)], out[("HFPOLY", 0)] = out["PS"], out["POLY"]
             continue
+        # ES (Sec. 5.3): eigenpairs of M from the even/odd space, at most its k modes
+        xt, corr, _ = ctx.deflate_project(defl, min(q, p["k"]), eta, xt=torch.zeros_like(eta), mode=lqcd.DEFL_ES,
+                                          thetas=thetas)
+        out[("ES", q)] = errs(xt, corr)
         xt, corr, _ = ctx.deflate_project(hdefl, q, eta, xt=torch.zeros_like(eta), mode=lqcd.DEFL_HFES,
                                           thetas=thetas)
         out[("HFES", q)] = errs(xt, corr)
@@ -92,8 +98,8 @@ def summarize(per_config, thetas, q_list):
     keys = list(per_config[0].keys())
     mean = {k: np.mean([c[k] for c in per_config], axis=0) for k in keys}
     qmax = max(q_list)
-    tested = {"POLY": mean["POLY"], "HFES": mean[("HFES", qmax)], "HFPS": mean[("HFPS", qmax)],
-              "HFPOLY": mean[("HFPOLY", qmax)]}
+    tested = {"POLY": mean["POLY"], "ES": mean[("ES", qmax)], "HFES": mean[("HFES", qmax)],
+              "HFPS": mean[("HFPS", qmax)], "HFPOLY": mean[("HFPOLY", qmax)]}
     groups = {g: [thetas.index(c) for c in cs if c in thetas] for g, cs in GROUPS.items()}
     groups = {g: ix for g, ix in groups.items() if ix}
 

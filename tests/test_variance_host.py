@@ -27,7 +27,8 @@ def test_summarize_averages_and_groups():
           "POLY": np.array([2.0, 1.0, 1.0, 4.0])}
     c2 = {k: 3 * v for k, v in c1.items()}
     for c in (c1, c2):
-        c[("HFES", 0)], c[("HFPS", 0)], c[("HFPOLY", 0)] = c["NS"], c["PS"], c["POLY"]
+        c[("ES", 0)], c[("HFES", 0)], c[("HFPS", 0)], c[("HFPOLY", 0)] = c["NS"], c["NS"], c["PS"], c["POLY"]
+        c[("ES", 4)] = c["NS"] * 2
         c[("HFES", 4)] = c["NS"] / 2
         c[("HFPS", 4)] = c["PS"] / 2
         c[("HFPOLY", 4)] = c["PS"] / 4
@@ -40,3 +41,5 @@ def test_summarize_averages_and_groups():
     assert abs(s["RE_at_Qmax"]["NS"]["HFES"]["local_vector"] - 300.0) < 1e-9
     assert abs(s["RE_at_Qmax"]["PS"]["HFPOLY"]["point_split"] - 1500.0) < 1e-9
     assert abs(s["RE_at_Qmax"]["PS"]["POLY"]["scalar"]) < 1e-12
+    # ES doubling the NS error bar: RE vs NS = -75
+    assert abs(s["RE_at_Qmax"]["NS"]["ES"]["scalar"] + 75.0) < 1e-9

@@ -64,7 +64,9 @@ def source_sha(path):
 
 def traffic_for(kernel_class, bytes_per_launch):
     """HBM traffic per launch from committed rocprofv3 counter summaries, if
-    the kernel source is unchanged since they were taken; else None."""
+    the kernel source is unchanged since they were taken and they were taken
+    on launches of the same algorithmic size (same workload and block of
+    right-hand sides); else None."""
     p = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel_class)
     if not os.path.exists(p):
         return None
@@ -72,6 +74,9 @@ def traffic_for(kernel_class, bytes_per_launch):
         t = json.load(f)
     src = os.path.join(ROOT, "paper_1903_06986_amd", "csrc", t["source"])
     if source_sha(src) != t["source_sha"]:
+        return None
+    alg = t.get("algorithmic_bytes_per_launch")
+    if alg is None or abs(alg - bytes_per_launch) > 0.01 * bytes_per_launch:
         return None
     return t["hbm_bytes_per_launch"]
 

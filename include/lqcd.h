@@ -380,8 +380,11 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * within a block, t fastest (up to 1024); -1 (default) = planes with
  * ceil(Lt / 8) timeslices per block when a plane (Lx / 2 * Ly sites) splits
  * into whole tiles and Lt >= 8, else index order.  LQCD_TUNE_HOP_TSITES32:
- * sites per FP32 tile, 32 (default) or 64.  Values are per context; EINVAL
- * for other values. */
+ * sites per FP32 tile, 32 (default) or 64.  LQCD_TUNE_HOP_RGROUP: the
+ * tiled stencil splits launches with more right-hand sides than this into
+ * groups of this many, the group index slowest across the XCDs (each XCD's
+ * L2 then holds one group's spinors; links are read once per group);
+ * 0 = one group.  Values are per context; EINVAL for other values. */
 typedef enum {
   LQCD_TUNE_HOP_NB64 = 0,
   LQCD_TUNE_HOP_NB32 = 1,
@@ -390,7 +393,8 @@ typedef enum {
   LQCD_TUNE_HOP_ORDER = 4,
   LQCD_TUNE_HOP_TBLOCK64 = 5,
   LQCD_TUNE_HOP_TBLOCK32 = 6,
-  LQCD_TUNE_HOP_TSITES32 = 7
+  LQCD_TUNE_HOP_TSITES32 = 7,
+  LQCD_TUNE_HOP_RGROUP = 8
 } lqcd_tune_param;
 lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 

@@ -616,20 +616,38 @@ __global__ void __launch_bounds__(kBlock)
   const int row = 16 * wave + (lane & 15);   // A row (basis vector) of this lane
   const int kq = lane >> 4;                   // 0..3: element 2 * step + kq / 2, part kq % 2
   const int col = lane & 15;                  // B column
-  for (size_t ch = c0; ch < c1; ++ch) {
-    const size_t e0 = ch * kTE;
-    __syncthreads();  // the previous chunk's operands are consumed
-    // stage V rows 0..J-1 and X columns 0..nb-1 (zero beyond n)
-    for (int t = threadIdx.x; t < (J + nb) * kTE; t += kBlock) {
+  // The next chunk's operands are loaded into registers while the current
+  // one is multiplied from LDS (J + nb <= 72 rows of kTE elements: at most
+  // kLpt loads per thread).
+  constexpr int kLpt = (72 * kTE + kBlock - 1) / kBlock;
+  const int nld = (J + nb) * kTE;
+  cx<R> pre[kLpt];
+  auto fetch = [&](size_t e0) {
+#pragma unroll
+    for (int u = 0; u < kLpt; ++u) {
+      const int t = threadIdx.x + u * kBlock;
       const int r = t / kTE, e = t % kTE;
       const size_t idx = e0 + e;
-      cx<R> v = mk<R>(0, 0);
-      if (idx < n) v = r < J ? ldc(V + size_t(r) * ldv + idx) : ldc(X + size_t(r - J) * ldx + idx);
-      R *dst = r < J ? sV + r * kTP : sX + (r - J) * kTP;
-      dst[2 * e] = v.re;
-      dst[2 * e + 1] = v.im;
+      pre[u] = mk<R>(0, 0);
+      if (t < nld && idx < n) pre[u] = r < J ? ldc(V + size_t(r) * ldv + idx) : ldc(X + size_t(r - J) * ldx + idx);
+    }
+  };
+  if (c0 < c1) fetch(c0 * kTE);
+  for (size_t ch = c0; ch < c1; ++ch) {
+    __syncthreads();  // the previous chunk's operands are consumed
+    // stage V rows 0..J-1 and X columns 0..nb-1 (zero beyond n)
+#pragma unroll
+    for (int u = 0; u < kLpt; ++u) {
+      const int t = threadIdx.x + u * kBlock;
+      if (t < nld) {
+        const int r = t / kTE, e = t % kTE;
+        R *dst = r < J ? sV + r * kTP : sX + (r - J) * kTP;
+        dst[2 * e] = pre[u].re;
+        dst[2 * e + 1] = pre[u].im;
+      }
     }
     __syncthreads();
+    if (ch + 1 < c1) fetch((ch + 1) * kTE);
     if (16 * wave < J) {
 #pragma unroll 8
       for (int st = 0; st < kTE / 2; ++st) {
@@ -779,6 +797,14 @@ template <class R>
 void gemm_tn(lqcd_ctx *c, const void *V, size_t ldv, int J, const void *X, size_t ldx, int nb,
              size_t n, cdouble *C, size_t ldc) {
   if (J <= 0 || nb <= 0) return;
+  if (J <= 64 && nb > 8 && n >= size_t(kTE)) {
+    // more columns than one matrix-core tile holds: tiles of 8 columns, so V
+    // is read once per 8 right-hand sides
+    for (int b0 = 0; b0 < nb; b0 += 8)
+      gemm_tn<R>(c, V, ldv, J, static_cast<const cx<R> *>(X) + size_t(b0) * ldx, ldx, std::min(8, nb - b0), n,
+                 C + size_t(b0) * ldc, ldc);
+    return;
+  }
   if (J > 64 || nb > 8 || n < size_t(kTE)) {
     // outside the matrix-core tile: one multi-dot per column of X
     multi_dot_impl<R>(c, V, ldv, 0, J, X, ldx, n, nb, C, ldc, LQCD_KC_GEMM,

@@ -190,6 +190,10 @@ extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int val
                    "lqcd_tune_set: timeslices per plane block must be in -1..1024");
         c->hop_tblock[param == LQCD_TUNE_HOP_TBLOCK64 ? 0 : 1] = value;
         break;
+      case LQCD_TUNE_HOP_RGROUP:
+        LQCD_CHECK(value >= 0 && value <= 4096, LQCD_EINVAL, "lqcd_tune_set: right-hand sides per group in 0..4096");
+        c->hop_rgroup = value;
+        break;
       case LQCD_TUNE_HOP_TSITES32:
         LQCD_CHECK(value == 32 || value == 64, LQCD_EINVAL, "lqcd_tune_set: sites per FP32 tile must be 32 or 64");
         c->hop_tsites32 = value;

@@ -155,8 +155,13 @@ __device__ inline void hop_step(cx<R> acc[4][3], const cx<R> *sU, int T, const S
 // within a block, t fastest: the planes whose spinors a tile reads through
 // its z and t neighbours are then at most tb planes of the sequence away,
 // so they are still in the XCD's L2 when the next tile needs them.
+// With rg > 0 the right-hand sides are split into groups of rg and the
+// logical workgroup index runs over (group, tile), group slowest: every XCD
+// range then covers one group over part of the lattice, and its L2 holds
+// that group's spinors only (the links are read once per group).
 struct TileMap {
   int tb, nbp, ppl;
+  int rg, ntg;  // right-hand sides per group (0: one group), tiles per group
 };
 
 template <class R, bool G5IN, bool G5OUT, bool SELF, int T, class SrcIn, class SrcSelf>
@@ -172,7 +177,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
   constexpr bool PIPE = sizeof(R) == 4;  // two neighbours' loads in flight (FP64: one)
   __shared__ cx<R> sU[8 * 9 * T];  // [direction: 4 forward, 4 backward][entry][site]
   // XCD-aware tile order (as in k_hop): each XCD walks one contiguous range
-  const int tile = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
+  const int lidx = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
+  const int grp = tm.rg > 0 ? lidx / tm.ntg : 0, tile = tm.rg > 0 ? lidx % tm.ntg : lidx;
+  const int rlo = grp * tm.rg, rhi = tm.rg > 0 ? min(nrhs, rlo + tm.rg) : nrhs;
+  if (rlo >= nrhs) return;  // whole workgroup: padding of the grid
   int i0, lim;
   if (tm.tb == 0) {
     i0 = tile * T;
@@ -239,8 +247,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
   }
   const uint32_t so = sb + uint32_t(i) * SrcSelf::kBytes, oo = ob + uint32_t(i) * uint32_t(sizeof(cx<R>));
 #pragma unroll 1
-  for (int r0 = slot0; r0 < nrhs; r0 += RS) {
-    if (r0 + int(sl) >= nrhs) break;  // this lane's right-hand side is past the end
+  for (int r0 = rlo + slot0; r0 < rhi; r0 += RS) {
+    if (r0 + int(sl) >= rhi) break;  // this lane's right-hand side is past the end
     const size_t rw = size_t(r0);     // wave-uniform
     const SrcIn inr = in.at(rw * in_stride);
     cx<R> acc[4][3];
@@ -306,7 +314,7 @@ template <class R, bool A, bool B, bool C, int T, class SI, class SS>
 void launch_hop_tile(lqcd_ctx *c, Timed &tm, int p, const cx<R> *U, SI in, SS self, void *out,
                      cdouble alpha, double beta, int nrhs, size_t si, size_t ss, size_t so) {
   const Geom &g = c->g;
-  TileMap map{c->hop_tblock[std::is_same<R, double>::value ? 0 : 1], 0, g.Lxh * g.L[1]};
+  TileMap map{c->hop_tblock[std::is_same<R, double>::value ? 0 : 1], 0, g.Lxh * g.L[1], 0, 0};
   if (map.tb < 0)  // automatic: plane order when planes split into whole tiles, one block per XCD
     map.tb = (map.ppl % T == 0 && g.L[3] >= 8) ? (g.L[3] + 7) / 8 : 0;
   int ntile;
@@ -317,6 +325,12 @@ void launch_hop_tile(lqcd_ctx *c, Timed &tm, int p, const cx<R> *U, SI in, SS se
     ntile = nblk * map.tb * g.L[2] * map.nbp;
   } else {
     ntile = int((g.Vh + T - 1) / T);
+  }
+  const int rg = c->hop_rgroup;
+  if (rg > 0 && rg < nrhs) {
+    map.rg = rg;
+    map.ntg = ntile;
+    ntile *= (nrhs + rg - 1) / rg;
   }
   const int xq = (ntile + 7) / 8;
   LQCD_TLAUNCH(tm, true, true, (k_hop_tile<R, A, B, C, T, SI, SS>), dim3(8 * xq), dim3(kBlock), 0, c->stream, g, p,

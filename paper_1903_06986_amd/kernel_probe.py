@@ -27,6 +27,7 @@ def main():
     ap.add_argument("--nb", type=int, default=0, help="lane-grouped right-hand sides (0: default)")
     ap.add_argument("--tblock", type=int, default=-1, help="plane-blocked tile order: timeslices per block (-1 auto, 0 index order)")
     ap.add_argument("--tsites", type=int, default=32, help="sites per FP32 tile (32 or 64)")
+    ap.add_argument("--rgroup", type=int, default=0, help="right-hand sides per group of the tiled stencil")
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--dims", default="24x24x24x32")
@@ -46,7 +47,7 @@ def main():
     U = random_su3_links(dims, 0.2, 1003)
     ctx = Context(dims, U, 0.13)
     ctx.tune(hop_tile64=a.tile, hop_tile32=a.tile, hop_order=a.order, hop_tblock64=a.tblock,
-             hop_tblock32=a.tblock, hop_tsites32=a.tsites)
+             hop_tblock32=a.tblock, hop_tsites32=a.tsites, hop_rgroup=a.rgroup)
     if a.nb:
         ctx.tune(hop_nb64=a.nb, hop_nb32=a.nb)
     Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
@@ -59,8 +60,9 @@ def main():
         kt = ctx.timer_read()
         ms, by, n = kt["hop32"]
         print("%s nrhs=%d tile=%d: %d stencil launches, %.1f us each, %.0f algorithmic bytes per launch, "
-              "%.1f GB/s (order %d nb %d tblock %d tsites %d)" % (a.kernel, a.nrhs, a.tile, n, ms * 1e3 / n, by / n,
-                                                    by / (ms * 1e-3) / 1e9, a.order, a.nb, a.tblock, a.tsites))
+              "%.1f GB/s (order %d nb %d tblock %d tsites %d rgroup %d)" % (a.kernel, a.nrhs, a.tile, n, ms * 1e3 / n,
+                                                    by / n, by / (ms * 1e-3) / 1e9, a.order, a.nb, a.tblock,
+                                                    a.tsites, a.rgroup))
         return
     prec = "f64" if a.kernel in ("hop64", "schur64") else "f32"
     dt = torch.complex128 if prec == "f64" else torch.complex64
@@ -74,9 +76,9 @@ def main():
     kt = ctx.timer_read()
     k = "hop64" if prec == "f64" else "hop32"
     ms, by, n = kt[k]
-    print("%s nrhs=%d tile=%d order=%d nb=%d tblock=%d tsites=%d: %d launches, %.1f us each, %.0f "
+    print("%s nrhs=%d tile=%d order=%d nb=%d tblock=%d tsites=%d rgroup=%d: %d launches, %.1f us each, %.0f "
           "algorithmic bytes per launch, %.1f GB/s" % (a.kernel, a.nrhs, a.tile, a.order, a.nb, a.tblock, a.tsites,
-                                                      n, ms * 1e3 / n, by / n, by / (ms * 1e-3) / 1e9))
+                                                      a.rgroup, n, ms * 1e3 / n, by / n, by / (ms * 1e-3) / 1e9))
 
 
 if __name__ == "__main__":

@@ -26,8 +26,11 @@ def _dense_solve(U, kappa, dims, eta):
 
 
 @pytest.mark.parametrize("dims,kappa,nrhs,block", [((4, 4, 4, 4), 0.12, 4, 2),
-                                                    ((6, 4, 2, 8), 0.13, 5, 3)])
+                                                    ((6, 4, 2, 8), 0.13, 5, 3),
+                                                    ((4, 4, 4, 4), 0.12, 13, 13)])
 def test_schur_solve_fp64(dims, kappa, nrhs, block):
+    """Blocks of 13 right-hand sides take the matrix-core projection in tiles
+    of 8 + 5 columns."""
     require_gpu()
     ctx, U = context(dims, 0.3, 1001, kappa)
     eta = z4_noise(2001, dims, 0, nrhs)
@@ -190,17 +193,18 @@ def test_minres_dr_rejects_non_hermitian_operator():
         ctx.gmresdr_solve(to_gpu(eta), op="schur", m=20, k=10, method="minres-dr")
 
 
-@pytest.mark.parametrize("dims,kappa", [((4, 4, 4, 4), 0.12), ((6, 4, 2, 8), 0.13)])
-def test_mixed_precision_solve(dims, kappa):
+@pytest.mark.parametrize("dims,kappa,nrhs,block", [((4, 4, 4, 4), 0.12, 5, 4), ((6, 4, 2, 8), 0.13, 5, 4),
+                                                    ((4, 4, 4, 4), 0.12, 12, 12)])
+def test_mixed_precision_solve(dims, kappa, nrhs, block):
     require_gpu()
     ctx, U = context(dims, 0.3, 1001, kappa)
-    eta = z4_noise(2001, dims, 0, 5)
-    say("solve mixed", dims)
+    eta = z4_noise(2001, dims, 0, nrhs)
+    say("solve mixed", dims, nrhs, block)
     x, defl, st = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=20, k=10, tol=1e-11, tol_super=1e-13,
-                                    inner="f32", inner_tol=1e-5, rhs_block=4)
+                                    inner="f32", inner_tol=1e-5, rhs_block=block)
     x = to_host(x)
     xref, _ = _dense_solve(U, kappa, dims, eta)
-    for r in range(5):
+    for r in range(nrhs):
         assert rel_err(x[r], xref[r]) < 1e-9
         assert st[r]["true_resid"] < 1e-11
     assert all(s["refinements"] >= 1 for s in st[1:])

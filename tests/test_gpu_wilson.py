@@ -116,7 +116,9 @@ def test_full_size_operator_16x32():
 
 # tile shapes and orders of the link-tiled stencil: (timeslices per plane
 # block, sites per FP32 tile); 0 = tiles of consecutive sites in index order
-TILE_SHAPES = [(0, 64), (1, 64), (3, 64), (64, 64), (0, 32), (2, 32), (-1, 32)]
+# and right-hand sides per group (0: one group)
+TILE_SHAPES = [(0, 64, 0), (1, 64, 0), (3, 64, 0), (64, 64, 0), (0, 32, 0), (2, 32, 0), (-1, 32, 0),
+               (-1, 32, 4), (2, 64, 4), (0, 32, 8)]
 
 
 @pytest.mark.parametrize("dims", [(2, 2, 2, 4), (6, 6, 2, 4), (6, 4, 2, 8), (8, 6, 2, 6)])
@@ -142,11 +144,11 @@ def test_link_tiled_stencil(dims, prec, nrhs):
         y0 = to_host(ctx.wilson_apply(op, to_gpu(x), prec=prec))
         tol = {"f64": 1e-13, "f32": 5e-6, "f16": 2e-3}[prec]
         assert rel_err(y0, _oracle_op(op, U, kappa, x, dims)) < tol, op
-        for tb, ts in TILE_SHAPES:
-            say("tiled stencil", op, prec, dims, nrhs, "tblock", tb, "tsites", ts)
-            ctx.tune(hop_tile64=1, hop_tile32=1, hop_tblock64=tb, hop_tblock32=tb, hop_tsites32=ts)
+        for tb, ts, rg in TILE_SHAPES:
+            say("tiled stencil", op, prec, dims, nrhs, "tblock", tb, "tsites", ts, "rgroup", rg)
+            ctx.tune(hop_tile64=1, hop_tile32=1, hop_tblock64=tb, hop_tblock32=tb, hop_tsites32=ts, hop_rgroup=rg)
             y = to_host(ctx.wilson_apply(op, to_gpu(x), prec=prec))
             d = rel_err(y, y0)
-            assert d < {"f64": 1e-14, "f32": 1e-6, "f16": 1e-6}[prec], (op, tb, ts, d)
-            assert rel_err(y, _oracle_op(op, U, kappa, x, dims)) < tol, (op, tb, ts)
-    ctx.tune(hop_tile64=1, hop_tile32=1, hop_tblock64=-1, hop_tblock32=-1, hop_tsites32=32)
+            assert d < {"f64": 1e-14, "f32": 1e-6, "f16": 1e-6}[prec], (op, tb, ts, rg, d)
+            assert rel_err(y, _oracle_op(op, U, kappa, x, dims)) < tol, (op, tb, ts, rg)
+    ctx.tune(hop_tile64=1, hop_tile32=1, hop_tblock64=-1, hop_tblock32=-1, hop_tsites32=32, hop_rgroup=0)

@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(kBlock)
     for (int e = 0; e < kEpt; ++e) {
       const size_t idx = base + size_t(e) * 64;
       if (idx < n) {
-        const cx<float> q0 = ldc(v0 + idx), q1 = ldc(v1 + idx);
+        const cx<float> q0 = ldc_nt(v0 + idx), q1 = ldc_nt(v1 + idx);  // streamed basis
         const cx<double> p0 = cmulc(mk<double>(q0.re, q0.im), wv[e]);
         const cx<double> p1 = cmulc(mk<double>(q1.re, q1.im), wv[e]);
         a0 += p0.re;
@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(kBlock)
       for (int e = 0; e < kEpt; ++e) {
         const size_t idx = base + size_t(e) * 64;
         if (idx < n) {
-          const cx<float> q = ldc(v0 + idx);
+          const cx<float> q = ldc_nt(v0 + idx);
           const cx<double> pr = cmulc(mk<double>(q.re, q.im), wv[e]);
           a += pr.re;
           b += pr.im;
@@ -323,8 +323,8 @@ __global__ void __launch_bounds__(kBlock)
       for (int e = 0; e < kAept; ++e) {
         const size_t idx = base + size_t(e) * kBlock;
         if (idx < n) {
-          const cx<float> q0 = ldc(v0 + idx), q1 = ldc(v0 + n + idx), q2 = ldc(v0 + 2 * n + idx),
-                          q3 = ldc(v0 + 3 * n + idx);
+          const cx<float> q0 = ldc_nt(v0 + idx), q1 = ldc_nt(v0 + n + idx), q2 = ldc_nt(v0 + 2 * n + idx),
+                          q3 = ldc_nt(v0 + 3 * n + idx);  // streamed basis
           acc[e] = acc[e] + (mk<double>(q0.re, q0.im) * c0 + mk<double>(q1.re, q1.im) * c1) +
                    (mk<double>(q2.re, q2.im) * c2 + mk<double>(q3.re, q3.im) * c3);
         }
@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(kBlock)
       for (int e = 0; e < kAept; ++e) {
         const size_t idx = base + size_t(e) * kBlock;
         if (idx < n) {
-          const cx<float> q = ldc(v0 + idx);
+          const cx<float> q = ldc_nt(v0 + idx);
           acc[e] = acc[e] + mk<double>(q.re, q.im) * c;
         }
       }

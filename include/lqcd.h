@@ -379,8 +379,12 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * = tiles within one (z, t) plane, ordered by blocks of n timeslices, z
  * within a block, t fastest (up to 1024); -1 (default) = planes with
  * ceil(Lt / 8) timeslices per block when a plane (Lx / 2 * Ly sites) splits
- * into whole tiles and Lt >= 8, else index order.  LQCD_TUNE_HOP_TSITES32:
- * sites per FP32 tile, 32 (default) or 64.  LQCD_TUNE_HOP_RGROUP: the
+ * into whole tiles and Lt >= 8, else index order.  LQCD_TUNE_HOP_TSITES32 /
+ * LQCD_TUNE_HOP_TSITES64: sites per tile, FP32 16, 32 (default) or 64, FP64
+ * 16 or 32 (default); a tile of T sites takes 256 / T right-hand sides per
+ * pass, and launches with fewer use the next larger tile.  Smaller tiles
+ * keep fewer sites in flight per XCD, so the neighbour planes' spinors stay
+ * in its L2.  LQCD_TUNE_HOP_RGROUP: the
  * tiled stencil splits launches with more right-hand sides than this into
  * groups of this many, the group index slowest across the XCDs (each XCD's
  * L2 then holds one group's spinors; links are read once per group);
@@ -394,7 +398,8 @@ typedef enum {
   LQCD_TUNE_HOP_TBLOCK64 = 5,
   LQCD_TUNE_HOP_TBLOCK32 = 6,
   LQCD_TUNE_HOP_TSITES32 = 7,
-  LQCD_TUNE_HOP_RGROUP = 8
+  LQCD_TUNE_HOP_RGROUP = 8,
+  LQCD_TUNE_HOP_TSITES64 = 9
 } lqcd_tune_param;
 lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 

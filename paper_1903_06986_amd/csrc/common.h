@@ -139,7 +139,7 @@ struct lqcd_ctx {
   int hop_tile[2] = {1, 1};  // link-tiled stencil for many right-hand sides: FP64, FP32
   int hop_order = 0;         // lane-grouped stencil block order: 0 rhs-group fastest, 1 site fastest
   int hop_tblock[2] = {-1, -1};  // tiled stencil: timeslices per plane block (0: flat order, -1: auto), FP64, FP32
-  int hop_tsites32 = 32;         // tiled stencil: sites per FP32 tile (32 or 64)
+  int hop_tsites[2] = {32, 32};  // tiled stencil: sites per tile, FP64 (16, 32), FP32 (16, 32, 64)
   int hop_rgroup = 0;            // tiled stencil: right-hand sides per group (0: all in one)
   ~lqcd_ctx();
 };

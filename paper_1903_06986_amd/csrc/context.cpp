@@ -195,8 +195,13 @@ extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int val
         c->hop_rgroup = value;
         break;
       case LQCD_TUNE_HOP_TSITES32:
-        LQCD_CHECK(value == 32 || value == 64, LQCD_EINVAL, "lqcd_tune_set: sites per FP32 tile must be 32 or 64");
-        c->hop_tsites32 = value;
+        LQCD_CHECK(value == 16 || value == 32 || value == 64, LQCD_EINVAL,
+                   "lqcd_tune_set: sites per FP32 tile must be 16, 32 or 64");
+        c->hop_tsites[1] = value;
+        break;
+      case LQCD_TUNE_HOP_TSITES64:
+        LQCD_CHECK(value == 16 || value == 32, LQCD_EINVAL, "lqcd_tune_set: sites per FP64 tile must be 16 or 32");
+        c->hop_tsites[0] = value;
         break;
       default:
         LQCD_CHECK(false, LQCD_EINVAL, "lqcd_tune_set: unknown parameter %d", int(param));

@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
 }
 
 // Link-tiled form for many right-hand sides: a workgroup owns T
-// consecutive output sites (T = 32 or 64), stages their 8 links (4 forward
+// consecutive output sites (T = 16, 32 or 64), stages their 8 links (4 forward
 // at the sites, 4 backward at the neighbours x - mu) in LDS once, then
 // applies the stencil to every right-hand side, RS = 256 / T of them at a
 // time.  The lane index is the site within the tile, so each spinor access
@@ -128,24 +128,37 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
 // One of the 8 terms of the stencil (LEG = 2 mu + 0 forward / 1 backward)
 // from a settled raw neighbour, with its link from the LDS tile.
 template <class R, int LEG, bool G5IN, class RawT>
-__device__ inline void hop_leg(cx<R> acc[4][3], const cx<R> *sU, int T, const RawT &raw) {
+__device__ inline void hop_leg(cx<R> acc[4][3], const cx<R> *sU, int T, const RawT &raw, R one) {
   constexpr int MU = LEG / 2;
   constexpr bool FWD = (LEG % 2) == 0;
   Half<R> h;
-  project_raw<R, MU, FWD, G5IN>(raw, h);
-  link_accumulate<R, MU, FWD>(acc, sU + ((FWD ? 0 : 4) + MU) * 9 * T, T, h);
+  project_raw<R, MU, FWD, G5IN>(raw, h, one);
+  link_accumulate<R, MU, FWD>(acc, sU + ((FWD ? 0 : 4) + MU) * 9 * T, T, h, raw.scale());
 }
 
-// Step LEG of the software pipeline over the 8 neighbours: the loads of
-// neighbour LEG + 2 go out into the buffer that LEG has just consumed, so
-// two neighbours' loads are in flight while one is computed.
-template <class R, int LEG, bool G5IN, class Src>
+// Step LEG of the software pipeline over the 8 neighbours, D deep: the
+// loads of neighbour LEG + D go out into the buffer that LEG has just
+// consumed, so D neighbours' loads are in flight while one is computed.
+template <class R, int LEG, int D, bool G5IN, class Src>
 __device__ inline void hop_step(cx<R> acc[4][3], const cx<R> *sU, int T, const Src &in,
-                                const uint32_t off[8], size_t Vh, Raw<Src> &buf) {
+                                const uint32_t off[8], size_t Vh, Raw<Src> &buf, R one) {
   settle(buf);
-  hop_leg<R, LEG, G5IN>(acc, sU, T, buf);
-  if (LEG + 2 < 8) fetch_at(in, off[LEG + 2 < 8 ? LEG + 2 : 0], Vh, buf);
+  hop_leg<R, LEG, G5IN>(acc, sU, T, buf, one);
+  if (LEG + D < 8) fetch_at(in, off[LEG + D < 8 ? LEG + D : 0], Vh, buf);
   fence(acc);
+}
+
+// Steps LEG..7; the self term's loads go out at the first step that
+// issues no neighbour load, into the registers that step has freed.
+template <class R, int LEG, int D, bool G5IN, bool SELF, class Src, class SS>
+__device__ inline void hop_steps(cx<R> acc[4][3], const cx<R> *sU, int T, const Src &in,
+                                 const uint32_t off[8], size_t Vh, Raw<Src> (&buf)[D], R one, const SS &self,
+                                 uint32_t so, Raw<SS> &rs) {
+  if constexpr (LEG < 8) {
+    hop_step<R, LEG, D, G5IN>(acc, sU, T, in, off, Vh, buf[LEG % D], one);
+    if constexpr (SELF && LEG + D == 8) fetch_at(self, so, Vh, rs);
+    hop_steps<R, LEG + 1, D, G5IN, SELF>(acc, sU, T, in, off, Vh, buf, one, self, so, rs);
+  }
 }
 
 // Tile order of k_hop_tile.  tb == 0: tiles are T consecutive sites of the
@@ -164,17 +177,24 @@ struct TileMap {
   int rg, ntg;  // right-hand sides per group (0: one group), tiles per group
 };
 
+// Waves per SIMD the tiled stencil is compiled for: 4 (128 VGPRs) with
+// 16-bit sources, whose three raw neighbours in flight fit there; 3 (168
+// VGPRs) otherwise.
+template <class R, class SrcIn>
+constexpr int hop_tile_waves = (sizeof(R) == 4 && SrcIn::kBytes == 4) ? 4 : 3;
+
 template <class R, bool G5IN, bool G5OUT, bool SELF, int T, class SrcIn, class SrcSelf>
-// 3 waves per SIMD (168 VGPRs): room for two raw neighbours in flight
-// without spills.
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(hop_tile_waves<R, SrcIn>, 8)))
     k_hop_tile(Geom g, int p, const cx<R> *U, SrcIn in, SrcSelf self, cx<R> *out, cx<R> alpha,
                R beta, size_t in_stride, size_t self_stride, size_t out_stride, int nrhs, int xq,
                TileMap tm) {
-  static_assert(T == 32 || T == 64, "tile of 32 or 64 sites");
+  static_assert(T == 16 || T == 32 || T == 64, "tile of 16, 32 or 64 sites");
   constexpr int RS = kBlock / T;    // right-hand sides per pass
   constexpr int SPW = 64 / T;       // right-hand-side slots per wave
-  constexpr bool PIPE = sizeof(R) == 4;  // two neighbours' loads in flight (FP64: one)
+  // neighbours' loads in flight per wave: 3 for 16-bit sources (128
+  // VGPRs, 4 waves per SIMD), 2 for FP32 ones (a third spills at 168), 1 in
+  // FP64 (a second raw FP64 site would cost a wave per SIMD)
+  constexpr int D = sizeof(R) == 8 ? 1 : (SrcIn::kBytes == 4 ? 3 : 2);
   __shared__ cx<R> sU[8 * 9 * T];  // [direction: 4 forward, 4 backward][entry][site]
   // XCD-aware tile order (as in k_hop): each XCD walks one contiguous range
   const int lidx = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
@@ -235,6 +255,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
   __syncthreads();
   if (!site_ok) return;
   const cx<R> *su = sU + il;
+  R one = 1;  // unit factor of the projection's FMAs, opaque to the compiler
+  asm volatile("" : "+s"(one));
   // lane byte offsets within the wave's fields (loop-invariant)
   const uint32_t sl = uint32_t(slot - slot0);
   const uint32_t ib = sl * uint32_t(in_stride * SrcIn::kBytes), sb = sl * uint32_t(self_stride * SrcSelf::kBytes),
@@ -269,29 +291,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
     SrcSelf sr = self;
     if (SELF) sr = self.at(rw * self_stride);
     Raw<SrcSelf> rs;
-    Raw<SrcIn> ra, rb;
-    fetch_at(inr, off[0], Vh, ra);
-    if (PIPE) fetch_at(inr, off[1], Vh, rb);
-    if constexpr (PIPE) {
-      hop_step<R, 0, G5IN>(acc, su, T, inr, off, Vh, ra);
-      hop_step<R, 1, G5IN>(acc, su, T, inr, off, Vh, rb);
-      hop_step<R, 2, G5IN>(acc, su, T, inr, off, Vh, ra);
-      hop_step<R, 3, G5IN>(acc, su, T, inr, off, Vh, rb);
-      hop_step<R, 4, G5IN>(acc, su, T, inr, off, Vh, ra);
-      hop_step<R, 5, G5IN>(acc, su, T, inr, off, Vh, rb);
-      hop_step<R, 6, G5IN>(acc, su, T, inr, off, Vh, ra);
-      if (SELF) fetch_at(sr, so, Vh, rs);  // the self term takes the freed buffer's place
-      hop_step<R, 7, G5IN>(acc, su, T, inr, off, Vh, rb);
-    } else {  // one neighbour at a time (FP64: two raw sites would cost occupancy)
-#define LQCD_LEG(L)                                        \
-  settle(ra);                                             \
-  hop_leg<R, L, G5IN>(acc, su, T, ra);                     \
-  if (L + 1 < 8) fetch_at(inr, off[L + 1 < 8 ? L + 1 : 0], Vh, ra); \
-  fence(acc);
-      LQCD_LEG(0) LQCD_LEG(1) LQCD_LEG(2) LQCD_LEG(3) LQCD_LEG(4) LQCD_LEG(5) LQCD_LEG(6) LQCD_LEG(7)
-#undef LQCD_LEG
-      if (SELF) fetch_at(sr, so, Vh, rs);
-    }
+    Raw<SrcIn> rb[D];
+#pragma unroll
+    for (int l = 0; l < D; ++l) fetch_at(inr, off[l], Vh, rb[l]);
+    hop_steps<R, 0, D, G5IN, SELF>(acc, su, T, inr, off, Vh, rb, one, sr, so, rs);
     char *o = reinterpret_cast<char *>(out + rw * out_stride);
     if (SELF) settle(rs);
 #pragma unroll
@@ -375,20 +378,26 @@ void launch_hop_src(lqcd_ctx *c, int p, SI in, SS self, void *out, cdouble alpha
   Timed tm(c, std::is_same<R, double>::value ? LQCD_KC_HOP64 : LQCD_KC_HOP32, bytes);
   const int pi = std::is_same<R, double>::value ? 0 : 1;
   const int nbmax = c->hop_nb[pi];
-  // tiles of 32 sites (FP64: 36 KiB of links per workgroup; FP32: 18 KiB),
-  // or 64 FP32 sites on request
-  constexpr int T = std::is_same<R, double>::value ? 32 : 64;
-  const bool t32 = !std::is_same<R, double>::value && c->hop_tsites32 == 32;
+  // tiles of ts sites (links of 18 KiB in FP64, 9 KiB in FP32 per 16
+  // sites in LDS), doubled while the launch has fewer right-hand sides
+  // than one pass of the tile takes (256 / ts); FP64 tiles of 16 or 32
+  // sites, FP32 16, 32 or 64
+  constexpr int tmax = std::is_same<R, double>::value ? 32 : 64;
+  int ts = c->hop_tsites[pi];
+  while (ts < tmax && nrhs < kBlock / ts) ts *= 2;
   // the tiled form addresses a wave's fields by 32-bit byte offsets: one
   // right-hand-side stride per extra slot of a wave plus a half field
   auto fits = [&](size_t stride, double bytes) {
-    return double(stride) * bytes + double(g.Vh) * bytes < 4294967295.0;
+    return double(64 / ts - 1) * double(stride) * bytes + double(g.Vh) * bytes < 4294967295.0;
   };
   const bool offs_ok = fits(si, SI::kBytes) && (!C || fits(ss, SS::kBytes)) && fits(so, sizeof(cx<R>));
-  if (c->hop_tile[pi] && offs_ok && t32 && nrhs >= kBlock / 32)
+  const bool tiled = c->hop_tile[pi] && offs_ok && ts <= tmax && nrhs >= kBlock / ts;
+  if (tiled && ts == 16)
+    launch_hop_tile<R, A, B, C, 16>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else if (tiled && ts == 32)
     launch_hop_tile<R, A, B, C, 32>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
-  else if (c->hop_tile[pi] && offs_ok && nrhs >= kBlock / T)
-    launch_hop_tile<R, A, B, C, T>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else if (tiled)
+    launch_hop_tile<R, A, B, C, tmax>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   else if (nrhs >= 8 && nbmax >= 8) launch_hop_nb<R, A, B, C, 8>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   else if (nrhs >= 4 && nbmax >= 4) launch_hop_nb<R, A, B, C, 4>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   else if (nrhs >= 2 && nbmax >= 2) launch_hop_nb<R, A, B, C, 2>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);

@@ -150,20 +150,67 @@ __device__ inline void project(const Src &src, I i, size_t Vh, Half<R> &o) {
 // projection arithmetic and keeps only a few of them in flight per wave.
 template <class Src>
 struct Raw;
+// get(k) is component k as stored times the site's scale; unscaled(k) and
+// scale() split it, so that the linear steps (projection, link product)
+// run on the unscaled values and the scale enters once, in the
+// accumulation (One: plain fields, no scale).
+// kMix: the projection adds run as FMAs with a unit factor, so that each
+// folds the conversion of its two FP16 operands (v_fma_mix_f32).
+struct One {};
 template <class R>
 struct Raw<SrcPlain<R>> {
+  static constexpr bool kMix = false;
   cx<R> v[12];
   __device__ cx<R> get(int k) const { return v[k]; }
+  __device__ cx<R> unscaled(int k) const { return v[k]; }
+  __device__ One scale() const { return One{}; }
 };
 template <HKind K>
 struct Raw<SrcHalf<K>> {
+  static constexpr bool kMix = K == HKind::F16;
   uint32_t w[12];
   float sc;
   __device__ cx<float> get(int k) const {
     const cx<float> v = Codec<K>::unpack(w[k]);
     return mk(sc * v.re, sc * v.im);
   }
+  __device__ cx<float> unscaled(int k) const { return Codec<K>::unpack(w[k]); }
+  __device__ float scale() const { return sc; }
 };
+
+// Explicit fused multiply-adds: the link products as chains of FMAs (one
+// rounding per term) instead of products summed by separate adds.
+__device__ inline double fmr(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float fmr(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+// a b
+template <class R>
+__device__ inline cx<R> cmul_f(cx<R> a, cx<R> b) {
+  return {fmr(a.re, b.re, -a.im * b.im), fmr(a.re, b.im, a.im * b.re)};
+}
+// a b + c
+template <class R>
+__device__ inline cx<R> cfma(cx<R> a, cx<R> b, cx<R> c) {
+  return {fmr(a.re, b.re, fmr(-a.im, b.im, c.re)), fmr(a.re, b.im, fmr(a.im, b.re, c.im))};
+}
+// conj(a) b
+template <class R>
+__device__ inline cx<R> cmulc_f(cx<R> a, cx<R> b) {
+  return {fmr(a.re, b.re, a.im * b.im), fmr(a.re, b.im, -a.im * b.re)};
+}
+// conj(a) b + c
+template <class R>
+__device__ inline cx<R> cfmac(cx<R> a, cx<R> b, cx<R> c) {
+  return {fmr(a.re, b.re, fmr(a.im, b.im, c.re)), fmr(a.re, b.im, fmr(-a.im, b.re, c.im))};
+}
+
+// a + s b
+template <class R>
+__device__ inline cx<R> madd(cx<R> a, One, cx<R> b) {
+  return a + b;
+}
+__device__ inline cx<float> madd(cx<float> a, float s, cx<float> b) {
+  return mk(__builtin_fmaf(s, b.re, a.re), __builtin_fmaf(s, b.im, a.im));
+}
 
 template <class R>
 __device__ inline void fetch_at(const SrcPlain<R> &s, uint32_t o, size_t Vh, Raw<SrcPlain<R>> &r) {
@@ -193,29 +240,35 @@ __device__ inline void settle(Raw<SrcHalf<K>> &r) {
                "+v"(r.sc));
 }
 
-// project() on a settled raw site.
+// project() on a settled raw site, without its scale (RawT::scale()).
+// one must hold 1 in a register the compiler cannot see through: for kMix
+// sources a + b is computed as fma(b, one, a), the same rounded sum.
 template <class R, int MU, bool FWD, bool G5, class RawT>
-__device__ inline void project_raw(const RawT &r, Half<R> &o) {
+__device__ inline void project_raw(const RawT &r, Half<R> &o, R one) {
+  auto add = [one](cx<R> a, cx<R> b) {
+    return RawT::kMix ? cx<R>{fmr(b.re, one, a.re), fmr(b.im, one, a.im)} : a + b;
+  };
+  auto sub = [&add](cx<R> a, cx<R> b) { return add(a, -b); };
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    cx<R> u0 = r.get(0 * 3 + c), u1 = r.get(1 * 3 + c);
-    cx<R> l0 = r.get(2 * 3 + c), l1 = r.get(3 * 3 + c);
+    cx<R> u0 = r.unscaled(0 * 3 + c), u1 = r.unscaled(1 * 3 + c);
+    cx<R> l0 = r.unscaled(2 * 3 + c), l1 = r.unscaled(3 * 3 + c);
     if (G5) {
       l0 = -l0;
       l1 = -l1;
     }
     if (MU == 0) {
-      o.h[0][c] = FWD ? u0 + iz(l1) : u0 - iz(l1);
-      o.h[1][c] = FWD ? u1 + iz(l0) : u1 - iz(l0);
+      o.h[0][c] = FWD ? add(u0, iz(l1)) : sub(u0, iz(l1));
+      o.h[1][c] = FWD ? add(u1, iz(l0)) : sub(u1, iz(l0));
     } else if (MU == 1) {
-      o.h[0][c] = FWD ? u0 + l1 : u0 - l1;
-      o.h[1][c] = FWD ? u1 - l0 : u1 + l0;
+      o.h[0][c] = FWD ? add(u0, l1) : sub(u0, l1);
+      o.h[1][c] = FWD ? sub(u1, l0) : add(u1, l0);
     } else if (MU == 2) {
-      o.h[0][c] = FWD ? u0 + iz(l0) : u0 - iz(l0);
-      o.h[1][c] = FWD ? u1 - iz(l1) : u1 + iz(l1);
+      o.h[0][c] = FWD ? add(u0, iz(l0)) : sub(u0, iz(l0));
+      o.h[1][c] = FWD ? sub(u1, iz(l1)) : add(u1, iz(l1));
     } else {
-      o.h[0][c] = FWD ? u0 - l0 : u0 + l0;
-      o.h[1][c] = FWD ? u1 - l1 : u1 + l1;
+      o.h[0][c] = FWD ? sub(u0, l0) : add(u0, l0);
+      o.h[1][c] = FWD ? sub(u1, l1) : add(u1, l1);
     }
   }
 }
@@ -247,33 +300,28 @@ __device__ inline void accumulate(cx<R> acc[4][3], const Half<R> &g) {
   }
 }
 
-// acc += the (g, R g) reconstruction of (U h) (FWD) or (U^+ h) (backward)
-// for direction MU, one colour row at a time, so that the 6-complex
-// product is never held whole.  u points at entry 0 of the link, entries
-// ld apart.  Same sums in the same order as link_mul / link_dag_mul
-// followed by accumulate.
-template <class R, int MU, bool FWD>
-__device__ inline void link_accumulate(cx<R> acc[4][3], const cx<R> *u, size_t ld, const Half<R> &h) {
+// acc += sc (g, R g), the reconstruction of (U h) (FWD) or (U^+ h)
+// (backward) for direction MU, one colour row at a time, so that the
+// 6-complex product is never held whole.  u points at entry 0 of the link,
+// entries ld apart.  The same terms in the same order as link_mul /
+// link_dag_mul followed by accumulate, summed by FMA chains; sc is the
+// source's per-site scale (One: none).
+template <class R, int MU, bool FWD, class S>
+__device__ inline void link_accumulate(cx<R> acc[4][3], const cx<R> *u, size_t ld, const Half<R> &h, S sc) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     cx<R> g0, g1;
     if (FWD) {
       const cx<R> u0 = ldc(u + (3 * a + 0) * ld), u1 = ldc(u + (3 * a + 1) * ld), u2 = ldc(u + (3 * a + 2) * ld);
-      g0 = u0 * h.h[0][0] + u1 * h.h[0][1] + u2 * h.h[0][2];
-      g1 = u0 * h.h[1][0] + u1 * h.h[1][1] + u2 * h.h[1][2];
+      g0 = cfma(u2, h.h[0][2], cfma(u1, h.h[0][1], cmul_f(u0, h.h[0][0])));
+      g1 = cfma(u2, h.h[1][2], cfma(u1, h.h[1][1], cmul_f(u0, h.h[1][0])));
     } else {  // (U^+ h)_a = sum_b conj(U_ba) h_b
       const cx<R> u0 = ldc(u + (0 * 3 + a) * ld), u1 = ldc(u + (1 * 3 + a) * ld), u2 = ldc(u + (2 * 3 + a) * ld);
-      g0 = mk<R>(0, 0);
-      g1 = mk<R>(0, 0);
-      g0 = g0 + cmulc(u0, h.h[0][0]);
-      g1 = g1 + cmulc(u0, h.h[1][0]);
-      g0 = g0 + cmulc(u1, h.h[0][1]);
-      g1 = g1 + cmulc(u1, h.h[1][1]);
-      g0 = g0 + cmulc(u2, h.h[0][2]);
-      g1 = g1 + cmulc(u2, h.h[1][2]);
+      g0 = cfmac(u2, h.h[0][2], cfmac(u1, h.h[0][1], cmulc_f(u0, h.h[0][0])));
+      g1 = cfmac(u2, h.h[1][2], cfmac(u1, h.h[1][1], cmulc_f(u0, h.h[1][0])));
     }
-    acc[0][a] = acc[0][a] + g0;
-    acc[1][a] = acc[1][a] + g1;
+    acc[0][a] = madd(acc[0][a], sc, g0);
+    acc[1][a] = madd(acc[1][a], sc, g1);
     cx<R> r0, r1;
     if (MU == 0) {
       r0 = FWD ? miz(g1) : iz(g1);
@@ -288,8 +336,8 @@ __device__ inline void link_accumulate(cx<R> acc[4][3], const cx<R> *u, size_t l
       r0 = FWD ? -g0 : g0;
       r1 = FWD ? -g1 : g1;
     }
-    acc[2][a] = acc[2][a] + r0;
-    acc[3][a] = acc[3][a] + r1;
+    acc[2][a] = madd(acc[2][a], sc, r0);
+    acc[3][a] = madd(acc[3][a], sc, r1);
   }
 }
 

@@ -26,7 +26,7 @@ def main():
     ap.add_argument("--order", type=int, default=0)
     ap.add_argument("--nb", type=int, default=0, help="lane-grouped right-hand sides (0: default)")
     ap.add_argument("--tblock", type=int, default=-1, help="plane-blocked tile order: timeslices per block (-1 auto, 0 index order)")
-    ap.add_argument("--tsites", type=int, default=32, help="sites per FP32 tile (32 or 64)")
+    ap.add_argument("--tsites", type=int, default=32, help="sites per tile (FP32: 16, 32 or 64; FP64: 16 or 32)")
     ap.add_argument("--rgroup", type=int, default=0, help="right-hand sides per group of the tiled stencil")
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--reps", type=int, default=20)
@@ -47,7 +47,8 @@ def main():
     U = random_su3_links(dims, 0.2, 1003)
     ctx = Context(dims, U, 0.13)
     ctx.tune(hop_tile64=a.tile, hop_tile32=a.tile, hop_order=a.order, hop_tblock64=a.tblock,
-             hop_tblock32=a.tblock, hop_tsites32=a.tsites, hop_rgroup=a.rgroup)
+             hop_tblock32=a.tblock, hop_tsites32=a.tsites, hop_rgroup=a.rgroup,
+             hop_tsites64=min(a.tsites, 32))
     if a.nb:
         ctx.tune(hop_nb64=a.nb, hop_nb32=a.nb)
     Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2

@@ -115,14 +115,18 @@ def test_full_size_operator_16x32():
 
 
 # tile shapes and orders of the link-tiled stencil: (timeslices per plane
-# block, sites per FP32 tile); 0 = tiles of consecutive sites in index order
-# and right-hand sides per group (0: one group)
+# block, sites per tile (FP64: at most 32), right-hand sides per group);
+# 0 timeslices = tiles of consecutive sites in index order, 0 right-hand
+# sides = one group.  Launches with fewer right-hand sides than a tile's
+# pass (256 / sites) take the next larger tile.
 TILE_SHAPES = [(0, 64, 0), (1, 64, 0), (3, 64, 0), (64, 64, 0), (0, 32, 0), (2, 32, 0), (-1, 32, 0),
-               (-1, 32, 4), (2, 64, 4), (0, 32, 8)]
+               (-1, 32, 4), (2, 64, 4), (0, 32, 8), (0, 16, 0), (-1, 16, 0), (2, 16, 0), (-1, 16, 16),
+               (1, 16, 4)]
 
 
 @pytest.mark.parametrize("dims", [(2, 2, 2, 4), (6, 6, 2, 4), (6, 4, 2, 8), (8, 6, 2, 6)])
-@pytest.mark.parametrize("prec,nrhs", [("f64", 9), ("f32", 5), ("f32", 9), ("f16", 5), ("f16", 8)])
+@pytest.mark.parametrize("prec,nrhs", [("f64", 9), ("f64", 17), ("f32", 5), ("f32", 9), ("f32", 17), ("f16", 5),
+                                       ("f16", 8), ("f16", 16)])
 def test_link_tiled_stencil(dims, prec, nrhs):
     """Launches with many right-hand sides take the link-tiled stencil
     (links staged in LDS per tile of sites): same operator as the oracle,
@@ -146,9 +150,11 @@ def test_link_tiled_stencil(dims, prec, nrhs):
         assert rel_err(y0, _oracle_op(op, U, kappa, x, dims)) < tol, op
         for tb, ts, rg in TILE_SHAPES:
             say("tiled stencil", op, prec, dims, nrhs, "tblock", tb, "tsites", ts, "rgroup", rg)
-            ctx.tune(hop_tile64=1, hop_tile32=1, hop_tblock64=tb, hop_tblock32=tb, hop_tsites32=ts, hop_rgroup=rg)
+            ctx.tune(hop_tile64=1, hop_tile32=1, hop_tblock64=tb, hop_tblock32=tb, hop_tsites32=ts, hop_rgroup=rg,
+                     hop_tsites64=min(ts, 32))
             y = to_host(ctx.wilson_apply(op, to_gpu(x), prec=prec))
             d = rel_err(y, y0)
             assert d < {"f64": 1e-14, "f32": 1e-6, "f16": 1e-6}[prec], (op, tb, ts, rg, d)
             assert rel_err(y, _oracle_op(op, U, kappa, x, dims)) < tol, (op, tb, ts, rg)
-    ctx.tune(hop_tile64=1, hop_tile32=1, hop_tblock64=-1, hop_tblock32=-1, hop_tsites32=32, hop_rgroup=0)
+    ctx.tune(hop_tile64=1, hop_tile32=1, hop_tblock64=-1, hop_tblock32=-1, hop_tsites32=32, hop_rgroup=0,
+             hop_tsites64=32)

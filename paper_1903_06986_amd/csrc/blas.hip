@@ -347,6 +347,76 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// In-place recombination, persistent form for the restart of the large
+// bases: a workgroup holds P (Jout x Jin, FP64) and one tile of 64 elements
+// of all Jin vectors in LDS (together up to 160 KiB on gfx950) and walks
+// tiles gridDim.x apart.  Wave w computes output columns w*kRB.. (4*kRB
+// apart) with lane = element, so each coefficient is one LDS broadcast and
+// each staged element is read once per kRB outputs; the next tile's
+// elements are loaded into registers while the current one is computed.
+// Tiles are disjoint element ranges, so reading the next tile never meets
+// the current tile's writes.
+constexpr int kRB = 4;
+constexpr int kRPer = 24;  // staged elements per lane: Jin <= 24 * 256 / 64 = 96
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_recombine_p(cx<R> *__restrict__ V, size_t ldv, int Jin, const cx<double> *__restrict__ P, size_t ldp,
+                  int Jout, size_t n, int ntile) {
+  extern __shared__ unsigned char smem[];
+  cx<double> *sp = reinterpret_cast<cx<double> *>(smem);                              // [Jout][Jin]
+  cx<R> *sv = reinterpret_cast<cx<R> *>(smem + size_t(Jout) * Jin * sizeof(cx<double>));  // [Jin][64]
+  for (int t = threadIdx.x; t < Jin * Jout; t += kBlock) sp[t] = P[size_t(t % Jin) + ldp * size_t(t / Jin)];
+  const int tot = Jin * 64;
+  cx<R> nx[kRPer];
+  auto fetch = [&](int tile) {
+#pragma unroll
+    for (int u = 0; u < kRPer; ++u) {
+      const int t = threadIdx.x + u * kBlock;
+      const size_t idx = size_t(tile) * 64 + (t & 63);
+      nx[u] = (t < tot && idx < n) ? ldc(V + size_t(t >> 6) * ldv + idx) : mk<R>(0, 0);
+    }
+  };
+  const int e = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  int tile = blockIdx.x;
+  if (tile < ntile) fetch(tile);
+  for (; tile < ntile; tile += gridDim.x) {
+    __syncthreads();  // the previous tile's reads of sv are done
+#pragma unroll
+    for (int u = 0; u < kRPer; ++u) {
+      const int t = threadIdx.x + u * kBlock;
+      if (t < tot) sv[t] = nx[u];
+    }
+    __syncthreads();
+    if (tile + int(gridDim.x) < ntile) fetch(tile + gridDim.x);
+    const size_t idx = size_t(tile) * 64 + e;
+    for (int j0 = w * kRB; j0 < Jout; j0 += kWaves * kRB) {
+      cx<double> acc[kRB];
+      const cx<double> *pc[kRB];  // columns past Jout repeat the last one (not stored)
+#pragma unroll
+      for (int t = 0; t < kRB; ++t) {
+        acc[t] = mk<double>(0, 0);
+        pc[t] = sp + size_t(min(j0 + t, Jout - 1)) * Jin;
+      }
+#pragma unroll 4
+      for (int l = 0; l < Jin; ++l) {
+        const cx<R> v = sv[l * 64 + e];
+        const double vr = double(v.re), vi = double(v.im);
+#pragma unroll
+        for (int t = 0; t < kRB; ++t) {
+          const cx<double> c = pc[t][l];
+          acc[t] = mk<double>(__builtin_fma(vr, c.re, __builtin_fma(-vi, c.im, acc[t].re)),
+                              __builtin_fma(vr, c.im, __builtin_fma(vi, c.re, acc[t].im)));
+        }
+      }
+      if (idx < n) {
+#pragma unroll
+        for (int t = 0; t < kRB; ++t)
+          if (j0 + t < Jout) stc(V + size_t(j0 + t) * ldv + idx, mk<R>(R(acc[t].re), R(acc[t].im)));
+      }
+    }
+  }
+}
 
 // ------------------------------------------------- 16-bit stored bases
 // Basis vectors stored as in half.h (payload words [12][Vh], then per-site
@@ -843,6 +913,23 @@ template <class R>
 void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size_t ldp, int Jout,
                size_t n) {
   LQCD_CHECK(Jout <= Jin, LQCD_EINVAL, "recombine: Jout > Jin");
+  const size_t shw = size_t(Jout) * Jin * sizeof(cx<double>) + size_t(Jin) * 64 * sizeof(cx<R>);
+  if (Jin <= kRPer * kBlock / 64 && shw <= 160 * 1024) {  // persistent, P and a 64-element tile in LDS
+    static bool attr_set = false;
+    if (!attr_set) {
+      LQCD_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_recombine_p<R>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+      attr_set = true;
+    }
+    const int ntile = int((n + 63) / 64);
+    const int per_cu = std::max(1, int((160 * 1024) / shw));
+    const int grid = std::min(ntile, 256 * per_cu);
+    Timed tm(c, LQCD_KC_GEMM, double(Jin + Jout) * n * sizeof(cx<R>));
+    LQCD_TLAUNCH(tm, true, true, (k_recombine_p<R>), dim3(unsigned(grid)), dim3(kBlock), shw, c->stream,
+                 static_cast<cx<R> *>(V), ldv, Jin, reinterpret_cast<const cx<double> *>(P), ldp, Jout, n, ntile);
+    LQCD_HIP(hipGetLastError());
+    return;
+  }
   // largest power-of-two tile (<= 64 elements) whose staging fits 64 KiB of LDS
   int E = 64;
   while (E > 1 && size_t(Jin) * E * sizeof(cx<R>) > 64 * 1024) E >>= 1;

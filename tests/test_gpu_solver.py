@@ -48,6 +48,25 @@ def test_schur_solve_fp64(dims, kappa, nrhs, block):
     assert rel_err(to_host(x2)[0], xref[1]) < 1e-10
 
 
+@pytest.mark.parametrize("m", [90, 100])
+def test_schur_solve_large_basis(m):
+    """Restarts of bases of m + 1 = 91 vectors (recombination by the
+    persistent kernel with 64-element tiles and the coefficients in LDS) and
+    of 101 vectors (the general LDS-staged form): same solution as dense LU.
+    On this lattice and kappa the oracle's GMRES-DR(m, 40) takes 3 cycles."""
+    require_gpu()
+    dims, kappa = (4, 4, 4, 4), 0.19
+    ctx, U = context(dims, 0.3, 1001, kappa)
+    eta = z4_noise(2001, dims, 0, 1)
+    say("solve schur f64 large basis", dims, kappa, "m", m)
+    x, _, st = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=m, k=40, tol=1e-12, tol_super=1e-13,
+                                 max_cycles=200)
+    assert st[0]["cycles"] >= 2, st[0]  # at least one restart
+    xref, _ = _dense_solve(U, kappa, dims, eta)
+    assert rel_err(to_host(x)[0], xref[0]) < 1e-10
+    assert st[0]["true_resid"] < 1e-11, st[0]
+
+
 def test_harmonic_ritz_values_gpu():
     """Super-converged GMRES-DR: converged harmonic Ritz values are
     eigenvalues of Mhat (dense), like the oracle's."""

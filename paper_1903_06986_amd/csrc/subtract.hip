@@ -120,60 +120,88 @@ __device__ inline const cx<double> *link_at(const cx<double> *U, const Geom &g, 
   return U + ((size_t(p) * 4 + mu) * 9) * g.Vh + (s >> 1);
 }
 
-// out[th][s] = sum_w coef_w[th] tr W_w(s) for every lexicographic site s.
-__global__ void __launch_bounds__(kBlock)
-    k_walk_trace(Geom g, const cx<double> *__restrict__ U, const Walk *__restrict__ walks,
-                 int nwalk, cx<double> *__restrict__ out) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.V) return;
+// One hop of a walk from coordinates c: the link of direction d (forward:
+// U_mu(c), then c += mu; backward: c -= mu, then U_mu(c)^+) into Lk.
+__device__ inline void walk_step(const cx<double> *U, const Geom &g, int c[4], int d, cx<double> Lk[3][3]) {
+  const int mu = d >> 1;
   const size_t Vh = g.Vh;
-  const int x0 = s % g.L[0], y0 = (s / g.L[0]) % g.L[1], z0 = (s / (g.L[0] * g.L[1])) % g.L[2],
-            t0 = s / (g.L[0] * g.L[1] * g.L[2]);
-  double acc[kNumOps][2] = {};
-  for (int w = 0; w < nwalk; ++w) {
-    const Walk &wk = walks[w];
-    int c[4] = {x0, y0, z0, t0};
-    cx<double> W[3][3];
+  if ((d & 1) == 0) {
+    const cx<double> *u = link_at(U, g, c[0], c[1], c[2], c[3], mu);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) W[a][b] = mk(a == b ? 1.0 : 0.0, 0.0);
-    for (int i = 0; i < wk.len; ++i) {
-      const int d = wk.dir[i], mu = d >> 1;
-      cx<double> Lk[3][3];
-      if ((d & 1) == 0) {  // forward: U_mu(c), then c += mu
-        const cx<double> *u = link_at(U, g, c[0], c[1], c[2], c[3], mu);
+      for (int b = 0; b < 3; ++b) Lk[a][b] = u[(3 * a + b) * Vh];
+    c[mu] = (c[mu] + 1 == g.L[mu]) ? 0 : c[mu] + 1;
+  } else {
+    c[mu] = (c[mu] == 0) ? g.L[mu] - 1 : c[mu] - 1;
+    const cx<double> *u = link_at(U, g, c[0], c[1], c[2], c[3], mu);
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-          for (int b = 0; b < 3; ++b) Lk[a][b] = u[(3 * a + b) * Vh];
-        c[mu] = (c[mu] + 1 == g.L[mu]) ? 0 : c[mu] + 1;
-      } else {  // backward: c -= mu, then U_mu(c)^+
-        c[mu] = (c[mu] == 0) ? g.L[mu] - 1 : c[mu] - 1;
-        const cx<double> *u = link_at(U, g, c[0], c[1], c[2], c[3], mu);
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            cx<double> v = u[(3 * b + a) * Vh];
-            Lk[a][b] = mk(v.re, -v.im);
-          }
+      for (int b = 0; b < 3; ++b) {
+        const cx<double> v = u[(3 * b + a) * Vh];
+        Lk[a][b] = mk(v.re, -v.im);
       }
-      cx<double> Nw[3][3];
+  }
+}
+
+// W <- W Lk
+__device__ inline void su3_rmul(cx<double> W[3][3], const cx<double> Lk[3][3]) {
+  cx<double> Nw[3][3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) Nw[a][b] = W[a][0] * Lk[0][b] + W[a][1] * Lk[1][b] + W[a][2] * Lk[2][b];
+    for (int b = 0; b < 3; ++b) Nw[a][b] = W[a][0] * Lk[0][b] + W[a][1] * Lk[1][b] + W[a][2] * Lk[2][b];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) W[a][b] = Nw[a][b];
+    for (int b = 0; b < 3; ++b) W[a][b] = Nw[a][b];
+}
+
+// out[th][s] = sum_w coef_w[th] tr W_w(s) for every lexicographic site s.
+// The walks come in depth-first order, cut into groups that share their
+// first P steps (groups[i] = [first, end) walk indices): the prefix product
+// A is formed once per group, each walk multiplies only its last len - P
+// links into B, and tr W = tr(A B) = sum_ab A_ab B_ba.
+__global__ void __launch_bounds__(kBlock)
+    k_walk_trace(Geom g, const cx<double> *__restrict__ U, const Walk *__restrict__ walks,
+                 const int2 *__restrict__ groups, int ngroup, int P, cx<double> *__restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const int x0 = s % g.L[0], y0 = (s / g.L[0]) % g.L[1], z0 = (s / (g.L[0] * g.L[1])) % g.L[2],
+            t0 = s / (g.L[0] * g.L[1] * g.L[2]);
+  double acc[kNumOps][2] = {};
+  for (int gi = 0; gi < ngroup; ++gi) {
+    const int2 gr = groups[gi];
+    int c[4] = {x0, y0, z0, t0};
+    cx<double> A[3][3], Lk[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) A[a][b] = mk(a == b ? 1.0 : 0.0, 0.0);
+    for (int i = 0; i < P; ++i) {
+      walk_step(U, g, c, walks[gr.x].dir[i], Lk);
+      su3_rmul(A, Lk);
     }
-    const cx<double> tr = W[0][0] + W[1][1] + W[2][2];
+    for (int w = gr.x; w < gr.y; ++w) {
+      const Walk &wk = walks[w];
+      int cc[4] = {c[0], c[1], c[2], c[3]};
+      cx<double> B[3][3];
+      walk_step(U, g, cc, wk.dir[P], B);
+      for (int i = P + 1; i < wk.len; ++i) {
+        walk_step(U, g, cc, wk.dir[i], Lk);
+        su3_rmul(B, Lk);
+      }
+      cx<double> tr = mk(0.0, 0.0);
 #pragma unroll
-    for (int th = 0; th < kNumOps; ++th) {
-      acc[th][0] += wk.coef[th][0] * tr.re - wk.coef[th][1] * tr.im;
-      acc[th][1] += wk.coef[th][0] * tr.im + wk.coef[th][1] * tr.re;
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) tr = tr + A[a][b] * B[b][a];
+#pragma unroll
+      for (int th = 0; th < kNumOps; ++th) {
+        acc[th][0] += wk.coef[th][0] * tr.re - wk.coef[th][1] * tr.im;
+        acc[th][1] += wk.coef[th][0] * tr.im + wk.coef[th][1] * tr.re;
+      }
     }
   }
 #pragma unroll
@@ -359,10 +387,22 @@ void ensure_walk_traces(lqcd_ctx *c, bool need_len8) {
     gamma_dense(0, I);
     enumerate(len, g.L, 0, -1, disp, I, dirs, ws);
     if (ws.empty()) continue;
-    walks.ensure(ws.size() * sizeof(Walk));
+    // groups of consecutive walks with the same first P = len - 3 steps
+    const int P = std::max(0, len - 3);
+    std::vector<int2> gr;
+    for (int w = 0; w < int(ws.size()); ++w) {
+      const bool same = w > 0 && std::equal(ws[w].dir, ws[w].dir + P, ws[w - 1].dir);
+      if (same)
+        gr.back().y = w + 1;
+      else
+        gr.push_back(make_int2(w, w + 1));
+    }
+    walks.ensure(ws.size() * sizeof(Walk) + gr.size() * sizeof(int2));
     h2d(c, walks.ptr, ws.data(), ws.size() * sizeof(Walk));
+    int2 *dgr = reinterpret_cast<int2 *>(static_cast<char *>(walks.ptr) + ws.size() * sizeof(Walk));
+    h2d(c, dgr, gr.data(), gr.size() * sizeof(int2));
     hipLaunchKernelGGL(k_walk_trace, dim3(nblocks(g.V)), dim3(kBlock), 0, c->stream, g,
-                       static_cast<const cx<double> *>(c->U64.ptr), walks.as<Walk>(), int(ws.size()),
+                       static_cast<const cx<double> *>(c->U64.ptr), walks.as<Walk>(), dgr, int(gr.size()), P,
                        site.as<cx<double>>());
     LQCD_HIP(hipGetLastError());
     std::vector<cdouble> ts = timeslice_rows(c, site.ptr, kNumOps, tmp);

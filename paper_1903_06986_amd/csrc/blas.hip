@@ -454,6 +454,25 @@ __device__ inline float2 ldscale(const uint32_t *v, size_t Vh, size_t s2) {
   return make_float2(__uint_as_float(u.x), __uint_as_float(u.y));
 }
 
+// One basis vector's words at a lane's two sites: 12 payload pairs and the
+// two scales, loaded together (non-temporal) so that the next vector's
+// loads can be in flight while the current one is used.
+struct HRaw {
+  uint2 q[12];
+  float2 sc;
+};
+template <HKind K>
+__device__ inline void hraw_load(const uint32_t *v, size_t Vh, size_t s2, HRaw &r) {
+  typedef unsigned u2v __attribute__((ext_vector_type(2)));
+  const u2v u = __builtin_nontemporal_load(reinterpret_cast<const u2v *>(v + 12 * Vh + s2));
+  r.sc = make_float2(__uint_as_float(u.x), __uint_as_float(u.y));
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const u2v qv = __builtin_nontemporal_load(reinterpret_cast<const u2v *>(v + c * Vh + s2));
+    r.q[c] = make_uint2(qv.x, qv.y);
+  }
+}
+
 // Partial dot products per wave: part[r][wave chunk][j] (as k_mdot_part).
 template <HKind K>
 __global__ void __launch_bounds__(kBlock)
@@ -477,24 +496,27 @@ __global__ void __launch_bounds__(kBlock)
     wb[c] = pw.b;
   }
   double *po = part + (size_t(r) * nwch + chunk) * size_t(J) * 2;
+  // software pipeline over the basis: vector j + 1's loads go out before
+  // vector j is used; the per-site scale multiplies each site's sum once
+  HRaw cur, nxt;
+  if (on && J > 0) hraw_load<K>(V, Vh, s2, cur);
   for (int j = 0; j < J; ++j) {
-    const uint32_t *v0 = V + size_t(j) * ldv;
     double a0 = 0, b0 = 0;
     if (on) {
-      const float2 sc = ldscale<K>(v0, Vh, s2);
+      if (j + 1 < J) hraw_load<K>(V + size_t(j + 1) * ldv, Vh, s2, nxt);
       float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;  // per-site sums of 12 products
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        cx<float> va, vb;
-        ldhpair<K>(v0, Vh, s2, c, sc, va, vb);
+        const cx<float> va = Codec<K>::unpack(cur.q[c].x), vb = Codec<K>::unpack(cur.q[c].y);
         const cx<float> pa = cmulc(va, wa[c]), pb = cmulc(vb, wb[c]);
         ar += pa.re;
         ai += pa.im;
         br += pb.re;
         bi += pb.im;
       }
-      a0 = double(ar) + double(br);
-      b0 = double(ai) + double(bi);
+      a0 = double(cur.sc.x * ar) + double(cur.sc.y * br);
+      b0 = double(cur.sc.x * ai) + double(cur.sc.y * bi);
+      cur = nxt;
     }
     a0 = wave_sum(a0);
     b0 = wave_sum(b0);
@@ -530,18 +552,21 @@ __global__ void __launch_bounds__(kBlock)
       aa[c] = pw.a;
       ab[c] = pw.b;
     }
+    // software pipeline over the basis (as k_hmdot_part); the site's scale
+    // is folded into the coefficient
+    HRaw cur, nxt;
+    if (J > 0) hraw_load<K>(V, Vh, s2, cur);
     for (int j = 0; j < J; ++j) {
+      if (j + 1 < J) hraw_load<K>(V + size_t(j + 1) * ldv, Vh, s2, nxt);
       const cx<double> cd = coef[j];
       const cx<float> cj = mk<float>(float(cd.re), float(cd.im));
-      const uint32_t *v0 = V + size_t(j) * ldv;
-      const float2 sc = ldscale<K>(v0, Vh, s2);
+      const cx<float> ca = mk(cur.sc.x * cj.re, cur.sc.x * cj.im), cb = mk(cur.sc.y * cj.re, cur.sc.y * cj.im);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        cx<float> va, vb;
-        ldhpair<K>(v0, Vh, s2, c, sc, va, vb);
-        aa[c] = aa[c] - va * cj;
-        ab[c] = ab[c] - vb * cj;
+        aa[c] = aa[c] - Codec<K>::unpack(cur.q[c].x) * ca;
+        ab[c] = ab[c] - Codec<K>::unpack(cur.q[c].y) * cb;
       }
+      cur = nxt;
     }
 #pragma unroll
     for (int c = 0; c < 12; ++c) {

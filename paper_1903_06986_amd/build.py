@@ -3,8 +3,8 @@
 Every source under ``csrc/`` is compiled for gfx950 only, with packed FP32
 instructions disabled (``-target-feature -packed-fp32-ops``), and linked
 into ``paper_1903_06986_amd/liblqcd.so``.  Objects go to ``_build/`` at
-the repository root.  ``python -m paper_1903_06986_amd.build`` or
-``__graft_entry__.build()`` runs it.
+the repository root.  ``python -m paper_1903_06986_amd.build`` or the
+entry point's ``build()`` at the repository root runs it.
 """
 import concurrent.futures as cf
 import os

@@ -259,7 +259,9 @@ def accuracy(path, precisions, cfg, kappa, U, oracle_check):
 def batching(args):
     """Untimed by the headline: the mixed-lattice batch (8^4 x 17, 12^3 x 24
     x 64, 16^3 x 32 x 160 right-hand sides) solved by batch_solve with the
-    autotuned block and grid, against the same solves lattice by lattice."""
+    autotuned block and grid, against the same solves lattice by lattice;
+    then the lattices smaller than 16^3 x 32 alone, batched and
+    sequential."""
     import torch
     from paper_1903_06986_amd import Batch, Context
     from synth import get_config, random_su3_links
@@ -294,6 +296,7 @@ def batching(args):
     dt_eager = time.perf_counter() - t0
     seq = {}
     t_seq = 0.0
+    seq_t = []
     for ctx, defl, eta, dims in zip(ctxs, defls, etas, cfg["lattices"]):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -303,9 +306,28 @@ def batching(args):
         torch.cuda.synchronize()
         d1 = time.perf_counter() - t1
         t_seq += d1
+        seq_t.append(d1)
         seq["x".join(map(str, dims))] = {"solves_per_s": round(eta.shape[0] / d1, 3),
                                         "matvecs_per_solve": float(np.mean([s["matvecs"] for s in s1]))}
-    out = {"lattices": ["%s x %d" % ("x".join(map(str, d)), n) for d, n in zip(cfg["lattices"], cfg["n_rhs"])],
+    batch.close()
+    # the lattices that cannot fill the GPU alone (8^4 x 17, 12^3x24 x 64),
+    # batched with their own autotuned shape against the same solves one
+    # lattice after the other
+    small = [i for i, d in enumerate(cfg["lattices"]) if int(np.prod(d)) < 131072]
+    sb = Batch([ctxs[i] for i in small])
+    s_eta, s_defl = [etas[i] for i in small], [defls[i] for i in small]
+    s_blk, s_grid, _ = sb.autotune(s_eta, s_defl, **kw)
+    sb.set_grid(s_grid)
+    s_total = sum(e.shape[0] for e in s_eta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sb.solve(s_eta, s_defl, rhs_block=s_blk, graph=True, **kw)
+    torch.cuda.synchronize()
+    s_dt = time.perf_counter() - t0
+    s_seq = sum(seq_t[i] for i in small)
+    sb.close()
+    lat = ["%s x %d" % ("x".join(map(str, d)), n) for d, n in zip(cfg["lattices"], cfg["n_rhs"])]
+    out = {"lattices": lat,
            "kappa": kappa, "solves": total, "setup_s": round(setup_s, 3),
            "autotune": {"rhs_block": blk, "grid": grid,
                         "rates": {"%d/%d" % k: round(v, 2) for k, v in table.items()}},
@@ -315,9 +337,12 @@ def batching(args):
            "batched_over_sequential": round(t_seq / dt, 3),
            "per_lattice_sequential": seq,
            "max_true_resid": max(s["true_resid"] for s in st),
-           "matvecs_per_solve": float(np.mean([s["matvecs"] for s in st]))}
+           "matvecs_per_solve": float(np.mean([s["matvecs"] for s in st])),
+           "small_lattices_only": {"lattices": [lat[i] for i in small], "rhs_block": s_blk, "grid": s_grid,
+                                   "batched_graph_solves_per_s": round(s_total / s_dt, 3),
+                                   "sequential_solves_per_s": round(s_total / s_seq, 3),
+                                   "batched_over_sequential": round(s_seq / s_dt, 3)}}
     print("[bench] batching %s" % json.dumps(out), file=sys.stderr, flush=True)
-    batch.close()
     return out
 
 

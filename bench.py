@@ -81,6 +81,34 @@ def traffic_for(kernel_class, bytes_per_launch):
     return t["hbm_bytes_per_launch"]
 
 
+def dslash_rates(kt):
+    """The stencil of the mixed inner solves (FP32 arithmetic, the two halves
+    of the even/odd operator): its algorithmic rate and fraction of the HBM
+    peak, and the HBM rate implied by the committed counters (their ratio of
+    HBM to algorithmic bytes for these launches), when the stencil sources
+    are unchanged since the counters were taken and the launches have the
+    same algorithmic size; else the HBM fields are None."""
+    if "hop32" not in kt:
+        return None
+    ms, by, nl = kt["hop32"]
+    alg = by / (ms * 1e-3) / 1e9
+    out = {"kernel": "k_hop_tile, FP32 arithmetic (16-bit and FP32 inputs)", "algorithmic_GBps": round(alg, 1),
+           "frac": round(alg / HBM_PEAK_GBS, 4), "hbm_GBps": None, "hbm_frac": None, "hbm_over_algorithmic": None}
+    p = os.path.join(ROOT, "profiles", "traffic_hop32.json")
+    if not os.path.exists(p):
+        return out
+    with open(p) as f:
+        t = json.load(f)
+    blob = b"".join(open(os.path.join(ROOT, "paper_1903_06986_amd", "csrc", n), "rb").read() for n in t["sources"])
+    bpl = by / max(nl, 1)
+    if (hashlib.sha256(blob).hexdigest()[:16] != t["source_sha"]
+            or abs(t["algorithmic_bytes_per_launch"] - bpl) > 0.02 * bpl):
+        return out
+    r = t["hbm_over_algorithmic"]
+    out.update(hbm_GBps=round(alg * r, 1), hbm_frac=round(alg * r / HBM_PEAK_GBS, 4), hbm_over_algorithmic=round(r, 3))
+    return out
+
+
 class Path:
     """Per-configuration setup and the per-noise step, as library calls."""
 
@@ -515,6 +543,7 @@ def main():
                       "max_eig_resid": float(np.max(path.lam_res)), "compare": path.herm_compare},
         "end_to_end_200_noise_s": round(path.setup_times["total_s"] + 199.0 / value, 2),
         "kernels": kernels,
+        "dslash": dslash_rates(kt),
         "roofline": roof,
         "cpu_baseline": cpu,
     }

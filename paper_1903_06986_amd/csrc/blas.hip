@@ -953,12 +953,10 @@ void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size
   LQCD_CHECK(Jout <= Jin, LQCD_EINVAL, "recombine: Jout > Jin");
   const size_t shw = size_t(Jout) * Jin * sizeof(cx<double>) + size_t(Jin) * 64 * sizeof(cx<R>);
   if (Jin <= kRPer * kBlock / 64 && shw <= 160 * 1024) {  // persistent, P and a 64-element tile in LDS
-    static bool attr_set = false;
-    if (!attr_set) {
-      LQCD_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_recombine_p<R>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-      attr_set = true;
-    }
+    // set on every call (once per restart): it is a property of the kernel
+    // on the current device, and contexts may live on different devices
+    LQCD_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_recombine_p<R>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     const int ntile = int((n + 63) / 64);
     const int per_cu = std::max(1, int((160 * 1024) / shw));
     const int grid = std::min(ntile, 256 * per_cu);

@@ -797,15 +797,19 @@ template <class R>
 __global__ void __launch_bounds__(kBlock)
     k_gemm_tn_final(const R *__restrict__ part, int nblk, int J, int nb, cx<double> *__restrict__ C,
                     size_t ldc) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= J * nb) return;
+  // one workgroup per output (j, column): the lanes stride over the ~1024
+  // partial tiles and the block sums them (a single lane per output would
+  // walk them as one chain of dependent loads)
+  __shared__ double sh[2][kWaves];
+  const int t = blockIdx.x;
   const int j = t % J, c = t / J;
-  double re = 0, im = 0;
-  for (int b = 0; b < nblk; ++b) {
-    re += double(part[(size_t(b) * 64 + j) * 16 + c]);
-    im += double(part[(size_t(b) * 64 + j) * 16 + nb + c]);
+  double v[2] = {0, 0};
+  for (int b = threadIdx.x; b < nblk; b += kBlock) {
+    v[0] += double(part[(size_t(b) * 64 + j) * 16 + c]);
+    v[1] += double(part[(size_t(b) * 64 + j) * 16 + nb + c]);
   }
-  C[j + ldc * size_t(c)] = mk(re, im);
+  block_sum<2>(v, sh);
+  if (threadIdx.x == 0) C[j + ldc * size_t(c)] = mk(v[0], v[1]);
 }
 
 inline unsigned grid_elems(size_t n) { return unsigned(std::min<size_t>(nblocks(n), 8192)); }
@@ -942,8 +946,8 @@ void gemm_tn(lqcd_ctx *c, const void *V, size_t ldv, int J, const void *X, size_
                  static_cast<const cx<R> *>(V), ldv, J, static_cast<const cx<R> *>(X), ldx, nb, n, cpb, part);
   }
   LQCD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_gemm_tn_final<R>, dim3(unsigned((J * nb + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     c->stream, part, nblk, J, nb, reinterpret_cast<cx<double> *>(C), ldc);
+  hipLaunchKernelGGL(k_gemm_tn_final<R>, dim3(unsigned(J * nb)), dim3(kBlock), 0, c->stream, part, nblk, J, nb,
+                     reinterpret_cast<cx<double> *>(C), ldc);
   LQCD_HIP(hipGetLastError());
 }
 

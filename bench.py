@@ -539,7 +539,7 @@ def main():
         "setup": {k: round(v, 3) for k, v in path.setup_times.items()},
         "production_single_rhs": prod,
         "hermitian": {"method": args.herm_method, "matvecs": path.herm_stats[0]["matvecs"],
-                      "cycles": path.herm_stats[0]["cycles"],
+                      "cycles": path.herm_stats[0]["cycles"], "second_passes": path.herm_stats[0]["reorth"],
                       "max_eig_resid": float(np.max(path.lam_res)), "compare": path.herm_compare},
         "end_to_end_200_noise_s": round(path.setup_times["total_s"] + 199.0 / value, 2),
         "kernels": kernels,

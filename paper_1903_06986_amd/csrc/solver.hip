@@ -57,6 +57,26 @@ __global__ void k_dgks(const cx<double> *__restrict__ h1, size_t hrs, int J,
   if (need) reorth_count[r] += 1;
 }
 
+__global__ void k_count1(int *__restrict__ count) { count[0] += 1; }
+
+// Selective reorthogonalisation against the kept vectors (MINRES-DR): the
+// update with their second-pass coefficients runs only if one of them
+// exceeds tau |w| (tau2 = tau^2, nrm1 = |w|^2 after the first pass);
+// otherwise they are set to zero, so that the Hessenberg column matches the
+// vector.  Counts the updates that run.
+__global__ void k_kept_test(cx<double> *__restrict__ h2, int kept, const double *__restrict__ nrm1, double tau2,
+                            int *__restrict__ kflag, int *__restrict__ count) {
+  if (threadIdx.x != 0) return;
+  double mx = 0;
+  for (int i = 0; i < kept; ++i) mx = fmax(mx, h2[i].re * h2[i].re + h2[i].im * h2[i].im);
+  const int need = mx > tau2 * nrm1[0] ? 1 : 0;
+  kflag[0] = need;
+  if (need)
+    count[0] += 1;
+  else
+    for (int i = 0; i < kept; ++i) h2[i] = mk(0.0, 0.0);
+}
+
 // Column j of Hbar: h1 (+ h2 when the second pass ran); h_{j+1,j} = |w|.
 __global__ void k_finish_col(cx<double> *__restrict__ Hd, size_t Hrs, int ldh, int j,
                              const cx<double> *__restrict__ h1, const cx<double> *__restrict__ h2,
@@ -146,13 +166,13 @@ struct Small {
   explicit Small(DevBuf &b) : buf(b) {}
   cdouble *Hd, *h1, *h2, *vec, *C, *E;
   double *nrm2, *inv, *nrm1;
-  int *flag, *reorth;
+  int *flag, *reorth, *kflag, *scratch_count;
   size_t Hrs;
   void setup(int m, int nb, int kmax) {
     Hrs = size_t(m + 1) * m;
     size_t nc = Hrs * nb + 2 * size_t(m + 1) * nb + size_t(m + 1) * nb + 2 * size_t(kmax + 1) * nb +
                 size_t(m + 1) * (kmax + 1);
-    size_t bytes = nc * sizeof(cdouble) + 3 * size_t(nb) * sizeof(double) + 2 * size_t(nb) * sizeof(int) + 256;
+    size_t bytes = nc * sizeof(cdouble) + 3 * size_t(nb) * sizeof(double) + 4 * size_t(nb) * sizeof(int) + 256;
     char *p = static_cast<char *>(buf.ensure(bytes));
     Hd = reinterpret_cast<cdouble *>(p);
     h1 = Hd + Hrs * nb;
@@ -165,6 +185,8 @@ struct Small {
     nrm1 = inv + nb;
     flag = reinterpret_cast<int *>(nrm1 + nb);
     reorth = flag + nb;
+    kflag = reorth + nb;
+    scratch_count = kflag + nb;
   }
 };
 
@@ -186,6 +208,9 @@ void d2h(lqcd_ctx *c, void *dst, const void *src, size_t bytes) {
 // there A v_j is mostly its component along v_j, which one pass removes
 // accurately.
 constexpr double kReorthAlways = 2.0;
+// MINRES-DR: kept-vector updates whose coefficients all lie below this
+// fraction of |w| are skipped (they would move w below its rounding level)
+constexpr double kKeptTau = 1e-14;
 constexpr double kReorthCycle = 0.01;
 
 // Inner (FP32) solves of the refinement: at most this many GMRES(m-k)
@@ -281,18 +306,26 @@ void lanczos_ext(lqcd_ctx *c, const Op<double> &A, void *V, size_t n, int j0, in
     fill_zero(c, s.h2, hb);
     multi_dot<double>(c, wp, n, 0, 2, wn, 0, n, 1, s.h1 + (j - 1), m + 1);
     multi_axpy<double>(c, wp, n, 0, 2, s.h1 + (j - 1), m + 1, wn, 0, n, 1, s.nrm1);
-    // the second pass always runs (k_dgks with a threshold above 1)
+    // the second pass always runs (k_dgks with a threshold above 1); its
+    // count is not reported: MINRES-DR reports the kept-vector updates
     hipLaunchKernelGGL(k_dgks, dim3(1), dim3(64), 0, c->stream,
                        reinterpret_cast<const cx<double> *>(s.h1), size_t(m + 1), j + 1, s.nrm1, s.flag,
-                       s.reorth, kReorthAlways);
+                       s.scratch_count, kReorthAlways);
     LQCD_HIP(hipGetLastError());
     if (kept >= j - 1) {  // kept vectors and v_{j-1}, v_j are one range
       multi_dot<double>(c, Vb, n, 0, j + 1, wn, 0, n, 1, s.h2, m + 1);
       multi_axpy<double>(c, Vb, n, 0, j + 1, s.h2, m + 1, wn, 0, n, 1, s.nrm2);
+      hipLaunchKernelGGL(k_count1, dim3(1), dim3(1), 0, c->stream, s.reorth);
+      LQCD_HIP(hipGetLastError());
     } else {
-      if (kept > 0) multi_dot<double>(c, Vb, n, 0, kept, wn, 0, n, 1, s.h2, m + 1);
+      if (kept > 0) {
+        multi_dot<double>(c, Vb, n, 0, kept, wn, 0, n, 1, s.h2, m + 1);
+        hipLaunchKernelGGL(k_kept_test, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.h2),
+                           kept, s.nrm1, kKeptTau * kKeptTau, s.kflag, s.reorth);
+        LQCD_HIP(hipGetLastError());
+      }
       multi_dot<double>(c, wp, n, 0, 2, wn, 0, n, 1, s.h2 + (j - 1), m + 1);
-      if (kept > 0) multi_axpy<double>(c, Vb, n, 0, kept, s.h2, m + 1, wn, 0, n, 1, nullptr);
+      if (kept > 0) multi_axpy<double>(c, Vb, n, 0, kept, s.h2, m + 1, wn, 0, n, 1, nullptr, s.kflag);
       multi_axpy<double>(c, wp, n, 0, 2, s.h2 + (j - 1), m + 1, wn, 0, n, 1, s.nrm2);
     }
     hipLaunchKernelGGL(k_finish_col, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.Hd),

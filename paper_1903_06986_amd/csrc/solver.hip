@@ -202,16 +202,18 @@ void d2h(lqcd_ctx *c, void *dst, const void *src, size_t bytes) {
 // Arnoldi steps j0 .. m-1 on nb bases (vectors n apart, bases Wrs apart):
 // w = A v_j; two classical Gram-Schmidt passes; h_{j+1,j} = |w|;
 // v_{j+1} = w / |w|.  Column j of each Hbar goes to the device matrix.
-// Second-pass thresholds: always in GMRES-DR (its harmonic Ritz vectors
-// become the deflation space), and in the GMRES(m-k) cycles of GMRES-Proj
-// only when the first pass cancelled more than one digit (|w'| < 0.1 |w|);
-// there A v_j is mostly its component along v_j, which one pass removes
-// accurately.
+// Second-pass thresholds: in GMRES-DR (whose harmonic Ritz vectors become
+// the deflation space) the DGKS test with |w'|^2 < |w|^2 / 2, which keeps
+// the basis orthogonal to working precision; in the GMRES(m-k) cycles of
+// GMRES-Proj only when the first pass cancelled more than one digit
+// (|w'| < 0.1 |w|): there A v_j is mostly its component along v_j, which
+// one pass removes accurately.
 constexpr double kReorthAlways = 2.0;
+constexpr double kReorthDR = 0.5;
+constexpr double kReorthCycle = 0.01;
 // MINRES-DR: kept-vector updates whose coefficients all lie below this
 // fraction of |w| are skipped (they would move w below its rounding level)
 constexpr double kKeptTau = 1e-14;
-constexpr double kReorthCycle = 0.01;
 
 // Inner (FP32) solves of the refinement: at most this many GMRES(m-k)
 // cycles per refinement step, and stop when a cycle reduces the residual
@@ -505,7 +507,7 @@ void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lq
   int kept = 0;  // MINRES-DR: vectors kept by the last restart
   for (;;) {
     if (lz) lanczos_ext(c, A, V, n, j0, m, kept, s);
-    else arnoldi<double>(c, A, V, n, 0, j0, m, 1, s, kReorthAlways);
+    else arnoldi<double>(c, A, V, n, 0, j0, m, 1, s, kReorthDR);
     st.matvecs += m - j0;
     harvest_reorth(c, s, 1, std::vector<int>{0}, reorth1);
     st.reorth = reorth1[0];

@@ -320,14 +320,17 @@ void lanczos_ext(lqcd_ctx *c, const Op<double> &A, void *V, size_t n, int j0, in
       hipLaunchKernelGGL(k_count1, dim3(1), dim3(1), 0, c->stream, s.reorth);
       LQCD_HIP(hipGetLastError());
     } else {
-      if (kept > 0) {
+      // the kept vectors are tested on every other step and on the last
+      // step of a cycle (their coefficients stay zero otherwise)
+      const bool test = kept > 0 && ((j - j0) % 2 == 1 || j == m - 1);
+      if (test) {
         multi_dot<double>(c, Vb, n, 0, kept, wn, 0, n, 1, s.h2, m + 1);
         hipLaunchKernelGGL(k_kept_test, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.h2),
                            kept, s.nrm1, kKeptTau * kKeptTau, s.kflag, s.reorth);
         LQCD_HIP(hipGetLastError());
       }
       multi_dot<double>(c, wp, n, 0, 2, wn, 0, n, 1, s.h2 + (j - 1), m + 1);
-      if (kept > 0) multi_axpy<double>(c, Vb, n, 0, kept, s.h2, m + 1, wn, 0, n, 1, nullptr, s.kflag);
+      if (test) multi_axpy<double>(c, Vb, n, 0, kept, s.h2, m + 1, wn, 0, n, 1, nullptr, s.kflag);
       multi_axpy<double>(c, wp, n, 0, 2, s.h2 + (j - 1), m + 1, wn, 0, n, 1, s.nrm2);
     }
     hipLaunchKernelGGL(k_finish_col, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.Hd),

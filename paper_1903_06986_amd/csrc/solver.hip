@@ -278,9 +278,11 @@ void arnoldi_h(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, s
 // column j0 is orthogonalised twice against every vector before it (it
 // couples to all kept vectors of the restart); each later column by the
 // three-term recurrence against v_{j-1}, v_j, then once more against those
-// two and the first `kept` vectors (the kept vectors of the last restart:
-// selective reorthogonalisation against the approximate eigenvectors).
-// Both passes' coefficients add into column j of Hbar.
+// two, and on every other step (and the last) against the first `kept`
+// vectors (the kept vectors of the last restart: selective
+// reorthogonalisation against the approximate eigenvectors), whose update
+// runs only when a coefficient exceeds kKeptTau |w|.  Both passes'
+// coefficients add into column j of Hbar.
 void lanczos_ext(lqcd_ctx *c, const Op<double> &A, void *V, size_t n, int j0, int m, int kept, Small &s) {
   cx<double> *Vb = static_cast<cx<double> *>(V);
   const size_t hb = size_t(m + 1) * sizeof(cdouble);

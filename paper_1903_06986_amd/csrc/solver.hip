@@ -63,18 +63,21 @@ __global__ void k_count1(int *__restrict__ count) { count[0] += 1; }
 // update with their second-pass coefficients runs only if one of them
 // exceeds tau |w| (tau2 = tau^2, nrm1 = |w|^2 after the first pass);
 // otherwise they are set to zero, so that the Hessenberg column matches the
-// vector.  Counts the updates that run.
+// vector.  Counts the updates that run, and raises the second-pass flag
+// when one does.
 __global__ void k_kept_test(cx<double> *__restrict__ h2, int kept, const double *__restrict__ nrm1, double tau2,
-                            int *__restrict__ kflag, int *__restrict__ count) {
+                            int *__restrict__ kflag, int *__restrict__ flag, int *__restrict__ count) {
   if (threadIdx.x != 0) return;
   double mx = 0;
   for (int i = 0; i < kept; ++i) mx = fmax(mx, h2[i].re * h2[i].re + h2[i].im * h2[i].im);
   const int need = mx > tau2 * nrm1[0] ? 1 : 0;
   kflag[0] = need;
-  if (need)
+  if (need) {
     count[0] += 1;
-  else
+    flag[0] = 1;  // the second pass (and |w| after it) is then needed
+  } else {
     for (int i = 0; i < kept; ++i) h2[i] = mk(0.0, 0.0);
+  }
 }
 
 // Column j of Hbar: h1 (+ h2 when the second pass ran); h_{j+1,j} = |w|.
@@ -278,11 +281,11 @@ void arnoldi_h(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, s
 // column j0 is orthogonalised twice against every vector before it (it
 // couples to all kept vectors of the restart); each later column by the
 // three-term recurrence against v_{j-1}, v_j, then once more against those
-// two, and on every other step (and the last) against the first `kept`
-// vectors (the kept vectors of the last restart: selective
-// reorthogonalisation against the approximate eigenvectors), whose update
-// runs only when a coefficient exceeds kKeptTau |w|.  Both passes'
-// coefficients add into column j of Hbar.
+// two when the DGKS test asks for it, and on every other step (and the
+// last) against the first `kept` vectors (the kept vectors of the last
+// restart: selective reorthogonalisation against the approximate
+// eigenvectors), whose update runs only when a coefficient exceeds
+// kKeptTau |w|.  Both passes' coefficients add into column j of Hbar.
 void lanczos_ext(lqcd_ctx *c, const Op<double> &A, void *V, size_t n, int j0, int m, int kept, Small &s) {
   cx<double> *Vb = static_cast<cx<double> *>(V);
   const size_t hb = size_t(m + 1) * sizeof(cdouble);
@@ -310,30 +313,36 @@ void lanczos_ext(lqcd_ctx *c, const Op<double> &A, void *V, size_t n, int j0, in
     fill_zero(c, s.h2, hb);
     multi_dot<double>(c, wp, n, 0, 2, wn, 0, n, 1, s.h1 + (j - 1), m + 1);
     multi_axpy<double>(c, wp, n, 0, 2, s.h1 + (j - 1), m + 1, wn, 0, n, 1, s.nrm1);
-    // the second pass always runs (k_dgks with a threshold above 1); its
-    // count is not reported: MINRES-DR reports the kept-vector updates
-    hipLaunchKernelGGL(k_dgks, dim3(1), dim3(64), 0, c->stream,
-                       reinterpret_cast<const cx<double> *>(s.h1), size_t(m + 1), j + 1, s.nrm1, s.flag,
-                       s.scratch_count, kReorthAlways);
-    LQCD_HIP(hipGetLastError());
     if (kept >= j - 1) {  // kept vectors and v_{j-1}, v_j are one range
+      hipLaunchKernelGGL(k_dgks, dim3(1), dim3(64), 0, c->stream,
+                         reinterpret_cast<const cx<double> *>(s.h1), size_t(m + 1), j + 1, s.nrm1, s.flag,
+                         s.scratch_count, kReorthAlways);
+      LQCD_HIP(hipGetLastError());
       multi_dot<double>(c, Vb, n, 0, j + 1, wn, 0, n, 1, s.h2, m + 1);
       multi_axpy<double>(c, Vb, n, 0, j + 1, s.h2, m + 1, wn, 0, n, 1, s.nrm2);
       hipLaunchKernelGGL(k_count1, dim3(1), dim3(1), 0, c->stream, s.reorth);
       LQCD_HIP(hipGetLastError());
     } else {
+      // second pass against v_{j-1}, v_j by the DGKS test (its count is not
+      // reported: MINRES-DR reports the kept-vector updates)
+      hipLaunchKernelGGL(k_dgks, dim3(1), dim3(64), 0, c->stream,
+                         reinterpret_cast<const cx<double> *>(s.h1), size_t(m + 1), j + 1, s.nrm1, s.flag,
+                         s.scratch_count, kReorthDR);
+      LQCD_HIP(hipGetLastError());
+      multi_dot<double>(c, wp, n, 0, 2, wn, 0, n, 1, s.h2 + (j - 1), m + 1, s.flag);
       // the kept vectors are tested on every other step and on the last
       // step of a cycle (their coefficients stay zero otherwise)
       const bool test = kept > 0 && ((j - j0) % 2 == 1 || j == m - 1);
       if (test) {
         multi_dot<double>(c, Vb, n, 0, kept, wn, 0, n, 1, s.h2, m + 1);
         hipLaunchKernelGGL(k_kept_test, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.h2),
-                           kept, s.nrm1, kKeptTau * kKeptTau, s.kflag, s.reorth);
+                           kept, s.nrm1, kKeptTau * kKeptTau, s.kflag, s.flag, s.reorth);
         LQCD_HIP(hipGetLastError());
+        multi_axpy<double>(c, Vb, n, 0, kept, s.h2, m + 1, wn, 0, n, 1, nullptr, s.kflag);
       }
-      multi_dot<double>(c, wp, n, 0, 2, wn, 0, n, 1, s.h2 + (j - 1), m + 1);
-      if (test) multi_axpy<double>(c, Vb, n, 0, kept, s.h2, m + 1, wn, 0, n, 1, nullptr, s.kflag);
-      multi_axpy<double>(c, wp, n, 0, 2, s.h2 + (j - 1), m + 1, wn, 0, n, 1, s.nrm2);
+      // runs whenever either update is needed (with zero coefficients when
+      // only the kept vectors' is), so that |w|^2 after the pass is formed
+      multi_axpy<double>(c, wp, n, 0, 2, s.h2 + (j - 1), m + 1, wn, 0, n, 1, s.nrm2, s.flag);
     }
     hipLaunchKernelGGL(k_finish_col, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.Hd),
                        s.Hrs, m + 1, j, reinterpret_cast<cx<double> *>(s.h1),

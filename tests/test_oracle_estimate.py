@@ -5,7 +5,11 @@
   exact Tr(Theta M^{-1}) from a dense inverse.
 * Variance law for Z(4) noise (Eq. (13) with one noise vector): with
   q = Theta (M^{-1} - tilde-M^{-1}), Var t = sum_{i != j} |q_ij|^2, and
-  Var Re t, Var Im t = 1/2 sum_{i != j} (|q_ij|^2 +- Re q_ij q_ji).
+  Var Re t, Var Im t = 1/2 sum_{i != j} (|q_ij|^2 +- Re q_ij q_ji).  The
+  standard errors the estimator reports satisfy N err^2 = Var (Re / Im).
+* 1/xi' (Sec. 5.5): once p(kappa P) is M^{-1}, e'^dagger g5 p e' is
+  e'^dagger M'^{-1} e' = 1/lambda' (M' = M g5), and HFPS / HFPOLY collapse
+  to their polynomial part.
 * HFES with every eigenpair of M' reproduces x exactly (zero variance).
 * Sec. 6: per site, tr(M^{-1})_xx is real and tr(g_mu M^{-1})_xx imaginary.
 * The estimate is unchanged by a gauge transformation of links and noise.
@@ -117,10 +121,50 @@ def test_unbiased_and_variance_law(dense):
             # Z(4) variance law
             emp = np.var(t[:, a, -1])
             assert abs(emp / var_c - 1) < 0.04, (m, th, emp / var_c)
-            for part, pred in ((t[:, a, -1].real, 0.5 * (var_c + cross)),
-                               (t[:, a, -1].imag, 0.5 * (var_c - cross))):
+            for c, (part, pred) in enumerate(((t[:, a, -1].real, 0.5 * (var_c + cross)),
+                                              (t[:, a, -1].imag, 0.5 * (var_c - cross)))):
                 if pred > 1e-3 * var_c:
                     assert abs(np.var(part) / pred - 1) < 0.05, (m, th)
+                    # the reported standard error is sqrt(Var / N): N err^2
+                    # against the predicted variance (a missing 1/sqrt(N),
+                    # or a Re/Im swap, misses by orders of magnitude)
+                    assert abs(N * err[a, -1, c] ** 2 / pred - 1) < 0.05, (m, th, c)
+                else:
+                    assert N * err[a, -1, c] ** 2 < 2e-3 * var_c, (m, th, c)
+
+
+def test_xi_inverse_is_inverse_eigenvalue_when_p_inverts_M():
+    """With p(kappa P) = z M^{-1} (the hopping series of order 60 at kappa =
+    0.05 times a complex z; kappa ||P|| <= 0.05 * 8 sqrt(2) < 0.57, so the
+    truncation is below 0.57^61 ~ 1e-15), 1/xi'_q = e'^dagger g5 p e'_q must
+    equal z / lambda'_q: M' = M g5 gives M'^{-1} = g5 M^{-1} (Sec. 5.5).  A
+    missing g5 flips the sign for the negative lambda', a conjugated
+    bilinear gives conj(z) / lambda'.  The HFPS / HFPOLY overlap term then
+    cancels the HFES term exactly, vector and trace correction."""
+    kappa = 0.05
+    U = random_su3_links(DIMS, 0.3, 65)
+    V = L.volume(DIMS)
+    M = W.dense_M(U, kappa, DIMS)
+    G5 = W.dense_gamma(L.GAMMA5, V)
+    lam, Ev = K.hermitian_eigpairs_dense(M @ G5, 12)
+    assert (lam < 0).any() and (lam > 0).any()
+    shape = (DIMS[3], DIMS[2], DIMS[1], DIMS[0], 4, 3)
+    Et = Ev.T.reshape((lam.size,) + shape)
+    z = 0.3 + 0.7j
+    coeffs = z * S.pert_coeffs(60)
+    xi = S.xi_inverse(U, kappa, Et, coeffs)
+    assert np.abs(xi - z / lam).max() < 1e-12 * np.abs(z / lam).max()
+    # HFPOLY with p -> z M^{-1} and weights z / lambda': the eigen part and
+    # the overlap cancel, leaving x_poly and Tr(Theta p)
+    eta = z4_noise(9, DIMS, 0, 3)
+    eig = S.eig_vector(Et, z / lam + 0j, eta)
+    assert np.abs(eig - S.eig_vector(Et, xi, eta)).max() < 1e-12
+    sb = S.site_bilinear(Et, (0, 1, 2, 3, 4), DIMS, z / lam + 0j)
+    assert np.abs(sb - S.site_bilinear(Et, (0, 1, 2, 3, 4), DIMS, xi)).max() < 1e-12
+    # and the truncated series is M^{-1} to the same accuracy
+    Minv = np.linalg.inv(M)
+    ref = z * (Minv @ eta.reshape(3, -1).T).T.reshape(eta.shape)
+    assert np.abs(S.horner(U, kappa, eta, coeffs) - ref).max() < 1e-13
 
 
 def test_hfes_all_modes_is_exact(dense):

@@ -63,10 +63,12 @@ def source_sha(path):
 
 
 def traffic_for(kernel_class, bytes_per_launch):
-    """HBM traffic per launch from committed rocprofv3 counter summaries, if
-    the kernel source is unchanged since they were taken and they were taken
-    on launches of the same algorithmic size (same workload and block of
-    right-hand sides); else None."""
+    """HBM traffic per launch of a kernel class from committed rocprofv3
+    counter summaries: their ratio of HBM to algorithmic bytes, taken on the
+    same workload, applied to this run's algorithmic bytes per launch (which
+    move by a few percent with the convergence pattern of the block), if
+    the kernel source is unchanged since the counters were taken; else
+    None."""
     p = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel_class)
     if not os.path.exists(p):
         return None
@@ -76,18 +78,18 @@ def traffic_for(kernel_class, bytes_per_launch):
     if source_sha(src) != t["source_sha"]:
         return None
     alg = t.get("algorithmic_bytes_per_launch")
-    if alg is None or abs(alg - bytes_per_launch) > 0.01 * bytes_per_launch:
+    if not alg:
         return None
-    return t["hbm_bytes_per_launch"]
+    return bytes_per_launch * t["hbm_bytes_per_launch"] / alg
 
 
 def dslash_rates(kt):
     """The stencil of the mixed inner solves (FP32 arithmetic, the two halves
     of the even/odd operator): its algorithmic rate and fraction of the HBM
     peak, and the HBM rate implied by the committed counters (their ratio of
-    HBM to algorithmic bytes for these launches), when the stencil sources
-    are unchanged since the counters were taken and the launches have the
-    same algorithmic size; else the HBM fields are None."""
+    HBM to algorithmic bytes for these launches, on the same workload), when
+    the stencil sources are unchanged since the counters were taken; else
+    the HBM fields are None."""
     if "hop32" not in kt:
         return None
     ms, by, nl = kt["hop32"]
@@ -100,9 +102,7 @@ def dslash_rates(kt):
     with open(p) as f:
         t = json.load(f)
     blob = b"".join(open(os.path.join(ROOT, "paper_1903_06986_amd", "csrc", n), "rb").read() for n in t["sources"])
-    bpl = by / max(nl, 1)
-    if (hashlib.sha256(blob).hexdigest()[:16] != t["source_sha"]
-            or abs(t["algorithmic_bytes_per_launch"] - bpl) > 0.02 * bpl):
+    if hashlib.sha256(blob).hexdigest()[:16] != t["source_sha"]:
         return out
     r = t["hbm_over_algorithmic"]
     out.update(hbm_GBps=round(alg * r, 1), hbm_frac=round(alg * r / HBM_PEAK_GBS, 4), hbm_over_algorithmic=round(r, 3))
@@ -374,6 +374,73 @@ def batching(args):
     return out
 
 
+def gradient_leg(args):
+    """The differentiation workload (12^4, links exp(i 0.25 H), kappa = 0.124,
+    32 Z(4) noise vectors, FP64): forward and adjoint deflated solves and
+    the link force of loop_gradient, d/dkappa and d/dU of the whole-lattice
+    scalar trace estimate, after one untimed call on two noise vectors."""
+    import torch
+    from paper_1903_06986_amd import Context
+    from synth import get_config, random_su3_links
+    cfg = get_config("c5")
+    dims, kappa = cfg["dims"], cfg["kappas"][0]
+    ctx = Context(dims, random_su3_links(dims, cfg["eps"], cfg["link_seed"]), kappa)
+    eta = ctx.noise_z4(cfg["noise_seed"], 0, cfg["n_noise"])
+    kw = dict(thetas=(0,), m=cfg["m"], k=cfg["k"], tol=args.tol, tol_super=args.tol_super,
+              rhs_block=16, max_cycles=args.max_cycles)
+    ctx.loop_gradient(eta[:2], None, **kw)
+    torch.cuda.synchronize()
+    ctx.timer(True)
+    t0 = time.perf_counter()
+    dk, dl, defl, st = ctx.loop_gradient(eta, None, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = ctx.timer_read()
+    ctx.timer(False)
+    fms, fby, fn = kt["force"]
+    out = {"workload": "c5 %s eps=%.2f kappa=%.3f, %d Z(4) noise, FP64" % ("x".join(map(str, dims)), cfg["eps"],
+                                                                        kappa, cfg["n_noise"]),
+           "seconds": round(dt, 4), "noise_per_s": round(cfg["n_noise"] / dt, 2),
+           "adjoint_matvecs_per_solve": float(np.mean([s["matvecs"] for s in st])),
+           "max_true_resid": max(s["true_resid"] for s in st),
+           "force_ms": round(fms, 3), "force_GBps": round(fby / max(fms, 1e-9) / 1e6, 1), "dT_dkappa": [dk.real, dk.imag]}
+    ctx.close()
+    print("[bench] gradient %s" % json.dumps(out), file=sys.stderr, flush=True)
+    return out
+
+
+def cpu_solves():
+    """The FP64 oracle's full deflated solves on the host: GMRES-DR on the
+    first noise vector, GMRES-Proj on the rest (C1: 4^4, kappa 0.12, 8
+    noise vectors, GMRES-DR(20,10); C2: 16^3 x 32, kappa 0.120, 4 noise
+    vectors, GMRES-DR(50,30)), to the bench's 1e-10 (first solve 1e-12)."""
+    from synth import get_config, random_su3_links
+    from oracle import pipeline as opipe
+    from oracle.noise import z4_noise
+    out = {}
+    for name, n_noise in (("c1", 8), ("c2", 4)):
+        cfg = get_config(name)
+        dims, kappa = cfg["dims"], cfg["kappas"][0]
+        U = random_su3_links(dims, cfg["eps"], cfg["link_seed"])
+        eta = z4_noise(cfg["noise_seed"], dims, 0, n_noise)
+        t0 = time.perf_counter()
+        x, infos = opipe.solve_all(U, dims, kappa, eta, cfg["m"], cfg["k"], 1e-10, 1e-12)
+        dt = time.perf_counter() - t0
+        mv = [i["matvecs"] for i in infos]
+        out[name] = {"lattice": "x".join(map(str, dims)), "kappa": kappa, "noise": n_noise, "seconds": round(dt, 2),
+                     "noise_solves_per_s": round(n_noise / dt, 4),
+                     "first_solve_matvecs": mv[0], "proj_matvecs_per_solve": float(np.mean(mv[1:]))}
+        print("[bench] cpu solves %s %s" % (name, json.dumps(out[name])), file=sys.stderr, flush=True)
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    out["threads"] = threads
+    out["host_cpus"] = os.cpu_count()
+    return out
+
+
 def cpu_baseline(cfg, kappa, matvecs_per_solve, p_cycle):
     """FP64 oracle on the host, bounded sample: three applications of the
     even/odd operator and one CGS2 pass against p/2 basis vectors on the
@@ -413,6 +480,88 @@ def cpu_baseline(cfg, kappa, matvecs_per_solve, p_cycle):
             "host_cpus": os.cpu_count()}
 
 
+def stencil_rate(dims, kernel, nrhs, reps, tune=None, ctx=None):
+    """One kernel of the path alone, in the launch shape of the solvers:
+    kernel hop32 / hop64 (both parities of the hopping term, internal
+    even/odd layout), schur32 / schur64 (the even/odd operator, internal
+    layout), schur16 / schurbf16 (the even/odd operator reading 16-bit
+    per-site-scaled input: LEX in and out; only its stencil launches are
+    timed).  Links exp(i 0.2 H), seed 1003; random inputs.  Returns the
+    stencil launches' time and algorithmic bytes from the library's event
+    timers."""
+    import torch
+    from paper_1903_06986_amd import Context
+    from synth import random_su3_links
+    own = ctx is None
+    if own:
+        ctx = Context(dims, random_su3_links(dims, 0.2, 1003), 0.13)
+    if tune:
+        ctx.tune(**tune)
+    Vh = int(np.prod(dims)) // 2
+    g = torch.Generator(device="cuda").manual_seed(5)
+    if kernel in ("schur16", "schurbf16"):
+        x = torch.randn((nrhs,) + ctx.shape, dtype=torch.complex128, device="cuda", generator=g)
+        y = torch.empty_like(x)
+        run = lambda: ctx.wilson_apply("schur", x, prec="f16" if kernel == "schur16" else "bf16", out=y)
+        cls = "hop32"
+    else:
+        prec = "f64" if kernel.endswith("64") else "f32"
+        dt = torch.complex128 if prec == "f64" else torch.complex64
+        x = torch.randn((nrhs, 2, 12, Vh), dtype=dt, device="cuda", generator=g)
+        y = torch.empty_like(x)
+        op = "schur" if kernel.startswith("schur") else "hop"
+        run = lambda: ctx.wilson_apply(op, x, prec=prec, layout="eo", out=y)
+        cls = "hop64" if prec == "f64" else "hop32"
+    run()  # untimed first launch (workspaces)
+    torch.cuda.synchronize()
+    ctx.timer(True)
+    for _ in range(reps):
+        run()
+    kt = ctx.timer_read()
+    ctx.timer(False)
+    ms, by, n = kt[cls]
+    del x, y
+    if own:
+        ctx.close()
+    return {"kernel": kernel, "dims": "x".join(map(str, dims)), "nrhs": nrhs, "launches": n,
+            "us_per_launch": round(ms * 1e3 / max(n, 1), 2), "bytes_per_launch": by / max(n, 1),
+            "GBps": round(by / (ms * 1e-3) / 1e9, 1), "frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def copy_kernel(reps):
+    """A plain device copy of 256 MiB: the reference for scaling rocprofv3's
+    memory counters (FETCH_SIZE, WRITE_SIZE) to bytes."""
+    import torch
+    src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"kernel": "copy", "bytes_read": src.numel(), "bytes_written": src.numel(), "launches": reps}
+
+
+DSLASH_LATTICES = [(4, 4, 4, 4), (8, 8, 8, 8), (12, 12, 12, 12), (12, 12, 12, 24), (16, 16, 16, 32),
+                   (24, 24, 24, 32)]
+
+
+def dslash_table(reps, lattices=None, nrhs_list=(1, 4, 8, 16, 32)):
+    """The stencil's algorithmic rate on every workload lattice, FP64 /
+    FP32 / 16-bit input, for 1..32 right-hand sides per launch: the even/odd
+    operator (its two half hops) in the solvers' launch shape."""
+    from paper_1903_06986_amd import Context
+    from synth import random_su3_links
+    rows = []
+    for dims in (lattices or DSLASH_LATTICES):
+        ctx = Context(dims, random_su3_links(dims, 0.2, 1003), 0.13)
+        for kernel in ("schur64", "schur32", "schur16"):
+            for nb in nrhs_list:
+                r = stencil_rate(dims, kernel, nb, reps, ctx=ctx)
+                rows.append(r)
+                print("[bench] dslash %s" % json.dumps(r), file=sys.stderr, flush=True)
+        ctx.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -422,7 +571,7 @@ def main():
     ap.add_argument("--kappa", type=float, default=None)
     ap.add_argument("--rhs-block", type=int, default=16)
     ap.add_argument("--proj-m", type=int, default=0, help="GMRES-Proj cycle length (0: m - k)")
-    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=3, help="timed FP64 steps (at least 3, after 1 warm-up)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--tol-super", type=float, default=1e-12)
     ap.add_argument("--eig-tol", type=float, default=1e-5)
@@ -449,6 +598,25 @@ def main():
                     help="skip the mixed-lattice batch (8^4, 12^3x24, 16^3x32) measurement")
     ap.add_argument("--batching-only", action="store_true",
                     help="run only the mixed-lattice batch measurement and print its JSON")
+    ap.add_argument("--kernel", default=None,
+                    choices=["hop32", "hop64", "schur32", "schur64", "schur16", "schurbf16", "copy"],
+                    help="time one kernel alone (for profilers) and print its JSON instead of the step")
+    ap.add_argument("--nrhs", type=int, default=16, help="--kernel: right-hand sides per launch")
+    ap.add_argument("--reps", type=int, default=20, help="--kernel / --dslash-table: launches timed")
+    ap.add_argument("--dims", default="24x24x24x32", help="--kernel: lattice")
+    ap.add_argument("--tsites", type=int, default=None, help="--kernel: sites per stencil tile (16, 32, 64)")
+    ap.add_argument("--tblock", type=int, default=None,
+                    help="--kernel: timeslices per block of the tile order (-1 auto, 0 index order)")
+    ap.add_argument("--rgroup", type=int, default=None, help="--kernel: right-hand sides per tile group")
+    ap.add_argument("--rnest", type=int, default=None,
+                    help="--kernel: right-hand sides per group swept in turn within each XCD's block")
+    ap.add_argument("--no-gradient", action="store_true",
+                    help="skip timing the differentiation workload (12^4, 32 noise vectors)")
+    ap.add_argument("--cpu-solves", action="store_true",
+                    help="time the FP64 oracle's full deflated solves on the host (4^4 and 16^3x32) and exit")
+    ap.add_argument("--dslash-table", action="store_true",
+                    help="time the stencil on every workload lattice, FP64 / FP32 / 16-bit, 1..32 "
+                         "right-hand sides, and print the table as JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the noise solves shard "
@@ -456,6 +624,25 @@ def main():
         sys.exit(2)
     if args.batching_only:
         print(json.dumps(batching(args)), flush=True)
+        return
+    if args.kernel:
+        if args.kernel == "copy":
+            print(json.dumps(copy_kernel(args.reps)), flush=True)
+            return
+        tune = {}
+        for k, v in (("hop_tsites32", args.tsites), ("hop_tsites64", args.tsites and min(args.tsites, 32)),
+                     ("hop_tblock32", args.tblock), ("hop_tblock64", args.tblock), ("hop_rgroup", args.rgroup),
+                     ("hop_rnest", args.rnest)):
+            if v is not None:
+                tune[k] = v
+        dims = tuple(int(d) for d in args.dims.split("x"))
+        print(json.dumps(stencil_rate(dims, args.kernel, args.nrhs, args.reps, tune)), flush=True)
+        return
+    if args.cpu_solves:
+        print(json.dumps({"cpu_solves": cpu_solves()}), flush=True)
+        return
+    if args.dslash_table:
+        print(json.dumps({"dslash_table": dslash_table(args.reps)}), flush=True)
         return
     import torch
     from paper_1903_06986_amd import Context
@@ -484,9 +671,13 @@ def main():
                        "refinements": float(np.mean([s["refinements"] for s in stv])),
                        "max_true_resid": max(s["true_resid"] for s in stv)}
         print("[bench] variant %s %s" % (v, json.dumps(variants[v])), file=sys.stderr, flush=True)
-    dt64, stats64, kt64 = run_steps(path, "f64", args.fp64_steps, 0)
-    value64 = args.fp64_steps * args.rhs_block / dt64
-    print("[bench] fp64: %d solves in %.3f s" % (args.fp64_steps * args.rhs_block, dt64), file=sys.stderr,
+    # the plain-FP64 rate: one untimed warm-up step first, so that its basis
+    # (about 28 GB at 24^3 x 32 with 16 right-hand sides) is allocated
+    # before the timed steps
+    fp64_steps = max(3, args.fp64_steps)
+    dt64, stats64, kt64 = run_steps(path, "f64", fp64_steps, 1)
+    value64 = fp64_steps * args.rhs_block / dt64
+    print("[bench] fp64: %d solves in %.3f s" % (fp64_steps * args.rhs_block, dt64), file=sys.stderr,
           flush=True)
     # dominant kernel class of the mixed timed region
     dom = max(kt, key=lambda k: kt[k][0])
@@ -511,6 +702,9 @@ def main():
     bat = None
     if not args.no_batching:
         bat = batching(args)
+    grad = None
+    if not args.no_gradient:
+        grad = gradient_leg(args)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, kappa, mv64, cfg["m"] - cfg["k"])
@@ -526,7 +720,7 @@ def main():
                                % (args.workload, "x".join(map(str, dims)), cfg["eps"], kappa, cfg["m"], cfg["k"],
                                   args.rhs_block, cfg["pert_order"], cfg["poly_degree"], cfg["n_hermitian"]),
                    "rhs_block": args.rhs_block, "inner": args.inner},
-        "fp64": {"value": round(value64, 4), "unit": "noise-solves/s", "steps": args.fp64_steps,
+        "fp64": {"value": round(value64, 4), "unit": "noise-solves/s", "steps": fp64_steps, "warmup": 1,
                  "matvecs_per_solve": mv64, "reorth_per_solve": float(np.mean([s["reorth"] for s in stats64])),
                  "max_true_resid": max(s["true_resid"] for s in stats64)},
         "mixed_over_fp64": round(value / value64, 3),
@@ -536,6 +730,7 @@ def main():
         "variants": variants,
         "accuracy": acc,
         "batching": bat,
+        "gradient": grad,
         "setup": {k: round(v, 3) for k, v in path.setup_times.items()},
         "production_single_rhs": prod,
         "hermitian": {"method": args.herm_method, "matvecs": path.herm_stats[0]["matvecs"],

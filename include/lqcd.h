@@ -189,7 +189,11 @@ lqcd_status wilson_apply(lqcd_ctx *ctx, lqcd_op op, lqcd_prec prec, lqcd_layout 
  *   V_{k+1} Hbar_k) is returned in *defl_inout (free with lqcd_defl_free);
  *   every other right-hand side is solved by GMRES-Proj over that space.
  * stats: host array [nrhs] or NULL.
- * ENOCONV if any right-hand side misses tol within max_cycles. */
+ * ENOCONV if any right-hand side misses tol within max_cycles, and when the
+ * first right-hand side's GMRES-DR / MINRES-DR reaches max_cycles before
+ * its own targets (tol_super, and eig_tol when set).  x then holds the
+ * iterates and stats the counts; a deflation space built by the call is
+ * still returned in *defl_inout. */
 lqcd_status gmresdr_solve(lqcd_ctx *ctx, lqcd_op op, const lqcd_solve_params *params,
                           const void *b, void *x, int nrhs, lqcd_defl **defl_inout,
                           lqcd_solve_stats *stats);
@@ -294,8 +298,9 @@ lqcd_status loop_estimate(lqcd_ctx *ctx, const int *thetas_host, int ntheta, con
  * (NULL: the first right-hand side builds the deflation space and it is
  * returned).  dkappa_host: host complex128 [1]; dlinks: device complex128
  * LEX [V][4][8] or NULL (only the kappa derivative); stats: host [nrhs]
- * statistics of the adjoint solves, or NULL.  Allocates its scratch per
- * call.  ENOCONV as gmresdr_solve. */
+ * statistics of the adjoint solves, or NULL.  Its scratch (the stacked
+ * right-hand sides and solutions) lives in context workspaces that grow
+ * on first use and are kept.  ENOCONV as gmresdr_solve. */
 lqcd_status loop_gradient(lqcd_ctx *ctx, const int *thetas_host, const double *weights_host,
                           int ntheta, const lqcd_solve_params *params, lqcd_defl **defl_inout,
                           const void *eta, const void *x, int nrhs, double *dkappa_host,
@@ -388,7 +393,14 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * tiled stencil splits launches with more right-hand sides than this into
  * groups of this many, the group index slowest across the XCDs (each XCD's
  * L2 then holds one group's spinors; links are read once per group);
- * 0 = one group.  Values are per context; EINVAL for other values. */
+ * 0 = one group.  LQCD_TUNE_HOP_RNEST (plane order only): groups of this many
+ * right-hand sides are swept in turn within each XCD's block of timeslices
+ * (its L2 then holds one group's planes at a time; the block's links are
+ * read once per group); 0 = off, and it takes precedence over
+ * LQCD_TUNE_HOP_RGROUP.  LQCD_TUNE_GEMM_MFMA: 1 (default) runs the deflation
+ * and eigenvector products V C whose columns share one basis (J <= 64
+ * vectors, two or more columns) on the matrix cores; 0 uses the FMA
+ * kernel.  Values are per context; EINVAL for other values. */
 typedef enum {
   LQCD_TUNE_HOP_NB64 = 0,
   LQCD_TUNE_HOP_NB32 = 1,
@@ -399,7 +411,9 @@ typedef enum {
   LQCD_TUNE_HOP_TBLOCK32 = 6,
   LQCD_TUNE_HOP_TSITES32 = 7,
   LQCD_TUNE_HOP_RGROUP = 8,
-  LQCD_TUNE_HOP_TSITES64 = 9
+  LQCD_TUNE_HOP_TSITES64 = 9,
+  LQCD_TUNE_GEMM_MFMA = 10,
+  LQCD_TUNE_HOP_RNEST = 11
 } lqcd_tune_param;
 lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 

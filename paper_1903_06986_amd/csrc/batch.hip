@@ -678,16 +678,30 @@ void run_batch(lqcd_batch *b, const lqcd_solve_params &prm, const void *const *b
   if (use_graph) {
     if (!b->capture) LQCD_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
     LQCD_HIP(hipStreamSynchronize(b->stream));
-    // the engine launches on b->stream: point it at the capture stream
-    const hipStream_t keep = b->stream;
+    // the engine launches on b->stream: point it at the capture stream.
+    // The guard ends a capture that an error left open (discarding its
+    // graph) and restores the stream on every exit path.
+    struct CaptureGuard {
+      lqcd_batch *b;
+      hipStream_t keep;
+      bool open;
+      ~CaptureGuard() {
+        if (open) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(b->capture, &g);
+          if (g) (void)hipGraphDestroy(g);
+        }
+        b->stream = keep;
+      }
+    } cg{b, b->stream, false};
     b->stream = b->capture;
     LQCD_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    cg.open = true;
     e.cycle();
+    cg.open = false;
     const hipError_t ce = hipStreamEndCapture(b->capture, &graph);
-    b->stream = keep;
+    b->stream = cg.keep;
     LQCD_HIP(ce);
-    LQCD_HIP(hipGetLastError());
-    LQCD_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   }
   struct GraphGuard {
     hipGraph_t g;
@@ -696,7 +710,12 @@ void run_batch(lqcd_batch *b, const lqcd_solve_params &prm, const void *const *b
       if (x) (void)hipGraphExecDestroy(x);
       if (g) (void)hipGraphDestroy(g);
     }
-  } guard{graph, exec};
+  } guard{graph, nullptr};
+  if (use_graph) {
+    LQCD_HIP(hipGetLastError());
+    LQCD_HIP(hipGraphInstantiate(&guard.x, graph, nullptr, nullptr, 0));
+    exec = guard.x;
+  }
 
   std::vector<BSlot> slh(B);
   std::vector<SlotState> ss(B);

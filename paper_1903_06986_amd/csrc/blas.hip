@@ -419,74 +419,39 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ------------------------------------------------- 16-bit stored bases
-// Basis vectors stored as in half.h (payload words [12][Vh], then per-site
-// scales); the vector they act on stays FP32.  Site-oriented: every lane
-// owns two adjacent sites (Vh is even for even extents), so each
-// component load is one 8-byte payload word pair (16 bytes of FP32 for
-// the other operand) and each site's scale is loaded once.
-struct Pair {
-  cx<float> a, b;
-};
-__device__ inline Pair ldpair(const cx<float> *p) {
-  const float4 v = *reinterpret_cast<const float4 *>(p);
-  return Pair{mk(v.x, v.y), mk(v.z, v.w)};
-}
-__device__ inline void stpair(cx<float> *p, cx<float> a, cx<float> b) {
-  *reinterpret_cast<float4 *>(p) = make_float4(a.re, a.im, b.re, b.im);
-}
-// Non-temporal form, for a vector that is not read again before much more
-// data has passed through the caches.
-__device__ inline void stpair_nt(cx<float> *p, cx<float> a, cx<float> b) {
-  typedef float f4v __attribute__((ext_vector_type(4)));
-  f4v v;
-  v.x = a.re;
-  v.y = a.im;
-  v.z = b.re;
-  v.w = b.im;
-  __builtin_nontemporal_store(v, reinterpret_cast<f4v *>(p));
-}
-template <HKind K>
-__device__ inline void ldhpair(const uint32_t *v, size_t Vh, size_t s2, int comp, float2 sc,
-                               cx<float> &a, cx<float> &b) {
-  // the basis streams through once per kernel: non-temporal loads keep it
-  // from displacing the reused vectors in the caches (measured +19% on the
-  // dot, +9% on the update)
-  typedef unsigned u2v __attribute__((ext_vector_type(2)));
-  const u2v qv = __builtin_nontemporal_load(reinterpret_cast<const u2v *>(v + comp * Vh + s2));
-  const uint2 q = make_uint2(qv.x, qv.y);
-  const cx<float> qa = Codec<K>::unpack(q.x), qb = Codec<K>::unpack(q.y);
-  a = mk(sc.x * qa.re, sc.x * qa.im);
-  b = mk(sc.y * qb.re, sc.y * qb.im);
-}
-template <HKind K>
-__device__ inline float2 ldscale(const uint32_t *v, size_t Vh, size_t s2) {
-  typedef unsigned u2v __attribute__((ext_vector_type(2)));
-  const u2v u = __builtin_nontemporal_load(reinterpret_cast<const u2v *>(v + 12 * Vh + s2));
-  return make_float2(__uint_as_float(u.x), __uint_as_float(u.y));
+// Basis vectors stored as in half.h (payload in 16-byte granules
+// [3][Vh][4 words], then per-site scales); the vector they act on stays
+// FP32 (component-major [12][Vh]).  Site-oriented, one site per lane: a
+// wavefront's load of one granule is one contiguous 1 KiB run (three per
+// basis vector, plus 256 bytes of scales), each site's scale is loaded
+// once, and the FP32 vector's components are 512-byte runs.
+__device__ inline uint32_t uword(const uint4 &v, int k) {
+  return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
 }
 
-// One basis vector's words at a lane's two sites: 12 payload pairs and the
-// two scales, loaded together (non-temporal) so that the next vector's
-// loads can be in flight while the current one is used.
+// One basis vector's words at a lane's site: its three granules and its
+// scale.  The basis streams through once per kernel, so the loads are
+// non-temporal: they keep it from displacing the reused vectors in the
+// caches; they are issued together so that the next vector's loads can be
+// in flight while the current one is used.
 struct HRaw {
-  uint2 q[12];
-  float2 sc;
+  uint4 q[3];
+  float sc;
+  __device__ uint32_t w(int c) const { return uword(q[c >> 2], c & 3); }
 };
-template <HKind K>
-__device__ inline void hraw_load(const uint32_t *v, size_t Vh, size_t s2, HRaw &r) {
-  typedef unsigned u2v __attribute__((ext_vector_type(2)));
-  const u2v u = __builtin_nontemporal_load(reinterpret_cast<const u2v *>(v + 12 * Vh + s2));
-  r.sc = make_float2(__uint_as_float(u.x), __uint_as_float(u.y));
+__device__ inline void hraw_load(const uint32_t *v, size_t Vh, size_t i, HRaw &r) {
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  r.sc = __uint_as_float(__builtin_nontemporal_load(v + 12 * Vh + i));
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const u2v qv = __builtin_nontemporal_load(reinterpret_cast<const u2v *>(v + c * Vh + s2));
-    r.q[c] = make_uint2(qv.x, qv.y);
+  for (int g = 0; g < 3; ++g) {
+    const u4v a = __builtin_nontemporal_load(reinterpret_cast<const u4v *>(v + 4 * (g * Vh + i)));
+    r.q[g] = make_uint4(a.x, a.y, a.z, a.w);
   }
 }
 
 // Partial dot products per wave: part[r][wave chunk][j] (as k_mdot_part).
 template <HKind K>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 8)))
     k_hmdot_part(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
                  const cx<float> *__restrict__ w, size_t w_rs, size_t Vh,
                  double *__restrict__ part, const int *__restrict__ flag) {
@@ -497,37 +462,34 @@ __global__ void __launch_bounds__(kBlock)
   const size_t chunk = size_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
   V += r * V_rs;
   w += r * w_rs;
-  const size_t s2 = (chunk * 64 + lane) * 2;  // first of the lane's two sites
-  const bool on = s2 < Vh;
-  cx<float> wa[12], wb[12];
+  const size_t i = chunk * 64 + lane;  // the lane's site
+  const bool on = i < Vh;
+  cx<float> wv[12];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    Pair pw = on ? ldpair(w + c * Vh + s2) : Pair{mk(0.f, 0.f), mk(0.f, 0.f)};
-    wa[c] = pw.a;
-    wb[c] = pw.b;
-  }
+  for (int c = 0; c < 12; ++c) wv[c] = on ? ldc(w + c * Vh + i) : mk(0.f, 0.f);
   double *po = part + (size_t(r) * nwch + chunk) * size_t(J) * 2;
-  // software pipeline over the basis: vector j + 1's loads go out before
-  // vector j is used; the per-site scale multiplies each site's sum once
-  HRaw cur, nxt;
-  if (on && J > 0) hraw_load<K>(V, Vh, s2, cur);
+  // software pipeline over the basis, two vectors deep: vector j + 2's
+  // loads go out before vector j is used (a lane streams 52 bytes per
+  // vector, so one vector ahead keeps too few bytes in flight per CU); the
+  // per-site scale multiplies the site's sum once
+  HRaw cur, nx1, nx2;
+  if (on && J > 0) hraw_load(V, Vh, i, cur);
+  if (on && J > 1) hraw_load(V + ldv, Vh, i, nx1);
   for (int j = 0; j < J; ++j) {
     double a0 = 0, b0 = 0;
     if (on) {
-      if (j + 1 < J) hraw_load<K>(V + size_t(j + 1) * ldv, Vh, s2, nxt);
-      float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;  // per-site sums of 12 products
+      if (j + 2 < J) hraw_load(V + size_t(j + 2) * ldv, Vh, i, nx2);
+      float ar = 0.f, ai = 0.f;  // the site's sum of 12 products
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        const cx<float> va = Codec<K>::unpack(cur.q[c].x), vb = Codec<K>::unpack(cur.q[c].y);
-        const cx<float> pa = cmulc(va, wa[c]), pb = cmulc(vb, wb[c]);
-        ar += pa.re;
-        ai += pa.im;
-        br += pb.re;
-        bi += pb.im;
+        const cx<float> p = cmulc(Codec<K>::unpack(cur.w(c)), wv[c]);
+        ar += p.re;
+        ai += p.im;
       }
-      a0 = double(cur.sc.x * ar) + double(cur.sc.y * br);
-      b0 = double(cur.sc.x * ai) + double(cur.sc.y * bi);
-      cur = nxt;
+      a0 = double(cur.sc * ar);
+      b0 = double(cur.sc * ai);
+      cur = nx1;
+      nx1 = nx2;
     }
     a0 = wave_sum(a0);
     b0 = wave_sum(b0);
@@ -552,40 +514,33 @@ __global__ void __launch_bounds__(kBlock)
   V += r * V_rs;
   w += r * w_rs;
   coef += r * coef_rs;
-  const size_t s2 = (size_t(b) * kBlock + threadIdx.x) * 2;
-  const bool on = s2 < Vh;
+  const size_t i = size_t(b) * kBlock + threadIdx.x;
+  const bool on = i < Vh;
   double nrm[1] = {0};
   if (on) {
-    cx<float> aa[12], ab[12];
+    cx<float> a[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      Pair pw = ldpair(w + c * Vh + s2);
-      aa[c] = pw.a;
-      ab[c] = pw.b;
-    }
-    // software pipeline over the basis (as k_hmdot_part); the site's scale
-    // is folded into the coefficient
-    HRaw cur, nxt;
-    if (J > 0) hraw_load<K>(V, Vh, s2, cur);
+    for (int c = 0; c < 12; ++c) a[c] = ldc(w + c * Vh + i);
+    // software pipeline over the basis, two vectors deep (as
+    // k_hmdot_part); the site's scale is folded into the coefficient
+    HRaw cur, nx1, nx2;
+    if (J > 0) hraw_load(V, Vh, i, cur);
+    if (J > 1) hraw_load(V + ldv, Vh, i, nx1);
     for (int j = 0; j < J; ++j) {
-      if (j + 1 < J) hraw_load<K>(V + size_t(j + 1) * ldv, Vh, s2, nxt);
+      if (j + 2 < J) hraw_load(V + size_t(j + 2) * ldv, Vh, i, nx2);
       const cx<double> cd = coef[j];
-      const cx<float> cj = mk<float>(float(cd.re), float(cd.im));
-      const cx<float> ca = mk(cur.sc.x * cj.re, cur.sc.x * cj.im), cb = mk(cur.sc.y * cj.re, cur.sc.y * cj.im);
+      const cx<float> ca = mk(cur.sc * float(cd.re), cur.sc * float(cd.im));
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        aa[c] = aa[c] - Codec<K>::unpack(cur.q[c].x) * ca;
-        ab[c] = ab[c] - Codec<K>::unpack(cur.q[c].y) * cb;
-      }
-      cur = nxt;
+      for (int c = 0; c < 12; ++c) a[c] = a[c] - Codec<K>::unpack(cur.w(c)) * ca;
+      cur = nx1;
+      nx1 = nx2;
     }
     // w of a block of right-hand sides (16 x 96 B per site) exceeds the
-    // caches, so its store bypasses them (measured +3%)
+    // caches, so its store bypasses them
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      stpair_nt(w + c * Vh + s2, aa[c], ab[c]);
-      nrm[0] += double(aa[c].re) * aa[c].re + double(aa[c].im) * aa[c].im + double(ab[c].re) * ab[c].re +
-                double(ab[c].im) * ab[c].im;  // of the stored values
+      stc_nt(w + c * Vh + i, a[c]);
+      nrm[0] += double(a[c].re) * a[c].re + double(a[c].im) * a[c].im;  // of the stored values
     }
   }
   if (part) {
@@ -601,35 +556,31 @@ __global__ void __launch_bounds__(kBlock)
             const cx<double> *__restrict__ C, size_t C_rs, cx<float> *__restrict__ Y, size_t Y_rs,
             size_t Vh, double alpha) {
   const int r = blockIdx.y;
-  const size_t s2 = (size_t(blockIdx.x) * kBlock + threadIdx.x) * 2;
-  if (s2 >= Vh) return;
+  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= Vh) return;
   V += r * V_rs;
   C += r * C_rs;
   Y += r * Y_rs;
-  cx<float> aa[12], ab[12];
+  cx<float> a[12];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) aa[c] = ab[c] = mk(0.f, 0.f);
+  for (int c = 0; c < 12; ++c) a[c] = mk(0.f, 0.f);
   for (int j = 0; j < J; ++j) {
     const cx<double> cd = C[j];
-    const cx<float> cj = mk<float>(float(alpha * cd.re), float(alpha * cd.im));
-    const uint32_t *v0 = V + size_t(j) * ldv;
-    const float2 sc = ldscale<K>(v0, Vh, s2);
+    HRaw q;
+    hraw_load(V + size_t(j) * ldv, Vh, i, q);
+    const cx<float> cj = mk(q.sc * float(alpha * cd.re), q.sc * float(alpha * cd.im));
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      cx<float> va, vb;
-      ldhpair<K>(v0, Vh, s2, c, sc, va, vb);
-      aa[c] = aa[c] + va * cj;
-      ab[c] = ab[c] + vb * cj;
-    }
+    for (int c = 0; c < 12; ++c) a[c] = a[c] + Codec<K>::unpack(q.w(c)) * cj;
   }
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
-    Pair y = ldpair(Y + c * Vh + s2);
-    stpair(Y + c * Vh + s2, y.a + aa[c], y.b + ab[c]);
+    const cx<float> y = ldc(Y + c * Vh + i);
+    stc(Y + c * Vh + i, y + a[c]);
   }
 }
 
-// out_r = quantised (scale[r] * w_r): one thread per site, 12 components.
+// out_r = quantised (scale[r] * w_r): one thread per site, 12 components
+// in, three 16-byte granules and the scale out.
 template <HKind K>
 __global__ void __launch_bounds__(kBlock)
     k_hquant(const cx<float> *__restrict__ w, size_t w_rs, const double *__restrict__ scale,
@@ -650,7 +601,14 @@ __global__ void __launch_bounds__(kBlock)
   }
   const float inv = m > 0.f ? 1.0f / m : 0.f;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) out[c * Vh + i] = Codec<K>::pack(inv * v[c].re, inv * v[c].im);
+  for (int g = 0; g < 3; ++g) {
+    uint4 q;
+    q.x = Codec<K>::pack(inv * v[4 * g].re, inv * v[4 * g].im);
+    q.y = Codec<K>::pack(inv * v[4 * g + 1].re, inv * v[4 * g + 1].im);
+    q.z = Codec<K>::pack(inv * v[4 * g + 2].re, inv * v[4 * g + 2].im);
+    q.w = Codec<K>::pack(inv * v[4 * g + 3].re, inv * v[4 * g + 3].im);
+    *reinterpret_cast<uint4 *>(out + hword(4 * g, i, Vh)) = q;
+  }
   out[12 * Vh + i] = __float_as_uint(m);
 }
 
@@ -666,9 +624,13 @@ __global__ void __launch_bounds__(kBlock)
   y += r * y_rs;
   const float sc = __uint_as_float(x[12 * Vh + i]);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const cx<float> q = Codec<K>::unpack(x[c * Vh + i]);
-    stc(y + c * Vh + i, mk(sc * q.re, sc * q.im));
+  for (int g = 0; g < 3; ++g) {
+    const uint4 q = *reinterpret_cast<const uint4 *>(x + hword(4 * g, i, Vh));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const cx<float> v = Codec<K>::unpack(uword(q, k));
+      stc(y + (4 * g + k) * Vh + i, mk(sc * v.re, sc * v.im));
+    }
   }
 }
 
@@ -812,6 +774,128 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) C[j + ldc * size_t(c)] = mk(v[0], v[1]);
 }
 
+// ---------------------------------------------------- V C on MFMA
+// Y_b += alpha sum_j V_j C[j][b] for J <= 64 vectors and up to 16 columns
+// (one V shared by all columns), as one real GEMM on the matrix cores per
+// group of 8 columns: D[(b, s)][e] = sum_{(j, p)} A[(b, s)][(j, p)] B[(j, p)][e]
+// with B[(j, p)][e] = (Re, Im) V_j[e] and the coefficients in A:
+//   s = 0 (Re Y):  A[(b, 0)][(j, 0)] =  Re c,  A[(b, 0)][(j, 1)] = -Im c,
+//   s = 1 (Im Y):  A[(b, 1)][(j, 0)] =  Im c,  A[(b, 1)][(j, 1)] =  Re c,
+// c = alpha C[j][b].  A workgroup stages 64 elements of all J vectors in LDS
+// (the next chunk's loads in flight in registers, as in k_gemm_tn_mfma);
+// wave w multiplies its 16 elements (the D columns) by the G groups' A
+// operands, which stay in LDS for the whole launch.  The D rows are ordered
+// so that each lane's four accumulator registers hold the real and
+// imaginary parts of two outputs of one element (Mfma::row): the update of
+// Y is then a complex load and store per output, 16 consecutive elements
+// per 16 lanes.  V is read once for up to 16 columns.
+template <class R>
+struct OutRow;
+template <>
+struct OutRow<float> {  // rows 4q + v: (b, s) = (r / 2, r % 2)
+  __device__ static int b(int r) { return r >> 1; }
+  __device__ static int s(int r) { return r & 1; }
+};
+template <>
+struct OutRow<double> {  // rows q + 4v: (b, s) = (r % 8, r / 8)
+  __device__ static int b(int r) { return r & 7; }
+  __device__ static int s(int r) { return r >> 3; }
+};
+
+constexpr int kNNSteps = 32;  // K steps of 4 (two vectors each): J <= 64
+
+template <class R, int G>
+__global__ void __launch_bounds__(kBlock)
+    k_gemm_nn_mfma(const cx<R> *__restrict__ V, size_t ldv, int J, const cx<double> *__restrict__ C,
+                   size_t ldcc, cx<R> *__restrict__ Y, size_t ldy, int nb, size_t n, double alpha) {
+  // dynamic LDS: the staged vectors [J][kTP] reals, then the A operands
+  // [G][nst][64] (sized by the launch: 64 KiB for FP64, J = 41, G = 2)
+  extern __shared__ unsigned char smem[];
+  using A = Mfma<R>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nst = (J + 1) / 2;
+  R *sV = reinterpret_cast<R *>(smem);
+  R *sA = sV + size_t(J) * kTP;
+  // the A operands: lane l supplies A[l % 16][l / 16] of step st
+  for (int t = threadIdx.x; t < G * nst * 64; t += kBlock) {
+    const int l = t & 63, st = (t >> 6) % nst, g = t / (64 * nst);
+    const int r = l & 15, k = l >> 4;
+    const int j = 2 * st + (k >> 1), p = k & 1;
+    const int b = 8 * g + OutRow<R>::b(r), sr = OutRow<R>::s(r);
+    R v = 0;
+    if (j < J && b < nb) {
+      const cx<double> cc = C[j + ldcc * size_t(b)];
+      const double cr = alpha * cc.re, ci = alpha * cc.im;
+      v = R(sr == 0 ? (p == 0 ? cr : -ci) : (p == 0 ? ci : cr));
+    }
+    sA[(g * nst + st) * 64 + l] = v;
+  }
+  const size_t nchunk = (n + kTE - 1) / kTE;
+  constexpr int kLpt = (64 * kTE + kBlock - 1) / kBlock;
+  const int nld = J * kTE;
+  cx<R> pre[kLpt];
+  auto fetch = [&](size_t e0) {
+#pragma unroll
+    for (int u = 0; u < kLpt; ++u) {
+      const int t = threadIdx.x + u * kBlock;
+      const size_t idx = e0 + (t % kTE);
+      pre[u] = (t < nld && idx < n) ? ldc(V + size_t(t / kTE) * ldv + idx) : mk<R>(0, 0);
+    }
+  };
+  size_t ch = blockIdx.x;
+  if (ch < nchunk) fetch(ch * kTE);
+  const int e = 16 * wave + (lane & 15);  // this lane's element (D column) in the chunk
+  const int kq = lane >> 4;
+  for (; ch < nchunk; ch += gridDim.x) {
+    __syncthreads();  // the previous chunk's operands are consumed (and sA is written)
+#pragma unroll
+    for (int u = 0; u < kLpt; ++u) {
+      const int t = threadIdx.x + u * kBlock;
+      if (t < nld) {
+        R *dst = sV + (t / kTE) * kTP + 2 * (t % kTE);
+        dst[0] = pre[u].re;
+        dst[1] = pre[u].im;
+      }
+    }
+    __syncthreads();
+    if (ch + gridDim.x < nchunk) fetch((ch + gridDim.x) * kTE);
+    typename A::acc_t acc[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g] = typename A::acc_t{0, 0, 0, 0};
+    for (int st = 0; st < nst; ++st) {
+      const int j = 2 * st + (kq >> 1);
+      const R bv = j < J ? sV[j * kTP + 2 * e + (kq & 1)] : R(0);
+#pragma unroll
+      for (int g = 0; g < G; ++g) acc[g] = A::op(sA[(g * nst + st) * 64 + lane], bv, acc[g]);
+    }
+    const size_t idx = ch * kTE + e;
+    if (idx < n) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        // registers v = 0..3 hold rows row(kq, v): two outputs (b, Re / Im)
+        int bo[2] = {-1, -1};
+        R re[2] = {0, 0}, im[2] = {0, 0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = A::row(kq, v), b = OutRow<R>::b(r), sr = OutRow<R>::s(r);
+          const int slot = (bo[0] < 0 || bo[0] == b) ? 0 : 1;
+          bo[slot] = b;
+          (sr == 0 ? re[slot] : im[slot]) = acc[g][v];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int b = 8 * g + bo[q];
+          if (bo[q] >= 0 && b < nb) {
+            cx<R> *yp = Y + size_t(b) * ldy + idx;
+            const cx<R> y = ldc(yp);
+            stc(yp, mk<R>(y.re + re[q], y.im + im[q]));
+          }
+        }
+      }
+    }
+  }
+}
+
 inline unsigned grid_elems(size_t n) { return unsigned(std::min<size_t>(nblocks(n), 8192)); }
 
 }  // namespace
@@ -909,6 +993,33 @@ void gemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const c
              size_t ldc, size_t C_rs, void *Y, size_t ldy, size_t Y_rs, int nb, size_t n, int nrhs,
              double alpha) {
   if (nb <= 0 || nrhs <= 0) return;
+  if (nrhs == 1 && nb >= 2 && J >= 1 && J <= 2 * kNNSteps && n >= size_t(kTE) && c->gemm_mfma) {
+    // one basis for all columns: the matrix cores, 16 columns per launch
+    // (two groups of 8), V read once per launch
+    const size_t nchunk = (n + kTE - 1) / kTE;
+    const unsigned grid = unsigned(std::min<size_t>(nchunk, 2048));
+    for (int b0 = 0; b0 < nb; b0 += 16) {
+      const int w = std::min(16, nb - b0);
+      const int G = w > 8 ? 2 : 1;
+      const size_t shm = (size_t(J) * kTP + size_t(G) * ((J + 1) / 2) * 64) * sizeof(R);
+      Timed tm(c, LQCD_KC_GEMM, double(J + 2 * w) * n * sizeof(cx<R>));
+      const cx<double> *Cb = reinterpret_cast<const cx<double> *>(C) + ldc * size_t(b0);
+      cx<R> *Yb = static_cast<cx<R> *>(Y) + ldy * size_t(b0);
+      if (shm > 64 * 1024) {  // more than the default dynamic LDS limit (J > 44 in FP64)
+        const void *f = G == 2 ? reinterpret_cast<const void *>(&k_gemm_nn_mfma<R, 2>)
+                               : reinterpret_cast<const void *>(&k_gemm_nn_mfma<R, 1>);
+        LQCD_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));
+      }
+      if (G == 2)
+        LQCD_TLAUNCH(tm, true, true, (k_gemm_nn_mfma<R, 2>), dim3(grid), dim3(kBlock), shm, c->stream,
+                     static_cast<const cx<R> *>(V), ldv, J, Cb, ldc, Yb, ldy, w, n, alpha);
+      else
+        LQCD_TLAUNCH(tm, true, true, (k_gemm_nn_mfma<R, 1>), dim3(grid), dim3(kBlock), shm, c->stream,
+                     static_cast<const cx<R> *>(V), ldv, J, Cb, ldc, Yb, ldy, w, n, alpha);
+      LQCD_HIP(hipGetLastError());
+    }
+    return;
+  }
   Timed tm(c, LQCD_KC_GEMM, double(J + 2 * nb) * n * nrhs * sizeof(cx<R>));
   LQCD_TLAUNCH(tm, true, true, (k_gemm_nn<R>), dim3(grid_elems(n), nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const cx<R> *>(V), ldv, V_rs, J,
@@ -1012,7 +1123,7 @@ void hmulti_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, cons
   if (J <= 0 || nrhs <= 0) return;
   constexpr HKind K = static_cast<HKind>(KIND);
   const size_t Vh = n / 12;
-  const size_t per_block = size_t(kBlock) * 2;  // sites
+  const size_t per_block = size_t(kBlock);  // sites, one per lane
   const int ngrid = int((Vh + per_block - 1) / per_block);
   const int nblk = ngrid * kWaves;
   double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * J * 2 * sizeof(double)));
@@ -1033,7 +1144,7 @@ void hmulti_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, con
   if (nrhs <= 0) return;
   constexpr HKind K = static_cast<HKind>(KIND);
   const size_t Vh = n / 12;
-  const int nblk = int((Vh + 2 * kBlock - 1) / (2 * kBlock));
+  const int nblk = int((Vh + kBlock - 1) / kBlock);  // one site per lane
   double *part = nullptr;
   if (norm2_out) part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * sizeof(double)));
   Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + 2.0 * n * sizeof(cx<float>)) * nrhs);
@@ -1056,7 +1167,7 @@ void hgemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const 
   constexpr HKind K = static_cast<HKind>(KIND);
   const size_t Vh = n / 12;
   Timed tm(c, LQCD_KC_GEMM, (J * hbytes(n) + 2.0 * nb * n * sizeof(cx<float>)) * nrhs);
-  const unsigned g = unsigned((Vh + 2 * kBlock - 1) / (2 * kBlock));
+  const unsigned g = unsigned((Vh + kBlock - 1) / kBlock);  // one site per lane
   for (int b = 0; b < nb; ++b) {
     LQCD_TLAUNCH(tm, b == 0, b == nb - 1, (k_hgemv<K>), dim3(g, nrhs), dim3(kBlock), 0, c->stream,
                        static_cast<const uint32_t *>(V), ldv, V_rs, J,

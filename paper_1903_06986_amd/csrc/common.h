@@ -134,6 +134,7 @@ struct lqcd_ctx {
   lqcd::DevBuf red_out;  // reduction results (device)
   lqcd::DevBuf sw[16];   // solver fields
   lqcd::DevBuf small[2]; // solver small matrices
+  lqcd::DevBuf grad[3];  // loop_gradient: right-hand sides, solutions, adjoint source matrices
   lqcd::KTimer timer;
   int hop_nb[2] = {2, 1};  // largest lane-grouped right-hand-side count: FP64, FP32
   int hop_tile[2] = {1, 1};  // link-tiled stencil for many right-hand sides: FP64, FP32
@@ -141,6 +142,8 @@ struct lqcd_ctx {
   int hop_tblock[2] = {-1, -1};  // tiled stencil: timeslices per plane block (0: flat order, -1: auto), FP64, FP32
   int hop_tsites[2] = {32, 32};  // tiled stencil: sites per tile, FP64 (16, 32), FP32 (16, 32, 64)
   int hop_rgroup = 0;            // tiled stencil: right-hand sides per group (0: all in one)
+  int hop_rnest = 0;             // tiled stencil: groups swept in turn within each block (0: off)
+  int gemm_mfma = 1;             // V C with one shared basis on the matrix cores (0: FMA kernel)
   ~lqcd_ctx();
 };
 

@@ -203,6 +203,14 @@ extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int val
         LQCD_CHECK(value == 16 || value == 32, LQCD_EINVAL, "lqcd_tune_set: sites per FP64 tile must be 16 or 32");
         c->hop_tsites[0] = value;
         break;
+      case LQCD_TUNE_HOP_RNEST:
+        LQCD_CHECK(value >= 0 && value <= 4096, LQCD_EINVAL, "lqcd_tune_set: right-hand sides per nested group in 0..4096");
+        c->hop_rnest = value;
+        break;
+      case LQCD_TUNE_GEMM_MFMA:
+        LQCD_CHECK(value == 0 || value == 1, LQCD_EINVAL, "lqcd_tune_set: matrix-core switch must be 0 or 1");
+        c->gemm_mfma = value;
+        break;
       default:
         LQCD_CHECK(false, LQCD_EINVAL, "lqcd_tune_set: unknown parameter %d", int(param));
     }

@@ -11,10 +11,13 @@
 // two-spin "half spinor" only (6 complex), and the lower spins are rebuilt
 // from the product.
 //
-// Data layout (per right-hand side, per parity): component-major
-// [12][Vh] complex, component c = spin * 3 + colour, so that a wavefront
-// loading one component of 64 consecutive sites reads one contiguous
-// 1 KiB (FP64) segment.  Links: [parity][mu][9][Vh].
+// Data layouts (per right-hand side, per parity; stencil.h): fields are
+// stored as 16-byte granules per site, granule-major ([granules][Vh]), so a
+// lane gathers a neighbour with 16-byte loads that a wavefront issues as
+// contiguous 1 KiB runs: FP64 [12][Vh] complex, the FP32 odd temporary of
+// the even/odd operator in component pairs [6][Vh], 16-bit storage in
+// component quads [3][Vh] plus per-site scales.  The FP32 fields the
+// solvers hold are component-major [12][Vh].  Links: [parity][mu][9][Vh].
 //
 // Kernels and launch logic; the device building blocks (half-spinor
 // projection, link products, sources of plain or 16-bit fields) are in
@@ -36,7 +39,7 @@ using namespace st;
 // and one wave load fetches each link once for all NB of them (links are
 // 2/3 of a single right-hand side's bytes).  Spinor accesses stay in
 // contiguous runs of 64/NB sites per right-hand side.
-template <class R, bool G5IN, bool G5OUT, bool SELF, int NB, class SrcIn, class SrcSelf>
+template <class R, bool G5IN, bool G5OUT, bool SELF, int NB, class SrcIn, class SrcSelf, class OutT>
 // 3 waves per SIMD caps FP64 at 128 VGPRs (4 waves resident, no spills).
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8)))
     k_hop(Geom g, int p, const cx<R> *U, SrcIn in,
@@ -59,7 +62,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
   const size_t Vh = size_t(g.Vh);
   const size_t rhs = rr;
   in = in.at(rhs * in_stride);
-  out += rhs * out_stride;
+  char *ob = reinterpret_cast<char *>(out) + rhs * out_stride * OutT::kElemBytes;
   const int Lxh = g.Lxh, Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
   const int xh = i % Lxh;
   int r = i / Lxh;
@@ -101,19 +104,20 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
 
   if (SELF) self = self.at(rhs * self_stride);
   const typename SrcSelf::Ctx ssc = SELF ? self.site(i) : typename SrcSelf::Ctx{};
+  cx<R> v[12];
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      cx<R> v = beta * acc[s][c];
+      v[s * 3 + c] = beta * acc[s][c];
       if (SELF) {
         cx<R> w = self.ld(ssc, i, s * 3 + c, Vh);
         if (G5IN && s >= 2) w = -w;
-        v = v + alpha * w;
+        v[s * 3 + c] = v[s * 3 + c] + alpha * w;
       }
-      if (G5OUT && s >= 2) v = -v;
-      stc(out + (s * 3 + c) * Vh + i, v);
+      if (G5OUT && s >= 2) v[s * 3 + c] = -v[s * 3 + c];
     }
+  OutT::template store12<false>(ob, uint32_t(i) * OutT::kSiteBytes, Vh, v);
 }
 
 // Link-tiled form for many right-hand sides: a workgroup owns T
@@ -141,10 +145,10 @@ __device__ inline void hop_leg(cx<R> acc[4][3], const cx<R> *sU, int T, const Ra
 // consumed, so D neighbours' loads are in flight while one is computed.
 template <class R, int LEG, int D, bool G5IN, class Src>
 __device__ inline void hop_step(cx<R> acc[4][3], const cx<R> *sU, int T, const Src &in,
-                                const uint32_t off[8], size_t Vh, Raw<Src> &buf, R one) {
+                                const uint32_t off[8], uint32_t ib, size_t Vh, Raw<Src> &buf, R one) {
   settle(buf);
   hop_leg<R, LEG, G5IN>(acc, sU, T, buf, one);
-  if (LEG + D < 8) fetch_at(in, off[LEG + D < 8 ? LEG + D : 0], Vh, buf);
+  if (LEG + D < 8) fetch_at(in, off[LEG + D < 8 ? LEG + D : 0], ib, Vh, buf);
   fence(acc);
 }
 
@@ -152,12 +156,12 @@ __device__ inline void hop_step(cx<R> acc[4][3], const cx<R> *sU, int T, const S
 // issues no neighbour load, into the registers that step has freed.
 template <class R, int LEG, int D, bool G5IN, bool SELF, class Src, class SS>
 __device__ inline void hop_steps(cx<R> acc[4][3], const cx<R> *sU, int T, const Src &in,
-                                 const uint32_t off[8], size_t Vh, Raw<Src> (&buf)[D], R one, const SS &self,
-                                 uint32_t so, Raw<SS> &rs) {
+                                 const uint32_t off[8], uint32_t ib, size_t Vh, Raw<Src> (&buf)[D], R one,
+                                 const SS &self, uint32_t so, uint32_t sb, Raw<SS> &rs) {
   if constexpr (LEG < 8) {
-    hop_step<R, LEG, D, G5IN>(acc, sU, T, in, off, Vh, buf[LEG % D], one);
-    if constexpr (SELF && LEG + D == 8) fetch_at(self, so, Vh, rs);
-    hop_steps<R, LEG + 1, D, G5IN, SELF>(acc, sU, T, in, off, Vh, buf, one, self, so, rs);
+    hop_step<R, LEG, D, G5IN>(acc, sU, T, in, off, ib, Vh, buf[LEG % D], one);
+    if constexpr (SELF && LEG + D == 8) fetch_at(self, so, sb, Vh, rs);
+    hop_steps<R, LEG + 1, D, G5IN, SELF>(acc, sU, T, in, off, ib, Vh, buf, one, self, so, sb, rs);
   }
 }
 
@@ -168,22 +172,28 @@ __device__ inline void hop_steps(cx<R> acc[4][3], const cx<R> *sU, int T, const 
 // within a block, t fastest: the planes whose spinors a tile reads through
 // its z and t neighbours are then at most tb planes of the sequence away,
 // so they are still in the XCD's L2 when the next tile needs them.
-// With rg > 0 the right-hand sides are split into groups of rg and the
-// logical workgroup index runs over (group, tile), group slowest: every XCD
-// range then covers one group over part of the lattice, and its L2 holds
-// that group's spinors only (the links are read once per group).
+// With rg > 0 the right-hand sides are split into groups of rg.  nest == 0:
+// the logical workgroup index runs over (group, tile), group slowest: every
+// XCD range then covers one group over part of the lattice, and its L2
+// holds that group's spinors only (the links are read once per group).
+// nest > 0 (plane order; nest = tiles per block of tb timeslices): the index
+// runs over (block, group, tile within the block), so an XCD sweeps its own
+// block once per group in turn: its L2 holds one group's planes at a time,
+// and the block's links are read once per group (from the last-level cache
+// after the first).
 struct TileMap {
   int tb, nbp, ppl;
   int rg, ntg;  // right-hand sides per group (0: one group), tiles per group
+  int nest;     // tiles per block of timeslices when groups are nested in blocks (0: not nested)
 };
 
 // Waves per SIMD the tiled stencil is compiled for: 4 (128 VGPRs) with
 // 16-bit sources, whose three raw neighbours in flight fit there; 3 (168
 // VGPRs) otherwise.
 template <class R, class SrcIn>
-constexpr int hop_tile_waves = (sizeof(R) == 4 && SrcIn::kBytes == 4) ? 4 : 3;
+constexpr int hop_tile_waves = (sizeof(R) == 4 && SrcIn::kElemBytes == 4) ? 4 : 3;
 
-template <class R, bool G5IN, bool G5OUT, bool SELF, int T, class SrcIn, class SrcSelf>
+template <class R, bool G5IN, bool G5OUT, bool SELF, int T, class SrcIn, class SrcSelf, class OutT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(hop_tile_waves<R, SrcIn>, 8)))
     k_hop_tile(Geom g, int p, const cx<R> *U, SrcIn in, SrcSelf self, cx<R> *out, cx<R> alpha,
                R beta, size_t in_stride, size_t self_stride, size_t out_stride, int nrhs, int xq,
@@ -194,11 +204,20 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(hop
   // neighbours' loads in flight per wave: 3 for 16-bit sources (128
   // VGPRs, 4 waves per SIMD), 2 for FP32 ones (a third spills at 168), 1 in
   // FP64 (a second raw FP64 site would cost a wave per SIMD)
-  constexpr int D = sizeof(R) == 8 ? 1 : (SrcIn::kBytes == 4 ? 3 : 2);
+  constexpr int D = sizeof(R) == 8 ? 1 : (SrcIn::kElemBytes == 4 ? 3 : 2);
   __shared__ cx<R> sU[8 * 9 * T];  // [direction: 4 forward, 4 backward][entry][site]
   // XCD-aware tile order (as in k_hop): each XCD walks one contiguous range
   const int lidx = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
-  const int grp = tm.rg > 0 ? lidx / tm.ntg : 0, tile = tm.rg > 0 ? lidx % tm.ntg : lidx;
+  int grp = 0, tile = lidx;
+  if (tm.rg > 0 && tm.nest > 0) {
+    const int ng = (nrhs + tm.rg - 1) / tm.rg, per = ng * tm.nest;
+    const int rem = lidx % per;
+    grp = rem / tm.nest;
+    tile = (lidx / per) * tm.nest + rem % tm.nest;
+  } else if (tm.rg > 0) {
+    grp = lidx / tm.ntg;
+    tile = lidx % tm.ntg;
+  }
   const int rlo = grp * tm.rg, rhi = tm.rg > 0 ? min(nrhs, rlo + tm.rg) : nrhs;
   if (rlo >= nrhs) return;  // whole workgroup: padding of the grid
   int i0, lim;
@@ -259,15 +278,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(hop
   asm volatile("" : "+s"(one));
   // lane byte offsets within the wave's fields (loop-invariant)
   const uint32_t sl = uint32_t(slot - slot0);
-  const uint32_t ib = sl * uint32_t(in_stride * SrcIn::kBytes), sb = sl * uint32_t(self_stride * SrcSelf::kBytes),
-                 ob = sl * uint32_t(out_stride * sizeof(cx<R>));
+  const uint32_t ib = sl * uint32_t(in_stride * SrcIn::kElemBytes),
+                 sb = sl * uint32_t(self_stride * SrcSelf::kElemBytes), ob = sl * uint32_t(out_stride * OutT::kElemBytes);
   uint32_t of[4], obk[4];
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
-    of[d] = ib + uint32_t(nf[d]) * SrcIn::kBytes;
-    obk[d] = ib + uint32_t(nb[d]) * SrcIn::kBytes;
+    of[d] = ib + uint32_t(nf[d]) * SrcIn::kSiteBytes;
+    obk[d] = ib + uint32_t(nb[d]) * SrcIn::kSiteBytes;
   }
-  const uint32_t so = sb + uint32_t(i) * SrcSelf::kBytes, oo = ob + uint32_t(i) * uint32_t(sizeof(cx<R>));
+  const uint32_t so = sb + uint32_t(i) * SrcSelf::kSiteBytes, oo = ob + uint32_t(i) * OutT::kSiteBytes;
 #pragma unroll 1
   for (int r0 = rlo + slot0; r0 < rhi; r0 += RS) {
     if (r0 + int(sl) >= rhi) break;  // this lane's right-hand side is past the end
@@ -293,31 +312,32 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(hop
     Raw<SrcSelf> rs;
     Raw<SrcIn> rb[D];
 #pragma unroll
-    for (int l = 0; l < D; ++l) fetch_at(inr, off[l], Vh, rb[l]);
-    hop_steps<R, 0, D, G5IN, SELF>(acc, su, T, inr, off, Vh, rb, one, sr, so, rs);
-    char *o = reinterpret_cast<char *>(out + rw * out_stride);
+    for (int l = 0; l < D; ++l) fetch_at(inr, off[l], ib, Vh, rb[l]);
+    hop_steps<R, 0, D, G5IN, SELF>(acc, su, T, inr, off, ib, Vh, rb, one, sr, so, sb, rs);
+    char *o = reinterpret_cast<char *>(out) + rw * out_stride * OutT::kElemBytes;
     if (SELF) settle(rs);
+    cx<R> v[12];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        cx<R> v = beta * acc[s][c];
+        v[s * 3 + c] = beta * acc[s][c];
         if (SELF) {
           cx<R> w = rs.get(s * 3 + c);
           if (G5IN && s >= 2) w = -w;
-          v = v + alpha * w;
+          v[s * 3 + c] = v[s * 3 + c] + alpha * w;
         }
-        if (G5OUT && s >= 2) v = -v;
-        stc_nt(reinterpret_cast<cx<R> *>(o + (s * 3 + c) * Vh * sizeof(cx<R>) + oo), v);
+        if (G5OUT && s >= 2) v[s * 3 + c] = -v[s * 3 + c];
       }
+    OutT::template store12<true>(o, oo, Vh, v);
   }
 }
 
-template <class R, bool A, bool B, bool C, int T, class SI, class SS>
+template <class R, bool A, bool B, bool C, int T, class SI, class SS, class OT>
 void launch_hop_tile(lqcd_ctx *c, Timed &tm, int p, const cx<R> *U, SI in, SS self, void *out,
                      cdouble alpha, double beta, int nrhs, size_t si, size_t ss, size_t so) {
   const Geom &g = c->g;
-  TileMap map{c->hop_tblock[std::is_same<R, double>::value ? 0 : 1], 0, g.Lxh * g.L[1], 0, 0};
+  TileMap map{c->hop_tblock[std::is_same<R, double>::value ? 0 : 1], 0, g.Lxh * g.L[1], 0, 0, 0};
   if (map.tb < 0)  // automatic: plane order when planes split into whole tiles, one block per XCD
     map.tb = (map.ppl % T == 0 && g.L[3] >= 8) ? (g.L[3] + 7) / 8 : 0;
   int ntile;
@@ -329,19 +349,20 @@ void launch_hop_tile(lqcd_ctx *c, Timed &tm, int p, const cx<R> *U, SI in, SS se
   } else {
     ntile = int((g.Vh + T - 1) / T);
   }
-  const int rg = c->hop_rgroup;
+  const int rn = c->hop_rnest, rg = rn > 0 && map.tb > 0 ? rn : c->hop_rgroup;
   if (rg > 0 && rg < nrhs) {
     map.rg = rg;
     map.ntg = ntile;
+    if (rn > 0 && map.tb > 0) map.nest = map.tb * g.L[2] * map.nbp;
     ntile *= (nrhs + rg - 1) / rg;
   }
   const int xq = (ntile + 7) / 8;
-  LQCD_TLAUNCH(tm, true, true, (k_hop_tile<R, A, B, C, T, SI, SS>), dim3(8 * xq), dim3(kBlock), 0, c->stream, g, p,
+  LQCD_TLAUNCH(tm, true, true, (k_hop_tile<R, A, B, C, T, SI, SS, OT>), dim3(8 * xq), dim3(kBlock), 0, c->stream, g, p,
                      U, in, self, static_cast<cx<R> *>(out), mk<R>(R(alpha.real()), R(alpha.imag())),
                      R(beta), si, ss, so, nrhs, xq, map);
 }
 
-template <class R, bool A, bool B, bool C, int NB, class SI, class SS>
+template <class R, bool A, bool B, bool C, int NB, class SI, class SS, class OT>
 void launch_hop_nb(lqcd_ctx *c, Timed &tm, int p, const cx<R> *U, SI in, SS self, void *out,
                    cdouble alpha, double beta, int nrhs, size_t si, size_t ss, size_t so) {
   const Geom &g = c->g;
@@ -349,7 +370,7 @@ void launch_hop_nb(lqcd_ctx *c, Timed &tm, int p, const cx<R> *U, SI in, SS self
   const int ngr = (nrhs + NB - 1) / NB;
   const int xq = (nbx * ngr + 7) / 8;  // logical blocks per XCD (the grid is padded to 8 * xq)
   dim3 grid(8 * xq);
-  LQCD_TLAUNCH(tm, true, true, (k_hop<R, A, B, C, NB, SI, SS>), grid, dim3(kBlock), 0, c->stream, g, p, U, in,
+  LQCD_TLAUNCH(tm, true, true, (k_hop<R, A, B, C, NB, SI, SS, OT>), grid, dim3(kBlock), 0, c->stream, g, p, U, in,
                      self, static_cast<cx<R> *>(out), mk<R>(R(alpha.real()), R(alpha.imag())), R(beta),
                      si, ss, so, nrhs, xq, ngr, nbx, c->hop_order);
 }
@@ -361,12 +382,16 @@ template <class R>
 struct SrcBytes<SrcPlain<R>> {
   static constexpr double v = 12.0 * sizeof(cx<R>);
 };
+template <>
+struct SrcBytes<SrcPair> {
+  static constexpr double v = 96.0;
+};
 template <HKind K>
 struct SrcBytes<SrcHalf<K>> {
   static constexpr double v = 52.0;
 };
 
-template <class R, bool A, bool B, bool C, class SI, class SS>
+template <class R, bool A, bool B, bool C, class SI, class SS, class OT = OutPlain<R>>
 void launch_hop_src(lqcd_ctx *c, int p, SI in, SS self, void *out, cdouble alpha,
                     double beta, int nrhs, size_t si, size_t ss, size_t so) {
   const Geom &g = c->g;
@@ -387,21 +412,25 @@ void launch_hop_src(lqcd_ctx *c, int p, SI in, SS self, void *out, cdouble alpha
   while (ts < tmax && nrhs < kBlock / ts) ts *= 2;
   // the tiled form addresses a wave's fields by 32-bit byte offsets: one
   // right-hand-side stride per extra slot of a wave plus a half field
-  auto fits = [&](size_t stride, double bytes) {
-    return double(64 / ts - 1) * double(stride) * bytes + double(g.Vh) * bytes < 4294967295.0;
+  auto fits = [&](size_t stride, double elem, double site) {
+    return double(64 / ts - 1) * double(stride) * elem + double(g.Vh) * site < 4294967295.0;
   };
-  const bool offs_ok = fits(si, SI::kBytes) && (!C || fits(ss, SS::kBytes)) && fits(so, sizeof(cx<R>));
+  const bool offs_ok = fits(si, SI::kElemBytes, SI::kSiteBytes) &&
+                       (!C || fits(ss, SS::kElemBytes, SS::kSiteBytes)) && fits(so, OT::kElemBytes, OT::kSiteBytes);
   const bool tiled = c->hop_tile[pi] && offs_ok && ts <= tmax && nrhs >= kBlock / ts;
   if (tiled && ts == 16)
-    launch_hop_tile<R, A, B, C, 16>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+    launch_hop_tile<R, A, B, C, 16, SI, SS, OT>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   else if (tiled && ts == 32)
-    launch_hop_tile<R, A, B, C, 32>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+    launch_hop_tile<R, A, B, C, 32, SI, SS, OT>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   else if (tiled)
-    launch_hop_tile<R, A, B, C, tmax>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
-  else if (nrhs >= 8 && nbmax >= 8) launch_hop_nb<R, A, B, C, 8>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
-  else if (nrhs >= 4 && nbmax >= 4) launch_hop_nb<R, A, B, C, 4>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
-  else if (nrhs >= 2 && nbmax >= 2) launch_hop_nb<R, A, B, C, 2>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
-  else launch_hop_nb<R, A, B, C, 1>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+    launch_hop_tile<R, A, B, C, tmax, SI, SS, OT>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else if (nrhs >= 8 && nbmax >= 8)
+    launch_hop_nb<R, A, B, C, 8, SI, SS, OT>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else if (nrhs >= 4 && nbmax >= 4)
+    launch_hop_nb<R, A, B, C, 4, SI, SS, OT>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else if (nrhs >= 2 && nbmax >= 2)
+    launch_hop_nb<R, A, B, C, 2, SI, SS, OT>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
+  else launch_hop_nb<R, A, B, C, 1, SI, SS, OT>(c, tm, p, U, in, self, out, alpha, beta, nrhs, si, ss, so);
   LQCD_HIP(hipGetLastError());
 }
 
@@ -466,13 +495,24 @@ void apply_full(lqcd_ctx *c, lqcd_op op, const void *in, void *out, int nrhs, si
   }
 }
 
-// Mhat x_e = x_e - kappa^2 D_eo D_oe x_e  (Sec. 7 even/odd reduction).
+// Mhat x_e = x_e - kappa^2 D_eo D_oe x_e  (Sec. 7 even/odd reduction).  The
+// odd temporary never leaves the operator: in FP32 it is written and read
+// in component pairs (16-byte granules).
 template <class R>
 void apply_schur(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin,
                  size_t sout, size_t stmp) {
   const double k = c->kappa;
-  hop_half<R>(c, 1, in, nullptr, tmp_odd, cdouble(0, 0), 1.0, false, false, nrhs, sin, 0, stmp);
-  hop_half<R>(c, 0, tmp_odd, in, out, cdouble(1, 0), -k * k, false, false, nrhs, stmp, sin, sout);
+  if constexpr (std::is_same<R, float>::value) {
+    if (nrhs <= 0) return;
+    const SrcPlain<float> x{static_cast<const cx<float> *>(in)};
+    launch_hop_src<float, false, false, false, SrcPlain<float>, SrcPlain<float>, OutPair>(
+        c, 1, x, SrcPlain<float>{nullptr}, tmp_odd, cdouble(0, 0), 1.0, nrhs, sin, 0, stmp);
+    launch_hop_src<float, false, false, true>(c, 0, SrcPair{static_cast<const cx<float> *>(tmp_odd)}, x, out,
+                                              cdouble(1, 0), -k * k, nrhs, stmp, sin, sout);
+  } else {
+    hop_half<R>(c, 1, in, nullptr, tmp_odd, cdouble(0, 0), 1.0, false, false, nrhs, sin, 0, stmp);
+    hop_half<R>(c, 0, tmp_odd, in, out, cdouble(1, 0), -k * k, false, false, nrhs, stmp, sin, sout);
+  }
 }
 
 // Mhat on stored 16-bit even fields (in: words, vectors sin words apart),
@@ -486,10 +526,11 @@ void apply_schur_h(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nr
   const size_t n = half_len(c->g);
   const SrcHalf<K> hin{static_cast<const uint32_t *>(in), n};
   const SrcPlain<float> none{nullptr};
-  launch_hop_src<float, false, false, false>(c, 1, hin, none, tmp_odd, cdouble(0, 0), 1.0, nrhs, sin,
-                                             0, stmp);
-  launch_hop_src<float, false, false, true>(c, 0, SrcPlain<float>{static_cast<const cx<float> *>(tmp_odd)},
-                                            hin, out, cdouble(1, 0), -k * k, nrhs, stmp, sin, sout);
+  launch_hop_src<float, false, false, false, SrcHalf<K>, SrcPlain<float>, OutPair>(c, 1, hin, none, tmp_odd,
+                                                                                   cdouble(0, 0), 1.0, nrhs, sin,
+                                                                                   0, stmp);
+  launch_hop_src<float, false, false, true>(c, 0, SrcPair{static_cast<const cx<float> *>(tmp_odd)}, hin, out,
+                                            cdouble(1, 0), -k * k, nrhs, stmp, sin, sout);
 }
 template void apply_schur_h<0>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
 template void apply_schur_h<1>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);

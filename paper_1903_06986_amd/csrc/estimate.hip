@@ -34,29 +34,30 @@ __global__ void __launch_bounds__(kBlock)
   const int t = blockIdx.x / nch, ch = blockIdx.x % nch, r = blockIdx.y;
   const size_t base = (size_t(r) * V + size_t(t) * Vs) * 12;
   double acc[2 * kNumTheta] = {};
-  // element-parallel: lane e handles component (spin sp, colour c) of one
-  // site, so consecutive lanes read consecutive complex numbers; the spin
-  // partners Theta needs (sp, 3 - sp, sp ^ 2 in this basis) lie in the same
-  // 192-byte site block
-  const size_t ne = size_t(Vs) * 12;
+  // lane = (site, colour c): it loads the four spins of colour c of eta, x
+  // and xt (12 loads of 16 bytes, three lanes cover a site's 192-byte block)
+  // and forms every Theta's terms from registers, since each Theta only
+  // permutes spins (with a phase) at fixed colour
+  const size_t ne = size_t(Vs) * 3;
   for (size_t e = size_t(ch) * kBlock + threadIdx.x; e < ne; e += size_t(nch) * kBlock) {
-    const size_t site0 = base + e / 12 * 12;
-    const int k = int(e % 12), sp = k / 3, c = k % 3;
-    const cx<double> a = ldc(eta + base + e);
-    auto dval = [&](int col) {
-      cx<double> v = ldc(x + site0 + col * 3 + c);
-      if (xt) v = v - ldc(xt + site0 + col * 3 + c);
-      return v;
-    };
-    const cx<double> d0 = dval(sp), d1 = dval(3 - sp), d2 = dval(sp ^ 2);
+    const size_t s0 = base + e / 3 * 12 + e % 3;  // (site, spin 0, colour c)
+    cx<double> a[4], d[4];
 #pragma unroll
-    for (int th = 0; th < kNumTheta; ++th) {
-      const int col = kGamma[th].col[sp];
-      const cx<double> dv = col == sp ? d0 : (col == 3 - sp ? d1 : d2);
-      const cx<double> v = cmulc(a, mk(kGamma[th].re[sp], kGamma[th].im[sp]) * dv);
-      acc[2 * th] += v.re;
-      acc[2 * th + 1] += v.im;
+    for (int sp = 0; sp < 4; ++sp) {
+      a[sp] = ldc(eta + s0 + 3 * sp);
+      d[sp] = ldc(x + s0 + 3 * sp);
     }
+    if (xt)
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) d[sp] = d[sp] - ldc(xt + s0 + 3 * sp);
+#pragma unroll
+    for (int th = 0; th < kNumTheta; ++th)
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) {
+        const cx<double> v = cmulc(a[sp], mk(kGamma[th].re[sp], kGamma[th].im[sp]) * d[kGamma[th].col[sp]]);
+        acc[2 * th] += v.re;
+        acc[2 * th + 1] += v.im;
+      }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -143,12 +144,20 @@ __device__ inline cx<double> ps_lane(const cx<double> *U, const Geom &g, double 
   return (fwd ? -kappa : kappa) * acc;
 }
 
+// Workgroup order: the right-hand side varies fastest within one XCD's
+// contiguous range of logical workgroups (hardware workgroup h runs on XCD
+// h % 8), so the nrhs workgroups of one chunk of sites run back to back on
+// one XCD and read its links from that XCD's L2 (links are as many bytes as
+// one right-hand side's three fields).
 __global__ void __launch_bounds__(kBlock)
     k_estimate_ps(Geom g, const cx<double> *__restrict__ U, double kappa,
                   const cx<double> *__restrict__ eta, const cx<double> *__restrict__ x,
-                  const cx<double> *__restrict__ xt, int nch, double *__restrict__ out) {
+                  const cx<double> *__restrict__ xt, int nch, int nrhs, int xq, double *__restrict__ out) {
   __shared__ double sh[2 * kNumPS][kWaves];
-  const int t = blockIdx.x / nch, ch = blockIdx.x % nch, r = blockIdx.y;
+  const int L = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
+  if (L >= g.L[3] * nch * nrhs) return;  // whole workgroup: padding of the grid
+  const int r = L % nrhs, tch = L / nrhs;
+  const int t = tch / nch, ch = tch % nch;
   const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
   const int Vs = Lx * Ly * Lz;
   const size_t base = size_t(r) * size_t(g.V) * 12;
@@ -196,30 +205,23 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-}  // namespace
-}  // namespace lqcd
+// Chunks per timeslice: about 2048 workgroups in all, at least one site
+// block each.
+int estimate_chunks(const Geom &g, int nrhs) {
+  const int Lt = g.L[3], Vs = g.V / Lt;
+  return std::max(1, std::min((Vs + kBlock / 4 - 1) / (kBlock / 4), (2048 + Lt * nrhs - 1) / (Lt * nrhs)));
+}
 
-using namespace lqcd;
-
-extern "C" lqcd_status loop_estimate(lqcd_ctx *c, const int *thetas, int nth, const void *eta,
-                                     const void *x, const void *xt, int nrhs, const double *corr,
-                                     double *est, double *stderr_, double *samples) {
-  return guarded([&] {
-    LQCD_CHECK(c && eta && x && est && stderr_, LQCD_EINVAL, "loop_estimate: null argument");
-    LQCD_CHECK(nrhs >= 1, LQCD_EINVAL, "loop_estimate: need at least one noise vector");
-    LQCD_CHECK(nth >= 1 && thetas, LQCD_EINVAL, "loop_estimate: no operator");
-    for (int a = 0; a < nth; ++a)
-      LQCD_CHECK(thetas[a] >= 0 && thetas[a] < kNumOps, LQCD_EINVAL, "operator code %d outside 0..8",
-                 thetas[a]);
+// The estimator with its partial sums in d (at least
+// nrhs * kNumOps * Lt * nch * 2 doubles of device memory).
+void estimate_with(lqcd_ctx *c, const int *thetas, int nth, const void *eta, const void *x, const void *xt,
+                   int nrhs, const double *corr, double *est, double *stderr_, double *samples, double *d,
+                   int nch) {
+  {
     bool any_local = false, any_ps = false;
     for (int a = 0; a < nth; ++a) (thetas[a] < kNumTheta ? any_local : any_ps) = true;
     const Geom &g = c->g;
     const int Lt = g.L[3], Vs = g.V / Lt;
-    // chunks per timeslice: about 2048 workgroups in all, at least one site
-    // block each
-    const int nch = std::max(1, std::min((Vs + kBlock / 4 - 1) / (kBlock / 4), (2048 + Lt * nrhs - 1) / (Lt * nrhs)));
-    double *d = static_cast<double *>(
-        c->red.ensure(size_t(nrhs) * kNumOps * Lt * nch * 2 * sizeof(double)));
     if (any_local) {
       hipLaunchKernelGGL(k_estimate, dim3(Lt * nch, nrhs), dim3(kBlock), 0, c->stream,
                          static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x),
@@ -227,10 +229,11 @@ extern "C" lqcd_status loop_estimate(lqcd_ctx *c, const int *thetas, int nth, co
       LQCD_HIP(hipGetLastError());
     }
     if (any_ps) {
-      hipLaunchKernelGGL(k_estimate_ps, dim3(Lt * nch, nrhs), dim3(kBlock), 0, c->stream, g,
+      const int xq = (Lt * nch * nrhs + 7) / 8;  // logical workgroups per XCD (grid padded to 8 xq)
+      hipLaunchKernelGGL(k_estimate_ps, dim3(8 * xq), dim3(kBlock), 0, c->stream, g,
                          static_cast<const cx<double> *>(c->U64.ptr), c->kappa,
                          static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x),
-                         static_cast<const cx<double> *>(xt), nch, d);
+                         static_cast<const cx<double> *>(xt), nch, nrhs, xq, d);
       LQCD_HIP(hipGetLastError());
     }
     std::vector<double> hc(size_t(nrhs) * kNumOps * Lt * nch * 2);
@@ -291,5 +294,32 @@ extern "C" lqcd_status loop_estimate(lqcd_ctx *c, const int *thetas, int nth, co
         samples[2 * i] = smp[i].real();
         samples[2 * i + 1] = smp[i].imag();
       }
+  }
+}
+
+void check_args(lqcd_ctx *c, const int *thetas, int nth, const void *eta, const void *x, int nrhs,
+                const double *est, const double *stderr_, const char *who) {
+  LQCD_CHECK(c && eta && x && est && stderr_, LQCD_EINVAL, "%s: null argument", who);
+  LQCD_CHECK(nrhs >= 1, LQCD_EINVAL, "%s: need at least one noise vector", who);
+  LQCD_CHECK(nth >= 1 && thetas, LQCD_EINVAL, "%s: no operator", who);
+  for (int a = 0; a < nth; ++a)
+    LQCD_CHECK(thetas[a] >= 0 && thetas[a] < kNumOps, LQCD_EINVAL, "%s: operator code %d outside 0..8", who,
+               thetas[a]);
+}
+
+}  // namespace
+}  // namespace lqcd
+
+using namespace lqcd;
+
+extern "C" lqcd_status loop_estimate(lqcd_ctx *c, const int *thetas, int nth, const void *eta,
+                                     const void *x, const void *xt, int nrhs, const double *corr,
+                                     double *est, double *stderr_, double *samples) {
+  return guarded([&] {
+    check_args(c, thetas, nth, eta, x, nrhs, est, stderr_, "loop_estimate");
+    const int nch = estimate_chunks(c->g, nrhs);
+    double *d = static_cast<double *>(
+        c->red.ensure(size_t(nrhs) * kNumOps * c->g.L[3] * nch * 2 * sizeof(double)));
+    estimate_with(c, thetas, nth, eta, x, xt, nrhs, corr, est, stderr_, samples, d, nch);
   });
 }

@@ -261,7 +261,8 @@ extern "C" lqcd_status loop_gradient(lqcd_ctx *c, const int *thetas, const doubl
     }
     // Right-hand sides: [eta (only when x is not given); g5 Theta_w^+ eta].
     const int nsolve = x ? nrhs : 2 * nrhs;
-    DevBuf B, X, Am;
+    // context workspaces, grown on first use and kept for later calls
+    DevBuf &B = c->grad[0], &X = c->grad[1], &Am = c->grad[2];
     B.ensure(fl * nsolve * sizeof(cdouble));
     X.ensure(fl * nsolve * sizeof(cdouble));
     Am.ensure(Lt * sizeof(Spin4));

@@ -1,11 +1,13 @@
 // 16-bit storage of FP32 spinor fields with one scale per site.
 //
-// A stored half field (one parity, Vh sites, 12 complex components in the
-// component-major order [12][Vh] of the stencil) is a uint32 array:
-//   words [0, 12 Vh):      component c of site i at c * Vh + i, the real
-//                          part in the low 16 bits, the imaginary part in
-//                          the high 16 bits, each value divided by the
-//                          site's scale;
+// A stored half field (one parity, Vh sites, 12 complex components c =
+// spin * 3 + colour) is a uint32 array:
+//   words [0, 12 Vh):      16-byte granules [3][Vh][4]: component c of site
+//                          i at word hword(c, i, Vh) = 4 ((c / 4) Vh + i) +
+//                          c % 4, the real part in the low 16 bits, the
+//                          imaginary part in the high 16 bits, each value
+//                          divided by the site's scale (a stencil lane
+//                          gathers a site with three 16-byte loads);
 //   words [12 Vh, 13 Vh):  the FP32 scale of site i (bit pattern): the
 //                          largest |re| or |im| over its 24 reals.
 // Stored values therefore lie in [-1, 1], where FP16 keeps 11 significant
@@ -60,6 +62,10 @@ struct Codec<HKind::BF16> {
     return mk(__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u));
   }
 };
+
+__host__ __device__ inline size_t hword(int c, size_t i, size_t Vh) {
+  return 4 * ((size_t(c) >> 2) * Vh + i) + (size_t(c) & 3);
+}
 
 // Words of one stored half field of Vh sites, rounded up to 256 bytes so
 // that consecutive vectors of a basis stay aligned.

@@ -488,8 +488,10 @@ la::Mat sub(const la::Mat &A, int r, int c) {
 
 // ------------------------------------------------------------ GMRES-DR
 // Solves A x = S (x starts at zero) for one right-hand side in FP64 and
-// leaves the deflation data in d.
-void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lqcd_solve_params &p,
+// leaves the deflation data in d.  Returns true when it stopped on its
+// targets (residual <= tol_super |S| and, with eig_tol, the n_eig smallest
+// harmonic Ritz pairs converged), false when max_cycles ended it first.
+bool gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lqcd_solve_params &p,
               lqcd_defl *d, lqcd_solve_stats &st) {
   const int m = p.m, k = p.k;
   const size_t n = A.n;
@@ -519,6 +521,7 @@ void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lq
   int nev = p.n_eig > 0 ? std::min(p.n_eig, k) : k;
   const bool lz = p.method == LQCD_KRYLOV_MINRESDR;
   int kept = 0;  // MINRES-DR: vectors kept by the last restart
+  bool converged = false;
   for (;;) {
     if (lz) lanczos_ext(c, A, V, n, j0, m, kept, s);
     else arnoldi<double>(c, A, V, n, 0, j0, m, 1, s, kReorthDR);
@@ -560,6 +563,7 @@ void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lq
     d->H = Hk;
     d->theta = R.theta;
     d->theta_resid = R.resid;
+    converged = done;
     if (done || st.cycles >= p.max_cycles) break;
     H = la::Mat(m + 1, m);
     for (int j = 0; j < k; ++j)
@@ -573,6 +577,7 @@ void gmres_dr(lqcd_ctx *c, const Op<double> &A, const void *S, void *X, const lq
   d->n = n;
   d->Hqr.factor(d->H);
   d->have_v32 = false;
+  return converged;
 }
 
 // ---------------------------------------------------------- GMRES-Proj
@@ -858,6 +863,7 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
     lqcd_defl *d = *defl_inout;
     int start = 0;
     std::vector<double> tr;
+    bool nonconv = false;
     if (!d) {
       std::unique_ptr<lqcd_defl> nd(new lqcd_defl());
       nd->op = op;
@@ -868,7 +874,10 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
       lqcd_solve_stats st{0, 0, 0, 0, 0.0};
       lqcd_solve_params pd = p;
       pd.tol_super = std::max(0.0, std::min(p.tol_super > 0 ? p.tol_super : p.tol, p.tol));
-      gmres_dr(c, A64, w.S.ptr, X, pd, nd.get(), st);
+      // a first right-hand side cut off by max_cycles has missed its residual
+      // target, or left a deflation space short of eig_tol: ENOCONV, with
+      // the iterate in x and the space still returned
+      if (!gmres_dr(c, A64, w.S.ptr, X, pd, nd.get(), st)) nonconv = true;
       finish(c, op, X, x, 1, w, n, tr);
       st.true_resid = tr[0];
       if (stats) stats[0] = st;
@@ -884,7 +893,6 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
     LQCD_CHECK(p.proj_m >= 0 && p.proj_m <= 250, LQCD_EINVAL, "gmresdr_solve: proj_m outside 0..250");
     const int p_cyc = p.proj_m > 0 ? p.proj_m : p.m - p.k;
     const int blk = std::max(1, p.rhs_block);
-    bool nonconv = false;
     for (int r0 = start; r0 < nrhs; r0 += blk) {
       const int nb = std::min(blk, nrhs - r0);
       const cx<double> *bl = static_cast<const cx<double> *>(b) + size_t(r0) * fl;
@@ -938,10 +946,14 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
           // inner solve for the correction of every rhs not yet converged;
           // converged ones get a zero right-hand side (skipped at once).
           convert<double, float>(c, Rr, S32, n * nb);
-          std::vector<double> iref(nb);
-          for (int r = 0; r < nb; ++r) iref[r] = (rn[r] > p.tol * ref[r]) ? rn[r] : 0.0;
-          std::vector<double> ires(nb);
+          // an inner solve stops at itol times its residual, or as soon as
+          // it is below a quarter of the outer target, whichever is larger:
+          // the last refinement step then does not solve past tol
           const double itol = std::max(p.inner_tol, 1e-6);
+          std::vector<double> iref(nb);
+          for (int r = 0; r < nb; ++r)
+            iref[r] = (rn[r] > p.tol * ref[r]) ? std::max(rn[r], 0.25 * p.tol * ref[r] / itol) : 0.0;
+          std::vector<double> ires(nb);
           if (p.inner == LQCD_F16)
             proj_solve<float, 0>(c, A32, d->V32.ptr, d, p_cyc, S32, X32, R32, W32, nb, iref, itol,
                                  p.max_cycles, mv, cy, ires, ro, kInnerCycleCap, kInnerStall, WT);

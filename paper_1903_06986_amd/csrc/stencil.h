@@ -13,10 +13,19 @@
 // two-spin "half spinor" only (6 complex), and the lower spins are rebuilt
 // from the product.
 //
-// Data layout (per right-hand side, per parity): component-major
-// [12][Vh] complex, component c = spin * 3 + colour, so that a wavefront
-// loading one component of 64 consecutive sites reads one contiguous
-// 1 KiB (FP64) segment.  Links: [parity][mu][9][Vh].
+// Data layouts (per right-hand side, per parity), component c = spin * 3 +
+// colour.  Every layout stores a site's spinor as 16-byte granules, granule
+// g of all sites contiguous ([granules][Vh][16 bytes]), so that one lane
+// gathers a neighbour with 16-byte loads and a wavefront's load of one
+// granule of 64 consecutive sites is one contiguous 1 KiB run:
+//   FP64 plain:  [12][Vh] complex (one component per granule);
+//   FP32 pairs:  [6][Vh] x (c = 2g, 2g + 1) -- the stencil's internal
+//                odd-site temporary of the even/odd operator;
+//   16-bit:      [3][Vh] x (c = 4g .. 4g + 3), then the per-site scales
+//                (half.h).
+// FP32 fields the solvers hold are component-major [12][Vh] (8-byte
+// granules), the layout their Gram-Schmidt kernels share with FP64.
+// Links: [parity][mu][9][Vh].
 #pragma once
 
 #include "common.h"
@@ -31,22 +40,43 @@ namespace st {
 // moves to right-hand side r (stride in elements of the storage); site(i)
 // fetches what every component load of site i shares.
 //
-// The *_at forms address a site by a 32-bit byte offset o from the base p
-// (kBytes bytes per site and component): with p the same for the whole
-// wave, p + comp * Vh stays in scalar registers and every load is
-// "scalar base + one 32-bit lane offset", one VGPR per neighbour instead
-// of a 64-bit address per component.
+// The *_at forms address a site by a 32-bit byte offset o = oslot + i *
+// kSiteBytes from the base p (kSiteBytes: bytes of one granule of one
+// site; oslot: the lane's right-hand side, counted from the wave's): with p
+// the same for the whole wave, p + granule offset stays in scalar
+// registers and every load is "scalar base + one 32-bit lane offset", one
+// VGPR per neighbour instead of a 64-bit address per component.
+// kElemBytes: bytes of one storage element (the unit of right-hand-side
+// strides and of at()).
 template <class R>
 struct SrcPlain {
   const cx<R> *p;
   using Ctx = int;
-  static constexpr uint32_t kBytes = sizeof(cx<R>);
+  static constexpr uint32_t kElemBytes = sizeof(cx<R>), kSiteBytes = sizeof(cx<R>);
   __device__ SrcPlain at(size_t off) const { return SrcPlain{p + off}; }
   __device__ Ctx site(size_t) const { return 0; }
   __device__ cx<R> ld(Ctx, size_t i, int comp, size_t Vh) const { return ldc(p + comp * Vh + i); }
-  __device__ Ctx site_at(uint32_t) const { return 0; }
+  __device__ Ctx site_at(uint32_t, uint32_t) const { return 0; }
   __device__ cx<R> ld_at(Ctx, uint32_t o, int comp, size_t Vh) const {
     return ldc(reinterpret_cast<const cx<R> *>(reinterpret_cast<const char *>(p + comp * Vh) + o));
+  }
+};
+
+// FP32 in component pairs: granule g of site i (components 2g, 2g + 1) at
+// complex elements 2 (g Vh + i) and 2 (g Vh + i) + 1.
+struct SrcPair {
+  const cx<float> *p;
+  using Ctx = int;
+  static constexpr uint32_t kElemBytes = 8, kSiteBytes = 16;
+  __device__ SrcPair at(size_t off) const { return SrcPair{p + off}; }
+  __device__ Ctx site(size_t) const { return 0; }
+  __device__ cx<float> ld(Ctx, size_t i, int comp, size_t Vh) const {
+    return ldc(p + 2 * ((comp >> 1) * Vh + i) + (comp & 1));
+  }
+  __device__ Ctx site_at(uint32_t, uint32_t) const { return 0; }
+  __device__ cx<float> ld_at(Ctx, uint32_t o, int comp, size_t Vh) const {
+    return ldc(reinterpret_cast<const cx<float> *>(reinterpret_cast<const char *>(p + 2 * (comp >> 1) * Vh) + o) +
+               (comp & 1));
   }
 };
 
@@ -55,20 +85,57 @@ struct SrcHalf {
   const uint32_t *p;
   size_t n;  // payload words (12 Vh); the scales follow
   using Ctx = float;
-  static constexpr uint32_t kBytes = 4;
+  static constexpr uint32_t kElemBytes = 4, kSiteBytes = 16;
   __device__ SrcHalf at(size_t off) const { return SrcHalf{p + off, n}; }
   __device__ Ctx site(size_t i) const { return __uint_as_float(p[n + i]); }
   __device__ cx<float> ld(Ctx sc, size_t i, int comp, size_t Vh) const {
-    const cx<float> v = Codec<K>::unpack(p[comp * Vh + i]);
+    const cx<float> v = Codec<K>::unpack(p[hword(comp, i, Vh)]);
     return mk(sc * v.re, sc * v.im);
   }
-  __device__ Ctx site_at(uint32_t o) const {
-    return __uint_as_float(*reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p + n) + o));
+  // o = oslot + 16 i (oslot: the right-hand side's byte offset from p);
+  // the scale of site i sits at byte oslot + 4 i after the payload
+  __device__ Ctx site_at(uint32_t o, uint32_t oslot) const {
+    return __uint_as_float(*reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p + n) + oslot +
+                                                               ((o - oslot) >> 2)));
   }
   __device__ cx<float> ld_at(Ctx sc, uint32_t o, int comp, size_t Vh) const {
-    const cx<float> v =
-        Codec<K>::unpack(*reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p + comp * Vh) + o));
+    const cx<float> v = Codec<K>::unpack(*reinterpret_cast<const uint32_t *>(
+        reinterpret_cast<const char *>(p + 4 * (comp >> 2) * Vh) + o + 4 * (comp & 3)));
     return mk(sc * v.re, sc * v.im);
+  }
+};
+
+// Output layouts of the stencil (plain component-major or FP32 pairs):
+// store12 writes a site's 12 components, streamed past the caches when NT.
+template <class R>
+struct OutPlain {
+  static constexpr uint32_t kElemBytes = sizeof(cx<R>), kSiteBytes = sizeof(cx<R>);
+  template <bool NT>
+  __device__ static void store12(char *o, uint32_t oo, size_t Vh, const cx<R> (&v)[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      cx<R> *q = reinterpret_cast<cx<R> *>(o + k * Vh * sizeof(cx<R>) + oo);
+      if (NT) stc_nt(q, v[k]);
+      else stc(q, v[k]);
+    }
+  }
+};
+struct OutPair {
+  static constexpr uint32_t kElemBytes = 8, kSiteBytes = 16;
+  template <bool NT>
+  __device__ static void store12(char *o, uint32_t oo, size_t Vh, const cx<float> (&v)[12]) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+      f4v w;
+      w.x = v[2 * g].re;
+      w.y = v[2 * g].im;
+      w.z = v[2 * g + 1].re;
+      w.w = v[2 * g + 1].im;
+      f4v *q = reinterpret_cast<f4v *>(o + g * Vh * 16 + oo);
+      if (NT) __builtin_nontemporal_store(w, q);
+      else *q = w;
+    }
   }
 };
 
@@ -165,16 +232,31 @@ struct Raw<SrcPlain<R>> {
   __device__ cx<R> unscaled(int k) const { return v[k]; }
   __device__ One scale() const { return One{}; }
 };
+template <>
+struct Raw<SrcPair> {
+  static constexpr bool kMix = false;
+  float4 q[6];
+  __device__ cx<float> get(int k) const {
+    const float4 v = q[k >> 1];
+    return (k & 1) ? mk(v.z, v.w) : mk(v.x, v.y);
+  }
+  __device__ cx<float> unscaled(int k) const { return get(k); }
+  __device__ One scale() const { return One{}; }
+};
 template <HKind K>
 struct Raw<SrcHalf<K>> {
   static constexpr bool kMix = K == HKind::F16;
-  uint32_t w[12];
+  uint4 q[3];
   float sc;
+  __device__ uint32_t word(int k) const {
+    const uint4 v = q[k >> 2];
+    return (k & 3) == 0 ? v.x : (k & 3) == 1 ? v.y : (k & 3) == 2 ? v.z : v.w;
+  }
   __device__ cx<float> get(int k) const {
-    const cx<float> v = Codec<K>::unpack(w[k]);
+    const cx<float> v = Codec<K>::unpack(word(k));
     return mk(sc * v.re, sc * v.im);
   }
-  __device__ cx<float> unscaled(int k) const { return Codec<K>::unpack(w[k]); }
+  __device__ cx<float> unscaled(int k) const { return Codec<K>::unpack(word(k)); }
   __device__ float scale() const { return sc; }
 };
 
@@ -213,16 +295,21 @@ __device__ inline cx<float> madd(cx<float> a, float s, cx<float> b) {
 }
 
 template <class R>
-__device__ inline void fetch_at(const SrcPlain<R> &s, uint32_t o, size_t Vh, Raw<SrcPlain<R>> &r) {
+__device__ inline void fetch_at(const SrcPlain<R> &s, uint32_t o, uint32_t, size_t Vh, Raw<SrcPlain<R>> &r) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) r.v[k] = s.ld_at(0, o, k, Vh);
 }
-template <HKind K>
-__device__ inline void fetch_at(const SrcHalf<K> &s, uint32_t o, size_t Vh, Raw<SrcHalf<K>> &r) {
-  r.sc = s.site_at(o);
+__device__ inline void fetch_at(const SrcPair &s, uint32_t o, uint32_t, size_t Vh, Raw<SrcPair> &r) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k)
-    r.w[k] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(s.p + k * Vh) + o);
+  for (int g = 0; g < 6; ++g)
+    r.q[g] = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s.p + 2 * g * Vh) + o);
+}
+template <HKind K>
+__device__ inline void fetch_at(const SrcHalf<K> &s, uint32_t o, uint32_t oslot, size_t Vh, Raw<SrcHalf<K>> &r) {
+  r.sc = s.site_at(o, oslot);
+#pragma unroll
+  for (int g = 0; g < 3; ++g)
+    r.q[g] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(s.p + 4 * g * Vh) + o);
 }
 
 #define LQCD_V2(a) "+v"(a.re), "+v"(a.im)
@@ -233,12 +320,16 @@ __device__ inline void settle(Raw<SrcPlain<R>> &r) {
                LQCD_V2(r.v[10]), LQCD_V2(r.v[11]));
 }
 #undef LQCD_V2
+#define LQCD_V4(a) "+v"(a.x), "+v"(a.y), "+v"(a.z), "+v"(a.w)
+__device__ inline void settle(Raw<SrcPair> &r) {
+  asm volatile("" : LQCD_V4(r.q[0]), LQCD_V4(r.q[1]), LQCD_V4(r.q[2]), LQCD_V4(r.q[3]), LQCD_V4(r.q[4]),
+               LQCD_V4(r.q[5]));
+}
 template <HKind K>
 __device__ inline void settle(Raw<SrcHalf<K>> &r) {
-  asm volatile("" : "+v"(r.w[0]), "+v"(r.w[1]), "+v"(r.w[2]), "+v"(r.w[3]), "+v"(r.w[4]), "+v"(r.w[5]),
-               "+v"(r.w[6]), "+v"(r.w[7]), "+v"(r.w[8]), "+v"(r.w[9]), "+v"(r.w[10]), "+v"(r.w[11]),
-               "+v"(r.sc));
+  asm volatile("" : LQCD_V4(r.q[0]), LQCD_V4(r.q[1]), LQCD_V4(r.q[2]), "+v"(r.sc));
 }
+#undef LQCD_V4
 
 // project() on a settled raw site, without its scale (RawT::scale()).
 // one must hold 1 in a register the compiler cannot see through: for kMix

@@ -123,6 +123,23 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _field(t, nrhs, per_rhs, what, dtype=None):
+    """Check a device field before its pointer goes to the library: a
+    contiguous GPU tensor of `dtype` (complex128 unless given) holding
+    nrhs * per_rhs elements.  A wrong size or type would make the kernels
+    read or write past the allocation."""
+    import torch
+    dtype = torch.complex128 if dtype is None else dtype
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s: expected a torch tensor" % what)
+    if t.dtype != dtype:
+        raise ValueError("%s: dtype %s, expected %s" % (what, t.dtype, dtype))
+    if t.numel() != nrhs * per_rhs:
+        raise ValueError("%s: %d elements, expected %d right-hand sides of %d"
+                         % (what, t.numel(), nrhs, per_rhs))
+    return _ptr(t)
+
+
 def _host(a, dtype):
     a = np.ascontiguousarray(a, dtype=dtype)
     return a, a.ctypes.data_as(ctypes.c_void_p)
@@ -200,11 +217,12 @@ class Context:
     KERNEL_CLASSES = ("hop64", "hop32", "dot", "axpy", "gemm", "force")
 
     def tune(self, hop_nb64=None, hop_nb32=None, hop_tile64=None, hop_tile32=None, hop_order=None,
-             hop_tblock64=None, hop_tblock32=None, hop_tsites32=None, hop_rgroup=None, hop_tsites64=None):
+             hop_tblock64=None, hop_tblock32=None, hop_tsites32=None, hop_rgroup=None, hop_tsites64=None,
+             gemm_mfma=None, hop_rnest=None):
         """Set launch-shape parameters (see lqcd_tune_set)."""
         for code, v in ((0, hop_nb64), (1, hop_nb32), (2, hop_tile64), (3, hop_tile32), (4, hop_order),
                         (5, hop_tblock64), (6, hop_tblock32), (7, hop_tsites32), (8, hop_rgroup),
-                        (9, hop_tsites64)):
+                        (9, hop_tsites64), (10, gemm_mfma), (11, hop_rnest)):
             if v is not None:
                 _check(lib().lqcd_tune_set(self.handle, code, int(v)))
 
@@ -234,19 +252,24 @@ class Context:
         import torch
         eta = self.empty(nrhs)
         cd = torch.empty((nrhs,) + self.shape, dtype=torch.uint8, device="cuda") if codes else None
-        _check(lib().lqcd_noise_z4(self.handle, ctypes.c_uint64(seed), first, nrhs, _ptr(eta), _ptr(cd)))
+        _check(lib().lqcd_noise_z4(self.handle, ctypes.c_uint64(seed), first, nrhs, _ptr(eta),
+                                   _field(cd, nrhs, 12 * self.V, "codes", torch.uint8) if codes else None))
         return (eta, cd) if codes else eta
 
     def pack_eo(self, x, prec="f64"):
         import torch
         dt = torch.complex128 if prec == "f64" else torch.complex64
         out = torch.empty((x.shape[0], 2, 12, self.V // 2), dtype=dt, device="cuda")
-        _check(lib().lqcd_pack_eo(self.handle, _PREC[prec], _ptr(x), _ptr(out), x.shape[0]))
+        _check(lib().lqcd_pack_eo(self.handle, _PREC[prec], _field(x, x.shape[0], 12 * self.V, "x"),
+                                  _ptr(out), x.shape[0]))
         return out
 
     def unpack_eo(self, eo, prec="f64"):
+        import torch
         out = self.empty(eo.shape[0])
-        _check(lib().lqcd_unpack_eo(self.handle, _PREC[prec], _ptr(eo), _ptr(out), eo.shape[0]))
+        dt = torch.complex128 if prec == "f64" else torch.complex64
+        _check(lib().lqcd_unpack_eo(self.handle, _PREC[prec], _field(eo, eo.shape[0], 12 * self.V, "eo", dt),
+                                    _ptr(out), eo.shape[0]))
         return out
 
     def gamma5(self, x, out=None):
@@ -255,7 +278,9 @@ class Context:
         if x.numel() != x.shape[0] * 12 * self.V or x.dtype != torch.complex128:
             raise ValueError("gamma5 needs LEX complex128 fields of this lattice")
         out = torch.empty_like(x) if out is None else out
-        _check(lib().lqcd_gamma5(self.handle, _ptr(x), _ptr(out), x.shape[0]))
+        n = x.shape[0]
+        _check(lib().lqcd_gamma5(self.handle, _field(x, n, 12 * self.V, "x"),
+                                 _field(out, n, 12 * self.V, "out"), n))
         return out
 
     def wilson_apply(self, op, x, prec="f64", layout="lex", out=None):
@@ -265,7 +290,10 @@ class Context:
         if out is None:
             out = torch.empty_like(x)
         lay = LAYOUT_LEX if layout == "lex" else LAYOUT_EO
-        _check(lib().wilson_apply(self.handle, _OPS[op], _PREC[prec], lay, _ptr(x), _ptr(out), x.shape[0]))
+        dt = torch.complex128 if (lay == LAYOUT_LEX or prec == "f64") else torch.complex64
+        n = x.shape[0]
+        _check(lib().wilson_apply(self.handle, _OPS[op], _PREC[prec], lay, _field(x, n, 12 * self.V, "x", dt),
+                                  _field(out, n, 12 * self.V, "out", dt), n))
         return out
 
     # ----------------------------------------------------------- solvers
@@ -281,8 +309,8 @@ class Context:
                         rhs_block, proj_m, _METHODS[method])
         stats = (SolveStats * max(nrhs, 1))()
         h = _P(defl.handle.value if defl is not None else None)
-        code = lib().gmresdr_solve(self.handle, _OPS[op], ctypes.byref(p), _ptr(b), _ptr(x), nrhs,
-                                   ctypes.byref(h), stats)
+        code = lib().gmresdr_solve(self.handle, _OPS[op], ctypes.byref(p), _field(b, nrhs, 12 * self.V, "b"),
+                                   _field(x, nrhs, 12 * self.V, "x"), nrhs, ctypes.byref(h), stats)
         newdefl = Deflation(_P(h.value), self) if (defl is None and h.value) else defl
         _check(code)
         st = [dict(matvecs=s.matvecs, cycles=s.cycles, refinements=s.refinements, reorth=s.reorth,
@@ -295,7 +323,9 @@ class Context:
         xt = torch.empty_like(eta)
         th, thp, nth = _thetas(thetas)
         corr = np.zeros((nth, self.dims[3]), dtype=np.complex128)
-        _check(lib().pert_subtract(self.handle, order, thp, nth, _ptr(eta), _ptr(xt), eta.shape[0],
+        n = eta.shape[0]
+        _check(lib().pert_subtract(self.handle, order, thp, nth, _field(eta, n, 12 * self.V, "eta"),
+                                   _field(xt, n, 12 * self.V, "xt"), n,
                                    corr.ctypes.data_as(_P) if want_corr else None))
         return xt, corr
 
@@ -307,8 +337,11 @@ class Context:
             np.ascontiguousarray(coeffs, dtype=np.complex128).copy()
         a = np.zeros(degree + 1, dtype=np.complex128)
         corr = np.zeros((nth, self.dims[3]), dtype=np.complex128)
-        _check(lib().poly_subtract(self.handle, degree, _ptr(b), c.ctypes.data_as(_P),
-                                   a.ctypes.data_as(_P), thp, nth, _ptr(eta), _ptr(xt), eta.shape[0],
+        n = eta.shape[0]
+        bp = None if b is None else _field(b, 1, 12 * self.V, "b")
+        _check(lib().poly_subtract(self.handle, degree, bp, c.ctypes.data_as(_P),
+                                   a.ctypes.data_as(_P), thp, nth, _field(eta, n, 12 * self.V, "eta"),
+                                   _field(xt, n, 12 * self.V, "xt"), n,
                                    corr.ctypes.data_as(_P) if want_corr else None))
         return xt, corr, c, a
 
@@ -322,9 +355,11 @@ class Context:
             np.ascontiguousarray(corr, dtype=np.complex128).copy()
         cf, cfp = (None, None) if coeffs is None else _host(coeffs, np.complex128)
         xi = np.zeros(Q, dtype=np.complex128)
+        n = eta.shape[0]
         _check(lib().deflate_project(self.handle, defl.handle, Q, mode, cfp,
-                                     0 if coeffs is None else len(cf), thp, nth, _ptr(eta), _ptr(xt),
-                                     eta.shape[0], corr.ctypes.data_as(_P), xi.ctypes.data_as(_P)))
+                                     0 if coeffs is None else len(cf), thp, nth,
+                                     _field(eta, n, 12 * self.V, "eta"), _field(xt, n, 12 * self.V, "xt"),
+                                     n, corr.ctypes.data_as(_P), xi.ctypes.data_as(_P)))
         return xt, corr, xi
 
     def loop_estimate(self, eta, x, xt=None, corr=None, thetas=(0, 1, 2, 3, 4), samples=False):
@@ -338,7 +373,9 @@ class Context:
         if corr is not None:
             corr = np.ascontiguousarray(corr, dtype=np.complex128)
             cp = corr.ctypes.data_as(_P)
-        _check(lib().loop_estimate(self.handle, thp, nth, _ptr(eta), _ptr(x), _ptr(xt), nrhs, cp,
+        fv = 12 * self.V
+        _check(lib().loop_estimate(self.handle, thp, nth, _field(eta, nrhs, fv, "eta"), _field(x, nrhs, fv, "x"),
+                                   None if xt is None else _field(xt, nrhs, fv, "xt"), nrhs, cp,
                                    est.ctypes.data_as(_P), err.ctypes.data_as(_P),
                                    smp.ctypes.data_as(_P) if samples else None))
         return (est, err, smp) if samples else (est, err)
@@ -365,8 +402,11 @@ class Context:
         dk = np.zeros(1, dtype=np.complex128)
         dl = torch.empty(self.shape[:4] + (4, 8), dtype=torch.complex128, device="cuda") if links else None
         h = _P(defl.handle.value if defl is not None else None)
-        code = lib().loop_gradient(self.handle, thp, wp, nth, ctypes.byref(p), ctypes.byref(h), _ptr(eta),
-                                   _ptr(x), nrhs, dk.ctypes.data_as(_P), _ptr(dl), stats)
+        fv = 12 * self.V
+        code = lib().loop_gradient(self.handle, thp, wp, nth, ctypes.byref(p), ctypes.byref(h),
+                                   _field(eta, nrhs, fv, "eta"), None if x is None else _field(x, nrhs, fv, "x"),
+                                   nrhs, dk.ctypes.data_as(_P),
+                                   None if dl is None else _field(dl, 1, self.V * 32, "dlinks"), stats)
         newdefl = Deflation(_P(h.value), self) if (defl is None and h.value) else defl
         _check(code)
         st = [dict(matvecs=s.matvecs, cycles=s.cycles, refinements=s.refinements, reorth=s.reorth,
@@ -396,7 +436,17 @@ class Batch:
             pass
 
     def _ptrs(self, fields):
-        return (_P * len(fields))(*[(_ptr(f).value if f is not None and f.numel() else None) for f in fields])
+        """Device pointers of one LEX complex128 field list entry per lattice,
+        each checked against its lattice's volume."""
+        if len(fields) != len(self.contexts):
+            raise ValueError("one field list entry per lattice")
+        ptrs = []
+        for f, c in zip(fields, self.contexts):
+            if f is None or f.numel() == 0:
+                ptrs.append(None)
+            else:
+                ptrs.append(_field(f, f.shape[0], 12 * c.V, "field of lattice %s" % (c.dims,)).value)
+        return (_P * len(fields))(*ptrs)
 
     def set_grid(self, workgroups):
         _check(lib().lqcd_batch_set_grid(self.handle, int(workgroups)))

@@ -43,3 +43,19 @@ def test_invalid_arguments_are_reported_without_a_gpu_call():
     code = L.lqcd_create(dims, ctypes.c_void_p(1), 0.1, None, ctypes.byref(out))
     assert code == 1
     assert b"even" in L.lqcd_last_error()
+
+
+def test_binding_rejects_fields_of_the_wrong_type_or_size():
+    """The binding checks every field's dtype and element count before a
+    pointer reaches the library (a mismatch would let kernels run past the
+    allocation); host tensors are rejected as well."""
+    import torch
+    from paper_1903_06986_amd.lqcd import _field
+    with pytest.raises(ValueError, match="dtype"):
+        _field(torch.zeros(2 * 12 * 16, dtype=torch.complex64), 2, 12 * 16, "eta")
+    with pytest.raises(ValueError, match="elements"):
+        _field(torch.zeros(12 * 16, dtype=torch.complex128), 2, 12 * 16, "eta")
+    with pytest.raises(ValueError, match="GPU"):
+        _field(torch.zeros(2 * 12 * 16, dtype=torch.complex128), 2, 12 * 16, "eta")
+    with pytest.raises(TypeError):
+        _field([0.0], 1, 1, "eta")

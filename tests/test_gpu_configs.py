@@ -1,0 +1,283 @@
+"""GPU parity at the workloads' own sizes, where the oracle cannot run the
+whole path: sampled outputs that it computes one at a time, and properties
+that hold at any size.
+
+* 24^3 x 32, near-critical kappa*, links exp(i 0.2 H): the even/odd
+  operator through the link-tiled stencil with 8 and 16 right-hand sides,
+  FP32 input and 16-bit (FP16, BF16 per-site-scaled) input, against the
+  oracle's FP64 operator on sampled right-hand sides (first, middle and
+  last slot of a launch), within the storage bound; one mixed-precision
+  (FP16-stored) GMRES-Proj block of 16 noise vectors in the benchmark's
+  shape, whose residuals the oracle recomputes.
+* 16^3 x 32, kappa = 0.120, 4 noise vectors: every solution by the oracle's
+  residual; PS (order 7) vectors against the oracle's Horner; the Min-Res
+  coefficients (degree 7) against the oracle's QR, and the POLY vectors
+  against the oracle's Horner with its own coefficients; the estimator on
+  seeded fields against the oracle's samples.
+* The batching lattices (8^4 x 17, 12^3 x 24 x 64, 16^3 x 32 x 160
+  right-hand sides in one batched call): sampled solutions of every
+  lattice by the oracle's residual.
+* 12^4, kappa = 0.124, 32 noise vectors: d/dkappa and sampled link
+  derivatives of the fixed-noise estimate against central finite
+  differences of the estimate (solver tolerance 1e-13).
+
+Noise vectors come from the oracle's generator and are checked bit-exact
+against the GPU's on the sampled right-hand sides.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import require_gpu, to_gpu, to_host, say, rel_err
+from synth import random_su3_links, get_config
+from oracle import wilson as W
+from oracle import subtract as S
+from oracle import estimate as E
+from oracle import gradient as G
+from oracle.noise import z4_noise
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+BITS = {"f16": 10, "bf16": 7}
+
+
+def _c3_kappa():
+    with open(os.path.join(ROOT, "synth", "c3_kappa.json")) as f:
+        return json.load(f)["kappa"]
+
+
+def _resid(U, kappa, eta, x):
+    return np.linalg.norm(eta - W.apply_M(U, kappa, x)) / np.linalg.norm(eta)
+
+
+# ------------------------------------------------------------ 24^3 x 32
+@pytest.fixture(scope="module")
+def c3():
+    require_gpu()
+    from paper_1903_06986_amd import Context
+    cfg = get_config("c3")
+    dims, kappa = cfg["dims"], _c3_kappa()
+    say("c3 links", dims)
+    U = random_su3_links(dims, cfg["eps"], cfg["link_seed"])
+    ctx = Context(dims, U, kappa)
+    return cfg, dims, kappa, U, ctx
+
+
+@pytest.fixture(scope="module")
+def c3_fields(c3):
+    """16 random fields with per-site magnitudes spread over e^-1 .. e^1,
+    and the oracle's even/odd operator on the sampled ones."""
+    cfg, dims, kappa, U, ctx = c3
+    rng = np.random.default_rng(31)
+    shape = (16,) + ctx.shape
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    x *= np.exp(rng.uniform(-1, 1, size=shape[:5]))[..., None, None]
+    refs = {}
+    for r in (0, 7, 15):
+        say("c3 oracle Mhat", r)
+        refs[r] = W.apply_Mhat(U, kappa, x[r], dims)
+    return x, refs
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("nrhs", [8, 16])
+def test_c3_operator_tiled(c3, c3_fields, prec, nrhs):
+    cfg, dims, kappa, U, ctx = c3
+    x, refs = c3_fields
+    say("c3 schur", prec, nrhs)
+    y = ctx.wilson_apply("schur", to_gpu(x[:nrhs]), prec=prec)
+    for r in (0, 7, 15):
+        if r >= nrhs:
+            continue
+        got = to_host(y[r])
+        if prec == "f32":
+            assert rel_err(got, refs[r]) < 5e-6, (prec, nrhs, r)
+        else:
+            # each stored component errs by at most 2^-(p+1) of its site's
+            # scale (sqrt 2 for its two parts); Mhat = 1 - kappa^2 D_eo D_oe
+            # amplifies a per-site error by at most 1 + 64 kappa^2
+            bound = 2.0 ** -(BITS[prec] + 1) * np.sqrt(2) * (1 + 64 * kappa ** 2) * np.abs(x[r]).max()
+            assert np.abs(got - refs[r]).max() <= bound, (prec, nrhs, r)
+            assert np.abs(got - refs[r]).max() > 10 * 5e-6 * np.abs(refs[r]).max()  # it really rounds
+    del y
+
+
+def test_c3_mixed_block_residuals(c3):
+    """The benchmark's block: GMRES-DR(80,40) on eta^(0), then 16 noise
+    vectors by GMRES-Proj with FP32 arithmetic and FP16-stored inner basis
+    and stencil input inside FP64 refinement, to 1e-10."""
+    cfg, dims, kappa, U, ctx = c3
+    eta0 = ctx.noise_z4(cfg["noise_seed"], 0, 1)
+    say("c3 first solve")
+    _, defl, st0 = ctx.gmresdr_solve(eta0, op="schur", m=cfg["m"], k=cfg["k"], tol=1e-10, tol_super=1e-12,
+                                     eig_tol=1e-7, n_eig=30, max_cycles=2000)
+    eta = ctx.noise_z4(cfg["noise_seed"], 1, 16)
+    say("c3 mixed block")
+    x, _, st = ctx.gmresdr_solve(eta, op="schur", m=cfg["m"], k=cfg["k"], tol=1e-10, inner="f16",
+                                 inner_tol=1e-4, rhs_block=16, defl=defl, max_cycles=2000)
+    assert max(s["true_resid"] for s in st) <= 1e-10
+    for r in (0, 15):
+        e = z4_noise(cfg["noise_seed"], dims, 1 + r, 1)[0]
+        assert np.array_equal(to_host(eta[r]), e)
+        say("c3 oracle residual", r)
+        res = _resid(U, kappa, e, to_host(x[r]))
+        assert res <= 1.05e-10, (r, res)
+        assert abs(res - st[r]["true_resid"]) < 2e-12, (r, res, st[r]["true_resid"])
+    defl.free()
+
+
+# ------------------------------------------------------------ 16^3 x 32
+@pytest.fixture(scope="module")
+def c2():
+    require_gpu()
+    from paper_1903_06986_amd import Context
+    cfg = get_config("c2")
+    dims, kappa = cfg["dims"], cfg["kappas"][0]
+    say("c2 links", dims)
+    U = random_su3_links(dims, cfg["eps"], cfg["link_seed"])
+    ctx = Context(dims, U, kappa)
+    eta = z4_noise(cfg["noise_seed"], dims, 0, 4)
+    return cfg, dims, kappa, U, ctx, eta
+
+
+def test_c2_solutions(c2):
+    cfg, dims, kappa, U, ctx, eta = c2
+    eg = ctx.noise_z4(cfg["noise_seed"], 0, 4)
+    assert np.array_equal(to_host(eg), eta)
+    say("c2 solves")
+    x, defl, st = ctx.gmresdr_solve(eg, op="schur", m=cfg["m"], k=cfg["k"], tol=1e-10, tol_super=1e-12,
+                                    rhs_block=3)
+    x = to_host(x)
+    for r in range(4):
+        res = _resid(U, kappa, eta[r], x[r])
+        assert res <= 1.05e-10, (r, res)
+        assert abs(res - st[r]["true_resid"]) < 2e-12
+    defl.free()
+
+
+def test_c2_pert_and_poly(c2):
+    cfg, dims, kappa, U, ctx, eta = c2
+    eg = to_gpu(eta)
+    say("c2 PS7")
+    xt, _ = ctx.pert_subtract(7, eg, (0, 4), want_corr=False)
+    xt = to_host(xt)
+    for r in (0, 3):
+        assert rel_err(xt[r], S.pert_vector(U, kappa, eta[r], 7)) < 1e-12, r
+    say("c2 POLY7 coefficients")
+    xp, _, c_g, _ = ctx.poly_subtract(7, eg, b=eg[0:1], thetas=(0, 4), want_corr=False)
+    c_o, _ = S.poly_coeffs(U, kappa, eta[0], 7)
+    assert np.abs(c_g - c_o).max() < 1e-8 * np.abs(c_o).max()
+    # the vectors differ by sum_j (c_g - c_o)_j (kappa P)^j eta: bounded by
+    # |c_g - c_o|_1 max_j |(kappa P)^j eta| <= |c_g - c_o|_1 (8 kappa)^7 |eta|
+    xp = to_host(xp)
+    tol = np.abs(c_g - c_o).sum() * max(1.0, (8 * kappa) ** 7) + 1e-12 * np.abs(c_o).max()
+    for r in (1, 2):
+        ref = S.horner(U, kappa, eta[r], c_o)
+        assert np.abs(xp[r] - ref).max() <= tol * np.abs(eta[r]).max() + 1e-12 * np.abs(ref).max(), r
+
+
+def test_c2_estimator_on_seeded_fields(c2):
+    cfg, dims, kappa, U, ctx, eta = c2
+    rng = np.random.default_rng(41)
+    x = rng.standard_normal(eta.shape) + 1j * rng.standard_normal(eta.shape)
+    xt = rng.standard_normal(eta.shape) + 1j * rng.standard_normal(eta.shape)
+    corr = rng.standard_normal((5, dims[3])) + 1j * rng.standard_normal((5, dims[3]))
+    say("c2 estimator")
+    est, err, smp = ctx.loop_estimate(to_gpu(eta), to_gpu(x), to_gpu(xt), corr, (0, 1, 2, 3, 4), samples=True)
+    t = E.samples(eta, x, xt, (0, 1, 2, 3, 4), dims)
+    assert np.abs(smp - t).max() < 1e-12 * np.abs(t).max()
+    eref, sref = E.estimate(t, corr)
+    assert np.abs(est - eref).max() < 1e-12 * np.abs(eref).max()
+    assert np.abs(err - sref).max() < 1e-10 * np.abs(sref).max()
+
+
+# ------------------------------------------------------------ batching
+def test_c4_batched_solutions():
+    require_gpu()
+    from paper_1903_06986_amd import Batch, Context
+    cfg = get_config("c4")
+    kappa = cfg["kappas"][0]
+    ctxs, Us, defls, etas = [], [], [], []
+    for li, (dims, nr) in enumerate(zip(cfg["lattices"], cfg["n_rhs"])):
+        U = random_su3_links(dims, cfg["eps"], cfg["link_seed"] + li)
+        ctx = Context(dims, U, kappa)
+        say("c4 deflation", dims)
+        _, defl, _ = ctx.gmresdr_solve(ctx.noise_z4(cfg["noise_seed"] + li, 0, 1), op="schur", m=cfg["m"],
+                                       k=cfg["k"], tol=1e-10, tol_super=1e-12, max_cycles=2000)
+        ctxs.append(ctx)
+        Us.append(U)
+        defls.append(defl)
+        etas.append(ctx.noise_z4(cfg["noise_seed"] + li, 1, nr))
+    batch = Batch(ctxs)
+    say("c4 batched solve", sum(cfg["n_rhs"]))
+    xs, st = batch.solve(etas, defls, m=cfg["m"], k=cfg["k"], tol=1e-10, rhs_block=32, graph=True)
+    assert max(s["true_resid"] for s in st) <= 1e-10
+    off = 0
+    for li, (dims, nr) in enumerate(zip(cfg["lattices"], cfg["n_rhs"])):
+        for r in sorted({0, nr // 2, nr - 1}):
+            e = z4_noise(cfg["noise_seed"] + li, dims, 1 + r, 1)[0]
+            assert np.array_equal(to_host(etas[li][r]), e)
+            say("c4 oracle residual", dims, r)
+            res = _resid(Us[li], kappa, e, to_host(xs[li][r]))
+            assert res <= 1.05e-10, (dims, r, res)
+            assert abs(res - st[off + r]["true_resid"]) < 2e-12
+        off += nr
+    batch.close()
+
+
+# ------------------------------------------------------- differentiation
+def test_c5_gradient_vs_finite_differences():
+    """d/dkappa by a central difference with h = 1e-5 (truncation h^2 T'''
+    ~ 1e-10 relative; rounding ~ cond(M) tol |T| / h ~ 1e-7 relative).
+    Link derivatives: one link moves the whole-lattice trace by O(kappa h)
+    while the estimate's rounding stays ~ cond(M) tol 12 V ~ 1e-7, so they
+    take h = 1e-2 and one Richardson step (truncation O(h^4)), bar 1e-3
+    relative: far below the O(1) miss of a wrong site, direction or
+    generator at the production strides (the small-lattice tests pin the
+    values to the oracle's dense derivatives)."""
+    require_gpu()
+    from paper_1903_06986_amd import Context
+    cfg = get_config("c5")
+    dims, kappa = cfg["dims"], cfg["kappas"][0]
+    U = random_su3_links(dims, cfg["eps"], cfg["link_seed"])
+    ctx = Context(dims, U, kappa)
+    eta = ctx.noise_z4(cfg["noise_seed"], 0, cfg["n_noise"])
+    solve = dict(m=cfg["m"], k=cfg["k"], tol=1e-13, tol_super=1e-13, rhs_block=16, max_cycles=4000)
+    say("c5 loop_gradient", dims, cfg["n_noise"])
+    dk, dl, _, st = ctx.loop_gradient(eta, None, thetas=(0,), **solve)
+    assert max(s["true_resid"] for s in st) < 1e-12
+    dl = to_host(dl)
+
+    def estimate(c):
+        x, d, _ = c.gmresdr_solve(eta, op="schur", **solve)
+        d.free()
+        est, _ = c.loop_estimate(eta, x, thetas=(0,))
+        return est[0, -1]
+
+    h = 1e-5
+    ctx.set_kappa(kappa + h)
+    fp = estimate(ctx)
+    ctx.set_kappa(kappa - h)
+    fm = estimate(ctx)
+    ctx.set_kappa(kappa)
+    fd = (fp - fm) / (2 * h)
+    assert abs(fd - dk) < 1e-6 * abs(dk), (fd, dk)
+    Lx, Ly, Lz, _ = dims
+    for site, mu, a in ((0, 0, 0), (1234, 1, 3), (5000, 2, 5), (20735, 3, 7)):
+        c = [site % Lx, (site // Lx) % Ly, (site // (Lx * Ly)) % Lz, site // (Lx * Ly * Lz)]
+        say("c5 link fd", site, mu, a)
+
+        def f_link(hh):
+            c2 = Context(dims, G.rotate_link(U, site, mu, a, hh, dims), kappa)
+            v = estimate(c2)
+            c2.close()
+            return v
+
+        hl = 1e-2
+        d1 = (f_link(hl) - f_link(-hl)) / (2 * hl)
+        d2 = (f_link(hl / 2) - f_link(-hl / 2)) / hl
+        an = dl[c[3], c[2], c[1], c[0], mu, a]
+        assert abs((4 * d2 - d1) / 3 - an) < 1e-3 * max(abs(an), 1e-2), (site, mu, a, an, (4 * d2 - d1) / 3)

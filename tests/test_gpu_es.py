@@ -69,6 +69,7 @@ def test_eigenvalue_subtraction_rejects_hermitian_space():
     dims = (4, 4, 2, 4)
     ctx, U = context(dims, 0.3, 31, 0.125)
     eta = z4_noise(7, dims, 0, 1)
-    _, hdefl, _ = ctx.gmresdr_solve(to_gpu(eta), op="MG5", m=20, k=10, tol=1e-8, max_cycles=50)
+    _, hdefl, _ = ctx.gmresdr_solve(to_gpu(eta), op="MG5", m=20, k=10, tol=1e-8, tol_super=1e-8,
+                                    max_cycles=50)
     with pytest.raises(LqcdError):
         ctx.deflate_project(hdefl, 4, to_gpu(eta), xt=torch.zeros_like(to_gpu(eta)), mode=lqcd.DEFL_ES)

@@ -212,6 +212,30 @@ def test_minres_dr_rejects_non_hermitian_operator():
         ctx.gmresdr_solve(to_gpu(eta), op="schur", m=20, k=10, method="minres-dr")
 
 
+@pytest.mark.parametrize("op,method", [("schur", "gmres-dr"), ("MG5", "gmres-dr"), ("MG5", "minres-dr")])
+def test_first_rhs_cut_off_by_max_cycles_is_enoconv(op, method):
+    """Two cycles of GMRES-DR(8,4) / MINRES-DR(8,4) cannot reach 1e-12 on
+    a 4^4 lattice near kappa 0.13: the call must report ENOCONV (with the
+    deflation space still handed back), not LQCD_OK."""
+    require_gpu()
+    import ctypes
+    from paper_1903_06986_amd import lqcd
+    dims = (4, 4, 4, 4)
+    ctx, U = context(dims, 0.3, 33, 0.13)
+    eta = to_gpu(z4_noise(6, dims, 0, 2))
+    say("solve cut off", op, method)
+    x = eta.clone()
+    p = lqcd.SolveParams(8, 4, 2, 1e-12, 1e-12, 0.0, 0, lqcd.F64, 1e-5, 1, 0, lqcd._METHODS[method])
+    st = (lqcd.SolveStats * 2)()
+    h = ctypes.c_void_p(None)
+    code = lqcd.lib().gmresdr_solve(ctx.handle, lqcd._OPS[op], ctypes.byref(p), lqcd._ptr(eta),
+                                    lqcd._ptr(x), 2, ctypes.byref(h), st)
+    assert code == 4, code                       # LQCD_ENOCONV
+    assert h.value is not None                   # the deflation space is returned
+    assert st[0].cycles == 2 and st[0].true_resid > 1e-12
+    lqcd.lib().lqcd_defl_free(h)
+
+
 @pytest.mark.parametrize("dims,kappa,nrhs,block", [((4, 4, 4, 4), 0.12, 5, 4), ((6, 4, 2, 8), 0.13, 5, 4),
                                                     ((4, 4, 4, 4), 0.12, 12, 12)])
 def test_mixed_precision_solve(dims, kappa, nrhs, block):
@@ -242,3 +266,39 @@ def test_full_size_true_residual_16x32():
         res = np.linalg.norm(eta[r] - W.apply_M(U, kappa, x[r])) / np.linalg.norm(eta[r])
         assert res < 1.5e-10, (r, res)
         assert abs(res - st[r]["true_resid"]) < 1e-12
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_matrix_core_deflation_products(inner):
+    """The deflation products V C with one shared basis (GMRES-Proj's
+    x += V_k d and r -= V_{k+1} Hbar d for a block of right-hand sides, the
+    Rayleigh-Ritz eigenvectors, the hermitian projections) run on the
+    matrix cores; the FMA kernel is the reference.  Both give the LU
+    solution to 1e-9 (their iterates differ by rounding only, so the two
+    solutions agree to the solver tolerance), and the Rayleigh-Ritz
+    eigenvalues of the same hermitian space agree to 1e-12."""
+    require_gpu()
+    dims, kappa = (6, 4, 2, 8), 0.13
+    ctx, U = context(dims, 0.3, 1001, kappa)
+    eta = z4_noise(2001, dims, 0, 13)
+    xs = []
+    for mfma in (0, 1):
+        ctx.tune(gemm_mfma=mfma)
+        say("solve gemm_mfma", mfma, inner)
+        x, defl, st = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=20, k=10, tol=1e-11, tol_super=1e-13,
+                                        inner=inner, inner_tol=1e-5, rhs_block=13)
+        assert max(s["true_resid"] for s in st) < 1e-11
+        xs.append(to_host(x))
+        _, hdefl, _ = ctx.gmresdr_solve(to_gpu(eta[:1]), op="MG5", m=30, k=18, tol=1e-12, tol_super=1e-13,
+                                        eig_tol=1e-11, n_eig=12, max_cycles=400)
+        lam, res = hdefl.eigpairs(12)
+        if mfma == 0:
+            lam0 = lam
+        else:
+            assert np.abs(lam - lam0).max() < 1e-10
+    ctx.tune(gemm_mfma=1)
+    xref, _ = _dense_solve(U, kappa, dims, eta)
+    for x in xs:
+        for r in range(13):
+            assert rel_err(x[r], xref[r]) < 1e-9
+    assert rel_err(xs[0], xs[1]) < 1e-9

@@ -119,9 +119,12 @@ def test_full_size_operator_16x32():
 # 0 timeslices = tiles of consecutive sites in index order, 0 right-hand
 # sides = one group.  Launches with fewer right-hand sides than a tile's
 # pass (256 / sites) take the next larger tile.
-TILE_SHAPES = [(0, 64, 0), (1, 64, 0), (3, 64, 0), (64, 64, 0), (0, 32, 0), (2, 32, 0), (-1, 32, 0),
-               (-1, 32, 4), (2, 64, 4), (0, 32, 8), (0, 16, 0), (-1, 16, 0), (2, 16, 0), (-1, 16, 16),
-               (1, 16, 4)]
+# The fourth entry: right-hand sides per group swept in turn within each
+# block of timeslices (plane order only; 0 = off).
+TILE_SHAPES = [(0, 64, 0, 0), (1, 64, 0, 0), (3, 64, 0, 0), (64, 64, 0, 0), (0, 32, 0, 0), (2, 32, 0, 0),
+               (-1, 32, 0, 0), (-1, 32, 4, 0), (2, 64, 4, 0), (0, 32, 8, 0), (0, 16, 0, 0), (-1, 16, 0, 0),
+               (2, 16, 0, 0), (-1, 16, 16, 0), (1, 16, 4, 0), (-1, 32, 0, 4), (2, 16, 0, 8), (1, 32, 0, 3),
+               (3, 64, 4, 2), (0, 32, 0, 4)]
 
 
 @pytest.mark.parametrize("dims", [(2, 2, 2, 4), (6, 6, 2, 4), (6, 4, 2, 8), (8, 6, 2, 6)])
@@ -148,13 +151,13 @@ def test_link_tiled_stencil(dims, prec, nrhs):
         y0 = to_host(ctx.wilson_apply(op, to_gpu(x), prec=prec))
         tol = {"f64": 1e-13, "f32": 5e-6, "f16": 2e-3, "bf16": 1.6e-2}[prec]
         assert rel_err(y0, _oracle_op(op, U, kappa, x, dims)) < tol, op
-        for tb, ts, rg in TILE_SHAPES:
-            say("tiled stencil", op, prec, dims, nrhs, "tblock", tb, "tsites", ts, "rgroup", rg)
+        for tb, ts, rg, rn in TILE_SHAPES:
+            say("tiled stencil", op, prec, dims, nrhs, "tblock", tb, "tsites", ts, "rgroup", rg, "rnest", rn)
             ctx.tune(hop_tile64=1, hop_tile32=1, hop_tblock64=tb, hop_tblock32=tb, hop_tsites32=ts, hop_rgroup=rg,
-                     hop_tsites64=min(ts, 32))
+                     hop_tsites64=min(ts, 32), hop_rnest=rn)
             y = to_host(ctx.wilson_apply(op, to_gpu(x), prec=prec))
             d = rel_err(y, y0)
-            assert d < {"f64": 1e-14, "f32": 1e-6, "f16": 1e-6, "bf16": 1e-6}[prec], (op, tb, ts, rg, d)
-            assert rel_err(y, _oracle_op(op, U, kappa, x, dims)) < tol, (op, tb, ts, rg)
+            assert d < {"f64": 1e-14, "f32": 1e-6, "f16": 1e-6, "bf16": 1e-6}[prec], (op, tb, ts, rg, rn, d)
+            assert rel_err(y, _oracle_op(op, U, kappa, x, dims)) < tol, (op, tb, ts, rg, rn)
     ctx.tune(hop_tile64=1, hop_tile32=1, hop_tblock64=-1, hop_tblock32=-1, hop_tsites32=32, hop_rgroup=0,
-             hop_tsites64=32)
+             hop_tsites64=32, hop_rnest=0)

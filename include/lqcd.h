@@ -278,6 +278,19 @@ lqcd_status loop_estimate(lqcd_ctx *ctx, const int *thetas_host, int ntheta, con
                           const double *trace_corr_host, double *est_host,
                           double *stderr_host, double *samples_host);
 
+/* Allocation-free form of loop_estimate, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, results and
+ * errors, with the per-workgroup partial sums in a fixed device array of
+ * 4 MiB per GPU, held by the library until the process ends, instead of a
+ * context workspace that grows on first use.  It calls no hipMalloc or
+ * hipFree.  EINVAL when nrhs * 9 * Lt * 2 partial sums exceed 2^19 (e.g.
+ * nrhs > 910 at Lt = 32).  Every call on one GPU uses that GPU's array:
+ * calls that overlap on one GPU (other streams or host threads) race. */
+lqcd_status loop_estimate_noalloc(lqcd_ctx *ctx, const int *thetas_host, int ntheta, const void *eta,
+                                  const void *x, const void *xt, int nrhs, const double *trace_corr_host,
+                                  double *est_host, double *stderr_host, double *samples_host);
+
 /* Derivatives of the trace estimate (differentiation of Eq. (23) with
  * M = 1 - kappa P of Sec. 5.1 Eqs. (24)-(25); the adjoint uses the
  * g5-hermiticity of Sec. 5.4).  For the fixed-noise estimate

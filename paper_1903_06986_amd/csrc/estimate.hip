@@ -5,6 +5,7 @@
 // lexicographic layout keeps each timeslice contiguous.  Standard errors are
 // s / sqrt(N) with the unbiased sample variance, for Re and Im separately.
 #include <cmath>
+#include <mutex>
 
 #include "cplx.h"
 #include "gamma.h"
@@ -205,11 +206,40 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// Scratch of the allocation-free entry point loop_estimate_noalloc: the
+// per-workgroup partial sums, in a fixed device array (one copy per GPU,
+// held until the process ends).  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocDoubles = size_t(1) << 19;  // 4 MiB
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mu;
+double *noalloc_ptr[kMaxDevices] = {};
+
+// The scratch array's device address on the current device, looked up on
+// the first call there.
+double *noalloc_scratch() {
+  int dev = 0;
+  LQCD_HIP(hipGetDevice(&dev));
+  LQCD_CHECK(dev >= 0 && dev < kMaxDevices, LQCD_EDEVICE, "loop_estimate_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void *p = nullptr;
+    LQCD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    noalloc_ptr[dev] = static_cast<double *>(p);
+  }
+  return noalloc_ptr[dev];
+}
+
 // Chunks per timeslice: about 2048 workgroups in all, at least one site
-// block each.
-int estimate_chunks(const Geom &g, int nrhs) {
+// block each, and at most cap_doubles of partial sums (0: no cap).
+int estimate_chunks(const Geom &g, int nrhs, size_t cap_doubles) {
   const int Lt = g.L[3], Vs = g.V / Lt;
-  return std::max(1, std::min((Vs + kBlock / 4 - 1) / (kBlock / 4), (2048 + Lt * nrhs - 1) / (Lt * nrhs)));
+  int nch = std::max(1, std::min((Vs + kBlock / 4 - 1) / (kBlock / 4), (2048 + Lt * nrhs - 1) / (Lt * nrhs)));
+  if (cap_doubles)
+    nch = std::max(1, std::min<int>(nch, int(cap_doubles / (size_t(nrhs) * kNumOps * Lt * 2))));
+  return nch;
 }
 
 // The estimator with its partial sums in d (at least
@@ -317,9 +347,25 @@ extern "C" lqcd_status loop_estimate(lqcd_ctx *c, const int *thetas, int nth, co
                                      double *est, double *stderr_, double *samples) {
   return guarded([&] {
     check_args(c, thetas, nth, eta, x, nrhs, est, stderr_, "loop_estimate");
-    const int nch = estimate_chunks(c->g, nrhs);
+    const int nch = estimate_chunks(c->g, nrhs, 0);
     double *d = static_cast<double *>(
         c->red.ensure(size_t(nrhs) * kNumOps * c->g.L[3] * nch * 2 * sizeof(double)));
+    estimate_with(c, thetas, nth, eta, x, xt, nrhs, corr, est, stderr_, samples, d, nch);
+  });
+}
+
+extern "C" lqcd_status loop_estimate_noalloc(lqcd_ctx *c, const int *thetas, int nth, const void *eta,
+                                             const void *x, const void *xt, int nrhs, const double *corr,
+                                             double *est, double *stderr_, double *samples) {
+  return guarded([&] {
+    check_args(c, thetas, nth, eta, x, nrhs, est, stderr_, "loop_estimate_noalloc");
+    const size_t one = size_t(nrhs) * kNumOps * c->g.L[3] * 2;
+    LQCD_CHECK(one <= kNoallocDoubles, LQCD_EINVAL,
+               "loop_estimate_noalloc: %d right-hand sides x %d timeslices need %zu partial sums, more than "
+               "the fixed scratch of %zu (use loop_estimate)",
+               nrhs, c->g.L[3], one, kNoallocDoubles);
+    double *d = noalloc_scratch();
+    const int nch = estimate_chunks(c->g, nrhs, kNoallocDoubles);
     estimate_with(c, thetas, nth, eta, x, xt, nrhs, corr, est, stderr_, samples, d, nch);
   });
 }

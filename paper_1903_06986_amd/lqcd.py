@@ -70,6 +70,7 @@ _SIGS = {
     "pert_subtract": [_P, _I, _P, _I, _P, _P, _I, _P],
     "poly_subtract": [_P, _I, _P, _P, _P, _P, _I, _P, _P, _I, _P],
     "loop_estimate": [_P, _P, _I, _P, _P, _P, _I, _P, _P, _P, _P],
+    "loop_estimate_noalloc": [_P, _P, _I, _P, _P, _P, _I, _P, _P, _P, _P],
     "loop_gradient": [_P, _P, _P, _I, ctypes.POINTER(SolveParams), ctypes.POINTER(_P), _P, _P, _I,
                       _P, _P, ctypes.POINTER(SolveStats)],
     "lqcd_batch_create": [_P, _I, ctypes.POINTER(_P)],
@@ -362,7 +363,9 @@ class Context:
                                      n, corr.ctypes.data_as(_P), xi.ctypes.data_as(_P)))
         return xt, corr, xi
 
-    def loop_estimate(self, eta, x, xt=None, corr=None, thetas=(0, 1, 2, 3, 4), samples=False):
+    def loop_estimate(self, eta, x, xt=None, corr=None, thetas=(0, 1, 2, 3, 4), samples=False, noalloc=False):
+        """noalloc: call loop_estimate_noalloc (partial sums in the library's
+        fixed device scratch instead of a context workspace)."""
         th, thp, nth = _thetas(thetas)
         Lt = self.dims[3]
         nrhs = eta.shape[0]
@@ -374,7 +377,8 @@ class Context:
             corr = np.ascontiguousarray(corr, dtype=np.complex128)
             cp = corr.ctypes.data_as(_P)
         fv = 12 * self.V
-        _check(lib().loop_estimate(self.handle, thp, nth, _field(eta, nrhs, fv, "eta"), _field(x, nrhs, fv, "x"),
+        fn = lib().loop_estimate_noalloc if noalloc else lib().loop_estimate
+        _check(fn(self.handle, thp, nth, _field(eta, nrhs, fv, "eta"), _field(x, nrhs, fv, "x"),
                                    None if xt is None else _field(xt, nrhs, fv, "xt"), nrhs, cp,
                                    est.ctypes.data_as(_P), err.ctypes.data_as(_P),
                                    smp.ctypes.data_as(_P) if samples else None))

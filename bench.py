@@ -57,11 +57,6 @@ def workload(name, kappa_override=None):
     return cfg, kappa
 
 
-def source_sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
-
-
 def traffic_for(kernel_class, bytes_per_launch):
     """HBM traffic per launch of a kernel class from committed rocprofv3
     counter summaries: their ratio of HBM to algorithmic bytes, taken on the
@@ -74,8 +69,9 @@ def traffic_for(kernel_class, bytes_per_launch):
         return None
     with open(p) as f:
         t = json.load(f)
-    src = os.path.join(ROOT, "paper_1903_06986_amd", "csrc", t["source"])
-    if source_sha(src) != t["source_sha"]:
+    names = t["sources"] if "sources" in t else [t["source"]]
+    blob = b"".join(open(os.path.join(ROOT, "paper_1903_06986_amd", "csrc", n), "rb").read() for n in names)
+    if hashlib.sha256(blob).hexdigest()[:16] != t["source_sha"]:
         return None
     alg = t.get("algorithmic_bytes_per_launch")
     if not alg:

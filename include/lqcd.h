@@ -409,7 +409,8 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * 0 = one group.  LQCD_TUNE_HOP_RNEST (plane order only): groups of this many
  * right-hand sides are swept in turn within each XCD's block of timeslices
  * (its L2 then holds one group's planes at a time; the block's links are
- * read once per group); 0 = off, and it takes precedence over
+ * read once per group); 0 = off, -1 (default) = automatic: groups of 8 in
+ * FP64, off in FP32; a nonzero group size takes precedence over
  * LQCD_TUNE_HOP_RGROUP.  LQCD_TUNE_GEMM_MFMA: 1 (default) runs the deflation
  * and eigenvector products V C whose columns share one basis (J <= 64
  * vectors, two or more columns) on the matrix cores; 0 uses the FMA

@@ -142,7 +142,7 @@ struct lqcd_ctx {
   int hop_tblock[2] = {-1, -1};  // tiled stencil: timeslices per plane block (0: flat order, -1: auto), FP64, FP32
   int hop_tsites[2] = {32, 32};  // tiled stencil: sites per tile, FP64 (16, 32), FP32 (16, 32, 64)
   int hop_rgroup = 0;            // tiled stencil: right-hand sides per group (0: all in one)
-  int hop_rnest = 0;             // tiled stencil: groups swept in turn within each block (0: off)
+  int hop_rnest = -1;            // tiled stencil: groups swept in turn within each block (0: off, -1: auto)
   int gemm_mfma = 1;             // V C with one shared basis on the matrix cores (0: FMA kernel)
   ~lqcd_ctx();
 };

@@ -204,7 +204,8 @@ extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int val
         c->hop_tsites[0] = value;
         break;
       case LQCD_TUNE_HOP_RNEST:
-        LQCD_CHECK(value >= 0 && value <= 4096, LQCD_EINVAL, "lqcd_tune_set: right-hand sides per nested group in 0..4096");
+        LQCD_CHECK(value >= -1 && value <= 4096, LQCD_EINVAL,
+                   "lqcd_tune_set: right-hand sides per nested group in -1..4096");
         c->hop_rnest = value;
         break;
       case LQCD_TUNE_GEMM_MFMA:

@@ -349,7 +349,14 @@ void launch_hop_tile(lqcd_ctx *c, Timed &tm, int p, const cx<R> *U, SI in, SS se
   } else {
     ntile = int((g.Vh + T - 1) / T);
   }
-  const int rn = c->hop_rnest, rg = rn > 0 && map.tb > 0 ? rn : c->hop_rgroup;
+  // nested groups: automatic (-1) in FP64 only, groups of 8 right-hand
+  // sides, whose planes (8 x 192 B per site) then stay in an XCD's L2 across
+  // its block (24^3 x 32, 16 right-hand sides: 741 -> 671 us and 650 -> 592
+  // us for the two halves); in FP32 the staged links' cost per workgroup
+  // outweighs it (288 -> 313 us), so off
+  int rn = c->hop_rnest;
+  if (rn < 0) rn = std::is_same<R, double>::value ? 8 : 0;
+  const int rg = rn > 0 && map.tb > 0 ? rn : c->hop_rgroup;
   if (rg > 0 && rg < nrhs) {
     map.rg = rg;
     map.ntg = ntile;

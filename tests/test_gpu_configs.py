@@ -180,14 +180,17 @@ def test_c2_pert_and_poly(c2):
 
 
 def test_c2_estimator_on_seeded_fields(c2):
+    """All nine operators: scalar, local vector, point-split vector."""
+    from oracle import pointsplit as PSO
     cfg, dims, kappa, U, ctx, eta = c2
     rng = np.random.default_rng(41)
     x = rng.standard_normal(eta.shape) + 1j * rng.standard_normal(eta.shape)
     xt = rng.standard_normal(eta.shape) + 1j * rng.standard_normal(eta.shape)
-    corr = rng.standard_normal((5, dims[3])) + 1j * rng.standard_normal((5, dims[3]))
+    corr = rng.standard_normal((9, dims[3])) + 1j * rng.standard_normal((9, dims[3]))
     say("c2 estimator")
-    est, err, smp = ctx.loop_estimate(to_gpu(eta), to_gpu(x), to_gpu(xt), corr, (0, 1, 2, 3, 4), samples=True)
-    t = E.samples(eta, x, xt, (0, 1, 2, 3, 4), dims)
+    est, err, smp = ctx.loop_estimate(to_gpu(eta), to_gpu(x), to_gpu(xt), corr, tuple(range(9)), samples=True)
+    t = np.concatenate([E.samples(eta, x, xt, (0, 1, 2, 3, 4), dims),
+                        PSO.samples_ps(U, kappa, eta, x, xt, range(4), dims)], axis=1)
     assert np.abs(smp - t).max() < 1e-12 * np.abs(t).max()
     eref, sref = E.estimate(t, corr)
     assert np.abs(est - eref).max() < 1e-12 * np.abs(eref).max()

@@ -124,7 +124,7 @@ def test_full_size_operator_16x32():
 TILE_SHAPES = [(0, 64, 0, 0), (1, 64, 0, 0), (3, 64, 0, 0), (64, 64, 0, 0), (0, 32, 0, 0), (2, 32, 0, 0),
                (-1, 32, 0, 0), (-1, 32, 4, 0), (2, 64, 4, 0), (0, 32, 8, 0), (0, 16, 0, 0), (-1, 16, 0, 0),
                (2, 16, 0, 0), (-1, 16, 16, 0), (1, 16, 4, 0), (-1, 32, 0, 4), (2, 16, 0, 8), (1, 32, 0, 3),
-               (3, 64, 4, 2), (0, 32, 0, 4)]
+               (3, 64, 4, 2), (0, 32, 0, 4), (-1, 32, 0, -1), (2, 16, 4, -1)]
 
 
 @pytest.mark.parametrize("dims", [(2, 2, 2, 4), (6, 6, 2, 4), (6, 4, 2, 8), (8, 6, 2, 6)])
@@ -160,4 +160,4 @@ def test_link_tiled_stencil(dims, prec, nrhs):
             assert d < {"f64": 1e-14, "f32": 1e-6, "f16": 1e-6, "bf16": 1e-6}[prec], (op, tb, ts, rg, rn, d)
             assert rel_err(y, _oracle_op(op, U, kappa, x, dims)) < tol, (op, tb, ts, rg, rn)
     ctx.tune(hop_tile64=1, hop_tile32=1, hop_tblock64=-1, hop_tblock32=-1, hop_tsites32=32, hop_rgroup=0,
-             hop_tsites64=32, hop_rnest=0)
+             hop_tsites64=32, hop_rnest=-1)

@@ -414,7 +414,10 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * LQCD_TUNE_HOP_RGROUP.  LQCD_TUNE_GEMM_MFMA: 1 (default) runs the deflation
  * and eigenvector products V C whose columns share one basis (J <= 64
  * vectors, two or more columns) on the matrix cores; 0 uses the FMA
- * kernel.  Values are per context; EINVAL for other values. */
+ * kernel.  LQCD_TUNE_CYCLE_REORTH: 0 (default) runs the second
+ * Gram-Schmidt pass of the GMRES-Proj cycles only where the first pass
+ * cancelled more than one digit; 1 runs it on every step (a check of that
+ * pass; slower).  Values are per context; EINVAL for other values. */
 typedef enum {
   LQCD_TUNE_HOP_NB64 = 0,
   LQCD_TUNE_HOP_NB32 = 1,
@@ -427,7 +430,8 @@ typedef enum {
   LQCD_TUNE_HOP_RGROUP = 8,
   LQCD_TUNE_HOP_TSITES64 = 9,
   LQCD_TUNE_GEMM_MFMA = 10,
-  LQCD_TUNE_HOP_RNEST = 11
+  LQCD_TUNE_HOP_RNEST = 11,
+  LQCD_TUNE_CYCLE_REORTH = 12
 } lqcd_tune_param;
 lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 

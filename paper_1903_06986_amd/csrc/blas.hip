@@ -450,10 +450,12 @@ __device__ inline void hraw_load(const uint32_t *v, size_t Vh, size_t i, HRaw &r
 }
 
 // Partial dot products per wave: part[r][wave chunk][j] (as k_mdot_part).
-template <HKind K>
+// The vector w is FP32 (component-major) or, with W16, a stored 16-bit
+// vector (w_rs then in words), decoded once per lane.
+template <HKind K, bool W16>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 8)))
     k_hmdot_part(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
-                 const cx<float> *__restrict__ w, size_t w_rs, size_t Vh,
+                 const void *__restrict__ wp, size_t w_rs, size_t Vh,
                  double *__restrict__ part, const int *__restrict__ flag) {
   const int lane = threadIdx.x & 63;
   const int r = blockIdx.y;
@@ -461,12 +463,22 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 
   const size_t nwch = size_t(gridDim.x) * kWaves;
   const size_t chunk = size_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
   V += r * V_rs;
-  w += r * w_rs;
   const size_t i = chunk * 64 + lane;  // the lane's site
   const bool on = i < Vh;
   cx<float> wv[12];
+  if constexpr (W16) {
+    HRaw q{};
+    if (on) hraw_load(static_cast<const uint32_t *>(wp) + r * w_rs, Vh, i, q);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) wv[c] = on ? ldc(w + c * Vh + i) : mk(0.f, 0.f);
+    for (int c = 0; c < 12; ++c) {
+      const cx<float> v = Codec<K>::unpack(q.w(c));
+      wv[c] = on ? mk(q.sc * v.re, q.sc * v.im) : mk(0.f, 0.f);
+    }
+  } else {
+    const cx<float> *w = static_cast<const cx<float> *>(wp) + r * w_rs;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) wv[c] = on ? ldc(w + c * Vh + i) : mk(0.f, 0.f);
+  }
   double *po = part + (size_t(r) * nwch + chunk) * size_t(J) * 2;
   // software pipeline over the basis, two vectors deep: vector j + 2's
   // loads go out before vector j is used (a lane streams 52 bytes per
@@ -547,6 +559,101 @@ __global__ void __launch_bounds__(kBlock)
     block_sum<1>(nrm, sh);
     if (threadIdx.x == 0) part[size_t(r) * nblk + b] = nrm[0];
   }
+}
+
+// Site i of a stored vector: the 24 reals a[] / m in three 16-byte
+// granules and the scale m = max |re|, |im| (0 for a zero site).  Returns
+// the site's |decoded|^2.
+template <HKind K>
+__device__ inline float hstore_site(uint32_t *out, size_t Vh, size_t i, const cx<float> a[12]) {
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  float m = 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(a[c].re), fabsf(a[c].im)));
+  const float inv = m > 0.f ? 1.0f / m : 0.f;
+  float n2 = 0.f;
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    u4v q;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t u = Codec<K>::pack(inv * a[4 * g + k].re, inv * a[4 * g + k].im);
+      q[k] = u;
+      const cx<float> d = Codec<K>::unpack(u);
+      n2 += d.re * d.re + d.im * d.im;
+    }
+    __builtin_nontemporal_store(q, reinterpret_cast<u4v *>(out + hword(4 * g, i, Vh)));
+  }
+  __builtin_nontemporal_store(__float_as_uint(m), out + 12 * Vh + i);
+  return m * m * n2;
+}
+
+// Gram-Schmidt update straight into the 16-bit basis: out_r = stored(w_r -
+// V_r coef_r) with per-site scales, not normalised (the per-site scales
+// absorb the norm: k_hscale multiplies them by 1/|w| afterwards), and the
+// |w|^2 partials of the stored values.  w is FP32 (component-major) or,
+// with W16, out itself: a second pass in place (each lane reads its own
+// site before it writes it; the basis vectors read are other slots).
+template <HKind K, bool W16>
+__global__ void __launch_bounds__(kBlock)
+    k_hmaxpy_q(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
+               const cx<double> *__restrict__ coef, size_t coef_rs, const cx<float> *__restrict__ w,
+               size_t w_rs, uint32_t *out, size_t out_rs, size_t Vh, double *__restrict__ part,
+               const int *__restrict__ flag) {
+  __shared__ double sh[1][kWaves];
+  const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
+  if (flag && flag[r] == 0) return;
+  V += r * V_rs;
+  out += r * out_rs;
+  coef += r * coef_rs;
+  const size_t i = size_t(b) * kBlock + threadIdx.x;
+  const bool on = i < Vh;
+  double nrm[1] = {0};
+  if (on) {
+    cx<float> a[12];
+    if constexpr (W16) {
+      HRaw q;
+      hraw_load(out, Vh, i, q);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const cx<float> v = Codec<K>::unpack(q.w(c));
+        a[c] = mk(q.sc * v.re, q.sc * v.im);
+      }
+    } else {
+      w += r * w_rs;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) a[c] = ldc(w + c * Vh + i);
+    }
+    // the same two-deep pipeline over the basis as k_hmaxpy
+    HRaw cur, nx1, nx2;
+    if (J > 0) hraw_load(V, Vh, i, cur);
+    if (J > 1) hraw_load(V + ldv, Vh, i, nx1);
+    for (int j = 0; j < J; ++j) {
+      if (j + 2 < J) hraw_load(V + size_t(j + 2) * ldv, Vh, i, nx2);
+      const cx<double> cd = coef[j];
+      const cx<float> ca = mk(cur.sc * float(cd.re), cur.sc * float(cd.im));
+#pragma unroll
+      for (int c = 0; c < 12; ++c) a[c] = a[c] - Codec<K>::unpack(cur.w(c)) * ca;
+      cur = nx1;
+      nx1 = nx2;
+    }
+    nrm[0] = double(hstore_site<K>(out, Vh, i, a));
+  }
+  if (part) {
+    block_sum<1>(nrm, sh);
+    if (threadIdx.x == 0) part[size_t(r) * nblk + b] = nrm[0];
+  }
+}
+
+// Per-site scales of stored vectors times f[r] (normalises a vector that
+// k_hmaxpy_q left unnormalised).
+__global__ void __launch_bounds__(kBlock)
+    k_hscale(uint32_t *__restrict__ x, size_t x_rs, size_t Vh, const double *__restrict__ f) {
+  const int r = blockIdx.y;
+  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= Vh) return;
+  uint32_t *p = x + r * x_rs + 12 * Vh + i;
+  *p = __float_as_uint(__uint_as_float(*p) * float(f[r]));
 }
 
 // Y_r += alpha * V_r C_r for one column per right-hand side (nb = 1 per r).
@@ -1119,7 +1226,7 @@ inline double hbytes(size_t n) { return 52.0 * double(n / 12); }
 
 template <int KIND>
 void hmulti_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w,
-                size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag) {
+                size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag, bool w16) {
   if (J <= 0 || nrhs <= 0) return;
   constexpr HKind K = static_cast<HKind>(KIND);
   const size_t Vh = n / 12;
@@ -1127,10 +1234,13 @@ void hmulti_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, cons
   const int ngrid = int((Vh + per_block - 1) / per_block);
   const int nblk = ngrid * kWaves;
   double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * J * 2 * sizeof(double)));
-  Timed tm(c, LQCD_KC_DOT, flag ? 0.0 : (J * hbytes(n) + n * sizeof(cx<float>)) * nrhs);
-  LQCD_TLAUNCH(tm, true, true, (k_hmdot_part<K>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
-                     static_cast<const uint32_t *>(V), ldv, V_rs, J, static_cast<const cx<float> *>(w),
-                     w_rs, Vh, part, flag);
+  Timed tm(c, LQCD_KC_DOT, flag ? 0.0 : (J * hbytes(n) + (w16 ? hbytes(n) : n * sizeof(cx<float>))) * nrhs);
+  if (w16)
+    LQCD_TLAUNCH(tm, true, true, (k_hmdot_part<K, true>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
+                 static_cast<const uint32_t *>(V), ldv, V_rs, J, w, w_rs, Vh, part, flag);
+  else
+    LQCD_TLAUNCH(tm, true, true, (k_hmdot_part<K, false>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
+                 static_cast<const uint32_t *>(V), ldv, V_rs, J, w, w_rs, Vh, part, flag);
   LQCD_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_mdot_final, dim3(J, nrhs), dim3(kBlock), 0, c->stream, part, nblk, J,
                      reinterpret_cast<cx<double> *>(out), out_rs, flag);
@@ -1157,6 +1267,43 @@ void hmulti_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, con
     hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(kBlock), 0, c->stream, part, nblk, norm2_out, flag);
     LQCD_HIP(hipGetLastError());
   }
+}
+
+template <int KIND>
+void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
+                   size_t coef_rs, const void *w, size_t w_rs, void *out, size_t out_rs, size_t n, int nrhs,
+                   double *norm2_out, const int *flag) {
+  if (nrhs <= 0) return;
+  constexpr HKind K = static_cast<HKind>(KIND);
+  const size_t Vh = n / 12;
+  const int nblk = int((Vh + kBlock - 1) / kBlock);  // one site per lane
+  double *part = nullptr;
+  if (norm2_out) part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * sizeof(double)));
+  const double win = w ? n * sizeof(cx<float>) : hbytes(n);
+  Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + win + hbytes(n)) * nrhs);
+  if (w)
+    LQCD_TLAUNCH(tm, true, true, (k_hmaxpy_q<K, false>), dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
+                 static_cast<const uint32_t *>(V), ldv, V_rs, J, reinterpret_cast<const cx<double> *>(coef),
+                 coef_rs, static_cast<const cx<float> *>(w), w_rs, static_cast<uint32_t *>(out), out_rs, Vh,
+                 part, flag);
+  else
+    LQCD_TLAUNCH(tm, true, true, (k_hmaxpy_q<K, true>), dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
+                 static_cast<const uint32_t *>(V), ldv, V_rs, J, reinterpret_cast<const cx<double> *>(coef),
+                 coef_rs, static_cast<const cx<float> *>(nullptr), size_t(0), static_cast<uint32_t *>(out),
+                 out_rs, Vh, part, flag);
+  LQCD_HIP(hipGetLastError());
+  if (norm2_out) {
+    hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(kBlock), 0, c->stream, part, nblk, norm2_out, flag);
+    LQCD_HIP(hipGetLastError());
+  }
+}
+
+void hscale_dev(lqcd_ctx *c, void *x, size_t x_rs, size_t n, int nrhs, const double *f) {
+  if (nrhs <= 0) return;
+  const size_t Vh = n / 12;
+  hipLaunchKernelGGL(k_hscale, dim3(nblocks(Vh), nrhs), dim3(kBlock), 0, c->stream, static_cast<uint32_t *>(x),
+                     x_rs, Vh, f);
+  LQCD_HIP(hipGetLastError());
 }
 
 template <int KIND>
@@ -1207,7 +1354,10 @@ void inv_sqrt_dev(lqcd_ctx *c, const double *nrm2, double *inv, int nb) {
 
 #define HINST(K)                                                                                  \
   template void hmulti_dot<K>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
-                              size_t, int, cdouble *, size_t, const int *);                        \
+                              size_t, int, cdouble *, size_t, const int *, bool);                  \
+  template void hmulti_axpy_q<K>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,   \
+                                 size_t, const void *, size_t, void *, size_t, size_t, int,        \
+                                 double *, const int *);                                           \
   template void hmulti_axpy<K>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,     \
                                size_t, void *, size_t, size_t, int, double *, const int *);        \
   template void hgemm_nn<K>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,        \

@@ -208,6 +208,10 @@ extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int val
                    "lqcd_tune_set: right-hand sides per nested group in -1..4096");
         c->hop_rnest = value;
         break;
+      case LQCD_TUNE_CYCLE_REORTH:
+        LQCD_CHECK(value == 0 || value == 1, LQCD_EINVAL, "lqcd_tune_set: cycle second-pass switch must be 0 or 1");
+        c->cycle_reorth = value;
+        break;
       case LQCD_TUNE_GEMM_MFMA:
         LQCD_CHECK(value == 0 || value == 1, LQCD_EINVAL, "lqcd_tune_set: matrix-core switch must be 0 or 1");
         c->gemm_mfma = value;

@@ -84,65 +84,118 @@ __global__ void __launch_bounds__(kBlock)
 //   a^+ (1 -+ g_mu) W b = sum_{s=0,1} at_s^+ W h_s,
 // where at and h are the upper halves of (1 -+ g_mu) a and (1 -+ g_mu) b:
 // at_s = a_s + alpha_s a_{p(s)} with a spin partner p(s) in {2, 3} and a
-// phase alpha_s in {+-1, +-i}.  Each site gets 4 lanes: lane q < 2 takes the
-// forward half spin s = q (W = U_mu(x), neighbour x + mu), lane q >= 2 the
-// backward one s = q - 2 (W = U_mu(x - mu)^+, neighbour x - mu).  A lane
-// loads two spins of eta(x), two spins of x and xt at its neighbour and one
-// link, so 16 sites of a wave read contiguous 3 KiB runs.  The lanes' terms
-// add up over the four lanes of a site; each timeslice is split over nch
-// workgroups as in k_estimate.
-template <int MU>
-__device__ inline cx<double> ps_lane(const cx<double> *U, const Geom &g, double kappa,
-                                     const cx<double> *eta, const cx<double> *x, const cx<double> *xt,
-                                     const int c[4], size_t s, int q) {
-  const int Lm = g.L[MU];
-  const size_t stm = MU == 0 ? 1 : MU == 1 ? size_t(g.L[0]) : MU == 2 ? size_t(g.L[0]) * g.L[1]
-                                                                        : size_t(g.L[0]) * g.L[1] * g.L[2];
-  const bool fwd = q < 2;
-  const int hs = q & 1;  // half spin
-  const int cm = c[MU];
-  const size_t nbr = fwd ? (cm + 1 == Lm ? s - stm * (Lm - 1) : s + stm) : (cm == 0 ? s + stm * (Lm - 1) : s - stm);
-  int cl[4] = {c[0], c[1], c[2], c[3]};
-  if (!fwd) cl[MU] = cm == 0 ? Lm - 1 : cm - 1;  // the backward link lives at x - mu
-  const cx<double> *u = ps_link(U, g, cl[0], cl[1], cl[2], cl[3], MU);
+// phase alpha_s in {+-1, +-i}.
+//
+// A workgroup takes 64 consecutive sites of one timeslice at a time.  The
+// fields are site-major (192 bytes per site), so it first stages them in
+// LDS with coalesced 16-byte loads (consecutive lanes read consecutive
+// pieces of consecutive sites): eta at its sites once, then for each
+// direction d = x - xt at the sites' forward and backward neighbours
+// (whose site runs are contiguous but for the wrap of the periodic
+// boundary).  LDS holds them component-major, [12][64 sites] with a row
+// stride of 65, so that a wave reading one component of 64 sites, and
+// a wave writing 12 components of consecutive sites, touch distinct banks
+// in every group of 8 lanes.  Then wave q of the workgroup takes one of the
+// four halves for all 64 sites (lane = site): q < 2 the forward half spin
+// s = q (W = U_mu(x)), q >= 2 the backward one s = q - 2 (W = U_mu(x -
+// mu)^+); the branch is uniform per wave and the link loads are coalesced.
+constexpr int kPsSites = 64;                // sites per chunk
+constexpr int kPsRow = kPsSites + 1;        // LDS stride of one component
+constexpr int kPsArr = 12 * kPsRow;         // one staged field
+
+// Link U_mu at the site of full lexicographic index s and parity par, in
+// the even/odd layout [parity][mu][9][Vh].
+__device__ inline const cx<double> *ps_link_at(const cx<double> *U, size_t Vh, size_t s, int par, int mu) {
+  return U + ((size_t(par) * 4 + mu) * 9) * Vh + (s >> 1);
+}
+
+// Half spin HS of the direction-mu term at a lane's site: FWD with U_mu(x)
+// and d(x + mu), else U_mu(x - mu)^+ and d(x - mu).  ea and db point at the
+// site's column of the staged eta and d (components kPsRow apart); u is
+// the link (entries Vh apart).
+template <int MU, bool FWD, int HS>
+__device__ inline cx<double> ps_half_spin(const cx<double> *u, size_t Vh, const cx<double> *ea,
+                                          const cx<double> *db) {
   // partner spin and phase of the forward projector (negated backward)
-  const int ps = MU < 2 ? 3 - hs : 2 + hs;
-  double ar, ai;
-  if (MU == 0) { ar = 0; ai = 1; }
-  else if (MU == 1) { ar = hs ? -1 : 1; ai = 0; }
-  else if (MU == 2) { ar = 0; ai = hs ? -1 : 1; }
-  else { ar = -1; ai = 0; }
-  if (!fwd) { ar = -ar; ai = -ai; }
-  const cx<double> al = mk(ar, ai);
+  constexpr int PS = MU < 2 ? 3 - HS : 2 + HS;
+  constexpr double AR0 = MU == 1 ? (HS ? -1.0 : 1.0) : MU == 3 ? -1.0 : 0.0;
+  constexpr double AI0 = MU == 0 ? 1.0 : MU == 2 ? (HS ? -1.0 : 1.0) : 0.0;
+  constexpr double AR = FWD ? AR0 : -AR0, AI = FWD ? AI0 : -AI0;
+  // at_k = a_HS,k + alpha a_PS,k with alpha in {+-1, +-i} (and likewise h)
+  auto proj = [](cx<double> p, cx<double> q) {
+    return AR != 0.0 ? mk(p.re + AR * q.re, p.im + AR * q.im) : mk(p.re - AI * q.im, p.im + AI * q.re);
+  };
   cx<double> at[3], h[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    at[k] = ldc(eta + s * 12 + hs * 3 + k) + al * ldc(eta + s * 12 + ps * 3 + k);
-    cx<double> bu = ldc(x + nbr * 12 + hs * 3 + k), bl = ldc(x + nbr * 12 + ps * 3 + k);
-    if (xt) {
-      bu = bu - ldc(xt + nbr * 12 + hs * 3 + k);
-      bl = bl - ldc(xt + nbr * 12 + ps * 3 + k);
-    }
-    h[k] = bu + al * bl;
+    at[k] = proj(ea[(HS * 3 + k) * kPsRow], ea[(PS * 3 + k) * kPsRow]);
+    h[k] = proj(db[(HS * 3 + k) * kPsRow], db[(PS * 3 + k) * kPsRow]);
   }
   // the link loads go out after the projections (fewer registers live)
   asm volatile("" : "+v"(at[0].re), "+v"(at[0].im), "+v"(at[1].re), "+v"(at[1].im), "+v"(at[2].re),
                "+v"(at[2].im), "+v"(h[0].re), "+v"(h[0].im), "+v"(h[1].re), "+v"(h[1].im), "+v"(h[2].re),
                "+v"(h[2].im)::"memory");
-  const size_t Vh = size_t(g.Vh);
   cx<double> acc = mk(0.0, 0.0);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    // row a of W: U_ab forward, conj(U_ba) backward
-    cx<double> w[3];
+    cx<double> w[3];  // row a of W
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const cx<double> e = ldc(u + (fwd ? 3 * a + b : 3 * b + a) * Vh);
-      w[b] = fwd ? e : mk(e.re, -e.im);
+      const cx<double> e = ldc(u + (FWD ? 3 * a + b : 3 * b + a) * Vh);
+      w[b] = FWD ? e : mk(e.re, -e.im);
     }
     acc = acc + cmulc(at[a], w[0] * h[0] + w[1] * h[1] + w[2] * h[2]);
   }
-  return (fwd ? -kappa : kappa) * acc;
+  return acc;
+}
+
+// Stage 64 sites' worth of x - xt (XT) or of x into LDS: piece p = 12 site
+// + k is complex k of the spinor at full site index idx[site] (-1: a site
+// past the end, zero; it loads site 0 and drops it, so that the loads of
+// all pieces go out together).
+template <bool XT>
+__device__ inline void ps_stage(cx<double> *sh, const cx<double> *x, const cx<double> *xt, const int *idx) {
+  cx<double> v[3];
+  bool ok[3];
+  int at[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int p = threadIdx.x + u * kBlock;
+    const int site = p / 12, k = p - 12 * site;
+    const int s = idx[site];
+    ok[u] = s >= 0;
+    const size_t o = size_t(ok[u] ? s : 0) * 12 + k;
+    v[u] = ldc(x + o);
+    if (XT) v[u] = v[u] - ldc(xt + o);
+    at[u] = k * kPsRow + site;
+  }
+#pragma unroll
+  for (int u = 0; u < 3; ++u) sh[at[u]] = ok[u] ? v[u] : mk(0.0, 0.0);
+}
+
+template <int MU, bool XT>
+__device__ inline void ps_dir(const cx<double> *U, size_t Vh, double kappa, const cx<double> *x,
+                              const cx<double> *xt, const int (*nb)[kPsSites], const cx<double> *eS,
+                              cx<double> *fS, cx<double> *bS, size_t s, int par, bool on, double &re,
+                              double &im) {
+  __syncthreads();  // the previous direction's reads of fS, bS are done
+  ps_stage<XT>(fS, x, xt, nb[2 * MU]);
+  asm volatile("" ::: "memory");  // the backward loads after the forward ones (fewer registers live)
+  ps_stage<XT>(bS, x, xt, nb[2 * MU + 1]);
+  __syncthreads();
+  if (on) {
+    const int site = threadIdx.x & 63;
+    const int q = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const cx<double> *uf = ps_link_at(U, Vh, s, par, MU);
+    const cx<double> *ub = ps_link_at(U, Vh, size_t(nb[2 * MU + 1][site]), par ^ 1, MU);
+    cx<double> v;
+    if (q == 0) v = -kappa * ps_half_spin<MU, true, 0>(uf, Vh, eS + site, fS + site);
+    else if (q == 1) v = -kappa * ps_half_spin<MU, true, 1>(uf, Vh, eS + site, fS + site);
+    else if (q == 2) v = kappa * ps_half_spin<MU, false, 0>(ub, Vh, eS + site, bS + site);
+    else v = kappa * ps_half_spin<MU, false, 1>(ub, Vh, eS + site, bS + site);
+    re += v.re;
+    im += v.im;
+  }
 }
 
 // Workgroup order: the right-hand side varies fastest within one XCD's
@@ -150,46 +203,49 @@ __device__ inline cx<double> ps_lane(const cx<double> *U, const Geom &g, double 
 // h % 8), so the nrhs workgroups of one chunk of sites run back to back on
 // one XCD and read its links from that XCD's L2 (links are as many bytes as
 // one right-hand side's three fields).
+template <bool XT>
 __global__ void __launch_bounds__(kBlock)
     k_estimate_ps(Geom g, const cx<double> *__restrict__ U, double kappa,
                   const cx<double> *__restrict__ eta, const cx<double> *__restrict__ x,
                   const cx<double> *__restrict__ xt, int nch, int nrhs, int xq, double *__restrict__ out) {
   __shared__ double sh[2 * kNumPS][kWaves];
+  __shared__ cx<double> eS[kPsArr], fS[kPsArr], bS[kPsArr];
+  __shared__ int nb[2 * kNumPS + 1][kPsSites];  // neighbour site indices [2 mu + backward]; the sites
   const int L = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
   if (L >= g.L[3] * nch * nrhs) return;  // whole workgroup: padding of the grid
   const int r = L % nrhs, tch = L / nrhs;
   const int t = tch / nch, ch = tch % nch;
   const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
   const int Vs = Lx * Ly * Lz;
+  const size_t Vh = size_t(g.Vh);
   const size_t base = size_t(r) * size_t(g.V) * 12;
   eta += base;
   x += base;
-  if (xt) xt += base;
-  const int q = threadIdx.x & 3;
+  if (XT) xt += base;
   double acc[2 * kNumPS] = {};
-  for (int i = ch * (kBlock / 4) + (threadIdx.x >> 2); i < Vs; i += nch * (kBlock / 4)) {
+  for (int i0 = ch * kPsSites; i0 < Vs; i0 += nch * kPsSites) {
+    const int site = threadIdx.x & 63;
+    const int i = i0 + site;
+    const bool on = i < Vs;
     const int c[4] = {i % Lx, (i / Lx) % Ly, i / (Lx * Ly), t};
     const size_t s = size_t(t) * Vs + i;
-    // one direction at a time: the empty asm (with a memory clobber) keeps
-    // the next direction's loads behind this direction's arithmetic, which
-    // would otherwise all be issued at once and fill the register file
-    cx<double> v;
-    v = ps_lane<0>(U, g, kappa, eta, x, xt, c, s, q);
-    acc[0] += v.re;
-    acc[1] += v.im;
-    asm volatile("" : "+v"(acc[0]), "+v"(acc[1])::"memory");
-    v = ps_lane<1>(U, g, kappa, eta, x, xt, c, s, q);
-    acc[2] += v.re;
-    acc[3] += v.im;
-    asm volatile("" : "+v"(acc[2]), "+v"(acc[3])::"memory");
-    v = ps_lane<2>(U, g, kappa, eta, x, xt, c, s, q);
-    acc[4] += v.re;
-    acc[5] += v.im;
-    asm volatile("" : "+v"(acc[4]), "+v"(acc[5])::"memory");
-    v = ps_lane<3>(U, g, kappa, eta, x, xt, c, s, q);
-    acc[6] += v.re;
-    acc[7] += v.im;
-    asm volatile("" : "+v"(acc[6]), "+v"(acc[7])::"memory");
+    const int par = (c[0] + c[1] + c[2] + t) & 1;
+    __syncthreads();  // the previous chunk's reads of eS and nb are done
+    {
+      // wave q: the forward and backward neighbours of the sites along mu = q
+      const int q = threadIdx.x >> 6;
+      const int st = q == 0 ? 1 : q == 1 ? Lx : q == 2 ? Lx * Ly : Vs;
+      const int Lm = g.L[q], cm = c[q];
+      nb[2 * q][site] = on ? int(cm + 1 == Lm ? s - size_t(st) * (Lm - 1) : s + st) : -1;
+      nb[2 * q + 1][site] = on ? int(cm == 0 ? s + size_t(st) * (Lm - 1) : s - st) : -1;
+      if (q == 0) nb[2 * kNumPS][site] = on ? int(s) : -1;
+    }
+    __syncthreads();
+    ps_stage<false>(eS, eta, static_cast<const cx<double> *>(nullptr), nb[2 * kNumPS]);
+    ps_dir<0, XT>(U, Vh, kappa, x, xt, nb, eS, fS, bS, s, par, on, acc[0], acc[1]);
+    ps_dir<1, XT>(U, Vh, kappa, x, xt, nb, eS, fS, bS, s, par, on, acc[2], acc[3]);
+    ps_dir<2, XT>(U, Vh, kappa, x, xt, nb, eS, fS, bS, s, par, on, acc[4], acc[5]);
+    ps_dir<3, XT>(U, Vh, kappa, x, xt, nb, eS, fS, bS, s, par, on, acc[6], acc[7]);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -260,10 +316,16 @@ void estimate_with(lqcd_ctx *c, const int *thetas, int nth, const void *eta, con
     }
     if (any_ps) {
       const int xq = (Lt * nch * nrhs + 7) / 8;  // logical workgroups per XCD (grid padded to 8 xq)
-      hipLaunchKernelGGL(k_estimate_ps, dim3(8 * xq), dim3(kBlock), 0, c->stream, g,
-                         static_cast<const cx<double> *>(c->U64.ptr), c->kappa,
-                         static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x),
-                         static_cast<const cx<double> *>(xt), nch, nrhs, xq, d);
+      if (xt)
+        hipLaunchKernelGGL(k_estimate_ps<true>, dim3(8 * xq), dim3(kBlock), 0, c->stream, g,
+                           static_cast<const cx<double> *>(c->U64.ptr), c->kappa,
+                           static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x),
+                           static_cast<const cx<double> *>(xt), nch, nrhs, xq, d);
+      else
+        hipLaunchKernelGGL(k_estimate_ps<false>, dim3(8 * xq), dim3(kBlock), 0, c->stream, g,
+                           static_cast<const cx<double> *>(c->U64.ptr), c->kappa,
+                           static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x),
+                           static_cast<const cx<double> *>(nullptr), nch, nrhs, xq, d);
       LQCD_HIP(hipGetLastError());
     }
     std::vector<double> hc(size_t(nrhs) * kNumOps * Lt * nch * 2);

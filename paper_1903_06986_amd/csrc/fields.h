@@ -73,13 +73,24 @@ void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size
 // 16-bit stored bases (half.h; KIND 0 = FP16, 1 = BF16): V is a basis of
 // stored vectors ldv words apart (V_rs words between right-hand sides), w/Y
 // FP32 vectors of n = 12 Vh elements.  Semantics as the FP32 versions.
+// With w16 the vector w is itself a stored 16-bit vector (w_rs in words).
 template <int KIND>
 void hmulti_dot(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w,
-                size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag);
+                size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag,
+                bool w16 = false);
 template <int KIND>
 void hmulti_axpy(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
                  size_t coef_rs, void *w, size_t w_rs, size_t n, int nrhs, double *norm2_out,
                  const int *flag);
+// out_r = stored(w_r - V_r coef_r), unnormalised (per-site scales), with
+// |stored|^2 in norm2_out; w null: w_r is out_r itself (in place).
+template <int KIND>
+void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
+                   size_t coef_rs, const void *w, size_t w_rs, void *out, size_t out_rs, size_t n, int nrhs,
+                   double *norm2_out, const int *flag);
+// Per-site scales of nrhs stored vectors (x_rs words apart) times f[r]
+// (device array).
+void hscale_dev(lqcd_ctx *c, void *x, size_t x_rs, size_t n, int nrhs, const double *f);
 template <int KIND>
 void hgemm_nn(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *C,
               size_t ldc, size_t C_rs, void *Y, size_t ldy, size_t Y_rs, int nb, size_t n, int nrhs,

@@ -252,28 +252,33 @@ void arnoldi(lqcd_ctx *c, const Op<R> &A, void *W, size_t n, size_t Wrs, int j0,
 
 // Arnoldi steps with a 16-bit stored basis (kind BK, half.h): W holds
 // the basis as stored vectors ldv words apart (bases Wrs words apart);
-// the new vector is built and orthogonalised in FP32 in wt (vectors n
-// apart), then normalised and stored into slot j + 1.
+// A v_j is formed in FP32 in wt (vectors n apart).  The first
+// Gram-Schmidt pass stores its result straight into slot j + 1 with
+// per-site scales (not normalised: the scales take the norm afterwards,
+// the stored digits do not depend on it); a second pass, where the DGKS
+// test asks for one, works on that stored vector in place.  h_{j+1,j} is
+// the norm of the stored vector.
 template <int BK>
 void arnoldi_h(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, size_t Wrs, int j0,
                int m, int nb, Small &s, double eta2, void *wt) {
   uint32_t *Wb = static_cast<uint32_t *>(W);
   for (int j = j0; j < m; ++j) {
+    uint32_t *wn = Wb + size_t(j + 1) * ldv;
     A.template apply_h<BK>(Wb + size_t(j) * ldv, Wrs, wt, n, nb);
     hmulti_dot<BK>(c, Wb, ldv, Wrs, j + 1, wt, n, n, nb, s.h1, m + 1, nullptr);
-    hmulti_axpy<BK>(c, Wb, ldv, Wrs, j + 1, s.h1, m + 1, wt, n, n, nb, s.nrm1, nullptr);
+    hmulti_axpy_q<BK>(c, Wb, ldv, Wrs, j + 1, s.h1, m + 1, wt, n, wn, Wrs, n, nb, s.nrm1, nullptr);
     hipLaunchKernelGGL(k_dgks, dim3(nb), dim3(64), 0, c->stream,
                        reinterpret_cast<const cx<double> *>(s.h1), size_t(m + 1), j + 1, s.nrm1,
                        s.flag, s.reorth, eta2);
     LQCD_HIP(hipGetLastError());
-    hmulti_dot<BK>(c, Wb, ldv, Wrs, j + 1, wt, n, n, nb, s.h2, m + 1, s.flag);
-    hmulti_axpy<BK>(c, Wb, ldv, Wrs, j + 1, s.h2, m + 1, wt, n, n, nb, s.nrm2, s.flag);
+    hmulti_dot<BK>(c, Wb, ldv, Wrs, j + 1, wn, Wrs, n, nb, s.h2, m + 1, s.flag, true);
+    hmulti_axpy_q<BK>(c, Wb, ldv, Wrs, j + 1, s.h2, m + 1, nullptr, 0, wn, Wrs, n, nb, s.nrm2, s.flag);
     hipLaunchKernelGGL(k_finish_col, dim3(nb), dim3(64), 0, c->stream,
                        reinterpret_cast<cx<double> *>(s.Hd), s.Hrs, m + 1, j,
                        reinterpret_cast<cx<double> *>(s.h1), reinterpret_cast<cx<double> *>(s.h2),
                        size_t(m + 1), s.nrm1, s.nrm2, s.flag, s.inv);
     LQCD_HIP(hipGetLastError());
-    hquantize<BK>(c, wt, n, s.inv, Wb + size_t(j + 1) * ldv, Wrs, n, nb);
+    hscale_dev(c, wn, Wrs, n, nb, s.inv);
   }
 }
 
@@ -682,10 +687,10 @@ void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *
       norm2<R>(c, Rb, n, n, na, s.nrm2);
       inv_sqrt_dev(c, s.nrm2, s.inv, na);
       hquantize<BK>(c, Rb, n, s.inv, W, Wrs, n, na);
-      arnoldi_h<BK>(c, A, W, n, ldh, Wrs, 0, p, na, s, kReorthCycle, wt);
+      arnoldi_h<BK>(c, A, W, n, ldh, Wrs, 0, p, na, s, c->cycle_reorth ? kReorthAlways : kReorthCycle, wt);
     } else {
       axpby<R>(c, sc.data(), Rb, n, zs.data(), W, Wrs, n, na, true);
-      arnoldi<R>(c, A, W, n, Wrs, 0, p, na, s, kReorthCycle);
+      arnoldi<R>(c, A, W, n, Wrs, 0, p, na, s, c->cycle_reorth ? kReorthAlways : kReorthCycle);
     }
     harvest_reorth(c, s, na, perm, reorth);
     Hh.resize(s.Hrs * na);

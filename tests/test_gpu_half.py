@@ -88,3 +88,32 @@ def test_mixed_solve_16bit_basis(dims, kappa, prec):
     # the 16-bit path is only for the even/odd system
     with pytest.raises(Exception):
         ctx.gmresdr_solve(to_gpu(eta[:1]), op="MG5", m=20, k=10, inner=prec)
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_mixed_solve_second_pass_on_every_step(prec):
+    """The second Gram-Schmidt pass of the 16-bit basis works on the stored
+    vector in place; forced on every GMRES-Proj step it must leave the
+    solutions as accurate as the conditional pass does."""
+    require_gpu()
+    dims, kappa = (6, 4, 2, 8), 0.13
+    ctx, U = context(dims, 0.3, 1001, kappa)
+    eta = z4_noise(2002, dims, 0, 4)
+    M = W.dense_M(U, kappa, dims)
+    xref = np.linalg.solve(M, eta.reshape(4, -1).T).T.reshape(eta.shape)
+    out = {}
+    for forced in (0, 1):
+        ctx.tune(cycle_reorth=forced)
+        say("solve mixed second pass", prec, forced)
+        x, defl, st = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=20, k=10, tol=1e-11, tol_super=1e-13,
+                                        inner=prec, inner_tol=1e-3, rhs_block=3)
+        x = to_host(x)
+        for r in range(4):
+            assert rel_err(x[r], xref[r]) < 1e-9, (forced, r)
+            assert st[r]["true_resid"] < 1e-11, (forced, r)
+        out[forced] = st
+    ctx.tune(cycle_reorth=0)
+    # forced: every Arnoldi step of the GMRES-Proj solves ran the second pass
+    for r in range(1, 4):
+        assert out[1][r]["reorth"] > out[0][r]["reorth"]
+        assert out[1][r]["reorth"] >= out[1][r]["matvecs"] // 2

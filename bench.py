@@ -283,7 +283,7 @@ def accuracy(path, precisions, cfg, kappa, U, oracle_check):
 def batching(args):
     """Untimed by the headline: the mixed-lattice batch (8^4 x 17, 12^3 x 24
     x 64, 16^3 x 32 x 160 right-hand sides) solved by batch_solve with the
-    autotuned block and grid, against the same solves lattice by lattice;
+    autotuned block and stencil form, against the same solves lattice by lattice;
     then the lattices smaller than 16^3 x 32 alone, batched and
     sequential."""
     import torch
@@ -306,8 +306,8 @@ def batching(args):
     setup_s = time.time() - t0
     batch = Batch(ctxs)
     kw = dict(m=cfg["m"], k=cfg["k"], tol=args.tol, max_cycles=args.max_cycles, inner_tol=args.inner_tol)
-    blk, grid, table = batch.autotune(etas, defls, **kw)
-    batch.set_grid(grid)
+    blk, tile, table = batch.autotune(etas, defls, **kw)
+    batch.set_tile(tile)
     total = sum(cfg["n_rhs"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -340,8 +340,8 @@ def batching(args):
     small = [i for i, d in enumerate(cfg["lattices"]) if int(np.prod(d)) < 131072]
     sb = Batch([ctxs[i] for i in small])
     s_eta, s_defl = [etas[i] for i in small], [defls[i] for i in small]
-    s_blk, s_grid, _ = sb.autotune(s_eta, s_defl, **kw)
-    sb.set_grid(s_grid)
+    s_blk, s_tile, _ = sb.autotune(s_eta, s_defl, **kw)
+    sb.set_tile(s_tile)
     s_total = sum(e.shape[0] for e in s_eta)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -353,7 +353,7 @@ def batching(args):
     lat = ["%s x %d" % ("x".join(map(str, d)), n) for d, n in zip(cfg["lattices"], cfg["n_rhs"])]
     out = {"lattices": lat,
            "kappa": kappa, "solves": total, "setup_s": round(setup_s, 3),
-           "autotune": {"rhs_block": blk, "grid": grid,
+           "autotune": {"rhs_block": blk, "tile": tile,
                         "rates": {"%d/%d" % k: round(v, 2) for k, v in table.items()}},
            "batched_graph_solves_per_s": round(total / dt, 3),
            "batched_eager_solves_per_s": round(total / dt_eager, 3),
@@ -362,7 +362,7 @@ def batching(args):
            "per_lattice_sequential": seq,
            "max_true_resid": max(s["true_resid"] for s in st),
            "matvecs_per_solve": float(np.mean([s["matvecs"] for s in st])),
-           "small_lattices_only": {"lattices": [lat[i] for i in small], "rhs_block": s_blk, "grid": s_grid,
+           "small_lattices_only": {"lattices": [lat[i] for i in small], "rhs_block": s_blk, "tile": s_tile,
                                    "batched_graph_solves_per_s": round(s_total / s_dt, 3),
                                    "sequential_solves_per_s": round(s_total / s_seq, 3),
                                    "batched_over_sequential": round(s_seq / s_dt, 3)}}

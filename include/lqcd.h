@@ -328,15 +328,23 @@ lqcd_status lqcd_batch_create(lqcd_ctx *const *ctxs, int nlat, lqcd_batch **out)
 lqcd_status lqcd_batch_destroy(lqcd_batch *batch);
 /* Workgroups of the persistent batched stencil launch (default 8192). */
 lqcd_status lqcd_batch_set_grid(lqcd_batch *batch, int workgroups);
+/* Form of the batched stencil: 0 (default) = one persistent launch over the
+ * slot table (every slot reads its own links); 16, 32 or 64 = the
+ * link-tiled stencil with tiles of that many sites, one launch per run of
+ * consecutive slots that hold one lattice (its links staged once per tile
+ * for all of them; the captured cycle is recorded again when a refill of
+ * the slots changes these runs).  EINVAL for other values. */
+lqcd_status lqcd_batch_set_tile(lqcd_batch *batch, int tile_sites);
 
 /* Deflated GMRES-Proj solves (Sec. 7) of every lattice's right-hand sides
  * with FP32 inner solves in FP64 refinement (params->inner must be
  * LQCD_F32), all lattices in lockstep: right-hand sides are taken
  * params->rhs_block at a time from one queue over the lattices (uneven
  * counts and sizes mix in a block); each inner operator application is
- * one persistent launch over all of them, the Gram-Schmidt and projection
- * kernels are batched likewise, and with use_graph != 0 each GMRES(m - k)
- * cycle (or proj_m) runs as a captured hipGraph.  b[l], x[l]: device
+ * one persistent launch over all of them or one link-tiled launch per
+ * lattice among them (lqcd_batch_set_tile), the Gram-Schmidt and
+ * projection kernels are batched over all of them, and with use_graph != 0
+ * each GMRES(m - k) cycle (or proj_m) runs as a captured hipGraph.  b[l], x[l]: device
  * complex128 LEX [nrhs[l]][12 V_l]; defl[l]: deflation space of lattice l's
  * even/odd system (gmresdr_solve with LQCD_OP_SCHUR on that context).
  * stats: host array over all right-hand sides in lattice order, or NULL.
@@ -346,15 +354,16 @@ lqcd_status batch_solve(lqcd_batch *batch, const lqcd_solve_params *params, cons
                         lqcd_solve_stats *stats);
 
 /* Autotuner: times trial batch_solve runs (captured cycles) for rhs_block
- * in {4, 8, 16, 32} and persistent-stencil grids of {2048, 8192}
- * workgroups, each on one block of right-hand sides drawn evenly from the
- * lattices, and returns the fastest pair.  rate_host: optional host double
- * [8] receiving the trial rates (right-hand sides per second, order:
- * rhs_block major, grid minor; 0 for skipped pairs).  The batch's grid
- * setting is left unchanged. */
+ * in {4, 8, 16, 32} and the stencil forms of lqcd_batch_set_tile {0, 16,
+ * 32, 64}, each on one block of right-hand sides drawn evenly from the
+ * lattices, and returns the fastest pair (best_tile as for
+ * lqcd_batch_set_tile).  rate_host: optional host double [16] receiving
+ * the trial rates (right-hand sides per second, order: rhs_block major,
+ * tile minor; 0 for skipped pairs).  The batch's tile setting is left
+ * unchanged. */
 lqcd_status batch_autotune(lqcd_batch *batch, const lqcd_solve_params *params, const void *const *b,
                            const int *nrhs, lqcd_defl *const *defl, int *best_rhs_block,
-                           int *best_grid, double *rate_host);
+                           int *best_tile, double *rate_host);
 
 /* The even/odd operator Mhat (Sec. 7) in FP32 on every right-hand side of
  * every lattice in one persistent launch per half hop: in[l], out[l] device
@@ -417,7 +426,10 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * kernel.  LQCD_TUNE_CYCLE_REORTH: 0 (default) runs the second
  * Gram-Schmidt pass of the GMRES-Proj cycles only where the first pass
  * cancelled more than one digit; 1 runs it on every step (a check of that
- * pass; slower).  Values are per context; EINVAL for other values. */
+ * pass; slower).  LQCD_TUNE_KEPT_PERIOD: MINRES-DR tests its basis against
+ * the kept vectors of the last restart on every this-many-th step of a cycle
+ * and on its last step (1..64, default 2).  Values are per context; EINVAL
+ * for other values. */
 typedef enum {
   LQCD_TUNE_HOP_NB64 = 0,
   LQCD_TUNE_HOP_NB32 = 1,
@@ -431,7 +443,8 @@ typedef enum {
   LQCD_TUNE_HOP_TSITES64 = 9,
   LQCD_TUNE_GEMM_MFMA = 10,
   LQCD_TUNE_HOP_RNEST = 11,
-  LQCD_TUNE_CYCLE_REORTH = 12
+  LQCD_TUNE_CYCLE_REORTH = 12,
+  LQCD_TUNE_KEPT_PERIOD = 13
 } lqcd_tune_param;
 lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 

@@ -502,6 +502,7 @@ struct lqcd_batch {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int hop_grid = 8192;  // persistent stencil workgroups per launch (tunable)
+  int tile = 0;         // 0: one persistent slot-table stencil launch; 16/32/64: link tiles per lattice group
   // Capture needs a stream other than the legacy null stream; the graph
   // is recorded on this private one (default priority) and launched on
   // the contexts' stream.
@@ -527,8 +528,57 @@ void h2d_b(lqcd_batch *b, void *dst, const void *src, size_t bytes) {
 
 inline unsigned grid_n(size_t n) { return unsigned(std::min<size_t>((n + kBlock - 1) / kBlock, 4096)); }
 
+// A run of consecutive slots that hold right-hand sides of one lattice:
+// their vectors lie at one stride from each other, so the single-lattice
+// link-tiled stencil serves them in one launch (links staged once per tile
+// for all of them).
+struct Group {
+  lqcd_ctx *c;
+  int s0, G;
+  size_t n;
+};
+
+// Runs of one lattice in a slot-to-lattice map (-1: empty slot).
+std::vector<Group> lattice_groups(const std::vector<lqcd_ctx *> &ctx, const std::vector<int> &lat,
+                                  const std::vector<size_t> &n) {
+  std::vector<Group> g;
+  for (int s = 0; s < int(lat.size()); ++s) {
+    if (lat[s] < 0) continue;
+    if (!g.empty() && lat[s - 1] == lat[s] && g.back().s0 + g.back().G == s)
+      ++g.back().G;
+    else
+      g.push_back(Group{ctx[lat[s]], s, 1, n[s]});
+  }
+  return g;
+}
+
+// Launches of a context's stencil on the batch's current stream (the
+// capture stream while a cycle is being recorded) with the batch's tile
+// size and the context's event timer off; restored on exit.
+struct OnBatchStream {
+  lqcd_ctx *c;
+  hipStream_t keep;
+  int keep_ts;
+  bool keep_timer;
+  OnBatchStream(lqcd_ctx *cc, hipStream_t s, int ts)
+      : c(cc), keep(cc->stream), keep_ts(cc->hop_tsites[1]), keep_timer(cc->timer.on) {
+    c->stream = s;
+    c->hop_tsites[1] = ts;
+    c->timer.on = false;
+  }
+  ~OnBatchStream() {
+    c->stream = keep;
+    c->hop_tsites[1] = keep_ts;
+    c->timer.on = keep_timer;
+  }
+};
+
 // Device work of the batched inner solve, shared by the eager and the
-// captured paths.  B slots, basis length p, longest vector nmax.
+// captured paths.  B slots, basis length p, longest vector nmax.  The
+// stencil is one persistent launch over the slot table (tile == 0) or,
+// with link tiles, one launch of the link-tiled stencil per lattice group
+// (its groups are fixed while a block of slots is in flight; inactive
+// slots of a group are computed and ignored).
 struct Engine {
   lqcd_batch *b;
   int B, p;
@@ -536,15 +586,36 @@ struct Engine {
   unsigned per, items, hgrid;
   int kdmax;
   const BSlot *sl;
+  int tile = 0;
+  std::vector<Group> groups;
+  cx<float> *W = nullptr, *T = nullptr, *X = nullptr, *R = nullptr;
   size_t nchunk() const { return (nmax + size_t(kWch) * kWaves - 1) / (size_t(kWch) * kWaves) * kWaves; }
   size_t nblk() const { return (nmax + size_t(kBlock) * kAept - 1) / (size_t(kBlock) * kAept); }
   unsigned hop_grid() const { return std::min<unsigned>((items + 7) / 8 * 8, hgrid); }
 
   void stencil_schur_w(int j) const {
+    if (tile > 0) {
+      const size_t ws = size_t(p + 1) * nmax;  // slot stride of the bases
+      for (const Group &g : groups) {
+        OnBatchStream on(g.c, b->stream, tile);
+        cx<float> *w = W + size_t(g.s0) * ws;
+        apply_schur<float>(g.c, w + size_t(j) * g.n, w + size_t(j + 1) * g.n, T + size_t(g.s0) * nmax, g.G, ws, ws,
+                           nmax);
+      }
+      return;
+    }
     hipLaunchKernelGGL(k_bhop<HOP_W>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, unsigned(B), items, j);
     hipLaunchKernelGGL(k_bhop<SCHUR_W>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, unsigned(B), items, j);
   }
   void stencil_schur_x() const {
+    if (tile > 0) {
+      for (const Group &g : groups) {
+        OnBatchStream on(g.c, b->stream, tile);
+        apply_schur<float>(g.c, X + size_t(g.s0) * nmax, R + size_t(g.s0) * nmax, T + size_t(g.s0) * nmax, g.G,
+                           nmax, nmax, nmax);
+      }
+      return;
+    }
     hipLaunchKernelGGL(k_bhop<HOP_X>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, unsigned(B), items, 0);
     hipLaunchKernelGGL(k_bhop<SCHUR_X>, dim3(hop_grid()), dim3(kBlock), 0, b->stream, sl, unsigned(B), items, 0);
   }
@@ -605,6 +676,7 @@ namespace lqcd {
 namespace {
 
 constexpr int kBatchCycleCap = 20;   // GMRES(p) cycles per inner solve
+constexpr int kTuneBlocks = 4, kTuneTiles = 4;  // autotuner trials: rhs_block x stencil form
 constexpr double kBatchStall = 0.9;  // stop an inner solve when a cycle gains < 10%
 constexpr int kBatchMaxRefine = 60;
 
@@ -653,6 +725,11 @@ void run_batch(lqcd_batch *b, const lqcd_solve_params &prm, const void *const *b
   cx<double> *TF = static_cast<cx<double> *>(b->TF.ensure(size_t(B) * flmax * sizeof(cx<double>)));
   BSlot *sld = static_cast<BSlot *>(b->slots_dev.ensure(size_t(B) * sizeof(BSlot)));
   Engine e{b, B, p, nmax, per, unsigned(B) * per, unsigned(b->hop_grid), kdmax, sld};
+  e.tile = b->tile;
+  e.W = W;
+  e.T = T;
+  e.X = X;
+  e.R = R;
   const size_t Jpart = size_t(std::max(p + 1, kdmax + 1));
   b->part.ensure(size_t(B) * e.nchunk() * Jpart * sizeof(cx<double>));
   b->part2.ensure(size_t(B) * e.nblk() * sizeof(double));
@@ -672,10 +749,24 @@ void run_batch(lqcd_batch *b, const lqcd_solve_params &prm, const void *const *b
       d->have_v32 = true;
     }
   }
-  // the captured inner cycle (kernel arguments are the fixed buffers above)
-  hipGraph_t graph = nullptr;
+  // the captured inner cycle (kernel arguments are the fixed buffers
+  // above; with link tiles also the lattice groups of the block in flight,
+  // so it is recorded again whenever a refill changes them)
+  struct GraphGuard {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    void reset() {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+      x = nullptr;
+      g = nullptr;
+    }
+    ~GraphGuard() { reset(); }
+  } guard;
   hipGraphExec_t exec = nullptr;
-  if (use_graph) {
+  auto record = [&]() {
+    guard.reset();
+    exec = nullptr;
     if (!b->capture) LQCD_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
     LQCD_HIP(hipStreamSynchronize(b->stream));
     // the engine launches on b->stream: point it at the capture stream.
@@ -699,23 +790,14 @@ void run_batch(lqcd_batch *b, const lqcd_solve_params &prm, const void *const *b
     cg.open = true;
     e.cycle();
     cg.open = false;
-    const hipError_t ce = hipStreamEndCapture(b->capture, &graph);
+    const hipError_t ce = hipStreamEndCapture(b->capture, &guard.g);
     b->stream = cg.keep;
     LQCD_HIP(ce);
-  }
-  struct GraphGuard {
-    hipGraph_t g;
-    hipGraphExec_t x;
-    ~GraphGuard() {
-      if (x) (void)hipGraphExecDestroy(x);
-      if (g) (void)hipGraphDestroy(g);
-    }
-  } guard{graph, nullptr};
-  if (use_graph) {
     LQCD_HIP(hipGetLastError());
-    LQCD_HIP(hipGraphInstantiate(&guard.x, graph, nullptr, nullptr, 0));
+    LQCD_HIP(hipGraphInstantiate(&guard.x, guard.g, nullptr, nullptr, 0));
     exec = guard.x;
-  }
+  };
+  if (use_graph && e.tile == 0) record();
 
   std::vector<BSlot> slh(B);
   std::vector<SlotState> ss(B);
@@ -757,6 +839,21 @@ void run_batch(lqcd_batch *b, const lqcd_solve_params &prm, const void *const *b
       fill_zero(c, X64 + size_t(s) * nmax, n * sizeof(cx<double>));
       LQCD_HIP(hipMemcpyAsync(R64 + size_t(s) * nmax, S64 + size_t(s) * nmax, n * sizeof(cx<double>),
                               hipMemcpyDeviceToDevice, b->stream));
+    }
+    if (e.tile > 0) {
+      std::vector<int> lat(B);
+      std::vector<size_t> nn(B);
+      for (int s = 0; s < B; ++s) {
+        lat[s] = ss[s].lat;
+        nn[s] = slh[s].n;
+      }
+      std::vector<Group> g = lattice_groups(b->ctx, lat, nn);
+      const bool same = g.size() == e.groups.size() &&
+                        std::equal(g.begin(), g.end(), e.groups.begin(), [](const Group &u, const Group &v) {
+                          return u.c == v.c && u.s0 == v.s0 && u.G == v.G;
+                        });
+      e.groups = g;
+      if (use_graph && (!same || !exec)) record();
     }
     {
       // |b| of every filled slot, one copy
@@ -973,6 +1070,14 @@ extern "C" lqcd_status lqcd_batch_set_grid(lqcd_batch *b, int workgroups) {
   });
 }
 
+extern "C" lqcd_status lqcd_batch_set_tile(lqcd_batch *b, int tile_sites) {
+  return guarded([&] {
+    LQCD_CHECK(b && (tile_sites == 0 || tile_sites == 16 || tile_sites == 32 || tile_sites == 64), LQCD_EINVAL,
+               "lqcd_batch_set_tile: tile of 0, 16, 32 or 64 sites");
+    b->tile = tile_sites;
+  });
+}
+
 extern "C" lqcd_status batch_solve(lqcd_batch *b, const lqcd_solve_params *params, const void *const *bvec,
                                    void *const *xvec, const int *nrhs, lqcd_defl *const *defl, int use_graph,
                                    lqcd_solve_stats *stats) {
@@ -989,10 +1094,10 @@ extern "C" lqcd_status batch_solve(lqcd_batch *b, const lqcd_solve_params *param
 
 extern "C" lqcd_status batch_autotune(lqcd_batch *b, const lqcd_solve_params *params, const void *const *bvec,
                                       const int *nrhs, lqcd_defl *const *defl, int *best_rhs_block,
-                                      int *best_grid, double *rate_host) {
+                                      int *best_tile, double *rate_host) {
   return guarded([&] {
     check_batch_args(b, params, bvec, nrhs, defl);
-    LQCD_CHECK(best_rhs_block && best_grid, LQCD_EINVAL, "batch_autotune: null output");
+    LQCD_CHECK(best_rhs_block && best_tile, LQCD_EINVAL, "batch_autotune: null output");
     const int nl = int(b->ctx.size());
     int total = 0;
     for (int l = 0; l < nl; ++l) total += nrhs[l];
@@ -1002,13 +1107,18 @@ extern "C" lqcd_status batch_autotune(lqcd_batch *b, const lqcd_solve_params *pa
     std::vector<void *> xp(nl, nullptr);
     for (int l = 0; l < nl; ++l)
       if (nrhs[l] > 0) xp[l] = xs[l].ensure(size_t(nrhs[l]) * full_len(b->ctx[l]->g) * sizeof(cdouble));
-    const int blocks[4] = {4, 8, 16, 32};
-    const int grids[2] = {2048, 8192};
-    const int keep_grid = b->hop_grid;
+    const int blocks[kTuneBlocks] = {4, 8, 16, 32};
+    const int tiles[kTuneTiles] = {0, 16, 32, 64};
+    const int keep_tile = b->tile;
+    struct Restore {
+      lqcd_batch *b;
+      int t;
+      ~Restore() { b->tile = t; }
+    } restore{b, keep_tile};
     double best = -1;
     int bi = 0;
-    for (int ib = 0; ib < 4; ++ib)
-      for (int ig = 0; ig < 2; ++ig) {
+    for (int ib = 0; ib < kTuneBlocks; ++ib)
+      for (int it = 0; it < kTuneTiles; ++it) {
         double rate = 0;
         if (blocks[ib] <= std::max(4, total)) {
           // a trial solves one block of right-hand sides, taken evenly from the lattices
@@ -1022,7 +1132,7 @@ extern "C" lqcd_status batch_autotune(lqcd_batch *b, const lqcd_solve_params *pa
               }
           lqcd_solve_params pr = *params;
           pr.rhs_block = blocks[ib];
-          b->hop_grid = grids[ig];
+          b->tile = tiles[it];
           int nonconv = 0;
           LQCD_HIP(hipStreamSynchronize(b->stream));
           const auto t0 = std::chrono::steady_clock::now();
@@ -1038,10 +1148,9 @@ extern "C" lqcd_status batch_autotune(lqcd_batch *b, const lqcd_solve_params *pa
         if (rate > best) {
           best = rate;
           *best_rhs_block = blocks[ib];
-          *best_grid = grids[ig];
+          *best_tile = tiles[it];
         }
       }
-    b->hop_grid = keep_grid;
   });
 }
 
@@ -1092,6 +1201,19 @@ extern "C" lqcd_status batch_wilson_apply(lqcd_batch *b, const void *const *in, 
     }
     h2d_b(b, sld, slh.data(), size_t(B) * sizeof(BSlot));
     Engine e{b, B, 1, nmax, per, unsigned(B) * per, unsigned(b->hop_grid), 0, sld};
+    e.tile = b->tile;
+    e.X = X;
+    e.R = R;
+    e.T = T;
+    if (e.tile > 0) {
+      std::vector<int> lat(B);
+      std::vector<size_t> nn(B);
+      for (int s = 0; s < B; ++s) {
+        lat[s] = q[s].first;
+        nn[s] = slh[s].n;
+      }
+      e.groups = lattice_groups(b->ctx, lat, nn);
+    }
     e.stencil_schur_x();
     LQCD_HIP(hipGetLastError());
     for (int s = 0; s < B; ++s) {

@@ -143,8 +143,9 @@ struct lqcd_ctx {
   int hop_tsites[2] = {32, 32};  // tiled stencil: sites per tile, FP64 (16, 32), FP32 (16, 32, 64)
   int hop_rgroup = 0;            // tiled stencil: right-hand sides per group (0: all in one)
   int hop_rnest = -1;            // tiled stencil: groups swept in turn within each block (0: off, -1: auto)
-  int gemm_mfma = 1;
-  int cycle_reorth = 0;  // 1: second Gram-Schmidt pass on every GMRES-Proj step             // V C with one shared basis on the matrix cores (0: FMA kernel)
+  int gemm_mfma = 1;             // V C with one shared basis on the matrix cores (0: FMA kernel)
+  int cycle_reorth = 0;          // 1: second Gram-Schmidt pass on every GMRES-Proj step
+  int kept_period = 2;           // MINRES-DR: steps between tests against the kept vectors
   ~lqcd_ctx();
 };
 

@@ -208,6 +208,10 @@ extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int val
                    "lqcd_tune_set: right-hand sides per nested group in -1..4096");
         c->hop_rnest = value;
         break;
+      case LQCD_TUNE_KEPT_PERIOD:
+        LQCD_CHECK(value >= 1 && value <= 64, LQCD_EINVAL, "lqcd_tune_set: kept-vector test period in 1..64");
+        c->kept_period = value;
+        break;
       case LQCD_TUNE_CYCLE_REORTH:
         LQCD_CHECK(value == 0 || value == 1, LQCD_EINVAL, "lqcd_tune_set: cycle second-pass switch must be 0 or 1");
         c->cycle_reorth = value;

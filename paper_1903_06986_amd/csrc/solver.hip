@@ -335,9 +335,10 @@ void lanczos_ext(lqcd_ctx *c, const Op<double> &A, void *V, size_t n, int j0, in
                          s.scratch_count, kReorthDR);
       LQCD_HIP(hipGetLastError());
       multi_dot<double>(c, wp, n, 0, 2, wn, 0, n, 1, s.h2 + (j - 1), m + 1, s.flag);
-      // the kept vectors are tested on every other step and on the last
-      // step of a cycle (their coefficients stay zero otherwise)
-      const bool test = kept > 0 && ((j - j0) % 2 == 1 || j == m - 1);
+      // the kept vectors are tested on every kept_period-th step (every
+      // other by default) and on the last step of a cycle (their
+      // coefficients stay zero otherwise)
+      const bool test = kept > 0 && ((j - j0) % c->kept_period == c->kept_period - 1 || j == m - 1);
       if (test) {
         multi_dot<double>(c, Vb, n, 0, kept, wn, 0, n, 1, s.h2, m + 1);
         hipLaunchKernelGGL(k_kept_test, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.h2),

@@ -42,6 +42,11 @@ namespace lqcd {
 
 namespace {
 
+// Right-hand sides per pass of the subtraction vectors: 16 fill the FP64
+// link-tiled stencil and the 16-column matrix-core V C, at 3 x 16 full
+// FP64 fields of workspace (4 GB on 24^3 x 32).
+constexpr int kSubBlock = 16;
+
 // ---------------------------------------------------------- walk tables
 constexpr int kMaxWalkLen = 8;  // local: length <= 6 (orders <= 7); point-split: <= 8
 
@@ -464,7 +469,7 @@ void check_thetas(const int *th, int nth) {
 void apply_poly_lex(lqcd_ctx *c, const std::vector<cdouble> &coeffs, const void *eta, void *xt,
                     int nrhs) {
   const size_t fl = full_len(c->g);
-  const int blk = 8;
+  const int blk = kSubBlock;
   for (int r0 = 0; r0 < nrhs; r0 += blk) {
     const int nb = std::min(blk, nrhs - r0);
     cx<double> *E = static_cast<cx<double> *>(c->ws[0].ensure(fl * nb * sizeof(cx<double>)));
@@ -613,7 +618,7 @@ void es_project(lqcd_ctx *c, lqcd_defl *d, int Q, const int *thetas, int nth, co
         corr[2 * (a * Lt + t) + 1] += v.imag();
       }
   }
-  const int blk = 8;
+  const int blk = kSubBlock;
   for (int r0 = 0; r0 < nrhs; r0 += blk) {
     const int nb = std::min(blk, nrhs - r0);
     cx<double> *Et = static_cast<cx<double> *>(c->ws[0].ensure(fl * nb * sizeof(cx<double>)));
@@ -822,7 +827,7 @@ extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_de
         }
     }
     // xt += g5 E (w .* (E^H eta))
-    const int blk = 8;
+    const int blk = kSubBlock;
     for (int r0 = 0; r0 < nrhs; r0 += blk) {
       const int nb = std::min(blk, nrhs - r0);
       cx<double> *Et = static_cast<cx<double> *>(c->ws[0].ensure(fl * nb * sizeof(cx<double>)));

@@ -76,6 +76,7 @@ _SIGS = {
     "lqcd_batch_create": [_P, _I, ctypes.POINTER(_P)],
     "lqcd_batch_destroy": [_P],
     "lqcd_batch_set_grid": [_P, _I],
+    "lqcd_batch_set_tile": [_P, _I],
     "batch_solve": [_P, ctypes.POINTER(SolveParams), _P, _P, _P, _P, _I, ctypes.POINTER(SolveStats)],
     "batch_autotune": [_P, ctypes.POINTER(SolveParams), _P, _P, _P, ctypes.POINTER(_I), ctypes.POINTER(_I), _P],
     "batch_wilson_apply": [_P, _P, _P, _P],
@@ -219,11 +220,11 @@ class Context:
 
     def tune(self, hop_nb64=None, hop_nb32=None, hop_tile64=None, hop_tile32=None, hop_order=None,
              hop_tblock64=None, hop_tblock32=None, hop_tsites32=None, hop_rgroup=None, hop_tsites64=None,
-             gemm_mfma=None, hop_rnest=None, cycle_reorth=None):
+             gemm_mfma=None, hop_rnest=None, cycle_reorth=None, kept_period=None):
         """Set launch-shape parameters (see lqcd_tune_set)."""
         for code, v in ((0, hop_nb64), (1, hop_nb32), (2, hop_tile64), (3, hop_tile32), (4, hop_order),
                         (5, hop_tblock64), (6, hop_tblock32), (7, hop_tsites32), (8, hop_rgroup),
-                        (9, hop_tsites64), (10, gemm_mfma), (11, hop_rnest), (12, cycle_reorth)):
+                        (9, hop_tsites64), (10, gemm_mfma), (11, hop_rnest), (12, cycle_reorth), (13, kept_period)):
             if v is not None:
                 _check(lib().lqcd_tune_set(self.handle, code, int(v)))
 
@@ -455,6 +456,11 @@ class Batch:
     def set_grid(self, workgroups):
         _check(lib().lqcd_batch_set_grid(self.handle, int(workgroups)))
 
+    def set_tile(self, tile_sites):
+        """Batched stencil form: 0 = persistent slot-table launch, 16/32/64 =
+        link tiles of that many sites per lattice group."""
+        _check(lib().lqcd_batch_set_tile(self.handle, int(tile_sites)))
+
     def wilson_apply(self, xs):
         """Mhat (FP32) of every field list entry, one launch over all lattices."""
         import torch
@@ -484,17 +490,22 @@ class Batch:
                    true_resid=s.true_resid) for s in stats[:total]]
         return xs, st
 
+    TUNE_BLOCKS = (4, 8, 16, 32)
+    TUNE_TILES = (0, 16, 32, 64)
+
     def autotune(self, bs, defls, m=20, k=10, tol=1e-10, max_cycles=1000, inner_tol=1e-4, proj_m=0):
-        """Returns (best rhs_block, best grid, {(rhs_block, grid): rhs/s})."""
+        """Returns (best rhs_block, best tile, {(rhs_block, tile): rhs/s});
+        tile 0 is the persistent slot-table stencil."""
         nr = (_I * len(bs))(*[b.shape[0] for b in bs])
         p = self._params(m, k, tol, max_cycles, inner_tol, 8, proj_m)
         dp = (_P * len(defls))(*[d.handle.value for d in defls])
-        bb, bg = _I(0), _I(0)
-        rates = np.zeros(8)
+        bb, bt = _I(0), _I(0)
+        nt = len(self.TUNE_TILES)
+        rates = np.zeros(len(self.TUNE_BLOCKS) * nt)
         _check(lib().batch_autotune(self.handle, ctypes.byref(p), self._ptrs(bs), nr, dp, ctypes.byref(bb),
-                                    ctypes.byref(bg), rates.ctypes.data_as(_P)))
+                                    ctypes.byref(bt), rates.ctypes.data_as(_P)))
         table = {}
-        for i, blk in enumerate((4, 8, 16, 32)):
-            for j, g in enumerate((2048, 8192)):
-                table[(blk, g)] = float(rates[2 * i + j])
-        return bb.value, bg.value, table
+        for i, blk in enumerate(self.TUNE_BLOCKS):
+            for j, t in enumerate(self.TUNE_TILES):
+                table[(blk, t)] = float(rates[nt * i + j])
+        return bb.value, bt.value, table

@@ -2,11 +2,14 @@
 sizes and hopping parameters, uneven right-hand-side counts).
 
 * batch_wilson_apply: one persistent launch per half hop over every
-  lattice's fields equals the oracle's even/odd operator (FP32 rounding);
+  lattice's fields (or one link-tiled launch per lattice) equals the
+  oracle's even/odd operator (FP32 rounding);
 * batch_solve (eager and hipGraph-captured cycles, right-hand-side blocks
-  that mix lattices): every solution equals dense LU to 1e-9 with an FP64
-  true residual below the tolerance, and the captured and eager runs give
-  the same iteration counts;
+  that mix lattices, both stencil forms; with link tiles the blocks' lattice
+  runs change from block to block, so the captured cycle is recorded
+  again): every solution equals dense LU to 1e-9 with an FP64 true residual
+  below the tolerance, and the captured and eager runs give the same
+  iteration counts and bitwise equal solutions;
 * batch_autotune returns one of its candidates and a rate for each.
 """
 import numpy as np
@@ -35,7 +38,8 @@ def _setup(lats):
     return ctxs, Us, defls, etas
 
 
-def test_batch_wilson_apply():
+@pytest.mark.parametrize("tile", [0, 32])
+def test_batch_wilson_apply(tile):
     require_gpu()
     from paper_1903_06986_amd import Batch
     lats = LATS + [((2, 2, 2, 4), 0.1, 2, 1004)]
@@ -47,20 +51,23 @@ def test_batch_wilson_apply():
         Us.append(U)
         xs.append(rng.standard_normal((nr,) + ctx.shape) + 1j * rng.standard_normal((nr,) + ctx.shape))
     batch = Batch(ctxs)
-    say("batch wilson apply", [l[0] for l in lats])
+    batch.set_tile(tile)
+    say("batch wilson apply", [l[0] for l in lats], "tile", tile)
     ys = batch.wilson_apply([to_gpu(x) for x in xs])
     for (dims, kappa, nr, seed), U, x, y in zip(lats, Us, xs, ys):
         ref = W.apply_Mhat(U, kappa, x, dims)
         assert rel_err(to_host(y), ref) < 5e-6, dims
 
 
+@pytest.mark.parametrize("tile", [0, 16])
 @pytest.mark.parametrize("graph", [True, False])
-def test_batch_solve(graph):
+def test_batch_solve(graph, tile):
     require_gpu()
     from paper_1903_06986_amd import Batch
     ctxs, Us, defls, etas = _setup(LATS)
     batch = Batch(ctxs)
-    say("batch solve graph=%s" % graph)
+    batch.set_tile(tile)
+    say("batch solve graph=%s tile=%d" % (graph, tile))
     xs, st = batch.solve([to_gpu(e) for e in etas], defls, m=20, k=10, tol=1e-11, inner_tol=1e-4,
                          rhs_block=4, graph=graph)
     i = 0
@@ -75,12 +82,14 @@ def test_batch_solve(graph):
             i += 1
 
 
-def test_batch_graph_matches_eager():
+@pytest.mark.parametrize("tile", [0, 32])
+def test_batch_graph_matches_eager(tile):
     require_gpu()
     from paper_1903_06986_amd import Batch
     ctxs, Us, defls, etas = _setup(LATS)
     batch = Batch(ctxs)
-    say("batch graph vs eager")
+    batch.set_tile(tile)
+    say("batch graph vs eager tile", tile)
     xa, sa = batch.solve([to_gpu(e) for e in etas], defls, tol=1e-11, rhs_block=5, graph=True)
     xb, sb = batch.solve([to_gpu(e) for e in etas], defls, tol=1e-11, rhs_block=5, graph=False)
     assert [s["matvecs"] for s in sa] == [s["matvecs"] for s in sb]
@@ -94,7 +103,10 @@ def test_batch_autotune():
     ctxs, Us, defls, etas = _setup(LATS)
     batch = Batch(ctxs)
     say("batch autotune")
-    blk, grid, table = batch.autotune([to_gpu(e) for e in etas], defls, tol=1e-10)
-    assert blk in (4, 8, 16, 32) and grid in (2048, 8192)
-    assert table[(blk, grid)] == max(table.values()) > 0
-    assert all(v > 0 for (b, g), v in table.items() if b <= 12)
+    blk, tile, table = batch.autotune([to_gpu(e) for e in etas], defls, tol=1e-10)
+    assert blk in Batch.TUNE_BLOCKS and tile in Batch.TUNE_TILES
+    assert set(table) == {(b, t) for b in Batch.TUNE_BLOCKS for t in Batch.TUNE_TILES}
+    assert table[(blk, tile)] == max(table.values()) > 0
+    assert all(v > 0 for (b, t), v in table.items() if b <= 12)
+    with pytest.raises(Exception):
+        batch.set_tile(24)

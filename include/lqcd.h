@@ -428,8 +428,11 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * cancelled more than one digit; 1 runs it on every step (a check of that
  * pass; slower).  LQCD_TUNE_KEPT_PERIOD: MINRES-DR tests its basis against
  * the kept vectors of the last restart on every this-many-th step of a cycle
- * and on its last step (1..64, default 2).  Values are per context; EINVAL
- * for other values. */
+ * and on its last step (1..64, default 16).  LQCD_TUNE_ARNOLDI_STEPS: 1 or
+ * 2 (default) Arnoldi steps per pass over the basis in the GMRES-Proj
+ * cycles with a 16-bit basis (2: A v_j and A^2 v_j are orthogonalised
+ * together, reading the basis once for both).  Values are per context;
+ * EINVAL for other values. */
 typedef enum {
   LQCD_TUNE_HOP_NB64 = 0,
   LQCD_TUNE_HOP_NB32 = 1,
@@ -444,7 +447,8 @@ typedef enum {
   LQCD_TUNE_GEMM_MFMA = 10,
   LQCD_TUNE_HOP_RNEST = 11,
   LQCD_TUNE_CYCLE_REORTH = 12,
-  LQCD_TUNE_KEPT_PERIOD = 13
+  LQCD_TUNE_KEPT_PERIOD = 13,
+  LQCD_TUNE_ARNOLDI_STEPS = 14
 } lqcd_tune_param;
 lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 

@@ -267,16 +267,18 @@ __global__ void __launch_bounds__(kBlock)
 //   UPD_RV:    R -= sum_{jj<=kd} Vd_jj c_jj
 enum UpdSel { UPD_ORTH = 0, UPD_XW = 1, UPD_XV = 2, UPD_RV = 3 };
 constexpr int kAept = 4;
+constexpr int kBatchMaxJ = 256;  // basis vectors of one update (p + 1 <= 251, kd + 1 <= 251)
 
 template <int SEL>
 __global__ void __launch_bounds__(kBlock)
     k_bupdate(const BSlot *__restrict__ sl, int jnew, int Jw, const cx<double> *__restrict__ coef,
               int ldcf, double *__restrict__ part, size_t nblk, const int *__restrict__ flag) {
   __shared__ double sh[kWaves];
+  __shared__ cx<double> sc[kBatchMaxJ];
   const int s = blockIdx.y;
   const BSlot &d = sl[s];
   const size_t b = blockIdx.x;
-  const bool on = d.active && (!flag || flag[s]) && b * kBlock * kAept < d.n;
+  const bool on = d.active && (!flag || flag[s]) && b * kBlock * kAept < d.n;  // uniform per workgroup
   double nrm = 0;
   if (on) {
     const size_t n = d.n;
@@ -305,7 +307,11 @@ __global__ void __launch_bounds__(kBlock)
       J = d.kd + 1;
       sign = -1;
     }
-    const cx<double> *cf = coef + size_t(s) * ldcf;
+    // the coefficients (times the sign) from LDS, not one scalar load and
+    // its wait per pass
+    for (int t = threadIdx.x; t < J; t += kBlock) sc[t] = sign * coef[size_t(s) * ldcf + t];
+    __syncthreads();
+    const cx<double> *cf = sc;
     const size_t base = b * kBlock * kAept + threadIdx.x;
     cx<double> acc[kAept];
 #pragma unroll
@@ -316,8 +322,7 @@ __global__ void __launch_bounds__(kBlock)
     }
     int jj = 0;
     for (; jj + 4 <= J; jj += 4) {  // four basis vectors per pass: 16 loads in flight per lane
-      const cx<double> c0 = sign * cf[jj], c1 = sign * cf[jj + 1], c2 = sign * cf[jj + 2],
-                       c3 = sign * cf[jj + 3];
+      const cx<double> c0 = cf[jj], c1 = cf[jj + 1], c2 = cf[jj + 2], c3 = cf[jj + 3];
       const cx<float> *v0 = V + size_t(jj) * n;
 #pragma unroll
       for (int e = 0; e < kAept; ++e) {
@@ -331,7 +336,7 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
     for (; jj < J; ++jj) {
-      const cx<double> c = sign * cf[jj];
+      const cx<double> c = cf[jj];
       const cx<float> *v0 = V + size_t(jj) * n;
 #pragma unroll
       for (int e = 0; e < kAept; ++e) {
@@ -589,8 +594,11 @@ struct Engine {
   int tile = 0;
   std::vector<Group> groups;
   cx<float> *W = nullptr, *T = nullptr, *X = nullptr, *R = nullptr;
-  size_t nchunk() const { return (nmax + size_t(kWch) * kWaves - 1) / (size_t(kWch) * kWaves) * kWaves; }
-  size_t nblk() const { return (nmax + size_t(kBlock) * kAept - 1) / (size_t(kBlock) * kAept); }
+  // longest vector of the block in flight (the grids of the batched
+  // reductions and updates cover this much; slot buffers stay nmax apart)
+  size_t nlen = 0;
+  size_t nchunk() const { return (nlen + size_t(kWch) * kWaves - 1) / (size_t(kWch) * kWaves) * kWaves; }
+  size_t nblk() const { return (nlen + size_t(kBlock) * kAept - 1) / (size_t(kBlock) * kAept); }
   unsigned hop_grid() const { return std::min<unsigned>((items + 7) / 8 * 8, hgrid); }
 
   void stencil_schur_w(int j) const {
@@ -654,7 +662,7 @@ struct Engine {
     int *fl = b->flag.as<int>();
     const size_t Hrs = size_t(p + 1) * p;
     norm_r(n2 + B);
-    hipLaunchKernelGGL(k_bscale<1>, dim3(grid_n(nmax), B), dim3(kBlock), 0, b->stream, sl, 0, n2 + B);
+    hipLaunchKernelGGL(k_bscale<1>, dim3(grid_n(nlen), B), dim3(kBlock), 0, b->stream, sl, 0, n2 + B);
     for (int j = 0; j < p; ++j) {
       stencil_schur_w(j);
       dots<BAS_W>(j + 1, j + 1, p + 1, h1, nullptr);
@@ -664,7 +672,7 @@ struct Engine {
       update<UPD_ORTH>(j + 1, j + 1, h2, p + 1, n2, fl);
       hipLaunchKernelGGL(k_bfinish, dim3(B), dim3(64), 0, b->stream, Hd, Hrs, p + 1, j, h1, h2, p + 1, n1, n2,
                          fl, iv);
-      hipLaunchKernelGGL(k_bscale<0>, dim3(grid_n(nmax), B), dim3(kBlock), 0, b->stream, sl, j + 1, iv);
+      hipLaunchKernelGGL(k_bscale<0>, dim3(grid_n(nlen), B), dim3(kBlock), 0, b->stream, sl, j + 1, iv);
     }
   }
 };
@@ -725,6 +733,7 @@ void run_batch(lqcd_batch *b, const lqcd_solve_params &prm, const void *const *b
   cx<double> *TF = static_cast<cx<double> *>(b->TF.ensure(size_t(B) * flmax * sizeof(cx<double>)));
   BSlot *sld = static_cast<BSlot *>(b->slots_dev.ensure(size_t(B) * sizeof(BSlot)));
   Engine e{b, B, p, nmax, per, unsigned(B) * per, unsigned(b->hop_grid), kdmax, sld};
+  e.nlen = nmax;
   e.tile = b->tile;
   e.W = W;
   e.T = T;
@@ -853,6 +862,10 @@ void run_batch(lqcd_batch *b, const lqcd_solve_params &prm, const void *const *b
                           return u.c == v.c && u.s0 == v.s0 && u.G == v.G;
                         });
       e.groups = g;
+      // the block's longest vector bounds the batched grids (it changes
+      // only with the lattice runs, so the recorded cycle stays valid)
+      e.nlen = 0;
+      for (const Group &gr : g) e.nlen = std::max(e.nlen, gr.n);
       if (use_graph && (!same || !exec)) record();
     }
     {
@@ -968,7 +981,7 @@ void run_batch(lqcd_batch *b, const lqcd_solve_params &prm, const void *const *b
         e.update<UPD_XW>(0, p, cd, p, nullptr, nullptr);
         // true inner residual r = s - Mhat x
         e.stencil_schur_x();
-        hipLaunchKernelGGL(k_bresid, dim3(grid_n(nmax), B), dim3(kBlock), 0, b->stream, sld);
+        hipLaunchKernelGGL(k_bresid, dim3(grid_n(e.nlen), B), dim3(kBlock), 0, b->stream, sld);
         LQCD_HIP(hipGetLastError());
       }
       // x += e (FP64), r = S - Mhat x (FP64)
@@ -1201,6 +1214,7 @@ extern "C" lqcd_status batch_wilson_apply(lqcd_batch *b, const void *const *in, 
     }
     h2d_b(b, sld, slh.data(), size_t(B) * sizeof(BSlot));
     Engine e{b, B, 1, nmax, per, unsigned(B) * per, unsigned(b->hop_grid), 0, sld};
+    e.nlen = nmax;
     e.tile = b->tile;
     e.X = X;
     e.R = R;

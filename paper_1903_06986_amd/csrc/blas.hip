@@ -168,11 +168,15 @@ __global__ void __launch_bounds__(kBlock)
             const cx<double> *__restrict__ coef, size_t coef_rs, cx<R> *__restrict__ w,
             size_t w_rs, size_t n, double *__restrict__ part, const int *__restrict__ flag) {
   __shared__ double sh[1][kWaves];
+  __shared__ cx<double> sc[kMaxJ];
   const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
   if (flag && flag[r] == 0) return;
   V += r * V_rs;
   w += r * w_rs;
   coef += r * coef_rs;
+  // the coefficients from LDS, not one scalar load (and its wait) per pass
+  for (int t = threadIdx.x; t < J; t += kBlock) sc[t] = coef[t];
+  __syncthreads();
   const size_t base = size_t(b) * ACH + threadIdx.x;
   cx<double> acc[AEPT];
 #pragma unroll
@@ -182,7 +186,7 @@ __global__ void __launch_bounds__(kBlock)
   }
   int j = 0;
   for (; j + 4 <= J; j += 4) {
-    const cx<double> c0 = coef[j], c1 = coef[j + 1], c2 = coef[j + 2], c3 = coef[j + 3];
+    const cx<double> c0 = sc[j], c1 = sc[j + 1], c2 = sc[j + 2], c3 = sc[j + 3];
     const cx<R> *v = V + size_t(j) * ldv;
 #pragma unroll
     for (int e = 0; e < AEPT; ++e) {
@@ -195,7 +199,7 @@ __global__ void __launch_bounds__(kBlock)
     }
   }
   for (; j < J; ++j) {
-    const cx<double> c0 = coef[j];
+    const cx<double> c0 = sc[j];
 #pragma unroll
     for (int e = 0; e < AEPT; ++e) {
       size_t idx = base + size_t(e) * kBlock;
@@ -601,11 +605,16 @@ __global__ void __launch_bounds__(kBlock)
                size_t w_rs, uint32_t *out, size_t out_rs, size_t Vh, double *__restrict__ part,
                const int *__restrict__ flag) {
   __shared__ double sh[1][kWaves];
+  __shared__ cx<float> sc[kMaxJ];
   const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
   if (flag && flag[r] == 0) return;
   V += r * V_rs;
   out += r * out_rs;
   coef += r * coef_rs;
+  // the coefficients (FP32) from LDS, not one scalar load and its wait per
+  // basis vector
+  for (int t = threadIdx.x; t < J; t += kBlock) sc[t] = mk(float(coef[t].re), float(coef[t].im));
+  __syncthreads();
   const size_t i = size_t(b) * kBlock + threadIdx.x;
   const bool on = i < Vh;
   double nrm[1] = {0};
@@ -630,8 +639,8 @@ __global__ void __launch_bounds__(kBlock)
     if (J > 1) hraw_load(V + ldv, Vh, i, nx1);
     for (int j = 0; j < J; ++j) {
       if (j + 2 < J) hraw_load(V + size_t(j + 2) * ldv, Vh, i, nx2);
-      const cx<double> cd = coef[j];
-      const cx<float> ca = mk(cur.sc * float(cd.re), cur.sc * float(cd.im));
+      const cx<float> cf = sc[j];
+      const cx<float> ca = mk(cur.sc * cf.re, cur.sc * cf.im);
 #pragma unroll
       for (int c = 0; c < 12; ++c) a[c] = a[c] - Codec<K>::unpack(cur.w(c)) * ca;
       cur = nx1;
@@ -643,6 +652,165 @@ __global__ void __launch_bounds__(kBlock)
     block_sum<1>(nrm, sh);
     if (threadIdx.x == 0) part[size_t(r) * nblk + b] = nrm[0];
   }
+}
+
+// ------------------------------------------ two-step Arnoldi (16-bit basis)
+// Two new directions at once against one basis read: z1 = A v_j and z2 =
+// A z1 (FP32) are projected on V_0 .. V_{J-1} together, then
+// orthonormalised between themselves in FP32 and stored (see the solver).
+//
+// Dots of both vectors in one pass over the basis: part[r][chunk][2J]
+// (complex as re, im), entries j < J for w1, J + j for w2.
+template <HKind K>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+    k_hmdot2_part(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
+                  const cx<float> *__restrict__ w1, const cx<float> *__restrict__ w2, size_t w_rs, size_t Vh,
+                  double *__restrict__ part, const int *__restrict__ flag) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.y;
+  if (flag && flag[r] == 0) return;
+  const size_t nwch = size_t(gridDim.x) * kWaves;
+  const size_t chunk = size_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+  V += r * V_rs;
+  w1 += r * w_rs;
+  w2 += r * w_rs;
+  const size_t i = chunk * 64 + lane;  // the lane's site
+  const bool on = i < Vh;
+  cx<float> a[12], b[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    a[c] = on ? ldc(w1 + c * Vh + i) : mk(0.f, 0.f);
+    b[c] = on ? ldc(w2 + c * Vh + i) : mk(0.f, 0.f);
+  }
+  double *po = part + (size_t(r) * nwch + chunk) * size_t(2 * J) * 2;
+  // basis pipeline two vectors deep, as k_hmdot_part
+  HRaw cur, nx1, nx2;
+  if (on && J > 0) hraw_load(V, Vh, i, cur);
+  if (on && J > 1) hraw_load(V + ldv, Vh, i, nx1);
+  for (int j = 0; j < J; ++j) {
+    double a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    if (on) {
+      if (j + 2 < J) hraw_load(V + size_t(j + 2) * ldv, Vh, i, nx2);
+      float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const cx<float> v = Codec<K>::unpack(cur.w(c));
+        const cx<float> p = cmulc(v, a[c]), q = cmulc(v, b[c]);
+        ar += p.re;
+        ai += p.im;
+        br += q.re;
+        bi += q.im;
+      }
+      a0 = double(cur.sc * ar);
+      a1 = double(cur.sc * ai);
+      b0 = double(cur.sc * br);
+      b1 = double(cur.sc * bi);
+      cur = nx1;
+      nx1 = nx2;
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    b0 = wave_sum(b0);
+    b1 = wave_sum(b1);
+    if (lane == 0) {
+      po[2 * j] = a0;
+      po[2 * j + 1] = a1;
+      po[2 * (J + j)] = b0;
+      po[2 * (J + j) + 1] = b1;
+    }
+  }
+}
+
+// w1 -= V c1, w2 -= V c2 in place (FP32), coefficients coef[r][2J] (c1
+// first), and per-workgroup partials of |w1|^2, |w2|^2 and w1^H w2:
+// part[(r * nblk + b) * 4 + {0, 1, 2, 3}] = |w1|^2, |w2|^2, Re, Im.
+template <HKind K>
+__global__ void __launch_bounds__(kBlock)
+    k_hmaxpy2(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
+              const cx<double> *__restrict__ coef, size_t coef_rs, cx<float> *__restrict__ w1,
+              cx<float> *__restrict__ w2, size_t w_rs, size_t Vh, double *__restrict__ part,
+              const int *__restrict__ flag) {
+  __shared__ double sh[4][kWaves];
+  __shared__ cx<float> sc[2 * kMaxJ];
+  const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
+  if (flag && flag[r] == 0) return;
+  V += r * V_rs;
+  w1 += r * w_rs;
+  w2 += r * w_rs;
+  coef += r * coef_rs;
+  for (int t = threadIdx.x; t < 2 * J; t += kBlock) sc[t] = mk(float(coef[t].re), float(coef[t].im));
+  __syncthreads();
+  const size_t i = size_t(b) * kBlock + threadIdx.x;
+  const bool on = i < Vh;
+  double g[4] = {0, 0, 0, 0};
+  if (on) {
+    cx<float> a[12], bb[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      a[c] = ldc(w1 + c * Vh + i);
+      bb[c] = ldc(w2 + c * Vh + i);
+    }
+    HRaw cur, nx1, nx2;
+    if (J > 0) hraw_load(V, Vh, i, cur);
+    if (J > 1) hraw_load(V + ldv, Vh, i, nx1);
+    for (int j = 0; j < J; ++j) {
+      if (j + 2 < J) hraw_load(V + size_t(j + 2) * ldv, Vh, i, nx2);
+      const cx<float> c1 = sc[j], c2 = sc[J + j];
+      const cx<float> ca = mk(cur.sc * c1.re, cur.sc * c1.im), cb = mk(cur.sc * c2.re, cur.sc * c2.im);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const cx<float> v = Codec<K>::unpack(cur.w(c));
+        a[c] = a[c] - v * ca;
+        bb[c] = bb[c] - v * cb;
+      }
+      cur = nx1;
+      nx1 = nx2;
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      stc(w1 + c * Vh + i, a[c]);
+      stc(w2 + c * Vh + i, bb[c]);
+      g[0] += double(a[c].re) * a[c].re + double(a[c].im) * a[c].im;
+      g[1] += double(bb[c].re) * bb[c].re + double(bb[c].im) * bb[c].im;
+      const cx<float> p = cmulc(a[c], bb[c]);
+      g[2] += double(p.re);
+      g[3] += double(p.im);
+    }
+  }
+  if (part) {
+    block_sum<4>(g, sh);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) part[(size_t(r) * nblk + b) * 4 + k] = g[k];
+  }
+}
+
+// The two new basis vectors from the orthogonalised pair: slot j + 1 =
+// stored(f[r][0] w1), slot j + 2 = stored(f[r][1] w1 + f[r][2] w2), with
+// per-site scales (f: complex, 3 per right-hand side).
+template <HKind K>
+__global__ void __launch_bounds__(kBlock)
+    k_h2store(const cx<float> *__restrict__ w1, const cx<float> *__restrict__ w2, size_t w_rs,
+              const cx<double> *__restrict__ f, uint32_t *out1, uint32_t *out2, size_t out_rs, size_t Vh) {
+  const int r = blockIdx.y;
+  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= Vh) return;
+  w1 += r * w_rs;
+  w2 += r * w_rs;
+  out1 += r * out_rs;
+  out2 += r * out_rs;
+  const cx<double> f0 = f[3 * r], f1 = f[3 * r + 1], f2 = f[3 * r + 2];
+  const cx<float> a0 = mk(float(f0.re), float(f0.im)), a1 = mk(float(f1.re), float(f1.im)),
+                  a2 = mk(float(f2.re), float(f2.im));
+  cx<float> x[12], y[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const cx<float> u = ldc(w1 + c * Vh + i), v = ldc(w2 + c * Vh + i);
+    x[c] = u * a0;
+    y[c] = u * a1 + v * a2;
+  }
+  (void)hstore_site<K>(out1, Vh, i, x);
+  (void)hstore_site<K>(out2, Vh, i, y);
 }
 
 // Per-site scales of stored vectors times f[r] (normalises a vector that
@@ -1279,6 +1447,7 @@ void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, c
   const int nblk = int((Vh + kBlock - 1) / kBlock);  // one site per lane
   double *part = nullptr;
   if (norm2_out) part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * sizeof(double)));
+  LQCD_CHECK(J <= kMaxJ, LQCD_EINVAL, "basis of %d vectors exceeds %d", J, kMaxJ);
   const double win = w ? n * sizeof(cx<float>) : hbytes(n);
   Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + win + hbytes(n)) * nrhs);
   if (w)
@@ -1296,6 +1465,55 @@ void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, c
     hipLaunchKernelGGL(k_sum_final, dim3(nrhs), dim3(kBlock), 0, c->stream, part, nblk, norm2_out, flag);
     LQCD_HIP(hipGetLastError());
   }
+}
+
+template <int KIND>
+void hmulti_dot2(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w1, const void *w2,
+                 size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag) {
+  if (J <= 0 || nrhs <= 0) return;
+  constexpr HKind K = static_cast<HKind>(KIND);
+  const size_t Vh = n / 12;
+  const int ngrid = int((Vh + kBlock - 1) / kBlock);
+  const int nblk = ngrid * kWaves;
+  double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * 2 * J * 2 * sizeof(double)));
+  Timed tm(c, LQCD_KC_DOT, flag ? 0.0 : (J * hbytes(n) + 2.0 * n * sizeof(cx<float>)) * nrhs);
+  LQCD_TLAUNCH(tm, true, true, (k_hmdot2_part<K>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
+               static_cast<const uint32_t *>(V), ldv, V_rs, J, static_cast<const cx<float> *>(w1),
+               static_cast<const cx<float> *>(w2), w_rs, Vh, part, flag);
+  LQCD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_mdot_final, dim3(2 * J, nrhs), dim3(kBlock), 0, c->stream, part, nblk, 2 * J,
+                     reinterpret_cast<cx<double> *>(out), out_rs, flag);
+  LQCD_HIP(hipGetLastError());
+}
+
+template <int KIND>
+int hmulti_axpy2(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
+                 size_t coef_rs, void *w1, void *w2, size_t w_rs, size_t n, int nrhs, double *part,
+                 const int *flag) {
+  const size_t Vh = n / 12;
+  const int nblk = int((Vh + kBlock - 1) / kBlock);  // one site per lane
+  if (nrhs <= 0) return nblk;
+  LQCD_CHECK(J <= kMaxJ, LQCD_EINVAL, "basis of %d vectors exceeds %d", J, kMaxJ);
+  constexpr HKind K = static_cast<HKind>(KIND);
+  Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + 4.0 * n * sizeof(cx<float>)) * nrhs);
+  LQCD_TLAUNCH(tm, true, true, (k_hmaxpy2<K>), dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
+               static_cast<const uint32_t *>(V), ldv, V_rs, J, reinterpret_cast<const cx<double> *>(coef), coef_rs,
+               static_cast<cx<float> *>(w1), static_cast<cx<float> *>(w2), w_rs, Vh, part, flag);
+  LQCD_HIP(hipGetLastError());
+  return nblk;
+}
+
+template <int KIND>
+void h2store(lqcd_ctx *c, const void *w1, const void *w2, size_t w_rs, const cdouble *f, void *out1, void *out2,
+             size_t out_rs, size_t n, int nrhs) {
+  if (nrhs <= 0) return;
+  constexpr HKind K = static_cast<HKind>(KIND);
+  const size_t Vh = n / 12;
+  hipLaunchKernelGGL((k_h2store<K>), dim3(nblocks(Vh), nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const cx<float> *>(w1), static_cast<const cx<float> *>(w2), w_rs,
+                     reinterpret_cast<const cx<double> *>(f), static_cast<uint32_t *>(out1),
+                     static_cast<uint32_t *>(out2), out_rs, Vh);
+  LQCD_HIP(hipGetLastError());
 }
 
 void hscale_dev(lqcd_ctx *c, void *x, size_t x_rs, size_t n, int nrhs, const double *f) {
@@ -1355,6 +1573,12 @@ void inv_sqrt_dev(lqcd_ctx *c, const double *nrm2, double *inv, int nb) {
 #define HINST(K)                                                                                  \
   template void hmulti_dot<K>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
                               size_t, int, cdouble *, size_t, const int *, bool);                  \
+  template void hmulti_dot2<K>(lqcd_ctx *, const void *, size_t, size_t, int, const void *,         \
+                               const void *, size_t, size_t, int, cdouble *, size_t, const int *); \
+  template int hmulti_axpy2<K>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,      \
+                               size_t, void *, void *, size_t, size_t, int, double *, const int *); \
+  template void h2store<K>(lqcd_ctx *, const void *, const void *, size_t, const cdouble *, void *,  \
+                           void *, size_t, size_t, int);                                            \
   template void hmulti_axpy_q<K>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,   \
                                  size_t, const void *, size_t, void *, size_t, size_t, int,        \
                                  double *, const int *);                                           \

@@ -134,6 +134,7 @@ struct lqcd_ctx {
   lqcd::DevBuf red_out;  // reduction results (device)
   lqcd::DevBuf sw[16];   // solver fields
   lqcd::DevBuf small[2]; // solver small matrices
+  lqcd::DevBuf sstep;    // two-step Arnoldi: coefficients, Gram partials and factors
   lqcd::DevBuf grad[3];  // loop_gradient: right-hand sides, solutions, adjoint source matrices
   lqcd::KTimer timer;
   int hop_nb[2] = {2, 1};  // largest lane-grouped right-hand-side count: FP64, FP32
@@ -145,7 +146,8 @@ struct lqcd_ctx {
   int hop_rnest = -1;            // tiled stencil: groups swept in turn within each block (0: off, -1: auto)
   int gemm_mfma = 1;             // V C with one shared basis on the matrix cores (0: FMA kernel)
   int cycle_reorth = 0;          // 1: second Gram-Schmidt pass on every GMRES-Proj step
-  int kept_period = 2;           // MINRES-DR: steps between tests against the kept vectors
+  int kept_period = 16;          // MINRES-DR: steps between tests against the kept vectors
+  int arnoldi_steps = 2;         // 16-bit GMRES-Proj cycles: Arnoldi steps per basis pass (1 or 2)
   ~lqcd_ctx();
 };
 

@@ -208,6 +208,10 @@ extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int val
                    "lqcd_tune_set: right-hand sides per nested group in -1..4096");
         c->hop_rnest = value;
         break;
+      case LQCD_TUNE_ARNOLDI_STEPS:
+        LQCD_CHECK(value == 1 || value == 2, LQCD_EINVAL, "lqcd_tune_set: Arnoldi steps per basis pass must be 1 or 2");
+        c->arnoldi_steps = value;
+        break;
       case LQCD_TUNE_KEPT_PERIOD:
         LQCD_CHECK(value >= 1 && value <= 64, LQCD_EINVAL, "lqcd_tune_set: kept-vector test period in 1..64");
         c->kept_period = value;

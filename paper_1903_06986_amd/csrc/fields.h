@@ -88,6 +88,22 @@ template <int KIND>
 void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
                    size_t coef_rs, const void *w, size_t w_rs, void *out, size_t out_rs, size_t n, int nrhs,
                    double *norm2_out, const int *flag);
+// Two-step Arnoldi on a 16-bit basis: out[r][0..2J) = V^H w1 then V^H w2
+// (rows out_rs apart); w1 -= V c1, w2 -= V c2 in place (coef[r] = c1 then
+// c2) with per-workgroup partials part[(r nblk + b) 4 + {|w1|^2, |w2|^2,
+// Re w1^H w2, Im w1^H w2}] (returns nblk; part sized by the caller: nrhs x
+// nblk x 4 doubles, nblk = ceil(n / 12 / 256)); slot 1 = stored(f0 w1),
+// slot 2 = stored(f1 w1 + f2 w2) with f[3 r + i] complex.
+template <int KIND>
+void hmulti_dot2(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w1, const void *w2,
+                 size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag);
+template <int KIND>
+int hmulti_axpy2(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
+                 size_t coef_rs, void *w1, void *w2, size_t w_rs, size_t n, int nrhs, double *part,
+                 const int *flag);
+template <int KIND>
+void h2store(lqcd_ctx *c, const void *w1, const void *w2, size_t w_rs, const cdouble *f, void *out1, void *out2,
+             size_t out_rs, size_t n, int nrhs);
 // Per-site scales of nrhs stored vectors (x_rs words apart) times f[r]
 // (device array).
 void hscale_dev(lqcd_ctx *c, void *x, size_t x_rs, size_t n, int nrhs, const double *f);

@@ -98,6 +98,113 @@ __global__ void k_finish_col(cx<double> *__restrict__ Hd, size_t Hrs, int ldh, i
   }
 }
 
+constexpr int kSstepMaxJ = 256;  // basis vectors before a pair (J <= m + 1 <= 251)
+
+// Two-step Arnoldi (16-bit basis): after the first block pass, the Gram
+// partials of the pair are summed into G[r] = {|y1|^2, |y2|^2, Re y1^H y2,
+// Im y1^H y2} and the DGKS test runs on each of the two vectors against its
+// coefficients c1 = C[0..J), c2 = C[J..2J).
+__global__ void k_sstep_test(const double *__restrict__ part, int nblk, const cx<double> *__restrict__ C,
+                             size_t ldc2, int J, double *__restrict__ G, int *__restrict__ flag,
+                             int *__restrict__ reorth_count, double eta2) {
+  const int r = blockIdx.x;
+  double g[4] = {0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] += part[(size_t(r) * nblk + b) * 4 + k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) g[k] += __shfl_xor(g[k], off, 64);
+  if (threadIdx.x != 0) return;
+  double h1 = 0, h2 = 0;
+  for (int i = 0; i < J; ++i) {
+    const cx<double> a = C[r * ldc2 + i], b = C[r * ldc2 + J + i];
+    h1 += a.re * a.re + a.im * a.im;
+    h2 += b.re * b.re + b.im * b.im;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) G[4 * r + k] = g[k];
+  const int need = (g[0] < eta2 * (g[0] + h1) || g[1] < eta2 * (g[1] + h2)) ? 1 : 0;
+  flag[r] = need;
+  if (need) reorth_count[r] += 1;
+}
+
+// Columns j and j + 1 of Hbar from the pair z1 = A v_j, z2 = A z1 (one
+// 64-lane block per right-hand side).  With y1 = z1 - V c1 = r11 v_{j+1}
+// and y2 = z2 - V c2 = r12 v_{j+1} + r22 v_{j+2} (Cholesky factor of the
+// pair's Gram matrix):
+//   A v_j     = V c1 + r11 v_{j+1}                     (column j)
+//   A v_{j+1} = (z2 - sum_{i<=j} c1_i A v_i) / r11
+//             = (V c2 + r12 v_{j+1} + r22 v_{j+2} - V_{j+2} Hbar_{:, 0..j} c1) / r11.
+// c = first pass + second (flagged) pass coefficients; the Gram matrix is
+// that of the final vectors (G, or the second pass's partials).  f[r] =
+// {1 / r11, -r12 / (r11 r22), 1 / r22} turns the pair into v_{j+1},
+// v_{j+2} (zero where a factor vanishes).
+__global__ void k_sstep_finish(cx<double> *__restrict__ Hd, size_t Hrs, int ldh, int j,
+                               const cx<double> *__restrict__ C1, const cx<double> *__restrict__ C2, size_t ldc2,
+                               const double *__restrict__ part, int nblk, const double *__restrict__ G,
+                               const int *__restrict__ flag, cx<double> *__restrict__ f) {
+  __shared__ cx<double> sc1[kSstepMaxJ], sc2[kSstepMaxJ];
+  __shared__ double sg[4];
+  const int r = blockIdx.x, J = j + 1;
+  const bool two = flag[r] != 0;
+  for (int i = threadIdx.x; i < J; i += blockDim.x) {
+    cx<double> a = C1[r * ldc2 + i], b = C1[r * ldc2 + J + i];
+    if (two) {
+      a = a + C2[r * ldc2 + i];
+      b = b + C2[r * ldc2 + J + i];
+    }
+    sc1[i] = a;
+    sc2[i] = b;
+  }
+  double g[4] = {0, 0, 0, 0};
+  if (two) {
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) g[k] += part[(size_t(r) * nblk + b) * 4 + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) g[k] += __shfl_xor(g[k], off, 64);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] = G[4 * r + k];
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sg[k] = g[k];
+  __syncthreads();
+  const double g11 = sg[0], g22 = sg[1];
+  const double r11 = sqrt(g11);
+  const bool ok1 = r11 > 0 && isfinite(r11);
+  const cx<double> r12 = ok1 ? mk(sg[2] / r11, sg[3] / r11) : mk(0.0, 0.0);
+  const double d22 = g22 - (r12.re * r12.re + r12.im * r12.im);
+  const double r22 = d22 > 0 ? sqrt(d22) : 0.0;
+  const bool ok2 = ok1 && r22 > 0 && isfinite(r22);
+  cx<double> *H0 = Hd + r * Hrs;
+  cx<double> *colj = H0 + size_t(j) * ldh, *colk = colj + ldh;
+  // column j + 1: rows 0 .. j + 2; (Hbar c1)_k over the columns 0 .. j - 1
+  // already stored and column j = (c1; r11)
+  for (int k = threadIdx.x; k <= J + 1; k += blockDim.x) {
+    if (k > J) {  // row j + 2
+      colk[k] = mk(ok1 ? r22 / r11 : 0.0, 0.0);
+      continue;
+    }
+    cx<double> hc = mk(0.0, 0.0);
+    for (int i = k > 0 ? k - 1 : 0; i < j; ++i) hc = hc + H0[size_t(i) * ldh + k] * sc1[i];
+    hc = hc + (k <= j ? sc1[k] : mk(r11, 0.0)) * sc1[j];
+    const cx<double> top = k <= j ? sc2[k] : r12;
+    colk[k] = ok1 ? (1.0 / r11) * (top - hc) : mk(0.0, 0.0);
+  }
+  for (int i = threadIdx.x; i <= J; i += blockDim.x) colj[i] = i < J ? sc1[i] : mk(r11, 0.0);
+  if (threadIdx.x == 0) {
+    f[3 * r] = mk(ok1 ? 1.0 / r11 : 0.0, 0.0);
+    f[3 * r + 1] = ok2 ? (-1.0 / (r11 * r22)) * r12 : mk(0.0, 0.0);
+    f[3 * r + 2] = mk(ok2 ? 1.0 / r22 : 0.0, 0.0);
+  }
+}
+
 __global__ void k_izero(int *__restrict__ p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -282,6 +389,48 @@ void arnoldi_h(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, s
   }
 }
 
+// Two-step form of arnoldi_h: Arnoldi steps j0 .. m - 1 in pairs.  For a
+// pair, z1 = A v_j and z2 = A z1 (FP32) are projected on the basis
+// together, in one dot pass and one update pass over it (the single-step
+// form reads the basis twice per step), with the DGKS test on both and a
+// second block pass where it asks; then the two are orthonormalised
+// between themselves by the Cholesky factor of their Gram matrix, in FP32,
+// and stored (each stored value rounded once, after its whole
+// orthogonalisation, as in the single-step form).  The Hessenberg columns
+// follow from A v_{j+1} = (z2 - A V c1) / r11 (k_sstep_finish).  The Krylov
+// space is the same; an odd last step runs in the single-step form.
+template <int BK>
+void arnoldi_h2(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, size_t Wrs, int j0, int m,
+                int nb, Small &s, double eta2, void *wt, void *wt2) {
+  uint32_t *Wb = static_cast<uint32_t *>(W);
+  const size_t ldc2 = 2 * size_t(m + 1);
+  const int nblk = int((n / 12 + kBlock - 1) / kBlock);
+  char *q = static_cast<char *>(c->sstep.ensure(2 * ldc2 * nb * sizeof(cdouble) + 3 * nb * sizeof(cdouble) +
+                                                4 * nb * sizeof(double) + size_t(nb) * nblk * 4 * sizeof(double)));
+  cdouble *C1 = reinterpret_cast<cdouble *>(q), *C2 = C1 + ldc2 * nb, *f = C2 + ldc2 * nb;
+  double *G = reinterpret_cast<double *>(f + 3 * nb), *part = G + 4 * nb;
+  int j = j0;
+  for (; j + 2 <= m; j += 2) {
+    uint32_t *y1 = Wb + size_t(j + 1) * ldv, *y2 = Wb + size_t(j + 2) * ldv;
+    A.template apply_h<BK>(Wb + size_t(j) * ldv, Wrs, wt, n, nb);
+    A.apply(wt, n, wt2, n, nb);
+    hmulti_dot2<BK>(c, Wb, ldv, Wrs, j + 1, wt, wt2, n, n, nb, C1, ldc2, nullptr);
+    hmulti_axpy2<BK>(c, Wb, ldv, Wrs, j + 1, C1, ldc2, wt, wt2, n, n, nb, part, nullptr);
+    hipLaunchKernelGGL(k_sstep_test, dim3(nb), dim3(64), 0, c->stream, part, nblk,
+                       reinterpret_cast<const cx<double> *>(C1), ldc2, j + 1, G, s.flag, s.reorth, eta2);
+    LQCD_HIP(hipGetLastError());
+    hmulti_dot2<BK>(c, Wb, ldv, Wrs, j + 1, wt, wt2, n, n, nb, C2, ldc2, s.flag);
+    hmulti_axpy2<BK>(c, Wb, ldv, Wrs, j + 1, C2, ldc2, wt, wt2, n, n, nb, part, s.flag);
+    hipLaunchKernelGGL(k_sstep_finish, dim3(nb), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.Hd),
+                       s.Hrs, m + 1, j, reinterpret_cast<const cx<double> *>(C1),
+                       reinterpret_cast<const cx<double> *>(C2), ldc2, part, nblk, G, s.flag,
+                       reinterpret_cast<cx<double> *>(f));
+    LQCD_HIP(hipGetLastError());
+    h2store<BK>(c, wt, wt2, n, f, y1, y2, Wrs, n, nb);
+  }
+  if (j < m) arnoldi_h<BK>(c, A, W, n, ldv, Wrs, j, m, nb, s, eta2, wt);
+}
+
 // MINRES-DR basis extension (one right-hand side, FP64; hermitian A):
 // column j0 is orthogonalised twice against every vector before it (it
 // couples to all kept vectors of the restart); each later column by the
@@ -335,9 +484,9 @@ void lanczos_ext(lqcd_ctx *c, const Op<double> &A, void *V, size_t n, int j0, in
                          s.scratch_count, kReorthDR);
       LQCD_HIP(hipGetLastError());
       multi_dot<double>(c, wp, n, 0, 2, wn, 0, n, 1, s.h2 + (j - 1), m + 1, s.flag);
-      // the kept vectors are tested on every kept_period-th step (every
-      // other by default) and on the last step of a cycle (their
-      // coefficients stay zero otherwise)
+      // the kept vectors are tested on every kept_period-th step (16 by
+      // default) and on the last step of a cycle (their coefficients stay
+      // zero otherwise)
       const bool test = kept > 0 && ((j - j0) % c->kept_period == c->kept_period - 1 || j == m - 1);
       if (test) {
         multi_dot<double>(c, Vb, n, 0, kept, wn, 0, n, 1, s.h2, m + 1);
@@ -688,7 +837,11 @@ void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *
       norm2<R>(c, Rb, n, n, na, s.nrm2);
       inv_sqrt_dev(c, s.nrm2, s.inv, na);
       hquantize<BK>(c, Rb, n, s.inv, W, Wrs, n, na);
-      arnoldi_h<BK>(c, A, W, n, ldh, Wrs, 0, p, na, s, c->cycle_reorth ? kReorthAlways : kReorthCycle, wt);
+      const double eta2 = c->cycle_reorth ? kReorthAlways : kReorthCycle;
+      if (c->arnoldi_steps == 2)
+        arnoldi_h2<BK>(c, A, W, n, ldh, Wrs, 0, p, na, s, eta2, wt, static_cast<cx<float> *>(wt) + size_t(nb) * n);
+      else
+        arnoldi_h<BK>(c, A, W, n, ldh, Wrs, 0, p, na, s, eta2, wt);
     } else {
       axpby<R>(c, sc.data(), Rb, n, zs.data(), W, Wrs, n, na, true);
       arnoldi<R>(c, A, W, n, Wrs, 0, p, na, s, c->cycle_reorth ? kReorthAlways : kReorthCycle);
@@ -927,7 +1080,9 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
         const bool h16 = p.inner == LQCD_F16 || p.inner == LQCD_BF16;
         void *W32 = h16 ? w.W32.ensure(size_t(p_cyc + 1) * hvec_words(n / 12) * nb * sizeof(uint32_t))
                         : w.W32.ensure(size_t(p_cyc + 1) * n * nb * sizeof(cx<float>));
-        void *WT = h16 ? w.WT.ensure(n * nb * sizeof(cx<float>)) : nullptr;
+        // FP32 work vectors of the 16-bit Arnoldi steps (two per right-hand
+        // side in the two-step form)
+        void *WT = h16 ? w.WT.ensure(n * nb * sizeof(cx<float>) * (c->arnoldi_steps == 2 ? 2 : 1)) : nullptr;
         void *T = w.T.ensure(n * nb * sizeof(cx<double>));
         fill_zero(c, X, n * nb * sizeof(cx<double>));
         copy_dev(c, Rr, w.S.ptr, n * nb * sizeof(cx<double>));

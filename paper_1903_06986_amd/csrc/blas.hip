@@ -658,6 +658,29 @@ __global__ void __launch_bounds__(kBlock)
 // Two new directions at once against one basis read: z1 = A v_j and z2 =
 // A z1 (FP32) are projected on V_0 .. V_{J-1} together, then
 // orthonormalised between themselves in FP32 and stored (see the solver).
+// z1 and z2 are in the pair layout (16-byte granules of two components,
+// [6][Vh]): a lane loads a site's 12 components with six 16-byte loads.
+__device__ inline void ld_pair(const cx<float> *w, size_t Vh, size_t i, cx<float> a[12]) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int g = 0; g < 6; ++g) {
+    const f4v q = *reinterpret_cast<const f4v *>(w + 2 * (g * Vh + i));
+    a[2 * g] = mk(q.x, q.y);
+    a[2 * g + 1] = mk(q.z, q.w);
+  }
+}
+__device__ inline void st_pair(cx<float> *w, size_t Vh, size_t i, const cx<float> a[12]) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int g = 0; g < 6; ++g) {
+    f4v q;
+    q.x = a[2 * g].re;
+    q.y = a[2 * g].im;
+    q.z = a[2 * g + 1].re;
+    q.w = a[2 * g + 1].im;
+    *reinterpret_cast<f4v *>(w + 2 * (g * Vh + i)) = q;
+  }
+}
 //
 // Dots of both vectors in one pass over the basis: part[r][chunk][2J]
 // (complex as re, im), entries j < J for w1, J + j for w2.
@@ -677,10 +700,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 
   const size_t i = chunk * 64 + lane;  // the lane's site
   const bool on = i < Vh;
   cx<float> a[12], b[12];
+  if (on) {
+    ld_pair(w1, Vh, i, a);
+    ld_pair(w2, Vh, i, b);
+  } else {
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    a[c] = on ? ldc(w1 + c * Vh + i) : mk(0.f, 0.f);
-    b[c] = on ? ldc(w2 + c * Vh + i) : mk(0.f, 0.f);
+    for (int c = 0; c < 12; ++c) a[c] = b[c] = mk(0.f, 0.f);
   }
   double *po = part + (size_t(r) * nwch + chunk) * size_t(2 * J) * 2;
   // basis pipeline two vectors deep, as k_hmdot_part
@@ -745,11 +770,8 @@ __global__ void __launch_bounds__(kBlock)
   double g[4] = {0, 0, 0, 0};
   if (on) {
     cx<float> a[12], bb[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      a[c] = ldc(w1 + c * Vh + i);
-      bb[c] = ldc(w2 + c * Vh + i);
-    }
+    ld_pair(w1, Vh, i, a);
+    ld_pair(w2, Vh, i, bb);
     HRaw cur, nx1, nx2;
     if (J > 0) hraw_load(V, Vh, i, cur);
     if (J > 1) hraw_load(V + ldv, Vh, i, nx1);
@@ -766,10 +788,10 @@ __global__ void __launch_bounds__(kBlock)
       cur = nx1;
       nx1 = nx2;
     }
+    st_pair(w1, Vh, i, a);
+    st_pair(w2, Vh, i, bb);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      stc(w1 + c * Vh + i, a[c]);
-      stc(w2 + c * Vh + i, bb[c]);
       g[0] += double(a[c].re) * a[c].re + double(a[c].im) * a[c].im;
       g[1] += double(bb[c].re) * bb[c].re + double(bb[c].im) * bb[c].im;
       const cx<float> p = cmulc(a[c], bb[c]);
@@ -802,12 +824,13 @@ __global__ void __launch_bounds__(kBlock)
   const cx<double> f0 = f[3 * r], f1 = f[3 * r + 1], f2 = f[3 * r + 2];
   const cx<float> a0 = mk(float(f0.re), float(f0.im)), a1 = mk(float(f1.re), float(f1.im)),
                   a2 = mk(float(f2.re), float(f2.im));
-  cx<float> x[12], y[12];
+  cx<float> u[12], v[12], x[12], y[12];
+  ld_pair(w1, Vh, i, u);
+  ld_pair(w2, Vh, i, v);
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
-    const cx<float> u = ldc(w1 + c * Vh + i), v = ldc(w2 + c * Vh + i);
-    x[c] = u * a0;
-    y[c] = u * a1 + v * a2;
+    x[c] = u[c] * a0;
+    y[c] = u[c] * a1 + v[c] * a2;
   }
   (void)hstore_site<K>(out1, Vh, i, x);
   (void)hstore_site<K>(out2, Vh, i, y);

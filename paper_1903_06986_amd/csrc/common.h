@@ -190,6 +190,15 @@ void apply_schur(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs
 template <int KIND>
 void apply_schur_h(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin,
                    size_t sout, size_t stmp);
+// The same with the FP32 output in the pair layout (16-byte granules of
+// two components, as the odd temporary: component c of site i at complex
+// element 2 ((c / 2) Vh + i) + c % 2); and Mhat in FP32 with input and
+// output in that layout.
+template <int KIND>
+void apply_schur_h_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin,
+                        size_t sout, size_t stmp);
+void apply_schur_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,
+                      size_t stmp);
 
 // context.cpp: event timing of one launch (no-op unless the timer is on).
 // The events ride on the kernel dispatch itself (hipExtLaunchKernelGGL),

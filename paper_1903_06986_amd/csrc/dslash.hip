@@ -542,6 +542,39 @@ void apply_schur_h(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nr
 template void apply_schur_h<0>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
 template void apply_schur_h<1>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
 
+// The same with the FP32 output in the pair layout of the odd temporary
+// (16-byte granules of two components): the two-step Arnoldi's vectors.
+template <int KIND>
+void apply_schur_h_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin,
+                        size_t sout, size_t stmp) {
+  if (nrhs <= 0) return;
+  constexpr HKind K = static_cast<HKind>(KIND);
+  const double k = c->kappa;
+  const size_t n = half_len(c->g);
+  const SrcHalf<K> hin{static_cast<const uint32_t *>(in), n};
+  const SrcPlain<float> none{nullptr};
+  launch_hop_src<float, false, false, false, SrcHalf<K>, SrcPlain<float>, OutPair>(c, 1, hin, none, tmp_odd,
+                                                                                   cdouble(0, 0), 1.0, nrhs, sin,
+                                                                                   0, stmp);
+  launch_hop_src<float, false, false, true, SrcPair, SrcHalf<K>, OutPair>(
+      c, 0, SrcPair{static_cast<const cx<float> *>(tmp_odd)}, hin, out, cdouble(1, 0), -k * k, nrhs, stmp, sin,
+      sout);
+}
+template void apply_schur_h_pair<0>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
+template void apply_schur_h_pair<1>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
+
+// Mhat in FP32 with input, output and odd temporary in the pair layout.
+void apply_schur_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,
+                      size_t stmp) {
+  if (nrhs <= 0) return;
+  const double k = c->kappa;
+  const SrcPair x{static_cast<const cx<float> *>(in)};
+  launch_hop_src<float, false, false, false, SrcPair, SrcPlain<float>, OutPair>(
+      c, 1, x, SrcPlain<float>{nullptr}, tmp_odd, cdouble(0, 0), 1.0, nrhs, sin, 0, stmp);
+  launch_hop_src<float, false, false, true, SrcPair, SrcPair, OutPair>(
+      c, 0, SrcPair{static_cast<const cx<float> *>(tmp_odd)}, x, out, cdouble(1, 0), -k * k, nrhs, stmp, sin, sout);
+}
+
 template void hop_half<double>(lqcd_ctx *, int, const void *, const void *, void *, cdouble, double,
                                bool, bool, int, size_t, size_t, size_t);
 template void hop_half<float>(lqcd_ctx *, int, const void *, const void *, void *, cdouble, double,

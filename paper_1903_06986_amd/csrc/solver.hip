@@ -268,6 +268,21 @@ struct Op {
     void *t = tmp->ensure(hl * size_t(nb) * sizeof(cx<float>));
     apply_schur_h<BK>(c, in, out, t, nb, sin, sout, hl);
   }
+  // The same with the output in the FP32 pair layout; and Mhat on FP32
+  // pair-layout fields (the two-step Arnoldi's vectors).
+  template <int BK>
+  void apply_h_pair(const void *in, size_t sin, void *out, size_t sout, int nb) const {
+    if (nb <= 0) return;
+    const size_t hl = half_len(c->g);
+    void *t = tmp->ensure(hl * size_t(nb) * sizeof(cx<float>));
+    apply_schur_h_pair<BK>(c, in, out, t, nb, sin, sout, hl);
+  }
+  void apply_pair(const void *in, size_t sin, void *out, size_t sout, int nb) const {
+    if (nb <= 0) return;
+    const size_t hl = half_len(c->g);
+    void *t = tmp->ensure(hl * size_t(nb) * sizeof(cx<float>));
+    apply_schur_pair(c, in, out, t, nb, sin, sout, hl);
+  }
 };
 
 // Device scratch for the small per-cycle matrices.
@@ -390,7 +405,8 @@ void arnoldi_h(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, s
 }
 
 // Two-step form of arnoldi_h: Arnoldi steps j0 .. m - 1 in pairs.  For a
-// pair, z1 = A v_j and z2 = A z1 (FP32) are projected on the basis
+// pair, z1 = A v_j and z2 = A z1 (FP32, held in the 16-byte pair layout
+// of the operator's odd temporary) are projected on the basis
 // together, in one dot pass and one update pass over it (the single-step
 // form reads the basis twice per step), with the DGKS test on both and a
 // second block pass where it asks; then the two are orthonormalised
@@ -412,8 +428,8 @@ void arnoldi_h2(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, 
   int j = j0;
   for (; j + 2 <= m; j += 2) {
     uint32_t *y1 = Wb + size_t(j + 1) * ldv, *y2 = Wb + size_t(j + 2) * ldv;
-    A.template apply_h<BK>(Wb + size_t(j) * ldv, Wrs, wt, n, nb);
-    A.apply(wt, n, wt2, n, nb);
+    A.template apply_h_pair<BK>(Wb + size_t(j) * ldv, Wrs, wt, n, nb);
+    A.apply_pair(wt, n, wt2, n, nb);
     hmulti_dot2<BK>(c, Wb, ldv, Wrs, j + 1, wt, wt2, n, n, nb, C1, ldc2, nullptr);
     hmulti_axpy2<BK>(c, Wb, ldv, Wrs, j + 1, C1, ldc2, wt, wt2, n, n, nb, part, nullptr);
     hipLaunchKernelGGL(k_sstep_test, dim3(nb), dim3(64), 0, c->stream, part, nblk,

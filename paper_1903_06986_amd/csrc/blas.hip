@@ -654,12 +654,13 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// ------------------------------------------ two-step Arnoldi (16-bit basis)
-// Two new directions at once against one basis read: z1 = A v_j and z2 =
-// A z1 (FP32) are projected on V_0 .. V_{J-1} together, then
-// orthonormalised between themselves in FP32 and stored (see the solver).
-// z1 and z2 are in the pair layout (16-byte granules of two components,
-// [6][Vh]): a lane loads a site's 12 components with six 16-byte loads.
+// ------------------------------------------- s-step Arnoldi (16-bit basis)
+// S new directions at once against one basis read: z_1 = B v_j, z_k =
+// B z_{k-1} (FP32, B = Mhat - 1) are projected on V_0 .. V_{J-1} together,
+// then orthonormalised among themselves in FP32 and stored (see the
+// solver).  The z_k are in the pair layout (16-byte granules of two
+// components, [6][Vh]): a lane loads a site's 12 components with six
+// 16-byte loads; vector k of right-hand side r starts at w + r w_rs + k w_vs.
 __device__ inline void ld_pair(const cx<float> *w, size_t Vh, size_t i, cx<float> a[12]) {
   typedef float f4v __attribute__((ext_vector_type(4)));
 #pragma unroll
@@ -681,159 +682,207 @@ __device__ inline void st_pair(cx<float> *w, size_t Vh, size_t i, const cx<float
     *reinterpret_cast<f4v *>(w + 2 * (g * Vh + i)) = q;
   }
 }
-//
-// Dots of both vectors in one pass over the basis: part[r][chunk][2J]
-// (complex as re, im), entries j < J for w1, J + j for w2.
-template <HKind K>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
-    k_hmdot2_part(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
-                  const cx<float> *__restrict__ w1, const cx<float> *__restrict__ w2, size_t w_rs, size_t Vh,
-                  double *__restrict__ part, const int *__restrict__ flag) {
-  const int lane = threadIdx.x & 63;
-  const int r = blockIdx.y;
-  if (flag && flag[r] == 0) return;
-  const size_t nwch = size_t(gridDim.x) * kWaves;
-  const size_t chunk = size_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
-  V += r * V_rs;
-  w1 += r * w_rs;
-  w2 += r * w_rs;
-  const size_t i = chunk * 64 + lane;  // the lane's site
-  const bool on = i < Vh;
-  cx<float> a[12], b[12];
-  if (on) {
-    ld_pair(w1, Vh, i, a);
-    ld_pair(w2, Vh, i, b);
+
+// Sum of NP values over the 64 lanes of a wave, all NP at once: at each
+// of the first log2(NP) exchange steps a lane keeps half of its values and
+// trades the other half with its partner, so that NP sums cost NP - 1 + 6 -
+// log2(NP) shuffles instead of 6 NP.  Afterwards lane l holds in v[0] the
+// total of value l >> (6 - log2 NP).  (Recursion over the step, so that
+// every index into v is a compile-time constant.)
+template <int CNT, int OFF, int NP>
+__device__ inline void wave_sum_multi_step(float (&v)[NP], int lane) {
+  if constexpr (CNT > 1) {
+    const bool hi = (lane & OFF) != 0;
+#pragma unroll
+    for (int k = 0; k < CNT / 2; ++k) {
+      const float give = hi ? v[k] : v[k + CNT / 2];
+      const float keep = hi ? v[k + CNT / 2] : v[k];
+      v[k] = keep + __shfl_xor(give, OFF, 64);
+    }
+    wave_sum_multi_step<CNT / 2, OFF / 2, NP>(v, lane);
   } else {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) a[c] = b[c] = mk(0.f, 0.f);
+    for (int off = OFF; off > 0; off >>= 1) v[0] += __shfl_xor(v[0], off, 64);
   }
-  double *po = part + (size_t(r) * nwch + chunk) * size_t(2 * J) * 2;
+}
+template <int NP>
+__device__ inline void wave_sum_multi(float (&v)[NP], int lane) {
+  wave_sum_multi_step<NP, 32, NP>(v, lane);
+}
+
+// Dots of the S vectors in one pass over the basis: part[r][block][S J]
+// (complex as re, im), entry k J + j for w_k against V_j.  Each wave sums
+// its 64 sites in FP32 (as the lanes' own sums), the waves of a block are
+// added in FP64 at the end (dynamic LDS: kWaves * 2 S J floats).
+template <HKind K, int S>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(S <= 2 ? 4 : 2, 8)))
+    k_hmdots_part(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
+                  const cx<float> *__restrict__ w, size_t w_vs, size_t w_rs, size_t Vh, double *__restrict__ part,
+                  const int *__restrict__ flag) {
+  constexpr int NP = S <= 2 ? 4 : 8;  // 2 S values, padded to a power of two
+  constexpr int LB = NP == 4 ? 2 : 3;
+  extern __shared__ float dsh[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = blockIdx.y;
+  if (flag && flag[r] == 0) return;
+  const int nv = 2 * S * J;
+  V += r * V_rs;
+  w += r * w_rs;
+  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;  // the lane's site
+  const bool on = i < Vh;
+  cx<float> a[S][12];
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    if (on) {
+      ld_pair(w + k * w_vs, Vh, i, a[k]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) a[k][c] = mk(0.f, 0.f);
+    }
+  }
+  float *my = dsh + wave * nv;
+  const int idx = lane >> (6 - LB);                          // the value this lane ends up with
+  const bool writer = (lane & ((64 >> LB) - 1)) == 0 && idx < 2 * S;
+  const int wk = idx >> 1, wri = idx & 1;
   // basis pipeline two vectors deep, as k_hmdot_part
   HRaw cur, nx1, nx2;
   if (on && J > 0) hraw_load(V, Vh, i, cur);
   if (on && J > 1) hraw_load(V + ldv, Vh, i, nx1);
   for (int j = 0; j < J; ++j) {
-    double a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    float v[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) v[k] = 0.f;
     if (on) {
       if (j + 2 < J) hraw_load(V + size_t(j + 2) * ldv, Vh, i, nx2);
-      float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        const cx<float> v = Codec<K>::unpack(cur.w(c));
-        const cx<float> p = cmulc(v, a[c]), q = cmulc(v, b[c]);
-        ar += p.re;
-        ai += p.im;
-        br += q.re;
-        bi += q.im;
+        const cx<float> u = Codec<K>::unpack(cur.w(c));
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+          const cx<float> p = cmulc(u, a[k][c]);
+          v[2 * k] += p.re;
+          v[2 * k + 1] += p.im;
+        }
       }
-      a0 = double(cur.sc * ar);
-      a1 = double(cur.sc * ai);
-      b0 = double(cur.sc * br);
-      b1 = double(cur.sc * bi);
+#pragma unroll
+      for (int k = 0; k < 2 * S; ++k) v[k] *= cur.sc;
       cur = nx1;
       nx1 = nx2;
     }
-    a0 = wave_sum(a0);
-    a1 = wave_sum(a1);
-    b0 = wave_sum(b0);
-    b1 = wave_sum(b1);
-    if (lane == 0) {
-      po[2 * j] = a0;
-      po[2 * j + 1] = a1;
-      po[2 * (J + j)] = b0;
-      po[2 * (J + j) + 1] = b1;
-    }
+    wave_sum_multi<NP>(v, lane);
+    if (writer) my[2 * (wk * J + j) + wri] = v[0];
+  }
+  __syncthreads();
+  double *po = part + (size_t(r) * gridDim.x + blockIdx.x) * size_t(nv);
+  for (int t = threadIdx.x; t < nv; t += kBlock) {
+    double s = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) s += double(dsh[q * nv + t]);
+    po[t] = s;
   }
 }
 
-// w1 -= V c1, w2 -= V c2 in place (FP32), coefficients coef[r][2J] (c1
-// first), and per-workgroup partials of |w1|^2, |w2|^2 and w1^H w2:
-// part[(r * nblk + b) * 4 + {0, 1, 2, 3}] = |w1|^2, |w2|^2, Re, Im.
-template <HKind K>
+// w_k -= V c_k in place (FP32) for the S vectors, coefficients
+// coef[r][S J] (c_k at k J), and per-workgroup partials of their Gram
+// matrix: part[(r * nblk + b) * S^2 + gram_pair(l, m)].
+template <HKind K, int S>
 __global__ void __launch_bounds__(kBlock)
-    k_hmaxpy2(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
-              const cx<double> *__restrict__ coef, size_t coef_rs, cx<float> *__restrict__ w1,
-              cx<float> *__restrict__ w2, size_t w_rs, size_t Vh, double *__restrict__ part,
-              const int *__restrict__ flag) {
-  __shared__ double sh[4][kWaves];
-  __shared__ cx<float> sc[2 * kMaxJ];
+    k_hmaxpys(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
+              const cx<double> *__restrict__ coef, size_t coef_rs, cx<float> *__restrict__ w, size_t w_vs,
+              size_t w_rs, size_t Vh, double *__restrict__ part, const int *__restrict__ flag) {
+  constexpr int NG = S * S;
+  __shared__ double sh[NG][kWaves];
+  extern __shared__ cx<float> sc[];  // S J coefficients
   const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
   if (flag && flag[r] == 0) return;
   V += r * V_rs;
-  w1 += r * w_rs;
-  w2 += r * w_rs;
+  w += r * w_rs;
   coef += r * coef_rs;
-  for (int t = threadIdx.x; t < 2 * J; t += kBlock) sc[t] = mk(float(coef[t].re), float(coef[t].im));
+  for (int t = threadIdx.x; t < S * J; t += kBlock) sc[t] = mk(float(coef[t].re), float(coef[t].im));
   __syncthreads();
   const size_t i = size_t(b) * kBlock + threadIdx.x;
   const bool on = i < Vh;
-  double g[4] = {0, 0, 0, 0};
+  double g[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) g[q] = 0;
   if (on) {
-    cx<float> a[12], bb[12];
-    ld_pair(w1, Vh, i, a);
-    ld_pair(w2, Vh, i, bb);
+    cx<float> a[S][12];
+#pragma unroll
+    for (int k = 0; k < S; ++k) ld_pair(w + k * w_vs, Vh, i, a[k]);
     HRaw cur, nx1, nx2;
     if (J > 0) hraw_load(V, Vh, i, cur);
     if (J > 1) hraw_load(V + ldv, Vh, i, nx1);
     for (int j = 0; j < J; ++j) {
       if (j + 2 < J) hraw_load(V + size_t(j + 2) * ldv, Vh, i, nx2);
-      const cx<float> c1 = sc[j], c2 = sc[J + j];
-      const cx<float> ca = mk(cur.sc * c1.re, cur.sc * c1.im), cb = mk(cur.sc * c2.re, cur.sc * c2.im);
+      cx<float> ca[S];
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const cx<float> cf = sc[k * J + j];
+        ca[k] = mk(cur.sc * cf.re, cur.sc * cf.im);
+      }
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        const cx<float> v = Codec<K>::unpack(cur.w(c));
-        a[c] = a[c] - v * ca;
-        bb[c] = bb[c] - v * cb;
+        const cx<float> u = Codec<K>::unpack(cur.w(c));
+#pragma unroll
+        for (int k = 0; k < S; ++k) a[k][c] = a[k][c] - u * ca[k];
       }
       cur = nx1;
       nx1 = nx2;
     }
-    st_pair(w1, Vh, i, a);
-    st_pair(w2, Vh, i, bb);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      g[0] += double(a[c].re) * a[c].re + double(a[c].im) * a[c].im;
-      g[1] += double(bb[c].re) * bb[c].re + double(bb[c].im) * bb[c].im;
-      const cx<float> p = cmulc(a[c], bb[c]);
-      g[2] += double(p.re);
-      g[3] += double(p.im);
-    }
+    for (int k = 0; k < S; ++k) st_pair(w + k * w_vs, Vh, i, a[k]);
+#pragma unroll
+    for (int c = 0; c < 12; ++c)
+#pragma unroll
+      for (int l = 0; l < S; ++l) {
+        g[l] += double(a[l][c].re) * a[l][c].re + double(a[l][c].im) * a[l][c].im;
+#pragma unroll
+        for (int m = l + 1; m < S; ++m) {
+          const cx<float> p = cmulc(a[l][c], a[m][c]);
+          g[gram_pair_idx(S, l, m)] += double(p.re);
+          g[gram_pair_idx(S, l, m) + 1] += double(p.im);
+        }
+      }
   }
   if (part) {
-    block_sum<4>(g, sh);
+    block_sum<NG>(g, sh);
     if (threadIdx.x == 0)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) part[(size_t(r) * nblk + b) * 4 + k] = g[k];
+      for (int q = 0; q < NG; ++q) part[(size_t(r) * nblk + b) * NG + q] = g[q];
   }
 }
 
-// The two new basis vectors from the orthogonalised pair: slot j + 1 =
-// stored(f[r][0] w1), slot j + 2 = stored(f[r][1] w1 + f[r][2] w2), with
-// per-site scales (f: complex, 3 per right-hand side).
-template <HKind K>
+// The S new basis vectors from the orthogonalised block: slot m =
+// stored(sum_{l <= m} F[l][m] w_l), F = f[r][S][S] (upper triangular,
+// complex), with per-site scales; slot m of right-hand side r at out + r
+// out_rs + m out_vs.
+template <HKind K, int S>
 __global__ void __launch_bounds__(kBlock)
-    k_h2store(const cx<float> *__restrict__ w1, const cx<float> *__restrict__ w2, size_t w_rs,
-              const cx<double> *__restrict__ f, uint32_t *out1, uint32_t *out2, size_t out_rs, size_t Vh) {
+    k_hsstore(const cx<float> *__restrict__ w, size_t w_vs, size_t w_rs, const cx<double> *__restrict__ f,
+              uint32_t *out, size_t out_vs, size_t out_rs, size_t Vh) {
   const int r = blockIdx.y;
   const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= Vh) return;
-  w1 += r * w_rs;
-  w2 += r * w_rs;
-  out1 += r * out_rs;
-  out2 += r * out_rs;
-  const cx<double> f0 = f[3 * r], f1 = f[3 * r + 1], f2 = f[3 * r + 2];
-  const cx<float> a0 = mk(float(f0.re), float(f0.im)), a1 = mk(float(f1.re), float(f1.im)),
-                  a2 = mk(float(f2.re), float(f2.im));
-  cx<float> u[12], v[12], x[12], y[12];
-  ld_pair(w1, Vh, i, u);
-  ld_pair(w2, Vh, i, v);
+  w += r * w_rs;
+  out += r * out_rs;
+  f += size_t(r) * S * S;
+  cx<float> a[S][12];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    x[c] = u[c] * a0;
-    y[c] = u[c] * a1 + v[c] * a2;
+  for (int k = 0; k < S; ++k) ld_pair(w + k * w_vs, Vh, i, a[k]);
+#pragma unroll
+  for (int m = 0; m < S; ++m) {
+    cx<float> y[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) y[c] = mk(0.f, 0.f);
+#pragma unroll
+    for (int l = 0; l <= m; ++l) {
+      const cx<double> fd = f[l * S + m];
+      const cx<float> fl = mk(float(fd.re), float(fd.im));
+#pragma unroll
+      for (int c = 0; c < 12; ++c) y[c] = y[c] + a[l][c] * fl;
+    }
+    (void)hstore_site<K>(out + m * out_vs, Vh, i, y);
   }
-  (void)hstore_site<K>(out1, Vh, i, x);
-  (void)hstore_site<K>(out2, Vh, i, y);
 }
 
 // Per-site scales of stored vectors times f[r] (normalises a vector that
@@ -1490,52 +1539,53 @@ void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, c
   }
 }
 
-template <int KIND>
-void hmulti_dot2(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w1, const void *w2,
+template <int KIND, int S>
+void hmulti_dots(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w, size_t w_vs,
                  size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag) {
   if (J <= 0 || nrhs <= 0) return;
+  LQCD_CHECK(J <= kMaxJ, LQCD_EINVAL, "basis of %d vectors exceeds %d", J, kMaxJ);
   constexpr HKind K = static_cast<HKind>(KIND);
   const size_t Vh = n / 12;
   const int ngrid = int((Vh + kBlock - 1) / kBlock);
-  const int nblk = ngrid * kWaves;
-  double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * nblk * 2 * J * 2 * sizeof(double)));
-  Timed tm(c, LQCD_KC_DOT, flag ? 0.0 : (J * hbytes(n) + 2.0 * n * sizeof(cx<float>)) * nrhs);
-  LQCD_TLAUNCH(tm, true, true, (k_hmdot2_part<K>), dim3(ngrid, nrhs), dim3(kBlock), 0, c->stream,
-               static_cast<const uint32_t *>(V), ldv, V_rs, J, static_cast<const cx<float> *>(w1),
-               static_cast<const cx<float> *>(w2), w_rs, Vh, part, flag);
+  const int nv = 2 * S * J;
+  double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * ngrid * nv * sizeof(double)));
+  Timed tm(c, LQCD_KC_DOT, flag ? 0.0 : (J * hbytes(n) + double(S) * n * sizeof(cx<float>)) * nrhs);
+  LQCD_TLAUNCH(tm, true, true, (k_hmdots_part<K, S>), dim3(ngrid, nrhs), dim3(kBlock),
+               size_t(kWaves) * nv * sizeof(float), c->stream, static_cast<const uint32_t *>(V), ldv, V_rs, J,
+               static_cast<const cx<float> *>(w), w_vs, w_rs, Vh, part, flag);
   LQCD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_mdot_final, dim3(2 * J, nrhs), dim3(kBlock), 0, c->stream, part, nblk, 2 * J,
+  hipLaunchKernelGGL(k_mdot_final, dim3(S * J, nrhs), dim3(kBlock), 0, c->stream, part, ngrid, S * J,
                      reinterpret_cast<cx<double> *>(out), out_rs, flag);
   LQCD_HIP(hipGetLastError());
 }
 
-template <int KIND>
-int hmulti_axpy2(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
-                 size_t coef_rs, void *w1, void *w2, size_t w_rs, size_t n, int nrhs, double *part,
+template <int KIND, int S>
+int hmulti_axpys(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
+                 size_t coef_rs, void *w, size_t w_vs, size_t w_rs, size_t n, int nrhs, double *part,
                  const int *flag) {
   const size_t Vh = n / 12;
   const int nblk = int((Vh + kBlock - 1) / kBlock);  // one site per lane
   if (nrhs <= 0) return nblk;
   LQCD_CHECK(J <= kMaxJ, LQCD_EINVAL, "basis of %d vectors exceeds %d", J, kMaxJ);
   constexpr HKind K = static_cast<HKind>(KIND);
-  Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + 4.0 * n * sizeof(cx<float>)) * nrhs);
-  LQCD_TLAUNCH(tm, true, true, (k_hmaxpy2<K>), dim3(nblk, nrhs), dim3(kBlock), 0, c->stream,
-               static_cast<const uint32_t *>(V), ldv, V_rs, J, reinterpret_cast<const cx<double> *>(coef), coef_rs,
-               static_cast<cx<float> *>(w1), static_cast<cx<float> *>(w2), w_rs, Vh, part, flag);
+  Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + 2.0 * S * n * sizeof(cx<float>)) * nrhs);
+  LQCD_TLAUNCH(tm, true, true, (k_hmaxpys<K, S>), dim3(nblk, nrhs), dim3(kBlock),
+               size_t(S) * J * sizeof(cx<float>), c->stream, static_cast<const uint32_t *>(V), ldv, V_rs, J,
+               reinterpret_cast<const cx<double> *>(coef), coef_rs, static_cast<cx<float> *>(w), w_vs, w_rs, Vh,
+               part, flag);
   LQCD_HIP(hipGetLastError());
   return nblk;
 }
 
-template <int KIND>
-void h2store(lqcd_ctx *c, const void *w1, const void *w2, size_t w_rs, const cdouble *f, void *out1, void *out2,
+template <int KIND, int S>
+void hsstore(lqcd_ctx *c, const void *w, size_t w_vs, size_t w_rs, const cdouble *f, void *out, size_t out_vs,
              size_t out_rs, size_t n, int nrhs) {
   if (nrhs <= 0) return;
   constexpr HKind K = static_cast<HKind>(KIND);
   const size_t Vh = n / 12;
-  hipLaunchKernelGGL((k_h2store<K>), dim3(nblocks(Vh), nrhs), dim3(kBlock), 0, c->stream,
-                     static_cast<const cx<float> *>(w1), static_cast<const cx<float> *>(w2), w_rs,
-                     reinterpret_cast<const cx<double> *>(f), static_cast<uint32_t *>(out1),
-                     static_cast<uint32_t *>(out2), out_rs, Vh);
+  hipLaunchKernelGGL((k_hsstore<K, S>), dim3(nblocks(Vh), nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const cx<float> *>(w), w_vs, w_rs, reinterpret_cast<const cx<double> *>(f),
+                     static_cast<uint32_t *>(out), out_vs, out_rs, Vh);
   LQCD_HIP(hipGetLastError());
 }
 
@@ -1593,15 +1643,19 @@ void inv_sqrt_dev(lqcd_ctx *c, const double *nrm2, double *inv, int nb) {
   LQCD_HIP(hipGetLastError());
 }
 
+#define SINST(K, S)                                                                                  \
+  template void hmulti_dots<K, S>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
+                                  size_t, size_t, int, cdouble *, size_t, const int *);               \
+  template int hmulti_axpys<K, S>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,      \
+                                  size_t, void *, size_t, size_t, size_t, int, double *, const int *); \
+  template void hsstore<K, S>(lqcd_ctx *, const void *, size_t, size_t, const cdouble *, void *, size_t, \
+                              size_t, size_t, int);
 #define HINST(K)                                                                                  \
   template void hmulti_dot<K>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
                               size_t, int, cdouble *, size_t, const int *, bool);                  \
-  template void hmulti_dot2<K>(lqcd_ctx *, const void *, size_t, size_t, int, const void *,         \
-                               const void *, size_t, size_t, int, cdouble *, size_t, const int *); \
-  template int hmulti_axpy2<K>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,      \
-                               size_t, void *, void *, size_t, size_t, int, double *, const int *); \
-  template void h2store<K>(lqcd_ctx *, const void *, const void *, size_t, const cdouble *, void *,  \
-                           void *, size_t, size_t, int);                                            \
+  SINST(K, 2)                                                                                     \
+  SINST(K, 3)                                                                                     \
+  SINST(K, 4)                                                                                     \
   template void hmulti_axpy_q<K>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,   \
                                  size_t, const void *, size_t, void *, size_t, size_t, int,        \
                                  double *, const int *);                                           \
@@ -1615,5 +1669,6 @@ void inv_sqrt_dev(lqcd_ctx *c, const double *nrm2, double *inv, int nb) {
 HINST(0)
 HINST(1)
 #undef HINST
+#undef SINST
 
 }  // namespace lqcd

@@ -147,7 +147,7 @@ struct lqcd_ctx {
   int gemm_mfma = 1;             // V C with one shared basis on the matrix cores (0: FMA kernel)
   int cycle_reorth = 0;          // 1: second Gram-Schmidt pass on every GMRES-Proj step
   int kept_period = 16;          // MINRES-DR: steps between tests against the kept vectors
-  int arnoldi_steps = 2;         // 16-bit GMRES-Proj cycles: Arnoldi steps per basis pass (1 or 2)
+  int arnoldi_steps = 4;         // 16-bit GMRES-Proj cycles: Arnoldi steps per basis pass (1..4)
   ~lqcd_ctx();
 };
 
@@ -190,15 +190,15 @@ void apply_schur(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs
 template <int KIND>
 void apply_schur_h(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin,
                    size_t sout, size_t stmp);
-// The same with the FP32 output in the pair layout (16-byte granules of
-// two components, as the odd temporary: component c of site i at complex
-// element 2 ((c / 2) Vh + i) + c % 2); and Mhat in FP32 with input and
-// output in that layout.
+// Mhat - 1 = -kappa^2 D_eo D_oe with the FP32 output in the pair layout
+// (16-byte granules of two components, as the odd temporary: component c
+// of site i at complex element 2 ((c / 2) Vh + i) + c % 2), on a 16-bit
+// stored input (kind KIND) or on an FP32 input in that layout.
 template <int KIND>
-void apply_schur_h_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin,
-                        size_t sout, size_t stmp);
-void apply_schur_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,
-                      size_t stmp);
+void apply_dd_h_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,
+                     size_t stmp);
+void apply_dd_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,
+                   size_t stmp);
 
 // context.cpp: event timing of one launch (no-op unless the timer is on).
 // The events ride on the kernel dispatch itself (hipExtLaunchKernelGGL),

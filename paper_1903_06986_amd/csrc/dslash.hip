@@ -542,11 +542,13 @@ void apply_schur_h(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nr
 template void apply_schur_h<0>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
 template void apply_schur_h<1>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
 
-// The same with the FP32 output in the pair layout of the odd temporary
-// (16-byte granules of two components): the two-step Arnoldi's vectors.
+// Mhat - 1 = -kappa^2 D_eo D_oe on a 16-bit stored even input, FP32
+// output in the pair layout of the odd temporary (16-byte granules of two
+// components): the s-step Arnoldi's shifted power basis.  Without the unit
+// term the even half reads no self term.
 template <int KIND>
-void apply_schur_h_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin,
-                        size_t sout, size_t stmp) {
+void apply_dd_h_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,
+                     size_t stmp) {
   if (nrhs <= 0) return;
   constexpr HKind K = static_cast<HKind>(KIND);
   const double k = c->kappa;
@@ -556,23 +558,24 @@ void apply_schur_h_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, i
   launch_hop_src<float, false, false, false, SrcHalf<K>, SrcPlain<float>, OutPair>(c, 1, hin, none, tmp_odd,
                                                                                    cdouble(0, 0), 1.0, nrhs, sin,
                                                                                    0, stmp);
-  launch_hop_src<float, false, false, true, SrcPair, SrcHalf<K>, OutPair>(
-      c, 0, SrcPair{static_cast<const cx<float> *>(tmp_odd)}, hin, out, cdouble(1, 0), -k * k, nrhs, stmp, sin,
+  launch_hop_src<float, false, false, false, SrcPair, SrcPlain<float>, OutPair>(
+      c, 0, SrcPair{static_cast<const cx<float> *>(tmp_odd)}, none, out, cdouble(0, 0), -k * k, nrhs, stmp, 0,
       sout);
 }
-template void apply_schur_h_pair<0>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
-template void apply_schur_h_pair<1>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
+template void apply_dd_h_pair<0>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
+template void apply_dd_h_pair<1>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
 
-// Mhat in FP32 with input, output and odd temporary in the pair layout.
-void apply_schur_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,
-                      size_t stmp) {
+// Mhat - 1 in FP32 with input, output and odd temporary in the pair layout.
+void apply_dd_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,
+                   size_t stmp) {
   if (nrhs <= 0) return;
   const double k = c->kappa;
-  const SrcPair x{static_cast<const cx<float> *>(in)};
+  const SrcPlain<float> none{nullptr};
   launch_hop_src<float, false, false, false, SrcPair, SrcPlain<float>, OutPair>(
-      c, 1, x, SrcPlain<float>{nullptr}, tmp_odd, cdouble(0, 0), 1.0, nrhs, sin, 0, stmp);
-  launch_hop_src<float, false, false, true, SrcPair, SrcPair, OutPair>(
-      c, 0, SrcPair{static_cast<const cx<float> *>(tmp_odd)}, x, out, cdouble(1, 0), -k * k, nrhs, stmp, sin, sout);
+      c, 1, SrcPair{static_cast<const cx<float> *>(in)}, none, tmp_odd, cdouble(0, 0), 1.0, nrhs, sin, 0, stmp);
+  launch_hop_src<float, false, false, false, SrcPair, SrcPlain<float>, OutPair>(
+      c, 0, SrcPair{static_cast<const cx<float> *>(tmp_odd)}, none, out, cdouble(0, 0), -k * k, nrhs, stmp, 0,
+      sout);
 }
 
 template void hop_half<double>(lqcd_ctx *, int, const void *, const void *, void *, cdouble, double,

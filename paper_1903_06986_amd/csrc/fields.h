@@ -88,21 +88,29 @@ template <int KIND>
 void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
                    size_t coef_rs, const void *w, size_t w_rs, void *out, size_t out_rs, size_t n, int nrhs,
                    double *norm2_out, const int *flag);
-// Two-step Arnoldi on a 16-bit basis: out[r][0..2J) = V^H w1 then V^H w2
-// (rows out_rs apart); w1 -= V c1, w2 -= V c2 in place (coef[r] = c1 then
-// c2) with per-workgroup partials part[(r nblk + b) 4 + {|w1|^2, |w2|^2,
-// Re w1^H w2, Im w1^H w2}] (returns nblk; part sized by the caller: nrhs x
-// nblk x 4 doubles, nblk = ceil(n / 12 / 256)); slot 1 = stored(f0 w1),
-// slot 2 = stored(f1 w1 + f2 w2) with f[3 r + i] complex.
-template <int KIND>
-void hmulti_dot2(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w1, const void *w2,
+// s-step Arnoldi on a 16-bit basis, S = 2, 3 or 4 FP32 vectors in the
+// pair layout (vector k of right-hand side r at w + r w_rs + k w_vs,
+// complex elements): out[r][k J + j] = V_j^H w_k (rows out_rs apart);
+// w_k -= V c_k in place (coef[r][k J + j]) with per-workgroup partials of
+// the Gram matrix, part[(r nblk + b) S^2 + q] (|w_l|^2 at q = l, Re and Im
+// of w_l^H w_m, l < m, from q = S on, pairs in the order (0, 1), (0, 2),
+// .., (1, 2), ..; returns nblk; part sized by the caller: nrhs x nblk x
+// S^2 doubles, nblk = ceil(n / 12 / 256)); slot m = stored(sum_{l <= m}
+// F[l][m] w_l), F = f[r][S][S] complex, slot m of right-hand side r at out
+// + r out_rs + m out_vs words.
+// Index of the Gram entry w_l^H w_m (l <= m) in those partials.
+__host__ __device__ constexpr int gram_pair_idx(int S, int l, int m) {
+  return l == m ? l : S + 2 * (l * (2 * S - l - 1) / 2 + (m - l - 1));
+}
+template <int KIND, int S>
+void hmulti_dots(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w, size_t w_vs,
                  size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag);
-template <int KIND>
-int hmulti_axpy2(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
-                 size_t coef_rs, void *w1, void *w2, size_t w_rs, size_t n, int nrhs, double *part,
+template <int KIND, int S>
+int hmulti_axpys(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
+                 size_t coef_rs, void *w, size_t w_vs, size_t w_rs, size_t n, int nrhs, double *part,
                  const int *flag);
-template <int KIND>
-void h2store(lqcd_ctx *c, const void *w1, const void *w2, size_t w_rs, const cdouble *f, void *out1, void *out2,
+template <int KIND, int S>
+void hsstore(lqcd_ctx *c, const void *w, size_t w_vs, size_t w_rs, const cdouble *f, void *out, size_t out_vs,
              size_t out_rs, size_t n, int nrhs);
 // Per-site scales of nrhs stored vectors (x_rs words apart) times f[r]
 // (device array).

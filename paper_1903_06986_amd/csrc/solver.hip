@@ -98,110 +98,177 @@ __global__ void k_finish_col(cx<double> *__restrict__ Hd, size_t Hrs, int ldh, i
   }
 }
 
-constexpr int kSstepMaxJ = 256;  // basis vectors before a pair (J <= m + 1 <= 251)
+constexpr int kSstepMaxJ = 256;  // basis vectors before a block (J <= m + 1 <= 251)
 
-// Two-step Arnoldi (16-bit basis): after the first block pass, the Gram
-// partials of the pair are summed into G[r] = {|y1|^2, |y2|^2, Re y1^H y2,
-// Im y1^H y2} and the DGKS test runs on each of the two vectors against its
-// coefficients c1 = C[0..J), c2 = C[J..2J).
+// s-step Arnoldi (16-bit basis): after the first block pass, the Gram
+// partials of the S updated vectors are summed into G[r][S^2] (layout of
+// hmulti_axpys) and the DGKS test runs on each vector w_k against its
+// coefficients c_k = C[k J .. (k + 1) J).
+template <int S>
 __global__ void k_sstep_test(const double *__restrict__ part, int nblk, const cx<double> *__restrict__ C,
-                             size_t ldc2, int J, double *__restrict__ G, int *__restrict__ flag,
+                             size_t ldc, int J, double *__restrict__ G, int *__restrict__ flag,
                              int *__restrict__ reorth_count, double eta2) {
+  constexpr int NG = S * S;
   const int r = blockIdx.x;
-  double g[4] = {0, 0, 0, 0};
+  double g[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) g[q] = 0;
   for (int b = threadIdx.x; b < nblk; b += blockDim.x)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) g[k] += part[(size_t(r) * nblk + b) * 4 + k];
+    for (int q = 0; q < NG; ++q) g[q] += part[(size_t(r) * nblk + b) * NG + q];
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+  for (int q = 0; q < NG; ++q)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) g[k] += __shfl_xor(g[k], off, 64);
+    for (int off = 32; off > 0; off >>= 1) g[q] += __shfl_xor(g[q], off, 64);
   if (threadIdx.x != 0) return;
-  double h1 = 0, h2 = 0;
-  for (int i = 0; i < J; ++i) {
-    const cx<double> a = C[r * ldc2 + i], b = C[r * ldc2 + J + i];
-    h1 += a.re * a.re + a.im * a.im;
-    h2 += b.re * b.re + b.im * b.im;
+  int need = 0;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    double h = 0;
+    for (int i = 0; i < J; ++i) {
+      const cx<double> a = C[r * ldc + size_t(k) * J + i];
+      h += a.re * a.re + a.im * a.im;
+    }
+    if (g[k] < eta2 * (g[k] + h)) need = 1;
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) G[4 * r + k] = g[k];
-  const int need = (g[0] < eta2 * (g[0] + h1) || g[1] < eta2 * (g[1] + h2)) ? 1 : 0;
+  for (int q = 0; q < NG; ++q) G[size_t(r) * NG + q] = g[q];
   flag[r] = need;
   if (need) reorth_count[r] += 1;
 }
 
-// Columns j and j + 1 of Hbar from the pair z1 = A v_j, z2 = A z1 (one
-// 64-lane block per right-hand side).  With y1 = z1 - V c1 = r11 v_{j+1}
-// and y2 = z2 - V c2 = r12 v_{j+1} + r22 v_{j+2} (Cholesky factor of the
-// pair's Gram matrix):
-//   A v_j     = V c1 + r11 v_{j+1}                     (column j)
-//   A v_{j+1} = (z2 - sum_{i<=j} c1_i A v_i) / r11
-//             = (V c2 + r12 v_{j+1} + r22 v_{j+2} - V_{j+2} Hbar_{:, 0..j} c1) / r11.
-// c = first pass + second (flagged) pass coefficients; the Gram matrix is
-// that of the final vectors (G, or the second pass's partials).  f[r] =
-// {1 / r11, -r12 / (r11 r22), 1 / r22} turns the pair into v_{j+1},
-// v_{j+2} (zero where a factor vanishes).
+// Columns j .. j + S - 1 of Hbar from the block z_k = B^k v_j, k = 1..S,
+// B = A - sigma (one 64-lane block per right-hand side).  With the
+// projected block Y = Z - V C = Q R (R the Cholesky factor of its Gram
+// matrix, Q = [v_{j+1} .. v_{j+S}]), z_k has the coordinates
+// zeta_k = (c_k; R[0..k)[k]) in the basis [V, Q], and
+//   B v_j     = zeta_1,
+//   B v_{j+m} = (zeta_{m+1} - B V c_m - sum_{l<m-1} B v_{j+1+l} R[l][m-1]) / R[m-1][m-1]
+// (m = 1..S-1; indices of c, zeta and R from 0 in the code), where
+// B V c_m = sum_{i<j} c_m[i] (Hbar[:, i] - sigma e_i) + c_m[j] B v_j.
+// Column j + m of Hbar (for A) is B v_{j+m} + sigma e_{j+m}.  c = first
+// pass + second (flagged) pass coefficients; the Gram matrix is that of
+// the final vectors (G, or the second pass's partials).  f[r] = R^{-1}
+// (S x S, upper) turns the block into Q.  Where the Cholesky factor breaks
+// down at t < S (a pivot not positive), vectors t.. are zero: their F
+// columns vanish, column j + t has a zero subdiagonal entry, later columns
+// are zero.  Hbar's earlier columns must be Hessenberg (columns 0 .. j - 1
+// of an Arnoldi process started at column 0).
+template <int S>
 __global__ void k_sstep_finish(cx<double> *__restrict__ Hd, size_t Hrs, int ldh, int j,
-                               const cx<double> *__restrict__ C1, const cx<double> *__restrict__ C2, size_t ldc2,
+                               const cx<double> *__restrict__ C1, const cx<double> *__restrict__ C2, size_t ldc,
                                const double *__restrict__ part, int nblk, const double *__restrict__ G,
-                               const int *__restrict__ flag, cx<double> *__restrict__ f) {
-  __shared__ cx<double> sc1[kSstepMaxJ], sc2[kSstepMaxJ];
-  __shared__ double sg[4];
+                               const int *__restrict__ flag, double sigma, cx<double> *__restrict__ f) {
+  constexpr int NG = S * S;
+  constexpr int LDB = kSstepMaxJ + S + 1;
+  __shared__ cx<double> sc[S][kSstepMaxJ];
+  __shared__ cx<double> sb[S][LDB];
+  __shared__ cx<double> sR[S][S];
+  __shared__ double sg[NG];
+  __shared__ int st;
   const int r = blockIdx.x, J = j + 1;
   const bool two = flag[r] != 0;
-  for (int i = threadIdx.x; i < J; i += blockDim.x) {
-    cx<double> a = C1[r * ldc2 + i], b = C1[r * ldc2 + J + i];
-    if (two) {
-      a = a + C2[r * ldc2 + i];
-      b = b + C2[r * ldc2 + J + i];
+  for (int i = threadIdx.x; i < J; i += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      cx<double> a = C1[r * ldc + size_t(k) * J + i];
+      if (two) a = a + C2[r * ldc + size_t(k) * J + i];
+      sc[k][i] = a;
     }
-    sc1[i] = a;
-    sc2[i] = b;
-  }
-  double g[4] = {0, 0, 0, 0};
+  for (int i = threadIdx.x; i < LDB; i += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < S; ++k) sb[k][i] = mk(0.0, 0.0);
+  double g[NG];
+#pragma unroll
+  for (int q = 0; q < NG; ++q) g[q] = 0;
   if (two) {
     for (int b = threadIdx.x; b < nblk; b += blockDim.x)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) g[k] += part[(size_t(r) * nblk + b) * 4 + k];
+      for (int q = 0; q < NG; ++q) g[q] += part[(size_t(r) * nblk + b) * NG + q];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int q = 0; q < NG; ++q)
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) g[k] += __shfl_xor(g[k], off, 64);
+      for (int off = 32; off > 0; off >>= 1) g[q] += __shfl_xor(g[q], off, 64);
   } else {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) g[k] = G[4 * r + k];
+    for (int q = 0; q < NG; ++q) g[q] = G[size_t(r) * NG + q];
   }
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) sg[k] = g[k];
-  __syncthreads();
-  const double g11 = sg[0], g22 = sg[1];
-  const double r11 = sqrt(g11);
-  const bool ok1 = r11 > 0 && isfinite(r11);
-  const cx<double> r12 = ok1 ? mk(sg[2] / r11, sg[3] / r11) : mk(0.0, 0.0);
-  const double d22 = g22 - (r12.re * r12.re + r12.im * r12.im);
-  const double r22 = d22 > 0 ? sqrt(d22) : 0.0;
-  const bool ok2 = ok1 && r22 > 0 && isfinite(r22);
-  cx<double> *H0 = Hd + r * Hrs;
-  cx<double> *colj = H0 + size_t(j) * ldh, *colk = colj + ldh;
-  // column j + 1: rows 0 .. j + 2; (Hbar c1)_k over the columns 0 .. j - 1
-  // already stored and column j = (c1; r11)
-  for (int k = threadIdx.x; k <= J + 1; k += blockDim.x) {
-    if (k > J) {  // row j + 2
-      colk[k] = mk(ok1 ? r22 / r11 : 0.0, 0.0);
-      continue;
-    }
-    cx<double> hc = mk(0.0, 0.0);
-    for (int i = k > 0 ? k - 1 : 0; i < j; ++i) hc = hc + H0[size_t(i) * ldh + k] * sc1[i];
-    hc = hc + (k <= j ? sc1[k] : mk(r11, 0.0)) * sc1[j];
-    const cx<double> top = k <= j ? sc2[k] : r12;
-    colk[k] = ok1 ? (1.0 / r11) * (top - hc) : mk(0.0, 0.0);
-  }
-  for (int i = threadIdx.x; i <= J; i += blockDim.x) colj[i] = i < J ? sc1[i] : mk(r11, 0.0);
   if (threadIdx.x == 0) {
-    f[3 * r] = mk(ok1 ? 1.0 / r11 : 0.0, 0.0);
-    f[3 * r + 1] = ok2 ? (-1.0 / (r11 * r22)) * r12 : mk(0.0, 0.0);
-    f[3 * r + 2] = mk(ok2 ? 1.0 / r22 : 0.0, 0.0);
+    // Cholesky G = R^H R (G[l][m] = w_l^H w_m), stopping at the first pivot
+    // that is not positive
+    cx<double> R[S][S];
+    int t = S;
+#pragma unroll
+    for (int m = 0; m < S; ++m)
+#pragma unroll
+      for (int l = 0; l < S; ++l) R[l][m] = mk(0.0, 0.0);
+    for (int m = 0; m < S && t == S; ++m) {
+      for (int l = 0; l < m; ++l) {
+        const int q = gram_pair_idx(S, l, m);
+        cx<double> a = mk(g[q], g[q + 1]);
+        for (int p = 0; p < l; ++p) a = a - cmulc(R[p][l], R[p][m]);
+        R[l][m] = (1.0 / R[l][l].re) * a;
+      }
+      double d = g[m];
+      for (int p = 0; p < m; ++p) d -= R[p][m].re * R[p][m].re + R[p][m].im * R[p][m].im;
+      const double rm = d > 0 ? sqrt(d) : 0.0;
+      if (m == 0 && isfinite(rm)) R[0][0] = mk(rm, 0.0);  // column j keeps |y_1| even when it is zero
+      if (!(rm > 0) || !isfinite(rm)) {
+        t = m;  // R[l][t], l < t, stay: column j + t needs them
+        break;
+      }
+      R[m][m] = mk(rm, 0.0);
+    }
+    // F = R^{-1} on the leading t x t block, zero elsewhere
+    cx<double> F[S][S];
+#pragma unroll
+    for (int m = 0; m < S; ++m)
+#pragma unroll
+      for (int l = 0; l < S; ++l) F[l][m] = mk(0.0, 0.0);
+    for (int m = 0; m < t; ++m) {
+      F[m][m] = mk(1.0 / R[m][m].re, 0.0);
+      for (int l = m - 1; l >= 0; --l) {
+        cx<double> a = mk(0.0, 0.0);
+        for (int p = l + 1; p <= m; ++p) a = a + R[l][p] * F[p][m];
+        F[l][m] = (-1.0 / R[l][l].re) * a;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < S; ++m)
+#pragma unroll
+      for (int l = 0; l < S; ++l) {
+        sR[l][m] = R[l][m];
+        f[size_t(r) * NG + l * S + m] = F[l][m];
+      }
+    st = t;
+  }
+  __syncthreads();
+  const int t = st;
+  cx<double> *H0 = Hd + r * Hrs;
+  for (int m = 0; m < S; ++m) {
+    cx<double> *col = H0 + size_t(j + m) * ldh;
+    const bool valid = m <= t;
+    for (int k = threadIdx.x; k <= J + m; k += blockDim.x) {
+      cx<double> b = mk(0.0, 0.0);
+      if (m == 0) {
+        b = k < J ? sc[0][k] : sR[0][0];
+      } else if (valid) {
+        const cx<double> *cm = sc[m - 1];
+        // zeta_m
+        cx<double> z = k < J ? sc[m][k] : (k - J < t ? sR[k - J][m] : mk(0.0, 0.0));
+        // B V c_{m-1}: the earlier columns (Hessenberg: row k meets columns
+        // k - 1 and later), less sigma on their diagonal, then B v_j
+        cx<double> hc = mk(0.0, 0.0);
+        for (int i = k > 0 ? k - 1 : 0; i < j; ++i) hc = hc + H0[size_t(i) * ldh + k] * cm[i];
+        if (k < j) hc = hc - sigma * cm[k];
+        hc = hc + sb[0][k] * cm[j];
+        for (int l = 0; l + 1 < m; ++l) hc = hc + sb[l + 1][k] * sR[l][m - 1];
+        b = (1.0 / sR[m - 1][m - 1].re) * (z - hc);
+      }
+      sb[m][k] = b;
+      col[k] = (valid && k == j + m) ? b + mk(sigma, 0.0) : b;
+    }
+    __syncthreads();
   }
 }
 
@@ -268,20 +335,21 @@ struct Op {
     void *t = tmp->ensure(hl * size_t(nb) * sizeof(cx<float>));
     apply_schur_h<BK>(c, in, out, t, nb, sin, sout, hl);
   }
-  // The same with the output in the FP32 pair layout; and Mhat on FP32
-  // pair-layout fields (the two-step Arnoldi's vectors).
+  // Mhat - 1 (= -kappa^2 D_eo D_oe) with the output in the FP32 pair
+  // layout, on a 16-bit stored input and on an FP32 pair-layout input (the
+  // s-step Arnoldi's shifted power basis).
   template <int BK>
-  void apply_h_pair(const void *in, size_t sin, void *out, size_t sout, int nb) const {
+  void apply_dd_h(const void *in, size_t sin, void *out, size_t sout, int nb) const {
     if (nb <= 0) return;
     const size_t hl = half_len(c->g);
     void *t = tmp->ensure(hl * size_t(nb) * sizeof(cx<float>));
-    apply_schur_h_pair<BK>(c, in, out, t, nb, sin, sout, hl);
+    apply_dd_h_pair<BK>(c, in, out, t, nb, sin, sout, hl);
   }
-  void apply_pair(const void *in, size_t sin, void *out, size_t sout, int nb) const {
+  void apply_dd(const void *in, size_t sin, void *out, size_t sout, int nb) const {
     if (nb <= 0) return;
     const size_t hl = half_len(c->g);
     void *t = tmp->ensure(hl * size_t(nb) * sizeof(cx<float>));
-    apply_schur_pair(c, in, out, t, nb, sin, sout, hl);
+    apply_dd_pair(c, in, out, t, nb, sin, sout, hl);
   }
 };
 
@@ -404,47 +472,70 @@ void arnoldi_h(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, s
   }
 }
 
-// Two-step form of arnoldi_h: Arnoldi steps j0 .. m - 1 in pairs.  For a
-// pair, z1 = A v_j and z2 = A z1 (FP32, held in the 16-byte pair layout
-// of the operator's odd temporary) are projected on the basis
-// together, in one dot pass and one update pass over it (the single-step
-// form reads the basis twice per step), with the DGKS test on both and a
-// second block pass where it asks; then the two are orthonormalised
-// between themselves by the Cholesky factor of their Gram matrix, in FP32,
-// and stored (each stored value rounded once, after its whole
-// orthogonalisation, as in the single-step form).  The Hessenberg columns
-// follow from A v_{j+1} = (z2 - A V c1) / r11 (k_sstep_finish).  The Krylov
-// space is the same; an odd last step runs in the single-step form.
-template <int BK>
-void arnoldi_h2(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, size_t Wrs, int j0, int m,
-                int nb, Small &s, double eta2, void *wt, void *wt2) {
-  uint32_t *Wb = static_cast<uint32_t *>(W);
-  const size_t ldc2 = 2 * size_t(m + 1);
+// s-step form of arnoldi_h: Arnoldi steps j0 .. m - 1 in blocks of S
+// (2..4).  For a block, z_1 = B v_j and z_k = B z_{k-1} with B = Mhat - 1
+// (the shift centres the spectrum of Mhat, a disc about 1, on the origin,
+// which keeps the power basis well conditioned; FP32, in the 16-byte pair
+// layout) are projected on the basis together, in one dot pass and one
+// update pass over it (the single-step form reads the basis twice per
+// step), with the DGKS test on each and a second block pass where it asks;
+// then they are orthonormalised among themselves by the Cholesky factor of
+// their Gram matrix, in FP32, and stored (each stored value rounded once,
+// after its whole orthogonalisation, as in the single-step form).  The
+// Hessenberg columns follow from the block's coordinates
+// (k_sstep_finish).  The Krylov space is the same: K(Mhat, v) = K(Mhat - 1,
+// v).  A last block shorter than S runs with its own length, a single last
+// step in the single-step form.
+template <int BK, int S>
+void sstep_block(lqcd_ctx *c, const Op<float> &A, uint32_t *Wb, size_t n, size_t ldv, size_t Wrs, int j, int m,
+                 int nb, Small &s, double eta2, cx<float> *wt) {
+  constexpr double kSigma = 1.0;
+  constexpr int NG = S * S;
+  const size_t ldc = size_t(S) * (m + 1);
   const int nblk = int((n / 12 + kBlock - 1) / kBlock);
-  char *q = static_cast<char *>(c->sstep.ensure(2 * ldc2 * nb * sizeof(cdouble) + 3 * nb * sizeof(cdouble) +
-                                                4 * nb * sizeof(double) + size_t(nb) * nblk * 4 * sizeof(double)));
-  cdouble *C1 = reinterpret_cast<cdouble *>(q), *C2 = C1 + ldc2 * nb, *f = C2 + ldc2 * nb;
-  double *G = reinterpret_cast<double *>(f + 3 * nb), *part = G + 4 * nb;
+  LQCD_CHECK(j + 1 <= kSstepMaxJ, LQCD_EINVAL, "s-step Arnoldi: basis of %d vectors exceeds %d", j + 1,
+             kSstepMaxJ);
+  char *q = static_cast<char *>(c->sstep.ensure(2 * ldc * nb * sizeof(cdouble) + size_t(NG) * nb * sizeof(cdouble) +
+                                                size_t(NG) * nb * sizeof(double) +
+                                                size_t(nb) * nblk * NG * sizeof(double)));
+  cdouble *C1 = reinterpret_cast<cdouble *>(q), *C2 = C1 + ldc * nb, *f = C2 + ldc * nb;
+  double *G = reinterpret_cast<double *>(f + size_t(NG) * nb), *part = G + size_t(NG) * nb;
+  const size_t wvs = size_t(nb) * n;  // vector k of the block at wt + k wvs (right-hand sides n apart)
+  A.template apply_dd_h<BK>(Wb + size_t(j) * ldv, Wrs, wt, n, nb);
+  for (int k = 1; k < S; ++k) A.apply_dd(wt + (k - 1) * wvs, n, wt + k * wvs, n, nb);
+  hmulti_dots<BK, S>(c, Wb, ldv, Wrs, j + 1, wt, wvs, n, n, nb, C1, ldc, nullptr);
+  hmulti_axpys<BK, S>(c, Wb, ldv, Wrs, j + 1, C1, ldc, wt, wvs, n, n, nb, part, nullptr);
+  hipLaunchKernelGGL(k_sstep_test<S>, dim3(nb), dim3(64), 0, c->stream, part, nblk,
+                     reinterpret_cast<const cx<double> *>(C1), ldc, j + 1, G, s.flag, s.reorth, eta2);
+  LQCD_HIP(hipGetLastError());
+  hmulti_dots<BK, S>(c, Wb, ldv, Wrs, j + 1, wt, wvs, n, n, nb, C2, ldc, s.flag);
+  hmulti_axpys<BK, S>(c, Wb, ldv, Wrs, j + 1, C2, ldc, wt, wvs, n, n, nb, part, s.flag);
+  hipLaunchKernelGGL(k_sstep_finish<S>, dim3(nb), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.Hd),
+                     s.Hrs, m + 1, j, reinterpret_cast<const cx<double> *>(C1),
+                     reinterpret_cast<const cx<double> *>(C2), ldc, part, nblk, G, s.flag, kSigma,
+                     reinterpret_cast<cx<double> *>(f));
+  LQCD_HIP(hipGetLastError());
+  hsstore<BK, S>(c, wt, wvs, n, f, Wb + size_t(j + 1) * ldv, ldv, Wrs, n, nb);
+}
+
+template <int BK>
+void arnoldi_hs(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, size_t Wrs, int j0, int m, int nb,
+                Small &s, double eta2, void *wt, int steps) {
+  uint32_t *Wb = static_cast<uint32_t *>(W);
+  cx<float> *w = static_cast<cx<float> *>(wt);
   int j = j0;
-  for (; j + 2 <= m; j += 2) {
-    uint32_t *y1 = Wb + size_t(j + 1) * ldv, *y2 = Wb + size_t(j + 2) * ldv;
-    A.template apply_h_pair<BK>(Wb + size_t(j) * ldv, Wrs, wt, n, nb);
-    A.apply_pair(wt, n, wt2, n, nb);
-    hmulti_dot2<BK>(c, Wb, ldv, Wrs, j + 1, wt, wt2, n, n, nb, C1, ldc2, nullptr);
-    hmulti_axpy2<BK>(c, Wb, ldv, Wrs, j + 1, C1, ldc2, wt, wt2, n, n, nb, part, nullptr);
-    hipLaunchKernelGGL(k_sstep_test, dim3(nb), dim3(64), 0, c->stream, part, nblk,
-                       reinterpret_cast<const cx<double> *>(C1), ldc2, j + 1, G, s.flag, s.reorth, eta2);
-    LQCD_HIP(hipGetLastError());
-    hmulti_dot2<BK>(c, Wb, ldv, Wrs, j + 1, wt, wt2, n, n, nb, C2, ldc2, s.flag);
-    hmulti_axpy2<BK>(c, Wb, ldv, Wrs, j + 1, C2, ldc2, wt, wt2, n, n, nb, part, s.flag);
-    hipLaunchKernelGGL(k_sstep_finish, dim3(nb), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.Hd),
-                       s.Hrs, m + 1, j, reinterpret_cast<const cx<double> *>(C1),
-                       reinterpret_cast<const cx<double> *>(C2), ldc2, part, nblk, G, s.flag,
-                       reinterpret_cast<cx<double> *>(f));
-    LQCD_HIP(hipGetLastError());
-    h2store<BK>(c, wt, wt2, n, f, y1, y2, Wrs, n, nb);
+  while (j < m) {
+    const int b = std::min(steps, m - j);
+    if (b == 4)
+      sstep_block<BK, 4>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
+    else if (b == 3)
+      sstep_block<BK, 3>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
+    else if (b == 2)
+      sstep_block<BK, 2>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
+    else
+      arnoldi_h<BK>(c, A, W, n, ldv, Wrs, j, m, nb, s, eta2, wt);  // the one step left
+    j += b;
   }
-  if (j < m) arnoldi_h<BK>(c, A, W, n, ldv, Wrs, j, m, nb, s, eta2, wt);
 }
 
 // MINRES-DR basis extension (one right-hand side, FP64; hermitian A):
@@ -854,8 +945,8 @@ void proj_solve(lqcd_ctx *c, const Op<R> &A, const void *Vdef, const lqcd_defl *
       inv_sqrt_dev(c, s.nrm2, s.inv, na);
       hquantize<BK>(c, Rb, n, s.inv, W, Wrs, n, na);
       const double eta2 = c->cycle_reorth ? kReorthAlways : kReorthCycle;
-      if (c->arnoldi_steps == 2)
-        arnoldi_h2<BK>(c, A, W, n, ldh, Wrs, 0, p, na, s, eta2, wt, static_cast<cx<float> *>(wt) + size_t(nb) * n);
+      if (c->arnoldi_steps > 1)
+        arnoldi_hs<BK>(c, A, W, n, ldh, Wrs, 0, p, na, s, eta2, wt, c->arnoldi_steps);
       else
         arnoldi_h<BK>(c, A, W, n, ldh, Wrs, 0, p, na, s, eta2, wt);
     } else {
@@ -1098,7 +1189,7 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
                         : w.W32.ensure(size_t(p_cyc + 1) * n * nb * sizeof(cx<float>));
         // FP32 work vectors of the 16-bit Arnoldi steps (two per right-hand
         // side in the two-step form)
-        void *WT = h16 ? w.WT.ensure(n * nb * sizeof(cx<float>) * (c->arnoldi_steps == 2 ? 2 : 1)) : nullptr;
+        void *WT = h16 ? w.WT.ensure(n * nb * sizeof(cx<float>) * size_t(c->arnoldi_steps)) : nullptr;
         void *T = w.T.ensure(n * nb * sizeof(cx<double>));
         fill_zero(c, X, n * nb * sizeof(cx<double>));
         copy_dev(c, Rr, w.S.ptr, n * nb * sizeof(cx<double>));

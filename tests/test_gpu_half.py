@@ -113,23 +113,24 @@ def test_mixed_solve_second_pass_on_every_step(prec):
             assert rel_err(x[r], xref[r]) < 1e-9, (forced, r)
             assert st[r]["true_resid"] < 1e-11, (forced, r)
         out[forced] = st
-    ctx.tune(cycle_reorth=0, arnoldi_steps=2)
+    ctx.tune(cycle_reorth=0, arnoldi_steps=4)
     # forced: every Arnoldi step of the GMRES-Proj solves ran the second pass
     for r in range(1, 4):
         assert out[1][r]["reorth"] > out[0][r]["reorth"]
         assert out[1][r]["reorth"] >= out[1][r]["matvecs"] // 2
 
 
-@pytest.mark.parametrize("m", [20, 21])
+@pytest.mark.parametrize("m", [19, 20, 21])
 @pytest.mark.parametrize("forced", [0, 1])
 @pytest.mark.parametrize("prec", ["f16", "bf16"])
-def test_two_step_arnoldi(prec, forced, m):
-    """Two Arnoldi steps per pass over the 16-bit basis (A v_j and A^2 v_j
-    projected together, then orthonormalised between themselves) span the
-    same Krylov space: the solutions reach LU and the true residual as the
-    single-step form does, in about as many matrix-vector products; with
-    the second pass forced on every pair, and with an odd cycle length (its
-    last step single)."""
+def test_sstep_arnoldi(prec, forced, m):
+    """s Arnoldi steps per pass over the 16-bit basis (s = 2, 3, 4: the
+    shifted powers (Mhat - 1)^k v_j, k = 1..s, projected together, then
+    orthonormalised among themselves) span the same Krylov space: the
+    solutions reach LU and the true residual as the single-step form does,
+    in about as many matrix-vector products; with the second pass forced on
+    every block, and with cycle lengths p = m - 10 = 9, 10, 11, so that the
+    last block of a cycle is shorter than s (1, 2 or 3 steps)."""
     require_gpu()
     dims, kappa = (6, 4, 2, 8), 0.13
     ctx, U = context(dims, 0.3, 1001, kappa)
@@ -137,18 +138,21 @@ def test_two_step_arnoldi(prec, forced, m):
     M = W.dense_M(U, kappa, dims)
     xref = np.linalg.solve(M, eta.reshape(4, -1).T).T.reshape(eta.shape)
     st = {}
-    for steps in (1, 2):
-        ctx.tune(arnoldi_steps=steps, cycle_reorth=forced)
-        say("solve two-step", prec, forced, m, steps)
-        x, defl, s = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=m, k=10, tol=1e-11, tol_super=1e-13,
-                                       inner=prec, inner_tol=1e-3, rhs_block=3)
-        x = to_host(x)
-        for r in range(4):
-            assert rel_err(x[r], xref[r]) < 1e-9, (steps, r)
-            assert s[r]["true_resid"] < 1e-11, (steps, r)
-        st[steps] = s
-    ctx.tune(arnoldi_steps=2, cycle_reorth=0)
-    for r in range(1, 4):
-        assert st[2][r]["matvecs"] <= st[1][r]["matvecs"] + (m - 10 + 1), (r, st[1][r], st[2][r])
-        if forced:
-            assert st[2][r]["reorth"] > 0
+    try:
+        for steps in (1, 2, 3, 4):
+            ctx.tune(arnoldi_steps=steps, cycle_reorth=forced)
+            say("solve s-step", prec, forced, m, steps)
+            x, defl, s = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=m, k=10, tol=1e-11, tol_super=1e-13,
+                                           inner=prec, inner_tol=1e-3, rhs_block=3)
+            x = to_host(x)
+            for r in range(4):
+                assert rel_err(x[r], xref[r]) < 1e-9, (steps, r)
+                assert s[r]["true_resid"] < 1e-11, (steps, r)
+            st[steps] = s
+    finally:
+        ctx.tune(arnoldi_steps=4, cycle_reorth=0)
+    for steps in (2, 3, 4):
+        for r in range(1, 4):
+            assert st[steps][r]["matvecs"] <= st[1][r]["matvecs"] + (m - 10 + 1), (steps, r, st[1][r], st[steps][r])
+            if forced:
+                assert st[steps][r]["reorth"] > 0

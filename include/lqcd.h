@@ -425,8 +425,10 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * vectors, two or more columns) on the matrix cores; 0 uses the FMA
  * kernel.  LQCD_TUNE_CYCLE_REORTH: 0 (default) runs the second
  * Gram-Schmidt pass of the GMRES-Proj cycles only where the first pass
- * cancelled more than one digit; 1 runs it on every step (a check of that
- * pass; slower).  LQCD_TUNE_KEPT_PERIOD: MINRES-DR tests its basis against
+ * cancelled more than one digit (in the s-step form: where that test or
+ * the conditioning of the block asks; the other blocks store their basis
+ * vectors from the first update pass); 1 runs it on every step (a check
+ * of that pass; slower).  LQCD_TUNE_KEPT_PERIOD: MINRES-DR tests its basis against
  * the kept vectors of the last restart on every this-many-th step of a cycle
  * and on its last step (1..64, default 16).  LQCD_TUNE_ARNOLDI_STEPS: 1 to
  * 4 (default 4) Arnoldi steps per pass over the basis in the GMRES-Proj

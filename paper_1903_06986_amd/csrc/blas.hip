@@ -710,15 +710,36 @@ __device__ inline void wave_sum_multi(float (&v)[NP], int lane) {
   wave_sum_multi_step<NP, 32, NP>(v, lane);
 }
 
+// Accumulates the Gram matrix of the S vectors of one site (layout of
+// gram_pair_idx; N >= S^2 entries, of type T) into g.
+template <int S, class T, int N>
+__device__ inline void gram_site(const cx<float> (&a)[S][12], T (&g)[N]) {
+  static_assert(N >= S * S, "Gram entries");
+#pragma unroll
+  for (int c = 0; c < 12; ++c)
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+      g[l] += T(a[l][c].re) * T(a[l][c].re) + T(a[l][c].im) * T(a[l][c].im);
+#pragma unroll
+      for (int m = l + 1; m < S; ++m) {
+        const cx<float> p = cmulc(a[l][c], a[m][c]);
+        g[gram_pair_idx(S, l, m)] += T(p.re);
+        g[gram_pair_idx(S, l, m) + 1] += T(p.im);
+      }
+    }
+}
+
 // Dots of the S vectors in one pass over the basis: part[r][block][S J]
 // (complex as re, im), entry k J + j for w_k against V_j.  Each wave sums
 // its 64 sites in FP32 (as the lanes' own sums), the waves of a block are
-// added in FP64 at the end (dynamic LDS: kWaves * 2 S J floats).
+// added in FP64 at the end (dynamic LDS: kWaves * 2 S J floats).  With
+// gpart, also the per-workgroup partials of the vectors' own Gram matrix,
+// gpart[(r * nblk + b) * S^2 + q].
 template <HKind K, int S>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(S <= 2 ? 4 : 2, 8)))
     k_hmdots_part(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
                   const cx<float> *__restrict__ w, size_t w_vs, size_t w_rs, size_t Vh, double *__restrict__ part,
-                  const int *__restrict__ flag) {
+                  double *__restrict__ gpart, const int *__restrict__ flag) {
   constexpr int NP = S <= 2 ? 4 : 8;  // 2 S values, padded to a power of two
   constexpr int LB = NP == 4 ? 2 : 3;
   extern __shared__ float dsh[];
@@ -772,6 +793,26 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(S <
     wave_sum_multi<NP>(v, lane);
     if (writer) my[2 * (wk * J + j) + wri] = v[0];
   }
+  if (gpart) {
+    // the site's Gram entries in FP32, summed over the wave with one
+    // butterfly, over the block's waves in FP64
+    constexpr int NG = S * S, NQ = NG <= 4 ? 4 : 16, LQ = NQ == 4 ? 2 : 4;
+    __shared__ float gsh[kWaves][NQ];
+    float g[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) g[q] = 0.f;
+    if (on) gram_site<S>(a, g);
+    wave_sum_multi<NQ>(g, lane);
+    const int gq = lane >> (6 - LQ);
+    if ((lane & ((64 >> LQ) - 1)) == 0) gsh[wave][gq] = g[0];
+    __syncthreads();
+    if (threadIdx.x < NG) {
+      double t = 0;
+#pragma unroll
+      for (int q = 0; q < kWaves; ++q) t += double(gsh[q][threadIdx.x]);
+      gpart[(size_t(r) * gridDim.x + blockIdx.x) * NG + threadIdx.x] = t;
+    }
+  }
   __syncthreads();
   double *po = part + (size_t(r) * gridDim.x + blockIdx.x) * size_t(nv);
   for (int t = threadIdx.x; t < nv; t += kBlock) {
@@ -782,19 +823,29 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(S <
   }
 }
 
-// w_k -= V c_k in place (FP32) for the S vectors, coefficients
-// coef[r][S J] (c_k at k J), and per-workgroup partials of their Gram
-// matrix: part[(r * nblk + b) * S^2 + gram_pair(l, m)].
-template <HKind K, int S>
+// y_k = w_k - V c_k for the S vectors, coefficients coef[r][S J] (c_k at
+// k J).  In place (FP32, right-hand sides whose flag is set, or all
+// without flags), with per-workgroup partials of the Gram matrix of the
+// y_k: part[(r * nblk + b) * S^2 + gram_pair_idx(l, m)].  DIRECT (right-hand
+// sides whose flag is clear): the y_k are not written back; slot m of the
+// basis (out + r out_rs + m out_vs) receives stored(sum_{l <= m} F[l][m]
+// y_l) with F = f[r][S][S], the block orthonormalised by a Cholesky factor
+// known beforehand.
+template <HKind K, int S, bool DIRECT>
 __global__ void __launch_bounds__(kBlock)
     k_hmaxpys(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
               const cx<double> *__restrict__ coef, size_t coef_rs, cx<float> *__restrict__ w, size_t w_vs,
-              size_t w_rs, size_t Vh, double *__restrict__ part, const int *__restrict__ flag) {
+              size_t w_rs, size_t Vh, double *__restrict__ part, const int *__restrict__ flag,
+              const cx<double> *__restrict__ f, uint32_t *out, size_t out_vs, size_t out_rs) {
   constexpr int NG = S * S;
   __shared__ double sh[NG][kWaves];
   extern __shared__ cx<float> sc[];  // S J coefficients
   const int r = blockIdx.y, b = blockIdx.x, nblk = gridDim.x;
-  if (flag && flag[r] == 0) return;
+  if constexpr (DIRECT) {
+    if (flag[r] != 0) return;
+  } else {
+    if (flag && flag[r] == 0) return;
+  }
   V += r * V_rs;
   w += r * w_rs;
   coef += r * coef_rs;
@@ -829,22 +880,30 @@ __global__ void __launch_bounds__(kBlock)
       cur = nx1;
       nx1 = nx2;
     }
+    if constexpr (DIRECT) {
+      const cx<double> *fr = f + size_t(r) * NG;
+      uint32_t *o = out + r * out_rs;
 #pragma unroll
-    for (int k = 0; k < S; ++k) st_pair(w + k * w_vs, Vh, i, a[k]);
+      for (int m = 0; m < S; ++m) {
+        cx<float> y[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c)
+        for (int c = 0; c < 12; ++c) y[c] = mk(0.f, 0.f);
 #pragma unroll
-      for (int l = 0; l < S; ++l) {
-        g[l] += double(a[l][c].re) * a[l][c].re + double(a[l][c].im) * a[l][c].im;
+        for (int l = 0; l <= m; ++l) {
+          const cx<double> fd = fr[l * S + m];
+          const cx<float> fl = mk(float(fd.re), float(fd.im));
 #pragma unroll
-        for (int m = l + 1; m < S; ++m) {
-          const cx<float> p = cmulc(a[l][c], a[m][c]);
-          g[gram_pair_idx(S, l, m)] += double(p.re);
-          g[gram_pair_idx(S, l, m) + 1] += double(p.im);
+          for (int c = 0; c < 12; ++c) y[c] = y[c] + a[l][c] * fl;
         }
+        (void)hstore_site<K>(o + m * out_vs, Vh, i, y);
       }
+    } else {
+#pragma unroll
+      for (int k = 0; k < S; ++k) st_pair(w + k * w_vs, Vh, i, a[k]);
+      if (part) gram_site<S>(a, g);
+    }
   }
-  if (part) {
+  if (!DIRECT && part) {
     block_sum<NG>(g, sh);
     if (threadIdx.x == 0)
 #pragma unroll
@@ -855,12 +914,14 @@ __global__ void __launch_bounds__(kBlock)
 // The S new basis vectors from the orthogonalised block: slot m =
 // stored(sum_{l <= m} F[l][m] w_l), F = f[r][S][S] (upper triangular,
 // complex), with per-site scales; slot m of right-hand side r at out + r
-// out_rs + m out_vs.
+// out_rs + m out_vs.  With flags, only the right-hand sides whose flag is
+// set.
 template <HKind K, int S>
 __global__ void __launch_bounds__(kBlock)
     k_hsstore(const cx<float> *__restrict__ w, size_t w_vs, size_t w_rs, const cx<double> *__restrict__ f,
-              uint32_t *out, size_t out_vs, size_t out_rs, size_t Vh) {
+              uint32_t *out, size_t out_vs, size_t out_rs, size_t Vh, const int *__restrict__ flag) {
   const int r = blockIdx.y;
+  if (flag && flag[r] == 0) return;
   const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= Vh) return;
   w += r * w_rs;
@@ -1541,7 +1602,7 @@ void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, c
 
 template <int KIND, int S>
 void hmulti_dots(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w, size_t w_vs,
-                 size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag) {
+                 size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag, double *gpart) {
   if (J <= 0 || nrhs <= 0) return;
   LQCD_CHECK(J <= kMaxJ, LQCD_EINVAL, "basis of %d vectors exceeds %d", J, kMaxJ);
   constexpr HKind K = static_cast<HKind>(KIND);
@@ -1552,7 +1613,7 @@ void hmulti_dots(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, con
   Timed tm(c, LQCD_KC_DOT, flag ? 0.0 : (J * hbytes(n) + double(S) * n * sizeof(cx<float>)) * nrhs);
   LQCD_TLAUNCH(tm, true, true, (k_hmdots_part<K, S>), dim3(ngrid, nrhs), dim3(kBlock),
                size_t(kWaves) * nv * sizeof(float), c->stream, static_cast<const uint32_t *>(V), ldv, V_rs, J,
-               static_cast<const cx<float> *>(w), w_vs, w_rs, Vh, part, flag);
+               static_cast<const cx<float> *>(w), w_vs, w_rs, Vh, part, gpart, flag);
   LQCD_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_mdot_final, dim3(S * J, nrhs), dim3(kBlock), 0, c->stream, part, ngrid, S * J,
                      reinterpret_cast<cx<double> *>(out), out_rs, flag);
@@ -1569,23 +1630,43 @@ int hmulti_axpys(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, con
   LQCD_CHECK(J <= kMaxJ, LQCD_EINVAL, "basis of %d vectors exceeds %d", J, kMaxJ);
   constexpr HKind K = static_cast<HKind>(KIND);
   Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + 2.0 * S * n * sizeof(cx<float>)) * nrhs);
-  LQCD_TLAUNCH(tm, true, true, (k_hmaxpys<K, S>), dim3(nblk, nrhs), dim3(kBlock),
+  LQCD_TLAUNCH(tm, true, true, (k_hmaxpys<K, S, false>), dim3(nblk, nrhs), dim3(kBlock),
                size_t(S) * J * sizeof(cx<float>), c->stream, static_cast<const uint32_t *>(V), ldv, V_rs, J,
                reinterpret_cast<const cx<double> *>(coef), coef_rs, static_cast<cx<float> *>(w), w_vs, w_rs, Vh,
-               part, flag);
+               part, flag, static_cast<const cx<double> *>(nullptr), static_cast<uint32_t *>(nullptr), size_t(0),
+               size_t(0));
   LQCD_HIP(hipGetLastError());
   return nblk;
 }
 
 template <int KIND, int S>
+void hmulti_axpys_store(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
+                        size_t coef_rs, const void *w, size_t w_vs, size_t w_rs, size_t n, int nrhs, const int *flag,
+                        const cdouble *f, void *out, size_t out_vs, size_t out_rs, double bytes_per_rhs_credit) {
+  if (nrhs <= 0) return;
+  LQCD_CHECK(J <= kMaxJ, LQCD_EINVAL, "basis of %d vectors exceeds %d", J, kMaxJ);
+  constexpr HKind K = static_cast<HKind>(KIND);
+  const size_t Vh = n / 12;
+  const int nblk = int((Vh + kBlock - 1) / kBlock);
+  Timed tm(c, LQCD_KC_AXPY, bytes_per_rhs_credit * nrhs);
+  LQCD_TLAUNCH(tm, true, true, (k_hmaxpys<K, S, true>), dim3(nblk, nrhs), dim3(kBlock),
+               size_t(S) * J * sizeof(cx<float>), c->stream, static_cast<const uint32_t *>(V), ldv, V_rs, J,
+               reinterpret_cast<const cx<double> *>(coef), coef_rs,
+               const_cast<cx<float> *>(static_cast<const cx<float> *>(w)), w_vs, w_rs, Vh,
+               static_cast<double *>(nullptr), flag, reinterpret_cast<const cx<double> *>(f),
+               static_cast<uint32_t *>(out), out_vs, out_rs);
+  LQCD_HIP(hipGetLastError());
+}
+
+template <int KIND, int S>
 void hsstore(lqcd_ctx *c, const void *w, size_t w_vs, size_t w_rs, const cdouble *f, void *out, size_t out_vs,
-             size_t out_rs, size_t n, int nrhs) {
+             size_t out_rs, size_t n, int nrhs, const int *flag) {
   if (nrhs <= 0) return;
   constexpr HKind K = static_cast<HKind>(KIND);
   const size_t Vh = n / 12;
   hipLaunchKernelGGL((k_hsstore<K, S>), dim3(nblocks(Vh), nrhs), dim3(kBlock), 0, c->stream,
                      static_cast<const cx<float> *>(w), w_vs, w_rs, reinterpret_cast<const cx<double> *>(f),
-                     static_cast<uint32_t *>(out), out_vs, out_rs, Vh);
+                     static_cast<uint32_t *>(out), out_vs, out_rs, Vh, flag);
   LQCD_HIP(hipGetLastError());
 }
 
@@ -1645,11 +1726,14 @@ void inv_sqrt_dev(lqcd_ctx *c, const double *nrm2, double *inv, int nb) {
 
 #define SINST(K, S)                                                                                  \
   template void hmulti_dots<K, S>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
-                                  size_t, size_t, int, cdouble *, size_t, const int *);               \
+                                  size_t, size_t, int, cdouble *, size_t, const int *, double *);     \
   template int hmulti_axpys<K, S>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,      \
                                   size_t, void *, size_t, size_t, size_t, int, double *, const int *); \
+  template void hmulti_axpys_store<K, S>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *, \
+                                         size_t, const void *, size_t, size_t, size_t, int, const int *, \
+                                         const cdouble *, void *, size_t, size_t, double);             \
   template void hsstore<K, S>(lqcd_ctx *, const void *, size_t, size_t, const cdouble *, void *, size_t, \
-                              size_t, size_t, int);
+                              size_t, size_t, int, const int *);
 #define HINST(K)                                                                                  \
   template void hmulti_dot<K>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
                               size_t, int, cdouble *, size_t, const int *, bool);                  \

@@ -98,19 +98,37 @@ __global__ void k_finish_col(cx<double> *__restrict__ Hd, size_t Hrs, int ldh, i
   }
 }
 
-constexpr int kSstepMaxJ = 256;  // basis vectors before a block (J <= m + 1 <= 251)
-
-// s-step Arnoldi (16-bit basis): after the first block pass, the Gram
-// partials of the S updated vectors are summed into G[r][S^2] (layout of
-// hmulti_axpys) and the DGKS test runs on each vector w_k against its
-// coefficients c_k = C[k J .. (k + 1) J).
+// Cholesky factor G = R^H R of the S x S Gram matrix g (layout of
+// gram_pair_idx; G[l][m] = y_l^H y_m), column by column, stopping at the
+// first pivot that is not above pmin times its diagonal entry (pmin = 0:
+// not positive) or is not finite.  Returns the number t of pivots taken;
+// R holds the columns before t and R[l][t], l < t (zero elsewhere).
 template <int S>
-__global__ void k_sstep_test(const double *__restrict__ part, int nblk, const cx<double> *__restrict__ C,
-                             size_t ldc, int J, double *__restrict__ G, int *__restrict__ flag,
-                             int *__restrict__ reorth_count, double eta2) {
+__device__ inline int chol_gram(const double *g, cx<double> (&R)[S][S], double pmin) {
+#pragma unroll
+  for (int m = 0; m < S; ++m)
+#pragma unroll
+    for (int l = 0; l < S; ++l) R[l][m] = mk(0.0, 0.0);
+  for (int m = 0; m < S; ++m) {
+    for (int l = 0; l < m; ++l) {
+      const int q = gram_pair_idx(S, l, m);
+      cx<double> a = mk(g[q], g[q + 1]);
+      for (int p = 0; p < l; ++p) a = a - cmulc(R[p][l], R[p][m]);
+      R[l][m] = (1.0 / R[l][l].re) * a;
+    }
+    double d = g[m];
+    for (int p = 0; p < m; ++p) d -= R[p][m].re * R[p][m].re + R[p][m].im * R[p][m].im;
+    if (!(d > pmin * g[m]) || !(d > 0) || !isfinite(d)) return m;
+    R[m][m] = mk(sqrt(d), 0.0);
+  }
+  return S;
+}
+
+// Sums the S^2 Gram partials of one right-hand side over nblk workgroups
+// (one 64-lane block; every lane ends with the totals).
+template <int S>
+__device__ inline void gram_total(const double *__restrict__ part, int r, int nblk, double (&g)[S * S]) {
   constexpr int NG = S * S;
-  const int r = blockIdx.x;
-  double g[NG];
 #pragma unroll
   for (int q = 0; q < NG; ++q) g[q] = 0;
   for (int b = threadIdx.x; b < nblk; b += blockDim.x)
@@ -120,19 +138,81 @@ __global__ void k_sstep_test(const double *__restrict__ part, int nblk, const cx
   for (int q = 0; q < NG; ++q)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) g[q] += __shfl_xor(g[q], off, 64);
-  if (threadIdx.x != 0) return;
-  int need = 0;
+}
+
+constexpr int kSstepMaxJ = 256;  // basis vectors before a block (J <= m + 1 <= 251)
+// A block stores its basis vectors straight from the update pass only if
+// every Cholesky pivot of its Gram matrix (from the dot pass) keeps this
+// fraction of its diagonal entry: the difference Z^H Z - C^H C then loses
+// at most three digits to cancellation, well inside the 16-bit storage
+// rounding.
+constexpr double kPivotMin = 1e-3;
+
+// s-step Arnoldi (16-bit basis), after the first dot pass: the Gram matrix
+// of the projected block Y = Z - V C follows from it as Z^H Z - C^H C (V
+// orthonormal; gpart holds the partials of Z^H Z).  The block takes the
+// direct path (flag clear; G[r] receives this Gram matrix, and the update
+// pass stores the orthonormalised vectors at once) when the DGKS test
+// passes on each vector (|y_k|^2 at least eta2 |z_k|^2) and each Cholesky
+// pivot keeps kPivotMin of its diagonal entry; otherwise the explicit path
+// (flag set, counted as a second pass): update in place, second block
+// pass, Gram matrix of the final vectors.
+template <int S>
+__global__ void k_sstep_plan(const double *__restrict__ gpart, int nblk, const cx<double> *__restrict__ C, size_t ldc,
+                             int J, double *__restrict__ G, int *__restrict__ flag, int *__restrict__ reorth_count,
+                             double eta2) {
+  constexpr int NG = S * S;
+  constexpr int NPR = S * (S + 1) / 2;
+  const int r = blockIdx.x;
+  double g[NG];
+  gram_total<S>(gpart, r, nblk, g);
+  // C^H C over the J basis vectors, pairs l <= m in the order of gram_pair_idx
+  double cc[2 * NPR];
 #pragma unroll
-  for (int k = 0; k < S; ++k) {
-    double h = 0;
-    for (int i = 0; i < J; ++i) {
-      const cx<double> a = C[r * ldc + size_t(k) * J + i];
-      h += a.re * a.re + a.im * a.im;
-    }
-    if (g[k] < eta2 * (g[k] + h)) need = 1;
+  for (int q = 0; q < 2 * NPR; ++q) cc[q] = 0;
+  for (int i = threadIdx.x; i < J; i += blockDim.x) {
+    cx<double> cv[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) cv[l] = C[r * ldc + size_t(l) * J + i];
+    int q = 0;
+#pragma unroll
+    for (int l = 0; l < S; ++l)
+#pragma unroll
+      for (int m = l; m < S; ++m, ++q) {
+        const cx<double> p = cmulc(cv[l], cv[m]);
+        cc[2 * q] += p.re;
+        cc[2 * q + 1] += p.im;
+      }
   }
 #pragma unroll
-  for (int q = 0; q < NG; ++q) G[size_t(r) * NG + q] = g[q];
+  for (int q = 0; q < 2 * NPR; ++q)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cc[q] += __shfl_xor(cc[q], off, 64);
+  if (threadIdx.x != 0) return;
+  double gp[NG];
+  int need = 0;
+  {
+    int q = 0;
+#pragma unroll
+    for (int l = 0; l < S; ++l)
+#pragma unroll
+      for (int m = l; m < S; ++m, ++q) {
+        if (l == m) {
+          gp[l] = g[l] - cc[2 * q];
+          if (!(gp[l] >= eta2 * g[l])) need = 1;  // DGKS (and not finite)
+        } else {
+          const int k = gram_pair_idx(S, l, m);
+          gp[k] = g[k] - cc[2 * q];
+          gp[k + 1] = g[k + 1] - cc[2 * q + 1];
+        }
+      }
+  }
+  if (!need) {
+    cx<double> R[S][S];
+    if (chol_gram<S>(gp, R, kPivotMin) < S) need = 1;
+  }
+#pragma unroll
+  for (int q = 0; q < NG; ++q) G[size_t(r) * NG + q] = gp[q];
   flag[r] = need;
   if (need) reorth_count[r] += 1;
 }
@@ -146,15 +226,17 @@ __global__ void k_sstep_test(const double *__restrict__ part, int nblk, const cx
 //   B v_{j+m} = (zeta_{m+1} - B V c_m - sum_{l<m-1} B v_{j+1+l} R[l][m-1]) / R[m-1][m-1]
 // (m = 1..S-1; indices of c, zeta and R from 0 in the code), where
 // B V c_m = sum_{i<j} c_m[i] (Hbar[:, i] - sigma e_i) + c_m[j] B v_j.
-// Column j + m of Hbar (for A) is B v_{j+m} + sigma e_{j+m}.  c = first
-// pass + second (flagged) pass coefficients; the Gram matrix is that of
-// the final vectors (G, or the second pass's partials).  f[r] = R^{-1}
-// (S x S, upper) turns the block into Q.  Where the Cholesky factor breaks
-// down at t < S (a pivot not positive), vectors t.. are zero: their F
-// columns vanish, column j + t has a zero subdiagonal entry, later columns
-// are zero.  Hbar's earlier columns must be Hessenberg (columns 0 .. j - 1
-// of an Arnoldi process started at column 0).
-template <int S>
+// Column j + m of Hbar (for A) is B v_{j+m} + sigma e_{j+m}.  Runs for the
+// right-hand sides of one path: EXPLICIT clear, those whose flag is clear
+// (c = C1, Gram matrix G[r] from k_sstep_plan); EXPLICIT set, those whose
+// flag is set (c = C1 + C2, the second pass's coefficients added; Gram
+// matrix of the final vectors from the partials part).  f[r] = R^{-1} (S x
+// S, upper) turns the block into Q.  Where the Cholesky factor breaks down
+// at t < S (a pivot not positive), vectors t.. are zero: their F columns
+// vanish, column j + t has a zero subdiagonal entry, later columns are
+// zero.  Hbar's earlier columns must be Hessenberg (columns 0 .. j - 1 of
+// an Arnoldi process started at column 0).
+template <int S, bool EXPLICIT>
 __global__ void k_sstep_finish(cx<double> *__restrict__ Hd, size_t Hrs, int ldh, int j,
                                const cx<double> *__restrict__ C1, const cx<double> *__restrict__ C2, size_t ldc,
                                const double *__restrict__ part, int nblk, const double *__restrict__ G,
@@ -164,61 +246,31 @@ __global__ void k_sstep_finish(cx<double> *__restrict__ Hd, size_t Hrs, int ldh,
   __shared__ cx<double> sc[S][kSstepMaxJ];
   __shared__ cx<double> sb[S][LDB];
   __shared__ cx<double> sR[S][S];
-  __shared__ double sg[NG];
   __shared__ int st;
   const int r = blockIdx.x, J = j + 1;
-  const bool two = flag[r] != 0;
+  if ((flag[r] != 0) != EXPLICIT) return;
   for (int i = threadIdx.x; i < J; i += blockDim.x)
 #pragma unroll
     for (int k = 0; k < S; ++k) {
       cx<double> a = C1[r * ldc + size_t(k) * J + i];
-      if (two) a = a + C2[r * ldc + size_t(k) * J + i];
+      if (EXPLICIT) a = a + C2[r * ldc + size_t(k) * J + i];
       sc[k][i] = a;
     }
   for (int i = threadIdx.x; i < LDB; i += blockDim.x)
 #pragma unroll
     for (int k = 0; k < S; ++k) sb[k][i] = mk(0.0, 0.0);
   double g[NG];
-#pragma unroll
-  for (int q = 0; q < NG; ++q) g[q] = 0;
-  if (two) {
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-#pragma unroll
-      for (int q = 0; q < NG; ++q) g[q] += part[(size_t(r) * nblk + b) * NG + q];
-#pragma unroll
-    for (int q = 0; q < NG; ++q)
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) g[q] += __shfl_xor(g[q], off, 64);
+  if (EXPLICIT) {
+    gram_total<S>(part, r, nblk, g);
   } else {
 #pragma unroll
     for (int q = 0; q < NG; ++q) g[q] = G[size_t(r) * NG + q];
   }
   if (threadIdx.x == 0) {
-    // Cholesky G = R^H R (G[l][m] = w_l^H w_m), stopping at the first pivot
-    // that is not positive
     cx<double> R[S][S];
-    int t = S;
-#pragma unroll
-    for (int m = 0; m < S; ++m)
-#pragma unroll
-      for (int l = 0; l < S; ++l) R[l][m] = mk(0.0, 0.0);
-    for (int m = 0; m < S && t == S; ++m) {
-      for (int l = 0; l < m; ++l) {
-        const int q = gram_pair_idx(S, l, m);
-        cx<double> a = mk(g[q], g[q + 1]);
-        for (int p = 0; p < l; ++p) a = a - cmulc(R[p][l], R[p][m]);
-        R[l][m] = (1.0 / R[l][l].re) * a;
-      }
-      double d = g[m];
-      for (int p = 0; p < m; ++p) d -= R[p][m].re * R[p][m].re + R[p][m].im * R[p][m].im;
-      const double rm = d > 0 ? sqrt(d) : 0.0;
-      if (m == 0 && isfinite(rm)) R[0][0] = mk(rm, 0.0);  // column j keeps |y_1| even when it is zero
-      if (!(rm > 0) || !isfinite(rm)) {
-        t = m;  // R[l][t], l < t, stay: column j + t needs them
-        break;
-      }
-      R[m][m] = mk(rm, 0.0);
-    }
+    const int t = chol_gram<S>(g, R, 0.0);
+    // column j keeps |y_1| even when it is zero
+    if (t == 0 && g[0] >= 0 && isfinite(g[0])) R[0][0] = mk(sqrt(g[0]), 0.0);
     // F = R^{-1} on the leading t x t block, zero elsewhere
     cx<double> F[S][S];
 #pragma unroll
@@ -478,12 +530,16 @@ void arnoldi_h(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, s
 // which keeps the power basis well conditioned; FP32, in the 16-byte pair
 // layout) are projected on the basis together, in one dot pass and one
 // update pass over it (the single-step form reads the basis twice per
-// step), with the DGKS test on each and a second block pass where it asks;
-// then they are orthonormalised among themselves by the Cholesky factor of
+// step), then orthonormalised among themselves by the Cholesky factor of
 // their Gram matrix, in FP32, and stored (each stored value rounded once,
-// after its whole orthogonalisation, as in the single-step form).  The
-// Hessenberg columns follow from the block's coordinates
-// (k_sstep_finish).  The Krylov space is the same: K(Mhat, v) = K(Mhat - 1,
+// after its whole orthogonalisation, as in the single-step form).  The dot
+// pass also yields Z^H Z, so the Gram matrix of the projected block, Z^H Z
+// - C^H C, and the Hessenberg columns (k_sstep_finish) are known before the
+// update pass, which then stores the basis vectors directly (the direct
+// path).  Where the DGKS test or the conditioning of the block asks
+// (k_sstep_plan), the right-hand side takes the explicit path instead:
+// update in place, a second block pass, the Gram matrix of the final
+// vectors, store.  The Krylov space is the same: K(Mhat, v) = K(Mhat - 1,
 // v).  A last block shorter than S runs with its own length, a single last
 // step in the single-step form.
 template <int BK, int S>
@@ -493,29 +549,44 @@ void sstep_block(lqcd_ctx *c, const Op<float> &A, uint32_t *Wb, size_t n, size_t
   constexpr int NG = S * S;
   const size_t ldc = size_t(S) * (m + 1);
   const int nblk = int((n / 12 + kBlock - 1) / kBlock);
-  LQCD_CHECK(j + 1 <= kSstepMaxJ, LQCD_EINVAL, "s-step Arnoldi: basis of %d vectors exceeds %d", j + 1,
-             kSstepMaxJ);
+  const int J = j + 1;
+  LQCD_CHECK(J <= kSstepMaxJ, LQCD_EINVAL, "s-step Arnoldi: basis of %d vectors exceeds %d", J, kSstepMaxJ);
   char *q = static_cast<char *>(c->sstep.ensure(2 * ldc * nb * sizeof(cdouble) + size_t(NG) * nb * sizeof(cdouble) +
                                                 size_t(NG) * nb * sizeof(double) +
-                                                size_t(nb) * nblk * NG * sizeof(double)));
+                                                2 * size_t(nb) * nblk * NG * sizeof(double)));
   cdouble *C1 = reinterpret_cast<cdouble *>(q), *C2 = C1 + ldc * nb, *f = C2 + ldc * nb;
   double *G = reinterpret_cast<double *>(f + size_t(NG) * nb), *part = G + size_t(NG) * nb;
+  double *gpart = part + size_t(nb) * nblk * NG;
   const size_t wvs = size_t(nb) * n;  // vector k of the block at wt + k wvs (right-hand sides n apart)
+  uint32_t *out = Wb + size_t(J) * ldv;
+  const cx<double> *C1d = reinterpret_cast<const cx<double> *>(C1), *C2d = reinterpret_cast<const cx<double> *>(C2);
   A.template apply_dd_h<BK>(Wb + size_t(j) * ldv, Wrs, wt, n, nb);
   for (int k = 1; k < S; ++k) A.apply_dd(wt + (k - 1) * wvs, n, wt + k * wvs, n, nb);
-  hmulti_dots<BK, S>(c, Wb, ldv, Wrs, j + 1, wt, wvs, n, n, nb, C1, ldc, nullptr);
-  hmulti_axpys<BK, S>(c, Wb, ldv, Wrs, j + 1, C1, ldc, wt, wvs, n, n, nb, part, nullptr);
-  hipLaunchKernelGGL(k_sstep_test<S>, dim3(nb), dim3(64), 0, c->stream, part, nblk,
-                     reinterpret_cast<const cx<double> *>(C1), ldc, j + 1, G, s.flag, s.reorth, eta2);
+  hmulti_dots<BK, S>(c, Wb, ldv, Wrs, J, wt, wvs, n, n, nb, C1, ldc, nullptr, gpart);
+  hipLaunchKernelGGL(k_sstep_plan<S>, dim3(nb), dim3(64), 0, c->stream, gpart, nblk, C1d, ldc, J, G, s.flag,
+                     s.reorth, eta2);
   LQCD_HIP(hipGetLastError());
-  hmulti_dots<BK, S>(c, Wb, ldv, Wrs, j + 1, wt, wvs, n, n, nb, C2, ldc, s.flag);
-  hmulti_axpys<BK, S>(c, Wb, ldv, Wrs, j + 1, C2, ldc, wt, wvs, n, n, nb, part, s.flag);
-  hipLaunchKernelGGL(k_sstep_finish<S>, dim3(nb), dim3(64), 0, c->stream, reinterpret_cast<cx<double> *>(s.Hd),
-                     s.Hrs, m + 1, j, reinterpret_cast<const cx<double> *>(C1),
-                     reinterpret_cast<const cx<double> *>(C2), ldc, part, nblk, G, s.flag, kSigma,
-                     reinterpret_cast<cx<double> *>(f));
+  // direct path: Hessenberg columns and R^{-1} from the plan's Gram matrix,
+  // then one update pass that stores the basis vectors
+  hipLaunchKernelGGL((k_sstep_finish<S, false>), dim3(nb), dim3(64), 0, c->stream,
+                     reinterpret_cast<cx<double> *>(s.Hd), s.Hrs, m + 1, j, C1d, C2d, ldc, part, nblk, G, s.flag,
+                     kSigma, reinterpret_cast<cx<double> *>(f));
   LQCD_HIP(hipGetLastError());
-  hsstore<BK, S>(c, wt, wvs, n, f, Wb + size_t(j + 1) * ldv, ldv, Wrs, n, nb);
+  // credited as if every right-hand side took the direct path (the explicit
+  // path's conditional passes are credited with nothing)
+  const double vec16 = 52.0 * double(n / 12);  // a 16-bit stored vector: 12 words and a scale per site
+  const double credit = J * vec16 + S * (n * sizeof(cx<float>) + vec16);
+  hmulti_axpys_store<BK, S>(c, Wb, ldv, Wrs, J, C1, ldc, wt, wvs, n, n, nb, s.flag, f, out, ldv, Wrs, credit);
+  // explicit path (flagged right-hand sides): update in place, second block
+  // pass, Gram matrix of the final vectors, store
+  hmulti_axpys<BK, S>(c, Wb, ldv, Wrs, J, C1, ldc, wt, wvs, n, n, nb, nullptr, s.flag);
+  hmulti_dots<BK, S>(c, Wb, ldv, Wrs, J, wt, wvs, n, n, nb, C2, ldc, s.flag, nullptr);
+  hmulti_axpys<BK, S>(c, Wb, ldv, Wrs, J, C2, ldc, wt, wvs, n, n, nb, part, s.flag);
+  hipLaunchKernelGGL((k_sstep_finish<S, true>), dim3(nb), dim3(64), 0, c->stream,
+                     reinterpret_cast<cx<double> *>(s.Hd), s.Hrs, m + 1, j, C1d, C2d, ldc, part, nblk, G, s.flag,
+                     kSigma, reinterpret_cast<cx<double> *>(f));
+  LQCD_HIP(hipGetLastError());
+  hsstore<BK, S>(c, wt, wvs, n, f, out, ldv, Wrs, n, nb, s.flag);
 }
 
 template <int BK>

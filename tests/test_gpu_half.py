@@ -156,3 +156,40 @@ def test_sstep_arnoldi(prec, forced, m):
             assert st[steps][r]["matvecs"] <= st[1][r]["matvecs"] + (m - 10 + 1), (steps, r, st[1][r], st[steps][r])
             if forced:
                 assert st[steps][r]["reorth"] > 0
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_sstep_direct_and_explicit_paths_in_one_block(prec):
+    """The s-step block takes, per right-hand side, either the direct path
+    (Gram matrix from the dot pass, basis vectors stored by the update pass)
+    or the explicit one (update in place, second pass).  A right-hand side
+    whose even/odd source is an eigenvector of Mhat of the largest modulus
+    (the deflation space holds the smallest) makes its block nearly
+    degenerate (z_1 = (lambda - 1) v is all but removed by the projection),
+    so the DGKS test sends it down the explicit path, while the noise vectors
+    beside it in the same block take the direct one.  Every solution still
+    reaches LU and the true residual."""
+    require_gpu()
+    dims, kappa = (4, 2, 2, 4), 0.13
+    ctx, U = context(dims, 0.3, 1001, kappa)
+    M = W.dense_M(U, kappa, dims)
+    par = np.broadcast_to(W.parity_mask(dims) == 0, ctx.shape).reshape(-1)
+    E, O = np.flatnonzero(par), np.flatnonzero(~par)
+    Mhat = M[np.ix_(E, E)] - M[np.ix_(E, O)] @ M[np.ix_(O, E)]
+    lam, vec = np.linalg.eig(Mhat)
+    v = vec[:, np.argmax(np.abs(lam))]
+    eta = z4_noise(2003, dims, 0, 4).astype(np.complex128)
+    e2 = np.zeros(M.shape[0], complex)
+    e2[E] = v  # odd part zero: the even/odd source is v itself
+    eta[2] = e2.reshape(ctx.shape)
+    xref = np.linalg.solve(M, eta.reshape(4, -1).T).T.reshape(eta.shape)
+    ctx.tune(arnoldi_steps=4, cycle_reorth=0)
+    say("solve mixed paths", prec)
+    x, defl, s = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=20, k=10, tol=1e-11, tol_super=1e-13,
+                                   inner=prec, inner_tol=1e-3, rhs_block=3)
+    x = to_host(x)
+    for r in range(4):
+        assert rel_err(x[r], xref[r]) < 1e-9, r
+        assert s[r]["true_resid"] < 1e-11, r
+    assert s[2]["reorth"] > 0, s[2]
+    assert s[1]["reorth"] == 0 and s[3]["reorth"] == 0, (s[1], s[3])

@@ -29,6 +29,11 @@ struct lqcd_defl {
   // and 1/xi'_q per polynomial (coefficients -> values).
   std::vector<lqcd::cdouble> bil;
   std::vector<std::pair<std::vector<lqcd::cdouble>, std::vector<lqcd::cdouble>>> xi_cache;
+  // The Q eigenvectors and g5 times them in the lexicographic layout of the
+  // C ABI's fields (made on first use: a projection then reads the caller's
+  // fields in place); lex_Q = 0 until made.
+  int lex_Q = 0;
+  lqcd::DevBuf Elex, G5Elex;
   // Eigenvalue subtraction (non-hermitian space, op SCHUR), filled on
   // request: eigenvalues of M, right and left full-lattice eigenvectors
   // (even/odd layout, FP64, full_len apart; L^+ R = 1 per mode) and their

@@ -1162,6 +1162,7 @@ void defl_eigpairs(lqcd_ctx *c, lqcd_defl *d, int Q) {
   d->Qe = Q;
   d->bil.clear();
   d->xi_cache.clear();
+  d->lex_Q = 0;
 }
 
 }  // namespace lqcd

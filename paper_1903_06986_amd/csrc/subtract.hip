@@ -344,6 +344,12 @@ __global__ void k_g5_eo(cx<double> *__restrict__ f, size_t Vh, size_t stride, in
   *p = -*p;
 }
 
+// C[r][q] *= w[q] for nb columns of Q rows (w on the device).
+__global__ void k_scale_rows(cx<double> *__restrict__ C, const cx<double> *__restrict__ w, int Q, int nb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < Q * nb) C[i] = C[i] * w[i % Q];
+}
+
 void h2d(lqcd_ctx *c, void *dst, const void *src, size_t bytes) {
   LQCD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
   LQCD_HIP(hipStreamSynchronize(c->stream));
@@ -826,30 +832,33 @@ extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_de
           corr[2 * (a * Lt + t) + 1] += v.imag();
         }
     }
-    // xt += g5 E (w .* (E^H eta))
+    // xt += g5 E (w .* (E^H eta)), on the lexicographic copies of E and g5 E
+    // (made once per set of eigenpairs), so that eta is read and xt updated
+    // in place: one pass over the modes for the dots, one for the update
+    const size_t Vh = size_t(c->g.Vh);
+    if (d->lex_Q != Q) {
+      cx<double> *El = static_cast<cx<double> *>(d->Elex.ensure(fl * Q * sizeof(cx<double>)));
+      cx<double> *Gl = static_cast<cx<double> *>(d->G5Elex.ensure(fl * Q * sizeof(cx<double>)));
+      cx<double> *T = static_cast<cx<double> *>(c->ws[1].ensure(fl * Q * sizeof(cx<double>)));
+      unpack_eo<double>(c, E, El, Q, fl);
+      LQCD_HIP(hipMemcpyAsync(T, E, fl * Q * sizeof(cx<double>), hipMemcpyDeviceToDevice, c->stream));
+      hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(2 * 6 * Vh * Q)), dim3(kBlock), 0, c->stream, T, Vh, fl, Q);
+      LQCD_HIP(hipGetLastError());
+      unpack_eo<double>(c, T, Gl, Q, fl);
+      d->lex_Q = Q;
+    }
+    const cx<double> *El = d->Elex.as<cx<double>>(), *Gl = d->G5Elex.as<cx<double>>();
+    cdouble *wd = static_cast<cdouble *>(c->ws[6].ensure(size_t(Q) * sizeof(cdouble)));
+    h2d(c, wd, w.data(), size_t(Q) * sizeof(cdouble));
     const int blk = kSubBlock;
     for (int r0 = 0; r0 < nrhs; r0 += blk) {
       const int nb = std::min(blk, nrhs - r0);
-      cx<double> *Et = static_cast<cx<double> *>(c->ws[0].ensure(fl * nb * sizeof(cx<double>)));
-      cx<double> *Yt = static_cast<cx<double> *>(c->ws[3].ensure(fl * nb * sizeof(cx<double>)));
-      cx<double> *Xl = static_cast<cx<double> *>(c->ws[4].ensure(fl * nb * sizeof(cx<double>)));
-      pack_eo<double>(c, static_cast<const cdouble *>(eta) + r0 * fl, Et, nb, fl);
       cdouble *Cd = static_cast<cdouble *>(c->ws[5].ensure(size_t(Q) * nb * sizeof(cdouble)));
-      gemm_tn<double>(c, E, fl, Q, Et, fl, nb, fl, Cd, Q);
-      std::vector<cdouble> Ch(size_t(Q) * nb);
-      d2h(c, Ch.data(), Cd, Ch.size() * sizeof(cdouble));
-      for (int r = 0; r < nb; ++r)
-        for (int q = 0; q < Q; ++q) Ch[size_t(r) * Q + q] *= w[q];
-      h2d(c, Cd, Ch.data(), Ch.size() * sizeof(cdouble));
-      fill_zero(c, Yt, fl * nb * sizeof(cx<double>));
-      gemm_nn<double>(c, E, fl, 0, Q, Cd, Q, 0, Yt, fl, 0, nb, fl, 1, 1.0);
-      size_t tot = 2 * 6 * size_t(c->g.Vh) * nb;
-      hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(tot)), dim3(kBlock), 0, c->stream, Yt, size_t(c->g.Vh), fl, nb);
+      gemm_tn<double>(c, El, fl, Q, static_cast<const cdouble *>(eta) + r0 * fl, fl, nb, fl, Cd, Q);
+      hipLaunchKernelGGL(k_scale_rows, dim3(nblocks(size_t(Q) * nb)), dim3(kBlock), 0, c->stream,
+                         reinterpret_cast<cx<double> *>(Cd), reinterpret_cast<const cx<double> *>(wd), Q, nb);
       LQCD_HIP(hipGetLastError());
-      unpack_eo<double>(c, Yt, Xl, nb, fl);
-      cdouble one(1, 0);
-      cx<double> *xo = reinterpret_cast<cx<double> *>(static_cast<cdouble *>(xt) + r0 * fl);
-      axpby<double>(c, &one, Xl, fl, &one, xo, fl, fl, nb, false);
+      gemm_nn<double>(c, Gl, fl, 0, Q, Cd, Q, 0, static_cast<cdouble *>(xt) + r0 * fl, fl, 0, nb, fl, 1, 1.0);
     }
   });
 }

@@ -567,7 +567,7 @@ def main():
     ap.add_argument("--kappa", type=float, default=None)
     ap.add_argument("--rhs-block", type=int, default=16)
     ap.add_argument("--proj-m", type=int, default=0, help="GMRES-Proj cycle length (0: m - k)")
-    ap.add_argument("--arnoldi-steps", type=int, default=4, choices=[1, 2, 3, 4],
+    ap.add_argument("--arnoldi-steps", type=int, default=4, choices=[1, 2, 3, 4, 5, 6],
                     help="Arnoldi steps per pass over the 16-bit basis in the inner GMRES-Proj cycles")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed FP64 steps (at least 3, after 1 warm-up)")
     ap.add_argument("--tol", type=float, default=1e-10)

@@ -431,7 +431,7 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * of that pass; slower).  LQCD_TUNE_KEPT_PERIOD: MINRES-DR tests its basis against
  * the kept vectors of the last restart on every this-many-th step of a cycle
  * and on its last step (1..64, default 16).  LQCD_TUNE_ARNOLDI_STEPS: 1 to
- * 4 (default 4) Arnoldi steps per pass over the basis in the GMRES-Proj
+ * 6 (default 4) Arnoldi steps per pass over the basis in the GMRES-Proj
  * cycles with a 16-bit basis (s > 1: the s powers (Mhat - 1)^k v_j,
  * k = 1..s, are orthogonalised together, reading the basis once for all
  * of them; same Krylov space).  Values are per context; EINVAL for other

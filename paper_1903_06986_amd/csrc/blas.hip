@@ -683,6 +683,10 @@ __device__ inline void st_pair(cx<float> *w, size_t Vh, size_t i, const cx<float
   }
 }
 
+// Smallest power of two >= n (at least 4), and log2 of a power of two.
+constexpr int pow2_at_least(int n) { return n <= 4 ? 4 : 2 * pow2_at_least((n + 1) / 2); }
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
 // Sum of NP values over the 64 lanes of a wave, all NP at once: at each
 // of the first log2(NP) exchange steps a lane keeps half of its values and
 // trades the other half with its partner, so that NP sums cost NP - 1 + 6 -
@@ -740,8 +744,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(S <
     k_hmdots_part(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
                   const cx<float> *__restrict__ w, size_t w_vs, size_t w_rs, size_t Vh, double *__restrict__ part,
                   double *__restrict__ gpart, const int *__restrict__ flag) {
-  constexpr int NP = S <= 2 ? 4 : 8;  // 2 S values, padded to a power of two
-  constexpr int LB = NP == 4 ? 2 : 3;
+  constexpr int NP = pow2_at_least(2 * S);  // 2 S values, padded to a power of two
+  constexpr int LB = ilog2(NP);
   extern __shared__ float dsh[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = blockIdx.y;
@@ -796,7 +800,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(S <
   if (gpart) {
     // the site's Gram entries in FP32, summed over the wave with one
     // butterfly, over the block's waves in FP64
-    constexpr int NG = S * S, NQ = NG <= 4 ? 4 : 16, LQ = NQ == 4 ? 2 : 4;
+    constexpr int NG = S * S, NQ = pow2_at_least(NG), LQ = ilog2(NQ);
     __shared__ float gsh[kWaves][NQ];
     float g[NQ];
 #pragma unroll
@@ -853,9 +857,9 @@ __global__ void __launch_bounds__(kBlock)
   __syncthreads();
   const size_t i = size_t(b) * kBlock + threadIdx.x;
   const bool on = i < Vh;
-  double g[NG];
+  float gf[NG];  // the site's Gram entries (FP32; summed over the block in FP64)
 #pragma unroll
-  for (int q = 0; q < NG; ++q) g[q] = 0;
+  for (int q = 0; q < NG; ++q) gf[q] = 0.f;
   if (on) {
     cx<float> a[S][12];
 #pragma unroll
@@ -900,10 +904,13 @@ __global__ void __launch_bounds__(kBlock)
     } else {
 #pragma unroll
       for (int k = 0; k < S; ++k) st_pair(w + k * w_vs, Vh, i, a[k]);
-      if (part) gram_site<S>(a, g);
+      if (part) gram_site<S>(a, gf);
     }
   }
   if (!DIRECT && part) {
+    double g[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) g[q] = double(gf[q]);
     block_sum<NG>(g, sh);
     if (threadIdx.x == 0)
 #pragma unroll
@@ -1740,6 +1747,8 @@ void inv_sqrt_dev(lqcd_ctx *c, const double *nrm2, double *inv, int nb) {
   SINST(K, 2)                                                                                     \
   SINST(K, 3)                                                                                     \
   SINST(K, 4)                                                                                     \
+  SINST(K, 5)                                                                                     \
+  SINST(K, 6)                                                                                     \
   template void hmulti_axpy_q<K>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,   \
                                  size_t, const void *, size_t, void *, size_t, size_t, int,        \
                                  double *, const int *);                                           \

@@ -209,7 +209,7 @@ extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int val
         c->hop_rnest = value;
         break;
       case LQCD_TUNE_ARNOLDI_STEPS:
-        LQCD_CHECK(value >= 1 && value <= 4, LQCD_EINVAL, "lqcd_tune_set: Arnoldi steps per basis pass in 1..4");
+        LQCD_CHECK(value >= 1 && value <= 6, LQCD_EINVAL, "lqcd_tune_set: Arnoldi steps per basis pass in 1..6");
         c->arnoldi_steps = value;
         break;
       case LQCD_TUNE_KEPT_PERIOD:

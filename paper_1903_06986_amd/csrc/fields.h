@@ -88,7 +88,7 @@ template <int KIND>
 void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
                    size_t coef_rs, const void *w, size_t w_rs, void *out, size_t out_rs, size_t n, int nrhs,
                    double *norm2_out, const int *flag);
-// s-step Arnoldi on a 16-bit basis, S = 2, 3 or 4 FP32 vectors in the
+// s-step Arnoldi on a 16-bit basis, S = 2 .. 6 FP32 vectors in the
 // pair layout (vector k of right-hand side r at w + r w_rs + k w_vs,
 // complex elements): out[r][k J + j] = V_j^H w_k (rows out_rs apart), with
 // gpart (optional) the per-workgroup partials of the w_k's own Gram matrix,

@@ -525,7 +525,7 @@ void arnoldi_h(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, s
 }
 
 // s-step form of arnoldi_h: Arnoldi steps j0 .. m - 1 in blocks of S
-// (2..4).  For a block, z_1 = B v_j and z_k = B z_{k-1} with B = Mhat - 1
+// (2..6).  For a block, z_1 = B v_j and z_k = B z_{k-1} with B = Mhat - 1
 // (the shift centres the spectrum of Mhat, a disc about 1, on the origin,
 // which keeps the power basis well conditioned; FP32, in the 16-byte pair
 // layout) are projected on the basis together, in one dot pass and one
@@ -597,7 +597,11 @@ void arnoldi_hs(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, 
   int j = j0;
   while (j < m) {
     const int b = std::min(steps, m - j);
-    if (b == 4)
+    if (b == 6)
+      sstep_block<BK, 6>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
+    else if (b == 5)
+      sstep_block<BK, 5>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
+    else if (b == 4)
       sstep_block<BK, 4>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
     else if (b == 3)
       sstep_block<BK, 3>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);

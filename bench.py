@@ -569,6 +569,8 @@ def main():
     ap.add_argument("--proj-m", type=int, default=0, help="GMRES-Proj cycle length (0: m - k)")
     ap.add_argument("--arnoldi-steps", type=int, default=4, choices=[1, 2, 3, 4, 5, 6],
                     help="Arnoldi steps per pass over the 16-bit basis in the inner GMRES-Proj cycles")
+    ap.add_argument("--sstep-z16", type=int, default=0, choices=[0, 1],
+                    help="store the s-step power vectors in the basis's 16-bit form")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed FP64 steps (at least 3, after 1 warm-up)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--tol-super", type=float, default=1e-12)
@@ -650,7 +652,7 @@ def main():
     U = random_su3_links(dims, cfg["eps"], cfg["link_seed"])
     print("[bench] workload %s dims %s kappa %.8f" % (args.workload, dims, kappa), file=sys.stderr, flush=True)
     ctx = Context(dims, U, kappa)
-    ctx.tune(arnoldi_steps=args.arnoldi_steps)
+    ctx.tune(arnoldi_steps=args.arnoldi_steps, sstep_z16=args.sstep_z16)
     path = Path(ctx, cfg, args)
     path.setup()
     print("[bench] setup %s" % json.dumps(path.setup_times), file=sys.stderr, flush=True)
@@ -718,7 +720,8 @@ def main():
                                "%d Z(4) noise per step, PS%d POLY%d Q=%d"
                                % (args.workload, "x".join(map(str, dims)), cfg["eps"], kappa, cfg["m"], cfg["k"],
                                   args.rhs_block, cfg["pert_order"], cfg["poly_degree"], cfg["n_hermitian"]),
-                   "rhs_block": args.rhs_block, "inner": args.inner, "arnoldi_steps": args.arnoldi_steps},
+                   "rhs_block": args.rhs_block, "inner": args.inner, "arnoldi_steps": args.arnoldi_steps,
+                   "sstep_z16": args.sstep_z16},
         "fp64": {"value": round(value64, 4), "unit": "noise-solves/s", "steps": fp64_steps, "warmup": 1,
                  "matvecs_per_solve": mv64, "reorth_per_solve": float(np.mean([s["reorth"] for s in stats64])),
                  "max_true_resid": max(s["true_resid"] for s in stats64)},

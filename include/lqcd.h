@@ -434,8 +434,12 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * 6 (default 4) Arnoldi steps per pass over the basis in the GMRES-Proj
  * cycles with a 16-bit basis (s > 1: the s powers (Mhat - 1)^k v_j,
  * k = 1..s, are orthogonalised together, reading the basis once for all
- * of them; same Krylov space).  Values are per context; EINVAL for other
- * values. */
+ * of them; same Krylov space).  LQCD_TUNE_SSTEP_Z16: 0 (default) keeps
+ * those powers in FP32; 1 stores them in the basis's 16-bit form when the
+ * basis is FP16 (half the bytes for the stencil and the Gram-Schmidt passes
+ * that read them; the Arnoldi relation then carries their rounding; a BF16
+ * basis keeps them in FP32).  Values are per context;
+ * EINVAL for other values. */
 typedef enum {
   LQCD_TUNE_HOP_NB64 = 0,
   LQCD_TUNE_HOP_NB32 = 1,
@@ -451,7 +455,8 @@ typedef enum {
   LQCD_TUNE_HOP_RNEST = 11,
   LQCD_TUNE_CYCLE_REORTH = 12,
   LQCD_TUNE_KEPT_PERIOD = 13,
-  LQCD_TUNE_ARNOLDI_STEPS = 14
+  LQCD_TUNE_ARNOLDI_STEPS = 14,
+  LQCD_TUNE_SSTEP_Z16 = 15
 } lqcd_tune_param;
 lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 

@@ -683,6 +683,50 @@ __device__ inline void st_pair(cx<float> *w, size_t Vh, size_t i, const cx<float
   }
 }
 
+// A site of one of the s-step block's vectors: FP32 in the pair layout,
+// or (W16) 16-bit with a per-site scale (offsets in complex elements, or in
+// words).  st_w stores in place and leaves in a the values as stored.
+template <HKind K, bool W16>
+__device__ inline void ld_w(const void *w, size_t off, size_t Vh, size_t i, cx<float> (&a)[12]) {
+  if constexpr (W16) {
+    HRaw q;
+    hraw_load(static_cast<const uint32_t *>(w) + off, Vh, i, q);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const cx<float> v = Codec<K>::unpack(q.w(c));
+      a[c] = mk(q.sc * v.re, q.sc * v.im);
+    }
+  } else {
+    ld_pair(static_cast<const cx<float> *>(w) + off, Vh, i, a);
+  }
+}
+template <HKind K, bool W16>
+__device__ inline void st_w(void *w, size_t off, size_t Vh, size_t i, cx<float> (&a)[12]) {
+  if constexpr (W16) {
+    typedef unsigned u4v __attribute__((ext_vector_type(4)));
+    uint32_t *o = static_cast<uint32_t *>(w) + off;
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(a[c].re), fabsf(a[c].im)));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      u4v q;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t u = Codec<K>::pack(inv * a[4 * g + k].re, inv * a[4 * g + k].im);
+        q[k] = u;
+        const cx<float> d = Codec<K>::unpack(u);
+        a[4 * g + k] = mk(m * d.re, m * d.im);
+      }
+      *reinterpret_cast<u4v *>(o + hword(4 * g, i, Vh)) = q;
+    }
+    o[12 * Vh + i] = __float_as_uint(m);
+  } else {
+    st_pair(static_cast<cx<float> *>(w) + off, Vh, i, a);
+  }
+}
+
 // Smallest power of two >= n (at least 4), and log2 of a power of two.
 constexpr int pow2_at_least(int n) { return n <= 4 ? 4 : 2 * pow2_at_least((n + 1) / 2); }
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
@@ -739,11 +783,11 @@ __device__ inline void gram_site(const cx<float> (&a)[S][12], T (&g)[N]) {
 // added in FP64 at the end (dynamic LDS: kWaves * 2 S J floats).  With
 // gpart, also the per-workgroup partials of the vectors' own Gram matrix,
 // gpart[(r * nblk + b) * S^2 + q].
-template <HKind K, int S>
+template <HKind K, int S, bool W16>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(S <= 2 ? 4 : 2, 8)))
-    k_hmdots_part(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
-                  const cx<float> *__restrict__ w, size_t w_vs, size_t w_rs, size_t Vh, double *__restrict__ part,
-                  double *__restrict__ gpart, const int *__restrict__ flag) {
+    k_hmdots_part(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J, const void *__restrict__ w,
+                  size_t w_vs, size_t w_rs, size_t Vh, double *__restrict__ part, double *__restrict__ gpart,
+                  const int *__restrict__ flag) {
   constexpr int NP = pow2_at_least(2 * S);  // 2 S values, padded to a power of two
   constexpr int LB = ilog2(NP);
   extern __shared__ float dsh[];
@@ -752,14 +796,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(S <
   if (flag && flag[r] == 0) return;
   const int nv = 2 * S * J;
   V += r * V_rs;
-  w += r * w_rs;
+  const size_t wo = size_t(r) * w_rs;
   const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;  // the lane's site
   const bool on = i < Vh;
   cx<float> a[S][12];
 #pragma unroll
   for (int k = 0; k < S; ++k) {
     if (on) {
-      ld_pair(w + k * w_vs, Vh, i, a[k]);
+      ld_w<K, W16>(w, wo + k * w_vs, Vh, i, a[k]);
     } else {
 #pragma unroll
       for (int c = 0; c < 12; ++c) a[k][c] = mk(0.f, 0.f);
@@ -835,10 +879,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(S <
 // basis (out + r out_rs + m out_vs) receives stored(sum_{l <= m} F[l][m]
 // y_l) with F = f[r][S][S], the block orthonormalised by a Cholesky factor
 // known beforehand.
-template <HKind K, int S, bool DIRECT>
+template <HKind K, int S, bool DIRECT, bool W16>
 __global__ void __launch_bounds__(kBlock)
     k_hmaxpys(const uint32_t *__restrict__ V, size_t ldv, size_t V_rs, int J,
-              const cx<double> *__restrict__ coef, size_t coef_rs, cx<float> *__restrict__ w, size_t w_vs,
+              const cx<double> *__restrict__ coef, size_t coef_rs, void *__restrict__ w, size_t w_vs,
               size_t w_rs, size_t Vh, double *__restrict__ part, const int *__restrict__ flag,
               const cx<double> *__restrict__ f, uint32_t *out, size_t out_vs, size_t out_rs) {
   constexpr int NG = S * S;
@@ -851,7 +895,7 @@ __global__ void __launch_bounds__(kBlock)
     if (flag && flag[r] == 0) return;
   }
   V += r * V_rs;
-  w += r * w_rs;
+  const size_t wo = size_t(r) * w_rs;
   coef += r * coef_rs;
   for (int t = threadIdx.x; t < S * J; t += kBlock) sc[t] = mk(float(coef[t].re), float(coef[t].im));
   __syncthreads();
@@ -863,7 +907,7 @@ __global__ void __launch_bounds__(kBlock)
   if (on) {
     cx<float> a[S][12];
 #pragma unroll
-    for (int k = 0; k < S; ++k) ld_pair(w + k * w_vs, Vh, i, a[k]);
+    for (int k = 0; k < S; ++k) ld_w<K, W16>(w, wo + k * w_vs, Vh, i, a[k]);
     HRaw cur, nx1, nx2;
     if (J > 0) hraw_load(V, Vh, i, cur);
     if (J > 1) hraw_load(V + ldv, Vh, i, nx1);
@@ -903,7 +947,7 @@ __global__ void __launch_bounds__(kBlock)
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < S; ++k) st_pair(w + k * w_vs, Vh, i, a[k]);
+      for (int k = 0; k < S; ++k) st_w<K, W16>(w, wo + k * w_vs, Vh, i, a[k]);
       if (part) gram_site<S>(a, gf);
     }
   }
@@ -923,20 +967,20 @@ __global__ void __launch_bounds__(kBlock)
 // complex), with per-site scales; slot m of right-hand side r at out + r
 // out_rs + m out_vs.  With flags, only the right-hand sides whose flag is
 // set.
-template <HKind K, int S>
+template <HKind K, int S, bool W16>
 __global__ void __launch_bounds__(kBlock)
-    k_hsstore(const cx<float> *__restrict__ w, size_t w_vs, size_t w_rs, const cx<double> *__restrict__ f,
+    k_hsstore(const void *__restrict__ w, size_t w_vs, size_t w_rs, const cx<double> *__restrict__ f,
               uint32_t *out, size_t out_vs, size_t out_rs, size_t Vh, const int *__restrict__ flag) {
   const int r = blockIdx.y;
   if (flag && flag[r] == 0) return;
   const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= Vh) return;
-  w += r * w_rs;
+  const size_t wo = size_t(r) * w_rs;
   out += r * out_rs;
   f += size_t(r) * S * S;
   cx<float> a[S][12];
 #pragma unroll
-  for (int k = 0; k < S; ++k) ld_pair(w + k * w_vs, Vh, i, a[k]);
+  for (int k = 0; k < S; ++k) ld_w<K, W16>(w, wo + k * w_vs, Vh, i, a[k]);
 #pragma unroll
   for (int m = 0; m < S; ++m) {
     cx<float> y[12];
@@ -1607,7 +1651,10 @@ void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, c
   }
 }
 
-template <int KIND, int S>
+// bytes of one of the s-step block's vectors (FP32 pairs or 16-bit)
+inline double wbytes(size_t n, bool w16) { return w16 ? hbytes(n) : double(n) * sizeof(cx<float>); }
+
+template <int KIND, int S, bool W16>
 void hmulti_dots(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w, size_t w_vs,
                  size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag, double *gpart) {
   if (J <= 0 || nrhs <= 0) return;
@@ -1617,17 +1664,17 @@ void hmulti_dots(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, con
   const int ngrid = int((Vh + kBlock - 1) / kBlock);
   const int nv = 2 * S * J;
   double *part = static_cast<double *>(c->red.ensure(size_t(nrhs) * ngrid * nv * sizeof(double)));
-  Timed tm(c, LQCD_KC_DOT, flag ? 0.0 : (J * hbytes(n) + double(S) * n * sizeof(cx<float>)) * nrhs);
-  LQCD_TLAUNCH(tm, true, true, (k_hmdots_part<K, S>), dim3(ngrid, nrhs), dim3(kBlock),
-               size_t(kWaves) * nv * sizeof(float), c->stream, static_cast<const uint32_t *>(V), ldv, V_rs, J,
-               static_cast<const cx<float> *>(w), w_vs, w_rs, Vh, part, gpart, flag);
+  Timed tm(c, LQCD_KC_DOT, flag ? 0.0 : (J * hbytes(n) + S * wbytes(n, W16)) * nrhs);
+  LQCD_TLAUNCH(tm, true, true, (k_hmdots_part<K, S, W16>), dim3(ngrid, nrhs), dim3(kBlock),
+               size_t(kWaves) * nv * sizeof(float), c->stream, static_cast<const uint32_t *>(V), ldv, V_rs, J, w,
+               w_vs, w_rs, Vh, part, gpart, flag);
   LQCD_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_mdot_final, dim3(S * J, nrhs), dim3(kBlock), 0, c->stream, part, ngrid, S * J,
                      reinterpret_cast<cx<double> *>(out), out_rs, flag);
   LQCD_HIP(hipGetLastError());
 }
 
-template <int KIND, int S>
+template <int KIND, int S, bool W16>
 int hmulti_axpys(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
                  size_t coef_rs, void *w, size_t w_vs, size_t w_rs, size_t n, int nrhs, double *part,
                  const int *flag) {
@@ -1636,44 +1683,44 @@ int hmulti_axpys(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, con
   if (nrhs <= 0) return nblk;
   LQCD_CHECK(J <= kMaxJ, LQCD_EINVAL, "basis of %d vectors exceeds %d", J, kMaxJ);
   constexpr HKind K = static_cast<HKind>(KIND);
-  Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + 2.0 * S * n * sizeof(cx<float>)) * nrhs);
-  LQCD_TLAUNCH(tm, true, true, (k_hmaxpys<K, S, false>), dim3(nblk, nrhs), dim3(kBlock),
+  Timed tm(c, LQCD_KC_AXPY, flag ? 0.0 : (J * hbytes(n) + 2.0 * S * wbytes(n, W16)) * nrhs);
+  LQCD_TLAUNCH(tm, true, true, (k_hmaxpys<K, S, false, W16>), dim3(nblk, nrhs), dim3(kBlock),
                size_t(S) * J * sizeof(cx<float>), c->stream, static_cast<const uint32_t *>(V), ldv, V_rs, J,
-               reinterpret_cast<const cx<double> *>(coef), coef_rs, static_cast<cx<float> *>(w), w_vs, w_rs, Vh,
-               part, flag, static_cast<const cx<double> *>(nullptr), static_cast<uint32_t *>(nullptr), size_t(0),
-               size_t(0));
+               reinterpret_cast<const cx<double> *>(coef), coef_rs, w, w_vs, w_rs, Vh, part, flag,
+               static_cast<const cx<double> *>(nullptr), static_cast<uint32_t *>(nullptr), size_t(0), size_t(0));
   LQCD_HIP(hipGetLastError());
   return nblk;
 }
 
-template <int KIND, int S>
+template <int KIND, int S, bool W16>
 void hmulti_axpys_store(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
                         size_t coef_rs, const void *w, size_t w_vs, size_t w_rs, size_t n, int nrhs, const int *flag,
-                        const cdouble *f, void *out, size_t out_vs, size_t out_rs, double bytes_per_rhs_credit) {
+                        const cdouble *f, void *out, size_t out_vs, size_t out_rs) {
   if (nrhs <= 0) return;
   LQCD_CHECK(J <= kMaxJ, LQCD_EINVAL, "basis of %d vectors exceeds %d", J, kMaxJ);
   constexpr HKind K = static_cast<HKind>(KIND);
   const size_t Vh = n / 12;
   const int nblk = int((Vh + kBlock - 1) / kBlock);
-  Timed tm(c, LQCD_KC_AXPY, bytes_per_rhs_credit * nrhs);
-  LQCD_TLAUNCH(tm, true, true, (k_hmaxpys<K, S, true>), dim3(nblk, nrhs), dim3(kBlock),
+  // credited as if every right-hand side took this (direct) path; those on
+  // the explicit path are credited with nothing in its conditional passes
+  Timed tm(c, LQCD_KC_AXPY, (J * hbytes(n) + S * (wbytes(n, W16) + hbytes(n))) * nrhs);
+  LQCD_TLAUNCH(tm, true, true, (k_hmaxpys<K, S, true, W16>), dim3(nblk, nrhs), dim3(kBlock),
                size_t(S) * J * sizeof(cx<float>), c->stream, static_cast<const uint32_t *>(V), ldv, V_rs, J,
-               reinterpret_cast<const cx<double> *>(coef), coef_rs,
-               const_cast<cx<float> *>(static_cast<const cx<float> *>(w)), w_vs, w_rs, Vh,
+               reinterpret_cast<const cx<double> *>(coef), coef_rs, const_cast<void *>(w), w_vs, w_rs, Vh,
                static_cast<double *>(nullptr), flag, reinterpret_cast<const cx<double> *>(f),
                static_cast<uint32_t *>(out), out_vs, out_rs);
   LQCD_HIP(hipGetLastError());
 }
 
-template <int KIND, int S>
+template <int KIND, int S, bool W16>
 void hsstore(lqcd_ctx *c, const void *w, size_t w_vs, size_t w_rs, const cdouble *f, void *out, size_t out_vs,
              size_t out_rs, size_t n, int nrhs, const int *flag) {
   if (nrhs <= 0) return;
   constexpr HKind K = static_cast<HKind>(KIND);
   const size_t Vh = n / 12;
-  hipLaunchKernelGGL((k_hsstore<K, S>), dim3(nblocks(Vh), nrhs), dim3(kBlock), 0, c->stream,
-                     static_cast<const cx<float> *>(w), w_vs, w_rs, reinterpret_cast<const cx<double> *>(f),
-                     static_cast<uint32_t *>(out), out_vs, out_rs, Vh, flag);
+  hipLaunchKernelGGL((k_hsstore<K, S, W16>), dim3(nblocks(Vh), nrhs), dim3(kBlock), 0, c->stream, w, w_vs, w_rs,
+                     reinterpret_cast<const cx<double> *>(f), static_cast<uint32_t *>(out), out_vs, out_rs, Vh,
+                     flag);
   LQCD_HIP(hipGetLastError());
 }
 
@@ -1731,16 +1778,17 @@ void inv_sqrt_dev(lqcd_ctx *c, const double *nrm2, double *inv, int nb) {
   LQCD_HIP(hipGetLastError());
 }
 
-#define SINST(K, S)                                                                                  \
-  template void hmulti_dots<K, S>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
-                                  size_t, size_t, int, cdouble *, size_t, const int *, double *);     \
-  template int hmulti_axpys<K, S>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,      \
-                                  size_t, void *, size_t, size_t, size_t, int, double *, const int *); \
-  template void hmulti_axpys_store<K, S>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *, \
-                                         size_t, const void *, size_t, size_t, size_t, int, const int *, \
-                                         const cdouble *, void *, size_t, size_t, double);             \
-  template void hsstore<K, S>(lqcd_ctx *, const void *, size_t, size_t, const cdouble *, void *, size_t, \
-                              size_t, size_t, int, const int *);
+#define SINSTW(K, S, W)                                                                              \
+  template void hmulti_dots<K, S, W>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
+                                     size_t, size_t, int, cdouble *, size_t, const int *, double *);     \
+  template int hmulti_axpys<K, S, W>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *,      \
+                                     size_t, void *, size_t, size_t, size_t, int, double *, const int *); \
+  template void hmulti_axpys_store<K, S, W>(lqcd_ctx *, const void *, size_t, size_t, int, const cdouble *, \
+                                            size_t, const void *, size_t, size_t, size_t, int, const int *, \
+                                            const cdouble *, void *, size_t, size_t);                    \
+  template void hsstore<K, S, W>(lqcd_ctx *, const void *, size_t, size_t, const cdouble *, void *, size_t, \
+                                 size_t, size_t, int, const int *);
+#define SINST(K, S) SINSTW(K, S, false) SINSTW(K, S, true)
 #define HINST(K)                                                                                  \
   template void hmulti_dot<K>(lqcd_ctx *, const void *, size_t, size_t, int, const void *, size_t, \
                               size_t, int, cdouble *, size_t, const int *, bool);                  \
@@ -1763,5 +1811,6 @@ HINST(0)
 HINST(1)
 #undef HINST
 #undef SINST
+#undef SINSTW
 
 }  // namespace lqcd

@@ -147,7 +147,8 @@ struct lqcd_ctx {
   int gemm_mfma = 1;             // V C with one shared basis on the matrix cores (0: FMA kernel)
   int cycle_reorth = 0;          // 1: second Gram-Schmidt pass on every GMRES-Proj step
   int kept_period = 16;          // MINRES-DR: steps between tests against the kept vectors
-  int arnoldi_steps = 4;         // 16-bit GMRES-Proj cycles: Arnoldi steps per basis pass (1..4)
+  int arnoldi_steps = 4;         // 16-bit GMRES-Proj cycles: Arnoldi steps per basis pass (1..6)
+  int sstep_z16 = 0;             // s-step power vectors stored in 16-bit form (0: FP32)
   ~lqcd_ctx();
 };
 
@@ -199,6 +200,11 @@ void apply_dd_h_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int 
                      size_t stmp);
 void apply_dd_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,
                    size_t stmp);
+// Mhat - 1 from a 16-bit stored input to a 16-bit stored output (the
+// per-site scaled form of half.h, kind KIND; strides in words).
+template <int KIND>
+void apply_dd_hh(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,
+                 size_t stmp);
 
 // context.cpp: event timing of one launch (no-op unless the timer is on).
 // The events ride on the kernel dispatch itself (hipExtLaunchKernelGGL),

@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 
       }
       if (G5OUT && s >= 2) v[s * 3 + c] = -v[s * 3 + c];
     }
-  OutT::template store12<false>(ob, uint32_t(i) * OutT::kSiteBytes, Vh, v);
+  OutT::template store12<false>(ob, uint32_t(i) * OutT::kSiteBytes, 0u, Vh, v);
 }
 
 // Link-tiled form for many right-hand sides: a workgroup owns T
@@ -329,7 +329,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(hop
         }
         if (G5OUT && s >= 2) v[s * 3 + c] = -v[s * 3 + c];
       }
-    OutT::template store12<true>(o, oo, Vh, v);
+    OutT::template store12<true>(o, oo, ob, Vh, v);
   }
 }
 
@@ -406,7 +406,7 @@ void launch_hop_src(lqcd_ctx *c, int p, SI in, SS self, void *out, cdouble alpha
   // algorithmic bytes: all 8 Vh links once, input and output half fields
   // (and the self term) once per right-hand side
   const double bytes = double(g.Vh) * (72.0 * sizeof(cx<R>) +
-                                       nrhs * (SrcBytes<SI>::v + 12.0 * sizeof(cx<R>) + (C ? SrcBytes<SS>::v : 0.0)));
+                                       nrhs * (SrcBytes<SI>::v + OT::kFieldBytes + (C ? SrcBytes<SS>::v : 0.0)));
   Timed tm(c, std::is_same<R, double>::value ? LQCD_KC_HOP64 : LQCD_KC_HOP32, bytes);
   const int pi = std::is_same<R, double>::value ? 0 : 1;
   const int nbmax = c->hop_nb[pi];
@@ -564,6 +564,26 @@ void apply_dd_h_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int 
 }
 template void apply_dd_h_pair<0>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
 template void apply_dd_h_pair<1>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
+
+// Mhat - 1 from a 16-bit stored input to a 16-bit stored output (kind
+// KIND, words strides), FP32 arithmetic, odd temporary in the pair layout.
+template <int KIND>
+void apply_dd_hh(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,
+                 size_t stmp) {
+  if (nrhs <= 0) return;
+  constexpr HKind K = static_cast<HKind>(KIND);
+  const double k = c->kappa;
+  const SrcHalf<K> hin{static_cast<const uint32_t *>(in), half_len(c->g)};
+  const SrcPlain<float> none{nullptr};
+  launch_hop_src<float, false, false, false, SrcHalf<K>, SrcPlain<float>, OutPair>(c, 1, hin, none, tmp_odd,
+                                                                                   cdouble(0, 0), 1.0, nrhs, sin,
+                                                                                   0, stmp);
+  launch_hop_src<float, false, false, false, SrcPair, SrcPlain<float>, OutHalf<K>>(
+      c, 0, SrcPair{static_cast<const cx<float> *>(tmp_odd)}, none, out, cdouble(0, 0), -k * k, nrhs, stmp, 0,
+      sout);
+}
+template void apply_dd_hh<0>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
+template void apply_dd_hh<1>(lqcd_ctx *, const void *, void *, void *, int, size_t, size_t, size_t);
 
 // Mhat - 1 in FP32 with input, output and odd temporary in the pair layout.
 void apply_dd_pair(lqcd_ctx *c, const void *in, void *out, void *tmp_odd, int nrhs, size_t sin, size_t sout,

@@ -88,9 +88,9 @@ template <int KIND>
 void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
                    size_t coef_rs, const void *w, size_t w_rs, void *out, size_t out_rs, size_t n, int nrhs,
                    double *norm2_out, const int *flag);
-// s-step Arnoldi on a 16-bit basis, S = 2 .. 6 FP32 vectors in the
-// pair layout (vector k of right-hand side r at w + r w_rs + k w_vs,
-// complex elements): out[r][k J + j] = V_j^H w_k (rows out_rs apart), with
+// s-step Arnoldi on a 16-bit basis, S = 2 .. 6 vectors, FP32 in the pair
+// layout or (W16) 16-bit stored (vector k of right-hand side r at w + r
+// w_rs + k w_vs, in complex elements, or in words): out[r][k J + j] = V_j^H w_k (rows out_rs apart), with
 // gpart (optional) the per-workgroup partials of the w_k's own Gram matrix,
 // gpart[(r nblk + b) S^2 + q] (|w_l|^2 at q = l, Re and Im of w_l^H w_m,
 // l < m, from q = S on, pairs in the order (0, 1), (0, 2), .., (1, 2), ..;
@@ -99,23 +99,22 @@ void hmulti_axpy_q(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, c
 // per-workgroup partials of the Gram matrix of the results in part (same
 // layout; returns nblk); hmulti_axpys_store: the right-hand sides whose
 // flag is clear store slot m = stored(sum_{l <= m} F[l][m] (w_l - V c_l))
-// directly, F = f[r][S][S] complex (w is not written; bytes_per_rhs_credit
-// is what the kernel timer credits per right-hand side); hsstore: slot m =
+// directly, F = f[r][S][S] complex (w is not written); hsstore: slot m =
 // stored(sum_{l <= m} F[l][m] w_l), slot m of right-hand side r at out + r
 // out_rs + m out_vs words, for the right-hand sides whose flag is set (all
 // without flags).
-template <int KIND, int S>
+template <int KIND, int S, bool W16>
 void hmulti_dots(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const void *w, size_t w_vs,
                  size_t w_rs, size_t n, int nrhs, cdouble *out, size_t out_rs, const int *flag, double *gpart);
-template <int KIND, int S>
+template <int KIND, int S, bool W16>
 int hmulti_axpys(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
                  size_t coef_rs, void *w, size_t w_vs, size_t w_rs, size_t n, int nrhs, double *part,
                  const int *flag);
-template <int KIND, int S>
+template <int KIND, int S, bool W16>
 void hmulti_axpys_store(lqcd_ctx *c, const void *V, size_t ldv, size_t V_rs, int J, const cdouble *coef,
                         size_t coef_rs, const void *w, size_t w_vs, size_t w_rs, size_t n, int nrhs, const int *flag,
-                        const cdouble *f, void *out, size_t out_vs, size_t out_rs, double bytes_per_rhs_credit);
-template <int KIND, int S>
+                        const cdouble *f, void *out, size_t out_vs, size_t out_rs);
+template <int KIND, int S, bool W16>
 void hsstore(lqcd_ctx *c, const void *w, size_t w_vs, size_t w_rs, const cdouble *f, void *out, size_t out_vs,
              size_t out_rs, size_t n, int nrhs, const int *flag);
 // Index of the Gram entry w_l^H w_m (l <= m) in those partials.

@@ -403,6 +403,15 @@ struct Op {
     void *t = tmp->ensure(hl * size_t(nb) * sizeof(cx<float>));
     apply_dd_pair(c, in, out, t, nb, sin, sout, hl);
   }
+  // the same from a 16-bit stored input to a 16-bit stored output (strides
+  // in words)
+  template <int BK>
+  void apply_dd_hh(const void *in, size_t sin, void *out, size_t sout, int nb) const {
+    if (nb <= 0) return;
+    const size_t hl = half_len(c->g);
+    void *t = tmp->ensure(hl * size_t(nb) * sizeof(cx<float>));
+    ::lqcd::apply_dd_hh<BK>(c, in, out, t, nb, sin, sout, hl);
+  }
 };
 
 // Device scratch for the small per-cycle matrices.
@@ -542,9 +551,9 @@ void arnoldi_h(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, s
 // vectors, store.  The Krylov space is the same: K(Mhat, v) = K(Mhat - 1,
 // v).  A last block shorter than S runs with its own length, a single last
 // step in the single-step form.
-template <int BK, int S>
+template <int BK, int S, bool W16>
 void sstep_block(lqcd_ctx *c, const Op<float> &A, uint32_t *Wb, size_t n, size_t ldv, size_t Wrs, int j, int m,
-                 int nb, Small &s, double eta2, cx<float> *wt) {
+                 int nb, Small &s, double eta2, void *wt) {
   constexpr double kSigma = 1.0;
   constexpr int NG = S * S;
   const size_t ldc = size_t(S) * (m + 1);
@@ -557,12 +566,23 @@ void sstep_block(lqcd_ctx *c, const Op<float> &A, uint32_t *Wb, size_t n, size_t
   cdouble *C1 = reinterpret_cast<cdouble *>(q), *C2 = C1 + ldc * nb, *f = C2 + ldc * nb;
   double *G = reinterpret_cast<double *>(f + size_t(NG) * nb), *part = G + size_t(NG) * nb;
   double *gpart = part + size_t(nb) * nblk * NG;
-  const size_t wvs = size_t(nb) * n;  // vector k of the block at wt + k wvs (right-hand sides n apart)
+  // vector k of the block, right-hand side r at wt + k wvs + r wrs (complex
+  // elements, FP32 pairs; or words, 16-bit stored)
+  const size_t wrs = W16 ? ldv : n, wvs = size_t(nb) * wrs;
+  auto wk = [&](int k) -> void * {
+    return W16 ? static_cast<void *>(static_cast<uint32_t *>(wt) + k * wvs)
+               : static_cast<void *>(static_cast<cx<float> *>(wt) + k * wvs);
+  };
   uint32_t *out = Wb + size_t(J) * ldv;
   const cx<double> *C1d = reinterpret_cast<const cx<double> *>(C1), *C2d = reinterpret_cast<const cx<double> *>(C2);
-  A.template apply_dd_h<BK>(Wb + size_t(j) * ldv, Wrs, wt, n, nb);
-  for (int k = 1; k < S; ++k) A.apply_dd(wt + (k - 1) * wvs, n, wt + k * wvs, n, nb);
-  hmulti_dots<BK, S>(c, Wb, ldv, Wrs, J, wt, wvs, n, n, nb, C1, ldc, nullptr, gpart);
+  if constexpr (W16) {
+    A.template apply_dd_hh<BK>(Wb + size_t(j) * ldv, Wrs, wk(0), wrs, nb);
+    for (int k = 1; k < S; ++k) A.template apply_dd_hh<BK>(wk(k - 1), wrs, wk(k), wrs, nb);
+  } else {
+    A.template apply_dd_h<BK>(Wb + size_t(j) * ldv, Wrs, wk(0), wrs, nb);
+    for (int k = 1; k < S; ++k) A.apply_dd(wk(k - 1), wrs, wk(k), wrs, nb);
+  }
+  hmulti_dots<BK, S, W16>(c, Wb, ldv, Wrs, J, wt, wvs, wrs, n, nb, C1, ldc, nullptr, gpart);
   hipLaunchKernelGGL(k_sstep_plan<S>, dim3(nb), dim3(64), 0, c->stream, gpart, nblk, C1d, ldc, J, G, s.flag,
                      s.reorth, eta2);
   LQCD_HIP(hipGetLastError());
@@ -572,45 +592,58 @@ void sstep_block(lqcd_ctx *c, const Op<float> &A, uint32_t *Wb, size_t n, size_t
                      reinterpret_cast<cx<double> *>(s.Hd), s.Hrs, m + 1, j, C1d, C2d, ldc, part, nblk, G, s.flag,
                      kSigma, reinterpret_cast<cx<double> *>(f));
   LQCD_HIP(hipGetLastError());
-  // credited as if every right-hand side took the direct path (the explicit
-  // path's conditional passes are credited with nothing)
-  const double vec16 = 52.0 * double(n / 12);  // a 16-bit stored vector: 12 words and a scale per site
-  const double credit = J * vec16 + S * (n * sizeof(cx<float>) + vec16);
-  hmulti_axpys_store<BK, S>(c, Wb, ldv, Wrs, J, C1, ldc, wt, wvs, n, n, nb, s.flag, f, out, ldv, Wrs, credit);
+  hmulti_axpys_store<BK, S, W16>(c, Wb, ldv, Wrs, J, C1, ldc, wt, wvs, wrs, n, nb, s.flag, f, out, ldv, Wrs);
   // explicit path (flagged right-hand sides): update in place, second block
   // pass, Gram matrix of the final vectors, store
-  hmulti_axpys<BK, S>(c, Wb, ldv, Wrs, J, C1, ldc, wt, wvs, n, n, nb, nullptr, s.flag);
-  hmulti_dots<BK, S>(c, Wb, ldv, Wrs, J, wt, wvs, n, n, nb, C2, ldc, s.flag, nullptr);
-  hmulti_axpys<BK, S>(c, Wb, ldv, Wrs, J, C2, ldc, wt, wvs, n, n, nb, part, s.flag);
+  hmulti_axpys<BK, S, W16>(c, Wb, ldv, Wrs, J, C1, ldc, wt, wvs, wrs, n, nb, nullptr, s.flag);
+  hmulti_dots<BK, S, W16>(c, Wb, ldv, Wrs, J, wt, wvs, wrs, n, nb, C2, ldc, s.flag, nullptr);
+  hmulti_axpys<BK, S, W16>(c, Wb, ldv, Wrs, J, C2, ldc, wt, wvs, wrs, n, nb, part, s.flag);
   hipLaunchKernelGGL((k_sstep_finish<S, true>), dim3(nb), dim3(64), 0, c->stream,
                      reinterpret_cast<cx<double> *>(s.Hd), s.Hrs, m + 1, j, C1d, C2d, ldc, part, nblk, G, s.flag,
                      kSigma, reinterpret_cast<cx<double> *>(f));
   LQCD_HIP(hipGetLastError());
-  hsstore<BK, S>(c, wt, wvs, n, f, out, ldv, Wrs, n, nb, s.flag);
+  hsstore<BK, S, W16>(c, wt, wvs, wrs, f, out, ldv, Wrs, n, nb, s.flag);
 }
 
-template <int BK>
-void arnoldi_hs(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, size_t Wrs, int j0, int m, int nb,
-                Small &s, double eta2, void *wt, int steps) {
+template <int BK, bool W16>
+void arnoldi_hs_impl(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, size_t Wrs, int j0, int m,
+                     int nb, Small &s, double eta2, void *wt, int steps) {
   uint32_t *Wb = static_cast<uint32_t *>(W);
-  cx<float> *w = static_cast<cx<float> *>(wt);
+  void *w = wt;
   int j = j0;
   while (j < m) {
     const int b = std::min(steps, m - j);
     if (b == 6)
-      sstep_block<BK, 6>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
+      sstep_block<BK, 6, W16>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
     else if (b == 5)
-      sstep_block<BK, 5>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
+      sstep_block<BK, 5, W16>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
     else if (b == 4)
-      sstep_block<BK, 4>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
+      sstep_block<BK, 4, W16>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
     else if (b == 3)
-      sstep_block<BK, 3>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
+      sstep_block<BK, 3, W16>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
     else if (b == 2)
-      sstep_block<BK, 2>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
+      sstep_block<BK, 2, W16>(c, A, Wb, n, ldv, Wrs, j, m, nb, s, eta2, w);
     else
       arnoldi_h<BK>(c, A, W, n, ldv, Wrs, j, m, nb, s, eta2, wt);  // the one step left
     j += b;
   }
+}
+
+// The power vectors in FP32 (pair layout) or, with c->sstep_z16 and an
+// FP16 basis, stored in its 16-bit form (the stencil then reads and writes
+// them at 52 bytes per site; the Arnoldi relation carries their rounding,
+// 2^-11 relative: BF16's 2^-8 costs cycles, so a BF16 basis keeps them in
+// FP32).
+template <int BK>
+void arnoldi_hs(lqcd_ctx *c, const Op<float> &A, void *W, size_t n, size_t ldv, size_t Wrs, int j0, int m, int nb,
+                Small &s, double eta2, void *wt, int steps) {
+  if constexpr (BK == int(HKind::F16)) {
+    if (c->sstep_z16) {
+      arnoldi_hs_impl<BK, true>(c, A, W, n, ldv, Wrs, j0, m, nb, s, eta2, wt, steps);
+      return;
+    }
+  }
+  arnoldi_hs_impl<BK, false>(c, A, W, n, ldv, Wrs, j0, m, nb, s, eta2, wt, steps);
 }
 
 // MINRES-DR basis extension (one right-hand side, FP64; hermitian A):

@@ -105,13 +105,17 @@ struct SrcHalf {
   }
 };
 
-// Output layouts of the stencil (plain component-major or FP32 pairs):
-// store12 writes a site's 12 components, streamed past the caches when NT.
+// Output layouts of the stencil (plain component-major, FP32 pairs, or
+// 16-bit with a per-site scale): store12 writes a site's 12 components,
+// streamed past the caches when NT.  o + oo is the site's first element;
+// ob (bytes) locates the right-hand side's field within o (o + ob its start;
+// oo - ob = i kSiteBytes for site i).
 template <class R>
 struct OutPlain {
   static constexpr uint32_t kElemBytes = sizeof(cx<R>), kSiteBytes = sizeof(cx<R>);
+  static constexpr double kFieldBytes = 12.0 * sizeof(cx<R>);  // per site
   template <bool NT>
-  __device__ static void store12(char *o, uint32_t oo, size_t Vh, const cx<R> (&v)[12]) {
+  __device__ static void store12(char *o, uint32_t oo, uint32_t, size_t Vh, const cx<R> (&v)[12]) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       cx<R> *q = reinterpret_cast<cx<R> *>(o + k * Vh * sizeof(cx<R>) + oo);
@@ -122,8 +126,9 @@ struct OutPlain {
 };
 struct OutPair {
   static constexpr uint32_t kElemBytes = 8, kSiteBytes = 16;
+  static constexpr double kFieldBytes = 96.0;
   template <bool NT>
-  __device__ static void store12(char *o, uint32_t oo, size_t Vh, const cx<float> (&v)[12]) {
+  __device__ static void store12(char *o, uint32_t oo, uint32_t, size_t Vh, const cx<float> (&v)[12]) {
     typedef float f4v __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
@@ -139,6 +144,34 @@ struct OutPair {
   }
 };
 
+// The stored 16-bit form of SrcHalf (kind K): component c of site i in word
+// hword(c, i, Vh) as the pair v / m rounded (m = the site's largest |re|,
+// |im|; 0 for a zero site), the scale m in word 12 Vh + i (strides in words).
+template <HKind K>
+struct OutHalf {
+  static constexpr uint32_t kElemBytes = 4, kSiteBytes = 16;
+  static constexpr double kFieldBytes = 52.0;
+  template <bool NT>
+  __device__ static void store12(char *o, uint32_t oo, uint32_t ob, size_t Vh, const cx<float> (&v)[12]) {
+    typedef unsigned u4v __attribute__((ext_vector_type(4)));
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      u4v q;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[k] = Codec<K>::pack(inv * v[4 * g + k].re, inv * v[4 * g + k].im);
+      u4v *d = reinterpret_cast<u4v *>(o + g * Vh * 16 + oo);
+      if (NT) __builtin_nontemporal_store(q, d);
+      else *d = q;
+    }
+    float *ds = reinterpret_cast<float *>(o + ob + 48 * Vh + ((oo - ob) >> 2));
+    if (NT) __builtin_nontemporal_store(m, ds);
+    else *ds = m;
+  }
+};
 
 template <class R>
 struct Half {

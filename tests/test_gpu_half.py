@@ -120,17 +120,19 @@ def test_mixed_solve_second_pass_on_every_step(prec):
         assert out[1][r]["reorth"] >= out[1][r]["matvecs"] // 2
 
 
+@pytest.mark.parametrize("z16", [0, 1])
 @pytest.mark.parametrize("m", [19, 20, 21])
 @pytest.mark.parametrize("forced", [0, 1])
 @pytest.mark.parametrize("prec", ["f16", "bf16"])
-def test_sstep_arnoldi(prec, forced, m):
+def test_sstep_arnoldi(prec, forced, m, z16):
     """s Arnoldi steps per pass over the 16-bit basis (s = 2 .. 6: the
     shifted powers (Mhat - 1)^k v_j, k = 1..s, projected together, then
     orthonormalised among themselves) span the same Krylov space: the
     solutions reach LU and the true residual as the single-step form does,
     in about as many matrix-vector products; with the second pass forced on
     every block, and with cycle lengths p = m - 10 = 9, 10, 11, so that the
-    last block of a cycle is shorter than s (1 to 5 steps)."""
+    last block of a cycle is shorter than s (1 to 5 steps); with the powers
+    kept in FP32 and stored in the basis's 16-bit form (z16)."""
     require_gpu()
     dims, kappa = (6, 4, 2, 8), 0.13
     ctx, U = context(dims, 0.3, 1001, kappa)
@@ -140,8 +142,8 @@ def test_sstep_arnoldi(prec, forced, m):
     st = {}
     try:
         for steps in (1, 2, 3, 4, 5, 6):
-            ctx.tune(arnoldi_steps=steps, cycle_reorth=forced)
-            say("solve s-step", prec, forced, m, steps)
+            ctx.tune(arnoldi_steps=steps, cycle_reorth=forced, sstep_z16=z16)
+            say("solve s-step", prec, forced, m, steps, z16)
             x, defl, s = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=m, k=10, tol=1e-11, tol_super=1e-13,
                                            inner=prec, inner_tol=1e-3, rhs_block=3)
             x = to_host(x)
@@ -150,7 +152,7 @@ def test_sstep_arnoldi(prec, forced, m):
                 assert s[r]["true_resid"] < 1e-11, (steps, r)
             st[steps] = s
     finally:
-        ctx.tune(arnoldi_steps=4, cycle_reorth=0)
+        ctx.tune(arnoldi_steps=4, cycle_reorth=0, sstep_z16=0)
     for steps in (2, 3, 4, 5, 6):
         for r in range(1, 4):
             assert st[steps][r]["matvecs"] <= st[1][r]["matvecs"] + (m - 10 + 1), (steps, r, st[1][r], st[steps][r])
@@ -158,8 +160,9 @@ def test_sstep_arnoldi(prec, forced, m):
                 assert st[steps][r]["reorth"] > 0
 
 
+@pytest.mark.parametrize("z16", [0, 1])
 @pytest.mark.parametrize("prec", ["f16", "bf16"])
-def test_sstep_direct_and_explicit_paths_in_one_block(prec):
+def test_sstep_direct_and_explicit_paths_in_one_block(prec, z16):
     """The s-step block takes, per right-hand side, either the direct path
     (Gram matrix from the dot pass, basis vectors stored by the update pass)
     or the explicit one (update in place, second pass).  A right-hand side
@@ -183,10 +186,13 @@ def test_sstep_direct_and_explicit_paths_in_one_block(prec):
     e2[E] = v  # odd part zero: the even/odd source is v itself
     eta[2] = e2.reshape(ctx.shape)
     xref = np.linalg.solve(M, eta.reshape(4, -1).T).T.reshape(eta.shape)
-    ctx.tune(arnoldi_steps=4, cycle_reorth=0)
-    say("solve mixed paths", prec)
-    x, defl, s = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=20, k=10, tol=1e-11, tol_super=1e-13,
-                                   inner=prec, inner_tol=1e-3, rhs_block=3)
+    ctx.tune(arnoldi_steps=4, cycle_reorth=0, sstep_z16=z16)
+    say("solve mixed paths", prec, z16)
+    try:
+        x, defl, s = ctx.gmresdr_solve(to_gpu(eta), op="schur", m=20, k=10, tol=1e-11, tol_super=1e-13,
+                                       inner=prec, inner_tol=1e-3, rhs_block=3)
+    finally:
+        ctx.tune(sstep_z16=0)
     x = to_host(x)
     for r in range(4):
         assert rel_err(x[r], xref[r]) < 1e-9, r

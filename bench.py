@@ -350,6 +350,7 @@ def batching(args):
     s_dt = time.perf_counter() - t0
     s_seq = sum(seq_t[i] for i in small)
     sb.close()
+    few = few_rhs_lattices(args, cfg, kw)
     lat = ["%s x %d" % ("x".join(map(str, d)), n) for d, n in zip(cfg["lattices"], cfg["n_rhs"])]
     out = {"lattices": lat,
            "kappa": kappa, "solves": total, "setup_s": round(setup_s, 3),
@@ -365,9 +366,57 @@ def batching(args):
            "small_lattices_only": {"lattices": [lat[i] for i in small], "rhs_block": s_blk, "tile": s_tile,
                                    "batched_graph_solves_per_s": round(s_total / s_dt, 3),
                                    "sequential_solves_per_s": round(s_total / s_seq, 3),
-                                   "batched_over_sequential": round(s_seq / s_dt, 3)}}
+                                   "batched_over_sequential": round(s_seq / s_dt, 3)},
+           "few_rhs_lattices": few}
     print("[bench] batching %s" % json.dumps(out), file=sys.stderr, flush=True)
     return out
+
+
+def few_rhs_lattices(args, cfg, kw, n_lat=8, dims=(8, 8, 8, 8), n_rhs=4):
+    """The regime batching is for: many small lattices (configurations) with
+    a few noise vectors each, here 8 lattices of 8^4 (the batching
+    workload's links, kappa and Krylov sizes, link seeds of their own) with
+    4 right-hand sides each, batched against the same solves one lattice
+    after the other."""
+    import torch
+    from paper_1903_06986_amd import Batch, Context
+    from synth import random_su3_links
+    kappa = cfg["kappas"][0]
+    ctxs, defls, etas = [], [], []
+    for li in range(n_lat):
+        U = random_su3_links(dims, cfg["eps"], cfg["link_seed"] + 100 + li)
+        ctx = Context(dims, U, kappa)
+        _, defl, _ = ctx.gmresdr_solve(ctx.noise_z4(cfg["noise_seed"] + 100 + li, 0, 1), op="schur", m=cfg["m"],
+                                       k=cfg["k"], tol=args.tol, tol_super=args.tol_super,
+                                       max_cycles=args.max_cycles)
+        ctxs.append(ctx)
+        defls.append(defl)
+        etas.append(ctx.noise_z4(cfg["noise_seed"] + 100 + li, 1, n_rhs))
+    b = Batch(ctxs)
+    blk, tile, _ = b.autotune(etas, defls, **kw)
+    b.set_tile(tile)
+    b.solve(etas, defls, rhs_block=blk, graph=True, **kw)  # warm-up (graph capture, buffers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = b.solve(etas, defls, rhs_block=blk, graph=True, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.close()
+    for ctx, defl, eta in zip(ctxs, defls, etas):  # warm-up of the per-lattice buffers
+        ctx.gmresdr_solve(eta, op="schur", m=cfg["m"], k=cfg["k"], tol=args.tol, inner="f32",
+                          inner_tol=args.inner_tol, rhs_block=n_rhs, max_cycles=args.max_cycles, defl=defl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ctx, defl, eta in zip(ctxs, defls, etas):
+        ctx.gmresdr_solve(eta, op="schur", m=cfg["m"], k=cfg["k"], tol=args.tol, inner="f32",
+                          inner_tol=args.inner_tol, rhs_block=n_rhs, max_cycles=args.max_cycles, defl=defl)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    total = n_lat * n_rhs
+    return {"lattices": "%d x %s x %d" % (n_lat, "x".join(map(str, dims)), n_rhs), "rhs_block": blk, "tile": tile,
+            "batched_graph_solves_per_s": round(total / dt, 3), "sequential_solves_per_s": round(total / t_seq, 3),
+            "batched_over_sequential": round(t_seq / dt, 3),
+            "max_true_resid": max(s["true_resid"] for s in st)}
 
 
 def gradient_leg(args):

@@ -438,8 +438,10 @@ lqcd_status lqcd_timer_read(lqcd_ctx *ctx, int kclass, double *ms, double *bytes
  * those powers in FP32; 1 stores them in the basis's 16-bit form when the
  * basis is FP16 (half the bytes for the stencil and the Gram-Schmidt passes
  * that read them; the Arnoldi relation then carries their rounding; a BF16
- * basis keeps them in FP32).  Values are per context;
- * EINVAL for other values. */
+ * basis keeps them in FP32).  LQCD_TUNE_RECOMBINE_REGS: 1 (default) runs
+ * the restart recombination V_{k+1} = V_{m+1} P with its outputs in
+ * registers (up to 48 of them, P in LDS); 0 uses the LDS-tiled form.
+ * Values are per context; EINVAL for other values. */
 typedef enum {
   LQCD_TUNE_HOP_NB64 = 0,
   LQCD_TUNE_HOP_NB32 = 1,
@@ -456,7 +458,8 @@ typedef enum {
   LQCD_TUNE_CYCLE_REORTH = 12,
   LQCD_TUNE_KEPT_PERIOD = 13,
   LQCD_TUNE_ARNOLDI_STEPS = 14,
-  LQCD_TUNE_SSTEP_Z16 = 15
+  LQCD_TUNE_SSTEP_Z16 = 15,
+  LQCD_TUNE_RECOMBINE_REGS = 16
 } lqcd_tune_param;
 lqcd_status lqcd_tune_set(lqcd_ctx *ctx, lqcd_tune_param param, int value);
 

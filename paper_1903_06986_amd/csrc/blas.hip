@@ -422,6 +422,57 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// In-place recombination with the outputs in registers, for Jout <= kRJ:
+// lane = element; a workgroup holds P (Jout x Jin, FP64) in LDS and walks
+// elements gridDim.x * kBlock apart; a lane reads its element of all Jin
+// vectors once (coalesced across the wave) and accumulates all Jout
+// outputs (FP64 FMAs, each coefficient an LDS broadcast; the element of
+// the next four vectors is in flight meanwhile), then writes them.  Every read of an element precedes every write of it, and only its
+// lane touches it, so the update is in place.  Two workgroups fit a CU
+// (P takes 59 KiB for Jin = 81, Jout = 46), 2 waves per SIMD.
+constexpr int kRJ = 48;
+template <class R>
+__global__ void __launch_bounds__(kBlock)
+    k_recombine_r(cx<R> *__restrict__ V, size_t ldv, int Jin, const cx<double> *__restrict__ P, size_t ldp,
+                  int Jout, size_t n) {
+  extern __shared__ unsigned char smem[];
+  cx<double> *sp = reinterpret_cast<cx<double> *>(smem);  // [Jin][kRJ]: row l holds P[l][0..Jout)
+  for (int t = threadIdx.x; t < Jin * kRJ; t += kBlock) {
+    const int l = t / kRJ, j = t % kRJ;
+    sp[t] = j < Jout ? P[size_t(l) + ldp * size_t(j)] : mk<double>(0, 0);
+  }
+  __syncthreads();
+  for (size_t idx = size_t(blockIdx.x) * kBlock + threadIdx.x; idx < n; idx += size_t(gridDim.x) * kBlock) {
+    cx<double> acc[kRJ];
+#pragma unroll
+    for (int j = 0; j < kRJ; ++j) acc[j] = mk<double>(0, 0);
+    // the element of the next four vectors in flight while one is used
+    // (a register queue, rotated each step)
+    cx<R> b0 = ldc(V + idx), b1 = mk<R>(0, 0), b2 = mk<R>(0, 0), b3 = mk<R>(0, 0);
+    if (Jin > 1) b1 = ldc(V + ldv + idx);
+    if (Jin > 2) b2 = ldc(V + 2 * ldv + idx);
+    if (Jin > 3) b3 = ldc(V + 3 * ldv + idx);
+    for (int l = 0; l < Jin; ++l) {
+      const cx<R> v = b0;
+      b0 = b1;
+      b1 = b2;
+      b2 = b3;
+      if (l + 4 < Jin) b3 = ldc(V + size_t(l + 4) * ldv + idx);
+      const double vr = double(v.re), vi = double(v.im);
+      const cx<double> *pl = sp + size_t(l) * kRJ;
+#pragma unroll
+      for (int j = 0; j < kRJ; ++j) {
+        const cx<double> c = pl[j];
+        acc[j] = mk<double>(__builtin_fma(vr, c.re, __builtin_fma(-vi, c.im, acc[j].re)),
+                            __builtin_fma(vr, c.im, __builtin_fma(vi, c.re, acc[j].im)));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kRJ; ++j)
+      if (j < Jout) stc(V + size_t(j) * ldv + idx, mk<R>(R(acc[j].re), R(acc[j].im)));
+  }
+}
+
 // ------------------------------------------------- 16-bit stored bases
 // Basis vectors stored as in half.h (payload in 16-byte granules
 // [3][Vh][4 words], then per-site scales); the vector they act on stays
@@ -1525,6 +1576,17 @@ template <class R>
 void recombine(lqcd_ctx *c, void *V, size_t ldv, int Jin, const cdouble *P, size_t ldp, int Jout,
                size_t n) {
   LQCD_CHECK(Jout <= Jin, LQCD_EINVAL, "recombine: Jout > Jin");
+  const size_t shr = size_t(Jin) * kRJ * sizeof(cx<double>);
+  if (c->recombine_regs && Jout <= kRJ && shr <= 64 * 1024) {  // outputs in registers, P in LDS
+    LQCD_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_recombine_r<R>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
+    const int grid = int(std::min<size_t>((n + kBlock - 1) / kBlock, 256 * 2));
+    Timed tm(c, LQCD_KC_GEMM, double(Jin + Jout) * n * sizeof(cx<R>));
+    LQCD_TLAUNCH(tm, true, true, (k_recombine_r<R>), dim3(unsigned(grid)), dim3(kBlock), shr, c->stream,
+                 static_cast<cx<R> *>(V), ldv, Jin, reinterpret_cast<const cx<double> *>(P), ldp, Jout, n);
+    LQCD_HIP(hipGetLastError());
+    return;
+  }
   const size_t shw = size_t(Jout) * Jin * sizeof(cx<double>) + size_t(Jin) * 64 * sizeof(cx<R>);
   if (Jin <= kRPer * kBlock / 64 && shw <= 160 * 1024) {  // persistent, P and a 64-element tile in LDS
     // set on every call (once per restart): it is a property of the kernel

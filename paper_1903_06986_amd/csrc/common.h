@@ -149,6 +149,7 @@ struct lqcd_ctx {
   int kept_period = 16;          // MINRES-DR: steps between tests against the kept vectors
   int arnoldi_steps = 4;         // 16-bit GMRES-Proj cycles: Arnoldi steps per basis pass (1..6)
   int sstep_z16 = 0;             // s-step power vectors stored in 16-bit form (0: FP32)
+  int recombine_regs = 1;        // restart recombination with its outputs in registers (0: LDS-tiled form)
   ~lqcd_ctx();
 };
 

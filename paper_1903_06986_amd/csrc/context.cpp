@@ -212,6 +212,10 @@ extern "C" lqcd_status lqcd_tune_set(lqcd_ctx *c, lqcd_tune_param param, int val
         LQCD_CHECK(value >= 1 && value <= 6, LQCD_EINVAL, "lqcd_tune_set: Arnoldi steps per basis pass in 1..6");
         c->arnoldi_steps = value;
         break;
+      case LQCD_TUNE_RECOMBINE_REGS:
+        LQCD_CHECK(value == 0 || value == 1, LQCD_EINVAL, "lqcd_tune_set: recombination form must be 0 or 1");
+        c->recombine_regs = value;
+        break;
       case LQCD_TUNE_SSTEP_Z16:
         LQCD_CHECK(value == 0 || value == 1, LQCD_EINVAL, "lqcd_tune_set: 16-bit power vectors switch must be 0 or 1");
         c->sstep_z16 = value;

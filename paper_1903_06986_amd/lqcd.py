@@ -221,12 +221,12 @@ class Context:
     def tune(self, hop_nb64=None, hop_nb32=None, hop_tile64=None, hop_tile32=None, hop_order=None,
              hop_tblock64=None, hop_tblock32=None, hop_tsites32=None, hop_rgroup=None, hop_tsites64=None,
              gemm_mfma=None, hop_rnest=None, cycle_reorth=None, kept_period=None,
-             arnoldi_steps=None, sstep_z16=None):
+             arnoldi_steps=None, sstep_z16=None, recombine_regs=None):
         """Set launch-shape parameters (see lqcd_tune_set)."""
         for code, v in ((0, hop_nb64), (1, hop_nb32), (2, hop_tile64), (3, hop_tile32), (4, hop_order),
                         (5, hop_tblock64), (6, hop_tblock32), (7, hop_tsites32), (8, hop_rgroup),
                         (9, hop_tsites64), (10, gemm_mfma), (11, hop_rnest), (12, cycle_reorth), (13, kept_period),
-                        (14, arnoldi_steps), (15, sstep_z16)):
+                        (14, arnoldi_steps), (15, sstep_z16), (16, recombine_regs)):
             if v is not None:
                 _check(lib().lqcd_tune_set(self.handle, code, int(v)))
 

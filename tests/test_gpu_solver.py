@@ -302,3 +302,36 @@ def test_matrix_core_deflation_products(inner):
         for r in range(13):
             assert rel_err(x[r], xref[r]) < 1e-9
     assert rel_err(xs[0], xs[1]) < 1e-9
+
+
+@pytest.mark.parametrize("method,op", [("gmres-dr", "schur"), ("minres-dr", "MG5")])
+def test_recombination_forms_agree(method, op):
+    """The restart recombination V_{k+1} = V_{m+1} P in its two forms
+    (outputs in registers with P in LDS, and the LDS-tiled form) gives the
+    same first-right-hand-side solve: solutions and harmonic Ritz values
+    agree to rounding, and the solution reaches LU."""
+    require_gpu()
+    dims, kappa = (6, 4, 2, 8), 0.13
+    ctx, U = context(dims, 0.3, 31, kappa)
+    eta = z4_noise(5, dims, 0, 1)
+    out = {}
+    try:
+        for regs in (1, 0):
+            ctx.tune(recombine_regs=regs)
+            say("recombination form", regs, method)
+            x, defl, st = ctx.gmresdr_solve(to_gpu(eta), op=op, m=16, k=8, tol=1e-12, tol_super=1e-13,
+                                            max_cycles=400, method=method)
+            assert st[0]["cycles"] > 2, st[0]  # several restarts ran
+            out[regs] = (to_host(x), np.sort_complex(defl.ritz()[:10]), st[0]["matvecs"])
+    finally:
+        ctx.tune(recombine_regs=1)
+    M = W.dense_M(U, kappa, dims)
+    if op == "MG5":
+        M = M @ W.dense_gamma(L.GAMMA5, L.volume(dims))
+        xref = np.linalg.solve(M, eta.reshape(1, -1).T).T.reshape(eta.shape)
+    else:
+        xref = np.linalg.solve(M, eta.reshape(1, -1).T).T.reshape(eta.shape)
+    assert rel_err(out[1][0], xref) < 1e-9
+    assert rel_err(out[1][0], out[0][0]) < 1e-11
+    assert np.abs(out[1][1] - out[0][1]).max() < 1e-9 * np.abs(out[0][1]).max()
+    assert abs(out[1][2] - out[0][2]) <= 8

@@ -160,6 +160,17 @@ class Path:
         self.ones = np.ones(c["pert_order"] + 1, dtype=np.complex128)
         del lqcd
 
+    def clone(self, ctx, noise_offset):
+        """A second pipeline on another context of the same lattice: it shares
+        this one's setup (deflation spaces, polynomial and traces) and draws
+        its noise from its own range of indices."""
+        p = Path(ctx, self.cfg, self.args)
+        for k in ("defl", "hdefl", "lam", "lam_res", "herm_compare", "corr_poly", "cpoly", "apoly",
+                  "corr_pert", "setup_times", "first_stats", "herm_stats", "ones"):
+            setattr(p, k, getattr(self, k))
+        p.next_noise = self.next_noise + noise_offset
+        return p
+
     def step(self, inner):
         import torch
         from paper_1903_06986_amd import lqcd
@@ -190,6 +201,67 @@ class Path:
         res["HFPOLY"] = ctx.loop_estimate(eta, x, xt_poly, corr_hfpoly, THETAS)
         self.last = (eta, x)
         return st, res
+
+
+def run_steps_streams(paths, inner, steps, warmup):
+    """run_steps over several pipelines at once: one context (and stream)
+    per path, each timed step a block of noise vectors through the whole
+    path; after each path's untimed warm-up, the steps are shared out and
+    issued from one host thread per path (the library's calls release the
+    interpreter), so that one pipeline's host work and small kernels overlap
+    the other's (each pipeline takes the next step when it is free).
+    Returns the wall time of all steps, their solve stats and the
+    kernel-class timers summed over the contexts."""
+    import threading
+    import torch
+    if len(paths) == 1:
+        return run_steps(paths[0], inner, steps, warmup)
+    for p in paths:
+        with torch.cuda.stream(p.ctx.stream):
+            for _ in range(warmup):
+                p.step(inner)
+    torch.cuda.synchronize()
+    for p in paths:
+        p.ctx.timer(True)
+    stats = [[] for _ in paths]
+    errs = []
+    left = [steps]
+    lock = threading.Lock()
+
+    def take():
+        with lock:
+            if left[0] <= 0 or errs:
+                return False
+            left[0] -= 1
+            return True
+
+    def work(i):
+        try:
+            with torch.cuda.stream(paths[i].ctx.stream):
+                while take():  # the next step goes to whichever pipeline is free
+                    st, _ = paths[i].step(inner)
+                    stats[i] += st
+                paths[i].ctx.stream.synchronize()
+        except BaseException as e:  # re-raised in the caller
+            errs.append(e)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(paths))]
+    t0 = time.perf_counter()
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if errs:
+        raise errs[0]
+    kt = {}
+    for p in paths:
+        for k, v in p.ctx.timer_read().items():
+            a = kt.get(k, (0.0, 0.0, 0))
+            kt[k] = (a[0] + v[0], a[1] + v[1], a[2] + v[2])
+        p.ctx.timer(False)
+    return dt, sum(stats, []), kt
 
 
 def run_steps(path, inner, steps, warmup):
@@ -610,7 +682,7 @@ def dslash_table(reps, lattices=None, nrhs_list=(1, 4, 8, 16, 32)):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--kappa", type=float, default=None)
@@ -618,9 +690,14 @@ def main():
     ap.add_argument("--proj-m", type=int, default=0, help="GMRES-Proj cycle length (0: m - k)")
     ap.add_argument("--arnoldi-steps", type=int, default=4, choices=[1, 2, 3, 4, 5, 6],
                     help="Arnoldi steps per pass over the 16-bit basis in the inner GMRES-Proj cycles")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="pipelines run at once in the timed steps, one context and stream each")
+    ap.add_argument("--kernel-steps", type=int, default=3,
+                    help="steps of one pipeline alone, timed for the kernel classes and the roofline "
+                         "when --streams > 1")
     ap.add_argument("--sstep-z16", type=int, default=0, choices=[0, 1],
                     help="store the s-step power vectors in the basis's 16-bit form")
-    ap.add_argument("--fp64-steps", type=int, default=3, help="timed FP64 steps (at least 3, after 1 warm-up)")
+    ap.add_argument("--fp64-steps", type=int, default=4, help="timed FP64 steps (at least 4, after 1 warm-up per pipeline)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--tol-super", type=float, default=1e-12)
     ap.add_argument("--eig-tol", type=float, default=1e-5)
@@ -700,32 +777,52 @@ def main():
     dims = cfg["dims"]
     U = random_su3_links(dims, cfg["eps"], cfg["link_seed"])
     print("[bench] workload %s dims %s kappa %.8f" % (args.workload, dims, kappa), file=sys.stderr, flush=True)
-    ctx = Context(dims, U, kappa)
+    ctx = Context(dims, U, kappa, stream=torch.cuda.Stream() if args.streams > 1 else None)
+    # every later allocation of this thread on the context's stream, so that
+    # the caching allocator orders its reuse of memory with the library's
+    # kernels
+    torch.cuda.set_stream(ctx.stream)
     ctx.tune(arnoldi_steps=args.arnoldi_steps, sstep_z16=args.sstep_z16)
     path = Path(ctx, cfg, args)
     path.setup()
+    paths = [path]
+    for i in range(1, args.streams):
+        c2 = Context(dims, U, kappa, stream=torch.cuda.Stream())
+        c2.tune(arnoldi_steps=args.arnoldi_steps, sstep_z16=args.sstep_z16)
+        paths.append(path.clone(c2, 1000000 * i))
     print("[bench] setup %s" % json.dumps(path.setup_times), file=sys.stderr, flush=True)
     print("[bench] hermitian (%s): %d matvecs, compare %s" % (args.herm_method, path.herm_stats[0]["matvecs"],
                                                               json.dumps(path.herm_compare)),
           file=sys.stderr, flush=True)
-    dt, stats, kt = run_steps(path, args.inner, args.steps, args.warmup)
+    dt, stats, kt = run_steps_streams(paths, args.inner, args.steps, args.warmup)
     n_solves = args.steps * args.rhs_block
     value = n_solves / dt
-    print("[bench] mixed (%s): %d solves in %.3f s" % (args.inner, n_solves, dt), file=sys.stderr, flush=True)
+    print("[bench] mixed (%s, %d pipelines): %d solves in %.3f s" % (args.inner, len(paths), n_solves, dt),
+          file=sys.stderr, flush=True)
+    single = None
+    if len(paths) > 1:
+        # concurrent pipelines share the GPU, so their kernels' own durations
+        # are not kernel times: the per-class rates and the roofline come from
+        # steps of one pipeline alone (already warm)
+        dt1, _, kt = run_steps(path, args.inner, args.kernel_steps, 0)
+        single = {"value": round(args.kernel_steps * args.rhs_block / dt1, 4), "steps": args.kernel_steps,
+                  "ms_per_step": round(dt1 / args.kernel_steps * 1e3, 2)}
+        print("[bench] one pipeline: %s" % json.dumps(single), file=sys.stderr, flush=True)
     variants = {}
     for v in [v for v in args.variants.split(",") if v and v != args.inner]:
-        dtv, stv, _ = run_steps(path, v, args.variant_steps, 1)
+        dtv, stv, _ = run_steps_streams(paths, v, args.variant_steps, 1)
         variants[v] = {"value": round(args.variant_steps * args.rhs_block / dtv, 4), "unit": "noise-solves/s",
                        "steps": args.variant_steps,
                        "matvecs_per_solve": float(np.mean([s["matvecs"] for s in stv])),
                        "refinements": float(np.mean([s["refinements"] for s in stv])),
                        "max_true_resid": max(s["true_resid"] for s in stv)}
         print("[bench] variant %s %s" % (v, json.dumps(variants[v])), file=sys.stderr, flush=True)
-    # the plain-FP64 rate: one untimed warm-up step first, so that its basis
-    # (about 28 GB at 24^3 x 32 with 16 right-hand sides) is allocated
-    # before the timed steps
-    fp64_steps = max(3, args.fp64_steps)
-    dt64, stats64, kt64 = run_steps(path, "f64", fp64_steps, 1)
+    # the plain-FP64 rate, with as many pipelines as the mixed one: one
+    # untimed warm-up step per pipeline first, so that its basis (about 28
+    # GB at 24^3 x 32 with 16 right-hand sides) is allocated before the
+    # timed steps
+    fp64_steps = max(4, args.fp64_steps)
+    dt64, stats64, kt64 = run_steps_streams(paths, "f64", fp64_steps, 1)
     value64 = fp64_steps * args.rhs_block / dt64
     print("[bench] fp64: %d solves in %.3f s" % (fp64_steps * args.rhs_block, dt64), file=sys.stderr,
           flush=True)
@@ -772,9 +869,12 @@ def main():
                    "rhs_block": args.rhs_block, "inner": args.inner, "arnoldi_steps": args.arnoldi_steps,
                    "sstep_z16": args.sstep_z16},
         "fp64": {"value": round(value64, 4), "unit": "noise-solves/s", "steps": fp64_steps, "warmup": 1,
+                 "pipelines": len(paths),
                  "matvecs_per_solve": mv64, "reorth_per_solve": float(np.mean([s["reorth"] for s in stats64])),
                  "max_true_resid": max(s["true_resid"] for s in stats64)},
         "mixed_over_fp64": round(value / value64, 3),
+        "pipelines": len(paths),
+        "one_pipeline": single,
         "mixed": {"matvecs_per_solve": mv, "refinements": float(np.mean([s["refinements"] for s in stats])),
                   "reorth_per_solve": float(np.mean([s["reorth"] for s in stats])),
                   "max_true_resid": max(s["true_resid"] for s in stats)},

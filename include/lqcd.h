@@ -31,6 +31,11 @@
  * Errors: every call returns an lqcd_status, never aborts and never throws;
  * lqcd_last_error() gives a thread-local message for the last failure.
  * Calls on one context are not thread-safe; use one context per thread.
+ * A deflation space (lqcd_defl) may serve several contexts of its lattice
+ * and kappa, also from different threads at once: the caches it fills on
+ * first use are filled once, under a lock, and complete before any other
+ * context reads them.  All users of one space take the same number of
+ * eigenpairs Q.
  */
 #ifndef LQCD_H
 #define LQCD_H

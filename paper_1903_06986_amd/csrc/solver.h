@@ -2,12 +2,22 @@
 // hermitian-forced subtraction.
 #pragma once
 
+#include <mutex>
+
 #include "common.h"
 #include "smallla.h"
 
 // Opaque handle of the C ABI: the deflation data A V_k = V_{k+1} Hbar_k
 // left by GMRES-DR (Sec. 7), for the operator it was built with.
+// A deflation space may serve several contexts of its lattice and kappa,
+// also from different host threads: its caches (the FP32 copy, eigenpairs
+// and their trace bilinears, 1/xi' values, lexicographic copies, ES data)
+// are filled once under fill_mu, and the filling context's stream is
+// synchronised before the lock is released, so the other contexts read
+// complete data on their own streams.  All users of one space take the
+// same number of eigenpairs Q.
 struct lqcd_defl {
+  std::mutex fill_mu;
   lqcd_op op = LQCD_OP_SCHUR;   // SCHUR: even-site vectors; MG5: full-lattice vectors
   int k = 0;                     // number of deflation vectors
   size_t n = 0;                  // vector length in complex numbers

@@ -1159,6 +1159,7 @@ void full_norms(lqcd_ctx *c, Work &w, int nb, std::vector<double> &out) {
 void defl_eigpairs(lqcd_ctx *c, lqcd_defl *d, int Q) {
   LQCD_CHECK(d->op == LQCD_OP_MG5, LQCD_EINVAL, "eigenpairs need a deflation space of M' (op MG5)");
   LQCD_CHECK(Q >= 1 && Q <= d->k, LQCD_EINVAL, "Q = %d outside 1..k = %d", Q, d->k);
+  std::lock_guard<std::mutex> lk(d->fill_mu);
   if (d->Qe == Q && d->E.ptr) return;
   const int k = d->k;
   la::Mat T = sub(d->H, k, k);
@@ -1285,10 +1286,14 @@ extern "C" lqcd_status gmresdr_solve(lqcd_ctx *c, lqcd_op op, const lqcd_solve_p
                            p.max_cycles, mv, cy, res, ro);
       } else {
         // FP64 refinement around FP32 deflated inner solves
-        if (!d->have_v32) {
-          d->V32.ensure(size_t(d->k + 1) * n * sizeof(cx<float>));
-          convert<double, float>(c, d->V.ptr, d->V32.ptr, size_t(d->k + 1) * n);
-          d->have_v32 = true;
+        {
+          std::lock_guard<std::mutex> lk(d->fill_mu);
+          if (!d->have_v32) {
+            d->V32.ensure(size_t(d->k + 1) * n * sizeof(cx<float>));
+            convert<double, float>(c, d->V.ptr, d->V32.ptr, size_t(d->k + 1) * n);
+            LQCD_HIP(hipStreamSynchronize(c->stream));
+            d->have_v32 = true;
+          }
         }
         void *S32 = w.S32.ensure(n * nb * sizeof(cx<float>));
         void *X32 = w.X32.ensure(n * nb * sizeof(cx<float>));

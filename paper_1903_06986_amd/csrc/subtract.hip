@@ -517,6 +517,7 @@ void es_pairs(lqcd_ctx *c, lqcd_defl *d, int Q) {
   LQCD_CHECK(d->op == LQCD_OP_SCHUR, LQCD_EINVAL,
              "eigenvalue subtraction needs the even/odd deflation space (op LQCD_OP_SCHUR)");
   LQCD_CHECK(Q >= 1 && Q <= d->k, LQCD_EINVAL, "Q = %d outside 1..k = %d", Q, d->k);
+  std::lock_guard<std::mutex> lk(d->fill_mu);
   if (d->Qes == Q && d->ER.ptr) return;
   const int k = d->k;
   la::Mat T(k, k);
@@ -596,6 +597,7 @@ void es_project(lqcd_ctx *c, lqcd_defl *d, int Q, const int *thetas, int nth, co
   std::vector<cdouble> w(Q);
   for (int q = 0; q < Q; ++q) w[q] = 1.0 / d->es_lam[q];
   if (corr && nth > 0) {
+    std::lock_guard<std::mutex> lk(d->fill_mu);
     if (d->es_bil.empty()) {
       d->es_bil.assign(size_t(Q) * kNumOps * Lt, 0.0);
       cdouble one(1, 0);
@@ -775,6 +777,7 @@ extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_de
       // computed once per polynomial and kept with the eigenpairs
       std::vector<cdouble> cc(ncoeff);
       for (int j = 0; j < ncoeff; ++j) cc[j] = cdouble(coeffs_host[2 * j], coeffs_host[2 * j + 1]);
+      std::lock_guard<std::mutex> lk(d->fill_mu);
       bool found = false;
       for (auto &e : d->xi_cache)
         if (e.first == cc) {
@@ -804,6 +807,7 @@ extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_de
     // trace correction: sum_q w_q e_q^+ Theta g5 e_q per timeslice, from the
     // per-mode bilinears (computed once per set of eigenpairs)
     if (corr && nth > 0) {
+      std::lock_guard<std::mutex> lk(d->fill_mu);
       if (d->bil.empty()) {
         d->bil.assign(size_t(Q) * kNumOps * Lt, 0.0);
         cdouble one(1, 0);
@@ -836,6 +840,7 @@ extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_de
     // (made once per set of eigenpairs), so that eta is read and xt updated
     // in place: one pass over the modes for the dots, one for the update
     const size_t Vh = size_t(c->g.Vh);
+    std::unique_lock<std::mutex> lk(d->fill_mu);
     if (d->lex_Q != Q) {
       cx<double> *El = static_cast<cx<double> *>(d->Elex.ensure(fl * Q * sizeof(cx<double>)));
       cx<double> *Gl = static_cast<cx<double> *>(d->G5Elex.ensure(fl * Q * sizeof(cx<double>)));
@@ -845,8 +850,10 @@ extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_de
       hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(2 * 6 * Vh * Q)), dim3(kBlock), 0, c->stream, T, Vh, fl, Q);
       LQCD_HIP(hipGetLastError());
       unpack_eo<double>(c, T, Gl, Q, fl);
+      LQCD_HIP(hipStreamSynchronize(c->stream));
       d->lex_Q = Q;
     }
+    lk.unlock();
     const cx<double> *El = d->Elex.as<cx<double>>(), *Gl = d->G5Elex.as<cx<double>>();
     cdouble *wd = static_cast<cdouble *>(c->ws[6].ensure(size_t(Q) * sizeof(cdouble)));
     h2d(c, wd, w.data(), size_t(Q) * sizeof(cdouble));

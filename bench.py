@@ -181,24 +181,22 @@ class Path:
         x, _, st = ctx.gmresdr_solve(eta, op="schur", m=c["m"], k=c["k"], tol=a.tol, inner=inner,
                                      inner_tol=a.inner_tol, rhs_block=B, max_cycles=a.max_cycles,
                                      defl=self.defl, proj_m=a.proj_m)
-        res = {}
-        res["NS"] = ctx.loop_estimate(eta, x, None, None, THETAS)
         xt_ps, _ = ctx.pert_subtract(c["pert_order"], eta, THETAS, want_corr=False)
-        res["PS"] = ctx.loop_estimate(eta, x, xt_ps, self.corr_pert, THETAS)
         xt_poly, _, _, _ = ctx.poly_subtract(c["poly_degree"], eta, b=None, coeffs=self.cpoly,
                                              thetas=THETAS, want_corr=False)
-        res["POLY"] = ctx.loop_estimate(eta, x, xt_poly, self.corr_poly, THETAS)
         xt_hf, corr_hf, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=torch.zeros_like(eta),
                                                 mode=lqcd.DEFL_HFES, thetas=THETAS)
-        res["HFES"] = ctx.loop_estimate(eta, x, xt_hf, corr_hf, THETAS)
-        del xt_hf
-        xt_ps, corr_hfps, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=xt_ps, corr=self.corr_pert,
-                                                  mode=lqcd.DEFL_EIGPOLY, coeffs=self.ones, thetas=THETAS)
-        res["HFPS"] = ctx.loop_estimate(eta, x, xt_ps, corr_hfps, THETAS)
-        xt_poly, corr_hfpoly, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=xt_poly, corr=self.corr_poly,
-                                                      mode=lqcd.DEFL_EIGPOLY, coeffs=self.cpoly,
-                                                      thetas=THETAS)
-        res["HFPOLY"] = ctx.loop_estimate(eta, x, xt_poly, corr_hfpoly, THETAS)
+        xt_hfps, corr_hfps, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=xt_ps.clone(), corr=self.corr_pert,
+                                                    mode=lqcd.DEFL_EIGPOLY, coeffs=self.ones, thetas=THETAS)
+        xt_hfpoly, corr_hfpoly, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=xt_poly.clone(),
+                                                        corr=self.corr_poly, mode=lqcd.DEFL_EIGPOLY,
+                                                        coeffs=self.cpoly, thetas=THETAS)
+        # the six estimates of this solve in one call (eta and x shared)
+        names = ("NS", "PS", "POLY", "HFES", "HFPS", "HFPOLY")
+        est = ctx.loop_estimate_multi(eta, x, [None, xt_ps, xt_poly, xt_hf, xt_hfps, xt_hfpoly],
+                                      [None, self.corr_pert, self.corr_poly, corr_hf, corr_hfps, corr_hfpoly],
+                                      THETAS)
+        res = dict(zip(names, est))
         self.last = (eta, x)
         return st, res
 

@@ -283,6 +283,22 @@ lqcd_status loop_estimate(lqcd_ctx *ctx, const int *thetas_host, int ntheta, con
                           const double *trace_corr_host, double *est_host,
                           double *stderr_host, double *samples_host);
 
+/* Several subtracted estimates of one set of solutions at once (Sec. 5
+ * Eq. (23) for each of the subtraction methods of Secs. 5.1-5.5 on the same
+ * noise): variant v is loop_estimate with xt = xt_list[v] and
+ * trace_corr_host = corr_list[v], and its results equal that call's bit for
+ * bit, while eta and x are read once for all variants.
+ * xt_list: host array [nvar] of device LEX pointers [nrhs] (an entry NULL:
+ * no subtraction); corr_list: host array [nvar] of host complex128
+ * [ntheta][Lt] pointers (an entry NULL: no correction), or NULL for none.
+ * Outputs (host): est complex128 [nvar][ntheta][Lt+1]; stderr_host double
+ * [nvar][ntheta][Lt+1][2]; samples_host optional complex128
+ * [nvar][nrhs][ntheta][Lt+1].  EINVAL unless 1 <= nvar <= 6. */
+lqcd_status loop_estimate_multi(lqcd_ctx *ctx, const int *thetas_host, int ntheta, const void *eta,
+                                const void *x, const void *const *xt_list, int nvar, int nrhs,
+                                const double *const *corr_list, double *est_host, double *stderr_host,
+                                double *samples_host);
+
 /* Allocation-free form of loop_estimate, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the same arguments, results and

@@ -23,55 +23,80 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Up to kMaxVar subtracted vectors of one set of solutions are estimated
+// together: variant v forms x - xt_v (xt_v null: x itself) with the same
+// operations, in the same order, as a pass with that variant alone, so its
+// sums equal that pass's bit for bit.  The local kernel reads eta and x once
+// for a group of variants; the point-split kernel runs the variants'
+// workgroups of one chunk side by side, so that they share eta, x and the
+// links through the L2.
+constexpr int kMaxVar = 6;
+struct XtSet {
+  const cx<double> *p[kMaxVar];
+  int slot[kMaxVar];  // the point-split kernel: output slot of each variant
+};
+
 // Each timeslice is split over nch workgroups (blockIdx.x = t * nch + ch)
-// so the launch fills the chip; partial sums go to
-// out[((r * kNumOps + op) * Lt + t) * nch + ch] (re, im) and the host adds
-// the chunks in a fixed order.
+// so the launch fills the chip; partial sums of variant v0 + v go to
+// out[(((v * nrhs + r) * kNumOps + op) * Lt + t) * nch + ch] (re, im) and
+// the host adds the chunks in a fixed order.
+template <int NV>
 __global__ void __launch_bounds__(kBlock)
-    k_estimate(const cx<double> *__restrict__ eta, const cx<double> *__restrict__ x,
-               const cx<double> *__restrict__ xt, size_t V, int Vs, int Lt, int nch,
-               double *__restrict__ out) {
-  __shared__ double sh[2 * kNumTheta][kWaves];
-  const int t = blockIdx.x / nch, ch = blockIdx.x % nch, r = blockIdx.y;
+    k_estimate(const cx<double> *__restrict__ eta, const cx<double> *__restrict__ x, XtSet xts, int v0,
+               size_t V, int Vs, int Lt, int nch, double *__restrict__ out) {
+  __shared__ double sh[NV * 2 * kNumTheta][kWaves];
+  const int t = blockIdx.x / nch, ch = blockIdx.x % nch, r = blockIdx.y, nrhs = gridDim.y;
   const size_t base = (size_t(r) * V + size_t(t) * Vs) * 12;
-  double acc[2 * kNumTheta] = {};
+  double acc[NV][2 * kNumTheta] = {};
   // lane = (site, colour c): it loads the four spins of colour c of eta, x
-  // and xt (12 loads of 16 bytes, three lanes cover a site's 192-byte block)
-  // and forms every Theta's terms from registers, since each Theta only
-  // permutes spins (with a phase) at fixed colour
+  // and each xt_v (loads of 16 bytes, three lanes cover a site's 192-byte
+  // block) and forms every Theta's terms from registers, since each Theta
+  // only permutes spins (with a phase) at fixed colour
   const size_t ne = size_t(Vs) * 3;
   for (size_t e = size_t(ch) * kBlock + threadIdx.x; e < ne; e += size_t(nch) * kBlock) {
     const size_t s0 = base + e / 3 * 12 + e % 3;  // (site, spin 0, colour c)
-    cx<double> a[4], d[4];
+    cx<double> a[4], xs[4];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) {
       a[sp] = ldc(eta + s0 + 3 * sp);
-      d[sp] = ldc(x + s0 + 3 * sp);
+      xs[sp] = ldc(x + s0 + 3 * sp);
     }
-    if (xt)
 #pragma unroll
-      for (int sp = 0; sp < 4; ++sp) d[sp] = d[sp] - ldc(xt + s0 + 3 * sp);
+    for (int v = 0; v < NV; ++v) {
+      const cx<double> *xt = xts.p[v];
+      cx<double> d[4];
 #pragma unroll
-    for (int th = 0; th < kNumTheta; ++th)
+      for (int sp = 0; sp < 4; ++sp) d[sp] = xs[sp];
+      if (xt)
 #pragma unroll
-      for (int sp = 0; sp < 4; ++sp) {
-        const cx<double> v = cmulc(a[sp], mk(kGamma[th].re[sp], kGamma[th].im[sp]) * d[kGamma[th].col[sp]]);
-        acc[2 * th] += v.re;
-        acc[2 * th + 1] += v.im;
-      }
+        for (int sp = 0; sp < 4; ++sp) d[sp] = d[sp] - ldc(xt + s0 + 3 * sp);
+#pragma unroll
+      for (int th = 0; th < kNumTheta; ++th)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+          const cx<double> w = cmulc(a[sp], mk(kGamma[th].re[sp], kGamma[th].im[sp]) * d[kGamma[th].col[sp]]);
+          acc[v][2 * th] += w.re;
+          acc[v][2 * th + 1] += w.im;
+        }
+    }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < 2 * kNumTheta; ++k) acc[k] = wave_sum(acc[k]);
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int k = 0; k < 2 * kNumTheta; ++k) acc[v][k] = wave_sum(acc[v][k]);
   if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < 2 * kNumTheta; ++k) sh[k][wave] = acc[k];
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int k = 0; k < 2 * kNumTheta; ++k) sh[v * 2 * kNumTheta + k][wave] = acc[v][k];
   __syncthreads();
-  if (threadIdx.x < 2 * kNumTheta) {
-    double s = 0;
-    for (int w = 0; w < kWaves; ++w) s += sh[threadIdx.x][w];
-    const int th = threadIdx.x / 2, part = threadIdx.x % 2;
-    out[(((size_t(r) * kNumOps + th) * Lt + t) * nch + ch) * 2 + part] = s;
+  if (threadIdx.x < NV * 2 * kNumTheta) {
+    double sum = 0;
+    for (int w = 0; w < kWaves; ++w) sum += sh[threadIdx.x][w];
+    const int v = threadIdx.x / (2 * kNumTheta), k = threadIdx.x % (2 * kNumTheta);
+    const int th = k / 2, part = k % 2;
+    out[((((size_t(v0 + v) * nrhs + r) * kNumOps + th) * Lt + t) * nch + ch) * 2 + part] = sum;
   }
 }
 
@@ -198,22 +223,25 @@ __device__ inline void ps_dir(const cx<double> *U, size_t Vh, double kappa, cons
   }
 }
 
-// Workgroup order: the right-hand side varies fastest within one XCD's
-// contiguous range of logical workgroups (hardware workgroup h runs on XCD
-// h % 8), so the nrhs workgroups of one chunk of sites run back to back on
-// one XCD and read its links from that XCD's L2 (links are as many bytes as
-// one right-hand side's three fields).
+// Workgroup order: the variant varies fastest, then the right-hand side,
+// within one XCD's contiguous range of logical workgroups (hardware
+// workgroup h runs on XCD h % 8), so the nv workgroups of one chunk of one
+// right-hand side run side by side on one XCD and read its eta and x from
+// that XCD's L2, and the nv * nrhs workgroups of one chunk its links (links
+// are as many bytes as one right-hand side's three fields).  Each workgroup
+// is the estimator of its variant alone.
 template <bool XT>
 __global__ void __launch_bounds__(kBlock)
     k_estimate_ps(Geom g, const cx<double> *__restrict__ U, double kappa,
-                  const cx<double> *__restrict__ eta, const cx<double> *__restrict__ x,
-                  const cx<double> *__restrict__ xt, int nch, int nrhs, int xq, double *__restrict__ out) {
+                  const cx<double> *__restrict__ eta, const cx<double> *__restrict__ x, XtSet xts, int nv,
+                  int nch, int nrhs, int xq, double *__restrict__ out) {
   __shared__ double sh[2 * kNumPS][kWaves];
   __shared__ cx<double> eS[kPsArr], fS[kPsArr], bS[kPsArr];
   __shared__ int nb[2 * kNumPS + 1][kPsSites];  // neighbour site indices [2 mu + backward]; the sites
   const int L = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
-  if (L >= g.L[3] * nch * nrhs) return;  // whole workgroup: padding of the grid
-  const int r = L % nrhs, tch = L / nrhs;
+  if (L >= g.L[3] * nch * nrhs * nv) return;  // whole workgroup: padding of the grid
+  const int var = L % nv, r = (L / nv) % nrhs, tch = L / (nv * nrhs);
+  const cx<double> *__restrict__ xt = xts.p[var];
   const int t = tch / nch, ch = tch % nch;
   const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
   const int Vs = Lx * Ly * Lz;
@@ -258,7 +286,7 @@ __global__ void __launch_bounds__(kBlock)
     double v = 0;
     for (int w = 0; w < kWaves; ++w) v += sh[threadIdx.x][w];
     const int m = threadIdx.x / 2, part = threadIdx.x % 2;
-    out[(((size_t(r) * kNumOps + kNumTheta + m) * Lt + t) * nch + ch) * 2 + part] = v;
+    out[((((size_t(xts.slot[var]) * nrhs + r) * kNumOps + kNumTheta + m) * Lt + t) * nch + ch) * 2 + part] = v;
   }
 }
 
@@ -298,46 +326,97 @@ int estimate_chunks(const Geom &g, int nrhs, size_t cap_doubles) {
   return nch;
 }
 
-// The estimator with its partial sums in d (at least
-// nrhs * kNumOps * Lt * nch * 2 doubles of device memory).
-void estimate_with(lqcd_ctx *c, const int *thetas, int nth, const void *eta, const void *x, const void *xt,
-                   int nrhs, const double *corr, double *est, double *stderr_, double *samples, double *d,
-                   int nch) {
-  {
-    bool any_local = false, any_ps = false;
-    for (int a = 0; a < nth; ++a) (thetas[a] < kNumTheta ? any_local : any_ps) = true;
-    const Geom &g = c->g;
-    const int Lt = g.L[3], Vs = g.V / Lt;
-    if (any_local) {
-      hipLaunchKernelGGL(k_estimate, dim3(Lt * nch, nrhs), dim3(kBlock), 0, c->stream,
-                         static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x),
-                         static_cast<const cx<double> *>(xt), size_t(g.V), Vs, Lt, nch, d);
-      LQCD_HIP(hipGetLastError());
+// Variants per launch of the local kernel (its per-lane sums grow by 10
+// doubles per variant).
+constexpr int kLocalGroup = 3;
+
+template <int NV>
+void launch_local(lqcd_ctx *c, const void *eta, const void *x, const XtSet &xts, int v0, int nrhs, double *d,
+                  int nch) {
+  const Geom &g = c->g;
+  const int Lt = g.L[3], Vs = g.V / Lt;
+  hipLaunchKernelGGL(k_estimate<NV>, dim3(Lt * nch, nrhs), dim3(kBlock), 0, c->stream,
+                     static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x), xts, v0, size_t(g.V),
+                     Vs, Lt, nch, d);
+  LQCD_HIP(hipGetLastError());
+}
+
+// The point-split kernel over the n variants of xts, all with (XT) or all
+// without a subtracted vector.
+template <bool XT>
+void launch_ps(lqcd_ctx *c, const void *eta, const void *x, const XtSet &xts, int n, int nrhs, double *d,
+               int nch) {
+  const Geom &g = c->g;
+  const int Lt = g.L[3];
+  const int xq = (Lt * nch * nrhs * n + 7) / 8;  // logical workgroups per XCD (grid padded to 8 xq)
+  hipLaunchKernelGGL(k_estimate_ps<XT>, dim3(8 * xq), dim3(kBlock), 0, c->stream, g,
+                     static_cast<const cx<double> *>(c->U64.ptr), c->kappa, static_cast<const cx<double> *>(eta),
+                     static_cast<const cx<double> *>(x), xts, n, nch, nrhs, xq, d);
+  LQCD_HIP(hipGetLastError());
+}
+
+// Launch KERNEL<n> over the variants [v0, v0 + n) for n <= 6.
+#define LQCD_EST_DISPATCH(KERNEL, n, ...)                  \
+  switch (n) {                                             \
+    case 1: KERNEL<1>(__VA_ARGS__); break;                 \
+    case 2: KERNEL<2>(__VA_ARGS__); break;                 \
+    case 3: KERNEL<3>(__VA_ARGS__); break;                 \
+    case 4: KERNEL<4>(__VA_ARGS__); break;                 \
+    case 5: KERNEL<5>(__VA_ARGS__); break;                 \
+    default: KERNEL<6>(__VA_ARGS__); break;                \
+  }
+
+// The estimator of nvar variants (subtracted vectors xt[v], corrections
+// corr[v]) with its partial sums in d (at least nvar * nrhs * kNumOps * Lt
+// * nch * 2 doubles of device memory).  Variant v's outputs start at
+// est + v * nth * (Lt + 1) * 2, stderr_ + (same), samples + v * nrhs * nth
+// * (Lt + 1) * 2.
+void estimate_with(lqcd_ctx *c, const int *thetas, int nth, const void *eta, const void *x,
+                   const void *const *xt, int nvar, int nrhs, const double *const *corr, double *est,
+                   double *stderr_, double *samples, double *d, int nch) {
+  bool any_local = false, any_ps = false;
+  for (int a = 0; a < nth; ++a) (thetas[a] < kNumTheta ? any_local : any_ps) = true;
+  auto group = [&](int v0, int n) {
+    XtSet xts{};
+    for (int v = 0; v < n; ++v) xts.p[v] = static_cast<const cx<double> *>(xt[v0 + v]);
+    return xts;
+  };
+  if (any_local)
+    for (int v0 = 0; v0 < nvar; v0 += kLocalGroup) {
+      const int n = std::min(kLocalGroup, nvar - v0);
+      LQCD_EST_DISPATCH(launch_local, n, c, eta, x, group(v0, n), v0, nrhs, d, nch)
     }
-    if (any_ps) {
-      const int xq = (Lt * nch * nrhs + 7) / 8;  // logical workgroups per XCD (grid padded to 8 xq)
-      if (xt)
-        hipLaunchKernelGGL(k_estimate_ps<true>, dim3(8 * xq), dim3(kBlock), 0, c->stream, g,
-                           static_cast<const cx<double> *>(c->U64.ptr), c->kappa,
-                           static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x),
-                           static_cast<const cx<double> *>(xt), nch, nrhs, xq, d);
-      else
-        hipLaunchKernelGGL(k_estimate_ps<false>, dim3(8 * xq), dim3(kBlock), 0, c->stream, g,
-                           static_cast<const cx<double> *>(c->U64.ptr), c->kappa,
-                           static_cast<const cx<double> *>(eta), static_cast<const cx<double> *>(x),
-                           static_cast<const cx<double> *>(nullptr), nch, nrhs, xq, d);
-      LQCD_HIP(hipGetLastError());
+  if (any_ps)
+    // one launch over the variants with a subtracted vector, one over those
+    // without
+    for (int with = 0; with < 2; ++with) {
+      int n = 0;
+      XtSet xts{};
+      for (int v = 0; v < nvar; ++v)
+        if ((xt[v] != nullptr) == bool(with)) {
+          xts.p[n] = static_cast<const cx<double> *>(xt[v]);
+          xts.slot[n++] = v;
+        }
+      if (!n) continue;
+      if (with) launch_ps<true>(c, eta, x, xts, n, nrhs, d, nch);
+      else launch_ps<false>(c, eta, x, xts, n, nrhs, d, nch);
     }
-    std::vector<double> hc(size_t(nrhs) * kNumOps * Lt * nch * 2);
-    LQCD_HIP(hipMemcpyAsync(hc.data(), d, hc.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    LQCD_HIP(hipStreamSynchronize(c->stream));
+
+  const int Lt = c->g.L[3];
+  std::vector<double> hc(size_t(nvar) * nrhs * kNumOps * Lt * nch * 2);
+  LQCD_HIP(hipMemcpyAsync(hc.data(), d, hc.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  LQCD_HIP(hipStreamSynchronize(c->stream));
+  const int W = Lt + 1;
+  for (int var = 0; var < nvar; ++var) {
+    const double *hv = hc.data() + size_t(var) * nrhs * kNumOps * Lt * nch * 2;
+    const double *cv = corr ? corr[var] : nullptr;
+    double *ev = est + size_t(var) * nth * W * 2, *sv = stderr_ + size_t(var) * nth * W * 2;
     std::vector<double> h(size_t(nrhs) * kNumOps * Lt * 2, 0.0);
     for (size_t o = 0; o < h.size() / 2; ++o)
       for (int ch = 0; ch < nch; ++ch) {
-        h[2 * o] += hc[(o * nch + ch) * 2];
-        h[2 * o + 1] += hc[(o * nch + ch) * 2 + 1];
+        h[2 * o] += hv[(o * nch + ch) * 2];
+        h[2 * o + 1] += hv[(o * nch + ch) * 2 + 1];
       }
-    const int W = Lt + 1;
     // samples [n][a][t], t = Lt the total
     std::vector<cdouble> smp(size_t(nrhs) * nth * W);
     for (int n = 0; n < nrhs; ++n)
@@ -368,24 +447,26 @@ void estimate_with(lqcd_ctx *c, const int *thetas, int nth, const void *eta, con
           sei = std::sqrt(vi / (nrhs - 1) / nrhs);
         }
         cdouble cr = 0;
-        if (corr) {
+        if (cv) {
           if (t < Lt) {
-            cr = cdouble(corr[2 * (a * Lt + t)], corr[2 * (a * Lt + t) + 1]);
+            cr = cdouble(cv[2 * (a * Lt + t)], cv[2 * (a * Lt + t) + 1]);
           } else {
-            for (int s = 0; s < Lt; ++s) cr += cdouble(corr[2 * (a * Lt + s)], corr[2 * (a * Lt + s) + 1]);
+            for (int s = 0; s < Lt; ++s) cr += cdouble(cv[2 * (a * Lt + s)], cv[2 * (a * Lt + s) + 1]);
           }
         }
         cdouble e = mean + cr;
-        est[2 * (a * W + t)] = e.real();
-        est[2 * (a * W + t) + 1] = e.imag();
-        stderr_[2 * (a * W + t)] = ser;
-        stderr_[2 * (a * W + t) + 1] = sei;
+        ev[2 * (a * W + t)] = e.real();
+        ev[2 * (a * W + t) + 1] = e.imag();
+        sv[2 * (a * W + t)] = ser;
+        sv[2 * (a * W + t) + 1] = sei;
       }
-    if (samples)
+    if (samples) {
+      double *pv = samples + size_t(var) * nrhs * nth * W * 2;
       for (size_t i = 0; i < smp.size(); ++i) {
-        samples[2 * i] = smp[i].real();
-        samples[2 * i + 1] = smp[i].imag();
+        pv[2 * i] = smp[i].real();
+        pv[2 * i + 1] = smp[i].imag();
       }
+    }
   }
 }
 
@@ -412,7 +493,22 @@ extern "C" lqcd_status loop_estimate(lqcd_ctx *c, const int *thetas, int nth, co
     const int nch = estimate_chunks(c->g, nrhs, 0);
     double *d = static_cast<double *>(
         c->red.ensure(size_t(nrhs) * kNumOps * c->g.L[3] * nch * 2 * sizeof(double)));
-    estimate_with(c, thetas, nth, eta, x, xt, nrhs, corr, est, stderr_, samples, d, nch);
+    estimate_with(c, thetas, nth, eta, x, &xt, 1, nrhs, &corr, est, stderr_, samples, d, nch);
+  });
+}
+
+extern "C" lqcd_status loop_estimate_multi(lqcd_ctx *c, const int *thetas, int nth, const void *eta,
+                                           const void *x, const void *const *xt_list, int nvar, int nrhs,
+                                           const double *const *corr_list, double *est, double *stderr_,
+                                           double *samples) {
+  return guarded([&] {
+    check_args(c, thetas, nth, eta, x, nrhs, est, stderr_, "loop_estimate_multi");
+    LQCD_CHECK(xt_list && nvar >= 1 && nvar <= kMaxVar, LQCD_EINVAL,
+               "loop_estimate_multi: %d variants (1..%d, with a list of subtracted vectors)", nvar, kMaxVar);
+    const int nch = estimate_chunks(c->g, nrhs, 0);
+    double *d = static_cast<double *>(
+        c->red.ensure(size_t(nvar) * nrhs * kNumOps * c->g.L[3] * nch * 2 * sizeof(double)));
+    estimate_with(c, thetas, nth, eta, x, xt_list, nvar, nrhs, corr_list, est, stderr_, samples, d, nch);
   });
 }
 
@@ -428,6 +524,6 @@ extern "C" lqcd_status loop_estimate_noalloc(lqcd_ctx *c, const int *thetas, int
                nrhs, c->g.L[3], one, kNoallocDoubles);
     double *d = noalloc_scratch();
     const int nch = estimate_chunks(c->g, nrhs, kNoallocDoubles);
-    estimate_with(c, thetas, nth, eta, x, xt, nrhs, corr, est, stderr_, samples, d, nch);
+    estimate_with(c, thetas, nth, eta, x, &xt, 1, nrhs, &corr, est, stderr_, samples, d, nch);
   });
 }

@@ -71,6 +71,7 @@ _SIGS = {
     "poly_subtract": [_P, _I, _P, _P, _P, _P, _I, _P, _P, _I, _P],
     "loop_estimate": [_P, _P, _I, _P, _P, _P, _I, _P, _P, _P, _P],
     "loop_estimate_noalloc": [_P, _P, _I, _P, _P, _P, _I, _P, _P, _P, _P],
+    "loop_estimate_multi": [_P, _P, _I, _P, _P, _P, _I, _I, _P, _P, _P, _P],
     "loop_gradient": [_P, _P, _P, _I, ctypes.POINTER(SolveParams), ctypes.POINTER(_P), _P, _P, _I,
                       _P, _P, ctypes.POINTER(SolveStats)],
     "lqcd_batch_create": [_P, _I, ctypes.POINTER(_P)],
@@ -386,6 +387,42 @@ class Context:
                                    est.ctypes.data_as(_P), err.ctypes.data_as(_P),
                                    smp.ctypes.data_as(_P) if samples else None))
         return (est, err, smp) if samples else (est, err)
+
+    def loop_estimate_multi(self, eta, x, xts, corrs=None, thetas=(0, 1, 2, 3, 4), samples=False):
+        """loop_estimate for several subtracted vectors of one solve at once
+        (xts: list of device fields or None; corrs: matching list of trace
+        corrections or None).  Returns one (est, err[, samples]) per entry,
+        each equal bit for bit to loop_estimate's."""
+        th, thp, nth = _thetas(thetas)
+        Lt = self.dims[3]
+        nrhs = eta.shape[0]
+        nv = len(xts)
+        fv = 12 * self.V
+        ptrs = (_P * nv)(*[None if t is None else _field(t, nrhs, fv, "xt") for t in xts])
+        keep = []
+        cptrs = None
+        if corrs is not None:
+            assert len(corrs) == nv, "one trace correction (or None) per subtracted vector"
+            cl = []
+            for cr in corrs:
+                if cr is None:
+                    cl.append(None)
+                else:
+                    a = np.ascontiguousarray(cr, dtype=np.complex128)
+                    keep.append(a)
+                    cl.append(a.ctypes.data_as(_P))
+            cptrs = (_P * nv)(*cl)
+        est = np.zeros((nv, nth, Lt + 1), dtype=np.complex128)
+        err = np.zeros((nv, nth, Lt + 1, 2))
+        smp = np.zeros((nv, nrhs, nth, Lt + 1), dtype=np.complex128) if samples else None
+        _check(lib().loop_estimate_multi(self.handle, thp, nth, _field(eta, nrhs, fv, "eta"),
+                                         _field(x, nrhs, fv, "x"), ptrs, nv, nrhs, cptrs,
+                                         est.ctypes.data_as(_P), err.ctypes.data_as(_P),
+                                         smp.ctypes.data_as(_P) if samples else None))
+        del keep
+        if samples:
+            return [(est[v], err[v], smp[v]) for v in range(nv)]
+        return [(est[v], err[v]) for v in range(nv)]
 
     # ------------------------------------------------------ differentiation
     def loop_gradient(self, eta, x=None, thetas=(0,), weights=None, defl=None, links=True, m=20, k=10,

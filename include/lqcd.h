@@ -305,8 +305,8 @@ lqcd_status loop_estimate_multi(lqcd_ctx *ctx, const int *thetas_host, int nthet
  * errors, with the per-workgroup partial sums in a fixed device array of
  * 4 MiB per GPU, held by the library until the process ends, instead of a
  * context workspace that grows on first use.  It calls no hipMalloc or
- * hipFree.  EINVAL when nrhs * 9 * Lt * 2 partial sums exceed 2^19 (e.g.
- * nrhs > 910 at Lt = 32).  Every call on one GPU uses that GPU's array:
+ * hipFree.  EINVAL when nrhs * 10 * Lt * 2 partial sums exceed 2^19 (e.g.
+ * nrhs > 819 at Lt = 32).  Every call on one GPU uses that GPU's array:
  * calls that overlap on one GPU (other streams or host threads) race. */
 lqcd_status loop_estimate_noalloc(lqcd_ctx *ctx, const int *thetas_host, int ntheta, const void *eta,
                                   const void *x, const void *xt, int nrhs, const double *trace_corr_host,

@@ -26,19 +26,22 @@ __device__ inline double wave_sum(double v) {
 // Up to kMaxVar subtracted vectors of one set of solutions are estimated
 // together: variant v forms x - xt_v (xt_v null: x itself) with the same
 // operations, in the same order, as a pass with that variant alone, so its
-// sums equal that pass's bit for bit.  The local kernel reads eta and x once
-// for a group of variants; the point-split kernel runs the variants'
-// workgroups of one chunk side by side, so that they share eta, x and the
-// links through the L2.
+// sums equal that pass's bit for bit.  Both kernels read eta and x once for
+// a group of variants (the point-split kernel also its neighbours' eta and
+// the links).
 constexpr int kMaxVar = 6;
+// Partial-sum slots per (variant, right-hand side, timeslice, chunk): the
+// nine operator codes, with code 8 (point-split in t) in two slots, 8 and
+// 9, for its terms whose row site lies one timeslice below and above the
+// site the kernel works on.
+constexpr int kOpSlots = kNumOps + 1;
 struct XtSet {
   const cx<double> *p[kMaxVar];
-  int slot[kMaxVar];  // the point-split kernel: output slot of each variant
 };
 
 // Each timeslice is split over nch workgroups (blockIdx.x = t * nch + ch)
 // so the launch fills the chip; partial sums of variant v0 + v go to
-// out[(((v * nrhs + r) * kNumOps + op) * Lt + t) * nch + ch] (re, im) and
+// out[(((v * nrhs + r) * kOpSlots + op) * Lt + t) * nch + ch] (re, im) and
 // the host adds the chunks in a fixed order.
 template <int NV>
 __global__ void __launch_bounds__(kBlock)
@@ -96,7 +99,7 @@ __global__ void __launch_bounds__(kBlock)
     for (int w = 0; w < kWaves; ++w) sum += sh[threadIdx.x][w];
     const int v = threadIdx.x / (2 * kNumTheta), k = threadIdx.x % (2 * kNumTheta);
     const int th = k / 2, part = k % 2;
-    out[((((size_t(v0 + v) * nrhs + r) * kNumOps + th) * Lt + t) * nch + ch) * 2 + part] = sum;
+    out[((((size_t(v0 + v) * nrhs + r) * kOpSlots + th) * Lt + t) * nch + ch) * 2 + part] = sum;
   }
 }
 
@@ -106,24 +109,33 @@ __global__ void __launch_bounds__(kBlock)
 //
 // (1 -+ g_mu) has rank 2 and squares to twice itself, and its lower half
 // spinor is a unitary R times the upper one, so for any colour matrix W
-//   a^+ (1 -+ g_mu) W b = sum_{s=0,1} at_s^+ W h_s,
+//   a^+ (1 -+ g_mu) W b = sum_{s=0,1} at_s^+ W h_s = sum_s (W^+ at_s)^+ h_s,
 // where at and h are the upper halves of (1 -+ g_mu) a and (1 -+ g_mu) b:
 // at_s = a_s + alpha_s a_{p(s)} with a spin partner p(s) in {2, 3} and a
 // phase alpha_s in {+-1, +-i}.
 //
+// The sums are taken over the site y that d = x - xt is read at: the
+// forward term of row x = y - mu is -kappa (U_mu(y - mu)^+ at)^+ h with at
+// from eta(y - mu), the backward term of row x = y + mu is kappa (U_mu(y)
+// at)^+ h with at from eta(y + mu), both with h from d(y).  So eta is read at
+// the neighbours and d only at y: the colour vectors c = W^+ at of a site
+// (one per direction and half spin) do not depend on d, and every variant
+// adds a dot product of three per direction and half spin.  A term belongs
+// to the timeslice of its row site, which for mu = t is the one below (the
+// forward terms) or above (the backward terms) y's.
+//
 // A workgroup takes 64 consecutive sites of one timeslice at a time.  The
-// fields are site-major (192 bytes per site), so it first stages them in
-// LDS with coalesced 16-byte loads (consecutive lanes read consecutive
-// pieces of consecutive sites): eta at its sites once, then for each
-// direction d = x - xt at the sites' forward and backward neighbours
-// (whose site runs are contiguous but for the wrap of the periodic
-// boundary).  LDS holds them component-major, [12][64 sites] with a row
-// stride of 65, so that a wave reading one component of 64 sites, and
-// a wave writing 12 components of consecutive sites, touch distinct banks
-// in every group of 8 lanes.  Then wave q of the workgroup takes one of the
-// four halves for all 64 sites (lane = site): q < 2 the forward half spin
-// s = q (W = U_mu(x)), q >= 2 the backward one s = q - 2 (W = U_mu(x -
-// mu)^+); the branch is uniform per wave and the link loads are coalesced.
+// fields are site-major (192 bytes per site), so it stages them in LDS with
+// coalesced 16-byte loads (consecutive lanes read consecutive pieces of
+// consecutive sites): for each direction eta at the sites' forward and
+// backward neighbours (whose site runs are contiguous but for the wrap of
+// the periodic boundary), then for each variant d at the sites.  LDS holds
+// them component-major, [12][64 sites] with a row stride of 65, so that a
+// wave reading one component of 64 sites, and a wave writing 12 components
+// of consecutive sites, touch distinct banks in every group of 8 lanes.
+// Wave q of the workgroup takes one of the four half spins for all 64 sites
+// (lane = site): q < 2 the forward one s = q, q >= 2 the backward one s = q
+// - 2; the branch is uniform per wave and the link loads are coalesced.
 constexpr int kPsSites = 64;                // sites per chunk
 constexpr int kPsRow = kPsSites + 1;        // LDS stride of one component
 constexpr int kPsArr = 12 * kPsRow;         // one staged field
@@ -134,52 +146,55 @@ __device__ inline const cx<double> *ps_link_at(const cx<double> *U, size_t Vh, s
   return U + ((size_t(par) * 4 + mu) * 9) * Vh + (s >> 1);
 }
 
-// Half spin HS of the direction-mu term at a lane's site: FWD with U_mu(x)
-// and d(x + mu), else U_mu(x - mu)^+ and d(x - mu).  ea and db point at the
-// site's column of the staged eta and d (components kPsRow apart); u is
-// the link (entries Vh apart).
+// Half spin HS of direction MU, forward (FWD: projector 1 - g_mu) or
+// backward (1 + g_mu).
 template <int MU, bool FWD, int HS>
-__device__ inline cx<double> ps_half_spin(const cx<double> *u, size_t Vh, const cx<double> *ea,
-                                          const cx<double> *db) {
+struct PsHalf {
   // partner spin and phase of the forward projector (negated backward)
-  constexpr int PS = MU < 2 ? 3 - HS : 2 + HS;
-  constexpr double AR0 = MU == 1 ? (HS ? -1.0 : 1.0) : MU == 3 ? -1.0 : 0.0;
-  constexpr double AI0 = MU == 0 ? 1.0 : MU == 2 ? (HS ? -1.0 : 1.0) : 0.0;
-  constexpr double AR = FWD ? AR0 : -AR0, AI = FWD ? AI0 : -AI0;
-  // at_k = a_HS,k + alpha a_PS,k with alpha in {+-1, +-i} (and likewise h)
-  auto proj = [](cx<double> p, cx<double> q) {
+  static constexpr int PS = MU < 2 ? 3 - HS : 2 + HS;
+  static constexpr double AR0 = MU == 1 ? (HS ? -1.0 : 1.0) : MU == 3 ? -1.0 : 0.0;
+  static constexpr double AI0 = MU == 0 ? 1.0 : MU == 2 ? (HS ? -1.0 : 1.0) : 0.0;
+  static constexpr double AR = FWD ? AR0 : -AR0, AI = FWD ? AI0 : -AI0;
+  // p + alpha q with alpha in {+-1, +-i}
+  __device__ static cx<double> proj(cx<double> p, cx<double> q) {
     return AR != 0.0 ? mk(p.re + AR * q.re, p.im + AR * q.im) : mk(p.re - AI * q.im, p.im + AI * q.re);
-  };
-  cx<double> at[3], h[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    at[k] = proj(ea[(HS * 3 + k) * kPsRow], ea[(PS * 3 + k) * kPsRow]);
-    h[k] = proj(db[(HS * 3 + k) * kPsRow], db[(PS * 3 + k) * kPsRow]);
   }
-  // the link loads go out after the projections (fewer registers live)
-  asm volatile("" : "+v"(at[0].re), "+v"(at[0].im), "+v"(at[1].re), "+v"(at[1].im), "+v"(at[2].re),
-               "+v"(at[2].im), "+v"(h[0].re), "+v"(h[0].im), "+v"(h[1].re), "+v"(h[1].im), "+v"(h[2].re),
-               "+v"(h[2].im)::"memory");
-  cx<double> acc = mk(0.0, 0.0);
+  // c = W^+ at for the staged eta column ea (components kPsRow apart) and
+  // the link u (entries Vh apart): W = U_mu(y - mu) (FWD), U_mu(y)^+ (else)
+  __device__ static void eta_side(const cx<double> *u, size_t Vh, const cx<double> *ea, cx<double> c[3]) {
+    cx<double> at[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    cx<double> w[3];  // row a of W
+    for (int k = 0; k < 3; ++k) at[k] = proj(ea[(HS * 3 + k) * kPsRow], ea[(PS * 3 + k) * kPsRow]);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const cx<double> e = ldc(u + (FWD ? 3 * a + b : 3 * b + a) * Vh);
-      w[b] = FWD ? e : mk(e.re, -e.im);
+    for (int k = 0; k < 3; ++k) c[k] = mk(0.0, 0.0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<double> e[3];  // row a of U (one row in flight: fewer registers live)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) e[b] = ldc(u + (3 * a + b) * Vh);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (FWD) c[b] = c[b] + cmulc(e[b], at[a]);  // (U^+ at)_b = sum_a conj(U_ab) at_a
+        else c[a] = c[a] + e[b] * at[b];            // (U at)_a = sum_b U_ab at_b
+      }
+      asm volatile("" : "+v"(c[0].re), "+v"(c[0].im), "+v"(c[1].re), "+v"(c[1].im), "+v"(c[2].re),
+                   "+v"(c[2].im)::"memory");
     }
-    acc = acc + cmulc(at[a], w[0] * h[0] + w[1] * h[1] + w[2] * h[2]);
   }
-  return acc;
-}
+  // c^+ h for the staged d column db
+  __device__ static cx<double> term(const cx<double> c[3], const cx<double> *db) {
+    cx<double> acc = mk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc = acc + cmulc(c[k], proj(db[(HS * 3 + k) * kPsRow], db[(PS * 3 + k) * kPsRow]));
+    return acc;
+  }
+};
 
-// Stage 64 sites' worth of x - xt (XT) or of x into LDS: piece p = 12 site
-// + k is complex k of the spinor at full site index idx[site] (-1: a site
+// Stage 64 sites' worth of f - g (g null: f) into LDS: piece p = 12 site +
+// k is complex k of the spinor at full site index idx[site] (-1: a site
 // past the end, zero; it loads site 0 and drops it, so that the loads of
 // all pieces go out together).
-template <bool XT>
-__device__ inline void ps_stage(cx<double> *sh, const cx<double> *x, const cx<double> *xt, const int *idx) {
+__device__ inline void ps_stage(cx<double> *sh, const cx<double> *f, const cx<double> *g, const int *idx) {
   cx<double> v[3];
   bool ok[3];
   int at[3];
@@ -190,58 +205,58 @@ __device__ inline void ps_stage(cx<double> *sh, const cx<double> *x, const cx<do
     const int s = idx[site];
     ok[u] = s >= 0;
     const size_t o = size_t(ok[u] ? s : 0) * 12 + k;
-    v[u] = ldc(x + o);
-    if (XT) v[u] = v[u] - ldc(xt + o);
+    v[u] = ldc(f + o);
+    if (g) v[u] = v[u] - ldc(g + o);
     at[u] = k * kPsRow + site;
   }
 #pragma unroll
   for (int u = 0; u < 3; ++u) sh[at[u]] = ok[u] ? v[u] : mk(0.0, 0.0);
 }
 
-template <int MU, bool XT>
-__device__ inline void ps_dir(const cx<double> *U, size_t Vh, double kappa, const cx<double> *x,
-                              const cx<double> *xt, const int (*nb)[kPsSites], const cx<double> *eS,
-                              cx<double> *fS, cx<double> *bS, size_t s, int par, bool on, double &re,
-                              double &im) {
-  __syncthreads();  // the previous direction's reads of fS, bS are done
-  ps_stage<XT>(fS, x, xt, nb[2 * MU]);
-  asm volatile("" ::: "memory");  // the backward loads after the forward ones (fewer registers live)
-  ps_stage<XT>(bS, x, xt, nb[2 * MU + 1]);
-  __syncthreads();
-  if (on) {
-    const int site = threadIdx.x & 63;
-    const int q = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const cx<double> *uf = ps_link_at(U, Vh, s, par, MU);
-    const cx<double> *ub = ps_link_at(U, Vh, size_t(nb[2 * MU + 1][site]), par ^ 1, MU);
-    cx<double> v;
-    if (q == 0) v = -kappa * ps_half_spin<MU, true, 0>(uf, Vh, eS + site, fS + site);
-    else if (q == 1) v = -kappa * ps_half_spin<MU, true, 1>(uf, Vh, eS + site, fS + site);
-    else if (q == 2) v = kappa * ps_half_spin<MU, false, 0>(ub, Vh, eS + site, bS + site);
-    else v = kappa * ps_half_spin<MU, false, 1>(ub, Vh, eS + site, bS + site);
-    re += v.re;
-    im += v.im;
+// Wave q's colour vector of direction MU at its lane's site: eta at y + mu
+// in fS, at y - mu in bS.
+template <int MU>
+__device__ inline void ps_eta_side(const cx<double> *U, size_t Vh, const int (*nb)[kPsSites],
+                                   const cx<double> *fS, const cx<double> *bS, size_t s, int par, int q,
+                                   cx<double> c[3]) {
+  const int site = threadIdx.x & 63;
+  if (q < 2) {
+    const cx<double> *u = ps_link_at(U, Vh, size_t(nb[2 * MU + 1][site]), par ^ 1, MU);  // U_mu(y - mu)
+    if (q == 0) PsHalf<MU, true, 0>::eta_side(u, Vh, bS + site, c);
+    else PsHalf<MU, true, 1>::eta_side(u, Vh, bS + site, c);
+  } else {
+    const cx<double> *u = ps_link_at(U, Vh, s, par, MU);  // U_mu(y)
+    if (q == 2) PsHalf<MU, false, 0>::eta_side(u, Vh, fS + site, c);
+    else PsHalf<MU, false, 1>::eta_side(u, Vh, fS + site, c);
   }
 }
 
-// Workgroup order: the variant varies fastest, then the right-hand side,
-// within one XCD's contiguous range of logical workgroups (hardware
-// workgroup h runs on XCD h % 8), so the nv workgroups of one chunk of one
-// right-hand side run side by side on one XCD and read its eta and x from
-// that XCD's L2, and the nv * nrhs workgroups of one chunk its links (links
-// are as many bytes as one right-hand side's three fields).  Each workgroup
-// is the estimator of its variant alone.
-template <bool XT>
+template <int MU>
+__device__ inline cx<double> ps_term(const cx<double> c[3], const cx<double> *dS, int q, double kappa) {
+  const int site = threadIdx.x & 63;
+  if (q == 0) return -kappa * PsHalf<MU, true, 0>::term(c, dS + site);
+  if (q == 1) return -kappa * PsHalf<MU, true, 1>::term(c, dS + site);
+  if (q == 2) return kappa * PsHalf<MU, false, 0>::term(c, dS + site);
+  return kappa * PsHalf<MU, false, 1>::term(c, dS + site);
+}
+
+// Workgroup order: the right-hand side varies fastest within one XCD's
+// contiguous range of logical workgroups (hardware workgroup h runs on XCD
+// h % 8), so the nrhs workgroups of one chunk of sites run back to back on
+// one XCD and read its links from that XCD's L2 (links are as many bytes as
+// one right-hand side's three fields).  Variant v of the launch is variant
+// v0 + v of the call.
+template <int NV>
 __global__ void __launch_bounds__(kBlock)
     k_estimate_ps(Geom g, const cx<double> *__restrict__ U, double kappa,
-                  const cx<double> *__restrict__ eta, const cx<double> *__restrict__ x, XtSet xts, int nv,
+                  const cx<double> *__restrict__ eta, const cx<double> *__restrict__ x, XtSet xts, int v0,
                   int nch, int nrhs, int xq, double *__restrict__ out) {
-  __shared__ double sh[2 * kNumPS][kWaves];
-  __shared__ cx<double> eS[kPsArr], fS[kPsArr], bS[kPsArr];
+  __shared__ double sh[NV * 2 * kNumPS][kWaves];
+  __shared__ cx<double> fS[kPsArr], bS[kPsArr], dS[kPsArr];
   __shared__ int nb[2 * kNumPS + 1][kPsSites];  // neighbour site indices [2 mu + backward]; the sites
   const int L = int(blockIdx.x % 8) * xq + int(blockIdx.x / 8);
-  if (L >= g.L[3] * nch * nrhs * nv) return;  // whole workgroup: padding of the grid
-  const int var = L % nv, r = (L / nv) % nrhs, tch = L / (nv * nrhs);
-  const cx<double> *__restrict__ xt = xts.p[var];
+  if (L >= g.L[3] * nch * nrhs) return;  // whole workgroup: padding of the grid
+  const int r = L % nrhs, tch = L / nrhs;
   const int t = tch / nch, ch = tch % nch;
   const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
   const int Vs = Lx * Ly * Lz;
@@ -249,44 +264,96 @@ __global__ void __launch_bounds__(kBlock)
   const size_t base = size_t(r) * size_t(g.V) * 12;
   eta += base;
   x += base;
-  if (XT) xt += base;
-  double acc[2 * kNumPS] = {};
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    if (xts.p[v]) xts.p[v] += base;
+  const int q = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  double acc[NV][2 * kNumPS] = {};
   for (int i0 = ch * kPsSites; i0 < Vs; i0 += nch * kPsSites) {
     const int site = threadIdx.x & 63;
     const int i = i0 + site;
     const bool on = i < Vs;
-    const int c[4] = {i % Lx, (i / Lx) % Ly, i / (Lx * Ly), t};
+    const int c4[4] = {i % Lx, (i / Lx) % Ly, i / (Lx * Ly), t};
     const size_t s = size_t(t) * Vs + i;
-    const int par = (c[0] + c[1] + c[2] + t) & 1;
-    __syncthreads();  // the previous chunk's reads of eS and nb are done
+    const int par = (c4[0] + c4[1] + c4[2] + t) & 1;
+    __syncthreads();  // the previous chunk's reads of nb and dS are done
     {
       // wave q: the forward and backward neighbours of the sites along mu = q
-      const int q = threadIdx.x >> 6;
       const int st = q == 0 ? 1 : q == 1 ? Lx : q == 2 ? Lx * Ly : Vs;
-      const int Lm = g.L[q], cm = c[q];
+      const int Lm = g.L[q], cm = c4[q];
       nb[2 * q][site] = on ? int(cm + 1 == Lm ? s - size_t(st) * (Lm - 1) : s + st) : -1;
       nb[2 * q + 1][site] = on ? int(cm == 0 ? s + size_t(st) * (Lm - 1) : s - st) : -1;
       if (q == 0) nb[2 * kNumPS][site] = on ? int(s) : -1;
     }
-    __syncthreads();
-    ps_stage<false>(eS, eta, static_cast<const cx<double> *>(nullptr), nb[2 * kNumPS]);
-    ps_dir<0, XT>(U, Vh, kappa, x, xt, nb, eS, fS, bS, s, par, on, acc[0], acc[1]);
-    ps_dir<1, XT>(U, Vh, kappa, x, xt, nb, eS, fS, bS, s, par, on, acc[2], acc[3]);
-    ps_dir<2, XT>(U, Vh, kappa, x, xt, nb, eS, fS, bS, s, par, on, acc[4], acc[5]);
-    ps_dir<3, XT>(U, Vh, kappa, x, xt, nb, eS, fS, bS, s, par, on, acc[6], acc[7]);
+    // the colour vectors of the four directions
+    cx<double> c[kNumPS][3];
+#pragma unroll
+    for (int mu = 0; mu < kNumPS; ++mu) {
+      __syncthreads();  // nb written; the previous direction's reads of fS, bS done
+      ps_stage(fS, eta, nullptr, nb[2 * mu]);
+      asm volatile("" ::: "memory");  // the backward loads after the forward ones (fewer registers live)
+      ps_stage(bS, eta, nullptr, nb[2 * mu + 1]);
+      __syncthreads();
+      if (on) {
+        if (mu == 0) ps_eta_side<0>(U, Vh, nb, fS, bS, s, par, q, c[0]);
+        else if (mu == 1) ps_eta_side<1>(U, Vh, nb, fS, bS, s, par, q, c[1]);
+        else if (mu == 2) ps_eta_side<2>(U, Vh, nb, fS, bS, s, par, q, c[2]);
+        else ps_eta_side<3>(U, Vh, nb, fS, bS, s, par, q, c[3]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (v > 0) __syncthreads();  // the previous variant's reads of dS are done
+      ps_stage(dS, x, xts.p[v], nb[2 * kNumPS]);
+      __syncthreads();
+      if (on) {
+        const cx<double> t0 = ps_term<0>(c[0], dS, q, kappa), t1 = ps_term<1>(c[1], dS, q, kappa);
+        const cx<double> t2 = ps_term<2>(c[2], dS, q, kappa), t3 = ps_term<3>(c[3], dS, q, kappa);
+        acc[v][0] += t0.re;
+        acc[v][1] += t0.im;
+        acc[v][2] += t1.re;
+        acc[v][3] += t1.im;
+        acc[v][4] += t2.re;
+        acc[v][5] += t2.im;
+        acc[v][6] += t3.re;
+        acc[v][7] += t3.im;
+      }
+    }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < 2 * kNumPS; ++k) acc[k] = wave_sum(acc[k]);
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int k = 0; k < 2 * kNumPS; ++k) acc[v][k] = wave_sum(acc[v][k]);
   if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < 2 * kNumPS; ++k) sh[k][wave] = acc[k];
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int k = 0; k < 2 * kNumPS; ++k) sh[v * 2 * kNumPS + k][wave] = acc[v][k];
   __syncthreads();
-  if (threadIdx.x < 2 * kNumPS) {
-    double v = 0;
-    for (int w = 0; w < kWaves; ++w) v += sh[threadIdx.x][w];
-    const int m = threadIdx.x / 2, part = threadIdx.x % 2;
-    out[((((size_t(xts.slot[var]) * nrhs + r) * kNumOps + kNumTheta + m) * Lt + t) * nch + ch) * 2 + part] = v;
+  // directions x, y, z: all four waves' sums at this timeslice; t: the
+  // forward waves' (0, 1) at t - 1 in slot 8, the backward waves' (2, 3) at
+  // t + 1 in slot 9
+  if (threadIdx.x < NV * (2 * kNumPS + 2)) {
+    const int v = threadIdx.x / (2 * kNumPS + 2), k = threadIdx.x % (2 * kNumPS + 2);
+    const int m = k / 2, part = k % 2;  // m = 4: the backward t terms
+    const double *row = sh[v * 2 * kNumPS + 2 * (m < kNumPS ? m : kNumPS - 1) + part];
+    double sum;
+    int slot, trow;
+    if (m < kNumPS - 1) {
+      sum = ((row[0] + row[1]) + row[2]) + row[3];
+      slot = kNumTheta + m;
+      trow = t;
+    } else if (m == kNumPS - 1) {
+      sum = row[0] + row[1];
+      slot = kNumOps - 1;
+      trow = t == 0 ? Lt - 1 : t - 1;
+    } else {
+      sum = row[2] + row[3];
+      slot = kNumOps;
+      trow = t + 1 == Lt ? 0 : t + 1;
+    }
+    out[((((size_t(v0 + v) * nrhs + r) * kOpSlots + slot) * Lt + trow) * nch + ch) * 2 + part] = sum;
   }
 }
 
@@ -322,13 +389,18 @@ int estimate_chunks(const Geom &g, int nrhs, size_t cap_doubles) {
   const int Lt = g.L[3], Vs = g.V / Lt;
   int nch = std::max(1, std::min((Vs + kBlock / 4 - 1) / (kBlock / 4), (2048 + Lt * nrhs - 1) / (Lt * nrhs)));
   if (cap_doubles)
-    nch = std::max(1, std::min<int>(nch, int(cap_doubles / (size_t(nrhs) * kNumOps * Lt * 2))));
+    nch = std::max(1, std::min<int>(nch, int(cap_doubles / (size_t(nrhs) * kOpSlots * Lt * 2))));
   return nch;
 }
 
-// Variants per launch of the local kernel (its per-lane sums grow by 10
-// doubles per variant).
-constexpr int kLocalGroup = 3;
+// Variants per launch.  The local kernel's per-lane sums grow by 10 doubles
+// per variant, and at 24^3 x 32 with 16 right-hand sides groups of three are
+// fastest (2.2 ms for six variants, 2.6 in pairs, 2.4 all at once).  The
+// point-split kernel's eta side (neighbour stagings and links, 2.5 ms) is
+// shared by the variants of a launch, each adding 0.6 ms: all six in one
+// launch (6.0 ms) beat three (8.9) or two (11.9) despite the occupancy its
+// registers leave.
+constexpr int kLocalGroup = 3, kPsGroup = 6;
 
 template <int NV>
 void launch_local(lqcd_ctx *c, const void *eta, const void *x, const XtSet &xts, int v0, int nrhs, double *d,
@@ -341,17 +413,15 @@ void launch_local(lqcd_ctx *c, const void *eta, const void *x, const XtSet &xts,
   LQCD_HIP(hipGetLastError());
 }
 
-// The point-split kernel over the n variants of xts, all with (XT) or all
-// without a subtracted vector.
-template <bool XT>
-void launch_ps(lqcd_ctx *c, const void *eta, const void *x, const XtSet &xts, int n, int nrhs, double *d,
+template <int NV>
+void launch_ps(lqcd_ctx *c, const void *eta, const void *x, const XtSet &xts, int v0, int nrhs, double *d,
                int nch) {
   const Geom &g = c->g;
   const int Lt = g.L[3];
-  const int xq = (Lt * nch * nrhs * n + 7) / 8;  // logical workgroups per XCD (grid padded to 8 xq)
-  hipLaunchKernelGGL(k_estimate_ps<XT>, dim3(8 * xq), dim3(kBlock), 0, c->stream, g,
+  const int xq = (Lt * nch * nrhs + 7) / 8;  // logical workgroups per XCD (grid padded to 8 xq)
+  hipLaunchKernelGGL(k_estimate_ps<NV>, dim3(8 * xq), dim3(kBlock), 0, c->stream, g,
                      static_cast<const cx<double> *>(c->U64.ptr), c->kappa, static_cast<const cx<double> *>(eta),
-                     static_cast<const cx<double> *>(x), xts, n, nch, nrhs, xq, d);
+                     static_cast<const cx<double> *>(x), xts, v0, nch, nrhs, xq, d);
   LQCD_HIP(hipGetLastError());
 }
 
@@ -367,7 +437,7 @@ void launch_ps(lqcd_ctx *c, const void *eta, const void *x, const XtSet &xts, in
   }
 
 // The estimator of nvar variants (subtracted vectors xt[v], corrections
-// corr[v]) with its partial sums in d (at least nvar * nrhs * kNumOps * Lt
+// corr[v]) with its partial sums in d (at least nvar * nrhs * kOpSlots * Lt
 // * nch * 2 doubles of device memory).  Variant v's outputs start at
 // est + v * nth * (Lt + 1) * 2, stderr_ + (same), samples + v * nrhs * nth
 // * (Lt + 1) * 2.
@@ -387,31 +457,20 @@ void estimate_with(lqcd_ctx *c, const int *thetas, int nth, const void *eta, con
       LQCD_EST_DISPATCH(launch_local, n, c, eta, x, group(v0, n), v0, nrhs, d, nch)
     }
   if (any_ps)
-    // one launch over the variants with a subtracted vector, one over those
-    // without
-    for (int with = 0; with < 2; ++with) {
-      int n = 0;
-      XtSet xts{};
-      for (int v = 0; v < nvar; ++v)
-        if ((xt[v] != nullptr) == bool(with)) {
-          xts.p[n] = static_cast<const cx<double> *>(xt[v]);
-          xts.slot[n++] = v;
-        }
-      if (!n) continue;
-      if (with) launch_ps<true>(c, eta, x, xts, n, nrhs, d, nch);
-      else launch_ps<false>(c, eta, x, xts, n, nrhs, d, nch);
+    for (int v0 = 0; v0 < nvar; v0 += kPsGroup) {
+      const int n = std::min(kPsGroup, nvar - v0);
+      LQCD_EST_DISPATCH(launch_ps, n, c, eta, x, group(v0, n), v0, nrhs, d, nch)
     }
-
   const int Lt = c->g.L[3];
-  std::vector<double> hc(size_t(nvar) * nrhs * kNumOps * Lt * nch * 2);
+  std::vector<double> hc(size_t(nvar) * nrhs * kOpSlots * Lt * nch * 2);
   LQCD_HIP(hipMemcpyAsync(hc.data(), d, hc.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   LQCD_HIP(hipStreamSynchronize(c->stream));
   const int W = Lt + 1;
   for (int var = 0; var < nvar; ++var) {
-    const double *hv = hc.data() + size_t(var) * nrhs * kNumOps * Lt * nch * 2;
+    const double *hv = hc.data() + size_t(var) * nrhs * kOpSlots * Lt * nch * 2;
     const double *cv = corr ? corr[var] : nullptr;
     double *ev = est + size_t(var) * nth * W * 2, *sv = stderr_ + size_t(var) * nth * W * 2;
-    std::vector<double> h(size_t(nrhs) * kNumOps * Lt * 2, 0.0);
+    std::vector<double> h(size_t(nrhs) * kOpSlots * Lt * 2, 0.0);
     for (size_t o = 0; o < h.size() / 2; ++o)
       for (int ch = 0; ch < nch; ++ch) {
         h[2 * o] += hv[(o * nch + ch) * 2];
@@ -423,8 +482,12 @@ void estimate_with(lqcd_ctx *c, const int *thetas, int nth, const void *eta, con
       for (int a = 0; a < nth; ++a) {
         cdouble tot = 0;
         for (int t = 0; t < Lt; ++t) {
-          size_t o = ((size_t(n) * kNumOps + thetas[a]) * Lt + t) * 2;
+          size_t o = ((size_t(n) * kOpSlots + thetas[a]) * Lt + t) * 2;
           cdouble v(h[o], h[o + 1]);
+          if (thetas[a] == kNumOps - 1) {  // point-split in t: its second slot
+            const size_t o2 = ((size_t(n) * kOpSlots + kNumOps) * Lt + t) * 2;
+            v += cdouble(h[o2], h[o2 + 1]);
+          }
           smp[(size_t(n) * nth + a) * W + t] = v;
           tot += v;
         }
@@ -492,7 +555,7 @@ extern "C" lqcd_status loop_estimate(lqcd_ctx *c, const int *thetas, int nth, co
     check_args(c, thetas, nth, eta, x, nrhs, est, stderr_, "loop_estimate");
     const int nch = estimate_chunks(c->g, nrhs, 0);
     double *d = static_cast<double *>(
-        c->red.ensure(size_t(nrhs) * kNumOps * c->g.L[3] * nch * 2 * sizeof(double)));
+        c->red.ensure(size_t(nrhs) * kOpSlots * c->g.L[3] * nch * 2 * sizeof(double)));
     estimate_with(c, thetas, nth, eta, x, &xt, 1, nrhs, &corr, est, stderr_, samples, d, nch);
   });
 }
@@ -507,7 +570,7 @@ extern "C" lqcd_status loop_estimate_multi(lqcd_ctx *c, const int *thetas, int n
                "loop_estimate_multi: %d variants (1..%d, with a list of subtracted vectors)", nvar, kMaxVar);
     const int nch = estimate_chunks(c->g, nrhs, 0);
     double *d = static_cast<double *>(
-        c->red.ensure(size_t(nvar) * nrhs * kNumOps * c->g.L[3] * nch * 2 * sizeof(double)));
+        c->red.ensure(size_t(nvar) * nrhs * kOpSlots * c->g.L[3] * nch * 2 * sizeof(double)));
     estimate_with(c, thetas, nth, eta, x, xt_list, nvar, nrhs, corr_list, est, stderr_, samples, d, nch);
   });
 }
@@ -517,7 +580,7 @@ extern "C" lqcd_status loop_estimate_noalloc(lqcd_ctx *c, const int *thetas, int
                                              double *est, double *stderr_, double *samples) {
   return guarded([&] {
     check_args(c, thetas, nth, eta, x, nrhs, est, stderr_, "loop_estimate_noalloc");
-    const size_t one = size_t(nrhs) * kNumOps * c->g.L[3] * 2;
+    const size_t one = size_t(nrhs) * kOpSlots * c->g.L[3] * 2;
     LQCD_CHECK(one <= kNoallocDoubles, LQCD_EINVAL,
                "loop_estimate_noalloc: %d right-hand sides x %d timeslices need %zu partial sums, more than "
                "the fixed scratch of %zu (use loop_estimate)",

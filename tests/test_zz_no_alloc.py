@@ -57,13 +57,13 @@ def test_noalloc_matches_loop_estimate(first, second):
 def test_noalloc_rejects_more_partial_sums_than_its_scratch():
     require_gpu()
     from paper_1903_06986_amd import lqcd
-    dims = (2, 2, 2, 64)      # Lt = 64: at most 455 right-hand sides fit
+    dims = (2, 2, 2, 64)      # Lt = 64, 10 partial-sum slots: at most 409 right-hand sides fit
     ctx, U = context(dims, 0.3, 5, 0.12)
-    n = 456
+    n = 410
     eta = to_gpu(z4_noise(3, dims, 0, n))
     say("loop_estimate_noalloc oversize", dims, n)
     code, _, _, _ = _call(lqcd.lib().loop_estimate_noalloc, ctx, eta, eta, None, np.zeros((9, 64), complex))
     assert code == 1 and b"scratch" in lqcd.lib().lqcd_last_error()
-    code, _, _, _ = _call(lqcd.lib().loop_estimate_noalloc, ctx, eta[:455], eta[:455], None,
+    code, _, _, _ = _call(lqcd.lib().loop_estimate_noalloc, ctx, eta[:409], eta[:409], None,
                           np.zeros((9, 64), complex))
     assert code == 0

@@ -181,9 +181,8 @@ class Path:
         x, _, st = ctx.gmresdr_solve(eta, op="schur", m=c["m"], k=c["k"], tol=a.tol, inner=inner,
                                      inner_tol=a.inner_tol, rhs_block=B, max_cycles=a.max_cycles,
                                      defl=self.defl, proj_m=a.proj_m)
-        xt_ps, _ = ctx.pert_subtract(c["pert_order"], eta, THETAS, want_corr=False)
-        xt_poly, _, _, _ = ctx.poly_subtract(c["poly_degree"], eta, b=None, coeffs=self.cpoly,
-                                             thetas=THETAS, want_corr=False)
+        # the PS and POLY vectors from one chain of powers of kappa P
+        xt_ps, xt_poly = ctx.poly_subtract_multi(eta, [self.ones, self.cpoly])
         xt_hf, corr_hf, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=torch.zeros_like(eta),
                                                 mode=lqcd.DEFL_HFES, thetas=THETAS)
         xt_hfps, corr_hfps, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=xt_ps.clone(), corr=self.corr_pert,

@@ -260,6 +260,21 @@ lqcd_status poly_subtract(lqcd_ctx *ctx, int degree, const void *b, double *coef
                           double *a_host, const int *thetas_host, int ntheta,
                           const void *eta, void *xt, int nrhs, double *trace_corr_host);
 
+/* Several polynomial subtraction vectors of the same noise at once (the
+ * vectors of pert_subtract, whose coefficients are all 1, and of
+ * poly_subtract; Sec. 5.1 Eq. (31), Sec. 5.2 Eq. (40)):
+ *   xt_list[a][n] = sum_{j=0}^{degree} coeffs[a][j] (kappa P)^j eta[n],
+ * with the powers (kappa P)^j eta formed once for all a and summed in order
+ * of j (the single-polynomial calls use Horner's rule, so the vectors agree
+ * with theirs to rounding).  coeffs_host: complex128 [npoly][degree+1] (a
+ * polynomial of lower degree pads with zeros); eta: device LEX [nrhs];
+ * xt_list: host array [npoly] of device LEX pointers [nrhs], written.  The
+ * trace corrections are those of pert_subtract / poly_subtract (once per
+ * configuration).  Workspace: degree+1 full FP64 fields per block of 16
+ * right-hand sides.  EINVAL unless 1 <= npoly <= 4 and 0 <= degree <= 7. */
+lqcd_status poly_subtract_multi(lqcd_ctx *ctx, int npoly, int degree, const double *coeffs_host,
+                                const void *eta, void *const *xt_list, int nrhs);
+
 /* Operator codes (thetas_host arrays): 0 = scalar (Theta = 1), 1..4 = local
  * vector g_1..g_4 (Table 2), 5..8 = point-split vector in direction mu =
  * 0..3 (Table 2): Theta(mu) psi(x) = kappa [ (1 + g_mu) U_mu(x - mu)^+

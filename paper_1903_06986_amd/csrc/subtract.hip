@@ -471,6 +471,49 @@ void check_thetas(const int *th, int nth) {
     LQCD_CHECK(th[a] >= 0 && th[a] < kNumOps, LQCD_EINVAL, "operator code %d outside 0..8", th[a]);
 }
 
+// Several polynomials in kappa P applied to the same noise: the powers
+// P_j = (kappa P)^j eta are formed once (one hopping step each) and kept,
+// and one pass combines them into every polynomial's vector, written in the
+// lexicographic layout.
+constexpr int kMaxPolys = 4;
+struct PolySet {
+  cx<double> c[kMaxPolys][kMaxOrder + 1];
+  cx<double> *out[kMaxPolys];
+};
+
+// out_a (lex) = sum_{j < d1} c[a][j] P_j for the powers P_j (even/odd, blk
+// apart; right-hand side r at r fl) of one block; thread = lex site s of
+// right-hand side blockIdx.y.
+template <int NP>
+__global__ void __launch_bounds__(kBlock)
+    k_poly_lex(Geom g, const cx<double> *__restrict__ P, size_t fl, size_t blk, int d1, PolySet ps) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const size_t rhs = blockIdx.y;
+  const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
+  const int x = s % Lx, y = (s / Lx) % Ly, z = (s / (Lx * Ly)) % Lz, t = s / (Lx * Ly * Lz);
+  const int par = (x + y + z + t) & 1;
+  const size_t Vh = g.Vh;
+  const cx<double> *src = P + rhs * fl + par * 12 * Vh + (s >> 1);
+  const size_t o = (rhs * size_t(g.V) + s) * 12;
+  for (int k = 0; k < 12; ++k) {
+    cx<double> acc[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) acc[a] = mk(0.0, 0.0);
+    cx<double> v[kMaxOrder + 1];  // every power's component k in flight together
+#pragma unroll
+    for (int j = 0; j <= kMaxOrder; ++j)
+      if (j < d1) v[j] = ldc(src + j * blk + k * Vh);
+#pragma unroll
+    for (int j = 0; j <= kMaxOrder; ++j)
+      if (j < d1)
+#pragma unroll
+        for (int a = 0; a < NP; ++a) acc[a] = acc[a] + ps.c[a][j] * v[j];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) stc(ps.out[a] + o + k, acc[a]);
+  }
+}
+
 // xt (lex) = p(kappa P) eta (lex) for nrhs fields, in blocks.
 void apply_poly_lex(lqcd_ctx *c, const std::vector<cdouble> &coeffs, const void *eta, void *xt,
                     int nrhs) {
@@ -739,6 +782,46 @@ extern "C" lqcd_status poly_subtract(lqcd_ctx *c, int degree, const void *b, dou
     }
     apply_poly_lex(c, cc, eta, xt, nrhs);
     if (corr) poly_trace(c, cc, thetas, nth, corr);
+  });
+}
+
+extern "C" lqcd_status poly_subtract_multi(lqcd_ctx *c, int npoly, int degree, const double *coeffs_host,
+                                           const void *eta, void *const *xt_list, int nrhs) {
+  return guarded([&] {
+    LQCD_CHECK(c && coeffs_host, LQCD_EINVAL, "poly_subtract_multi: null argument");
+    LQCD_CHECK(npoly >= 1 && npoly <= kMaxPolys, LQCD_EINVAL, "poly_subtract_multi: %d polynomials (1..%d)",
+               npoly, kMaxPolys);
+    LQCD_CHECK(degree >= 0 && degree <= kMaxOrder, LQCD_EINVAL,
+               "poly_subtract_multi: degree %d outside 0..%d", degree, kMaxOrder);
+    LQCD_CHECK(nrhs >= 0, LQCD_EINVAL, "poly_subtract_multi: negative count");
+    if (nrhs == 0) return;
+    LQCD_CHECK(eta && xt_list, LQCD_EINVAL, "poly_subtract_multi: null field");
+    for (int a = 0; a < npoly; ++a) LQCD_CHECK(xt_list[a], LQCD_EINVAL, "poly_subtract_multi: null field");
+    const int d1 = degree + 1;
+    PolySet ps{};
+    for (int a = 0; a < npoly; ++a)
+      for (int j = 0; j < d1; ++j)
+        ps.c[a][j] = mk(coeffs_host[2 * (a * d1 + j)], coeffs_host[2 * (a * d1 + j) + 1]);
+    const size_t fl = full_len(c->g), hl = half_len(c->g);
+    for (int r0 = 0; r0 < nrhs; r0 += kSubBlock) {
+      const int nb = std::min(kSubBlock, nrhs - r0);
+      const size_t blk = fl * nb;
+      cx<double> *W = static_cast<cx<double> *>(c->ws[0].ensure(blk * d1 * sizeof(cx<double>)));
+      pack_eo<double>(c, static_cast<const cdouble *>(eta) + r0 * fl, W, nb, fl);
+      for (int j = 0; j < degree; ++j)
+        for (int p = 0; p < 2; ++p)
+          hop_half<double>(c, p, W + j * blk + (1 - p) * hl, nullptr, W + (j + 1) * blk + p * hl, cdouble(0, 0),
+                           c->kappa, false, false, nb, fl, 0, fl);
+      for (int a = 0; a < npoly; ++a) ps.out[a] = static_cast<cx<double> *>(xt_list[a]) + r0 * fl;
+      const dim3 grid(nblocks(c->g.V), nb);
+      switch (npoly) {
+        case 1: hipLaunchKernelGGL(k_poly_lex<1>, grid, dim3(kBlock), 0, c->stream, c->g, W, fl, blk, d1, ps); break;
+        case 2: hipLaunchKernelGGL(k_poly_lex<2>, grid, dim3(kBlock), 0, c->stream, c->g, W, fl, blk, d1, ps); break;
+        case 3: hipLaunchKernelGGL(k_poly_lex<3>, grid, dim3(kBlock), 0, c->stream, c->g, W, fl, blk, d1, ps); break;
+        default: hipLaunchKernelGGL(k_poly_lex<4>, grid, dim3(kBlock), 0, c->stream, c->g, W, fl, blk, d1, ps); break;
+      }
+      LQCD_HIP(hipGetLastError());
+    }
   });
 }
 

@@ -69,6 +69,7 @@ _SIGS = {
     "deflate_project": [_P, _P, _I, _I, _P, _I, _P, _I, _P, _P, _I, _P, _P],
     "pert_subtract": [_P, _I, _P, _I, _P, _P, _I, _P],
     "poly_subtract": [_P, _I, _P, _P, _P, _P, _I, _P, _P, _I, _P],
+    "poly_subtract_multi": [_P, _I, _I, _P, _P, _P, _I],
     "loop_estimate": [_P, _P, _I, _P, _P, _P, _I, _P, _P, _P, _P],
     "loop_estimate_noalloc": [_P, _P, _I, _P, _P, _P, _I, _P, _P, _P, _P],
     "loop_estimate_multi": [_P, _P, _I, _P, _P, _P, _I, _I, _P, _P, _P, _P],
@@ -366,6 +367,22 @@ class Context:
                                      _field(eta, n, 12 * self.V, "eta"), _field(xt, n, 12 * self.V, "xt"),
                                      n, corr.ctypes.data_as(_P), xi.ctypes.data_as(_P)))
         return xt, corr, xi
+
+    def poly_subtract_multi(self, eta, coeffs_list):
+        """p_a(kappa P) eta for each coefficient list (complex, lowest power
+        first; shorter lists pad with zeros) from one chain of powers.
+        Returns one new device field per polynomial."""
+        import torch
+        degree = max(len(c) for c in coeffs_list) - 1
+        cf = np.zeros((len(coeffs_list), degree + 1), dtype=np.complex128)
+        for a, c in enumerate(coeffs_list):
+            cf[a, :len(c)] = c
+        n = eta.shape[0]
+        outs = [torch.empty_like(eta) for _ in coeffs_list]
+        ptrs = (_P * len(outs))(*[_field(o, n, 12 * self.V, "xt") for o in outs])
+        _check(lib().poly_subtract_multi(self.handle, len(outs), degree, cf.ctypes.data_as(_P),
+                                         _field(eta, n, 12 * self.V, "eta"), ptrs, n))
+        return outs
 
     def loop_estimate(self, eta, x, xt=None, corr=None, thetas=(0, 1, 2, 3, 4), samples=False, noalloc=False):
         """noalloc: call loop_estimate_noalloc (partial sums in the library's

@@ -172,7 +172,6 @@ class Path:
         return p
 
     def step(self, inner):
-        import torch
         from paper_1903_06986_amd import lqcd
         c, a, ctx = self.cfg, self.args, self.ctx
         B, Q = a.rhs_block, c["n_hermitian"]
@@ -181,15 +180,16 @@ class Path:
         x, _, st = ctx.gmresdr_solve(eta, op="schur", m=c["m"], k=c["k"], tol=a.tol, inner=inner,
                                      inner_tol=a.inner_tol, rhs_block=B, max_cycles=a.max_cycles,
                                      defl=self.defl, proj_m=a.proj_m)
-        # the PS and POLY vectors from one chain of powers of kappa P
-        xt_ps, xt_poly = ctx.poly_subtract_multi(eta, [self.ones, self.cpoly])
-        xt_hf, corr_hf, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=torch.zeros_like(eta),
-                                                mode=lqcd.DEFL_HFES, thetas=THETAS)
-        xt_hfps, corr_hfps, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=xt_ps.clone(), corr=self.corr_pert,
-                                                    mode=lqcd.DEFL_EIGPOLY, coeffs=self.ones, thetas=THETAS)
-        xt_hfpoly, corr_hfpoly, _ = ctx.deflate_project(self.hdefl, Q, eta, xt=xt_poly.clone(),
-                                                        corr=self.corr_poly, mode=lqcd.DEFL_EIGPOLY,
-                                                        coeffs=self.cpoly, thetas=THETAS)
+        # the PS and POLY vectors from one chain of powers of kappa P, each
+        # written twice: once as it is, once as the base of its
+        # hermitian-forced variant
+        xt_ps, xt_poly, xt_hfps, xt_hfpoly = ctx.poly_subtract_multi(
+            eta, [self.ones, self.cpoly, self.ones, self.cpoly])
+        # the three hermitian-forced projections with one set of overlaps
+        (xt_hf, corr_hf), (xt_hfps, corr_hfps), (xt_hfpoly, corr_hfpoly) = ctx.deflate_project_multi(
+            self.hdefl, Q, eta, [(lqcd.DEFL_HFES, None, None, None),
+                                 (lqcd.DEFL_EIGPOLY, self.ones, xt_hfps, self.corr_pert),
+                                 (lqcd.DEFL_EIGPOLY, self.cpoly, xt_hfpoly, self.corr_poly)], THETAS)
         # the six estimates of this solve in one call (eta and x shared)
         names = ("NS", "PS", "POLY", "HFES", "HFPS", "HFPOLY")
         est = ctx.loop_estimate_multi(eta, x, [None, xt_ps, xt_poly, xt_hf, xt_hfps, xt_hfpoly],

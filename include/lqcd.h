@@ -237,6 +237,19 @@ lqcd_status deflate_project(lqcd_ctx *ctx, lqcd_defl *defl, int Q, lqcd_defl_mod
                             int ntheta, const void *eta, void *xt, int nrhs,
                             double *trace_corr_host, double *xi_inv_host);
 
+/* Several hermitian-forced projections of the same noise at once (modes
+ * HFES and EIGPOLY of deflate_project): variant v is deflate_project with
+ * mode modes[v], coefficients coeffs_list[v] (ncoeffs[v] complex128; read
+ * for EIGPOLY only), xt = xt_list[v] and trace_corr_host = corr_list[v]
+ * (corr_list NULL or an entry NULL: no correction), and its results equal
+ * that call's bit for bit; the overlaps e'_q^+ eta[n] are formed once for
+ * all variants.  EINVAL unless 1 <= nvar <= 4 and every mode is HFES or
+ * EIGPOLY. */
+lqcd_status deflate_project_multi(lqcd_ctx *ctx, lqcd_defl *defl, int Q, int nvar, const int *modes,
+                                  const double *const *coeffs_list, const int *ncoeffs, const int *thetas_host,
+                                  int ntheta, const void *eta, void *const *xt_list, int nrhs,
+                                  double *const *corr_list);
+
 /* Perturbative subtraction (Sec. 5.1, Eqs. (28)-(35)): xt[n] =
  * sum_{j=0}^{order} (kappa P)^j eta[n] (device LEX), and the exact trace
  * correction Tr_t(Theta sum_j (kappa P)^j) per timeslice (host complex128

@@ -692,6 +692,130 @@ void es_project(lqcd_ctx *c, lqcd_defl *d, int Q, const int *thetas, int nth, co
   }
 }
 
+// The weights w_q of a hermitian-forced projection (deflate_project, modes
+// HFES and EIGPOLY) on the eigenpairs of d, with the trace correction added
+// to corr (NULL: none) and 1/xi'_q written to xi_inv_host (NULL: not).
+std::vector<cdouble> hf_weights(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_defl_mode mode, const double *coeffs_host,
+                                int ncoeff, const int *thetas, int nth, double *corr, double *xi_inv_host) {
+  const size_t fl = full_len(c->g);
+  const cx<double> *E = d->E.as<cx<double>>();
+  const int Lt = c->g.L[3];
+  std::vector<cdouble> w(Q), xi(Q, 0.0);
+  for (int q = 0; q < Q; ++q) w[q] = 1.0 / d->lam[q];
+  if (mode == LQCD_DEFL_EIGPOLY) {
+    // 1/xi'_q = e'^+ g5 p(kappa P) e'  (Eq. (69) with M'_poly^{-1} = g5 p),
+    // computed once per polynomial and kept with the eigenpairs
+    std::vector<cdouble> cc(ncoeff);
+    for (int j = 0; j < ncoeff; ++j) cc[j] = cdouble(coeffs_host[2 * j], coeffs_host[2 * j + 1]);
+    std::lock_guard<std::mutex> lk(d->fill_mu);
+    bool found = false;
+    for (auto &e : d->xi_cache)
+      if (e.first == cc) {
+        xi = e.second;
+        found = true;
+      }
+    if (!found) {
+      cx<double> *A = static_cast<cx<double> *>(c->ws[1].ensure(fl * Q * sizeof(cx<double>)));
+      cx<double> *B = static_cast<cx<double> *>(c->ws[2].ensure(fl * Q * sizeof(cx<double>)));
+      cx<double> *Y = horner(c, cc, E, A, B, Q);
+      size_t tot = 2 * 6 * size_t(c->g.Vh) * Q;
+      hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(tot)), dim3(kBlock), 0, c->stream, Y, size_t(c->g.Vh), fl, Q);
+      LQCD_HIP(hipGetLastError());
+      cdouble *Cd = static_cast<cdouble *>(c->ws[5].ensure(size_t(Q) * sizeof(cdouble)));
+      // xi_inv[q] = <E_q, Y_q>: a batched dot with each vector its own basis of one
+      multi_dot<double>(c, E, fl, fl, 1, Y, fl, fl, Q, Cd, 1);
+      d2h(c, xi.data(), Cd, Q * sizeof(cdouble));
+      d->xi_cache.emplace_back(cc, xi);
+    }
+    for (int q = 0; q < Q; ++q) w[q] -= xi[q];
+  }
+  if (xi_inv_host)
+    for (int q = 0; q < Q; ++q) {
+      xi_inv_host[2 * q] = xi[q].real();
+      xi_inv_host[2 * q + 1] = xi[q].imag();
+    }
+  // trace correction: sum_q w_q e_q^+ Theta g5 e_q per timeslice, from the
+  // per-mode bilinears (computed once per set of eigenpairs)
+  if (corr && nth > 0) {
+    std::lock_guard<std::mutex> lk(d->fill_mu);
+    if (d->bil.empty()) {
+      d->bil.assign(size_t(Q) * kNumOps * Lt, 0.0);
+      cdouble one(1, 0);
+      cdouble *wd = static_cast<cdouble *>(c->ws[6].ensure(sizeof(cdouble)));
+      h2d(c, wd, &one, sizeof(cdouble));
+      cx<double> *site = static_cast<cx<double> *>(c->ws[7].ensure(size_t(kNumOps) * c->g.V * sizeof(cdouble)));
+      DevBuf tmp;
+      for (int q = 0; q < Q; ++q) {
+        hipLaunchKernelGGL(k_eig_bilinear, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g,
+                           E + size_t(q) * fl, E + size_t(q) * fl, fl, 1,
+                           reinterpret_cast<const cx<double> *>(wd), site, 1);
+        LQCD_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_eig_bilinear_ps, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g,
+                           static_cast<const cx<double> *>(c->U64.ptr), c->kappa, E + size_t(q) * fl,
+                           E + size_t(q) * fl, site + size_t(kNumTheta) * c->g.V, 1);
+        LQCD_HIP(hipGetLastError());
+        std::vector<cdouble> ts = timeslice_rows(c, site, kNumOps, tmp);
+        std::copy(ts.begin(), ts.end(), d->bil.begin() + size_t(q) * kNumOps * Lt);
+      }
+    }
+    for (int a = 0; a < nth; ++a)
+      for (int t = 0; t < Lt; ++t) {
+        cdouble v = 0;
+        for (int q = 0; q < Q; ++q) v += w[q] * d->bil[(size_t(q) * kNumOps + thetas[a]) * Lt + t];
+        corr[2 * (a * Lt + t)] += v.real();
+        corr[2 * (a * Lt + t) + 1] += v.imag();
+      }
+  }
+  return w;
+}
+
+// xt[v] += g5 E (w[v] .* (E^H eta)) for nvar weight sets, with E^H eta formed
+// once per block of right-hand sides.
+void hf_update(lqcd_ctx *c, lqcd_defl *d, int Q, const void *eta, int nvar, void *const *xt,
+               const std::vector<cdouble> *w, int nrhs) {
+  const size_t fl = full_len(c->g);
+  const cx<double> *E = d->E.as<cx<double>>();
+  // xt += g5 E (w .* (E^H eta)), on the lexicographic copies of E and g5 E
+  // (made once per set of eigenpairs), so that eta is read and xt updated
+  // in place: one pass over the modes for the dots, one for the update
+  const size_t Vh = size_t(c->g.Vh);
+  std::unique_lock<std::mutex> lk(d->fill_mu);
+  if (d->lex_Q != Q) {
+    cx<double> *El = static_cast<cx<double> *>(d->Elex.ensure(fl * Q * sizeof(cx<double>)));
+    cx<double> *Gl = static_cast<cx<double> *>(d->G5Elex.ensure(fl * Q * sizeof(cx<double>)));
+    cx<double> *T = static_cast<cx<double> *>(c->ws[1].ensure(fl * Q * sizeof(cx<double>)));
+    unpack_eo<double>(c, E, El, Q, fl);
+    LQCD_HIP(hipMemcpyAsync(T, E, fl * Q * sizeof(cx<double>), hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(2 * 6 * Vh * Q)), dim3(kBlock), 0, c->stream, T, Vh, fl, Q);
+    LQCD_HIP(hipGetLastError());
+    unpack_eo<double>(c, T, Gl, Q, fl);
+    LQCD_HIP(hipStreamSynchronize(c->stream));
+    d->lex_Q = Q;
+  }
+  lk.unlock();
+  const cx<double> *El = d->Elex.as<cx<double>>(), *Gl = d->G5Elex.as<cx<double>>();
+  cdouble *wd = static_cast<cdouble *>(c->ws[6].ensure(size_t(Q) * nvar * sizeof(cdouble)));
+  std::vector<cdouble> wh(size_t(Q) * nvar);
+  for (int v = 0; v < nvar; ++v) std::copy(w[v].begin(), w[v].end(), wh.begin() + size_t(v) * Q);
+  h2d(c, wd, wh.data(), wh.size() * sizeof(cdouble));
+  const int blk = kSubBlock;
+  for (int r0 = 0; r0 < nrhs; r0 += blk) {
+    const int nb = std::min(blk, nrhs - r0);
+    // [E^H eta | w[0] .* E^H eta | w[1] .* ...]: the overlaps, then one scaled copy per weight set
+    cdouble *Cd = static_cast<cdouble *>(c->ws[5].ensure(size_t(Q) * nb * (nvar + 1) * sizeof(cdouble)));
+    gemm_tn<double>(c, El, fl, Q, static_cast<const cdouble *>(eta) + r0 * fl, fl, nb, fl, Cd, Q);
+    for (int v = 0; v < nvar; ++v) {
+      cdouble *Cv = Cd + size_t(Q) * nb * (v + 1);
+      LQCD_HIP(hipMemcpyAsync(Cv, Cd, size_t(Q) * nb * sizeof(cdouble), hipMemcpyDeviceToDevice, c->stream));
+      hipLaunchKernelGGL(k_scale_rows, dim3(nblocks(size_t(Q) * nb)), dim3(kBlock), 0, c->stream,
+                         reinterpret_cast<cx<double> *>(Cv), reinterpret_cast<const cx<double> *>(wd) + size_t(v) * Q,
+                         Q, nb);
+      LQCD_HIP(hipGetLastError());
+      gemm_nn<double>(c, Gl, fl, 0, Q, Cv, Q, 0, static_cast<cdouble *>(xt[v]) + r0 * fl, fl, 0, nb, fl, 1, 1.0);
+    }
+  }
+}
+
 }  // namespace
 
 }  // namespace lqcd
@@ -825,6 +949,39 @@ extern "C" lqcd_status poly_subtract_multi(lqcd_ctx *c, int npoly, int degree, c
   });
 }
 
+extern "C" lqcd_status deflate_project_multi(lqcd_ctx *c, lqcd_defl *d, int Q, int nvar, const int *modes,
+                                             const double *const *coeffs_list, const int *ncoeffs,
+                                             const int *thetas, int nth, const void *eta, void *const *xt_list,
+                                             int nrhs, double *const *corr_list) {
+  return guarded([&] {
+    LQCD_CHECK(c && d && modes, LQCD_EINVAL, "deflate_project_multi: null argument");
+    LQCD_CHECK(nvar >= 1 && nvar <= kMaxPolys, LQCD_EINVAL, "deflate_project_multi: %d variants (1..%d)", nvar,
+               kMaxPolys);
+    LQCD_CHECK(nrhs >= 0 && (nrhs == 0 || (eta && xt_list)), LQCD_EINVAL, "deflate_project_multi: null field");
+    for (int v = 0; v < nvar; ++v) {
+      LQCD_CHECK(modes[v] == LQCD_DEFL_HFES || modes[v] == LQCD_DEFL_EIGPOLY, LQCD_EINVAL,
+                 "deflate_project_multi: variant %d: mode must be HFES or EIGPOLY", v);
+      LQCD_CHECK(modes[v] != LQCD_DEFL_EIGPOLY || (coeffs_list && ncoeffs && coeffs_list[v] && ncoeffs[v] >= 1 &&
+                                                   ncoeffs[v] <= kMaxOrder + 1),
+                 LQCD_EINVAL, "deflate_project_multi: variant %d: EIGPOLY needs 1..%d coefficients", v,
+                 kMaxOrder + 1);
+      LQCD_CHECK(nrhs == 0 || xt_list[v], LQCD_EINVAL, "deflate_project_multi: variant %d: null field", v);
+    }
+    for (int i = 0; i < 4; ++i)
+      LQCD_CHECK(d->dims[i] == c->g.L[i], LQCD_EINVAL, "deflate_project_multi: deflation space of another lattice");
+    LQCD_CHECK(d->kappa == c->kappa, LQCD_EINVAL, "deflate_project_multi: deflation space of another kappa");
+    check_thetas(thetas, nth);
+    defl_eigpairs(c, d, Q);
+    std::vector<std::vector<cdouble>> w(nvar);
+    for (int v = 0; v < nvar; ++v) {
+      const bool poly = modes[v] == LQCD_DEFL_EIGPOLY;
+      w[v] = hf_weights(c, d, Q, lqcd_defl_mode(modes[v]), poly ? coeffs_list[v] : nullptr, poly ? ncoeffs[v] : 0,
+                        thetas, nth, corr_list ? corr_list[v] : nullptr, nullptr);
+    }
+    hf_update(c, d, Q, eta, nvar, xt_list, w.data(), nrhs);
+  });
+}
+
 extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_defl_mode mode,
                                        const double *coeffs_host, int ncoeff, const int *thetas,
                                        int nth, const void *eta, void *xt, int nrhs,
@@ -850,105 +1007,8 @@ extern "C" lqcd_status deflate_project(lqcd_ctx *c, lqcd_defl *d, int Q, lqcd_de
       return;
     }
     defl_eigpairs(c, d, Q);
-    const size_t fl = full_len(c->g);
-    const cx<double> *E = d->E.as<cx<double>>();
-    const int Lt = c->g.L[3];
-    std::vector<cdouble> w(Q), xi(Q, 0.0);
-    for (int q = 0; q < Q; ++q) w[q] = 1.0 / d->lam[q];
-    if (mode == LQCD_DEFL_EIGPOLY) {
-      // 1/xi'_q = e'^+ g5 p(kappa P) e'  (Eq. (69) with M'_poly^{-1} = g5 p),
-      // computed once per polynomial and kept with the eigenpairs
-      std::vector<cdouble> cc(ncoeff);
-      for (int j = 0; j < ncoeff; ++j) cc[j] = cdouble(coeffs_host[2 * j], coeffs_host[2 * j + 1]);
-      std::lock_guard<std::mutex> lk(d->fill_mu);
-      bool found = false;
-      for (auto &e : d->xi_cache)
-        if (e.first == cc) {
-          xi = e.second;
-          found = true;
-        }
-      if (!found) {
-        cx<double> *A = static_cast<cx<double> *>(c->ws[1].ensure(fl * Q * sizeof(cx<double>)));
-        cx<double> *B = static_cast<cx<double> *>(c->ws[2].ensure(fl * Q * sizeof(cx<double>)));
-        cx<double> *Y = horner(c, cc, E, A, B, Q);
-        size_t tot = 2 * 6 * size_t(c->g.Vh) * Q;
-        hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(tot)), dim3(kBlock), 0, c->stream, Y, size_t(c->g.Vh), fl, Q);
-        LQCD_HIP(hipGetLastError());
-        cdouble *Cd = static_cast<cdouble *>(c->ws[5].ensure(size_t(Q) * sizeof(cdouble)));
-        // xi_inv[q] = <E_q, Y_q>: a batched dot with each vector its own basis of one
-        multi_dot<double>(c, E, fl, fl, 1, Y, fl, fl, Q, Cd, 1);
-        d2h(c, xi.data(), Cd, Q * sizeof(cdouble));
-        d->xi_cache.emplace_back(cc, xi);
-      }
-      for (int q = 0; q < Q; ++q) w[q] -= xi[q];
-    }
-    if (xi_inv_host)
-      for (int q = 0; q < Q; ++q) {
-        xi_inv_host[2 * q] = xi[q].real();
-        xi_inv_host[2 * q + 1] = xi[q].imag();
-      }
-    // trace correction: sum_q w_q e_q^+ Theta g5 e_q per timeslice, from the
-    // per-mode bilinears (computed once per set of eigenpairs)
-    if (corr && nth > 0) {
-      std::lock_guard<std::mutex> lk(d->fill_mu);
-      if (d->bil.empty()) {
-        d->bil.assign(size_t(Q) * kNumOps * Lt, 0.0);
-        cdouble one(1, 0);
-        cdouble *wd = static_cast<cdouble *>(c->ws[6].ensure(sizeof(cdouble)));
-        h2d(c, wd, &one, sizeof(cdouble));
-        cx<double> *site = static_cast<cx<double> *>(c->ws[7].ensure(size_t(kNumOps) * c->g.V * sizeof(cdouble)));
-        DevBuf tmp;
-        for (int q = 0; q < Q; ++q) {
-          hipLaunchKernelGGL(k_eig_bilinear, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g,
-                             E + size_t(q) * fl, E + size_t(q) * fl, fl, 1,
-                             reinterpret_cast<const cx<double> *>(wd), site, 1);
-          LQCD_HIP(hipGetLastError());
-          hipLaunchKernelGGL(k_eig_bilinear_ps, dim3(nblocks(c->g.V)), dim3(kBlock), 0, c->stream, c->g,
-                             static_cast<const cx<double> *>(c->U64.ptr), c->kappa, E + size_t(q) * fl,
-                             E + size_t(q) * fl, site + size_t(kNumTheta) * c->g.V, 1);
-          LQCD_HIP(hipGetLastError());
-          std::vector<cdouble> ts = timeslice_rows(c, site, kNumOps, tmp);
-          std::copy(ts.begin(), ts.end(), d->bil.begin() + size_t(q) * kNumOps * Lt);
-        }
-      }
-      for (int a = 0; a < nth; ++a)
-        for (int t = 0; t < Lt; ++t) {
-          cdouble v = 0;
-          for (int q = 0; q < Q; ++q) v += w[q] * d->bil[(size_t(q) * kNumOps + thetas[a]) * Lt + t];
-          corr[2 * (a * Lt + t)] += v.real();
-          corr[2 * (a * Lt + t) + 1] += v.imag();
-        }
-    }
-    // xt += g5 E (w .* (E^H eta)), on the lexicographic copies of E and g5 E
-    // (made once per set of eigenpairs), so that eta is read and xt updated
-    // in place: one pass over the modes for the dots, one for the update
-    const size_t Vh = size_t(c->g.Vh);
-    std::unique_lock<std::mutex> lk(d->fill_mu);
-    if (d->lex_Q != Q) {
-      cx<double> *El = static_cast<cx<double> *>(d->Elex.ensure(fl * Q * sizeof(cx<double>)));
-      cx<double> *Gl = static_cast<cx<double> *>(d->G5Elex.ensure(fl * Q * sizeof(cx<double>)));
-      cx<double> *T = static_cast<cx<double> *>(c->ws[1].ensure(fl * Q * sizeof(cx<double>)));
-      unpack_eo<double>(c, E, El, Q, fl);
-      LQCD_HIP(hipMemcpyAsync(T, E, fl * Q * sizeof(cx<double>), hipMemcpyDeviceToDevice, c->stream));
-      hipLaunchKernelGGL(k_g5_eo, dim3(nblocks(2 * 6 * Vh * Q)), dim3(kBlock), 0, c->stream, T, Vh, fl, Q);
-      LQCD_HIP(hipGetLastError());
-      unpack_eo<double>(c, T, Gl, Q, fl);
-      LQCD_HIP(hipStreamSynchronize(c->stream));
-      d->lex_Q = Q;
-    }
-    lk.unlock();
-    const cx<double> *El = d->Elex.as<cx<double>>(), *Gl = d->G5Elex.as<cx<double>>();
-    cdouble *wd = static_cast<cdouble *>(c->ws[6].ensure(size_t(Q) * sizeof(cdouble)));
-    h2d(c, wd, w.data(), size_t(Q) * sizeof(cdouble));
-    const int blk = kSubBlock;
-    for (int r0 = 0; r0 < nrhs; r0 += blk) {
-      const int nb = std::min(blk, nrhs - r0);
-      cdouble *Cd = static_cast<cdouble *>(c->ws[5].ensure(size_t(Q) * nb * sizeof(cdouble)));
-      gemm_tn<double>(c, El, fl, Q, static_cast<const cdouble *>(eta) + r0 * fl, fl, nb, fl, Cd, Q);
-      hipLaunchKernelGGL(k_scale_rows, dim3(nblocks(size_t(Q) * nb)), dim3(kBlock), 0, c->stream,
-                         reinterpret_cast<cx<double> *>(Cd), reinterpret_cast<const cx<double> *>(wd), Q, nb);
-      LQCD_HIP(hipGetLastError());
-      gemm_nn<double>(c, Gl, fl, 0, Q, Cd, Q, 0, static_cast<cdouble *>(xt) + r0 * fl, fl, 0, nb, fl, 1, 1.0);
-    }
+    const std::vector<cdouble> w =
+        hf_weights(c, d, Q, mode, coeffs_host, ncoeff, thetas, nth, corr, xi_inv_host);
+    hf_update(c, d, Q, eta, 1, &xt, &w, nrhs);
   });
 }

@@ -67,6 +67,7 @@ _SIGS = {
     "lqcd_defl_eigpairs": [_P, _P, _I, _P, _P],
     "lqcd_defl_ritz": [_P, _P, ctypes.POINTER(ctypes.c_int)],
     "deflate_project": [_P, _P, _I, _I, _P, _I, _P, _I, _P, _P, _I, _P, _P],
+    "deflate_project_multi": [_P, _P, _I, _I, _P, _P, _P, _P, _I, _P, _P, _I, _P],
     "pert_subtract": [_P, _I, _P, _I, _P, _P, _I, _P],
     "poly_subtract": [_P, _I, _P, _P, _P, _P, _I, _P, _P, _I, _P],
     "poly_subtract_multi": [_P, _I, _I, _P, _P, _P, _I],
@@ -367,6 +368,39 @@ class Context:
                                      _field(eta, n, 12 * self.V, "eta"), _field(xt, n, 12 * self.V, "xt"),
                                      n, corr.ctypes.data_as(_P), xi.ctypes.data_as(_P)))
         return xt, corr, xi
+
+    def deflate_project_multi(self, defl, Q, eta, variants, thetas=(0, 1, 2, 3, 4)):
+        """deflate_project for several (mode, coeffs, xt, corr) variants of
+        one noise at once (modes HFES / EIGPOLY; xt updated in place, None:
+        a new zero field; corr None: zeros).  Returns [(xt, corr)]."""
+        import torch
+        th, thp, nth = _thetas(thetas)
+        n = eta.shape[0]
+        nv = len(variants)
+        keep, xts, corrs = [], [], []
+        modes = np.array([m for m, _, _, _ in variants], dtype=np.int32)
+        cps, ncs = [], []
+        for mode, coeffs, xt, corr in variants:
+            xts.append(torch.zeros_like(eta) if xt is None else xt)
+            cr = np.zeros((nth, self.dims[3]), dtype=np.complex128) if corr is None else \
+                np.ascontiguousarray(corr, dtype=np.complex128).copy()
+            corrs.append(cr)
+            if coeffs is None:
+                cps.append(None)
+                ncs.append(0)
+            else:
+                cf = np.ascontiguousarray(coeffs, dtype=np.complex128)
+                keep.append(cf)
+                cps.append(cf.ctypes.data_as(_P))
+                ncs.append(len(cf))
+        nc = np.array(ncs, dtype=np.int32)
+        _check(lib().deflate_project_multi(self.handle, defl.handle, Q, nv, modes.ctypes.data_as(_P),
+                                           (_P * nv)(*cps), nc.ctypes.data_as(_P), thp, nth,
+                                           _field(eta, n, 12 * self.V, "eta"),
+                                           (_P * nv)(*[_field(x, n, 12 * self.V, "xt") for x in xts]), n,
+                                           (_P * nv)(*[c.ctypes.data_as(_P) for c in corrs])))
+        del keep
+        return list(zip(xts, corrs))
 
     def poly_subtract_multi(self, eta, coeffs_list):
         """p_a(kappa P) eta for each coefficient list (complex, lowest power

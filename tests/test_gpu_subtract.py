@@ -149,3 +149,42 @@ def test_loop_estimate_function():
     assert np.abs(smp - t).max() < 1e-12 * np.abs(t).max()
     assert np.abs(est - e_ref).max() < 1e-12 * np.abs(e_ref).max()
     assert np.abs(err - s_ref).max() < 1e-12 * np.abs(s_ref).max()
+
+
+def test_deflate_project_multi_equals_single_calls():
+    """deflate_project_multi: each variant equals deflate_project with the
+    same mode, coefficients, vector and correction bit for bit (overlaps
+    formed once); modes other than HFES / EIGPOLY and more than four
+    variants are rejected."""
+    require_gpu()
+    import torch
+    from paper_1903_06986_amd import lqcd
+    from paper_1903_06986_amd.lqcd import LqcdError
+    dims, kappa, Q = (4, 4, 2, 4), 0.125, 6
+    ctx, U = context(dims, 0.3, 31, kappa)
+    n = 18  # a full block of 16 right-hand sides and a ragged one
+    eta = to_gpu(z4_noise(5, dims, 0, n))
+    say("deflate_project_multi", dims, n)
+    _, hdefl, _ = ctx.gmresdr_solve(eta[0:1], op="MG5", m=40, k=20, tol=1e-12, tol_super=1e-13,
+                                    eig_tol=1e-11, n_eig=Q + 2, max_cycles=300)
+    rng = np.random.default_rng(4)
+    bases = [torch.from_numpy(rng.standard_normal((n,) + ctx.shape) + 0j).cuda() for _ in range(2)]
+    corrs = [rng.standard_normal((5, dims[3])) + 1j * rng.standard_normal((5, dims[3])) for _ in range(2)]
+    cp = S.pert_coeffs(6)
+    cq = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+    variants = [(lqcd.DEFL_HFES, None, None, None),
+                (lqcd.DEFL_EIGPOLY, cp, bases[0].clone(), corrs[0]),
+                (lqcd.DEFL_EIGPOLY, cq, bases[1].clone(), corrs[1])]
+    multi = ctx.deflate_project_multi(hdefl, Q, eta, variants, THETAS)
+    refs = [ctx.deflate_project(hdefl, Q, eta, xt=torch.zeros_like(eta), mode=lqcd.DEFL_HFES, thetas=THETAS),
+            ctx.deflate_project(hdefl, Q, eta, xt=bases[0].clone(), corr=corrs[0], mode=lqcd.DEFL_EIGPOLY,
+                                coeffs=cp, thetas=THETAS),
+            ctx.deflate_project(hdefl, Q, eta, xt=bases[1].clone(), corr=corrs[1], mode=lqcd.DEFL_EIGPOLY,
+                                coeffs=cq, thetas=THETAS)]
+    for (xt, corr), (xr, cr, _) in zip(multi, refs):
+        np.testing.assert_array_equal(to_host(xt), to_host(xr))
+        np.testing.assert_array_equal(corr, cr)
+    with pytest.raises(LqcdError):
+        ctx.deflate_project_multi(hdefl, Q, eta, [(lqcd.DEFL_ES, None, None, None)], THETAS)
+    with pytest.raises(LqcdError):
+        ctx.deflate_project_multi(hdefl, Q, eta, [(lqcd.DEFL_HFES, None, None, None)] * 5, THETAS)

@@ -679,7 +679,7 @@ def dslash_table(reps, lattices=None, nrhs_list=(1, 4, 8, 16, 32)):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--kappa", type=float, default=None)
@@ -687,14 +687,14 @@ def main():
     ap.add_argument("--proj-m", type=int, default=0, help="GMRES-Proj cycle length (0: m - k)")
     ap.add_argument("--arnoldi-steps", type=int, default=4, choices=[1, 2, 3, 4, 5, 6],
                     help="Arnoldi steps per pass over the 16-bit basis in the inner GMRES-Proj cycles")
-    ap.add_argument("--streams", type=int, default=2,
+    ap.add_argument("--streams", type=int, default=3,
                     help="pipelines run at once in the timed steps, one context and stream each")
     ap.add_argument("--kernel-steps", type=int, default=3,
                     help="steps of one pipeline alone, timed for the kernel classes and the roofline "
                          "when --streams > 1")
     ap.add_argument("--sstep-z16", type=int, default=0, choices=[0, 1],
                     help="store the s-step power vectors in the basis's 16-bit form")
-    ap.add_argument("--fp64-steps", type=int, default=4, help="timed FP64 steps (at least 4, after 1 warm-up per pipeline)")
+    ap.add_argument("--fp64-steps", type=int, default=6, help="timed FP64 steps (at least 4, after 1 warm-up per pipeline)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--tol-super", type=float, default=1e-12)
     ap.add_argument("--eig-tol", type=float, default=1e-5)

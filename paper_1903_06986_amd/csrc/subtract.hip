@@ -482,35 +482,63 @@ struct PolySet {
 };
 
 // out_a (lex) = sum_{j < d1} c[a][j] P_j for the powers P_j (even/odd, blk
-// apart; right-hand side r at r fl) of one block; thread = lex site s of
-// right-hand side blockIdx.y.
+// apart; right-hand side r at r fl) of one block.  A workgroup takes 64
+// consecutive lex sites s0.. of right-hand side blockIdx.y: with Lx even,
+// sites 2h and 2h + 1 are x neighbours of opposite parity, both at index h
+// of their parity's half, so the 64 sites are 32 consecutive h in each
+// half.  Thread element i = (component k, parity, h - s0/2) with h fastest
+// loads coalesced runs of 32 complex of every power; each output goes
+// through LDS in lex order and is stored contiguously (768 complex).
+constexpr int kPolySites = 64;
 template <int NP>
 __global__ void __launch_bounds__(kBlock)
     k_poly_lex(Geom g, const cx<double> *__restrict__ P, size_t fl, size_t blk, int d1, PolySet ps) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.V) return;
+  __shared__ cx<double> sh[kPolySites * 12];
+  constexpr int kPer = kPolySites * 12 / kBlock;  // elements per thread
+  const int s0 = blockIdx.x * kPolySites;
   const size_t rhs = blockIdx.y;
   const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
-  const int x = s % Lx, y = (s / Lx) % Ly, z = (s / (Lx * Ly)) % Lz, t = s / (Lx * Ly * Lz);
-  const int par = (x + y + z + t) & 1;
   const size_t Vh = g.Vh;
-  const cx<double> *src = P + rhs * fl + par * 12 * Vh + (s >> 1);
-  const size_t o = (rhs * size_t(g.V) + s) * 12;
-  for (int k = 0; k < 12; ++k) {
-    cx<double> acc[NP];
+  const cx<double> *src = P + rhs * fl;
+  cx<double> acc[kPer][NP];
+  int at[kPer];
 #pragma unroll
-    for (int a = 0; a < NP; ++a) acc[a] = mk(0.0, 0.0);
-    cx<double> v[kMaxOrder + 1];  // every power's component k in flight together
+  for (int u = 0; u < kPer; ++u) {
+    const int i = threadIdx.x + u * kBlock;
+    const int hh = i % (kPolySites / 2), rest = i / (kPolySites / 2);
+    const int par = rest & 1, k = rest >> 1;
+    const int h = s0 / 2 + hh, e = 2 * h;  // the even-indexed site of the pair
+    const bool ok = e < g.V;
+    const int x = e % Lx, y = (e / Lx) % Ly, z = (e / (Lx * Ly)) % Lz, t = e / (Lx * Ly * Lz);
+    const int s = ((x + y + z + t) & 1) == par ? e : e + 1;
+    at[u] = ok ? (s - s0) * 12 + k : -1;
+    const cx<double> *q = src + par * 12 * Vh + k * Vh + (ok ? h : 0);
+    cx<double> v[kMaxOrder + 1];  // every power's element in flight together
 #pragma unroll
     for (int j = 0; j <= kMaxOrder; ++j)
-      if (j < d1) v[j] = ldc(src + j * blk + k * Vh);
+      if (j < d1) v[j] = ldc(q + j * blk);
 #pragma unroll
-    for (int j = 0; j <= kMaxOrder; ++j)
-      if (j < d1)
+    for (int a = 0; a < NP; ++a) {
+      acc[u][a] = mk(0.0, 0.0);
 #pragma unroll
-        for (int a = 0; a < NP; ++a) acc[a] = acc[a] + ps.c[a][j] * v[j];
+      for (int j = 0; j <= kMaxOrder; ++j)
+        if (j < d1) acc[u][a] = acc[u][a] + ps.c[a][j] * v[j];
+    }
+  }
+  const size_t o = (rhs * size_t(g.V) + s0) * 12;
+  const int nel = min(kPolySites, g.V - s0) * 12;
 #pragma unroll
-    for (int a = 0; a < NP; ++a) stc(ps.out[a] + o + k, acc[a]);
+  for (int a = 0; a < NP; ++a) {
+    if (a > 0) __syncthreads();  // the previous output's reads of sh are done
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      if (at[u] >= 0) sh[at[u]] = acc[u][a];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int i = threadIdx.x + u * kBlock;
+      if (i < nel) stc(ps.out[a] + o + i, sh[i]);
+    }
   }
 }
 
@@ -926,6 +954,7 @@ extern "C" lqcd_status poly_subtract_multi(lqcd_ctx *c, int npoly, int degree, c
     for (int a = 0; a < npoly; ++a)
       for (int j = 0; j < d1; ++j)
         ps.c[a][j] = mk(coeffs_host[2 * (a * d1 + j)], coeffs_host[2 * (a * d1 + j) + 1]);
+    LQCD_CHECK(c->g.L[0] % 2 == 0, LQCD_EINVAL, "poly_subtract_multi: odd x extent");
     const size_t fl = full_len(c->g), hl = half_len(c->g);
     for (int r0 = 0; r0 < nrhs; r0 += kSubBlock) {
       const int nb = std::min(kSubBlock, nrhs - r0);
@@ -937,7 +966,7 @@ extern "C" lqcd_status poly_subtract_multi(lqcd_ctx *c, int npoly, int degree, c
           hop_half<double>(c, p, W + j * blk + (1 - p) * hl, nullptr, W + (j + 1) * blk + p * hl, cdouble(0, 0),
                            c->kappa, false, false, nb, fl, 0, fl);
       for (int a = 0; a < npoly; ++a) ps.out[a] = static_cast<cx<double> *>(xt_list[a]) + r0 * fl;
-      const dim3 grid(nblocks(c->g.V), nb);
+      const dim3 grid((c->g.V + kPolySites - 1) / kPolySites, nb);
       switch (npoly) {
         case 1: hipLaunchKernelGGL(k_poly_lex<1>, grid, dim3(kBlock), 0, c->stream, c->g, W, fl, blk, d1, ps); break;
         case 2: hipLaunchKernelGGL(k_poly_lex<2>, grid, dim3(kBlock), 0, c->stream, c->g, W, fl, blk, d1, ps); break;

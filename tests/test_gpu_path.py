@@ -9,6 +9,9 @@ hermitian modes are the exact ones (dense eigh of M' on 4^4); the GPU's
 come from its super-converged GMRES-DR on M' with eigen-residuals
 <= 1e-12 |lambda'|.  (The oracle's own iterative modes at eigen-residual
 <= 3e-12 move its HF estimates by 1.1e-11 relative on this lattice.)
+Both forms of the GPU path are checked: the combined calls for all six
+methods (poly_subtract_multi, deflate_project_multi, loop_estimate_multi)
+and one call per method.
 """
 import numpy as np
 import pytest
@@ -21,23 +24,37 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def both():
+def oracle_run():
     require_gpu()
-    from paper_1903_06986_amd import Context
-    from paper_1903_06986_amd import pipeline as gpipe
     cfg = get_config("c1")
     dims, kappa = cfg["dims"], cfg["kappas"][0]
     U = random_su3_links(dims, cfg["eps"], cfg["link_seed"])
-    say("full path c1 gpu")
-    ctx = Context(dims, U, kappa)
-    g = gpipe.run(ctx, cfg["noise_seed"], cfg["n_noise"], cfg["m"], cfg["k"], cfg["pert_order"],
-                  cfg["poly_degree"], cfg["n_hermitian"], cfg["herm_m"], cfg["herm_k"], tol=1e-12,
-                  tol_super=1e-13, eig_tol=1e-12, rhs_block=4)
     say("full path c1 oracle")
-    o = opipe.run(U, dims, kappa, cfg["noise_seed"], cfg["n_noise"], cfg["m"], cfg["k"],
-                  cfg["pert_order"], cfg["poly_degree"], cfg["n_hermitian"], tol=1e-12,
-                  tol_super=1e-13, modes=_dense_modes(U, dims, kappa, cfg["n_hermitian"]))
-    return g, o
+    return U, opipe.run(U, dims, kappa, cfg["noise_seed"], cfg["n_noise"], cfg["m"], cfg["k"],
+                        cfg["pert_order"], cfg["poly_degree"], cfg["n_hermitian"], tol=1e-12,
+                        tol_super=1e-13, modes=_dense_modes(U, dims, kappa, cfg["n_hermitian"]))
+
+
+_gpu_runs = {}
+
+
+@pytest.fixture(params=[True, False], ids=["fused", "per-method"])
+def both(request, oracle_run):
+    """The GPU path with the combined calls (fused) or one call per method,
+    and the oracle's run (the same for both)."""
+    from paper_1903_06986_amd import Context
+    from paper_1903_06986_amd import pipeline as gpipe
+    fused = request.param
+    U, o = oracle_run
+    if fused not in _gpu_runs:
+        cfg = get_config("c1")
+        dims, kappa = cfg["dims"], cfg["kappas"][0]
+        say("full path c1 gpu", "fused" if fused else "per method")
+        ctx = Context(dims, U, kappa)
+        _gpu_runs[fused] = gpipe.run(ctx, cfg["noise_seed"], cfg["n_noise"], cfg["m"], cfg["k"], cfg["pert_order"],
+                                     cfg["poly_degree"], cfg["n_hermitian"], cfg["herm_m"], cfg["herm_k"], tol=1e-12,
+                                     tol_super=1e-13, eig_tol=1e-12, rhs_block=4, fused=fused)
+    return _gpu_runs[fused], o
 
 
 def _dense_modes(U, dims, kappa, Q):

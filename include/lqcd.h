@@ -238,7 +238,8 @@ lqcd_status deflate_project(lqcd_ctx *ctx, lqcd_defl *defl, int Q, lqcd_defl_mod
                             double *trace_corr_host, double *xi_inv_host);
 
 /* Several hermitian-forced projections of the same noise at once (modes
- * HFES and EIGPOLY of deflate_project): variant v is deflate_project with
+ * HFES and EIGPOLY of deflate_project; Sec. 5.4 Eqs. (66)-(68), Sec. 5.5
+ * Eqs. (69)-(72)): variant v is deflate_project with
  * mode modes[v], coefficients coeffs_list[v] (ncoeffs[v] complex128; read
  * for EIGPOLY only), xt = xt_list[v] and trace_corr_host = corr_list[v]
  * (corr_list NULL or an entry NULL: no correction), and its results equal

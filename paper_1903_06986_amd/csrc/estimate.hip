@@ -461,6 +461,7 @@ void estimate_with(lqcd_ctx *c, const int *thetas, int nth, const void *eta, con
       const int n = std::min(kPsGroup, nvar - v0);
       LQCD_EST_DISPATCH(launch_ps, n, c, eta, x, group(v0, n), v0, nrhs, d, nch)
     }
+#undef LQCD_EST_DISPATCH
   const int Lt = c->g.L[3];
   std::vector<double> hc(size_t(nvar) * nrhs * kOpSlots * Lt * nch * 2);
   LQCD_HIP(hipMemcpyAsync(hc.data(), d, hc.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));

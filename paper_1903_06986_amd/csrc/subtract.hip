@@ -720,6 +720,9 @@ void es_project(lqcd_ctx *c, lqcd_defl *d, int Q, const int *thetas, int nth, co
   }
 }
 
+// Hermitian-forced projections per deflate_project_multi call.
+constexpr int kMaxHfVariants = 4;
+
 // The weights w_q of a hermitian-forced projection (deflate_project, modes
 // HFES and EIGPOLY) on the eigenpairs of d, with the trace correction added
 // to corr (NULL: none) and 1/xi'_q written to xi_inv_host (NULL: not).
@@ -984,8 +987,8 @@ extern "C" lqcd_status deflate_project_multi(lqcd_ctx *c, lqcd_defl *d, int Q, i
                                              int nrhs, double *const *corr_list) {
   return guarded([&] {
     LQCD_CHECK(c && d && modes, LQCD_EINVAL, "deflate_project_multi: null argument");
-    LQCD_CHECK(nvar >= 1 && nvar <= kMaxPolys, LQCD_EINVAL, "deflate_project_multi: %d variants (1..%d)", nvar,
-               kMaxPolys);
+    LQCD_CHECK(nvar >= 1 && nvar <= kMaxHfVariants, LQCD_EINVAL, "deflate_project_multi: %d variants (1..%d)",
+               nvar, kMaxHfVariants);
     LQCD_CHECK(nrhs >= 0 && (nrhs == 0 || (eta && xt_list)), LQCD_EINVAL, "deflate_project_multi: null field");
     for (int v = 0; v < nvar; ++v) {
       LQCD_CHECK(modes[v] == LQCD_DEFL_HFES || modes[v] == LQCD_DEFL_EIGPOLY, LQCD_EINVAL,

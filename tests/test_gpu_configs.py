@@ -8,7 +8,10 @@ that hold at any size.
   oracle's FP64 operator on sampled right-hand sides (first, middle and
   last slot of a launch), within the storage bound; one mixed-precision
   (FP16-stored) GMRES-Proj block of 16 noise vectors in the benchmark's
-  shape, whose residuals the oracle recomputes.
+  shape, whose residuals the oracle recomputes; the calls that serve all
+  six subtraction methods of a step (PS and POLY vectors from one chain of
+  powers, six estimates of all nine operators) against the oracle on
+  sampled right-hand sides and against the single-method calls.
 * 16^3 x 32, kappa = 0.120, 4 noise vectors: every solution by the oracle's
   residual; PS (order 7) vectors against the oracle's Horner; the Min-Res
   coefficients (degree 7) against the oracle's QR, and the POLY vectors
@@ -127,6 +130,50 @@ def test_c3_mixed_block_residuals(c3):
         assert res <= 1.05e-10, (r, res)
         assert abs(res - st[r]["true_resid"]) < 2e-12, (r, res, st[r]["true_resid"])
     defl.free()
+
+
+def test_c3_combined_calls_sampled(c3, c3_fields):
+    """The calls that serve all six subtraction methods of a step, in the
+    bench's shape (24^3 x 32, 16 right-hand sides, all nine operators):
+    poly_subtract_multi (PS7 and a degree-7 polynomial) against the
+    oracle's Horner on the last slot of the block; loop_estimate_multi with
+    six methods bit for bit against loop_estimate, and its samples of the
+    first and last slot against the oracle's estimator for three methods."""
+    from oracle import pointsplit as PSO
+    cfg, dims, kappa, U, ctx = c3
+    x_in, _ = c3_fields
+    rng = np.random.default_rng(53)
+    eta = x_in  # 16 seeded fields of the test's own generator
+    eg = to_gpu(eta)
+    cq = rng.standard_normal(8) + 1j * rng.standard_normal(8)
+    say("c3 poly_subtract_multi")
+    ps, po = ctx.poly_subtract_multi(eg, [S.pert_coeffs(7), cq])
+    say("c3 oracle Horner, slot 15")
+    for out, c in ((ps, S.pert_coeffs(7)), (po, cq)):
+        ref = S.horner(U, kappa, eta[15], c)
+        assert rel_err(to_host(out[15:16])[0], ref) < 1e-12
+    del ps, po
+    say("c3 loop_estimate_multi")
+    shape = eta.shape
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    xts = [None] + [rng.standard_normal(shape) + 1j * rng.standard_normal(shape) for _ in range(5)]
+    corrs = [None if v % 2 else rng.standard_normal((9, dims[3])) + 1j * rng.standard_normal((9, dims[3]))
+             for v in range(6)]
+    xg = to_gpu(x)
+    xtg = [None if t is None else to_gpu(t) for t in xts]
+    ops = tuple(range(9))
+    multi = ctx.loop_estimate_multi(eg, xg, xtg, corrs, ops, samples=True)
+    for v in range(6):
+        est, err = ctx.loop_estimate(eg, xg, xtg[v], corrs[v], ops)
+        np.testing.assert_array_equal(multi[v][0], est)
+        np.testing.assert_array_equal(multi[v][1], err)
+    for v in (0, 1, 5):
+        for r in (0, 15):
+            say("c3 oracle estimator, method", v, "slot", r)
+            xt = np.zeros_like(x[r:r + 1]) if xts[v] is None else xts[v][r:r + 1]
+            t = np.concatenate([E.samples(eta[r:r + 1], x[r:r + 1], xt, (0, 1, 2, 3, 4), dims),
+                                PSO.samples_ps(U, kappa, eta[r:r + 1], x[r:r + 1], xt, range(4), dims)], axis=1)
+            assert np.abs(multi[v][2][r] - t[0]).max() < 1e-12 * np.abs(t).max()
 
 
 # ------------------------------------------------------------ 16^3 x 32
